@@ -1,0 +1,102 @@
+"""Pins of the oracle's ParaDIAG pieces: the alpha-circulant eigen-
+decomposition against its definition and a library eigensolver, the
+all-at-once solve against a dense Kronecker solve, and the heat pipeline and
+its gradient against the closed-form mode recurrence."""
+import numpy as np
+import pytest
+
+from oracle import exact, paradiag as pd, spectral
+from paper_2203_11154_amd import inputs
+
+
+@pytest.mark.parametrize("n", [8, 16, 64])
+def test_alpha_circulant_closed_form(n):
+    alpha, tau = 0.01, 1.0 / n
+    C = spectral.alpha_circulant(n, alpha, tau)
+    lam, V, Vinv = spectral.alpha_circulant_eig(n, alpha, tau)
+    assert np.linalg.norm(C @ V - V * lam[None, :]) <= 1e-11 * np.linalg.norm(C) * np.linalg.norm(V)
+    assert np.linalg.norm(V @ Vinv - np.eye(n)) <= 1e-11 * n
+    # condition number alpha^{-(n-1)/n}
+    s = np.linalg.svd(V, compute_uv=False)
+    assert s[0] / s[-1] == pytest.approx(alpha ** (-(n - 1) / n), rel=1e-9)
+    ref = np.linalg.eigvals(C)
+    key = lambda z: (round(z.real, 6), round(z.imag, 6))
+    np.testing.assert_allclose(sorted(lam, key=key), sorted(ref, key=key), rtol=1e-9)
+
+
+def test_workload_generator_matches_oracle_decomposition():
+    n = 32
+    lam_o, V_o, Vi_o = spectral.alpha_circulant_eig(n, 0.01, 1.0 / n)
+    V, Vi = inputs.alpha_circulant_vectors(n, 0.01)
+    np.testing.assert_allclose(inputs.alpha_circulant_shifts(n, 0.01), lam_o, rtol=1e-13)
+    np.testing.assert_allclose(V, V_o, rtol=1e-13)
+    np.testing.assert_allclose(Vi, Vi_o, rtol=1e-12, atol=1e-16)
+
+
+def test_paradiag_apply_matches_dense_all_at_once():
+    """eq. (1): (B kron I + I kron A)^{-1} f with B = C_alpha, on a tiny grid."""
+    n, nx = 6, 7
+    h = 1.0 / (nx + 1)
+    lam, V, Vinv = spectral.alpha_circulant_eig(n, 0.05, 1.0 / n)
+    B = spectral.alpha_circulant(n, 0.05, 1.0 / n)
+    rng = np.random.default_rng(3)
+    F = rng.standard_normal((n, nx, nx)) + 1j * rng.standard_normal((n, nx, nx))
+    K = np.kron(B, np.eye(nx * nx)) + np.kron(np.eye(n), exact.dense_laplacian(nx, nx, h))
+    ref = np.linalg.solve(K, F.ravel()).reshape(F.shape)
+    U = pd.paradiag_apply(F, lam, V, Vinv, h, tol=1e-13)
+    np.testing.assert_allclose(U, ref, rtol=1e-8, atol=1e-12)
+    U2 = pd.paradiag_apply(F, lam, V, Vinv, h, solver="dst")
+    np.testing.assert_allclose(U2, ref, rtol=1e-10, atol=1e-13)
+
+
+def test_backward_euler_operator_and_transpose():
+    n, nx = 5, 7
+    h, tau = 1.0 / 8, 0.2
+    rng = np.random.default_rng(5)
+    U = rng.standard_normal((n, nx, nx)) + 0j
+    W = rng.standard_normal((n, nx, nx)) + 0j
+    Bbe = (np.eye(n) - np.eye(n, k=-1)) / tau
+    K = np.kron(Bbe, np.eye(nx * nx)) + np.kron(np.eye(n), exact.dense_laplacian(nx, nx, h))
+    np.testing.assert_allclose(pd.backward_euler_apply(U, tau, h).ravel(), K @ U.ravel(), rtol=1e-12)
+    np.testing.assert_allclose(pd.backward_euler_apply_transpose(W, tau, h).ravel(), K.T @ W.ravel(), rtol=1e-12)
+
+
+@pytest.mark.parametrize("solver", ["dst", "multigrid"])
+def test_heat_pipeline_closed_form(solver):
+    """Full ParaDIAG-II for the heat workload (small grid) against the
+    closed-form backward-Euler mode recurrence."""
+    n, nx = 16, 31
+    h, tau = 1.0 / (nx + 1), 1.0 / n
+    theta = inputs.heat_parameters(8)
+    f = pd.heat_source(theta, n, nx, tau)
+    lam, V, Vinv = spectral.alpha_circulant_eig(n, 0.01, tau)
+    u, outer, rel = pd.paradiag_heat_solve(f, tau, h, lam, V, Vinv, tol=1e-10, solver=solver)
+    assert rel <= 1e-10 and outer <= 8
+    c = pd.heat_mode_coefficients(n, nx, tau)
+    ref = np.zeros((n, nx, nx))
+    for k, th in enumerate(theta, start=1):
+        ref += th * c[k - 1][:, None, None] * exact.sine_mode(k, k, nx, nx)[None]
+    assert np.linalg.norm(u - ref) <= 1e-8 * np.linalg.norm(ref)
+
+
+def test_heat_gradient_adjoint_vs_closed_form():
+    """dL/dtheta from the adjoint w = K^{-T} 2(u - u*) equals the closed form,
+    and the closed form equals central differences of the closed-form loss."""
+    n, nx, K = 8, 15, 4
+    h, tau = 1.0 / (nx + 1), 1.0 / n
+    th = inputs.heat_parameters(K)
+    ths = inputs.heat_parameters(K, seed=inputs.SEED_THETA_STAR)
+    lam, V, Vinv = spectral.alpha_circulant_eig(n, 0.01, tau)
+    u, _, _ = pd.paradiag_heat_solve(pd.heat_source(th, n, nx, tau), tau, h, lam, V, Vinv, solver="dst")
+    us, _, _ = pd.paradiag_heat_solve(pd.heat_source(ths, n, nx, tau), tau, h, lam, V, Vinv, solver="dst")
+    w, _, _ = pd.paradiag_heat_solve(2 * (u - us), tau, h, lam, V, Vinv, transpose=True, solver="dst")
+    grad = np.array([np.vdot(pd.heat_source(np.eye(K)[k], n, nx, tau), w).real for k in range(K)])
+    L, g = pd.heat_loss_closed_form(th, ths, n, nx, tau)
+    np.testing.assert_allclose(grad, g, rtol=1e-7)
+    assert np.sum(np.abs(u - us) ** 2) == pytest.approx(L, rel=1e-9)
+    eps = 1e-3
+    for k in range(K):
+        d = np.eye(K)[k] * eps
+        Lp, _ = pd.heat_loss_closed_form(th + d, ths, n, nx, tau)
+        Lm, _ = pd.heat_loss_closed_form(th - d, ths, n, nx, tau)
+        assert (Lp - Lm) / (2 * eps) == pytest.approx(g[k], rel=1e-8)
