@@ -1,0 +1,206 @@
+/*
+ * vanka_mg.h - C ABI of the MI355X (gfx950) Vanka-multigrid library for the
+ * complex-shifted Laplacian systems of diagonalisation-based parallel-in-time
+ * (ParaDIAG) methods.
+ *
+ * Method: He & Liu, "A Vanka-type multigrid solver for complex-shifted
+ * Laplacian systems from diagonalization-based parallel-in-time algorithms"
+ * (arXiv 2203.11154).
+ *   - eq. (1): (B kron I_h + I_t kron A) u = f with B = V D V^{-1} splits into
+ *     G = (V^{-1} kron I_h) F, n independent shifted solves, U = (V kron I_h) Z.
+ *   - eq. (2): the shifted systems L_j z = (A + lambda_j I) z = b_j, A the
+ *     5-point Laplacian (1/h^2)[., -1, .; -1, 4, -1; ., -1, .] on a rectangle
+ *     with homogeneous Dirichlet boundary (Sec. 1).
+ *   - eqs. (3) and (6): the additive element-wise Vanka smoother, applied as the
+ *     explicit stencil M_{e,j} = (h^2/4)[c 2b c; 2b 4a 2b; c 2b c] with one
+ *     precomputed patch inverse (a, b, c) per shift and level, relaxation
+ *     weight omega = 24/25 (Sec. 2.1, after Theorem 2.1).
+ *   - Sec. 3: re-discretised coarse operators (2h), full-weighting
+ *     restriction, linear interpolation, a direct solve on the coarsest grid,
+ *     and a stop on the reduction of the relative residual norm.
+ *
+ * Data conventions (all entry points)
+ *   - Complex numbers are interleaved (re, im) doubles (C99 double _Complex /
+ *     numpy complex128 / torch.complex128 layout).
+ *   - A grid has nx x ny interior nodes, x fastest.  A vector of one system is
+ *     ny*nx complex values, row-major; the systems of all grids are
+ *     concatenated in the order the grids were given to vanka_mg_setup, and
+ *     within a grid in system order.
+ *   - "device" pointers are HIP device memory of the GPU that was current at
+ *     setup; "host" pointers are ordinary host memory.
+ *   - hip_stream is a hipStream_t (NULL = the default stream).  Work is
+ *     enqueued on that stream; a call returns once its work is enqueued unless
+ *     it has host outputs, which imply a synchronisation of that stream.
+ *   - The caller owns every buffer it passes in; the library owns everything
+ *     inside a handle.  A handle is used from one host thread and one stream at
+ *     a time.
+ *
+ * Errors: every int-returning call returns one of the VMG_* codes below and
+ * never throws or aborts.  On an error no output is valid unless stated.
+ */
+#ifndef VANKA_MG_H
+#define VANKA_MG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    VMG_OK = 0,
+    VMG_NOT_CONVERGED = 1,   /* outputs valid; some system hit max_iter      */
+    VMG_INVALID_ARG = -1,    /* null pointer, bad size, bad option            */
+    VMG_HIP_ERROR = -2,      /* a HIP runtime call failed                     */
+    VMG_OOM = -3,            /* device or host allocation failed              */
+    VMG_SINGULAR = -4,       /* a shifted coarsest-grid matrix is singular    */
+    VMG_NAN_DETECTED = -5    /* a residual norm became NaN or Inf             */
+};
+
+/* Operation codes of vanka_mg_apply_op (single kernels, for tests/tuning). */
+enum {
+    VMG_OP_SWEEP = 0,            /* out = x + omega M_{e,j}(b - L_j x)          */
+    VMG_OP_RESIDUAL = 1,         /* out = b - L_j x                              */
+    VMG_OP_RESTRICT_RESIDUAL = 2,/* out (coarse) = FW(b - L_j x)                 */
+    VMG_OP_PROLONG_CORRECT = 3,  /* out = x + P e, e = b argument on the coarse grid */
+    VMG_OP_COARSE_SOLVE = 4,     /* out = (A_c + lambda_j I)^{-1} b, coarsest    */
+    VMG_OP_CYCLE = 5             /* out = one multigrid cycle from x with rhs b  */
+};
+
+typedef struct vmg_handle vmg_handle;
+
+/* One grid and the systems solved on it. */
+typedef struct {
+    int32_t nx, ny;       /* interior nodes; each level above the coarsest
+                             must have odd nx, ny >= 3 (coarse = (n-1)/2)      */
+    double h;             /* mesh width (unit square: 1/(nx+1))                */
+    int32_t levels;       /* number of levels; 0 = coarsen until the smaller
+                             side has at most 7 nodes (h0 = 1/8, Sec. 3)      */
+    int32_t num_systems;  /* shifts solved on this grid                        */
+} vmg_grid;
+
+typedef struct {
+    double omega;         /* relaxation weight; default 24/25 (Sec. 2.1)      */
+    int32_t nu1, nu2;     /* pre-/post-smoothing steps; default 2, 2          */
+    int32_t gamma;        /* 1 = V-cycle (default), 2 = W-cycle (Sec. 3)     */
+    int32_t max_iter;     /* cycle (or refinement step) limit; default 100    */
+    int32_t precision;    /* 0 = complex128 cycles (default);
+                             1 = complex64 cycles inside FP64 iterative
+                                 refinement (residual and update in FP64)    */
+    int32_t smoother;     /* 0 = additive Vanka (default); 1 = damped Jacobi,
+                             the comparison smoother of Sec. 3 (omega 4/5)   */
+    int32_t ir_inner;     /* complex64 cycles per refinement step; default 3 */
+    int32_t check_every;  /* cycles enqueued between host convergence checks;
+                             default 4 (the stop itself is exact per system:
+                             it is decided on the device after every cycle)  */
+} vmg_opts;
+
+/* Fill *opts with the defaults listed above.  Returns VMG_OK or
+ * VMG_INVALID_ARG (opts NULL). */
+int vanka_mg_default_opts(vmg_opts* opts);
+
+/*
+ * Build the level hierarchy, the per-(shift, level) Vanka coefficients
+ * (eq. (6), eta = lambda_j h_l^2, evaluated in FP64 over one common
+ * denominator) and the inverse of every shifted coarsest-grid matrix, and
+ * allocate all device buffers.
+ *   grids    host, n_grids entries (n_grids >= 1).
+ *   shifts   host, sum(num_systems) complex lambda_j (interleaved doubles),
+ *            copied.
+ *   opts     host, NULL = defaults.
+ *   out      receives the new handle (NULL on failure).
+ * Errors: VMG_INVALID_ARG (sizes, levels that cannot coarsen, a coarsest grid
+ * with more than 256 nodes, bad options), VMG_OOM, VMG_SINGULAR, VMG_HIP_ERROR.
+ */
+int vanka_mg_setup(const vmg_grid* grids, int32_t n_grids, const double* shifts,
+                   const vmg_opts* opts, void* hip_stream, vmg_handle** out);
+
+/*
+ * Solve (A + lambda_j I) z_j = b_j for every system (eq. (2)), or with
+ * conj != 0 the adjoint systems (A + conj(lambda_j) I) z_j = b_j.
+ *   B, Z        device, complex128, all systems concatenated (see above).
+ *               Z may not alias B.  The iteration starts from z = 0.
+ *   tol         relative residual target ||b_j - L_j z_j||_2 / ||b_j||_2 > 0.
+ *   fixed_iters host, NULL or one count per system: run exactly that many
+ *               cycles (refinement steps) for system j and ignore tol.
+ *   iters       host, NULL or one int per system: cycles (refinement steps)
+ *               run.  relres: host, NULL or one double per system: final
+ *               relative residual.  If both are NULL and every system has a
+ *               fixed count, the call is fully asynchronous.
+ * A system with b_j = 0 returns z_j = 0 after zero cycles.
+ * Returns VMG_OK, VMG_NOT_CONVERGED (some system reached max_iter above tol;
+ * outputs valid), VMG_NAN_DETECTED, VMG_INVALID_ARG, VMG_HIP_ERROR.
+ */
+int vanka_mg_solve(vmg_handle* h, const double* B, double* Z, double tol, int32_t conj,
+                   const int32_t* fixed_iters, int32_t* iters, double* relres, void* hip_stream);
+
+/*
+ * ParaDIAG step of eq. (1) for a handle whose systems are the n time modes
+ * (n = total number of systems, all on one grid with m = nx*ny nodes):
+ *   G = (Vinv kron I) F;  Z_j = L_j^{-1} G_j;  U = (V kron I) Z.
+ *   V, Vinv  device, complex128 n x n row-major, V Vinv = I expected.
+ *   F, U     device, complex128 n x m row-major (row = time slice).  U may
+ *            alias F.
+ *   conj     solve with conj(lambda_j) (the adjoint of the block solves).
+ * The shifts given at setup must be the eigenvalues D of B = V D V^{-1}.
+ * Returns as vanka_mg_solve.
+ */
+int paradiag_apply(vmg_handle* h, const double* V, const double* Vinv, const double* F,
+                   double* U, double tol, int32_t conj, void* hip_stream);
+
+/*
+ * The time transform of eq. (1) on its own: out = (M kron I_m) in, i.e.
+ * out[i, p] = sum_k M[i, k] in[k, p] for i, k < n and p < m, as a complex
+ * GEMM on the FP64 matrix cores.  With trans_conj != 0, M^H replaces M.
+ *   M        device, complex128 n x n row-major (1 <= n <= 512).
+ *   in, out  device, complex128 n x m row-major; may not alias.
+ * Returns VMG_OK, VMG_INVALID_ARG, VMG_HIP_ERROR.
+ */
+int paradiag_transform(int32_t n, int64_t m, const double* M, int32_t trans_conj,
+                       const double* in, double* out, void* hip_stream);
+
+/*
+ * Run one operation (VMG_OP_*) of the solver on caller data, for every system
+ * of every grid at level `level` (0 = finest), with the handle's shifts (conj
+ * as in vanka_mg_solve).  Vectors use the unpadded layout above at that
+ * level's size (coarse ops: `out` at level+1 for RESTRICT_RESIDUAL, `b` at
+ * level+1 for PROLONG_CORRECT).  x may be NULL for x = 0 (not for
+ * PROLONG_CORRECT).  The handle's work buffers at that level are overwritten.
+ * Every grid must have more than `level` levels (COARSE_SOLVE: `level` is the
+ * coarsest of every grid).  Exists for per-kernel parity tests and tuning.
+ * Returns VMG_OK, VMG_INVALID_ARG, VMG_HIP_ERROR.
+ */
+int vanka_mg_apply_op(vmg_handle* h, int32_t op, int32_t level, int32_t conj,
+                      const double* x, const double* b, double* out, void* hip_stream);
+
+/*
+ * Kernel timing: with enable != 0 every later kernel launch of the handle is
+ * bracketed by HIP events on its stream, and vanka_mg_kernel_stats reports,
+ * per kernel class k < VMG_NUM_KCLASS, the launch count, the summed duration
+ * (ms) and the summed algorithmic bytes (compulsory HBM bytes of each launch,
+ * counted per node as documented for each class).  enable = 0 stops timing;
+ * reset clears the sums.
+ */
+enum {
+    VMG_K_SWEEP = 0, VMG_K_RESTRICT = 1, VMG_K_PROLONG = 2, VMG_K_NORM = 3,
+    VMG_K_COARSE = 4, VMG_K_PACK = 5, VMG_K_TRANSFORM = 6, VMG_K_IR = 7,
+    VMG_NUM_KCLASS = 8
+};
+int vanka_mg_set_timing(vmg_handle* h, int32_t enable, int32_t reset);
+int vanka_mg_kernel_stats(vmg_handle* h, int64_t* launches /* [VMG_NUM_KCLASS] */,
+                          double* total_ms, double* total_bytes);
+
+/* Levels of grid g: writes count and, if non-NULL, nx/ny per level. */
+int vanka_mg_levels(const vmg_handle* h, int32_t g, int32_t* count, int32_t* nx, int32_t* ny);
+
+/* Release every resource of the handle (NULL is accepted). */
+int vanka_mg_destroy(vmg_handle* h);
+
+/* Static text for a VMG_* code. */
+const char* vanka_mg_error_string(int code);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* VANKA_MG_H */

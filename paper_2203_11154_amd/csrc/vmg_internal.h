@@ -1,0 +1,102 @@
+// Internal declarations shared by the kernels and the host runtime of the
+// Vanka multigrid library (not part of the C ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace vmg {
+
+template <typename T> struct cplx_t;
+template <> struct cplx_t<double> { using type = double2; };
+template <> struct cplx_t<float> { using type = float2; };
+template <typename T> using cplx = typename cplx_t<T>::type;
+
+// Geometry of one level of one grid.  Every system owns a padded plane of
+// (ny + 2) rows of `pitch` elements; interior node (i, k), 1 <= i <= nx,
+// 1 <= k <= ny, is element k * pitch + i of its plane, and the ring i or k in
+// {0, n + 1} (plus the row padding beyond nx + 1) always holds zero.
+struct LevelView {
+    int nx, ny;
+    int pitch;
+    int64_t plane;
+};
+
+// Per (system, level) constants of the shifted operator and the smoother:
+//   (L x)_p = d x_p - s (x_N + x_S + x_E + x_W),  d = 4/h^2 + lambda,  s = 1/h^2
+//   x'_p = x_p + ca r_p + cb (r_N + r_S + r_E + r_W) + cc (r_NE + r_NW + r_SE + r_SW)
+// For the Vanka stencil of eq. (6) with weight omega: ca = omega h^2 a,
+// cb = omega h^2 b / 2, cc = omega h^2 c / 4.  For damped Jacobi: ca = omega/d.
+template <typename T> struct Coef {
+    cplx<T> d, ca, cb, cc;
+};
+
+// Algorithmic (compulsory) bytes per fine node, complex element size E:
+//   sweep: read x, b, write x'            3E
+//   residual + restriction: read x, b; write r_H on a quarter of the nodes  2E + E/4
+//   prolongation + correction: read x, e (quarter), write x               2E + E/4
+//   norm: read x, b                        2E
+struct KernelStats;
+
+// ---- launchers (defined in vmg_kernels.hip); all enqueue on `st` ----
+template <typename T>
+void launch_sweep(const cplx<T>* x, const cplx<T>* b, cplx<T>* xo, LevelView lv, T s,
+                  const Coef<T>* coef, const int* active, int nsys, int x_zero, hipStream_t st);
+
+template <typename T>
+void launch_restrict(const cplx<T>* x, const cplx<T>* b, cplx<T>* bc, LevelView lf, LevelView lc, T s,
+                     const Coef<T>* coef, const int* active, int nsys, int x_zero, hipStream_t st);
+
+template <typename T>
+void launch_prolong(cplx<T>* x, const cplx<T>* e, LevelView lf, LevelView lc, const int* active,
+                    int nsys, int x_zero, hipStream_t st);
+
+// r = b - L x; optionally stores r (as TO, in layout lo) and per-tile partial
+// sums of |r|^2 (partial[sys * ntiles + tile]).  Returns ntiles per system.
+template <typename T, typename TO>
+int launch_residual(const cplx<T>* x, const cplx<T>* b, cplx<TO>* rout, LevelView lv, LevelView lo, T s,
+                    const Coef<T>* coef, const int* active, int nsys, int x_zero, double* partial,
+                    hipStream_t st);
+int residual_tiles(LevelView lv);
+
+template <typename T>
+void launch_coarse(const cplx<T>* b, cplx<T>* x, LevelView lc, const cplx<T>* cinvT, int nc,
+                   const int* active, int nsys, hipStream_t st);
+
+// x64 = (x_zero ? 0 : x64) + e (per active system)
+void launch_ir_update(double2* x, const float2* e, LevelView lx, LevelView le, const int* active, int nsys,
+                      int x_zero, hipStream_t st);
+
+// unpadded <-> padded interior copies.  For unpack, if iters != NULL a system
+// with iters[s] == 0 is written as zero, and if sel != NULL system s reads
+// src1 instead of src0 when ((iters[s] * flips) & 1).
+template <typename T>
+void launch_pack(const cplx<T>* src, cplx<T>* dst, LevelView lv, int nsys, hipStream_t st);
+template <typename T>
+void launch_unpack(const cplx<T>* src0, const cplx<T>* src1, cplx<T>* dst, LevelView lv, int nsys,
+                   const int* iters, int flips, hipStream_t st);
+
+// Convergence bookkeeping (one thread block per system, fixed summation order).
+// mode 0 (init): bb[s] = sum of partials; iters = 0; active = (bb > 0) && target > 0;
+//                relres = active ? 1 : 0.
+// mode 1 (check): for active systems: iters++, relres = sqrt(rr / bb), stop if
+//                 NaN (flag), iters >= target, or (!fixed && relres <= tol).
+void launch_norm_finalize(const double* partial, int ntiles, int nsys, int sys_off, int mode, double tol,
+                          int fixed, double* bb, double* relres, int* iters, int* active, const int* target,
+                          int* nanflag, hipStream_t st);
+
+void launch_fill_int(int* p, int value, int n, hipStream_t st);
+
+// Complex GEMM out[i, p] = sum_k M[i, k] in[k, p] (M^H with trans_conj)
+// on FP64 matrix cores.  in/out rows may be padded planes: element p of row i
+// sits at i * row + (p / nx) * pitch + p % nx + off.
+struct RowLayout {
+    int nx;        // nodes per grid row
+    int pitch;     // elements per stored grid row
+    int64_t row;   // elements per matrix row (one system / time slice)
+    int64_t off;   // element offset of node 0
+};
+void launch_transform(int n, int64_t m, const double2* M, int trans_conj, const double2* in, RowLayout li,
+                      double2* out, RowLayout lo, double2* mbuf, hipStream_t st);
+
+}  // namespace vmg

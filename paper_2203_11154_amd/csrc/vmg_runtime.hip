@@ -1,0 +1,945 @@
+// Host runtime of the Vanka multigrid library: hierarchy and coefficient
+// setup, the multigrid cycle driver, convergence control, refinement, and the
+// extern "C" entry points declared in include/vanka_mg.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <complex>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "../../include/vanka_mg.h"
+#include "vmg_internal.h"
+
+using cd = std::complex<double>;
+
+namespace vmg {
+
+// ----------------------------------------------------------------------------
+// small helpers
+// ----------------------------------------------------------------------------
+struct Status {
+    int code = VMG_OK;
+};
+
+#define VMG_HIP(call)                                      \
+    do {                                                   \
+        hipError_t e_ = (call);                            \
+        if (e_ != hipSuccess) return VMG_HIP_ERROR;        \
+    } while (0)
+
+template <typename T> constexpr int align_elems() { return 128 / (int)sizeof(cplx<T>); }
+
+static int64_t round_up(int64_t v, int64_t a) { return (v + a - 1) / a * a; }
+
+template <typename T> LevelView make_view(int nx, int ny) {
+    LevelView v;
+    v.nx = nx;
+    v.ny = ny;
+    v.pitch = (int)round_up(nx + 2, align_elems<T>());
+    v.plane = round_up((int64_t)v.pitch * (ny + 2), align_elems<T>());
+    return v;
+}
+
+// A device allocation holding `nsys` padded planes; `ptr` is offset so that
+// interior column 1 of every row starts on a 128-byte boundary.
+struct DevBuf {
+    void* alloc = nullptr;
+    void* ptr = nullptr;
+};
+
+struct Level {
+    LevelView v{};
+    double h = 0;
+    DevBuf x[2];
+    DevBuf b;
+};
+
+struct Group {
+    int nx = 0, ny = 0, S = 0, sys0 = 0, L = 0;
+    double h = 0;
+    std::vector<Level> lv64;   // precision 0: all levels; precision 1: level 0 (x[0], b)
+    std::vector<Level> lv32;   // precision 1: all levels
+    Coef<double>* coef64[2] = {nullptr, nullptr};  // [conj][level * S + s]
+    Coef<float>* coef32[2] = {nullptr, nullptr};
+    double2* cinv64[2] = {nullptr, nullptr};       // [conj][s * nc * nc] transposed
+    float2* cinv32[2] = {nullptr, nullptr};
+    int nc = 0;
+    double* partial = nullptr;
+    int ntiles0 = 0;
+};
+
+struct TimedLaunch {
+    int kclass;
+    double bytes;
+    hipEvent_t a, b;
+};
+
+}  // namespace vmg
+
+using namespace vmg;
+
+struct vmg_handle {
+    int device = 0;
+    vmg_opts opts{};
+    int S = 0;
+    std::vector<Group> groups;
+    std::vector<cd> shifts;
+    double* bb = nullptr;
+    double* relres = nullptr;
+    int* iters = nullptr;
+    int* active = nullptr;
+    int* target = nullptr;
+    int* nanflag = nullptr;
+    // pinned host staging
+    int* h_int = nullptr;      // 3 * S ints
+    double* h_dbl = nullptr;   // S doubles
+    double2* mbuf = nullptr;   // n x n transform scratch (paradiag_apply)
+    double2* gbuf = nullptr;   // n x m intermediate of paradiag_apply
+    int64_t gbuf_elems = 0;
+    std::vector<void*> allocations;
+    // timing
+    bool timing = false;
+    std::vector<TimedLaunch> pending;
+    std::vector<hipEvent_t> event_pool;
+    int64_t launches[VMG_NUM_KCLASS] = {};
+    double total_ms[VMG_NUM_KCLASS] = {};
+    double total_bytes[VMG_NUM_KCLASS] = {};
+};
+
+namespace {
+
+int dev_malloc(vmg_handle* H, void** p, size_t bytes) {
+    *p = nullptr;
+    if (bytes == 0) bytes = 256;
+    if (hipMalloc(p, bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        *p = nullptr;
+        return VMG_OOM;
+    }
+    H->allocations.push_back(*p);
+    if (hipMemset(*p, 0, bytes) != hipSuccess) return VMG_HIP_ERROR;
+    return VMG_OK;
+}
+
+template <typename T> int alloc_planes(vmg_handle* H, DevBuf& buf, const LevelView& v, int nsys) {
+    const int a = align_elems<T>();
+    const size_t elems = (size_t)v.plane * nsys + a;
+    int rc = dev_malloc(H, &buf.alloc, elems * sizeof(cplx<T>));
+    if (rc) return rc;
+    buf.ptr = static_cast<cplx<T>*>(buf.alloc) + (a - 1);
+    return VMG_OK;
+}
+
+template <typename T> cplx<T>* P(const DevBuf& b) { return static_cast<cplx<T>*>(b.ptr); }
+
+// ---- timing ----
+hipEvent_t get_event(vmg_handle* H) {
+    if (!H->event_pool.empty()) {
+        hipEvent_t e = H->event_pool.back();
+        H->event_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+struct Timer {
+    vmg_handle* H;
+    hipStream_t st;
+    int kclass;
+    double bytes;
+    hipEvent_t a = nullptr;
+    Timer(vmg_handle* H_, hipStream_t st_, int k, double by) : H(H_), st(st_), kclass(k), bytes(by) {
+        if (H->timing) {
+            a = get_event(H);
+            if (a) (void)hipEventRecord(a, st);
+        }
+    }
+    ~Timer() {
+        if (H->timing && a) {
+            hipEvent_t b = get_event(H);
+            if (b) {
+                (void)hipEventRecord(b, st);
+                H->pending.push_back({kclass, bytes, a, b});
+            }
+        }
+    }
+};
+
+int collect_timing(vmg_handle* H) {
+    for (auto& t : H->pending) {
+        if (hipEventSynchronize(t.b) != hipSuccess) return VMG_HIP_ERROR;
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, t.a, t.b) != hipSuccess) return VMG_HIP_ERROR;
+        H->launches[t.kclass] += 1;
+        H->total_ms[t.kclass] += ms;
+        H->total_bytes[t.kclass] += t.bytes;
+        H->event_pool.push_back(t.a);
+        H->event_pool.push_back(t.b);
+    }
+    H->pending.clear();
+    return VMG_OK;
+}
+
+// ---- coefficients (eq. (6)) ----
+void vanka_coef(cd lam, double h, double omega, int smoother, Coef<double>& c) {
+    const cd eta = lam * h * h;
+    const cd d4 = 4.0 / (h * h) + lam;
+    cd ca, cb, cc;
+    if (smoother == 1) {
+        ca = omega / d4;
+        cb = 0.0;
+        cc = 0.0;
+    } else {
+        // a, b, c of eq. (6) over the common denominator (2+eta)(4+eta)(6+eta)
+        const cd den = (2.0 + eta) * (4.0 + eta) * (6.0 + eta);
+        const cd a = (14.0 + 8.0 * eta + eta * eta) / den;
+        const cd b = 1.0 / ((2.0 + eta) * (6.0 + eta));
+        const cd cc_ = 2.0 / den;
+        ca = omega * h * h * a;
+        cb = omega * h * h * b / 2.0;
+        cc = omega * h * h * cc_ / 4.0;
+    }
+    c.d = make_double2(d4.real(), d4.imag());
+    c.ca = make_double2(ca.real(), ca.imag());
+    c.cb = make_double2(cb.real(), cb.imag());
+    c.cc = make_double2(cc.real(), cc.imag());
+}
+
+Coef<float> to_float(const Coef<double>& c) {
+    Coef<float> f;
+    f.d = make_float2((float)c.d.x, (float)c.d.y);
+    f.ca = make_float2((float)c.ca.x, (float)c.ca.y);
+    f.cb = make_float2((float)c.cb.x, (float)c.cb.y);
+    f.cc = make_float2((float)c.cc.x, (float)c.cc.y);
+    return f;
+}
+
+// Inverse of the dense coarsest-grid matrix A_c + lambda I (5-point, Dirichlet,
+// x-fastest) by Gauss-Jordan elimination with partial pivoting.
+int coarse_inverse(int nx, int ny, double h, cd lam, std::vector<cd>& inv) {
+    const int n = nx * ny;
+    std::vector<cd> a((size_t)n * n, 0.0);
+    inv.assign((size_t)n * n, 0.0);
+    const double s = 1.0 / (h * h);
+    for (int k = 0; k < ny; ++k)
+        for (int i = 0; i < nx; ++i) {
+            const int r = k * nx + i;
+            a[(size_t)r * n + r] = 4.0 * s + lam;
+            if (i > 0) a[(size_t)r * n + r - 1] = -s;
+            if (i < nx - 1) a[(size_t)r * n + r + 1] = -s;
+            if (k > 0) a[(size_t)r * n + r - nx] = -s;
+            if (k < ny - 1) a[(size_t)r * n + r + nx] = -s;
+        }
+    double anorm = 0.0;
+    for (auto& v : a) anorm = std::max(anorm, std::abs(v));
+    for (int r = 0; r < n; ++r) inv[(size_t)r * n + r] = 1.0;
+    for (int c = 0; c < n; ++c) {
+        int p = c;
+        for (int r = c + 1; r < n; ++r)
+            if (std::abs(a[(size_t)r * n + c]) > std::abs(a[(size_t)p * n + c])) p = r;
+        if (std::abs(a[(size_t)p * n + c]) <= 1e-13 * anorm) return VMG_SINGULAR;
+        if (p != c)
+            for (int j = 0; j < n; ++j) {
+                std::swap(a[(size_t)p * n + j], a[(size_t)c * n + j]);
+                std::swap(inv[(size_t)p * n + j], inv[(size_t)c * n + j]);
+            }
+        const cd piv = 1.0 / a[(size_t)c * n + c];
+        for (int j = 0; j < n; ++j) {
+            a[(size_t)c * n + j] *= piv;
+            inv[(size_t)c * n + j] *= piv;
+        }
+        for (int r = 0; r < n; ++r) {
+            if (r == c) continue;
+            const cd f = a[(size_t)r * n + c];
+            if (f == 0.0) continue;
+            for (int j = 0; j < n; ++j) {
+                a[(size_t)r * n + j] -= f * a[(size_t)c * n + j];
+                inv[(size_t)r * n + j] -= f * inv[(size_t)c * n + j];
+            }
+        }
+    }
+    return VMG_OK;
+}
+
+template <typename T> const Coef<T>* coef_of(const Group& g, int conj, int level);
+template <> const Coef<double>* coef_of<double>(const Group& g, int conj, int level) {
+    return g.coef64[conj] + (size_t)level * g.S;
+}
+template <> const Coef<float>* coef_of<float>(const Group& g, int conj, int level) {
+    return g.coef32[conj] + (size_t)level * g.S;
+}
+template <typename T> const cplx<T>* cinv_of(const Group& g, int conj);
+template <> const double2* cinv_of<double>(const Group& g, int conj) { return g.cinv64[conj]; }
+template <> const float2* cinv_of<float>(const Group& g, int conj) { return g.cinv32[conj]; }
+template <typename T> std::vector<Level>& levels_of(Group& g);
+template <> std::vector<Level>& levels_of<double>(Group& g) { return g.lv64; }
+template <> std::vector<Level>& levels_of<float>(Group& g) { return g.lv32; }
+
+double nodes(const LevelView& v) { return (double)v.nx * v.ny; }
+
+// ---- one multigrid cycle of one group from `level` (Sec. 3 components) ----
+template <typename T>
+struct CycleCtx {
+    vmg_handle* H;
+    Group* g;
+    int conj;
+    hipStream_t st;
+    std::vector<int> cur;  // which ping-pong buffer holds x, per level
+};
+
+template <typename T> void enqueue_cycle(CycleCtx<T>& c, int l, bool x_zero) {
+    vmg_handle* H = c.H;
+    Group& g = *c.g;
+    auto& L = levels_of<T>(g);
+    Level& lv = L[l];
+    const int* act = H->active + g.sys0;
+    const double E = sizeof(cplx<T>);
+    const T s = (T)(1.0 / (lv.h * lv.h));
+    const Coef<T>* cf = coef_of<T>(g, c.conj, l);
+    if (l == g.L - 1) {
+        Timer t(H, c.st, VMG_K_COARSE, E * ((double)g.nc * g.nc + 2.0 * g.nc) * g.S);
+        launch_coarse<T>(P<T>(lv.b), P<T>(lv.x[c.cur[l]]), lv.v, cinv_of<T>(g, c.conj), g.nc, act, g.S, c.st);
+        return;
+    }
+    const vmg_opts& o = H->opts;
+    for (int i = 0; i < o.nu1; ++i) {
+        Timer t(H, c.st, VMG_K_SWEEP, (x_zero ? 2.0 : 3.0) * E * nodes(lv.v) * g.S);
+        launch_sweep<T>(P<T>(lv.x[c.cur[l]]), P<T>(lv.b), P<T>(lv.x[1 - c.cur[l]]), lv.v, s, cf, act, g.S, x_zero,
+                        c.st);
+        c.cur[l] ^= 1;
+        x_zero = false;
+    }
+    Level& lc = L[l + 1];
+    {
+        Timer t(H, c.st, VMG_K_RESTRICT, ((x_zero ? 1.0 : 2.0) + 0.25) * E * nodes(lv.v) * g.S);
+        launch_restrict<T>(P<T>(lv.x[c.cur[l]]), P<T>(lv.b), P<T>(lc.b), lv.v, lc.v, s, cf, act, g.S, x_zero, c.st);
+    }
+    bool cz = true;
+    for (int k = 0; k < o.gamma; ++k) {
+        enqueue_cycle<T>(c, l + 1, cz);
+        cz = false;
+    }
+    {
+        Timer t(H, c.st, VMG_K_PROLONG, ((x_zero ? 1.0 : 2.0) + 0.25) * E * nodes(lv.v) * g.S);
+        launch_prolong<T>(P<T>(lv.x[c.cur[l]]), P<T>(lc.x[c.cur[l + 1]]), lv.v, lc.v, act, g.S, x_zero, c.st);
+    }
+    x_zero = false;
+    for (int i = 0; i < o.nu2; ++i) {
+        Timer t(H, c.st, VMG_K_SWEEP, 3.0 * E * nodes(lv.v) * g.S);
+        launch_sweep<T>(P<T>(lv.x[c.cur[l]]), P<T>(lv.b), P<T>(lv.x[1 - c.cur[l]]), lv.v, s, cf, act, g.S, 0, c.st);
+        c.cur[l] ^= 1;
+    }
+}
+
+int check_hip() {
+    hipError_t e = hipGetLastError();
+    return e == hipSuccess ? VMG_OK : VMG_HIP_ERROR;
+}
+
+bool valid_grid_level(int n) { return n >= 3 && (n % 2) == 1; }
+
+// residual norms of level 0 of every group, then the convergence update
+int enqueue_norm_check(vmg_handle* H, hipStream_t st, int mode, double tol, int fixed, int conj, int cur) {
+    const bool x_zero = false;
+    for (auto& g : H->groups) {
+        const int* act = H->active + g.sys0;
+        if (H->opts.precision == 0) {
+            Level& l0 = g.lv64[0];
+            Timer t(H, st, VMG_K_NORM, 2.0 * 16.0 * nodes(l0.v) * g.S);
+            launch_residual<double, double>(P<double>(l0.x[cur]), P<double>(l0.b), nullptr, l0.v, l0.v,
+                                            1.0 / (l0.h * l0.h), coef_of<double>(g, conj, 0), act, g.S, x_zero,
+                                            g.partial, st);
+        } else {
+            Level& l0 = g.lv64[0];
+            Level& e0 = g.lv32[0];
+            Timer t(H, st, VMG_K_IR, (2.0 * 16.0 + 8.0) * nodes(l0.v) * g.S);
+            launch_residual<double, float>(P<double>(l0.x[0]), P<double>(l0.b), P<float>(e0.b), l0.v, e0.v,
+                                           1.0 / (l0.h * l0.h), coef_of<double>(g, conj, 0), act, g.S, x_zero,
+                                           g.partial, st);
+        }
+        launch_norm_finalize(g.partial, g.ntiles0, g.S, g.sys0, mode, tol, fixed, H->bb, H->relres, H->iters,
+                             H->active, H->target, H->nanflag, st);
+    }
+    return check_hip();
+}
+
+int solve_impl(vmg_handle* H, const double* B, double* Z, double tol, int conj, const int32_t* fixed,
+               int32_t* iters_out, double* relres_out, hipStream_t st) {
+    const vmg_opts& o = H->opts;
+    const int S = H->S;
+    int maxc = 0;
+    for (int s = 0; s < S; ++s) {
+        H->h_int[s] = fixed ? fixed[s] : o.max_iter;
+        if (H->h_int[s] < 0) return VMG_INVALID_ARG;
+        maxc = std::max(maxc, H->h_int[s]);
+    }
+    VMG_HIP(hipMemcpyAsync(H->target, H->h_int, sizeof(int) * S, hipMemcpyHostToDevice, st));
+    launch_fill_int(H->active, 1, S, st);
+    // pack B and measure ||b_j||
+    int64_t off = 0;
+    for (auto& g : H->groups) {
+        Level& l0 = g.lv64[0];
+        if (B) {
+            Timer t(H, st, VMG_K_PACK, 32.0 * nodes(l0.v) * g.S);
+            launch_pack<double>(reinterpret_cast<const double2*>(B) + off, P<double>(l0.b), l0.v, g.S, st);
+        }
+        off += (int64_t)g.nx * g.ny * g.S;
+    }
+    // ||b_j||: the residual of x = 0
+    for (auto& g : H->groups) {
+        Level& l0 = g.lv64[0];
+        const int* act = H->active + g.sys0;
+        if (o.precision == 0) {
+            Timer t(H, st, VMG_K_NORM, 16.0 * nodes(l0.v) * g.S);
+            launch_residual<double, double>(nullptr, P<double>(l0.b), nullptr, l0.v, l0.v, 1.0, coef_of<double>(g, 0, 0),
+                                            act, g.S, 1, g.partial, st);
+        } else {
+            Level& e0 = g.lv32[0];
+            Timer t(H, st, VMG_K_IR, 24.0 * nodes(l0.v) * g.S);
+            launch_residual<double, float>(nullptr, P<double>(l0.b), P<float>(e0.b), l0.v, e0.v, 1.0,
+                                           coef_of<double>(g, 0, 0), act, g.S, 1, g.partial, st);
+        }
+        launch_norm_finalize(g.partial, g.ntiles0, g.S, g.sys0, 0, tol, fixed != nullptr, H->bb, H->relres, H->iters,
+                             H->active, H->target, H->nanflag, st);
+    }
+    if (check_hip()) return VMG_HIP_ERROR;
+
+    const int batch = std::max(1, o.check_every);
+    int done = 0;
+    while (done < maxc) {
+        const int nb = std::min(batch, maxc - done);
+        for (int c = 0; c < nb; ++c) {
+            const bool first = (done + c) == 0;
+            for (auto& g : H->groups) {
+                if (o.precision == 0) {
+                    CycleCtx<double> ctx{H, &g, conj, st, std::vector<int>(g.L, 0)};
+                    // level-0 buffer parity is a function of the cycles run so far
+                    ctx.cur[0] = (int)(((int64_t)(done + c) * (o.nu1 + o.nu2)) & 1);
+                    enqueue_cycle<double>(ctx, 0, first);
+                } else {
+                    CycleCtx<float> ctx{H, &g, conj, st, std::vector<int>(g.L, 0)};
+                    for (int k = 0; k < o.ir_inner; ++k) enqueue_cycle<float>(ctx, 0, k == 0);
+                    Level& l0 = g.lv64[0];
+                    Level& e0 = g.lv32[0];
+                    Timer t(H, st, VMG_K_IR, (first ? 24.0 : 40.0) * nodes(l0.v) * g.S);
+                    launch_ir_update(P<double>(l0.x[0]), P<float>(e0.x[ctx.cur[0]]), l0.v, e0.v,
+                                     H->active + g.sys0, g.S, first, st);
+                }
+            }
+            const int cur0 = (int)(((int64_t)(done + c + 1) * (o.nu1 + o.nu2)) & 1);
+            if (enqueue_norm_check(H, st, 1, tol, fixed != nullptr, conj, o.precision == 0 ? cur0 : 0))
+                return VMG_HIP_ERROR;
+        }
+        done += nb;
+        VMG_HIP(hipMemcpyAsync(H->h_int + S, H->active, sizeof(int) * S, hipMemcpyDeviceToHost, st));
+        VMG_HIP(hipStreamSynchronize(st));
+        bool any = false;
+        for (int s = 0; s < S; ++s) any |= H->h_int[S + s] != 0;
+        if (!any) break;
+    }
+    off = 0;
+    for (auto& g : H->groups) {
+        Level& l0 = g.lv64[0];
+        Timer t(H, st, VMG_K_PACK, 32.0 * nodes(l0.v) * g.S);
+        const int flips = o.precision == 0 ? (o.nu1 + o.nu2) : 0;
+        launch_unpack<double>(P<double>(l0.x[0]), o.precision == 0 ? P<double>(l0.x[1]) : nullptr,
+                              reinterpret_cast<double2*>(Z) + off, l0.v, g.S, H->iters + g.sys0, flips, st);
+        off += (int64_t)g.nx * g.ny * g.S;
+    }
+    if (check_hip()) return VMG_HIP_ERROR;
+    VMG_HIP(hipMemcpyAsync(H->h_int, H->iters, sizeof(int) * S, hipMemcpyDeviceToHost, st));
+    VMG_HIP(hipMemcpyAsync(H->h_int + S, H->nanflag, sizeof(int) * S, hipMemcpyDeviceToHost, st));
+    VMG_HIP(hipMemcpyAsync(H->h_int + 2 * S, H->active, sizeof(int) * S, hipMemcpyDeviceToHost, st));
+    VMG_HIP(hipMemcpyAsync(H->h_dbl, H->relres, sizeof(double) * S, hipMemcpyDeviceToHost, st));
+    VMG_HIP(hipStreamSynchronize(st));
+    int rc = VMG_OK;
+    for (int s = 0; s < S; ++s) {
+        if (iters_out) iters_out[s] = H->h_int[s];
+        if (relres_out) relres_out[s] = H->h_dbl[s];
+        if (H->h_int[S + s]) rc = VMG_NAN_DETECTED;
+        else if (!fixed && rc == VMG_OK && H->h_dbl[s] > tol) rc = VMG_NOT_CONVERGED;
+    }
+    return rc;
+}
+
+}  // namespace
+
+// ============================================================================
+// C ABI
+// ============================================================================
+extern "C" {
+
+int vanka_mg_default_opts(vmg_opts* o) {
+    if (!o) return VMG_INVALID_ARG;
+    o->omega = 24.0 / 25.0;
+    o->nu1 = 2;
+    o->nu2 = 2;
+    o->gamma = 1;
+    o->max_iter = 100;
+    o->precision = 0;
+    o->smoother = 0;
+    o->ir_inner = 3;
+    o->check_every = 4;
+    return VMG_OK;
+}
+
+const char* vanka_mg_error_string(int code) {
+    switch (code) {
+        case VMG_OK: return "ok";
+        case VMG_NOT_CONVERGED: return "not converged: a system reached max_iter above the tolerance";
+        case VMG_INVALID_ARG: return "invalid argument";
+        case VMG_HIP_ERROR: return "HIP runtime error";
+        case VMG_OOM: return "out of memory";
+        case VMG_SINGULAR: return "singular shifted coarsest-grid matrix";
+        case VMG_NAN_DETECTED: return "NaN or Inf in a residual norm";
+        default: return "unknown error code";
+    }
+}
+
+int vanka_mg_destroy(vmg_handle* H) {
+    if (!H) return VMG_OK;
+    int prev = 0;
+    (void)hipGetDevice(&prev);
+    (void)hipSetDevice(H->device);
+    (void)hipDeviceSynchronize();
+    for (auto& t : H->pending) {
+        (void)hipEventDestroy(t.a);
+        (void)hipEventDestroy(t.b);
+    }
+    for (auto e : H->event_pool) (void)hipEventDestroy(e);
+    for (void* p : H->allocations) (void)hipFree(p);
+    if (H->h_int) (void)hipHostFree(H->h_int);
+    if (H->h_dbl) (void)hipHostFree(H->h_dbl);
+    (void)hipSetDevice(prev);
+    delete H;
+    return VMG_OK;
+}
+
+int vanka_mg_setup(const vmg_grid* grids, int32_t n_grids, const double* shifts, const vmg_opts* opts,
+                   void* hip_stream, vmg_handle** out) {
+    if (!out) return VMG_INVALID_ARG;
+    *out = nullptr;
+    if (!grids || n_grids < 1 || !shifts) return VMG_INVALID_ARG;
+    vmg_opts o;
+    vanka_mg_default_opts(&o);
+    if (opts) o = *opts;
+    if (!(o.omega > 0.0) || o.nu1 < 0 || o.nu2 < 0 || o.nu1 + o.nu2 < 1 || o.gamma < 1 || o.gamma > 2 ||
+        o.max_iter < 1 || o.precision < 0 || o.precision > 1 || o.smoother < 0 || o.smoother > 1 ||
+        o.ir_inner < 1 || o.check_every < 1)
+        return VMG_INVALID_ARG;
+    (void)hip_stream;
+    vmg_handle* H = new (std::nothrow) vmg_handle();
+    if (!H) return VMG_OOM;
+    H->opts = o;
+    if (hipGetDevice(&H->device) != hipSuccess) {
+        delete H;
+        return VMG_HIP_ERROR;
+    }
+    int total = 0;
+    for (int g = 0; g < n_grids; ++g) {
+        const vmg_grid& gr = grids[g];
+        if (gr.nx < 1 || gr.ny < 1 || !(gr.h > 0.0) || gr.num_systems < 1 || gr.levels < 0 || gr.levels > 30) {
+            delete H;
+            return VMG_INVALID_ARG;
+        }
+        Group G;
+        G.nx = gr.nx;
+        G.ny = gr.ny;
+        G.h = gr.h;
+        G.S = gr.num_systems;
+        G.sys0 = total;
+        total += gr.num_systems;
+        // level sizes
+        std::vector<int> nxs{gr.nx}, nys{gr.ny};
+        if (gr.levels > 0) {
+            for (int l = 1; l < gr.levels; ++l) {
+                if (!valid_grid_level(nxs.back()) || !valid_grid_level(nys.back())) {
+                    delete H;
+                    return VMG_INVALID_ARG;
+                }
+                nxs.push_back((nxs.back() - 1) / 2);
+                nys.push_back((nys.back() - 1) / 2);
+            }
+        } else {
+            while (std::min(nxs.back(), nys.back()) > 7) {
+                if (!valid_grid_level(nxs.back()) || !valid_grid_level(nys.back())) {
+                    delete H;
+                    return VMG_INVALID_ARG;
+                }
+                nxs.push_back((nxs.back() - 1) / 2);
+                nys.push_back((nys.back() - 1) / 2);
+            }
+        }
+        G.L = (int)nxs.size();
+        G.nc = nxs.back() * nys.back();
+        if (G.nc > 256 || G.L < 2) {
+            delete H;
+            return VMG_INVALID_ARG;
+        }
+        H->groups.push_back(G);
+        (void)nys;
+        // stash sizes in the level vectors
+        Group& GG = H->groups.back();
+        const int nlev64 = o.precision == 0 ? GG.L : 1;
+        GG.lv64.resize(nlev64);
+        for (int l = 0; l < nlev64; ++l) {
+            GG.lv64[l].v = make_view<double>(nxs[l], nys[l]);
+            GG.lv64[l].h = gr.h * std::ldexp(1.0, l);
+        }
+        if (o.precision == 1) {
+            GG.lv32.resize(GG.L);
+            for (int l = 0; l < GG.L; ++l) {
+                GG.lv32[l].v = make_view<float>(nxs[l], nys[l]);
+                GG.lv32[l].h = gr.h * std::ldexp(1.0, l);
+            }
+        }
+    }
+    H->S = total;
+    H->shifts.resize(total);
+    for (int s = 0; s < total; ++s) H->shifts[s] = cd(shifts[2 * s], shifts[2 * s + 1]);
+
+    int rc = VMG_OK;
+#define VMG_TRY(x)                 \
+    do {                           \
+        rc = (x);                  \
+        if (rc) {                  \
+            vanka_mg_destroy(H);   \
+            return rc;             \
+        }                          \
+    } while (0)
+    // per-system state
+    VMG_TRY(dev_malloc(H, (void**)&H->bb, sizeof(double) * total));
+    VMG_TRY(dev_malloc(H, (void**)&H->relres, sizeof(double) * total));
+    VMG_TRY(dev_malloc(H, (void**)&H->iters, sizeof(int) * total));
+    VMG_TRY(dev_malloc(H, (void**)&H->active, sizeof(int) * total));
+    VMG_TRY(dev_malloc(H, (void**)&H->target, sizeof(int) * total));
+    VMG_TRY(dev_malloc(H, (void**)&H->nanflag, sizeof(int) * total));
+    if (hipHostMalloc((void**)&H->h_int, sizeof(int) * 3 * total) != hipSuccess) VMG_TRY(VMG_OOM);
+    if (hipHostMalloc((void**)&H->h_dbl, sizeof(double) * total) != hipSuccess) VMG_TRY(VMG_OOM);
+
+    for (auto& G : H->groups) {
+        // buffers
+        for (size_t l = 0; l < G.lv64.size(); ++l) {
+            Level& L = G.lv64[l];
+            VMG_TRY(alloc_planes<double>(H, L.x[0], L.v, G.S));
+            if (o.precision == 0) VMG_TRY(alloc_planes<double>(H, L.x[1], L.v, G.S));
+            VMG_TRY(alloc_planes<double>(H, L.b, L.v, G.S));
+        }
+        for (size_t l = 0; l < G.lv32.size(); ++l) {
+            Level& L = G.lv32[l];
+            VMG_TRY(alloc_planes<float>(H, L.x[0], L.v, G.S));
+            VMG_TRY(alloc_planes<float>(H, L.x[1], L.v, G.S));
+            VMG_TRY(alloc_planes<float>(H, L.b, L.v, G.S));
+        }
+        G.ntiles0 = residual_tiles(G.lv64[0].v);
+        VMG_TRY(dev_malloc(H, (void**)&G.partial, sizeof(double) * (size_t)G.ntiles0 * G.S));
+        // coefficients for all levels, both conj variants
+        std::vector<Coef<double>> c64((size_t)G.L * G.S);
+        std::vector<Coef<float>> c32((size_t)G.L * G.S);
+        const int nc = G.nc;
+        std::vector<double2> inv64((size_t)G.S * nc * nc);
+        std::vector<float2> inv32((size_t)G.S * nc * nc);
+        const int cnx = o.precision == 0 ? G.lv64.back().v.nx : G.lv32.back().v.nx;
+        const int cny = o.precision == 0 ? G.lv64.back().v.ny : G.lv32.back().v.ny;
+        const double ch = G.h * std::ldexp(1.0, G.L - 1);
+        for (int conj = 0; conj < 2; ++conj) {
+            for (int l = 0; l < G.L; ++l) {
+                const double hl = G.h * std::ldexp(1.0, l);
+                for (int s = 0; s < G.S; ++s) {
+                    cd lam = H->shifts[G.sys0 + s];
+                    if (conj) lam = std::conj(lam);
+                    vanka_coef(lam, hl, o.omega, o.smoother, c64[(size_t)l * G.S + s]);
+                    c32[(size_t)l * G.S + s] = to_float(c64[(size_t)l * G.S + s]);
+                }
+            }
+            for (int s = 0; s < G.S; ++s) {
+                cd lam = H->shifts[G.sys0 + s];
+                if (conj) lam = std::conj(lam);
+                std::vector<cd> inv;
+                VMG_TRY(coarse_inverse(cnx, cny, ch, lam, inv));
+                for (int r = 0; r < nc; ++r)
+                    for (int k = 0; k < nc; ++k) {
+                        const cd v = inv[(size_t)r * nc + k];
+                        inv64[(size_t)s * nc * nc + (size_t)k * nc + r] = make_double2(v.real(), v.imag());
+                        inv32[(size_t)s * nc * nc + (size_t)k * nc + r] = make_float2((float)v.real(), (float)v.imag());
+                    }
+            }
+            VMG_TRY(dev_malloc(H, (void**)&G.coef64[conj], sizeof(Coef<double>) * c64.size()));
+            VMG_TRY(dev_malloc(H, (void**)&G.coef32[conj], sizeof(Coef<float>) * c32.size()));
+            VMG_TRY(dev_malloc(H, (void**)&G.cinv64[conj], sizeof(double2) * inv64.size()));
+            VMG_TRY(dev_malloc(H, (void**)&G.cinv32[conj], sizeof(float2) * inv32.size()));
+            if (hipMemcpy(G.coef64[conj], c64.data(), sizeof(Coef<double>) * c64.size(), hipMemcpyHostToDevice) ||
+                hipMemcpy(G.coef32[conj], c32.data(), sizeof(Coef<float>) * c32.size(), hipMemcpyHostToDevice) ||
+                hipMemcpy(G.cinv64[conj], inv64.data(), sizeof(double2) * inv64.size(), hipMemcpyHostToDevice) ||
+                hipMemcpy(G.cinv32[conj], inv32.data(), sizeof(float2) * inv32.size(), hipMemcpyHostToDevice))
+                VMG_TRY(VMG_HIP_ERROR);
+        }
+    }
+#undef VMG_TRY
+    *out = H;
+    return VMG_OK;
+}
+
+int vanka_mg_solve(vmg_handle* H, const double* B, double* Z, double tol, int32_t conj, const int32_t* fixed_iters,
+                   int32_t* iters, double* relres, void* hip_stream) {
+    if (!H || !B || !Z || !(tol > 0.0) || B == Z) return VMG_INVALID_ARG;
+    hipStream_t st = (hipStream_t)hip_stream;
+    int rc = solve_impl(H, B, Z, tol, conj ? 1 : 0, fixed_iters, iters, relres, st);
+    return rc;
+}
+
+int vanka_mg_levels(const vmg_handle* H, int32_t g, int32_t* count, int32_t* nx, int32_t* ny) {
+    if (!H || !count || g < 0 || g >= (int)H->groups.size()) return VMG_INVALID_ARG;
+    const Group& G = H->groups[g];
+    *count = G.L;
+    int cx = G.nx, cy = G.ny;
+    for (int l = 0; l < G.L; ++l) {
+        if (nx) nx[l] = cx;
+        if (ny) ny[l] = cy;
+        cx = (cx - 1) / 2;
+        cy = (cy - 1) / 2;
+    }
+    return VMG_OK;
+}
+
+int vanka_mg_set_timing(vmg_handle* H, int32_t enable, int32_t reset) {
+    if (!H) return VMG_INVALID_ARG;
+    int rc = collect_timing(H);
+    if (rc) return rc;
+    H->timing = enable != 0;
+    if (reset) {
+        for (int k = 0; k < VMG_NUM_KCLASS; ++k) {
+            H->launches[k] = 0;
+            H->total_ms[k] = 0;
+            H->total_bytes[k] = 0;
+        }
+    }
+    return VMG_OK;
+}
+
+int vanka_mg_kernel_stats(vmg_handle* H, int64_t* launches, double* total_ms, double* total_bytes) {
+    if (!H) return VMG_INVALID_ARG;
+    int rc = collect_timing(H);
+    if (rc) return rc;
+    for (int k = 0; k < VMG_NUM_KCLASS; ++k) {
+        if (launches) launches[k] = H->launches[k];
+        if (total_ms) total_ms[k] = H->total_ms[k];
+        if (total_bytes) total_bytes[k] = H->total_bytes[k];
+    }
+    return VMG_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// time transform and the ParaDIAG step (eq. (1))
+// ---------------------------------------------------------------------------
+namespace {
+
+// Scratch for the expanded real transform matrix of the stand-alone
+// paradiag_transform entry point: one buffer per device, grown on demand and
+// kept until the process ends.
+struct TransformScratch {
+    void* ptr = nullptr;
+    size_t bytes = 0;
+};
+TransformScratch g_tscratch[64];
+
+int transform_scratch(size_t bytes, double2** out) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return VMG_HIP_ERROR;
+    TransformScratch& sc = g_tscratch[dev];
+    if (sc.bytes < bytes) {
+        if (sc.ptr) {
+            if (hipDeviceSynchronize() != hipSuccess) return VMG_HIP_ERROR;
+            (void)hipFree(sc.ptr);
+            sc.ptr = nullptr;
+            sc.bytes = 0;
+        }
+        if (hipMalloc(&sc.ptr, bytes) != hipSuccess) {
+            (void)hipGetLastError();
+            return VMG_OOM;
+        }
+        sc.bytes = bytes;
+    }
+    *out = static_cast<double2*>(sc.ptr);
+    return VMG_OK;
+}
+
+RowLayout dense_rows(int64_t m) {
+    RowLayout L;
+    L.nx = (int)std::min<int64_t>(m, 1 << 30);
+    L.pitch = L.nx;
+    L.row = m;
+    L.off = 0;
+    return L;
+}
+
+}  // namespace
+
+extern "C" int paradiag_transform(int32_t n, int64_t m, const double* M, int32_t trans_conj, const double* in,
+                                  double* out, void* hip_stream) {
+    if (n < 1 || n > 512 || m < 1 || m >= (int64_t)1 << 30 || !M || !in || !out || in == out)
+        return VMG_INVALID_ARG;
+    double2* mx = nullptr;
+    int rc = transform_scratch(sizeof(double) * 4 * (size_t)n * n, &mx);
+    if (rc) return rc;
+    launch_transform(n, m, reinterpret_cast<const double2*>(M), trans_conj ? 1 : 0,
+                     reinterpret_cast<const double2*>(in), dense_rows(m), reinterpret_cast<double2*>(out),
+                     dense_rows(m), mx, (hipStream_t)hip_stream);
+    return check_hip();
+}
+
+extern "C" int paradiag_apply(vmg_handle* H, const double* V, const double* Vinv, const double* F, double* U,
+                              double tol, int32_t conj, void* hip_stream) {
+    if (!H || !V || !Vinv || !F || !U || !(tol > 0.0)) return VMG_INVALID_ARG;
+    if (H->groups.size() != 1 || H->S > 512) return VMG_INVALID_ARG;
+    hipStream_t st = (hipStream_t)hip_stream;
+    Group& g = H->groups[0];
+    const int n = H->S;
+    const int64_t m = (int64_t)g.nx * g.ny;
+    if (!H->mbuf) {
+        int rc = dev_malloc(H, (void**)&H->mbuf, sizeof(double) * 4 * (size_t)n * n);
+        if (rc) return rc;
+    }
+    if (!H->gbuf) {
+        int rc = dev_malloc(H, (void**)&H->gbuf, sizeof(double2) * (size_t)n * m);
+        if (rc) return rc;
+        H->gbuf_elems = (int64_t)n * m;
+    }
+    // G = (Vinv kron I) F (adjoint: V^H), written straight into the padded
+    // level-0 right-hand sides
+    Level& l0 = g.lv64[0];
+    RowLayout lb;
+    lb.nx = l0.v.nx;
+    lb.pitch = l0.v.pitch;
+    lb.row = l0.v.plane;
+    lb.off = l0.v.pitch + 1;
+    {
+        Timer t(H, st, VMG_K_TRANSFORM, 32.0 * (double)n * m);
+        launch_transform(n, m, reinterpret_cast<const double2*>(conj ? V : Vinv), conj ? 1 : 0,
+                         reinterpret_cast<const double2*>(F), dense_rows(m), P<double>(l0.b), lb, H->mbuf, st);
+    }
+    if (check_hip()) return VMG_HIP_ERROR;
+    int rc = solve_impl(H, nullptr, reinterpret_cast<double*>(H->gbuf), tol, conj ? 1 : 0, nullptr, nullptr,
+                        nullptr, st);
+    if (rc < 0) return rc;
+    {
+        Timer t(H, st, VMG_K_TRANSFORM, 32.0 * (double)n * m);
+        launch_transform(n, m, reinterpret_cast<const double2*>(conj ? Vinv : V), conj ? 1 : 0, H->gbuf,
+                         dense_rows(m), reinterpret_cast<double2*>(U), dense_rows(m), H->mbuf, st);
+    }
+    if (check_hip()) return VMG_HIP_ERROR;
+    return rc;
+}
+
+// ---------------------------------------------------------------------------
+// single operations for tests and tuning
+// ---------------------------------------------------------------------------
+namespace {
+
+template <typename T>
+int apply_op_impl(vmg_handle* H, int op, int level, int conj, const double* x, const double* b, double* out,
+                  hipStream_t st) {
+    // parity operations run on the complex128 hierarchy only
+    int64_t off_f = 0, off_c = 0;
+    for (auto& g : H->groups) {
+        auto& L = levels_of<T>(g);
+        if (level < 0 || level >= g.L || (int)L.size() != g.L) return VMG_INVALID_ARG;
+        const bool needs_coarse = op == VMG_OP_RESTRICT_RESIDUAL || op == VMG_OP_PROLONG_CORRECT;
+        if (needs_coarse && level + 1 >= g.L) return VMG_INVALID_ARG;
+        if (op == VMG_OP_COARSE_SOLVE && level != g.L - 1) return VMG_INVALID_ARG;
+        if ((op == VMG_OP_SWEEP || op == VMG_OP_RESIDUAL || op == VMG_OP_CYCLE) && level == g.L - 1 && op != VMG_OP_CYCLE)
+            ;  // allowed on the coarsest level too
+    }
+    for (auto& g : H->groups) {
+        auto& L = levels_of<T>(g);
+        Level& lv = L[level];
+        const int64_t nf = (int64_t)lv.v.nx * lv.v.ny * g.S;
+        const double2* xf = x ? reinterpret_cast<const double2*>(x) + off_f : nullptr;
+        const int* act = H->active + g.sys0;
+        const T s = (T)(1.0 / (lv.h * lv.h));
+        const Coef<T>* cf = coef_of<T>(g, conj, level);
+        launch_fill_int(H->active + g.sys0, 1, g.S, st);
+        switch (op) {
+            case VMG_OP_SWEEP: {
+                if (xf) launch_pack<T>(xf, P<T>(lv.x[0]), lv.v, g.S, st);
+                launch_pack<T>(reinterpret_cast<const double2*>(b) + off_f, P<T>(lv.b), lv.v, g.S, st);
+                launch_sweep<T>(P<T>(lv.x[0]), P<T>(lv.b), P<T>(lv.x[1]), lv.v, s, cf, act, g.S, xf == nullptr, st);
+                launch_unpack<T>(P<T>(lv.x[1]), nullptr, reinterpret_cast<double2*>(out) + off_f, lv.v, g.S, nullptr, 0,
+                                 st);
+                off_f += nf;
+                break;
+            }
+            case VMG_OP_RESIDUAL: {
+                if (xf) launch_pack<T>(xf, P<T>(lv.x[0]), lv.v, g.S, st);
+                launch_pack<T>(reinterpret_cast<const double2*>(b) + off_f, P<T>(lv.b), lv.v, g.S, st);
+                launch_residual<T, T>(P<T>(lv.x[0]), P<T>(lv.b), P<T>(lv.x[1]), lv.v, lv.v, s, cf, act, g.S,
+                                      xf == nullptr, nullptr, st);
+                launch_unpack<T>(P<T>(lv.x[1]), nullptr, reinterpret_cast<double2*>(out) + off_f, lv.v, g.S, nullptr, 0,
+                                 st);
+                off_f += nf;
+                break;
+            }
+            case VMG_OP_RESTRICT_RESIDUAL: {
+                Level& lc = L[level + 1];
+                if (xf) launch_pack<T>(xf, P<T>(lv.x[0]), lv.v, g.S, st);
+                launch_pack<T>(reinterpret_cast<const double2*>(b) + off_f, P<T>(lv.b), lv.v, g.S, st);
+                launch_restrict<T>(P<T>(lv.x[0]), P<T>(lv.b), P<T>(lc.b), lv.v, lc.v, s, cf, act, g.S, xf == nullptr,
+                                   st);
+                launch_unpack<T>(P<T>(lc.b), nullptr, reinterpret_cast<double2*>(out) + off_c, lc.v, g.S, nullptr, 0,
+                                 st);
+                off_f += nf;
+                off_c += (int64_t)lc.v.nx * lc.v.ny * g.S;
+                break;
+            }
+            case VMG_OP_PROLONG_CORRECT: {
+                Level& lc = L[level + 1];
+                if (!xf) return VMG_INVALID_ARG;
+                launch_pack<T>(xf, P<T>(lv.x[0]), lv.v, g.S, st);
+                launch_pack<T>(reinterpret_cast<const double2*>(b) + off_c, P<T>(lc.x[0]), lc.v, g.S, st);
+                launch_prolong<T>(P<T>(lv.x[0]), P<T>(lc.x[0]), lv.v, lc.v, act, g.S, 0, st);
+                launch_unpack<T>(P<T>(lv.x[0]), nullptr, reinterpret_cast<double2*>(out) + off_f, lv.v, g.S, nullptr, 0,
+                                 st);
+                off_f += nf;
+                off_c += (int64_t)lc.v.nx * lc.v.ny * g.S;
+                break;
+            }
+            case VMG_OP_COARSE_SOLVE: {
+                launch_pack<T>(reinterpret_cast<const double2*>(b) + off_f, P<T>(lv.b), lv.v, g.S, st);
+                launch_coarse<T>(P<T>(lv.b), P<T>(lv.x[0]), lv.v, cinv_of<T>(g, conj), g.nc, act, g.S, st);
+                launch_unpack<T>(P<T>(lv.x[0]), nullptr, reinterpret_cast<double2*>(out) + off_f, lv.v, g.S, nullptr, 0,
+                                 st);
+                off_f += nf;
+                break;
+            }
+            case VMG_OP_CYCLE: {
+                if (xf) launch_pack<T>(xf, P<T>(lv.x[0]), lv.v, g.S, st);
+                launch_pack<T>(reinterpret_cast<const double2*>(b) + off_f, P<T>(lv.b), lv.v, g.S, st);
+                CycleCtx<T> ctx{H, &g, conj, st, std::vector<int>(g.L, 0)};
+                enqueue_cycle<T>(ctx, level, xf == nullptr);
+                launch_unpack<T>(P<T>(lv.x[ctx.cur[level]]), nullptr, reinterpret_cast<double2*>(out) + off_f, lv.v, g.S,
+                                 nullptr, 0, st);
+                off_f += nf;
+                break;
+            }
+            default: return VMG_INVALID_ARG;
+        }
+    }
+    return check_hip();
+}
+
+}  // namespace
+
+extern "C" int vanka_mg_apply_op(vmg_handle* H, int32_t op, int32_t level, int32_t conj, const double* x,
+                                 const double* b, double* out, void* hip_stream) {
+    if (!H || !b || !out) return VMG_INVALID_ARG;
+    if (H->opts.precision != 0) return VMG_INVALID_ARG;
+    return apply_op_impl<double>(H, op, level, conj ? 1 : 0, x, b, out, (hipStream_t)hip_stream);
+}

@@ -1,0 +1,134 @@
+// Time transform of eq. (1): out = (M kron I_m) in, a complex (n x n) by
+// (n x m) product, on the FP64 matrix cores of gfx950, and the ParaDIAG step
+// that wraps the shifted solves between two such transforms.
+//
+// The complex product is run as one real GEMM of twice the size: with
+// interleaved storage, the real row index 2i + c of `in` is component c of
+// complex row i, and the expanded real matrix
+//   Mx[2i][2k] = Re M_ik, Mx[2i][2k+1] = -Im M_ik,
+//   Mx[2i+1][2k] = Im M_ik, Mx[2i+1][2k+1] = Re M_ik
+// maps it to the same interleaved layout of `out` (8 n^2 m flops, no waste).
+#include <hip/hip_runtime.h>
+
+#include "vmg_internal.h"
+
+namespace vmg {
+
+namespace {
+
+typedef double dbl4 __attribute__((ext_vector_type(4)));
+
+constexpr int TN = 256;        // threads per block, 4 waves
+constexpr int ROWS = 256;      // real output rows per block (64 per wave)
+constexpr int COLS = 64;       // grid nodes per block
+constexpr int KC = 16;         // real K per LDS chunk (8 complex time slices)
+
+// Mx from M (or M^H when trans_conj), n2 = 2n.
+__global__ void k_expand(const double2* __restrict__ M, int n, int trans_conj, double* __restrict__ Mx) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n * n) return;
+    const int i = t / n, k = t - i * n;
+    double2 v = trans_conj ? M[(int64_t)k * n + i] : M[(int64_t)i * n + k];
+    if (trans_conj) v.y = -v.y;
+    const int64_t n2 = 2 * (int64_t)n;
+    Mx[(2 * i) * n2 + 2 * k] = v.x;
+    Mx[(2 * i) * n2 + 2 * k + 1] = -v.y;
+    Mx[(2 * i + 1) * n2 + 2 * k] = v.y;
+    Mx[(2 * i + 1) * n2 + 2 * k + 1] = v.x;
+}
+
+__device__ __forceinline__ int tile_row_perm(int r) { return 2 * ((r & 3) + 4 * (r >> 3)) + ((r >> 2) & 1); }
+
+__device__ __forceinline__ int64_t node_off(const RowLayout& L, int64_t p) {
+    const int64_t r = p / L.nx;
+    return L.off + r * L.pitch + (p - r * L.nx);
+}
+
+// One block: real rows [rb*ROWS, +ROWS) x nodes [cb*COLS, +COLS).
+// Wave w owns rows w*64..w*64+63 as 4 x 4 MFMA 16x16 tiles.
+// v_mfma_f64_16x16x4_f64 lane layout (measured on gfx950): A[i][k] at lane
+// i + 16k, B[k][j] at lane j + 16k, D[i][j] at lane j + 16(i%4), element
+// i/4.  A lane therefore holds tile rows g, g+4, g+8, g+12 (g = lane/16).
+// Feeding MFMA row r from real row perm(r) = 2((r%4) + 4(r/8)) + (r/4)%2
+// makes those four values (re, im) of complex rows g and g+4 of the tile's
+// eight complex rows, so each lane stores two whole double2 results.
+__global__ __launch_bounds__(TN) void k_transform(int n, int64_t m, const double* __restrict__ Mx,
+                                                  const double2* __restrict__ in, RowLayout li,
+                                                  double2* __restrict__ out, RowLayout lo) {
+    __shared__ double sA[ROWS][KC + 1];
+    __shared__ double sB[KC][COLS + 1];
+    const int n2 = 2 * n;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int row0 = blockIdx.y * ROWS;
+    const int64_t col0 = (int64_t)blockIdx.x * COLS;
+    const int wrow = row0 + wave * 64;
+    const bool wave_active = wrow < n2;
+    const int arow = tile_row_perm(lane & 15);
+    dbl4 acc[4][4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) acc[a][b] = dbl4{0.0, 0.0, 0.0, 0.0};
+
+    for (int kc = 0; kc < n2; kc += KC) {
+        // A chunk: ROWS x KC from Mx (L2 resident)
+        for (int t = threadIdx.x; t < ROWS * KC; t += TN) {
+            const int r = t / KC, k = t - r * KC;
+            const int gr = row0 + r, gk = kc + k;
+            sA[r][k] = (gr < n2 && gk < n2) ? Mx[(int64_t)gr * n2 + gk] : 0.0;
+        }
+        // B chunk: KC/2 complex rows x COLS nodes
+        for (int t = threadIdx.x; t < (KC / 2) * COLS; t += TN) {
+            const int kr = t / COLS, c = t - kr * COLS;
+            const int gk = kc / 2 + kr;
+            const int64_t p = col0 + c;
+            double2 v = make_double2(0.0, 0.0);
+            if (gk < n && p < m) v = in[(int64_t)gk * li.row + node_off(li, p)];
+            sB[2 * kr][c] = v.x;
+            sB[2 * kr + 1][c] = v.y;
+        }
+        __syncthreads();
+        if (wave_active) {
+#pragma unroll
+            for (int ks = 0; ks < KC; ks += 4) {
+                double av[4], bv[4];
+#pragma unroll
+                for (int a = 0; a < 4; ++a) av[a] = sA[wave * 64 + a * 16 + arow][ks + (lane >> 4)];
+#pragma unroll
+                for (int b = 0; b < 4; ++b) bv[b] = sB[ks + (lane >> 4)][b * 16 + (lane & 15)];
+#pragma unroll
+                for (int a = 0; a < 4; ++a)
+#pragma unroll
+                    for (int b = 0; b < 4; ++b)
+                        acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], bv[b], acc[a][b], 0, 0, 0);
+            }
+        }
+        __syncthreads();
+    }
+    if (!wave_active) return;
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+        // complex rows of this lane: cr and cr + 4 (elements 0,1 and 2,3)
+        const int cr = (wrow + a * 16) / 2 + (lane >> 4);
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            const int64_t p = col0 + b * 16 + (lane & 15);
+            if (p >= m) continue;
+            const int64_t o = node_off(lo, p);
+            if (cr < n) out[(int64_t)cr * lo.row + o] = make_double2(acc[a][b][0], acc[a][b][1]);
+            if (cr + 4 < n) out[(int64_t)(cr + 4) * lo.row + o] = make_double2(acc[a][b][2], acc[a][b][3]);
+        }
+    }
+}
+
+}  // namespace
+
+void launch_transform(int n, int64_t m, const double2* M, int trans_conj, const double2* in, RowLayout li,
+                      double2* out, RowLayout lo, double2* mbuf, hipStream_t st) {
+    double* Mx = reinterpret_cast<double*>(mbuf);
+    hipLaunchKernelGGL(k_expand, dim3((n * n + 255) / 256), dim3(256), 0, st, M, n, trans_conj, Mx);
+    const dim3 grid((unsigned)((m + COLS - 1) / COLS), (unsigned)((2 * n + ROWS - 1) / ROWS));
+    hipLaunchKernelGGL(k_transform, grid, dim3(TN), 0, st, n, m, Mx, in, li, out, lo);
+}
+
+}  // namespace vmg

@@ -1,0 +1,174 @@
+"""Python face of the HIP library: torch tensors in, torch tensors out.
+
+Only argument marshalling happens here; every step of the solve runs in the
+library's kernels.  torch provides device memory and the current stream.
+"""
+import ctypes
+
+import numpy as np
+import torch
+
+from . import _lib
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _require_gpu():
+    if not torch.cuda.is_available():
+        raise RuntimeError("the Vanka multigrid library needs a ROCm GPU (torch.cuda is unavailable)")
+
+
+class Grid:
+    """One grid and the number of shifted systems solved on it."""
+
+    def __init__(self, nx, ny=None, h=None, num_systems=1, levels=0):
+        self.nx = int(nx)
+        self.ny = int(nx if ny is None else ny)
+        self.h = float(1.0 / (self.nx + 1) if h is None else h)
+        self.num_systems = int(num_systems)
+        self.levels = int(levels)
+
+    def to_c(self):
+        return _lib.VmgGrid(self.nx, self.ny, self.h, self.levels, self.num_systems)
+
+
+class VankaMG:
+    """Setup, solve and ParaDIAG application for batches of shifted systems
+    (A + lambda_j I) z_j = b_j on one or more grids.
+
+    precision: "c128" (complex128 cycles) or "c64_ir" (complex64 cycles inside
+    FP64 iterative refinement).  smoother: "vanka" or "jacobi".
+    """
+
+    def __init__(self, grids, shifts, omega=24.0 / 25.0, nu1=2, nu2=2, gamma=1, max_iter=100,
+                 precision="c128", smoother="vanka", ir_inner=3, check_every=4):
+        _require_gpu()
+        self.lib = _lib.load()
+        if isinstance(grids, Grid):
+            grids = [grids]
+        self.grids = list(grids)
+        shifts = np.ascontiguousarray(np.asarray(shifts, dtype=np.complex128).ravel())
+        self.num_systems = sum(g.num_systems for g in self.grids)
+        if shifts.size != self.num_systems:
+            raise ValueError(f"{shifts.size} shifts for {self.num_systems} systems")
+        self.shifts = shifts
+        self.device = torch.cuda.current_device()
+        opts = _lib.VmgOpts()
+        self.lib.vanka_mg_default_opts(ctypes.byref(opts))
+        opts.omega = omega
+        opts.nu1, opts.nu2, opts.gamma, opts.max_iter = nu1, nu2, gamma, max_iter
+        opts.precision = {"c128": 0, "c64_ir": 1}[precision]
+        opts.smoother = {"vanka": 0, "jacobi": 1}[smoother]
+        opts.ir_inner, opts.check_every = ir_inner, check_every
+        self.opts = opts
+        self.precision = precision
+        arr = (_lib.VmgGrid * len(self.grids))(*[g.to_c() for g in self.grids])
+        handle = ctypes.c_void_p()
+        sh = shifts.view(np.float64)
+        code = self.lib.vanka_mg_setup(arr, len(self.grids), sh.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                       ctypes.byref(opts), _stream(), ctypes.byref(handle))
+        _lib.check(code, "vanka_mg_setup")
+        self.handle = handle
+        self.sizes = [g.nx * g.ny * g.num_systems for g in self.grids]
+        self.total = sum(self.sizes)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            self.lib.vanka_mg_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def levels(self, g=0):
+        cnt = ctypes.c_int32()
+        nx = (ctypes.c_int32 * 32)()
+        ny = (ctypes.c_int32 * 32)()
+        _lib.check(self.lib.vanka_mg_levels(self.handle, g, ctypes.byref(cnt), nx, ny), "vanka_mg_levels")
+        return [(nx[i], ny[i]) for i in range(cnt.value)]
+
+    def _check_vec(self, t, n, name):
+        if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.complex128 and t.is_contiguous()):
+            raise TypeError(f"{name} must be a contiguous complex128 CUDA tensor")
+        if t.numel() != n:
+            raise ValueError(f"{name} has {t.numel()} elements, expected {n}")
+
+    def solve(self, B, tol=1e-10, conj=False, fixed_iters=None, out=None):
+        """Solve every system; B holds all systems concatenated (any shape with
+        the right number of elements).  Returns (Z, iters, relres, status)."""
+        self._check_vec(B, self.total, "B")
+        Z = torch.empty_like(B) if out is None else out
+        self._check_vec(Z, self.total, "out")
+        iters = np.zeros(self.num_systems, dtype=np.int32)
+        relres = np.zeros(self.num_systems, dtype=np.float64)
+        fx = None
+        if fixed_iters is not None:
+            fa = np.ascontiguousarray(np.asarray(fixed_iters, dtype=np.int32).ravel())
+            if fa.size != self.num_systems:
+                raise ValueError("fixed_iters needs one count per system")
+            fx = fa.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+        code = self.lib.vanka_mg_solve(self.handle, _ptr(B), _ptr(Z), float(tol), int(bool(conj)), fx,
+                                       iters.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                                       relres.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), _stream())
+        if fixed_iters is not None:
+            self._keep = fa
+        status = _lib.check(code, "vanka_mg_solve")
+        return Z, iters, relres, status
+
+    def apply_op(self, op, level, b, x=None, conj=False, out_numel=None):
+        """One solver operation (``_lib.OP_*``) on caller data at `level`."""
+        out = torch.empty(out_numel if out_numel is not None else b.numel(), dtype=torch.complex128,
+                          device=b.device)
+        code = self.lib.vanka_mg_apply_op(self.handle, op, level, int(bool(conj)),
+                                          _ptr(x) if x is not None else None, _ptr(b), _ptr(out), _stream())
+        _lib.check(code, "vanka_mg_apply_op")
+        return out
+
+    def paradiag_apply(self, V, Vinv, F, tol=1e-10, conj=False, out=None):
+        """U = (V kron I) blockdiag(L_j^{-1}) (Vinv kron I) F (eq. (1)); with
+        conj the adjoint (V^{-H} kron I) blockdiag(L_j^{-H}) (V^H kron I) F."""
+        n = self.num_systems
+        for t, nm in ((V, "V"), (Vinv, "Vinv")):
+            self._check_vec(t, n * n, nm)
+        self._check_vec(F, self.total, "F")
+        U = torch.empty_like(F) if out is None else out
+        code = self.lib.paradiag_apply(self.handle, _ptr(V), _ptr(Vinv), _ptr(F), _ptr(U), float(tol),
+                                       int(bool(conj)), _stream())
+        status = _lib.check(code, "paradiag_apply")
+        return U, status
+
+    def set_timing(self, enable=True, reset=True):
+        _lib.check(self.lib.vanka_mg_set_timing(self.handle, int(enable), int(reset)), "vanka_mg_set_timing")
+
+    def kernel_stats(self):
+        """{class: (launches, total_ms, total_algorithmic_bytes)}"""
+        n = _lib.NUM_KCLASS
+        la = (ctypes.c_int64 * n)()
+        ms = (ctypes.c_double * n)()
+        by = (ctypes.c_double * n)()
+        _lib.check(self.lib.vanka_mg_kernel_stats(self.handle, la, ms, by), "vanka_mg_kernel_stats")
+        return {k: (la[i], ms[i], by[i]) for i, k in enumerate(_lib.KERNEL_CLASSES)}
+
+
+def transform(M, F, trans_conj=False, out=None):
+    """out = (M kron I) F for complex128 CUDA tensors M (n x n) and F (n x m)."""
+    _require_gpu()
+    lib = _lib.load()
+    n = M.shape[0]
+    m = F.numel() // n
+    for t in (M, F):
+        if not (t.is_cuda and t.dtype == torch.complex128 and t.is_contiguous()):
+            raise TypeError("transform needs contiguous complex128 CUDA tensors")
+    out = torch.empty_like(F) if out is None else out
+    code = lib.paradiag_transform(n, m, _ptr(M), int(bool(trans_conj)), _ptr(F), _ptr(out), _stream())
+    _lib.check(code, "paradiag_transform")
+    return out
