@@ -190,6 +190,14 @@ int vanka_mg_set_timing(vmg_handle* h, int32_t enable, int32_t reset);
 int vanka_mg_kernel_stats(vmg_handle* h, int64_t* launches /* [VMG_NUM_KCLASS] */,
                           double* total_ms, double* total_bytes);
 
+/*
+ * Per-system results of the last vanka_mg_solve or paradiag_apply on this
+ * handle: cycles (refinement steps) run and final relative residual.  Host
+ * arrays of the handle's system count (either may be NULL); synchronises
+ * hip_stream.  Returns VMG_OK, VMG_INVALID_ARG, VMG_HIP_ERROR.
+ */
+int vanka_mg_last_stats(vmg_handle* h, int32_t* iters, double* relres, void* hip_stream);
+
 /* Levels of grid g: writes count and, if non-NULL, nx/ny per level. */
 int vanka_mg_levels(const vmg_handle* h, int32_t g, int32_t* count, int32_t* nx, int32_t* ny);
 

@@ -29,7 +29,7 @@ NUM_KCLASS = len(KERNEL_CLASSES)
 
 EXPORTED = ["vanka_mg_default_opts", "vanka_mg_setup", "vanka_mg_solve", "paradiag_apply",
             "paradiag_transform", "vanka_mg_apply_op", "vanka_mg_set_timing", "vanka_mg_kernel_stats",
-            "vanka_mg_levels", "vanka_mg_destroy", "vanka_mg_error_string"]
+            "vanka_mg_levels", "vanka_mg_last_stats", "vanka_mg_destroy", "vanka_mg_error_string"]
 
 
 class VmgGrid(ctypes.Structure):
@@ -69,6 +69,7 @@ def load():
     lib.vanka_mg_set_timing.argtypes = [vp, i32, i32]
     lib.vanka_mg_kernel_stats.argtypes = [vp, pi64, pdbl, pdbl]
     lib.vanka_mg_levels.argtypes = [vp, i32, pi32, pi32, pi32]
+    lib.vanka_mg_last_stats.argtypes = [vp, pi32, pdbl, vp]
     lib.vanka_mg_destroy.argtypes = [vp]
     lib.vanka_mg_error_string.argtypes = [ctypes.c_int]
     lib.vanka_mg_error_string.restype = ctypes.c_char_p

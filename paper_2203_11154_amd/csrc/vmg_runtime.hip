@@ -694,6 +694,15 @@ int vanka_mg_solve(vmg_handle* H, const double* B, double* Z, double tol, int32_
     return rc;
 }
 
+int vanka_mg_last_stats(vmg_handle* H, int32_t* iters, double* relres, void* hip_stream) {
+    if (!H) return VMG_INVALID_ARG;
+    hipStream_t st = (hipStream_t)hip_stream;
+    if (iters) VMG_HIP(hipMemcpyAsync(iters, H->iters, sizeof(int) * H->S, hipMemcpyDeviceToHost, st));
+    if (relres) VMG_HIP(hipMemcpyAsync(relres, H->relres, sizeof(double) * H->S, hipMemcpyDeviceToHost, st));
+    VMG_HIP(hipStreamSynchronize(st));
+    return VMG_OK;
+}
+
 int vanka_mg_levels(const vmg_handle* H, int32_t g, int32_t* count, int32_t* nx, int32_t* ny) {
     if (!H || !count || g < 0 || g >= (int)H->groups.size()) return VMG_INVALID_ARG;
     const Group& G = H->groups[g];

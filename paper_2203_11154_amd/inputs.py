@@ -43,7 +43,7 @@ def alpha_circulant_vectors(n, alpha=0.01):
     scale = alpha ** (i / n)
     V = F / scale[:, None]
     Vinv = (F.conj().T * scale[None, :]) / n
-    return V, Vinv
+    return np.ascontiguousarray(V), np.ascontiguousarray(Vinv)
 
 
 def uniform_shifts(S, seed=SEED_SHIFTS, re=(1.0, 1e4), im=(-1e4, 1e4)):

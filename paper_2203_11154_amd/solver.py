@@ -146,6 +146,15 @@ class VankaMG:
         status = _lib.check(code, "paradiag_apply")
         return U, status
 
+    def last_stats(self):
+        """(iters, relres) per system of the last solve or ParaDIAG step."""
+        iters = np.zeros(self.num_systems, dtype=np.int32)
+        relres = np.zeros(self.num_systems, dtype=np.float64)
+        _lib.check(self.lib.vanka_mg_last_stats(self.handle, iters.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                                                relres.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), _stream()),
+                   "vanka_mg_last_stats")
+        return iters, relres
+
     def set_timing(self, enable=True, reset=True):
         _lib.check(self.lib.vanka_mg_set_timing(self.handle, int(enable), int(reset)), "vanka_mg_set_timing")
 
