@@ -26,6 +26,18 @@ METRIC = "shifted systems solved/s to 1e-10 rel. residual, FP32+IR vs FP64; HBM 
 HBM_PEAK_GBS = 8000.0
 FP64_MFMA_PEAK_TFLOPS = 78.6
 
+# HBM bytes per launch of the sweep kernel measured with rocprofv3 FETCH_SIZE
+# and WRITE_SIZE on this workload, each scaled by its reading for a plain
+# 1 GiB copy (profiles/plain_1023_fp64_kernels.md).  Valid only for the
+# kernel source it was measured on: reported as null once that changes.
+MEASURED_TRAFFIC = {"source_sha256_16": "8ce47553b4ed082f", "sweep_bytes_per_launch": 701.1e6}
+
+
+def kernel_source_hash():
+    import hashlib
+    path = os.path.join(ROOT, "paper_2203_11154_amd", "csrc", "vmg_kernels.hip")
+    return hashlib.sha256(open(path, "rb").read()).hexdigest()[:16]
+
 
 def parse():
     p = argparse.ArgumentParser()
@@ -38,6 +50,8 @@ def parse():
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-ir", action="store_true")
     p.add_argument("--cpu-sample", type=int, default=2, help="systems the oracle solves for the CPU baseline")
+    p.add_argument("--copy-calibration", action="store_true",
+                   help="run one plain 1 GiB device copy first (reference for hardware byte counters)")
     return p.parse_args()
 
 
@@ -88,6 +102,13 @@ def main():
     Ud = torch.empty_like(Fd)
     del F_host
 
+    if args.copy_calibration:
+        src = torch.ones(1 << 27, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+
     solver = VankaMG([Grid(n, num_systems=S)], lam)
     for _ in range(args.warmup):
         solver.paradiag_apply(Vd, Vinvd, Fd, tol=tol, out=Ud)
@@ -104,9 +125,12 @@ def main():
     # dominant kernel: the Vanka sweep (HBM bound)
     la, ms, by = stats["sweep"]
     sweep_gbs = by / (ms * 1e-3) / 1e9
+    traffic = None
+    if kernel_source_hash() == MEASURED_TRAFFIC["source_sha256_16"]:
+        traffic = MEASURED_TRAFFIC["sweep_bytes_per_launch"]
     roofline = {"bound": "hbm", "kernel": "k_sweep<double,16>", "achieved": round(sweep_gbs, 1),
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(sweep_gbs / HBM_PEAK_GBS, 4),
-                "traffic": None, "launches": la, "avg_ms": round(ms / max(la, 1), 5),
+                "traffic": traffic, "launches": la, "avg_ms": round(ms / max(la, 1), 5),
                 "algorithmic_bytes_per_launch": round(by / max(la, 1)),
                 "bytes_per_node": "48 (read x, b; write x'), 32 when x = 0"}
     tl, tms, tby = stats["transform"]

@@ -70,6 +70,7 @@ struct Group {
     int nc = 0;
     double* partial = nullptr;
     int ntiles0 = 0;
+    int nact = 0;   // systems active at the last host check (for byte accounting)
 };
 
 struct TimedLaunch {
@@ -303,13 +304,13 @@ template <typename T> void enqueue_cycle(CycleCtx<T>& c, int l, bool x_zero) {
     const T s = (T)(1.0 / (lv.h * lv.h));
     const Coef<T>* cf = coef_of<T>(g, c.conj, l);
     if (l == g.L - 1) {
-        Timer t(H, c.st, VMG_K_COARSE, E * ((double)g.nc * g.nc + 2.0 * g.nc) * g.S);
+        Timer t(H, c.st, VMG_K_COARSE, E * ((double)g.nc * g.nc + 2.0 * g.nc) * g.nact);
         launch_coarse<T>(P<T>(lv.b), P<T>(lv.x[c.cur[l]]), lv.v, cinv_of<T>(g, c.conj), g.nc, act, g.S, c.st);
         return;
     }
     const vmg_opts& o = H->opts;
     for (int i = 0; i < o.nu1; ++i) {
-        Timer t(H, c.st, VMG_K_SWEEP, (x_zero ? 2.0 : 3.0) * E * nodes(lv.v) * g.S);
+        Timer t(H, c.st, VMG_K_SWEEP, (x_zero ? 2.0 : 3.0) * E * nodes(lv.v) * g.nact);
         launch_sweep<T>(P<T>(lv.x[c.cur[l]]), P<T>(lv.b), P<T>(lv.x[1 - c.cur[l]]), lv.v, s, cf, act, g.S, x_zero,
                         c.st);
         c.cur[l] ^= 1;
@@ -317,7 +318,7 @@ template <typename T> void enqueue_cycle(CycleCtx<T>& c, int l, bool x_zero) {
     }
     Level& lc = L[l + 1];
     {
-        Timer t(H, c.st, VMG_K_RESTRICT, ((x_zero ? 1.0 : 2.0) + 0.25) * E * nodes(lv.v) * g.S);
+        Timer t(H, c.st, VMG_K_RESTRICT, ((x_zero ? 1.0 : 2.0) + 0.25) * E * nodes(lv.v) * g.nact);
         launch_restrict<T>(P<T>(lv.x[c.cur[l]]), P<T>(lv.b), P<T>(lc.b), lv.v, lc.v, s, cf, act, g.S, x_zero, c.st);
     }
     bool cz = true;
@@ -326,12 +327,12 @@ template <typename T> void enqueue_cycle(CycleCtx<T>& c, int l, bool x_zero) {
         cz = false;
     }
     {
-        Timer t(H, c.st, VMG_K_PROLONG, ((x_zero ? 1.0 : 2.0) + 0.25) * E * nodes(lv.v) * g.S);
+        Timer t(H, c.st, VMG_K_PROLONG, ((x_zero ? 1.0 : 2.0) + 0.25) * E * nodes(lv.v) * g.nact);
         launch_prolong<T>(P<T>(lv.x[c.cur[l]]), P<T>(lc.x[c.cur[l + 1]]), lv.v, lc.v, act, g.S, x_zero, c.st);
     }
     x_zero = false;
     for (int i = 0; i < o.nu2; ++i) {
-        Timer t(H, c.st, VMG_K_SWEEP, 3.0 * E * nodes(lv.v) * g.S);
+        Timer t(H, c.st, VMG_K_SWEEP, 3.0 * E * nodes(lv.v) * g.nact);
         launch_sweep<T>(P<T>(lv.x[c.cur[l]]), P<T>(lv.b), P<T>(lv.x[1 - c.cur[l]]), lv.v, s, cf, act, g.S, 0, c.st);
         c.cur[l] ^= 1;
     }
@@ -351,14 +352,14 @@ int enqueue_norm_check(vmg_handle* H, hipStream_t st, int mode, double tol, int 
         const int* act = H->active + g.sys0;
         if (H->opts.precision == 0) {
             Level& l0 = g.lv64[0];
-            Timer t(H, st, VMG_K_NORM, 2.0 * 16.0 * nodes(l0.v) * g.S);
+            Timer t(H, st, VMG_K_NORM, 2.0 * 16.0 * nodes(l0.v) * g.nact);
             launch_residual<double, double>(P<double>(l0.x[cur]), P<double>(l0.b), nullptr, l0.v, l0.v,
                                             1.0 / (l0.h * l0.h), coef_of<double>(g, conj, 0), act, g.S, x_zero,
                                             g.partial, st);
         } else {
             Level& l0 = g.lv64[0];
             Level& e0 = g.lv32[0];
-            Timer t(H, st, VMG_K_IR, (2.0 * 16.0 + 8.0) * nodes(l0.v) * g.S);
+            Timer t(H, st, VMG_K_IR, (2.0 * 16.0 + 8.0) * nodes(l0.v) * g.nact);
             launch_residual<double, float>(P<double>(l0.x[0]), P<double>(l0.b), P<float>(e0.b), l0.v, e0.v,
                                            1.0 / (l0.h * l0.h), coef_of<double>(g, conj, 0), act, g.S, x_zero,
                                            g.partial, st);
@@ -367,6 +368,76 @@ int enqueue_norm_check(vmg_handle* H, hipStream_t st, int mode, double tol, int 
                              H->active, H->target, H->nanflag, st);
     }
     return check_hip();
+}
+
+// Copy active flags, iteration counts and relative residuals to the host and
+// refresh the per-group active counts.
+int read_state(vmg_handle* H, hipStream_t st) {
+    const int S = H->S;
+    VMG_HIP(hipMemcpyAsync(H->h_int + S, H->active, sizeof(int) * S, hipMemcpyDeviceToHost, st));
+    VMG_HIP(hipMemcpyAsync(H->h_int + 2 * S, H->iters, sizeof(int) * S, hipMemcpyDeviceToHost, st));
+    VMG_HIP(hipMemcpyAsync(H->h_dbl, H->relres, sizeof(double) * S, hipMemcpyDeviceToHost, st));
+    VMG_HIP(hipStreamSynchronize(st));
+    for (auto& g : H->groups) {
+        g.nact = 0;
+        for (int s = 0; s < g.S; ++s) g.nact += H->h_int[S + g.sys0 + s] != 0;
+    }
+    return VMG_OK;
+}
+
+bool any_active(const vmg_handle* H) {
+    for (auto& g : H->groups)
+        if (g.nact) return true;
+    return false;
+}
+
+// Two-grid factor rho(nu) of the smoother (Table 1 of the paper: Vanka with
+// omega = 24/25 and damped Jacobi with omega = 4/5), used only to size the
+// first batch of cycles.
+double rho_estimate(const vmg_opts& o) {
+    static const double vanka[4] = {0.28, 0.116, 0.082, 0.064};
+    static const double jacobi[4] = {0.60, 0.36, 0.216, 0.137};
+    const int nu = std::max(1, o.nu1 + o.nu2);
+    const double* t = o.smoother == 0 ? vanka : jacobi;
+    double r = nu <= 4 ? t[nu - 1] : std::pow(t[3], nu / 4.0);
+    if (o.gamma == 1) r = std::min(0.9, 1.2 * r);  // V-cycles lose a little against two-grid
+    if (o.precision == 1) r = std::max(std::pow(r, o.ir_inner), 1e-5);
+    return r;
+}
+
+int first_batch(const vmg_opts& o, double tol, const int32_t* fixed, const vmg_handle* H, int maxc) {
+    if (fixed) {
+        int b = maxc;
+        for (int s = 0; s < H->S; ++s)
+            if (H->h_int[H->S + s]) b = std::min(b, fixed[s]);
+        return std::max(1, b);
+    }
+    const double r = rho_estimate(o);
+    const int est = (int)std::floor(std::log(tol) / std::log(r));
+    return std::max(1, std::min(est, maxc));
+}
+
+// Smallest predicted number of further cycles over the active systems, from
+// each system's observed mean reduction per cycle.
+int next_batch(const vmg_opts& o, double tol, const int32_t* fixed, const vmg_handle* H) {
+    const int S = H->S;
+    int b = 1 << 30;
+    for (int s = 0; s < S; ++s) {
+        if (!H->h_int[S + s]) continue;
+        const int it = H->h_int[2 * S + s];
+        if (fixed) {
+            b = std::min(b, fixed[s] - it);
+            continue;
+        }
+        const double rr = H->h_dbl[s];
+        int need = 1;
+        if (it > 0 && rr > 0.0 && rr < 1.0) {
+            const double rate = std::min(0.999, std::max(1e-6, std::pow(rr, 1.0 / it)));
+            need = (int)std::ceil(std::log(tol / rr) / std::log(rate));
+        }
+        b = std::min(b, std::max(1, std::min(need, o.max_iter - it)));
+    }
+    return std::max(1, b == (1 << 30) ? 1 : b);
 }
 
 int solve_impl(vmg_handle* H, const double* B, double* Z, double tol, int conj, const int32_t* fixed,
@@ -410,13 +481,18 @@ int solve_impl(vmg_handle* H, const double* B, double* Z, double tol, int conj, 
     }
     if (check_hip()) return VMG_HIP_ERROR;
 
-    const int batch = std::max(1, o.check_every);
+    // Cycles are enqueued in batches sized so that no system is expected to
+    // stop inside a batch: the device decides every stop exactly, the host
+    // only avoids launching cycles for systems that have already stopped.
     int done = 0;
-    while (done < maxc) {
-        const int nb = std::min(batch, maxc - done);
+    if (read_state(H, st)) return VMG_HIP_ERROR;
+    int batch = first_batch(o, tol, fixed, H, maxc);
+    while (done < maxc && any_active(H)) {
+        const int nb = std::max(1, std::min(batch, maxc - done));
         for (int c = 0; c < nb; ++c) {
             const bool first = (done + c) == 0;
             for (auto& g : H->groups) {
+                if (g.nact == 0) continue;
                 if (o.precision == 0) {
                     CycleCtx<double> ctx{H, &g, conj, st, std::vector<int>(g.L, 0)};
                     // level-0 buffer parity is a function of the cycles run so far
@@ -427,7 +503,7 @@ int solve_impl(vmg_handle* H, const double* B, double* Z, double tol, int conj, 
                     for (int k = 0; k < o.ir_inner; ++k) enqueue_cycle<float>(ctx, 0, k == 0);
                     Level& l0 = g.lv64[0];
                     Level& e0 = g.lv32[0];
-                    Timer t(H, st, VMG_K_IR, (first ? 24.0 : 40.0) * nodes(l0.v) * g.S);
+                    Timer t(H, st, VMG_K_IR, (first ? 24.0 : 40.0) * nodes(l0.v) * g.nact);
                     launch_ir_update(P<double>(l0.x[0]), P<float>(e0.x[ctx.cur[0]]), l0.v, e0.v,
                                      H->active + g.sys0, g.S, first, st);
                 }
@@ -437,11 +513,8 @@ int solve_impl(vmg_handle* H, const double* B, double* Z, double tol, int conj, 
                 return VMG_HIP_ERROR;
         }
         done += nb;
-        VMG_HIP(hipMemcpyAsync(H->h_int + S, H->active, sizeof(int) * S, hipMemcpyDeviceToHost, st));
-        VMG_HIP(hipStreamSynchronize(st));
-        bool any = false;
-        for (int s = 0; s < S; ++s) any |= H->h_int[S + s] != 0;
-        if (!any) break;
+        if (read_state(H, st)) return VMG_HIP_ERROR;
+        batch = next_batch(o, tol, fixed, H);
     }
     off = 0;
     for (auto& g : H->groups) {
@@ -553,6 +626,7 @@ int vanka_mg_setup(const vmg_grid* grids, int32_t n_grids, const double* shifts,
         G.ny = gr.ny;
         G.h = gr.h;
         G.S = gr.num_systems;
+        G.nact = gr.num_systems;
         G.sys0 = total;
         total += gr.num_systems;
         // level sizes
@@ -876,6 +950,7 @@ int apply_op_impl(vmg_handle* H, int op, int level, int conj, const double* x, c
         const T s = (T)(1.0 / (lv.h * lv.h));
         const Coef<T>* cf = coef_of<T>(g, conj, level);
         launch_fill_int(H->active + g.sys0, 1, g.S, st);
+        g.nact = g.S;
         switch (op) {
             case VMG_OP_SWEEP: {
                 if (xf) launch_pack<T>(xf, P<T>(lv.x[0]), lv.v, g.S, st);
