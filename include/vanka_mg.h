@@ -141,12 +141,66 @@ int vanka_mg_solve(vmg_handle* h, const double* B, double* Z, double tol, int32_
  *   V, Vinv  device, complex128 n x n row-major, V Vinv = I expected.
  *   F, U     device, complex128 n x m row-major (row = time slice).  U may
  *            alias F.
- *   conj     solve with conj(lambda_j) (the adjoint of the block solves).
+ *   conj     apply the adjoint instead,
+ *            U = (V^{-H} kron I) blockdiag((A + conj(lambda_j) I)^{-1}) (V^H kron I) F.
+ *   fixed_iters  host, NULL or one cycle count per system (as in
+ *            vanka_mg_solve; freezes the solve into a fixed linear map).
  * The shifts given at setup must be the eigenvalues D of B = V D V^{-1}.
+ * Per-system counts and residuals: vanka_mg_last_stats.
  * Returns as vanka_mg_solve.
  */
 int paradiag_apply(vmg_handle* h, const double* V, const double* Vinv, const double* F,
-                   double* U, double tol, int32_t conj, void* hip_stream);
+                   double* U, double tol, int32_t conj, const int32_t* fixed_iters, void* hip_stream);
+
+/*
+ * Sensitivity of the shifted solves to their shifts (eq. (2)): with
+ * z_j = L_j^{-1} b_j, dz_j/dlambda_j = -L_j^{-1} z_j, so for an adjoint
+ * solution g_j = L_j^{-H} w_j the vector-Jacobian product is
+ *   grad_lambda[j] = -sum_p conj(z_j[p]) g_j[p].
+ *   Z, G         device, complex128, the handle's concatenated layout.
+ *   grad_lambda  device, complex128, one value per system.
+ * Fixed-order reduction (bitwise repeatable).  Returns VMG_OK,
+ * VMG_INVALID_ARG, VMG_HIP_ERROR.
+ */
+int vanka_mg_shift_gradient(vmg_handle* h, const double* Z, const double* G, double* grad_lambda,
+                            void* hip_stream);
+
+/*
+ * Residual of the backward-Euler all-at-once heat system that the alpha-
+ * circulant ParaDIAG preconditioner is iterated on (eq. (1) with
+ * B = (1/tau)(I - Z), Z the down-shift, zero initial value):
+ *   transpose = 0:  R^m = F^m - ((U^m - U^{m-1})/tau + A U^m),  U^{-1} = 0
+ *   transpose = 1:  R^m = F^m - ((U^m - U^{m+1})/tau + A U^m),  U^{n} = 0
+ * for the handle's single grid (n = number of systems, m = nx*ny).
+ *   U, F, R  device, complex128 n x m; R may alias F.
+ *   norm2    host, NULL or receives ||R||_2^2 (synchronises the stream).
+ * Returns VMG_OK, VMG_INVALID_ARG, VMG_HIP_ERROR.
+ */
+int paradiag_heat_residual(vmg_handle* h, double tau, const double* U, const double* F, double* R,
+                           int32_t transpose, double* norm2, void* hip_stream);
+
+/*
+ * ParaDIAG-II iteration for the backward-Euler heat all-at-once system
+ * K u = f, K = B kron I + I kron A with B = (1/tau)(I - Z) (Z the down-shift,
+ * zero initial value), preconditioned by the alpha-circulant system
+ * P = C_alpha kron I + I kron A whose eigen-decomposition C_alpha = V D V^{-1}
+ * the caller supplies (D = the shifts given at setup; eq. (1)):
+ *   u^0 = 0,  u^{k+1} = u^k + P^{-1}(f - K u^k)  until ||f - K u|| <= tol ||f||,
+ * every P^{-1} applied by paradiag_apply with inner tolerance inner_tol.
+ *   transpose != 0: solve K^T w = f with P^{-T} = P^{-H} (P is real), the
+ *            adjoint solve of the heat problem.
+ *   replay != 0: repeat exactly the outer and per-system inner iteration
+ *            counts recorded by the last call with replay = 0 and the same
+ *            transpose flag, making the solve one fixed linear map of f.
+ *   F, U     device, complex128 n x m; U may not alias F.
+ *   outer    host, NULL or receives the number of preconditioned steps.
+ *   relres   host, NULL or receives the final ||f - K u|| / ||f||.
+ * Returns VMG_OK, VMG_NOT_CONVERGED (max_outer reached), VMG_INVALID_ARG,
+ * VMG_HIP_ERROR, VMG_NAN_DETECTED.
+ */
+int paradiag_heat_solve(vmg_handle* h, const double* V, const double* Vinv, double tau, const double* F,
+                        double* U, double tol, double inner_tol, int32_t transpose, int32_t replay,
+                        int32_t max_outer, int32_t* outer, double* relres, void* hip_stream);
 
 /*
  * The time transform of eq. (1) on its own: out = (M kron I_m) in, i.e.

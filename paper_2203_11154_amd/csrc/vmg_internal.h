@@ -87,8 +87,8 @@ void launch_norm_finalize(const double* partial, int ntiles, int nsys, int sys_o
 
 void launch_fill_int(int* p, int value, int n, hipStream_t st);
 
-// Complex GEMM out[i, p] = sum_k M[i, k] in[k, p] (M^H with trans_conj)
-// on FP64 matrix cores.  in/out rows may be padded planes: element p of row i
+// Complex GEMM out[i, p] = sum_k M[i, k] in[k, p] (M^H with trans_conj),
+// added to out when accumulate != 0, on FP64 matrix cores.  in/out rows may be padded planes: element p of row i
 // sits at i * row + (p / nx) * pitch + p % nx + off.
 struct RowLayout {
     int nx;        // nodes per grid row
@@ -97,6 +97,16 @@ struct RowLayout {
     int64_t off;   // element offset of node 0
 };
 void launch_transform(int n, int64_t m, const double2* M, int trans_conj, const double2* in, RowLayout li,
-                      double2* out, RowLayout lo, double2* mbuf, hipStream_t st);
+                      double2* out, RowLayout lo, double2* mbuf, hipStream_t st, int accumulate = 0);
+
+// Shift sensitivities out[s] = -sum_p conj(z[s*m + p]) g[s*m + p]; partial
+// holds nsys * aux_tiles(m) double2.
+int aux_tiles(int64_t m);
+void launch_shift_gradient(const double2* z, const double2* g, int64_t m, int nsys, double2* partial,
+                           double2* out, hipStream_t st);
+// Backward-Euler all-at-once heat residual (n slices of nx x ny); partial
+// holds n * aux_tiles(nx * ny) doubles; *out_norm2 (device) = ||R||^2.
+void launch_heat_residual(const double2* U, const double2* F, double2* R, int n, int nx, int ny, double h,
+                          double tau, int transpose, double* partial, double* out_norm2, hipStream_t st);
 
 }  // namespace vmg

@@ -101,6 +101,10 @@ struct vmg_handle {
     double2* mbuf = nullptr;   // n x n transform scratch (paradiag_apply)
     double2* gbuf = nullptr;   // n x m intermediate of paradiag_apply
     int64_t gbuf_elems = 0;
+    double2* cdot_partial = nullptr;   // shift-gradient partial sums
+    double2* rbuf = nullptr;           // heat residual of paradiag_heat_solve
+    std::vector<std::vector<int32_t>> heat_record[2];  // inner counts per outer step [transpose]
+    double* heat_partial = nullptr;    // heat-residual partial sums (+1: the total)
     std::vector<void*> allocations;
     // timing
     bool timing = false;
@@ -879,11 +883,12 @@ extern "C" int paradiag_transform(int32_t n, int64_t m, const double* M, int32_t
     return check_hip();
 }
 
-extern "C" int paradiag_apply(vmg_handle* H, const double* V, const double* Vinv, const double* F, double* U,
-                              double tol, int32_t conj, void* hip_stream) {
-    if (!H || !V || !Vinv || !F || !U || !(tol > 0.0)) return VMG_INVALID_ARG;
-    if (H->groups.size() != 1 || H->S > 512) return VMG_INVALID_ARG;
-    hipStream_t st = (hipStream_t)hip_stream;
+namespace {
+
+// One application of (V kron I) blockdiag(L_j^{-1}) (Vinv kron I) (or its
+// adjoint) to F; the result is written to U, or added to U with accumulate.
+int paradiag_core(vmg_handle* H, const double* V, const double* Vinv, const double* F, double* U, double tol,
+                  int conj, const int32_t* fixed_iters, int accumulate, hipStream_t st) {
     Group& g = H->groups[0];
     const int n = H->S;
     const int64_t m = (int64_t)g.nx * g.ny;
@@ -910,16 +915,119 @@ extern "C" int paradiag_apply(vmg_handle* H, const double* V, const double* Vinv
                          reinterpret_cast<const double2*>(F), dense_rows(m), P<double>(l0.b), lb, H->mbuf, st);
     }
     if (check_hip()) return VMG_HIP_ERROR;
-    int rc = solve_impl(H, nullptr, reinterpret_cast<double*>(H->gbuf), tol, conj ? 1 : 0, nullptr, nullptr,
+    int rc = solve_impl(H, nullptr, reinterpret_cast<double*>(H->gbuf), tol, conj ? 1 : 0, fixed_iters, nullptr,
                         nullptr, st);
     if (rc < 0) return rc;
     {
-        Timer t(H, st, VMG_K_TRANSFORM, 32.0 * (double)n * m);
+        Timer t(H, st, VMG_K_TRANSFORM, (accumulate ? 48.0 : 32.0) * (double)n * m);
         launch_transform(n, m, reinterpret_cast<const double2*>(conj ? Vinv : V), conj ? 1 : 0, H->gbuf,
-                         dense_rows(m), reinterpret_cast<double2*>(U), dense_rows(m), H->mbuf, st);
+                         dense_rows(m), reinterpret_cast<double2*>(U), dense_rows(m), H->mbuf, st, accumulate);
     }
     if (check_hip()) return VMG_HIP_ERROR;
     return rc;
+}
+
+}  // namespace
+
+extern "C" int paradiag_apply(vmg_handle* H, const double* V, const double* Vinv, const double* F, double* U,
+                              double tol, int32_t conj, const int32_t* fixed_iters, void* hip_stream) {
+    if (!H || !V || !Vinv || !F || !U || !(tol > 0.0)) return VMG_INVALID_ARG;
+    if (H->groups.size() != 1 || H->S > 512) return VMG_INVALID_ARG;
+    return paradiag_core(H, V, Vinv, F, U, tol, conj ? 1 : 0, fixed_iters, 0, (hipStream_t)hip_stream);
+}
+
+extern "C" int paradiag_heat_solve(vmg_handle* H, const double* V, const double* Vinv, double tau, const double* F,
+                                   double* U, double tol, double inner_tol, int32_t transpose, int32_t replay,
+                                   int32_t max_outer, int32_t* outer, double* relres, void* hip_stream) {
+    if (!H || !V || !Vinv || !F || !U || F == U || !(tau > 0.0) || !(tol > 0.0) || !(inner_tol > 0.0) ||
+        max_outer < 1)
+        return VMG_INVALID_ARG;
+    if (H->groups.size() != 1 || H->S > 512) return VMG_INVALID_ARG;
+    hipStream_t st = (hipStream_t)hip_stream;
+    Group& g = H->groups[0];
+    const int n = H->S;
+    const int64_t m = (int64_t)g.nx * g.ny;
+    const int tr = transpose ? 1 : 0;
+    auto& rec = H->heat_record[tr];
+    if (replay && rec.empty()) return VMG_INVALID_ARG;
+    if (!H->rbuf) {
+        int rc = dev_malloc(H, (void**)&H->rbuf, sizeof(double2) * (size_t)n * m);
+        if (rc) return rc;
+    }
+    VMG_HIP(hipMemsetAsync(U, 0, sizeof(double2) * (size_t)n * m, st));
+    if (!replay) rec.clear();
+    const int nrec = (int)rec.size();
+    double fn2 = 0.0, rel = 1.0;
+    int k = 0;
+    int rc = VMG_OK;
+    std::vector<int32_t> its(n);
+    for (;; ++k) {
+        double rr = 0.0;
+        rc = paradiag_heat_residual(H, tau, reinterpret_cast<const double*>(U), F,
+                                    reinterpret_cast<double*>(H->rbuf), tr, &rr, hip_stream);
+        if (rc) return rc;
+        if (k == 0) fn2 = rr;
+        if (!(rr == rr)) return VMG_NAN_DETECTED;
+        rel = fn2 > 0.0 ? std::sqrt(rr / fn2) : 0.0;
+        if (replay ? k >= nrec : (rel <= tol || k >= max_outer)) break;
+        const int32_t* fx = replay ? rec[k].data() : nullptr;
+        rc = paradiag_core(H, V, Vinv, reinterpret_cast<const double*>(H->rbuf), U, inner_tol, tr, fx, 1, st);
+        if (rc < 0) return rc;
+        if (!replay) {
+            VMG_HIP(hipMemcpyAsync(its.data(), H->iters, sizeof(int) * n, hipMemcpyDeviceToHost, st));
+            VMG_HIP(hipStreamSynchronize(st));
+            rec.push_back(its);
+        }
+    }
+    if (outer) *outer = k;
+    if (relres) *relres = rel;
+    return (!replay && rel > tol) ? VMG_NOT_CONVERGED : VMG_OK;
+}
+
+extern "C" int vanka_mg_shift_gradient(vmg_handle* H, const double* Z, const double* G, double* grad_lambda,
+                                       void* hip_stream) {
+    if (!H || !Z || !G || !grad_lambda) return VMG_INVALID_ARG;
+    hipStream_t st = (hipStream_t)hip_stream;
+    size_t need = 0;
+    for (auto& g : H->groups) need += (size_t)g.S * aux_tiles((int64_t)g.nx * g.ny);
+    if (!H->cdot_partial) {
+        int rc = dev_malloc(H, (void**)&H->cdot_partial, sizeof(double2) * need);
+        if (rc) return rc;
+    }
+    int64_t off = 0;
+    size_t poff = 0;
+    for (auto& g : H->groups) {
+        const int64_t m = (int64_t)g.nx * g.ny;
+        launch_shift_gradient(reinterpret_cast<const double2*>(Z) + off, reinterpret_cast<const double2*>(G) + off,
+                              m, g.S, H->cdot_partial + poff, reinterpret_cast<double2*>(grad_lambda) + g.sys0, st);
+        off += m * g.S;
+        poff += (size_t)g.S * aux_tiles(m);
+    }
+    return check_hip();
+}
+
+extern "C" int paradiag_heat_residual(vmg_handle* H, double tau, const double* U, const double* F, double* R,
+                                      int32_t transpose, double* norm2, void* hip_stream) {
+    if (!H || !U || !F || !R || U == R || !(tau > 0.0) || H->groups.size() != 1) return VMG_INVALID_ARG;
+    hipStream_t st = (hipStream_t)hip_stream;
+    Group& g = H->groups[0];
+    const int n = H->S;
+    const int64_t m = (int64_t)g.nx * g.ny;
+    if (!H->heat_partial) {
+        int rc = dev_malloc(H, (void**)&H->heat_partial, sizeof(double) * ((size_t)n * aux_tiles(m) + 1));
+        if (rc) return rc;
+    }
+    double* total = H->heat_partial + (size_t)n * aux_tiles(m);
+    launch_heat_residual(reinterpret_cast<const double2*>(U), reinterpret_cast<const double2*>(F),
+                         reinterpret_cast<double2*>(R), n, g.nx, g.ny, g.h, tau, transpose ? 1 : 0, H->heat_partial,
+                         total, st);
+    if (check_hip()) return VMG_HIP_ERROR;
+    if (norm2) {
+        VMG_HIP(hipMemcpyAsync(H->h_dbl, total, sizeof(double), hipMemcpyDeviceToHost, st));
+        VMG_HIP(hipStreamSynchronize(st));
+        *norm2 = H->h_dbl[0];
+    }
+    return VMG_OK;
 }
 
 // ---------------------------------------------------------------------------

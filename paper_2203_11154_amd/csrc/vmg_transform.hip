@@ -54,7 +54,7 @@ __device__ __forceinline__ int64_t node_off(const RowLayout& L, int64_t p) {
 // eight complex rows, so each lane stores two whole double2 results.
 __global__ __launch_bounds__(TN) void k_transform(int n, int64_t m, const double* __restrict__ Mx,
                                                   const double2* __restrict__ in, RowLayout li,
-                                                  double2* __restrict__ out, RowLayout lo) {
+                                                  double2* __restrict__ out, RowLayout lo, int accumulate) {
     __shared__ double sA[ROWS][KC + 1];
     __shared__ double sB[KC][COLS + 1];
     const int n2 = 2 * n;
@@ -115,8 +115,18 @@ __global__ __launch_bounds__(TN) void k_transform(int n, int64_t m, const double
             const int64_t p = col0 + b * 16 + (lane & 15);
             if (p >= m) continue;
             const int64_t o = node_off(lo, p);
-            if (cr < n) out[(int64_t)cr * lo.row + o] = make_double2(acc[a][b][0], acc[a][b][1]);
-            if (cr + 4 < n) out[(int64_t)(cr + 4) * lo.row + o] = make_double2(acc[a][b][2], acc[a][b][3]);
+            if (cr < n) {
+                double2 v = make_double2(acc[a][b][0], acc[a][b][1]);
+                double2* q = out + (int64_t)cr * lo.row + o;
+                if (accumulate) { const double2 w = *q; v.x += w.x; v.y += w.y; }
+                *q = v;
+            }
+            if (cr + 4 < n) {
+                double2 v = make_double2(acc[a][b][2], acc[a][b][3]);
+                double2* q = out + (int64_t)(cr + 4) * lo.row + o;
+                if (accumulate) { const double2 w = *q; v.x += w.x; v.y += w.y; }
+                *q = v;
+            }
         }
     }
 }
@@ -124,11 +134,11 @@ __global__ __launch_bounds__(TN) void k_transform(int n, int64_t m, const double
 }  // namespace
 
 void launch_transform(int n, int64_t m, const double2* M, int trans_conj, const double2* in, RowLayout li,
-                      double2* out, RowLayout lo, double2* mbuf, hipStream_t st) {
+                      double2* out, RowLayout lo, double2* mbuf, hipStream_t st, int accumulate) {
     double* Mx = reinterpret_cast<double*>(mbuf);
     hipLaunchKernelGGL(k_expand, dim3((n * n + 255) / 256), dim3(256), 0, st, M, n, trans_conj, Mx);
     const dim3 grid((unsigned)((m + COLS - 1) / COLS), (unsigned)((2 * n + ROWS - 1) / ROWS));
-    hipLaunchKernelGGL(k_transform, grid, dim3(TN), 0, st, n, m, Mx, in, li, out, lo);
+    hipLaunchKernelGGL(k_transform, grid, dim3(TN), 0, st, n, m, Mx, in, li, out, lo, accumulate);
 }
 
 }  // namespace vmg

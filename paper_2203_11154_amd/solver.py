@@ -133,7 +133,15 @@ class VankaMG:
         _lib.check(code, "vanka_mg_apply_op")
         return out
 
-    def paradiag_apply(self, V, Vinv, F, tol=1e-10, conj=False, out=None):
+    def _fixed(self, fixed_iters):
+        if fixed_iters is None:
+            return None, None
+        fa = np.ascontiguousarray(np.asarray(fixed_iters, dtype=np.int32).ravel())
+        if fa.size != self.num_systems:
+            raise ValueError("fixed_iters needs one count per system")
+        return fa, fa.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+
+    def paradiag_apply(self, V, Vinv, F, tol=1e-10, conj=False, out=None, fixed_iters=None):
         """U = (V kron I) blockdiag(L_j^{-1}) (Vinv kron I) F (eq. (1)); with
         conj the adjoint (V^{-H} kron I) blockdiag(L_j^{-H}) (V^H kron I) F."""
         n = self.num_systems
@@ -141,10 +149,33 @@ class VankaMG:
             self._check_vec(t, n * n, nm)
         self._check_vec(F, self.total, "F")
         U = torch.empty_like(F) if out is None else out
+        keep, fx = self._fixed(fixed_iters)
         code = self.lib.paradiag_apply(self.handle, _ptr(V), _ptr(Vinv), _ptr(F), _ptr(U), float(tol),
-                                       int(bool(conj)), _stream())
+                                       int(bool(conj)), fx, _stream())
+        del keep
         status = _lib.check(code, "paradiag_apply")
         return U, status
+
+    def shift_gradient(self, Z, G):
+        """grad_lambda[j] = -sum conj(Z_j) G_j (one complex value per system)."""
+        self._check_vec(Z, self.total, "Z")
+        self._check_vec(G, self.total, "G")
+        out = torch.empty(self.num_systems, dtype=torch.complex128, device=Z.device)
+        _lib.check(self.lib.vanka_mg_shift_gradient(self.handle, _ptr(Z), _ptr(G), _ptr(out), _stream()),
+                   "vanka_mg_shift_gradient")
+        return out
+
+    def heat_residual(self, tau, U, F, out=None, transpose=False, norm=True):
+        """R = F - K U for the backward-Euler all-at-once operator K (K^T with
+        transpose); returns (R, ||R||^2 or None)."""
+        self._check_vec(U, self.total, "U")
+        self._check_vec(F, self.total, "F")
+        R = torch.empty_like(F) if out is None else out
+        nrm = ctypes.c_double(0.0)
+        code = self.lib.paradiag_heat_residual(self.handle, float(tau), _ptr(U), _ptr(F), _ptr(R),
+                                               int(bool(transpose)), ctypes.byref(nrm) if norm else None, _stream())
+        _lib.check(code, "paradiag_heat_residual")
+        return R, (nrm.value if norm else None)
 
     def last_stats(self):
         """(iters, relres) per system of the last solve or ParaDIAG step."""

@@ -1,0 +1,146 @@
+"""Differentiation through the HIP path: adjoint (conjugate-shift) solves give
+gradients with respect to the right-hand sides, the shifts and the heat
+source parameters, checked against the oracle, closed forms and central
+finite differences."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import exact, paradiag as opd, spectral
+from paper_2203_11154_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(np.asarray(a, dtype=np.complex128))).to("cuda")
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy()
+
+
+def test_shifted_solve_gradients():
+    from paper_2203_11154_amd import Grid, VankaMG
+    from paper_2203_11154_amd.autograd import ShiftedSolve
+    n, S = 31, 4
+    h = 1.0 / (n + 1)
+    lam = inputs.alpha_circulant_shifts(S) + np.array([0, 5j, -3j, 2])
+    b = inputs.rhs(S, n, n, seed=31)
+    y = inputs.rhs(S, n, n, seed=32)
+    solver = VankaMG([Grid(n, num_systems=S)], lam)
+    bt = dev(b.ravel()).requires_grad_(True)
+    lt = dev(lam).requires_grad_(True)
+    z = ShiftedSolve.apply(bt, lt, solver, 1e-13)
+    loss = ((z - dev(y.ravel())).abs() ** 2).sum()
+    loss.backward()
+    # oracle: g = dL/dconj(z) convention -> 2 (z - y); grad_b = L^{-H} g
+    zr = exact.dst_solve(b, lam, h)
+    g = 2 * (zr - y)
+    gb = exact.dst_solve(g, np.conj(lam), h)
+    glam = -np.sum(np.conj(zr) * gb, axis=(1, 2))
+    np.testing.assert_allclose(host(bt.grad).reshape(S, n, n), gb, rtol=1e-9, atol=1e-12 * np.abs(gb).max())
+    np.testing.assert_allclose(host(lt.grad), glam, rtol=1e-8)
+
+    # central differences on Re and Im of one shift: grad = dL/dRe + i dL/dIm
+    def loss_at(lmb):
+        s = VankaMG([Grid(n, num_systems=S)], lmb)
+        zz, _, _, _ = s.solve(dev(b.ravel()), tol=1e-13)
+        return float(((zz - dev(y.ravel())).abs() ** 2).sum())
+    j, d = 1, 1e-4
+    e = np.zeros(S, dtype=complex)
+    e[j] = d
+    dre = (loss_at(lam + e) - loss_at(lam - e)) / (2 * d)
+    dim = (loss_at(lam + 1j * e) - loss_at(lam - 1j * e)) / (2 * d)
+    got = host(lt.grad)[j]
+    assert abs(got - (dre + 1j * dim)) <= 1e-6 * abs(got)
+
+
+def test_paradiag_gradient_matches_adjoint():
+    from paper_2203_11154_amd import Grid, VankaMG
+    from paper_2203_11154_amd.autograd import ParaDiag
+    nt, nx = 8, 31
+    h = 1.0 / (nx + 1)
+    lam = inputs.alpha_circulant_shifts(nt)
+    V, Vinv = inputs.alpha_circulant_vectors(nt)
+    rng = np.random.default_rng(4)
+    F = rng.standard_normal((nt, nx, nx)) + 1j * rng.standard_normal((nt, nx, nx))
+    Y = rng.standard_normal((nt, nx, nx)) + 1j * rng.standard_normal((nt, nx, nx))
+    solver = VankaMG([Grid(nx, num_systems=nt)], lam)
+    Ft = dev(F.ravel()).requires_grad_(True)
+    U = ParaDiag.apply(Ft, solver, dev(V), dev(Vinv), 1e-13)
+    loss = ((U - dev(Y.ravel())).abs() ** 2).sum()
+    loss.backward()
+    Ur = opd.paradiag_apply(F, lam, V, Vinv, h, solver="dst")
+    g = 2 * (Ur - Y)
+    gF = opd.paradiag_apply(g, np.conj(lam), Vinv.conj().T, V.conj().T, h, solver="dst")
+    np.testing.assert_allclose(host(Ft.grad).reshape(F.shape), gF, rtol=1e-8, atol=1e-10 * np.abs(gF).max())
+
+
+def heat_setup(nx, n, K, alpha=0.01):
+    from paper_2203_11154_amd.autograd import HeatProblem
+    tau = 1.0 / n
+    lam = inputs.alpha_circulant_shifts(n, alpha)
+    V, Vinv = inputs.alpha_circulant_vectors(n, alpha)
+    prob = HeatProblem(nx, n, tau, lam, V, Vinv, tol=1e-10, inner_tol=1e-12)
+    xs = np.arange(1, nx + 1) / (nx + 1)
+    basis = np.stack([np.outer(np.sin(k * np.pi * xs), np.sin(k * np.pi * xs)) for k in range(1, K + 1)])
+    tdecay = np.exp(-tau * np.arange(1, n + 1))
+    return prob, torch.from_numpy(basis).cuda(), torch.from_numpy(tdecay).cuda(), tau
+
+
+def heat_source(theta, basis, tdecay):
+    """f^m = sum_k theta_k sin(k pi x) sin(k pi y) exp(-t_m) (real), as complex128."""
+    spatial = torch.tensordot(theta, basis, dims=1)
+    return (tdecay[:, None, None] * spatial[None]).to(torch.complex128).reshape(-1)
+
+
+@pytest.mark.parametrize("nx,n", [(63, 16), (511, 128)])
+def test_heat_gradient_closed_form(nx, n):
+    """Full ParaDIAG-II heat pipeline: u from the preconditioned iteration,
+    L = sum (u - u*)^2, dL/dtheta by the adjoint (transposed) iteration; both
+    against the closed-form backward-Euler mode recurrence."""
+    from paper_2203_11154_amd.autograd import HeatSolve
+    K = 16
+    prob, basis, tdecay, tau = heat_setup(nx, n, K)
+    theta_np = inputs.heat_parameters(K)
+    theta_star = inputs.heat_parameters(K, seed=inputs.SEED_THETA_STAR)
+    c = opd.heat_mode_coefficients(n, nx, tau)[:K]
+    ustar = np.einsum("k,km,kij->mij", theta_star, c, basis.cpu().numpy())
+    theta = torch.from_numpy(theta_np).cuda().requires_grad_(True)
+    u = HeatSolve.apply(heat_source(theta, basis, tdecay), prob)
+    assert prob.last["relres"] <= 1e-10 and prob.last["outer"] <= 8
+    loss = ((u.real - torch.from_numpy(ustar.ravel()).cuda()) ** 2).sum()
+    loss.backward()
+    L_cf, g_cf = opd.heat_loss_closed_form(theta_np, theta_star, n, nx, tau)
+    # u meets ||f - K u|| <= 1e-10 ||f||; the error in u, and so in L and its
+    # gradient, is that residual times the conditioning of K
+    assert float(loss) == pytest.approx(L_cf, rel=1e-6)
+    np.testing.assert_allclose(theta.grad.cpu().numpy(), g_cf, rtol=1e-6)
+
+
+def test_heat_gradient_finite_differences():
+    """Central differences with step 1e-6 on frozen iteration counts (the
+    solve is then one fixed linear map of f, so the quadratic loss has no
+    truncation error) against the adjoint gradient."""
+    from paper_2203_11154_amd.autograd import HeatSolve
+    nx, n, K = 127, 32, 16
+    prob, basis, tdecay, tau = heat_setup(nx, n, K)
+    theta_np = inputs.heat_parameters(K)
+    theta_star = inputs.heat_parameters(K, seed=inputs.SEED_THETA_STAR)
+    ustar = HeatSolve.apply(heat_source(torch.from_numpy(theta_star).cuda(), basis, tdecay), prob).real.clone()
+    theta = torch.from_numpy(theta_np).cuda().requires_grad_(True)
+    u = HeatSolve.apply(heat_source(theta, basis, tdecay), prob)   # records the counts
+    loss = ((u.real - ustar) ** 2).sum()
+    loss.backward()
+    grad = theta.grad.cpu().numpy()
+    step = 1e-6
+    for k in (0, 5, 15):
+        e = torch.zeros(K, dtype=torch.float64, device="cuda")
+        e[k] = step
+        lp = float(((HeatSolve.apply(heat_source(theta.detach() + e, basis, tdecay), prob, True).real - ustar) ** 2).sum())
+        lm = float(((HeatSolve.apply(heat_source(theta.detach() - e, basis, tdecay), prob, True).real - ustar) ** 2).sum())
+        fd = (lp - lm) / (2 * step)
+        assert fd == pytest.approx(grad[k], rel=1e-5, abs=1e-9 * np.abs(grad).max())
