@@ -26,16 +26,17 @@ METRIC = "shifted systems solved/s to 1e-10 rel. residual, FP32+IR vs FP64; HBM 
 HBM_PEAK_GBS = 8000.0
 FP64_MFMA_PEAK_TFLOPS = 78.6
 
-# HBM bytes per launch of the sweep kernel measured with rocprofv3 FETCH_SIZE
-# and WRITE_SIZE on this workload, each scaled by its reading for a plain
-# 1 GiB copy (profiles/plain_1023_fp64_kernels.md).  Valid only for the
-# kernel source it was measured on: reported as null once that changes.
-MEASURED_TRAFFIC = {"source_sha256_16": "8ce47553b4ed082f", "sweep_bytes_per_launch": 701.1e6}
+# HBM bytes per launch of the dominant kernel measured with rocprofv3
+# FETCH_SIZE and WRITE_SIZE on this workload, each scaled by its reading for a
+# plain 1 GiB copy (profiles/).  Valid only for the kernel source it was
+# measured on: reported as null once that file changes.
+MEASURED_TRAFFIC = {"source": "vmg_stream.hip", "source_sha256_16": None, "bytes_per_launch": None}
+DOMINANT = "k_up<double, 2, true>"   # fused correction + 2 sweeps + norm, finest level only
 
 
-def kernel_source_hash():
+def kernel_source_hash(name):
     import hashlib
-    path = os.path.join(ROOT, "paper_2203_11154_amd", "csrc", "vmg_kernels.hip")
+    path = os.path.join(ROOT, "paper_2203_11154_amd", "csrc", name)
     return hashlib.sha256(open(path, "rb").read()).hexdigest()[:16]
 
 
@@ -122,17 +123,24 @@ def main():
     ms_per_step = 1e3 * dt / args.steps
     value = S * args.steps / dt
 
-    # dominant kernel: the Vanka sweep (HBM bound)
-    la, ms, by = stats["sweep"]
-    sweep_gbs = by / (ms * 1e-3) / 1e9
+    # dominant kernel: the finest-level fused correction + post-smoothing kernel
+    # (HBM bound); it is the only launch of its instantiation, so HIP-event
+    # and rocprofv3 averages cover the same launches
+    la, ms, by = solver.level_stats("up")[0]
+    gbs = by / (ms * 1e-3) / 1e9
     traffic = None
-    if kernel_source_hash() == MEASURED_TRAFFIC["source_sha256_16"]:
-        traffic = MEASURED_TRAFFIC["sweep_bytes_per_launch"]
-    roofline = {"bound": "hbm", "kernel": "k_sweep<double,16>", "achieved": round(sweep_gbs, 1),
-                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(sweep_gbs / HBM_PEAK_GBS, 4),
+    if MEASURED_TRAFFIC["source_sha256_16"] == kernel_source_hash(MEASURED_TRAFFIC["source"]):
+        traffic = MEASURED_TRAFFIC["bytes_per_launch"]
+    roofline = {"bound": "hbm", "kernel": DOMINANT, "achieved": round(gbs, 1),
+                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4),
                 "traffic": traffic, "launches": la, "avg_ms": round(ms / max(la, 1), 5),
                 "algorithmic_bytes_per_launch": round(by / max(la, 1)),
-                "bytes_per_node": "48 (read x, b; write x'), 32 when x = 0"}
+                "bytes_per_node": "52 (read x, b, e/4; write x)"}
+    levels = {}
+    for k in ("down", "up"):
+        levels[k] = [{"level": l, "launches": a, "avg_ms": round(m / max(a, 1), 4),
+                      "GB/s": round(b_ / (m * 1e-3) / 1e9, 1) if m > 0 else None}
+                     for l, (a, m, b_) in enumerate(solver.level_stats(k))]
     tl, tms, tby = stats["transform"]
     flops = 8.0 * S * S * n * n * tl
     kernels = {k: {"launches": v[0], "ms": round(v[1], 3),
@@ -151,7 +159,7 @@ def main():
                       "omega": 0.96, "precision": "FP64"},
            "iterations": {"min": int(iters.min()), "max": int(iters.max())},
            "max_relres": float(relres.max()),
-           "roofline": roofline, "kernels": kernels}
+           "roofline": roofline, "kernels": kernels, "fused_by_level": levels}
     del solver
     torch.cuda.empty_cache()
 

@@ -238,11 +238,17 @@ int vanka_mg_apply_op(vmg_handle* h, int32_t op, int32_t level, int32_t conj,
 enum {
     VMG_K_SWEEP = 0, VMG_K_RESTRICT = 1, VMG_K_PROLONG = 2, VMG_K_NORM = 3,
     VMG_K_COARSE = 4, VMG_K_PACK = 5, VMG_K_TRANSFORM = 6, VMG_K_IR = 7,
-    VMG_NUM_KCLASS = 8
+    VMG_K_DOWN = 8,   /* fused pre-smoothing + residual + restriction */
+    VMG_K_UP = 9,     /* fused correction + post-smoothing (+ norm)    */
+    VMG_NUM_KCLASS = 10
 };
 int vanka_mg_set_timing(vmg_handle* h, int32_t enable, int32_t reset);
 int vanka_mg_kernel_stats(vmg_handle* h, int64_t* launches /* [VMG_NUM_KCLASS] */,
                           double* total_ms, double* total_bytes);
+/* The same sums for one kernel class split by multigrid level (0 = finest;
+ * kernels outside the cycle count as level 0); arrays of nlev entries. */
+int vanka_mg_level_stats(vmg_handle* h, int32_t kclass, int32_t nlev, int64_t* launches,
+                         double* total_ms, double* total_bytes);
 
 /*
  * Per-system results of the last vanka_mg_solve or paradiag_apply on this

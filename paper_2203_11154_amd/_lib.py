@@ -7,7 +7,7 @@ import ctypes
 import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libvanka_mg.so")
+LIB_PATH = os.environ.get("VMG_LIBRARY") or os.path.join(HERE, "libvanka_mg.so")
 
 VMG_OK = 0
 VMG_NOT_CONVERGED = 1
@@ -24,12 +24,13 @@ OP_PROLONG_CORRECT = 3
 OP_COARSE_SOLVE = 4
 OP_CYCLE = 5
 
-KERNEL_CLASSES = ["sweep", "restrict", "prolong", "norm", "coarse", "pack", "transform", "ir"]
+KERNEL_CLASSES = ["sweep", "restrict", "prolong", "norm", "coarse", "pack", "transform", "ir", "down", "up"]
 NUM_KCLASS = len(KERNEL_CLASSES)
 
 EXPORTED = ["vanka_mg_default_opts", "vanka_mg_setup", "vanka_mg_solve", "paradiag_apply",
             "vanka_mg_shift_gradient", "paradiag_heat_residual", "paradiag_heat_solve",
             "paradiag_transform", "vanka_mg_apply_op", "vanka_mg_set_timing", "vanka_mg_kernel_stats",
+            "vanka_mg_level_stats",
             "vanka_mg_levels", "vanka_mg_last_stats", "vanka_mg_destroy", "vanka_mg_error_string"]
 
 
@@ -72,6 +73,7 @@ def load():
     lib.vanka_mg_apply_op.argtypes = [vp, i32, i32, i32, vp, vp, vp, vp]
     lib.vanka_mg_set_timing.argtypes = [vp, i32, i32]
     lib.vanka_mg_kernel_stats.argtypes = [vp, pi64, pdbl, pdbl]
+    lib.vanka_mg_level_stats.argtypes = [vp, i32, i32, pi64, pdbl, pdbl]
     lib.vanka_mg_levels.argtypes = [vp, i32, pi32, pi32, pi32]
     lib.vanka_mg_last_stats.argtypes = [vp, pi32, pdbl, vp]
     lib.vanka_mg_destroy.argtypes = [vp]

@@ -99,6 +99,20 @@ struct RowLayout {
 void launch_transform(int n, int64_t m, const double2* M, int trans_conj, const double2* in, RowLayout li,
                       double2* out, RowLayout lo, double2* mbuf, hipStream_t st, int accumulate = 0);
 
+// Fused register-streaming level kernels (vmg_stream.hip), nu in {0, 1, 2}:
+//   down: nu sweeps, residual, full weighting -> xo (x_nu), bc (coarse rhs)
+//   up:   x + P e, nu sweeps -> xo; per-block |b - L xo|^2 into partial
+//         (partial[sys * stream_tiles + tile]) when partial != NULL.
+// ty = rows per block.
+template <typename T>
+void launch_down(const cplx<T>* x, const cplx<T>* b, cplx<T>* xo, cplx<T>* bc, LevelView lf, LevelView lc, T s,
+                 const Coef<T>* coef, const int* active, int nsys, int nu, int x_zero, int ty, hipStream_t st);
+template <typename T>
+void launch_up(const cplx<T>* x, const cplx<T>* e, const cplx<T>* b, cplx<T>* xo, LevelView lf, LevelView lc, T s,
+               const Coef<T>* coef, const int* active, int nsys, int nu, int ty, double* partial, hipStream_t st);
+int stream_tiles(int nx, int ny, int nu, bool norm, int ty);
+template <typename T> void launch_fill_zero(cplx<T>* x, LevelView lv, int nsys, hipStream_t st);
+
 // Shift sensitivities out[s] = -sum_p conj(z[s*m + p]) g[s*m + p]; partial
 // holds nsys * aux_tiles(m) double2.
 int aux_tiles(int64_t m);

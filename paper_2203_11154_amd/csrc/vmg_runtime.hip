@@ -7,6 +7,7 @@
 #include <cmath>
 #include <complex>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <vector>
@@ -75,9 +76,12 @@ struct Group {
 
 struct TimedLaunch {
     int kclass;
+    int level;
     double bytes;
     hipEvent_t a, b;
 };
+
+constexpr int MAX_STAT_LEVELS = 32;
 
 }  // namespace vmg
 
@@ -95,6 +99,7 @@ struct vmg_handle {
     int* active = nullptr;
     int* target = nullptr;
     int* nanflag = nullptr;
+    int stream_rows = 0;       // rows per block of the streaming kernels (0: by level size)
     // pinned host staging
     int* h_int = nullptr;      // 3 * S ints
     double* h_dbl = nullptr;   // S doubles
@@ -113,6 +118,9 @@ struct vmg_handle {
     int64_t launches[VMG_NUM_KCLASS] = {};
     double total_ms[VMG_NUM_KCLASS] = {};
     double total_bytes[VMG_NUM_KCLASS] = {};
+    int64_t lv_launches[VMG_NUM_KCLASS][MAX_STAT_LEVELS] = {};
+    double lv_ms[VMG_NUM_KCLASS][MAX_STAT_LEVELS] = {};
+    double lv_bytes[VMG_NUM_KCLASS][MAX_STAT_LEVELS] = {};
 };
 
 namespace {
@@ -158,8 +166,10 @@ struct Timer {
     hipStream_t st;
     int kclass;
     double bytes;
+    int level;
     hipEvent_t a = nullptr;
-    Timer(vmg_handle* H_, hipStream_t st_, int k, double by) : H(H_), st(st_), kclass(k), bytes(by) {
+    Timer(vmg_handle* H_, hipStream_t st_, int k, double by, int lev = 0)
+        : H(H_), st(st_), kclass(k), bytes(by), level(lev) {
         if (H->timing) {
             a = get_event(H);
             if (a) (void)hipEventRecord(a, st);
@@ -170,7 +180,7 @@ struct Timer {
             hipEvent_t b = get_event(H);
             if (b) {
                 (void)hipEventRecord(b, st);
-                H->pending.push_back({kclass, bytes, a, b});
+                H->pending.push_back({kclass, level, bytes, a, b});
             }
         }
     }
@@ -184,6 +194,10 @@ int collect_timing(vmg_handle* H) {
         H->launches[t.kclass] += 1;
         H->total_ms[t.kclass] += ms;
         H->total_bytes[t.kclass] += t.bytes;
+        const int lv = std::min(std::max(t.level, 0), MAX_STAT_LEVELS - 1);
+        H->lv_launches[t.kclass][lv] += 1;
+        H->lv_ms[t.kclass][lv] += ms;
+        H->lv_bytes[t.kclass][lv] += t.bytes;
         H->event_pool.push_back(t.a);
         H->event_pool.push_back(t.b);
     }
@@ -295,8 +309,24 @@ struct CycleCtx {
     Group* g;
     int conj;
     hipStream_t st;
-    std::vector<int> cur;  // which ping-pong buffer holds x, per level
+    std::vector<int> cur;       // which ping-pong buffer holds x, per level
+    double* norm_partial = nullptr;  // level 0: fuse the stopping-test residual norm
+    bool norm_fused = false;    // set when the last cycle produced those partials
 };
+
+// Levels at least this wide run the fused streaming kernels.
+constexpr int STREAM_MIN_NX = 96;
+
+bool use_stream(const vmg_opts& o, const LevelView& v) {
+    return v.nx >= STREAM_MIN_NX && o.nu1 <= 2 && o.nu2 <= 2;
+}
+
+// Rows per block: tall blocks amortise the pipeline's start-up rows, short
+// ones give small levels enough blocks to fill the GPU.
+int stream_rows_for(const vmg_handle* H, const LevelView& v) {
+    if (H->stream_rows > 0) return H->stream_rows;
+    return v.ny > 600 ? 128 : (v.ny > 200 ? 64 : 32);
+}
 
 template <typename T> void enqueue_cycle(CycleCtx<T>& c, int l, bool x_zero) {
     vmg_handle* H = c.H;
@@ -307,22 +337,54 @@ template <typename T> void enqueue_cycle(CycleCtx<T>& c, int l, bool x_zero) {
     const double E = sizeof(cplx<T>);
     const T s = (T)(1.0 / (lv.h * lv.h));
     const Coef<T>* cf = coef_of<T>(g, c.conj, l);
+    const vmg_opts& o = H->opts;
+    if (l == 0) c.norm_fused = false;
     if (l == g.L - 1) {
-        Timer t(H, c.st, VMG_K_COARSE, E * ((double)g.nc * g.nc + 2.0 * g.nc) * g.nact);
+        Timer t(H, c.st, VMG_K_COARSE, E * ((double)g.nc * g.nc + 2.0 * g.nc) * g.nact, l);
         launch_coarse<T>(P<T>(lv.b), P<T>(lv.x[c.cur[l]]), lv.v, cinv_of<T>(g, c.conj), g.nc, act, g.S, c.st);
         return;
     }
-    const vmg_opts& o = H->opts;
+    Level& lc = L[l + 1];
+    if (use_stream(o, lv.v)) {
+        // fused: nu1 sweeps + residual + restriction, recursion, correction + nu2 sweeps
+        {
+            const double by = ((x_zero ? 0.0 : 1.0) + 1.0 + (o.nu1 > 0 ? 1.0 : 0.0) + 0.25) * E * nodes(lv.v) * g.nact;
+            Timer t(H, c.st, VMG_K_DOWN, by, l);
+            launch_down<T>(P<T>(lv.x[c.cur[l]]), P<T>(lv.b), P<T>(lv.x[1 - c.cur[l]]), P<T>(lc.b), lv.v, lc.v, s, cf,
+                           act, g.S, o.nu1, x_zero, stream_rows_for(H, lv.v), c.st);
+        }
+        if (o.nu1 > 0) {
+            c.cur[l] ^= 1;
+        } else if (x_zero) {
+            // no sweep materialised x: the correction below reads it, so it
+            // must hold zeros (the ring is zero already)
+            launch_fill_zero<T>(P<T>(lv.x[c.cur[l]]), lv.v, g.S, c.st);
+        }
+        bool cz = true;
+        for (int k = 0; k < o.gamma; ++k) {
+            enqueue_cycle<T>(c, l + 1, cz);
+            cz = false;
+        }
+        double* np = (l == 0) ? c.norm_partial : nullptr;
+        {
+            const double by = (2.0 + 0.25 + ((o.nu2 > 0 || np) ? 1.0 : 0.0)) * E * nodes(lv.v) * g.nact;
+            Timer t(H, c.st, VMG_K_UP, by, l);
+            launch_up<T>(P<T>(lv.x[c.cur[l]]), P<T>(lc.x[c.cur[l + 1]]), P<T>(lv.b), P<T>(lv.x[1 - c.cur[l]]), lv.v,
+                         lc.v, s, cf, act, g.S, o.nu2, stream_rows_for(H, lv.v), np, c.st);
+        }
+        c.cur[l] ^= 1;
+        if (np) c.norm_fused = true;
+        return;
+    }
     for (int i = 0; i < o.nu1; ++i) {
-        Timer t(H, c.st, VMG_K_SWEEP, (x_zero ? 2.0 : 3.0) * E * nodes(lv.v) * g.nact);
+        Timer t(H, c.st, VMG_K_SWEEP, (x_zero ? 2.0 : 3.0) * E * nodes(lv.v) * g.nact, l);
         launch_sweep<T>(P<T>(lv.x[c.cur[l]]), P<T>(lv.b), P<T>(lv.x[1 - c.cur[l]]), lv.v, s, cf, act, g.S, x_zero,
                         c.st);
         c.cur[l] ^= 1;
         x_zero = false;
     }
-    Level& lc = L[l + 1];
     {
-        Timer t(H, c.st, VMG_K_RESTRICT, ((x_zero ? 1.0 : 2.0) + 0.25) * E * nodes(lv.v) * g.nact);
+        Timer t(H, c.st, VMG_K_RESTRICT, ((x_zero ? 1.0 : 2.0) + 0.25) * E * nodes(lv.v) * g.nact, l);
         launch_restrict<T>(P<T>(lv.x[c.cur[l]]), P<T>(lv.b), P<T>(lc.b), lv.v, lc.v, s, cf, act, g.S, x_zero, c.st);
     }
     bool cz = true;
@@ -331,12 +393,12 @@ template <typename T> void enqueue_cycle(CycleCtx<T>& c, int l, bool x_zero) {
         cz = false;
     }
     {
-        Timer t(H, c.st, VMG_K_PROLONG, ((x_zero ? 1.0 : 2.0) + 0.25) * E * nodes(lv.v) * g.nact);
+        Timer t(H, c.st, VMG_K_PROLONG, ((x_zero ? 1.0 : 2.0) + 0.25) * E * nodes(lv.v) * g.nact, l);
         launch_prolong<T>(P<T>(lv.x[c.cur[l]]), P<T>(lc.x[c.cur[l + 1]]), lv.v, lc.v, act, g.S, x_zero, c.st);
     }
     x_zero = false;
     for (int i = 0; i < o.nu2; ++i) {
-        Timer t(H, c.st, VMG_K_SWEEP, 3.0 * E * nodes(lv.v) * g.nact);
+        Timer t(H, c.st, VMG_K_SWEEP, 3.0 * E * nodes(lv.v) * g.nact, l);
         launch_sweep<T>(P<T>(lv.x[c.cur[l]]), P<T>(lv.b), P<T>(lv.x[1 - c.cur[l]]), lv.v, s, cf, act, g.S, 0, c.st);
         c.cur[l] ^= 1;
     }
@@ -350,14 +412,34 @@ int check_hip() {
 bool valid_grid_level(int n) { return n >= 3 && (n % 2) == 1; }
 
 // residual norms of level 0 of every group, then the convergence update
-int enqueue_norm_check(vmg_handle* H, hipStream_t st, int mode, double tol, int fixed, int conj, int cur) {
+// Flips of the level-0 ping-pong buffer per cycle (a cycle always leaves the
+// finest iterate in the same buffer if this is even).
+int level0_flips(const vmg_handle* H, const Group& g) {
+    const vmg_opts& o = H->opts;
+    const LevelView& v = (o.precision == 0 ? g.lv64[0] : g.lv32[0]).v;
+    if (g.L > 1 && use_stream(o, v)) return (o.nu1 > 0 ? 1 : 0) + 1;
+    return o.nu1 + o.nu2;
+}
+
+int norm_tiles(const vmg_handle* H, const Group& g) {
+    return stream_tiles(g.lv64[0].v.nx, g.lv64[0].v.ny, H->opts.nu2, true, stream_rows_for(H, g.lv64[0].v));
+}
+
+// residual norms of level 0 of every group (unless the last cycle's fused
+// kernel already produced the partial sums), then the convergence update
+int enqueue_norm_check(vmg_handle* H, hipStream_t st, int mode, double tol, int fixed, int conj,
+                       const std::vector<int>& cur, const std::vector<char>& fused) {
     const bool x_zero = false;
-    for (auto& g : H->groups) {
+    for (size_t gi = 0; gi < H->groups.size(); ++gi) {
+        Group& g = H->groups[gi];
         const int* act = H->active + g.sys0;
-        if (H->opts.precision == 0) {
+        int ntiles = g.ntiles0;
+        if (fused[gi]) {
+            ntiles = norm_tiles(H, g);
+        } else if (H->opts.precision == 0) {
             Level& l0 = g.lv64[0];
             Timer t(H, st, VMG_K_NORM, 2.0 * 16.0 * nodes(l0.v) * g.nact);
-            launch_residual<double, double>(P<double>(l0.x[cur]), P<double>(l0.b), nullptr, l0.v, l0.v,
+            launch_residual<double, double>(P<double>(l0.x[cur[gi]]), P<double>(l0.b), nullptr, l0.v, l0.v,
                                             1.0 / (l0.h * l0.h), coef_of<double>(g, conj, 0), act, g.S, x_zero,
                                             g.partial, st);
         } else {
@@ -368,7 +450,7 @@ int enqueue_norm_check(vmg_handle* H, hipStream_t st, int mode, double tol, int 
                                            1.0 / (l0.h * l0.h), coef_of<double>(g, conj, 0), act, g.S, x_zero,
                                            g.partial, st);
         }
-        launch_norm_finalize(g.partial, g.ntiles0, g.S, g.sys0, mode, tol, fixed, H->bb, H->relres, H->iters,
+        launch_norm_finalize(g.partial, ntiles, g.S, g.sys0, mode, tol, fixed, H->bb, H->relres, H->iters,
                              H->active, H->target, H->nanflag, st);
     }
     return check_hip();
@@ -491,17 +573,24 @@ int solve_impl(vmg_handle* H, const double* B, double* Z, double tol, int conj, 
     int done = 0;
     if (read_state(H, st)) return VMG_HIP_ERROR;
     int batch = first_batch(o, tol, fixed, H, maxc);
+    std::vector<int> cur0(H->groups.size(), 0);
+    std::vector<char> fused(H->groups.size(), 0);
     while (done < maxc && any_active(H)) {
         const int nb = std::max(1, std::min(batch, maxc - done));
         for (int c = 0; c < nb; ++c) {
             const bool first = (done + c) == 0;
-            for (auto& g : H->groups) {
+            for (size_t gi = 0; gi < H->groups.size(); ++gi) {
+                Group& g = H->groups[gi];
+                fused[gi] = 0;
                 if (g.nact == 0) continue;
                 if (o.precision == 0) {
                     CycleCtx<double> ctx{H, &g, conj, st, std::vector<int>(g.L, 0)};
                     // level-0 buffer parity is a function of the cycles run so far
-                    ctx.cur[0] = (int)(((int64_t)(done + c) * (o.nu1 + o.nu2)) & 1);
+                    ctx.cur[0] = (int)(((int64_t)(done + c) * level0_flips(H, g)) & 1);
+                    ctx.norm_partial = g.partial;
                     enqueue_cycle<double>(ctx, 0, first);
+                    cur0[gi] = ctx.cur[0];
+                    fused[gi] = ctx.norm_fused;
                 } else {
                     CycleCtx<float> ctx{H, &g, conj, st, std::vector<int>(g.L, 0)};
                     for (int k = 0; k < o.ir_inner; ++k) enqueue_cycle<float>(ctx, 0, k == 0);
@@ -512,9 +601,7 @@ int solve_impl(vmg_handle* H, const double* B, double* Z, double tol, int conj, 
                                      H->active + g.sys0, g.S, first, st);
                 }
             }
-            const int cur0 = (int)(((int64_t)(done + c + 1) * (o.nu1 + o.nu2)) & 1);
-            if (enqueue_norm_check(H, st, 1, tol, fixed != nullptr, conj, o.precision == 0 ? cur0 : 0))
-                return VMG_HIP_ERROR;
+            if (enqueue_norm_check(H, st, 1, tol, fixed != nullptr, conj, cur0, fused)) return VMG_HIP_ERROR;
         }
         done += nb;
         if (read_state(H, st)) return VMG_HIP_ERROR;
@@ -524,7 +611,7 @@ int solve_impl(vmg_handle* H, const double* B, double* Z, double tol, int conj, 
     for (auto& g : H->groups) {
         Level& l0 = g.lv64[0];
         Timer t(H, st, VMG_K_PACK, 32.0 * nodes(l0.v) * g.S);
-        const int flips = o.precision == 0 ? (o.nu1 + o.nu2) : 0;
+        const int flips = o.precision == 0 ? level0_flips(H, g) : 0;
         launch_unpack<double>(P<double>(l0.x[0]), o.precision == 0 ? P<double>(l0.x[1]) : nullptr,
                               reinterpret_cast<double2*>(Z) + off, l0.v, g.S, H->iters + g.sys0, flips, st);
         off += (int64_t)g.nx * g.ny * g.S;
@@ -679,6 +766,10 @@ int vanka_mg_setup(const vmg_grid* grids, int32_t n_grids, const double* shifts,
         }
     }
     H->S = total;
+    if (const char* e = std::getenv("VMG_STREAM_ROWS")) {
+        const int r = std::atoi(e);
+        if (r >= 16 && r <= 4096) H->stream_rows = r;
+    }
     H->shifts.resize(total);
     for (int s = 0; s < total; ++s) H->shifts[s] = cd(shifts[2 * s], shifts[2 * s + 1]);
 
@@ -716,7 +807,11 @@ int vanka_mg_setup(const vmg_grid* grids, int32_t n_grids, const double* shifts,
             VMG_TRY(alloc_planes<float>(H, L.b, L.v, G.S));
         }
         G.ntiles0 = residual_tiles(G.lv64[0].v);
-        VMG_TRY(dev_malloc(H, (void**)&G.partial, sizeof(double) * (size_t)G.ntiles0 * G.S));
+        {
+            // the smallest row block the tuning range allows sets the largest tile count
+            const int nt = std::max(G.ntiles0, stream_tiles(G.lv64[0].v.nx, G.lv64[0].v.ny, o.nu2, true, 16));
+            VMG_TRY(dev_malloc(H, (void**)&G.partial, sizeof(double) * (size_t)nt * G.S));
+        }
         // coefficients for all levels, both conj variants
         std::vector<Coef<double>> c64((size_t)G.L * G.S);
         std::vector<Coef<float>> c32((size_t)G.L * G.S);
@@ -772,6 +867,20 @@ int vanka_mg_solve(vmg_handle* H, const double* B, double* Z, double tol, int32_
     return rc;
 }
 
+int vanka_mg_level_stats(vmg_handle* H, int32_t kclass, int32_t nlev, int64_t* launches, double* total_ms,
+                         double* total_bytes) {
+    if (!H || kclass < 0 || kclass >= VMG_NUM_KCLASS || nlev < 0) return VMG_INVALID_ARG;
+    int rc = collect_timing(H);
+    if (rc) return rc;
+    for (int l = 0; l < nlev; ++l) {
+        const bool in = l < MAX_STAT_LEVELS;
+        if (launches) launches[l] = in ? H->lv_launches[kclass][l] : 0;
+        if (total_ms) total_ms[l] = in ? H->lv_ms[kclass][l] : 0.0;
+        if (total_bytes) total_bytes[l] = in ? H->lv_bytes[kclass][l] : 0.0;
+    }
+    return VMG_OK;
+}
+
 int vanka_mg_last_stats(vmg_handle* H, int32_t* iters, double* relres, void* hip_stream) {
     if (!H) return VMG_INVALID_ARG;
     hipStream_t st = (hipStream_t)hip_stream;
@@ -805,6 +914,11 @@ int vanka_mg_set_timing(vmg_handle* H, int32_t enable, int32_t reset) {
             H->launches[k] = 0;
             H->total_ms[k] = 0;
             H->total_bytes[k] = 0;
+            for (int l = 0; l < MAX_STAT_LEVELS; ++l) {
+                H->lv_launches[k][l] = 0;
+                H->lv_ms[k][l] = 0;
+                H->lv_bytes[k][l] = 0;
+            }
         }
     }
     return VMG_OK;

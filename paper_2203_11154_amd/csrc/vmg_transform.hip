@@ -18,10 +18,12 @@ namespace {
 
 typedef double dbl4 __attribute__((ext_vector_type(4)));
 
-constexpr int TN = 256;        // threads per block, 4 waves
-constexpr int ROWS = 256;      // real output rows per block (64 per wave)
+constexpr int TN = 512;        // threads per block, 8 waves
+constexpr int ROWS = 256;      // real output rows per block (32 per wave)
 constexpr int COLS = 64;       // grid nodes per block
 constexpr int KC = 16;         // real K per LDS chunk (8 complex time slices)
+constexpr int A_PER_T = ROWS * KC / TN;          // A-chunk doubles staged per thread
+constexpr int B_PER_T = (KC / 2) * COLS / TN;    // B-chunk complex values per thread
 
 // Mx from M (or M^H when trans_conj), n2 = 2n.
 __global__ void k_expand(const double2* __restrict__ M, int n, int trans_conj, double* __restrict__ Mx) {
@@ -45,13 +47,15 @@ __device__ __forceinline__ int64_t node_off(const RowLayout& L, int64_t p) {
 }
 
 // One block: real rows [rb*ROWS, +ROWS) x nodes [cb*COLS, +COLS).
-// Wave w owns rows w*64..w*64+63 as 4 x 4 MFMA 16x16 tiles.
+// Wave w owns rows w*32..w*32+31 as 2 x 4 MFMA 16x16 tiles.
 // v_mfma_f64_16x16x4_f64 lane layout (measured on gfx950): A[i][k] at lane
 // i + 16k, B[k][j] at lane j + 16k, D[i][j] at lane j + 16(i%4), element
 // i/4.  A lane therefore holds tile rows g, g+4, g+8, g+12 (g = lane/16).
 // Feeding MFMA row r from real row perm(r) = 2((r%4) + 4(r/8)) + (r/4)%2
 // makes those four values (re, im) of complex rows g and g+4 of the tile's
 // eight complex rows, so each lane stores two whole double2 results.
+// The next K chunk is fetched into registers while the current one is
+// multiplied out of LDS.
 __global__ __launch_bounds__(TN) void k_transform(int n, int64_t m, const double* __restrict__ Mx,
                                                   const double2* __restrict__ in, RowLayout li,
                                                   double2* __restrict__ out, RowLayout lo, int accumulate) {
@@ -61,53 +65,80 @@ __global__ __launch_bounds__(TN) void k_transform(int n, int64_t m, const double
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int row0 = blockIdx.y * ROWS;
     const int64_t col0 = (int64_t)blockIdx.x * COLS;
-    const int wrow = row0 + wave * 64;
+    const int wrow = row0 + wave * 32;
     const bool wave_active = wrow < n2;
     const int arow = tile_row_perm(lane & 15);
-    dbl4 acc[4][4];
+    dbl4 acc[2][4];
 #pragma unroll
-    for (int a = 0; a < 4; ++a)
+    for (int a = 0; a < 2; ++a)
 #pragma unroll
         for (int b = 0; b < 4; ++b) acc[a][b] = dbl4{0.0, 0.0, 0.0, 0.0};
 
-    for (int kc = 0; kc < n2; kc += KC) {
-        // A chunk: ROWS x KC from Mx (L2 resident)
-        for (int t = threadIdx.x; t < ROWS * KC; t += TN) {
+    double ra[A_PER_T];
+    double2 rb[B_PER_T];
+    auto fetch = [&](int kc) {
+#pragma unroll
+        for (int q = 0; q < A_PER_T; ++q) {
+            const int t = threadIdx.x + q * TN;
             const int r = t / KC, k = t - r * KC;
             const int gr = row0 + r, gk = kc + k;
-            sA[r][k] = (gr < n2 && gk < n2) ? Mx[(int64_t)gr * n2 + gk] : 0.0;
+            ra[q] = (gr < n2 && gk < n2) ? Mx[(int64_t)gr * n2 + gk] : 0.0;
         }
-        // B chunk: KC/2 complex rows x COLS nodes
-        for (int t = threadIdx.x; t < (KC / 2) * COLS; t += TN) {
+#pragma unroll
+        for (int q = 0; q < B_PER_T; ++q) {
+            const int t = threadIdx.x + q * TN;
             const int kr = t / COLS, c = t - kr * COLS;
             const int gk = kc / 2 + kr;
             const int64_t p = col0 + c;
-            double2 v = make_double2(0.0, 0.0);
-            if (gk < n && p < m) v = in[(int64_t)gk * li.row + node_off(li, p)];
-            sB[2 * kr][c] = v.x;
-            sB[2 * kr + 1][c] = v.y;
+            rb[q] = (gk < n && p < m) ? in[(int64_t)gk * li.row + node_off(li, p)] : make_double2(0.0, 0.0);
         }
-        __syncthreads();
+    };
+    auto stage = [&]() {
+#pragma unroll
+        for (int q = 0; q < A_PER_T; ++q) {
+            const int t = threadIdx.x + q * TN;
+            const int r = t / KC, k = t - r * KC;
+            sA[r][k] = ra[q];
+        }
+#pragma unroll
+        for (int q = 0; q < B_PER_T; ++q) {
+            const int t = threadIdx.x + q * TN;
+            const int kr = t / COLS, c = t - kr * COLS;
+            sB[2 * kr][c] = rb[q].x;
+            sB[2 * kr + 1][c] = rb[q].y;
+        }
+    };
+
+    fetch(0);
+    stage();
+    __syncthreads();
+    for (int kc = 0; kc < n2; kc += KC) {
+        const bool more = kc + KC < n2;
+        if (more) fetch(kc + KC);
         if (wave_active) {
 #pragma unroll
             for (int ks = 0; ks < KC; ks += 4) {
-                double av[4], bv[4];
+                double av[2], bv[4];
 #pragma unroll
-                for (int a = 0; a < 4; ++a) av[a] = sA[wave * 64 + a * 16 + arow][ks + (lane >> 4)];
+                for (int a = 0; a < 2; ++a) av[a] = sA[wave * 32 + a * 16 + arow][ks + (lane >> 4)];
 #pragma unroll
                 for (int b = 0; b < 4; ++b) bv[b] = sB[ks + (lane >> 4)][b * 16 + (lane & 15)];
 #pragma unroll
-                for (int a = 0; a < 4; ++a)
+                for (int a = 0; a < 2; ++a)
 #pragma unroll
                     for (int b = 0; b < 4; ++b)
                         acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], bv[b], acc[a][b], 0, 0, 0);
             }
         }
         __syncthreads();
+        if (more) {
+            stage();
+            __syncthreads();
+        }
     }
     if (!wave_active) return;
 #pragma unroll
-    for (int a = 0; a < 4; ++a) {
+    for (int a = 0; a < 2; ++a) {
         // complex rows of this lane: cr and cr + 4 (elements 0,1 and 2,3)
         const int cr = (wrow + a * 16) / 2 + (lane >> 4);
 #pragma unroll
