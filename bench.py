@@ -30,7 +30,7 @@ FP64_MFMA_PEAK_TFLOPS = 78.6
 # FETCH_SIZE and WRITE_SIZE on this workload, each scaled by its reading for a
 # plain 1 GiB copy (profiles/).  Valid only for the kernel source it was
 # measured on: reported as null once that file changes.
-MEASURED_TRAFFIC = {"source": "vmg_stream.hip", "source_sha256_16": None, "bytes_per_launch": None}
+MEASURED_TRAFFIC = {"source": "vmg_stream.hip", "source_sha256_16": "73f42c9418efe715", "bytes_per_launch": 3924.2e6}
 DOMINANT = "k_up<double, 2, true>"   # fused correction + 2 sweeps + norm, finest level only
 
 
@@ -116,7 +116,7 @@ def main():
     solver.set_timing(True, reset=True)
     dt, status = run_steps(solver, Vd, Vinvd, Fd, Ud, args.steps, tol, torch)
     stats = solver.kernel_stats()
-    solver.set_timing(False)
+    solver.set_timing(False, reset=False)
     iters, relres = solver.last_stats()
     if status != 0 or not np.all(relres <= tol):
         raise SystemExit(f"FP64 ParaDIAG step did not converge: status {status}, max relres {relres.max():.3e}")
@@ -169,7 +169,7 @@ def main():
             ir.paradiag_apply(Vd, Vinvd, Fd, tol=tol, out=Ud)
         ir.set_timing(True, reset=True)
         dti, st_ir = run_steps(ir, Vd, Vinvd, Fd, Ud, args.steps, tol, torch)
-        ir.set_timing(False)
+        ir.set_timing(False, reset=False)
         it_ir, rr_ir = ir.last_stats()
         ok = st_ir == 0 and bool(np.all(rr_ir <= tol))
         out["fp32_ir"] = {"value": round(S * args.steps / dti, 2), "unit": "systems/s",

@@ -90,9 +90,14 @@ typedef struct {
     int32_t smoother;     /* 0 = additive Vanka (default); 1 = damped Jacobi,
                              the comparison smoother of Sec. 3 (omega 4/5)   */
     int32_t ir_inner;     /* complex64 cycles per refinement step; default 3 */
-    int32_t check_every;  /* cycles enqueued between host convergence checks;
-                             default 4 (the stop itself is exact per system:
-                             it is decided on the device after every cycle)  */
+    int32_t check_every;  /* most cycles enqueued between two host checks of
+                             the stop flags; default 64 (the stop itself is
+                             exact per system: it is decided on the device
+                             after every cycle, and the host sizes batches
+                             from the observed convergence rates)            */
+    int32_t graphs;       /* 1 (default): replay each cycle as a captured
+                             hipGraph (eager launches while kernel timing is
+                             on); 0: always launch eagerly                   */
 } vmg_opts;
 
 /* Fill *opts with the defaults listed above.  Returns VMG_OK or

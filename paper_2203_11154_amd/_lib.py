@@ -42,7 +42,8 @@ class VmgGrid(ctypes.Structure):
 class VmgOpts(ctypes.Structure):
     _fields_ = [("omega", ctypes.c_double), ("nu1", ctypes.c_int32), ("nu2", ctypes.c_int32),
                 ("gamma", ctypes.c_int32), ("max_iter", ctypes.c_int32), ("precision", ctypes.c_int32),
-                ("smoother", ctypes.c_int32), ("ir_inner", ctypes.c_int32), ("check_every", ctypes.c_int32)]
+                ("smoother", ctypes.c_int32), ("ir_inner", ctypes.c_int32), ("check_every", ctypes.c_int32),
+                ("graphs", ctypes.c_int32)]
 
 
 _lib = None

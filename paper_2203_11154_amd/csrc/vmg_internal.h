@@ -31,6 +31,43 @@ template <typename T> struct Coef {
     cplx<T> d, ca, cb, cc;
 };
 
+// One grid's share of a batched launch.  A launch covers up to MAXSEG grids
+// (segments) that may differ in size; blockIdx.z runs over the systems of all
+// segments (segment q owns z0[q] .. z0[q+1]-1) and blocks beyond a segment's
+// own grid extent (gx, gy) return at once.
+constexpr int MAXSEG = 8;
+template <typename T> struct LevelSeg {
+    const cplx<T>* x;     // iterate read (padded planes)
+    const cplx<T>* b;     // right-hand side
+    cplx<T>* xo;          // iterate written
+    cplx<T>* c;           // coarse right-hand side written (restriction) or
+                          // coarse correction read (prolongation)
+    LevelView lf, lc;     // this level and the next coarser one
+    T s;                  // 1 / h^2 of this level
+    const Coef<T>* coef;  // per system of the segment
+    const int* active;    // per system of the segment
+    const cplx<T>* cinvT; // coarsest level: transposed inverses
+    double* partial;      // fused norm partial sums, or NULL
+    int x_zero;           // the iterate read is zero (not loaded)
+    int nc;               // coarsest level: unknowns per system
+    int z0;               // first blockIdx.z of the segment
+    int gx, gy;           // blocks of the segment in x and y
+};
+template <typename T> struct SegTable {
+    int n;
+    LevelSeg<T> s[MAXSEG];
+};
+
+#ifdef __HIPCC__
+template <typename T> __device__ __forceinline__ LevelSeg<T> seg_of(const SegTable<T>& t, int z) {
+    LevelSeg<T> r = t.s[0];
+#pragma unroll
+    for (int q = 1; q < MAXSEG; ++q)
+        if (q < t.n && z >= t.s[q].z0) r = t.s[q];
+    return r;
+}
+#endif
+
 // Algorithmic (compulsory) bytes per fine node, complex element size E:
 //   sweep: read x, b, write x'            3E
 //   residual + restriction: read x, b; write r_H on a quarter of the nodes  2E + E/4
@@ -39,17 +76,16 @@ template <typename T> struct Coef {
 struct KernelStats;
 
 // ---- launchers (defined in vmg_kernels.hip); all enqueue on `st` ----
-template <typename T>
-void launch_sweep(const cplx<T>* x, const cplx<T>* b, cplx<T>* xo, LevelView lv, T s,
-                  const Coef<T>* coef, const int* active, int nsys, int x_zero, hipStream_t st);
-
-template <typename T>
-void launch_restrict(const cplx<T>* x, const cplx<T>* b, cplx<T>* bc, LevelView lf, LevelView lc, T s,
-                     const Coef<T>* coef, const int* active, int nsys, int x_zero, hipStream_t st);
-
-template <typename T>
-void launch_prolong(cplx<T>* x, const cplx<T>* e, LevelView lf, LevelView lc, const int* active,
-                    int nsys, int x_zero, hipStream_t st);
+// Batched launchers: every segment's nsys systems, one launch.  nsys[q] is
+// the system count of segment q (z0/gx/gy are filled in here).
+//   sweep:    xo = x + omega M (b - L x)                      (x, b, xo)
+//   restrict: c = FW(b - L x)                                 (x, b, c)
+//   prolong:  xo = x + P c  (in place when xo == x)           (x, c, xo)
+//   coarse:   xo = cinvT^T b                                  (b, xo, cinvT, nc)
+template <typename T> void launch_sweep(SegTable<T> tab, const int* nsys, hipStream_t st);
+template <typename T> void launch_restrict(SegTable<T> tab, const int* nsys, hipStream_t st);
+template <typename T> void launch_prolong(SegTable<T> tab, const int* nsys, hipStream_t st);
+template <typename T> void launch_coarse(SegTable<T> tab, const int* nsys, hipStream_t st);
 
 // r = b - L x; optionally stores r (as TO, in layout lo) and per-tile partial
 // sums of |r|^2 (partial[sys * ntiles + tile]).  Returns ntiles per system.
@@ -59,9 +95,6 @@ int launch_residual(const cplx<T>* x, const cplx<T>* b, cplx<TO>* rout, LevelVie
                     hipStream_t st);
 int residual_tiles(LevelView lv);
 
-template <typename T>
-void launch_coarse(const cplx<T>* b, cplx<T>* x, LevelView lc, const cplx<T>* cinvT, int nc,
-                   const int* active, int nsys, hipStream_t st);
 
 // x64 = (x_zero ? 0 : x64) + e (per active system)
 void launch_ir_update(double2* x, const float2* e, LevelView lx, LevelView le, const int* active, int nsys,
@@ -99,17 +132,16 @@ struct RowLayout {
 void launch_transform(int n, int64_t m, const double2* M, int trans_conj, const double2* in, RowLayout li,
                       double2* out, RowLayout lo, double2* mbuf, hipStream_t st, int accumulate = 0);
 
-// Fused register-streaming level kernels (vmg_stream.hip), nu in {0, 1, 2}:
-//   down: nu sweeps, residual, full weighting -> xo (x_nu), bc (coarse rhs)
-//   up:   x + P e, nu sweeps -> xo; per-block |b - L xo|^2 into partial
-//         (partial[sys * stream_tiles + tile]) when partial != NULL.
+// Fused register-streaming level kernels (vmg_stream.hip), nu in {0, 1, 2},
+// batched over segments like the launchers above:
+//   down: nu sweeps, residual, full weighting -> xo (x_nu), c (coarse rhs)
+//   up:   x + P c, nu sweeps -> xo; per-block |b - L xo|^2 into a segment's
+//         partial (partial[sys * tiles + tile], tiles = stream_tiles(..., norm
+//         = true, ty)) when that pointer is not NULL.  `norm` selects the
+//         geometry with the extra halo lane the norm needs.
 // ty = rows per block.
-template <typename T>
-void launch_down(const cplx<T>* x, const cplx<T>* b, cplx<T>* xo, cplx<T>* bc, LevelView lf, LevelView lc, T s,
-                 const Coef<T>* coef, const int* active, int nsys, int nu, int x_zero, int ty, hipStream_t st);
-template <typename T>
-void launch_up(const cplx<T>* x, const cplx<T>* e, const cplx<T>* b, cplx<T>* xo, LevelView lf, LevelView lc, T s,
-               const Coef<T>* coef, const int* active, int nsys, int nu, int ty, double* partial, hipStream_t st);
+template <typename T> void launch_down(SegTable<T> tab, const int* nsys, int nu, int ty, hipStream_t st);
+template <typename T> void launch_up(SegTable<T> tab, const int* nsys, int nu, bool norm, int ty, hipStream_t st);
 int stream_tiles(int nx, int ny, int nu, bool norm, int ty);
 template <typename T> void launch_fill_zero(cplx<T>* x, LevelView lv, int nsys, hipStream_t st);
 

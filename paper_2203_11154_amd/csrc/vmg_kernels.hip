@@ -40,24 +40,26 @@ template <typename C> __device__ __forceinline__ C cfma(C a, C b, C c) {
 // Tile: TX = 64 columns (one wave per row segment) by TY rows.
 // ---------------------------------------------------------------------------
 template <typename T, int TY>
-__global__ __launch_bounds__(NT) void k_sweep(const cplx<T>* __restrict__ x, const cplx<T>* __restrict__ b,
-                                              cplx<T>* __restrict__ xo, LevelView lv, T s,
-                                              const Coef<T>* __restrict__ coef, const int* __restrict__ active,
-                                              int x_zero) {
+__global__ __launch_bounds__(NT) void k_sweep(SegTable<T> tab) {
     using C = cplx<T>;
     constexpr int TX = 64;
     constexpr int XW = TX + 4, XH = TY + 4;
     constexpr int RW = TX + 2, RH = TY + 2;
     __shared__ C sx[XH * XW];
     __shared__ C sr[RH * RW];
-    const int sys = blockIdx.z;
-    if (!active[sys]) return;
+    const LevelSeg<T> S = seg_of(tab, blockIdx.z);
+    const int sys = blockIdx.z - S.z0;
+    if ((int)blockIdx.x >= S.gx || (int)blockIdx.y >= S.gy) return;
+    if (!S.active[sys]) return;
+    const LevelView lv = S.lf;
+    const int x_zero = S.x_zero;
     const int i0 = blockIdx.x * TX + 1;
     const int k0 = blockIdx.y * TY + 1;
     const int64_t base = (int64_t)sys * lv.plane;
-    const C* xs = x + base;
-    const C* bs = b + base;
-    const Coef<T> cf = coef[sys];
+    const C* xs = S.x + base;
+    const C* bs = S.b + base;
+    const Coef<T> cf = S.coef[sys];
+    const T s = S.s;
 
     if (!x_zero) {
         for (int t = threadIdx.x; t < XH * XW; t += NT) {
@@ -96,7 +98,7 @@ __global__ __launch_bounds__(NT) void k_sweep(const cplx<T>* __restrict__ x, con
         v = cfma(v, cf.ca, sr[c]);
         v = cfma(v, cf.cb, edge);
         v = cfma(v, cf.cc, corner);
-        xo[base + (int64_t)k * lv.pitch + i] = v;
+        S.xo[base + (int64_t)k * lv.pitch + i] = v;
     }
 }
 
@@ -107,24 +109,26 @@ __global__ __launch_bounds__(NT) void k_sweep(const cplx<T>* __restrict__ x, con
 // (2 TXC + 1) x (2 TYC + 1) nodes they cover.
 // ---------------------------------------------------------------------------
 template <typename T>
-__global__ __launch_bounds__(NT) void k_restrict(const cplx<T>* __restrict__ x, const cplx<T>* __restrict__ b,
-                                                 cplx<T>* __restrict__ bc, LevelView lf, LevelView lc, T s,
-                                                 const Coef<T>* __restrict__ coef,
-                                                 const int* __restrict__ active, int x_zero) {
+__global__ __launch_bounds__(NT) void k_restrict(SegTable<T> tab) {
     using C = cplx<T>;
     constexpr int TXC = 32, TYC = 8;
     constexpr int RW = 2 * TXC + 1, RH = 2 * TYC + 1;
     constexpr int XW = RW + 2, XH = RH + 2;
     __shared__ C sx[XH * XW];
     __shared__ C sr[RH * RW];
-    const int sys = blockIdx.z;
-    if (!active[sys]) return;
+    const LevelSeg<T> S = seg_of(tab, blockIdx.z);
+    const int sys = blockIdx.z - S.z0;
+    if ((int)blockIdx.x >= S.gx || (int)blockIdx.y >= S.gy) return;
+    if (!S.active[sys]) return;
+    const LevelView lf = S.lf, lc = S.lc;
+    const int x_zero = S.x_zero;
     const int I0 = blockIdx.x * TXC + 1, K0 = blockIdx.y * TYC + 1;
     const int fi0 = 2 * I0 - 1, fk0 = 2 * K0 - 1;  // first fine node of the residual region
     const int64_t basef = (int64_t)sys * lf.plane;
-    const C* xs = x + basef;
-    const C* bs = b + basef;
-    const Coef<T> cf = coef[sys];
+    const C* xs = S.x + basef;
+    const C* bs = S.b + basef;
+    const Coef<T> cf = S.coef[sys];
+    const T s = S.s;
     if (!x_zero) {
         for (int t = threadIdx.x; t < XH * XW; t += NT) {
             const int ry = t / XW, rx = t - ry * XW;
@@ -160,7 +164,7 @@ __global__ __launch_bounds__(NT) void k_restrict(const cplx<T>* __restrict__ x, 
         C v = cscale(sr[c], (T)0.25);
         v = cadd(v, cscale(edge, (T)0.125));
         v = cadd(v, cscale(corner, (T)0.0625));
-        bc[(int64_t)sys * lc.plane + (int64_t)K * lc.pitch + I] = v;
+        S.c[(int64_t)sys * lc.plane + (int64_t)K * lc.pitch + I] = v;
     }
 }
 
@@ -170,17 +174,19 @@ __global__ __launch_bounds__(NT) void k_restrict(const cplx<T>* __restrict__ x, 
 // with weights 1, 1/2, 1/4 (the coarse ring holds zeros).
 // ---------------------------------------------------------------------------
 template <typename T>
-__global__ __launch_bounds__(NT) void k_prolong(cplx<T>* __restrict__ x, const cplx<T>* __restrict__ e,
-                                                LevelView lf, LevelView lc, const int* __restrict__ active,
-                                                int x_zero) {
+__global__ __launch_bounds__(NT) void k_prolong(SegTable<T> tab) {
     using C = cplx<T>;
     constexpr int TX = 64, TY = 16;
-    const int sys = blockIdx.z;
-    if (!active[sys]) return;
+    const LevelSeg<T> S = seg_of(tab, blockIdx.z);
+    const int sys = blockIdx.z - S.z0;
+    if ((int)blockIdx.x >= S.gx || (int)blockIdx.y >= S.gy) return;
+    if (!S.active[sys]) return;
+    const LevelView lf = S.lf, lc = S.lc;
     const int i = blockIdx.x * TX + (threadIdx.x & 63) + 1;
     if (i > lf.nx) return;
-    const C* es = e + (int64_t)sys * lc.plane;
-    C* xs = x + (int64_t)sys * lf.plane;
+    const C* es = S.c + (int64_t)sys * lc.plane;
+    const C* xs = S.x + (int64_t)sys * lf.plane;
+    C* xos = S.xo + (int64_t)sys * lf.plane;
     const int il = i >> 1, ir = (i + 1) >> 1;       // coarse columns around fine i
     const T wx = (i & 1) ? (T)0.5 : (T)1.0;         // odd: average of two
     for (int k = blockIdx.y * TY + (threadIdx.x >> 6) + 1; k <= min(lf.ny, (int)(blockIdx.y + 1) * TY);
@@ -202,7 +208,7 @@ __global__ __launch_bounds__(NT) void k_prolong(cplx<T>* __restrict__ x, const c
             v = cscale(v, wx * wy);
         }
         const int64_t o = (int64_t)k * lf.pitch + i;
-        xs[o] = x_zero ? v : cadd(xs[o], v);
+        xos[o] = S.x_zero ? v : cadd(xs[o], v);
     }
 }
 
@@ -260,27 +266,28 @@ __global__ __launch_bounds__(NT) void k_residual(const cplx<T>* __restrict__ x, 
 // on the host (stored transposed: cinvT[k * nc + row]).  One block per system.
 // ---------------------------------------------------------------------------
 template <typename T>
-__global__ __launch_bounds__(NT) void k_coarse(const cplx<T>* __restrict__ b, cplx<T>* __restrict__ x,
-                                               LevelView lc, const cplx<T>* __restrict__ cinvT, int nc,
-                                               const int* __restrict__ active) {
+__global__ __launch_bounds__(NT) void k_coarse(SegTable<T> tab) {
     using C = cplx<T>;
     __shared__ C sb[NT];
-    const int sys = blockIdx.x;
-    if (!active[sys]) return;
+    const LevelSeg<T> S = seg_of(tab, blockIdx.z);
+    const int sys = blockIdx.z - S.z0;
+    if (!S.active[sys]) return;
+    const LevelView lc = S.lf;
+    const int nc = S.nc;
     const int t = threadIdx.x;
     const int64_t base = (int64_t)sys * lc.plane;
     int64_t o = 0;
     if (t < nc) {
         const int k = t / lc.nx + 1, i = t - (k - 1) * lc.nx + 1;
         o = base + (int64_t)k * lc.pitch + i;
-        sb[t] = b[o];
+        sb[t] = S.b[o];
     }
     __syncthreads();
     if (t < nc) {
-        const C* ci = cinvT + (int64_t)sys * nc * nc;
+        const C* ci = S.cinvT + (int64_t)sys * nc * nc;
         C acc = czero<C>();
         for (int k = 0; k < nc; ++k) acc = cfma(acc, ci[(int64_t)k * nc + t], sb[k]);
-        x[o] = acc;
+        S.xo[o] = acc;
     }
 }
 
@@ -379,26 +386,41 @@ inline dim3 grid2(int nx, int ny, int tx, int ty, int nsys) {
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
-template <typename T>
-void launch_sweep(const cplx<T>* x, const cplx<T>* b, cplx<T>* xo, LevelView lv, T s, const Coef<T>* coef,
-                  const int* active, int nsys, int x_zero, hipStream_t st) {
+// Fill z0 and the per-segment block extents; return the launch grid.
+template <typename T> dim3 seg_grid(SegTable<T>& tab, const int* nsys, int tx, int ty, bool coarse_dims) {
+    int z = 0, gx = 1, gy = 1;
+    for (int q = 0; q < tab.n; ++q) {
+        LevelSeg<T>& S = tab.s[q];
+        const LevelView& v = coarse_dims ? S.lc : S.lf;
+        S.z0 = z;
+        S.gx = (v.nx + tx - 1) / tx;
+        S.gy = (v.ny + ty - 1) / ty;
+        gx = max(gx, S.gx);
+        gy = max(gy, S.gy);
+        z += nsys[q];
+    }
+    return dim3(gx, gy, z);
+}
+
+template <typename T> void launch_sweep(SegTable<T> tab, const int* nsys, hipStream_t st) {
     constexpr int TY = 16;
-    hipLaunchKernelGGL((k_sweep<T, TY>), grid2(lv.nx, lv.ny, 64, TY, nsys), dim3(NT), 0, st, x, b, xo, lv, s, coef,
-                       active, x_zero);
+    const dim3 g = seg_grid(tab, nsys, 64, TY, false);
+    hipLaunchKernelGGL((k_sweep<T, TY>), g, dim3(NT), 0, st, tab);
 }
 
-template <typename T>
-void launch_restrict(const cplx<T>* x, const cplx<T>* b, cplx<T>* bc, LevelView lf, LevelView lc, T s,
-                     const Coef<T>* coef, const int* active, int nsys, int x_zero, hipStream_t st) {
-    hipLaunchKernelGGL((k_restrict<T>), grid2(lc.nx, lc.ny, 32, 8, nsys), dim3(NT), 0, st, x, b, bc, lf, lc, s, coef,
-                       active, x_zero);
+template <typename T> void launch_restrict(SegTable<T> tab, const int* nsys, hipStream_t st) {
+    const dim3 g = seg_grid(tab, nsys, 32, 8, true);
+    hipLaunchKernelGGL((k_restrict<T>), g, dim3(NT), 0, st, tab);
 }
 
-template <typename T>
-void launch_prolong(cplx<T>* x, const cplx<T>* e, LevelView lf, LevelView lc, const int* active, int nsys,
-                    int x_zero, hipStream_t st) {
-    hipLaunchKernelGGL((k_prolong<T>), grid2(lf.nx, lf.ny, 64, 16, nsys), dim3(NT), 0, st, x, e, lf, lc, active,
-                       x_zero);
+template <typename T> void launch_prolong(SegTable<T> tab, const int* nsys, hipStream_t st) {
+    const dim3 g = seg_grid(tab, nsys, 64, 16, false);
+    hipLaunchKernelGGL((k_prolong<T>), g, dim3(NT), 0, st, tab);
+}
+
+template <typename T> void launch_coarse(SegTable<T> tab, const int* nsys, hipStream_t st) {
+    const dim3 g = seg_grid(tab, nsys, 1 << 20, 1 << 20, false);
+    hipLaunchKernelGGL((k_coarse<T>), dim3(1, 1, g.z), dim3(NT), 0, st, tab);
 }
 
 int residual_tiles(LevelView lv) { return ((lv.nx + 63) / 64) * ((lv.ny + 15) / 16); }
@@ -409,12 +431,6 @@ int launch_residual(const cplx<T>* x, const cplx<T>* b, cplx<TO>* rout, LevelVie
     hipLaunchKernelGGL((k_residual<T, TO>), grid2(lv.nx, lv.ny, 64, 16, nsys), dim3(NT), 0, st, x, b, rout, lv, lo, s,
                        coef, active, x_zero, partial);
     return residual_tiles(lv);
-}
-
-template <typename T>
-void launch_coarse(const cplx<T>* b, cplx<T>* x, LevelView lc, const cplx<T>* cinvT, int nc, const int* active,
-                   int nsys, hipStream_t st) {
-    hipLaunchKernelGGL((k_coarse<T>), dim3(nsys), dim3(NT), 0, st, b, x, lc, cinvT, nc, active);
 }
 
 void launch_ir_update(double2* x, const float2* e, LevelView lx, LevelView le, const int* active, int nsys,
@@ -447,14 +463,10 @@ void launch_fill_int(int* p, int value, int n, hipStream_t st) {
 }
 
 #define VMG_INST(T)                                                                                              \
-    template void launch_sweep<T>(const cplx<T>*, const cplx<T>*, cplx<T>*, LevelView, T, const Coef<T>*,       \
-                                  const int*, int, int, hipStream_t);                                           \
-    template void launch_restrict<T>(const cplx<T>*, const cplx<T>*, cplx<T>*, LevelView, LevelView, T,         \
-                                     const Coef<T>*, const int*, int, int, hipStream_t);                        \
-    template void launch_prolong<T>(cplx<T>*, const cplx<T>*, LevelView, LevelView, const int*, int, int,       \
-                                    hipStream_t);                                                               \
-    template void launch_coarse<T>(const cplx<T>*, cplx<T>*, LevelView, const cplx<T>*, int, const int*, int,   \
-                                   hipStream_t);                                                                \
+    template void launch_sweep<T>(SegTable<T>, const int*, hipStream_t);                                         \
+    template void launch_restrict<T>(SegTable<T>, const int*, hipStream_t);                                      \
+    template void launch_prolong<T>(SegTable<T>, const int*, hipStream_t);                                       \
+    template void launch_coarse<T>(SegTable<T>, const int*, hipStream_t);                                        \
     template void launch_pack<T>(const cplx<T>*, cplx<T>*, LevelView, int, hipStream_t);                      \
     template void launch_unpack<T>(const cplx<T>*, const cplx<T>*, cplx<T>*, LevelView, int, const int*, int,  \
                                    hipStream_t);

@@ -74,6 +74,14 @@ struct Group {
     int nact = 0;   // systems active at the last host check (for byte accounting)
 };
 
+struct GraphKey {
+    int first, conj, fixed, parity;
+    double tol;
+    bool operator==(const GraphKey& o) const {
+        return first == o.first && conj == o.conj && fixed == o.fixed && parity == o.parity && tol == o.tol;
+    }
+};
+
 struct TimedLaunch {
     int kclass;
     int level;
@@ -111,6 +119,9 @@ struct vmg_handle {
     std::vector<std::vector<int32_t>> heat_record[2];  // inner counts per outer step [transpose]
     double* heat_partial = nullptr;    // heat-residual partial sums (+1: the total)
     std::vector<void*> allocations;
+    // captured cycles
+    hipStream_t cap_stream = nullptr;
+    std::vector<std::pair<GraphKey, hipGraphExec_t>> graphs;
     // timing
     bool timing = false;
     std::vector<TimedLaunch> pending;
@@ -328,20 +339,67 @@ int stream_rows_for(const vmg_handle* H, const LevelView& v) {
     return v.ny > 600 ? 128 : (v.ny > 200 ? 64 : 32);
 }
 
+// One grid's segment at level l (see LevelSeg).
+template <typename T>
+LevelSeg<T> make_seg(vmg_handle* H, Group& g, int conj, int l, const cplx<T>* x, const cplx<T>* b, cplx<T>* xo,
+                     cplx<T>* c, int x_zero, double* partial) {
+    auto& L = levels_of<T>(g);
+    LevelSeg<T> S{};
+    S.x = x;
+    S.b = b;
+    S.xo = xo;
+    S.c = c;
+    S.lf = L[l].v;
+    S.lc = (l + 1 < g.L) ? L[l + 1].v : L[l].v;
+    S.s = (T)(1.0 / (L[l].h * L[l].h));
+    S.coef = coef_of<T>(g, conj, l);
+    S.active = H->active + g.sys0;
+    S.cinvT = cinv_of<T>(g, conj);
+    S.nc = g.nc;
+    S.partial = partial;
+    S.x_zero = x_zero;
+    return S;
+}
+
+template <typename T> SegTable<T> one_seg(const LevelSeg<T>& S) {
+    SegTable<T> t{};
+    t.n = 1;
+    t.s[0] = S;
+    return t;
+}
+
+// Accumulates the segments of one batched launch (flushed every MAXSEG).
+template <typename T> struct SegBatch {
+    SegTable<T> tab{};
+    int nsys[MAXSEG] = {};
+    double bytes = 0.0;
+    void add(const LevelSeg<T>& S, int n, double by) {
+        tab.s[tab.n] = S;
+        nsys[tab.n] = n;
+        ++tab.n;
+        bytes += by;
+    }
+    bool full() const { return tab.n == MAXSEG; }
+    void clear() {
+        tab.n = 0;
+        bytes = 0.0;
+    }
+};
+
 template <typename T> void enqueue_cycle(CycleCtx<T>& c, int l, bool x_zero) {
     vmg_handle* H = c.H;
     Group& g = *c.g;
     auto& L = levels_of<T>(g);
     Level& lv = L[l];
-    const int* act = H->active + g.sys0;
     const double E = sizeof(cplx<T>);
-    const T s = (T)(1.0 / (lv.h * lv.h));
-    const Coef<T>* cf = coef_of<T>(g, c.conj, l);
     const vmg_opts& o = H->opts;
+    const int one = g.S;
     if (l == 0) c.norm_fused = false;
     if (l == g.L - 1) {
         Timer t(H, c.st, VMG_K_COARSE, E * ((double)g.nc * g.nc + 2.0 * g.nc) * g.nact, l);
-        launch_coarse<T>(P<T>(lv.b), P<T>(lv.x[c.cur[l]]), lv.v, cinv_of<T>(g, c.conj), g.nc, act, g.S, c.st);
+        launch_coarse<T>(one_seg(make_seg<T>(H, g, c.conj, l, nullptr, P<T>(lv.b), P<T>(lv.x[c.cur[l]]), nullptr, 0,
+                                             nullptr)),
+                         &one, c.st);
         return;
     }
     Level& lc = L[l + 1];
@@ -350,8 +408,9 @@ template <typename T> void enqueue_cycle(CycleCtx<T>& c, int l, bool x_zero) {
         {
             const double by = ((x_zero ? 0.0 : 1.0) + 1.0 + (o.nu1 > 0 ? 1.0 : 0.0) + 0.25) * E * nodes(lv.v) * g.nact;
             Timer t(H, c.st, VMG_K_DOWN, by, l);
-            launch_down<T>(P<T>(lv.x[c.cur[l]]), P<T>(lv.b), P<T>(lv.x[1 - c.cur[l]]), P<T>(lc.b), lv.v, lc.v, s, cf,
-                           act, g.S, o.nu1, x_zero, stream_rows_for(H, lv.v), c.st);
+            launch_down<T>(one_seg(make_seg<T>(H, g, c.conj, l, P<T>(lv.x[c.cur[l]]), P<T>(lv.b),
+                                               P<T>(lv.x[1 - c.cur[l]]), P<T>(lc.b), x_zero, nullptr)),
+                           &one, o.nu1, stream_rows_for(H, lv.v), c.st);
         }
         if (o.nu1 > 0) {
             c.cur[l] ^= 1;
@@ -369,8 +428,9 @@ template <typename T> void enqueue_cycle(CycleCtx<T>& c, int l, bool x_zero) {
         {
             const double by = (2.0 + 0.25 + ((o.nu2 > 0 || np) ? 1.0 : 0.0)) * E * nodes(lv.v) * g.nact;
             Timer t(H, c.st, VMG_K_UP, by, l);
-            launch_up<T>(P<T>(lv.x[c.cur[l]]), P<T>(lc.x[c.cur[l + 1]]), P<T>(lv.b), P<T>(lv.x[1 - c.cur[l]]), lv.v,
-                         lc.v, s, cf, act, g.S, o.nu2, stream_rows_for(H, lv.v), np, c.st);
+            launch_up<T>(one_seg(make_seg<T>(H, g, c.conj, l, P<T>(lv.x[c.cur[l]]), P<T>(lv.b),
+                                             P<T>(lv.x[1 - c.cur[l]]), P<T>(lc.x[c.cur[l + 1]]), 0, np)),
+                         &one, o.nu2, np != nullptr, stream_rows_for(H, lv.v), c.st);
         }
         c.cur[l] ^= 1;
         if (np) c.norm_fused = true;
@@ -378,14 +438,17 @@ template <typename T> void enqueue_cycle(CycleCtx<T>& c, int l, bool x_zero) {
     }
     for (int i = 0; i < o.nu1; ++i) {
         Timer t(H, c.st, VMG_K_SWEEP, (x_zero ? 2.0 : 3.0) * E * nodes(lv.v) * g.nact, l);
-        launch_sweep<T>(P<T>(lv.x[c.cur[l]]), P<T>(lv.b), P<T>(lv.x[1 - c.cur[l]]), lv.v, s, cf, act, g.S, x_zero,
-                        c.st);
+        launch_sweep<T>(one_seg(make_seg<T>(H, g, c.conj, l, P<T>(lv.x[c.cur[l]]), P<T>(lv.b), P<T>(lv.x[1 - c.cur[l]]),
+                                            nullptr, x_zero, nullptr)),
+                        &one, c.st);
         c.cur[l] ^= 1;
         x_zero = false;
     }
     {
         Timer t(H, c.st, VMG_K_RESTRICT, ((x_zero ? 1.0 : 2.0) + 0.25) * E * nodes(lv.v) * g.nact, l);
-        launch_restrict<T>(P<T>(lv.x[c.cur[l]]), P<T>(lv.b), P<T>(lc.b), lv.v, lc.v, s, cf, act, g.S, x_zero, c.st);
+        launch_restrict<T>(one_seg(make_seg<T>(H, g, c.conj, l, P<T>(lv.x[c.cur[l]]), P<T>(lv.b), nullptr,
+                                               P<T>(lc.b), x_zero, nullptr)),
+                           &one, c.st);
     }
     bool cz = true;
     for (int k = 0; k < o.gamma; ++k) {
@@ -394,13 +457,206 @@ template <typename T> void enqueue_cycle(CycleCtx<T>& c, int l, bool x_zero) {
     }
     {
         Timer t(H, c.st, VMG_K_PROLONG, ((x_zero ? 1.0 : 2.0) + 0.25) * E * nodes(lv.v) * g.nact, l);
-        launch_prolong<T>(P<T>(lv.x[c.cur[l]]), P<T>(lc.x[c.cur[l + 1]]), lv.v, lc.v, act, g.S, x_zero, c.st);
+        launch_prolong<T>(one_seg(make_seg<T>(H, g, c.conj, l, P<T>(lv.x[c.cur[l]]), nullptr, P<T>(lv.x[c.cur[l]]),
+                                              P<T>(lc.x[c.cur[l + 1]]), x_zero, nullptr)),
+                          &one, c.st);
     }
     x_zero = false;
     for (int i = 0; i < o.nu2; ++i) {
         Timer t(H, c.st, VMG_K_SWEEP, 3.0 * E * nodes(lv.v) * g.nact, l);
-        launch_sweep<T>(P<T>(lv.x[c.cur[l]]), P<T>(lv.b), P<T>(lv.x[1 - c.cur[l]]), lv.v, s, cf, act, g.S, 0, c.st);
+        launch_sweep<T>(one_seg(make_seg<T>(H, g, c.conj, l, P<T>(lv.x[c.cur[l]]), P<T>(lv.b), P<T>(lv.x[1 - c.cur[l]]),
+                                            nullptr, 0, nullptr)),
+                        &one, c.st);
         c.cur[l] ^= 1;
+    }
+}
+
+// One V-cycle of every grid, batched: the grids are aligned at their
+// coarsest level, so phase d (d levels above the coarsest) is one launch per
+// kernel over all grids that reach that high, whatever their sizes.
+//   cur[g][l]   ping-pong state of grid g, level l (updated)
+//   first       level 0 starts from x = 0 (first cycle)
+//   partials[g] fused finest-level norm target of grid g (or NULL)
+//   fused[g]    set when grid g's norm partials were produced
+template <typename T>
+void enqueue_batched_vcycle(vmg_handle* H, int conj, hipStream_t st, bool first, std::vector<std::vector<int>>& cur,
+                            const std::vector<double*>& partials, std::vector<char>& fused) {
+    const vmg_opts& o = H->opts;
+    const double E = sizeof(cplx<T>);
+    const int ng = (int)H->groups.size();
+    int dmax = 0;
+    for (auto& g : H->groups) dmax = std::max(dmax, g.L - 1);
+    for (int gi = 0; gi < ng; ++gi) fused[gi] = 0;
+    auto level_of = [&](int gi, int d) { return H->groups[gi].L - 1 - d; };
+    auto bytes_of = [&](Group& g, int l, double per_node) { return per_node * E * nodes(levels_of<T>(g)[l].v) * g.nact; };
+
+    // ---------------- descent: phases d = dmax .. 1
+    for (int d = dmax; d >= 1; --d) {
+        std::vector<int> sg, lg;  // streamed / LDS-path grids of this phase
+        for (int gi = 0; gi < ng; ++gi) {
+            if (H->groups[gi].L - 1 < d) continue;
+            const int l = level_of(gi, d);
+            (use_stream(o, levels_of<T>(H->groups[gi])[l].v) ? sg : lg).push_back(gi);
+        }
+        // streamed grids: one fused launch per row-block height
+        while (!sg.empty()) {
+            const int ty = stream_rows_for(H, levels_of<T>(H->groups[sg[0]])[level_of(sg[0], d)].v);
+            SegBatch<T> bt;
+            std::vector<int> rest, done;
+            for (int gi : sg) {
+                Group& g = H->groups[gi];
+                const int l = level_of(gi, d);
+                auto& L = levels_of<T>(g);
+                if (stream_rows_for(H, L[l].v) != ty || bt.full()) {
+                    rest.push_back(gi);
+                    continue;
+                }
+                const int xz = (l > 0 || first) ? 1 : 0;
+                bt.add(make_seg<T>(H, g, conj, l, P<T>(L[l].x[cur[gi][l]]), P<T>(L[l].b), P<T>(L[l].x[1 - cur[gi][l]]),
+                                   P<T>(L[l + 1].b), xz, nullptr),
+                       g.S, bytes_of(g, l, (xz ? 0.0 : 1.0) + 1.0 + (o.nu1 > 0 ? 1.0 : 0.0) + 0.25));
+                done.push_back(gi);
+            }
+            {
+                Timer t(H, st, VMG_K_DOWN, bt.bytes, level_of(done[0], d));
+                launch_down<T>(bt.tab, bt.nsys, o.nu1, ty, st);
+            }
+            for (int gi : done) {
+                Group& g = H->groups[gi];
+                const int l = level_of(gi, d);
+                auto& L = levels_of<T>(g);
+                if (o.nu1 > 0) cur[gi][l] ^= 1;
+                else if (l > 0 || first) launch_fill_zero<T>(P<T>(L[l].x[cur[gi][l]]), L[l].v, g.S, st);
+            }
+            sg.swap(rest);
+        }
+        // LDS-path grids: nu1 batched sweeps, then a batched restriction
+        if (!lg.empty()) {
+            std::vector<int> xz(ng, 0);
+            for (int gi : lg) xz[gi] = (level_of(gi, d) > 0 || first) ? 1 : 0;
+            for (int it = 0; it < o.nu1; ++it) {
+                for (size_t k0 = 0; k0 < lg.size(); k0 += MAXSEG) {
+                    SegBatch<T> bt;
+                    for (size_t k = k0; k < lg.size() && k < k0 + MAXSEG; ++k) {
+                        const int gi = lg[k];
+                        Group& g = H->groups[gi];
+                        const int l = level_of(gi, d);
+                        auto& L = levels_of<T>(g);
+                        bt.add(make_seg<T>(H, g, conj, l, P<T>(L[l].x[cur[gi][l]]), P<T>(L[l].b),
+                                           P<T>(L[l].x[1 - cur[gi][l]]), nullptr, xz[gi], nullptr),
+                               g.S, bytes_of(g, l, xz[gi] ? 2.0 : 3.0));
+                    }
+                    Timer t(H, st, VMG_K_SWEEP, bt.bytes, level_of(lg[k0], d));
+                    launch_sweep<T>(bt.tab, bt.nsys, st);
+                }
+                for (int gi : lg) {
+                    cur[gi][level_of(gi, d)] ^= 1;
+                    xz[gi] = 0;
+                }
+            }
+            for (size_t k0 = 0; k0 < lg.size(); k0 += MAXSEG) {
+                SegBatch<T> bt;
+                for (size_t k = k0; k < lg.size() && k < k0 + MAXSEG; ++k) {
+                    const int gi = lg[k];
+                    Group& g = H->groups[gi];
+                    const int l = level_of(gi, d);
+                    auto& L = levels_of<T>(g);
+                    bt.add(make_seg<T>(H, g, conj, l, P<T>(L[l].x[cur[gi][l]]), P<T>(L[l].b), nullptr,
+                                       P<T>(L[l + 1].b), xz[gi], nullptr),
+                           g.S, bytes_of(g, l, (xz[gi] ? 1.0 : 2.0) + 0.25));
+                }
+                Timer t(H, st, VMG_K_RESTRICT, bt.bytes, level_of(lg[k0], d));
+                launch_restrict<T>(bt.tab, bt.nsys, st);
+            }
+        }
+    }
+    // ---------------- coarsest level of every grid: one batched direct solve
+    for (int k0 = 0; k0 < ng; k0 += MAXSEG) {
+        SegBatch<T> bt;
+        for (int gi = k0; gi < ng && gi < k0 + MAXSEG; ++gi) {
+            Group& g = H->groups[gi];
+            const int l = g.L - 1;
+            auto& L = levels_of<T>(g);
+            bt.add(make_seg<T>(H, g, conj, l, nullptr, P<T>(L[l].b), P<T>(L[l].x[cur[gi][l]]), nullptr, 0, nullptr),
+                   g.S, E * ((double)g.nc * g.nc + 2.0 * g.nc) * g.nact);
+        }
+        Timer t(H, st, VMG_K_COARSE, bt.bytes, H->groups[k0].L - 1);
+        launch_coarse<T>(bt.tab, bt.nsys, st);
+    }
+    // ---------------- ascent: phases d = 1 .. dmax
+    for (int d = 1; d <= dmax; ++d) {
+        std::vector<int> sg, lg;
+        for (int gi = 0; gi < ng; ++gi) {
+            if (H->groups[gi].L - 1 < d) continue;
+            const int l = level_of(gi, d);
+            (use_stream(o, levels_of<T>(H->groups[gi])[l].v) ? sg : lg).push_back(gi);
+        }
+        while (!sg.empty()) {
+            const int ty = stream_rows_for(H, levels_of<T>(H->groups[sg[0]])[level_of(sg[0], d)].v);
+            SegBatch<T> bt;
+            std::vector<int> rest, done;
+            bool any_norm = false;
+            for (int gi : sg) {
+                Group& g = H->groups[gi];
+                const int l = level_of(gi, d);
+                auto& L = levels_of<T>(g);
+                if (stream_rows_for(H, L[l].v) != ty || bt.full()) {
+                    rest.push_back(gi);
+                    continue;
+                }
+                double* np = (l == 0) ? partials[gi] : nullptr;
+                any_norm |= np != nullptr;
+                bt.add(make_seg<T>(H, g, conj, l, P<T>(L[l].x[cur[gi][l]]), P<T>(L[l].b), P<T>(L[l].x[1 - cur[gi][l]]),
+                                   P<T>(L[l + 1].x[cur[gi][l + 1]]), 0, np),
+                       g.S, bytes_of(g, l, 2.0 + 0.25 + ((o.nu2 > 0 || np) ? 1.0 : 0.0)));
+                done.push_back(gi);
+            }
+            {
+                Timer t(H, st, VMG_K_UP, bt.bytes, level_of(done[0], d));
+                launch_up<T>(bt.tab, bt.nsys, o.nu2, any_norm, ty, st);
+            }
+            for (int gi : done) {
+                const int l = level_of(gi, d);
+                cur[gi][l] ^= 1;
+                if (l == 0 && partials[gi]) fused[gi] = 1;
+            }
+            sg.swap(rest);
+        }
+        if (!lg.empty()) {
+            for (size_t k0 = 0; k0 < lg.size(); k0 += MAXSEG) {
+                SegBatch<T> bt;
+                for (size_t k = k0; k < lg.size() && k < k0 + MAXSEG; ++k) {
+                    const int gi = lg[k];
+                    Group& g = H->groups[gi];
+                    const int l = level_of(gi, d);
+                    auto& L = levels_of<T>(g);
+                    // with nu1 = 0 the iterate of a zero start is still zero here
+                    const int xz = (o.nu1 == 0 && (l > 0 || first)) ? 1 : 0;
+                    bt.add(make_seg<T>(H, g, conj, l, P<T>(L[l].x[cur[gi][l]]), nullptr, P<T>(L[l].x[cur[gi][l]]),
+                                       P<T>(L[l + 1].x[cur[gi][l + 1]]), xz, nullptr),
+                           g.S, bytes_of(g, l, (xz ? 1.0 : 2.0) + 0.25));
+                }
+                Timer t(H, st, VMG_K_PROLONG, bt.bytes, level_of(lg[k0], d));
+                launch_prolong<T>(bt.tab, bt.nsys, st);
+            }
+            for (int it = 0; it < o.nu2; ++it) {
+                for (size_t k0 = 0; k0 < lg.size(); k0 += MAXSEG) {
+                    SegBatch<T> bt;
+                    for (size_t k = k0; k < lg.size() && k < k0 + MAXSEG; ++k) {
+                        const int gi = lg[k];
+                        Group& g = H->groups[gi];
+                        const int l = level_of(gi, d);
+                        auto& L = levels_of<T>(g);
+                        bt.add(make_seg<T>(H, g, conj, l, P<T>(L[l].x[cur[gi][l]]), P<T>(L[l].b),
+                                           P<T>(L[l].x[1 - cur[gi][l]]), nullptr, 0, nullptr),
+                               g.S, bytes_of(g, l, 3.0));
+                    }
+                    Timer t(H, st, VMG_K_SWEEP, bt.bytes, level_of(lg[k0], d));
+                    launch_sweep<T>(bt.tab, bt.nsys, st);
+                }
+                for (int gi : lg) cur[gi][level_of(gi, d)] ^= 1;
+            }
+        }
     }
 }
 
@@ -526,6 +782,99 @@ int next_batch(const vmg_opts& o, double tol, const int32_t* fixed, const vmg_ha
     return std::max(1, b == (1 << 30) ? 1 : b);
 }
 
+// Everything one cycle (complex128) or one refinement step (complex64 cycles
+// inside FP64 refinement) enqueues, including the convergence update.
+int enqueue_cycle_all(vmg_handle* H, int conj, hipStream_t st, int64_t cycle, double tol, int fixed) {
+    const vmg_opts& o = H->opts;
+    const bool first = cycle == 0;
+    const size_t ng = H->groups.size();
+    std::vector<int> cur0(ng, 0);
+    std::vector<char> fused(ng, 0);
+    if (o.precision == 0) {
+        if (o.gamma == 1) {
+            std::vector<std::vector<int>> cur(ng);
+            std::vector<double*> parts(ng);
+            for (size_t gi = 0; gi < ng; ++gi) {
+                Group& g = H->groups[gi];
+                cur[gi].assign(g.L, 0);
+                // level-0 buffer parity is a function of the cycles run so far
+                cur[gi][0] = (int)((cycle * level0_flips(H, g)) & 1);
+                parts[gi] = g.partial;
+            }
+            enqueue_batched_vcycle<double>(H, conj, st, first, cur, parts, fused);
+            for (size_t gi = 0; gi < ng; ++gi) cur0[gi] = cur[gi][0];
+        } else {
+            for (size_t gi = 0; gi < ng; ++gi) {
+                Group& g = H->groups[gi];
+                CycleCtx<double> ctx{H, &g, conj, st, std::vector<int>(g.L, 0)};
+                ctx.cur[0] = (int)((cycle * level0_flips(H, g)) & 1);
+                ctx.norm_partial = g.partial;
+                enqueue_cycle<double>(ctx, 0, first);
+                cur0[gi] = ctx.cur[0];
+                fused[gi] = ctx.norm_fused;
+            }
+        }
+    } else {
+        std::vector<std::vector<int>> cur(ng);
+        for (size_t gi = 0; gi < ng; ++gi) cur[gi].assign(H->groups[gi].L, 0);
+        if (o.gamma == 1) {
+            std::vector<double*> parts(ng, nullptr);
+            std::vector<char> dummy(ng, 0);
+            for (int k = 0; k < o.ir_inner; ++k) enqueue_batched_vcycle<float>(H, conj, st, k == 0, cur, parts, dummy);
+        } else {
+            for (size_t gi = 0; gi < ng; ++gi) {
+                Group& g = H->groups[gi];
+                CycleCtx<float> ctx{H, &g, conj, st, cur[gi]};
+                for (int k = 0; k < o.ir_inner; ++k) enqueue_cycle<float>(ctx, 0, k == 0);
+                cur[gi] = ctx.cur;
+            }
+        }
+        for (size_t gi = 0; gi < ng; ++gi) {
+            Group& g = H->groups[gi];
+            Level& l0 = g.lv64[0];
+            Level& e0 = g.lv32[0];
+            Timer t(H, st, VMG_K_IR, (first ? 24.0 : 40.0) * nodes(l0.v) * g.nact);
+            launch_ir_update(P<double>(l0.x[0]), P<float>(e0.x[cur[gi][0]]), l0.v, e0.v, H->active + g.sys0, g.S, first,
+                             st);
+        }
+    }
+    return enqueue_norm_check(H, st, 1, tol, fixed, conj, cur0, fused);
+}
+
+// Enqueue one cycle, replaying a captured hipGraph of it when graphs are on
+// and kernel timing is off.  A graph is captured once per distinct launch
+// sequence (first cycle or not, conj, level-0 buffer parity, tolerance).
+int run_cycle(vmg_handle* H, int conj, hipStream_t st, int64_t cycle, double tol, int fixed) {
+    if (!H->opts.graphs || H->timing) return enqueue_cycle_all(H, conj, st, cycle, tol, fixed);
+    int par = 0;
+    for (size_t gi = 0; gi < H->groups.size(); ++gi)
+        par |= (int)(((cycle * level0_flips(H, H->groups[gi])) & 1) << (gi & 31));
+    if (H->opts.precision == 1) par = 0;
+    GraphKey key{cycle == 0 ? 1 : 0, conj, fixed, par, tol};
+    hipGraphExec_t exec = nullptr;
+    for (auto& e : H->graphs)
+        if (e.first == key) exec = e.second;
+    if (!exec) {
+        if (!H->cap_stream && hipStreamCreateWithFlags(&H->cap_stream, hipStreamNonBlocking) != hipSuccess)
+            return VMG_HIP_ERROR;
+        hipGraph_t graph = nullptr;
+        VMG_HIP(hipStreamBeginCapture(H->cap_stream, hipStreamCaptureModeThreadLocal));
+        const int rc = enqueue_cycle_all(H, conj, H->cap_stream, cycle, tol, fixed);
+        const hipError_t ec = hipStreamEndCapture(H->cap_stream, &graph);
+        if (rc) {
+            if (graph) (void)hipGraphDestroy(graph);
+            return rc;
+        }
+        if (ec != hipSuccess || !graph) return VMG_HIP_ERROR;
+        const hipError_t ei = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (ei != hipSuccess) return VMG_HIP_ERROR;
+        H->graphs.push_back({key, exec});
+    }
+    VMG_HIP(hipGraphLaunch(exec, st));
+    return VMG_OK;
+}
+
 int solve_impl(vmg_handle* H, const double* B, double* Z, double tol, int conj, const int32_t* fixed,
                int32_t* iters_out, double* relres_out, hipStream_t st) {
     const vmg_opts& o = H->opts;
@@ -573,35 +922,11 @@ int solve_impl(vmg_handle* H, const double* B, double* Z, double tol, int conj, 
     int done = 0;
     if (read_state(H, st)) return VMG_HIP_ERROR;
     int batch = first_batch(o, tol, fixed, H, maxc);
-    std::vector<int> cur0(H->groups.size(), 0);
-    std::vector<char> fused(H->groups.size(), 0);
     while (done < maxc && any_active(H)) {
         const int nb = std::max(1, std::min(batch, maxc - done));
         for (int c = 0; c < nb; ++c) {
-            const bool first = (done + c) == 0;
-            for (size_t gi = 0; gi < H->groups.size(); ++gi) {
-                Group& g = H->groups[gi];
-                fused[gi] = 0;
-                if (g.nact == 0) continue;
-                if (o.precision == 0) {
-                    CycleCtx<double> ctx{H, &g, conj, st, std::vector<int>(g.L, 0)};
-                    // level-0 buffer parity is a function of the cycles run so far
-                    ctx.cur[0] = (int)(((int64_t)(done + c) * level0_flips(H, g)) & 1);
-                    ctx.norm_partial = g.partial;
-                    enqueue_cycle<double>(ctx, 0, first);
-                    cur0[gi] = ctx.cur[0];
-                    fused[gi] = ctx.norm_fused;
-                } else {
-                    CycleCtx<float> ctx{H, &g, conj, st, std::vector<int>(g.L, 0)};
-                    for (int k = 0; k < o.ir_inner; ++k) enqueue_cycle<float>(ctx, 0, k == 0);
-                    Level& l0 = g.lv64[0];
-                    Level& e0 = g.lv32[0];
-                    Timer t(H, st, VMG_K_IR, (first ? 24.0 : 40.0) * nodes(l0.v) * g.nact);
-                    launch_ir_update(P<double>(l0.x[0]), P<float>(e0.x[ctx.cur[0]]), l0.v, e0.v,
-                                     H->active + g.sys0, g.S, first, st);
-                }
-            }
-            if (enqueue_norm_check(H, st, 1, tol, fixed != nullptr, conj, cur0, fused)) return VMG_HIP_ERROR;
+            const int rc = run_cycle(H, conj, st, done + c, tol, fixed != nullptr);
+            if (rc) return rc;
         }
         done += nb;
         if (read_state(H, st)) return VMG_HIP_ERROR;
@@ -649,7 +974,8 @@ int vanka_mg_default_opts(vmg_opts* o) {
     o->precision = 0;
     o->smoother = 0;
     o->ir_inner = 3;
-    o->check_every = 4;
+    o->check_every = 64;
+    o->graphs = 1;
     return VMG_OK;
 }
 
@@ -677,6 +1003,8 @@ int vanka_mg_destroy(vmg_handle* H) {
         (void)hipEventDestroy(t.b);
     }
     for (auto e : H->event_pool) (void)hipEventDestroy(e);
+    for (auto& gr : H->graphs) (void)hipGraphExecDestroy(gr.second);
+    if (H->cap_stream) (void)hipStreamDestroy(H->cap_stream);
     for (void* p : H->allocations) (void)hipFree(p);
     if (H->h_int) (void)hipHostFree(H->h_int);
     if (H->h_dbl) (void)hipHostFree(H->h_dbl);
@@ -695,7 +1023,7 @@ int vanka_mg_setup(const vmg_grid* grids, int32_t n_grids, const double* shifts,
     if (opts) o = *opts;
     if (!(o.omega > 0.0) || o.nu1 < 0 || o.nu2 < 0 || o.nu1 + o.nu2 < 1 || o.gamma < 1 || o.gamma > 2 ||
         o.max_iter < 1 || o.precision < 0 || o.precision > 1 || o.smoother < 0 || o.smoother > 1 ||
-        o.ir_inner < 1 || o.check_every < 1)
+        o.ir_inner < 1 || o.check_every < 1 || o.graphs < 0 || o.graphs > 1)
         return VMG_INVALID_ARG;
     (void)hip_stream;
     vmg_handle* H = new (std::nothrow) vmg_handle();
@@ -1177,7 +1505,9 @@ int apply_op_impl(vmg_handle* H, int op, int level, int conj, const double* x, c
             case VMG_OP_SWEEP: {
                 if (xf) launch_pack<T>(xf, P<T>(lv.x[0]), lv.v, g.S, st);
                 launch_pack<T>(reinterpret_cast<const double2*>(b) + off_f, P<T>(lv.b), lv.v, g.S, st);
-                launch_sweep<T>(P<T>(lv.x[0]), P<T>(lv.b), P<T>(lv.x[1]), lv.v, s, cf, act, g.S, xf == nullptr, st);
+                launch_sweep<T>(one_seg(make_seg<T>(H, g, conj, level, P<T>(lv.x[0]), P<T>(lv.b), P<T>(lv.x[1]), nullptr,
+                                                    xf == nullptr, nullptr)),
+                                &g.S, st);
                 launch_unpack<T>(P<T>(lv.x[1]), nullptr, reinterpret_cast<double2*>(out) + off_f, lv.v, g.S, nullptr, 0,
                                  st);
                 off_f += nf;
@@ -1197,8 +1527,9 @@ int apply_op_impl(vmg_handle* H, int op, int level, int conj, const double* x, c
                 Level& lc = L[level + 1];
                 if (xf) launch_pack<T>(xf, P<T>(lv.x[0]), lv.v, g.S, st);
                 launch_pack<T>(reinterpret_cast<const double2*>(b) + off_f, P<T>(lv.b), lv.v, g.S, st);
-                launch_restrict<T>(P<T>(lv.x[0]), P<T>(lv.b), P<T>(lc.b), lv.v, lc.v, s, cf, act, g.S, xf == nullptr,
-                                   st);
+                launch_restrict<T>(one_seg(make_seg<T>(H, g, conj, level, P<T>(lv.x[0]), P<T>(lv.b), nullptr,
+                                                       P<T>(lc.b), xf == nullptr, nullptr)),
+                                   &g.S, st);
                 launch_unpack<T>(P<T>(lc.b), nullptr, reinterpret_cast<double2*>(out) + off_c, lc.v, g.S, nullptr, 0,
                                  st);
                 off_f += nf;
@@ -1210,7 +1541,9 @@ int apply_op_impl(vmg_handle* H, int op, int level, int conj, const double* x, c
                 if (!xf) return VMG_INVALID_ARG;
                 launch_pack<T>(xf, P<T>(lv.x[0]), lv.v, g.S, st);
                 launch_pack<T>(reinterpret_cast<const double2*>(b) + off_c, P<T>(lc.x[0]), lc.v, g.S, st);
-                launch_prolong<T>(P<T>(lv.x[0]), P<T>(lc.x[0]), lv.v, lc.v, act, g.S, 0, st);
+                launch_prolong<T>(one_seg(make_seg<T>(H, g, conj, level, P<T>(lv.x[0]), nullptr, P<T>(lv.x[0]),
+                                                      P<T>(lc.x[0]), 0, nullptr)),
+                                  &g.S, st);
                 launch_unpack<T>(P<T>(lv.x[0]), nullptr, reinterpret_cast<double2*>(out) + off_f, lv.v, g.S, nullptr, 0,
                                  st);
                 off_f += nf;
@@ -1219,7 +1552,9 @@ int apply_op_impl(vmg_handle* H, int op, int level, int conj, const double* x, c
             }
             case VMG_OP_COARSE_SOLVE: {
                 launch_pack<T>(reinterpret_cast<const double2*>(b) + off_f, P<T>(lv.b), lv.v, g.S, st);
-                launch_coarse<T>(P<T>(lv.b), P<T>(lv.x[0]), lv.v, cinv_of<T>(g, conj), g.nc, act, g.S, st);
+                launch_coarse<T>(one_seg(make_seg<T>(H, g, conj, level, nullptr, P<T>(lv.b), P<T>(lv.x[0]), nullptr, 0,
+                                                     nullptr)),
+                                 &g.S, st);
                 launch_unpack<T>(P<T>(lv.x[0]), nullptr, reinterpret_cast<double2*>(out) + off_f, lv.v, g.S, nullptr, 0,
                                  st);
                 off_f += nf;

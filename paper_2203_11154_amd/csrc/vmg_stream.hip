@@ -116,17 +116,19 @@ __device__ __forceinline__ bool in_rows(int k, int ny) { return k >= 1 && k <= n
 
 // ---------------------------------------------------------------------------
 template <typename T, int NS>
-__global__ __launch_bounds__(NT) void k_down(const cplx<T>* __restrict__ x, const cplx<T>* __restrict__ b,
-                                             cplx<T>* __restrict__ xo, cplx<T>* __restrict__ bc, LevelView lf,
-                                             LevelView lc, T s, const Coef<T>* __restrict__ coef,
-                                             const int* __restrict__ active, int x_zero, int ty) {
+__global__ __launch_bounds__(NT) void k_down(SegTable<T> tab, int ty) {
     using C = cplx<T>;
     constexpr int HALO = 2 * NS + 2;
     constexpr int OWN = 64 - 2 * HALO;
     constexpr int NB = 2 * NS + 1;  // b rows in flight
     const int lane = threadIdx.x & 63;
-    const int sys = blockIdx.z;
-    if (!active[sys]) return;
+    const LevelSeg<T> S = seg_of(tab, blockIdx.z);
+    const int sys = blockIdx.z - S.z0;
+    if ((int)blockIdx.x >= S.gx || (int)blockIdx.y >= S.gy) return;
+    if (!S.active[sys]) return;
+    const LevelView lf = S.lf, lc = S.lc;
+    const int x_zero = S.x_zero;
+    const T s = S.s;
     const int c0 = 1 + (int)(blockIdx.x * (NT / 64) + (threadIdx.x >> 6)) * OWN;
     if (c0 > lf.nx) return;  // whole wave idle; no block barriers in this kernel
     const int i = c0 - HALO + lane;
@@ -136,11 +138,11 @@ __global__ __launch_bounds__(NT) void k_down(const cplx<T>* __restrict__ x, cons
     const int k0 = 1 + (int)blockIdx.y * ty;
     const int k1 = min(lf.ny, k0 + ty - 1);
     const int64_t base = (int64_t)sys * lf.plane;
-    const C* xs = x + base;
-    const C* bs = b + base;
-    C* xos = xo + base;
-    C* bcs = bc + (int64_t)sys * lc.plane;
-    const Coef<T> cf = coef[sys];
+    const C* xs = S.x + base;
+    const C* bs = S.b + base;
+    C* xos = S.xo + base;
+    C* bcs = S.c + (int64_t)sys * lc.plane;
+    const Coef<T> cf = S.coef[sys];
 
     Win<C> X[NS + 1], R[NS + 1], N[NS + 1];
 #pragma unroll
@@ -212,18 +214,21 @@ __global__ __launch_bounds__(NT) void k_down(const cplx<T>* __restrict__ x, cons
 
 // ---------------------------------------------------------------------------
 template <typename T, int NS, bool NORM>
-__global__ __launch_bounds__(NT) void k_up(const cplx<T>* __restrict__ x, const cplx<T>* __restrict__ e,
-                                           const cplx<T>* __restrict__ b, cplx<T>* __restrict__ xo, LevelView lf,
-                                           LevelView lc, T s, const Coef<T>* __restrict__ coef,
-                                           const int* __restrict__ active, int ty, double* __restrict__ partial) {
+__global__ __launch_bounds__(NT) void k_up(SegTable<T> tab, int ty) {
     using C = cplx<T>;
     constexpr int HALO = NORM ? 2 * NS + 1 : (NS > 0 ? 2 * NS : 1);
     constexpr int OWN = 64 - 2 * HALO;
     constexpr int NB = 2 * NS + 1;
     __shared__ double red[NT / 64];
     const int lane = threadIdx.x & 63;
-    const int sys = blockIdx.z;
-    if (!active[sys]) return;  // uniform over the block
+    const LevelSeg<T> S = seg_of(tab, blockIdx.z);
+    const int sys = blockIdx.z - S.z0;
+    // both exits are uniform over the block (before its only barrier)
+    if ((int)blockIdx.x >= S.gx || (int)blockIdx.y >= S.gy) return;
+    if (!S.active[sys]) return;
+    const LevelView lf = S.lf, lc = S.lc;
+    const T s = S.s;
+    double* partial = S.partial;
     const int c0 = 1 + (int)(blockIdx.x * (NT / 64) + (threadIdx.x >> 6)) * OWN;
     const bool wave_on = c0 <= lf.nx;
     const int i = c0 - HALO + lane;
@@ -232,11 +237,11 @@ __global__ __launch_bounds__(NT) void k_up(const cplx<T>* __restrict__ x, const 
     const int k0 = 1 + (int)blockIdx.y * ty;
     const int k1 = min(lf.ny, k0 + ty - 1);
     const int64_t base = (int64_t)sys * lf.plane;
-    const C* xs = x + base;
-    const C* bs = b + base;
-    const C* es = e + (int64_t)sys * lc.plane;
-    C* xos = xo + base;
-    const Coef<T> cf = coef[sys];
+    const C* xs = S.x + base;
+    const C* bs = S.b + base;
+    const C* es = S.c + (int64_t)sys * lc.plane;
+    C* xos = S.xo + base;
+    const Coef<T> cf = S.coef[sys];
 
     Win<C> X[NS + 1], R[NS + 1], N[NS + 1];
 #pragma unroll
@@ -311,7 +316,7 @@ __global__ __launch_bounds__(NT) void k_up(const cplx<T>* __restrict__ x, const 
                 if (q == NS) {
                     if (own && rrow >= k0 && rrow <= k1) acc += (double)r.x * (double)r.x + (double)r.y * (double)r.y;
                     break;
-                }
+                }  // (the sum is written only for segments with a partial buffer)
                 R[q].push(r);
                 N[q].push(add(from_left(r), from_right(r)));
                 const int xrow = j - 2 * q - 2;
@@ -323,14 +328,14 @@ __global__ __launch_bounds__(NT) void k_up(const cplx<T>* __restrict__ x, const 
             if (own && orow >= k0 && orow <= k1) xos[(int64_t)orow * lf.pitch + i] = X[NS].r[2];
         }
     }
-    if (NORM) {
+    if (NORM && partial) {
         for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
         if (lane == 0) red[threadIdx.x >> 6] = acc;
         __syncthreads();
         if (threadIdx.x == 0) {
             double t = 0.0;
             for (int w = 0; w < NT / 64; ++w) t += red[w];
-            partial[(int64_t)sys * (gridDim.x * gridDim.y) + blockIdx.y * gridDim.x + blockIdx.x] = t;
+            partial[(int64_t)sys * (S.gx * S.gy) + blockIdx.y * S.gx + blockIdx.x] = t;
         }
     }
 }
@@ -351,6 +356,21 @@ inline dim3 stream_grid(int nx, int ny, int own, int ty, int nsys) {
     return dim3((tiles + NT / 64 - 1) / (NT / 64), (ny + ty - 1) / ty, nsys);
 }
 
+template <typename T> dim3 stream_seg_grid(SegTable<T>& tab, const int* nsys, int own, int ty) {
+    int z = 0, gx = 1, gy = 1;
+    for (int q = 0; q < tab.n; ++q) {
+        LevelSeg<T>& S = tab.s[q];
+        const dim3 g = stream_grid(S.lf.nx, S.lf.ny, own, ty, 1);
+        S.z0 = z;
+        S.gx = (int)g.x;
+        S.gy = (int)g.y;
+        gx = max(gx, S.gx);
+        gy = max(gy, S.gy);
+        z += nsys[q];
+    }
+    return dim3(gx, gy, z);
+}
+
 }  // namespace
 
 int stream_tiles(int nx, int ny, int nu, bool norm, int ty) {
@@ -364,32 +384,32 @@ int stream_tiles(int nx, int ny, int nu, bool norm, int ty) {
     return (int)(g.x * g.y);
 }
 
-template <typename T>
-void launch_down(const cplx<T>* x, const cplx<T>* b, cplx<T>* xo, cplx<T>* bc, LevelView lf, LevelView lc, T s,
-                 const Coef<T>* coef, const int* active, int nsys, int nu, int x_zero, int ty, hipStream_t st) {
+template <typename T> void launch_down(SegTable<T> tab, const int* nsys, int nu, int ty, hipStream_t st) {
     switch (nu) {
-        case 0:
-            hipLaunchKernelGGL((k_down<T, 0>), stream_grid(lf.nx, lf.ny, down_own<0>(), ty, nsys), dim3(NT), 0, st, x,
-                               b, xo, bc, lf, lc, s, coef, active, x_zero, ty);
+        case 0: {
+            const dim3 g = stream_seg_grid(tab, nsys, down_own<0>(), ty);
+            hipLaunchKernelGGL((k_down<T, 0>), g, dim3(NT), 0, st, tab, ty);
             break;
-        case 1:
-            hipLaunchKernelGGL((k_down<T, 1>), stream_grid(lf.nx, lf.ny, down_own<1>(), ty, nsys), dim3(NT), 0, st, x,
-                               b, xo, bc, lf, lc, s, coef, active, x_zero, ty);
+        }
+        case 1: {
+            const dim3 g = stream_seg_grid(tab, nsys, down_own<1>(), ty);
+            hipLaunchKernelGGL((k_down<T, 1>), g, dim3(NT), 0, st, tab, ty);
             break;
-        default:
-            hipLaunchKernelGGL((k_down<T, 2>), stream_grid(lf.nx, lf.ny, down_own<2>(), ty, nsys), dim3(NT), 0, st, x,
-                               b, xo, bc, lf, lc, s, coef, active, x_zero, ty);
+        }
+        default: {
+            const dim3 g = stream_seg_grid(tab, nsys, down_own<2>(), ty);
+            hipLaunchKernelGGL((k_down<T, 2>), g, dim3(NT), 0, st, tab, ty);
             break;
+        }
     }
 }
 
-template <typename T>
-void launch_up(const cplx<T>* x, const cplx<T>* e, const cplx<T>* b, cplx<T>* xo, LevelView lf, LevelView lc, T s,
-               const Coef<T>* coef, const int* active, int nsys, int nu, int ty, double* partial, hipStream_t st) {
-    const bool norm = partial != nullptr;
-#define VMG_UP(NSV, NORMV)                                                                                        \
-    hipLaunchKernelGGL((k_up<T, NSV, NORMV>), stream_grid(lf.nx, lf.ny, up_own<NSV, NORMV>(), ty, nsys), dim3(NT), \
-                       0, st, x, e, b, xo, lf, lc, s, coef, active, ty, partial)
+template <typename T> void launch_up(SegTable<T> tab, const int* nsys, int nu, bool norm, int ty, hipStream_t st) {
+#define VMG_UP(NSV, NORMV)                                                          \
+    do {                                                                            \
+        const dim3 g = stream_seg_grid(tab, nsys, up_own<NSV, NORMV>(), ty);        \
+        hipLaunchKernelGGL((k_up<T, NSV, NORMV>), g, dim3(NT), 0, st, tab, ty);     \
+    } while (0)
     switch (nu) {
         case 0: if (norm) VMG_UP(0, true); else VMG_UP(0, false); break;
         case 1: if (norm) VMG_UP(1, true); else VMG_UP(1, false); break;
@@ -404,13 +424,9 @@ template <typename T> void launch_fill_zero(cplx<T>* x, LevelView lv, int nsys, 
 template void launch_fill_zero<double>(double2*, LevelView, int, hipStream_t);
 template void launch_fill_zero<float>(float2*, LevelView, int, hipStream_t);
 
-template void launch_down<double>(const double2*, const double2*, double2*, double2*, LevelView, LevelView, double,
-                                  const Coef<double>*, const int*, int, int, int, int, hipStream_t);
-template void launch_down<float>(const float2*, const float2*, float2*, float2*, LevelView, LevelView, float,
-                                 const Coef<float>*, const int*, int, int, int, int, hipStream_t);
-template void launch_up<double>(const double2*, const double2*, const double2*, double2*, LevelView, LevelView,
-                                double, const Coef<double>*, const int*, int, int, int, double*, hipStream_t);
-template void launch_up<float>(const float2*, const float2*, const float2*, float2*, LevelView, LevelView, float,
-                               const Coef<float>*, const int*, int, int, int, double*, hipStream_t);
+template void launch_down<double>(SegTable<double>, const int*, int, int, hipStream_t);
+template void launch_down<float>(SegTable<float>, const int*, int, int, hipStream_t);
+template void launch_up<double>(SegTable<double>, const int*, int, bool, int, hipStream_t);
+template void launch_up<float>(SegTable<float>, const int*, int, bool, int, hipStream_t);
 
 }  // namespace vmg

@@ -47,7 +47,7 @@ class VankaMG:
     """
 
     def __init__(self, grids, shifts, omega=24.0 / 25.0, nu1=2, nu2=2, gamma=1, max_iter=100,
-                 precision="c128", smoother="vanka", ir_inner=3, check_every=4):
+                 precision="c128", smoother="vanka", ir_inner=3, check_every=64, graphs=True):
         _require_gpu()
         self.lib = _lib.load()
         if isinstance(grids, Grid):
@@ -66,6 +66,7 @@ class VankaMG:
         opts.precision = {"c128": 0, "c64_ir": 1}[precision]
         opts.smoother = {"vanka": 0, "jacobi": 1}[smoother]
         opts.ir_inner, opts.check_every = ir_inner, check_every
+        opts.graphs = int(bool(graphs))
         self.opts = opts
         self.precision = precision
         arr = (_lib.VmgGrid * len(self.grids))(*[g.to_c() for g in self.grids])

@@ -53,4 +53,4 @@ def test_error_strings_and_defaults_without_gpu():
 def test_struct_layouts_match_header():
     from paper_2203_11154_amd import _lib
     assert ctypes.sizeof(_lib.VmgGrid) == 24
-    assert ctypes.sizeof(_lib.VmgOpts) == 40
+    assert ctypes.sizeof(_lib.VmgOpts) == 48
