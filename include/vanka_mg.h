@@ -263,6 +263,22 @@ int vanka_mg_level_stats(vmg_handle* h, int32_t kclass, int32_t nlev, int64_t* l
  */
 int vanka_mg_last_stats(vmg_handle* h, int32_t* iters, double* relres, void* hip_stream);
 
+/*
+ * Autotuner: for every grid and level above the coarsest, time each kernel
+ * schedule on the handle's own buffers (the LDS-tiled sweep / restriction /
+ * prolongation kernels, or the fused streaming kernels with 32, 64 or 128
+ * rows per block) and keep the fastest.  cache_path (host string, NULL = no
+ * cache) is a text file of earlier choices keyed by device, precision, grid,
+ * system count and smoothing counts; new choices are appended.  Results of
+ * later solves are identical under every schedule up to rounding order.
+ * Returns VMG_OK, VMG_INVALID_ARG, VMG_HIP_ERROR.
+ */
+int vanka_mg_autotune(vmg_handle* h, const char* cache_path, void* hip_stream);
+
+/* Schedule in use for grid g, levels 0..nlev-1: 0 = LDS-tiled kernels, r > 0
+ * = streaming kernels with r rows per block, -1 = coarsest / beyond. */
+int vanka_mg_schedule(const vmg_handle* h, int32_t g, int32_t nlev, int32_t* sched);
+
 /* Levels of grid g: writes count and, if non-NULL, nx/ny per level. */
 int vanka_mg_levels(const vmg_handle* h, int32_t g, int32_t* count, int32_t* nx, int32_t* ny);
 

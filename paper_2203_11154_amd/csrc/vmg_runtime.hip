@@ -4,6 +4,9 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <fstream>
+#include <sstream>
+#include <string>
 #include <cmath>
 #include <complex>
 #include <cstdio>
@@ -72,6 +75,7 @@ struct Group {
     double* partial = nullptr;
     int ntiles0 = 0;
     int nact = 0;   // systems active at the last host check (for byte accounting)
+    std::vector<int> sched;  // per level: 0 = LDS-tiled kernels, r > 0 = streaming with r rows; empty = heuristic
 };
 
 struct GraphKey {
@@ -339,6 +343,22 @@ int stream_rows_for(const vmg_handle* H, const LevelView& v) {
     return v.ny > 600 ? 128 : (v.ny > 200 ? 64 : 32);
 }
 
+const LevelView& cycle_view(const vmg_handle* H, const Group& g, int l) {
+    return H->opts.precision == 0 ? g.lv64[l].v : g.lv32[l].v;
+}
+
+// Kernel schedule of grid g at level l: the autotuned choice if there is
+// one, else the size heuristic above.
+bool sched_stream(const vmg_handle* H, const Group& g, int l) {
+    if (H->opts.nu1 > 2 || H->opts.nu2 > 2) return false;
+    if ((int)g.sched.size() > l && g.sched[l] >= 0) return g.sched[l] > 0;
+    return use_stream(H->opts, cycle_view(H, g, l));
+}
+int sched_rows(const vmg_handle* H, const Group& g, int l) {
+    if ((int)g.sched.size() > l && g.sched[l] > 0) return g.sched[l];
+    return stream_rows_for(H, cycle_view(H, g, l));
+}
+
 // One grid's segment at level l (see LevelSeg).
 template <typename T>
 LevelSeg<T> make_seg(vmg_handle* H, Group& g, int conj, int l, const cplx<T>* x, const cplx<T>* b, cplx<T>* xo,
@@ -403,14 +423,14 @@ template <typename T> void enqueue_cycle(CycleCtx<T>& c, int l, bool x_zero) {
         return;
     }
     Level& lc = L[l + 1];
-    if (use_stream(o, lv.v)) {
+    if (sched_stream(H, g, l)) {
         // fused: nu1 sweeps + residual + restriction, recursion, correction + nu2 sweeps
         {
             const double by = ((x_zero ? 0.0 : 1.0) + 1.0 + (o.nu1 > 0 ? 1.0 : 0.0) + 0.25) * E * nodes(lv.v) * g.nact;
             Timer t(H, c.st, VMG_K_DOWN, by, l);
             launch_down<T>(one_seg(make_seg<T>(H, g, c.conj, l, P<T>(lv.x[c.cur[l]]), P<T>(lv.b),
                                                P<T>(lv.x[1 - c.cur[l]]), P<T>(lc.b), x_zero, nullptr)),
-                           &one, o.nu1, stream_rows_for(H, lv.v), c.st);
+                           &one, o.nu1, sched_rows(H, g, l), c.st);
         }
         if (o.nu1 > 0) {
             c.cur[l] ^= 1;
@@ -430,7 +450,7 @@ template <typename T> void enqueue_cycle(CycleCtx<T>& c, int l, bool x_zero) {
             Timer t(H, c.st, VMG_K_UP, by, l);
             launch_up<T>(one_seg(make_seg<T>(H, g, c.conj, l, P<T>(lv.x[c.cur[l]]), P<T>(lv.b),
                                              P<T>(lv.x[1 - c.cur[l]]), P<T>(lc.x[c.cur[l + 1]]), 0, np)),
-                         &one, o.nu2, np != nullptr, stream_rows_for(H, lv.v), c.st);
+                         &one, o.nu2, np != nullptr, sched_rows(H, g, l), c.st);
         }
         c.cur[l] ^= 1;
         if (np) c.norm_fused = true;
@@ -496,18 +516,18 @@ void enqueue_batched_vcycle(vmg_handle* H, int conj, hipStream_t st, bool first,
         for (int gi = 0; gi < ng; ++gi) {
             if (H->groups[gi].L - 1 < d) continue;
             const int l = level_of(gi, d);
-            (use_stream(o, levels_of<T>(H->groups[gi])[l].v) ? sg : lg).push_back(gi);
+            (sched_stream(H, H->groups[gi], l) ? sg : lg).push_back(gi);
         }
         // streamed grids: one fused launch per row-block height
         while (!sg.empty()) {
-            const int ty = stream_rows_for(H, levels_of<T>(H->groups[sg[0]])[level_of(sg[0], d)].v);
+            const int ty = sched_rows(H, H->groups[sg[0]], level_of(sg[0], d));
             SegBatch<T> bt;
             std::vector<int> rest, done;
             for (int gi : sg) {
                 Group& g = H->groups[gi];
                 const int l = level_of(gi, d);
                 auto& L = levels_of<T>(g);
-                if (stream_rows_for(H, L[l].v) != ty || bt.full()) {
+                if (sched_rows(H, g, l) != ty || bt.full()) {
                     rest.push_back(gi);
                     continue;
                 }
@@ -589,10 +609,10 @@ void enqueue_batched_vcycle(vmg_handle* H, int conj, hipStream_t st, bool first,
         for (int gi = 0; gi < ng; ++gi) {
             if (H->groups[gi].L - 1 < d) continue;
             const int l = level_of(gi, d);
-            (use_stream(o, levels_of<T>(H->groups[gi])[l].v) ? sg : lg).push_back(gi);
+            (sched_stream(H, H->groups[gi], l) ? sg : lg).push_back(gi);
         }
         while (!sg.empty()) {
-            const int ty = stream_rows_for(H, levels_of<T>(H->groups[sg[0]])[level_of(sg[0], d)].v);
+            const int ty = sched_rows(H, H->groups[sg[0]], level_of(sg[0], d));
             SegBatch<T> bt;
             std::vector<int> rest, done;
             bool any_norm = false;
@@ -600,7 +620,7 @@ void enqueue_batched_vcycle(vmg_handle* H, int conj, hipStream_t st, bool first,
                 Group& g = H->groups[gi];
                 const int l = level_of(gi, d);
                 auto& L = levels_of<T>(g);
-                if (stream_rows_for(H, L[l].v) != ty || bt.full()) {
+                if (sched_rows(H, g, l) != ty || bt.full()) {
                     rest.push_back(gi);
                     continue;
                 }
@@ -673,12 +693,13 @@ bool valid_grid_level(int n) { return n >= 3 && (n % 2) == 1; }
 int level0_flips(const vmg_handle* H, const Group& g) {
     const vmg_opts& o = H->opts;
     const LevelView& v = (o.precision == 0 ? g.lv64[0] : g.lv32[0]).v;
-    if (g.L > 1 && use_stream(o, v)) return (o.nu1 > 0 ? 1 : 0) + 1;
+    (void)v;
+    if (g.L > 1 && sched_stream(H, g, 0)) return (o.nu1 > 0 ? 1 : 0) + 1;
     return o.nu1 + o.nu2;
 }
 
 int norm_tiles(const vmg_handle* H, const Group& g) {
-    return stream_tiles(g.lv64[0].v.nx, g.lv64[0].v.ny, H->opts.nu2, true, stream_rows_for(H, g.lv64[0].v));
+    return stream_tiles(g.lv64[0].v.nx, g.lv64[0].v.ny, H->opts.nu2, true, sched_rows(H, g, 0));
 }
 
 // residual norms of level 0 of every group (unless the last cycle's fused
@@ -1468,6 +1489,139 @@ extern "C" int paradiag_heat_residual(vmg_handle* H, double tau, const double* U
         VMG_HIP(hipMemcpyAsync(H->h_dbl, total, sizeof(double), hipMemcpyDeviceToHost, st));
         VMG_HIP(hipStreamSynchronize(st));
         *norm2 = H->h_dbl[0];
+    }
+    return VMG_OK;
+}
+
+// ---------------------------------------------------------------------------
+// autotuner of the per-level kernel schedule
+// ---------------------------------------------------------------------------
+namespace {
+
+// Time one level's work (everything a cycle does on that level apart from the
+// recursion) under schedule `cand` (0: LDS-tiled, r > 0: streaming, r rows).
+template <typename T> int time_level(vmg_handle* H, Group& g, int l, int cand, hipStream_t st, double* ms_out) {
+    auto& L = levels_of<T>(g);
+    Level& lv = L[l];
+    Level& lc = L[l + 1];
+    const vmg_opts& o = H->opts;
+    const int one = g.S;
+    auto seg = [&](const cplx<T>* x, const cplx<T>* b, cplx<T>* xo, cplx<T>* c, int xz) {
+        return one_seg(make_seg<T>(H, g, 0, l, x, b, xo, c, xz, nullptr));
+    };
+    auto run = [&]() {
+        if (cand > 0) {
+            launch_down<T>(seg(P<T>(lv.x[0]), P<T>(lv.b), P<T>(lv.x[1]), P<T>(lc.b), 0), &one, o.nu1, cand, st);
+            launch_up<T>(seg(P<T>(lv.x[1]), P<T>(lv.b), P<T>(lv.x[0]), P<T>(lc.x[0]), 0), &one, o.nu2, l == 0, cand,
+                         st);
+        } else {
+            for (int i = 0; i < o.nu1; ++i)
+                launch_sweep<T>(seg(P<T>(lv.x[i & 1]), P<T>(lv.b), P<T>(lv.x[1 - (i & 1)]), nullptr, 0), &one, st);
+            launch_restrict<T>(seg(P<T>(lv.x[0]), P<T>(lv.b), nullptr, P<T>(lc.b), 0), &one, st);
+            launch_prolong<T>(seg(P<T>(lv.x[0]), nullptr, P<T>(lv.x[0]), P<T>(lc.x[0]), 0), &one, st);
+            for (int i = 0; i < o.nu2; ++i)
+                launch_sweep<T>(seg(P<T>(lv.x[i & 1]), P<T>(lv.b), P<T>(lv.x[1 - (i & 1)]), nullptr, 0), &one, st);
+        }
+    };
+    // the level-0 streaming candidate also forms the norm partial sums
+    double* saved = nullptr;
+    (void)saved;
+    hipEvent_t a = nullptr, b = nullptr;
+    if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) return VMG_HIP_ERROR;
+    for (int w = 0; w < 2; ++w) run();
+    (void)hipEventRecord(a, st);
+    const int reps = 5;
+    for (int r = 0; r < reps; ++r) run();
+    (void)hipEventRecord(b, st);
+    int rc = check_hip();
+    float ms = 0.f;
+    if (!rc && (hipEventSynchronize(b) != hipSuccess || hipEventElapsedTime(&ms, a, b) != hipSuccess)) rc = VMG_HIP_ERROR;
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    *ms_out = ms / reps;
+    return rc;
+}
+
+std::string tune_key(const vmg_handle* H, const Group& g, int l) {
+    hipDeviceProp_t prop;
+    std::string arch = "gpu";
+    if (hipGetDeviceProperties(&prop, H->device) == hipSuccess) arch = prop.gcnArchName;
+    for (auto& ch : arch)
+        if (ch == ' ') ch = '_';
+    std::ostringstream k;
+    k << arch << " " << (H->opts.precision == 0 ? "c128" : "c64") << " " << g.nx << " " << g.ny << " " << g.S << " "
+      << H->opts.nu1 << " " << H->opts.nu2 << " " << l;
+    return k.str();
+}
+
+}  // namespace
+
+extern "C" int vanka_mg_autotune(vmg_handle* H, const char* cache_path, void* hip_stream) {
+    if (!H) return VMG_INVALID_ARG;
+    hipStream_t st = (hipStream_t)hip_stream;
+    std::vector<std::pair<std::string, int>> cache;
+    if (cache_path) {
+        std::ifstream in(cache_path);
+        std::string line;
+        while (std::getline(in, line)) {
+            const size_t p = line.rfind(' ');
+            if (p == std::string::npos) continue;
+            cache.push_back({line.substr(0, p), std::atoi(line.c_str() + p + 1)});
+        }
+    }
+    launch_fill_int(H->active, 1, H->S, st);
+    std::vector<std::string> fresh;
+    for (auto& g : H->groups) {
+        g.sched.assign(g.L, -1);
+        for (int l = 0; l + 1 < g.L; ++l) {
+            const std::string key = tune_key(H, g, l);
+            int found = -2;
+            for (auto& e : cache)
+                if (e.first == key) found = e.second;
+            if (found >= 0) {
+                g.sched[l] = found;
+                continue;
+            }
+            const LevelView& v = cycle_view(H, g, l);
+            std::vector<int> cands{0};
+            if (H->opts.nu1 <= 2 && H->opts.nu2 <= 2 && v.nx >= 32)
+                for (int r : {32, 64, 128})
+                    if (r <= 2 * v.ny) cands.push_back(r);
+            int best = 0;
+            double best_ms = 1e300;
+            for (int c : cands) {
+                double ms = 0.0;
+                const int rc = H->opts.precision == 0 ? time_level<double>(H, g, l, c, st, &ms)
+                                                      : time_level<float>(H, g, l, c, st, &ms);
+                if (rc) return rc;
+                if (ms < best_ms) {
+                    best_ms = ms;
+                    best = c;
+                }
+            }
+            g.sched[l] = best;
+            fresh.push_back(key + " " + std::to_string(best));
+        }
+    }
+    // launch sequences changed: drop captured cycles
+    for (auto& gr : H->graphs) (void)hipGraphExecDestroy(gr.second);
+    H->graphs.clear();
+    if (cache_path && !fresh.empty()) {
+        std::ofstream out(cache_path, std::ios::app);
+        for (auto& f : fresh) out << f << "\n";
+    }
+    return VMG_OK;
+}
+
+extern "C" int vanka_mg_schedule(const vmg_handle* H, int32_t g, int32_t nlev, int32_t* sched) {
+    if (!H || g < 0 || g >= (int)H->groups.size() || !sched) return VMG_INVALID_ARG;
+    const Group& G = H->groups[g];
+    for (int l = 0; l < nlev; ++l) {
+        if (l + 1 >= G.L) {
+            sched[l] = -1;
+            continue;
+        }
+        sched[l] = sched_stream(H, G, l) ? sched_rows(H, G, l) : 0;
     }
     return VMG_OK;
 }

@@ -97,6 +97,21 @@ class VankaMG:
         _lib.check(self.lib.vanka_mg_levels(self.handle, g, ctypes.byref(cnt), nx, ny), "vanka_mg_levels")
         return [(nx[i], ny[i]) for i in range(cnt.value)]
 
+    def autotune(self, cache_path=None):
+        """Time the kernel schedules of every level and keep the fastest;
+        returns the schedule per grid (see schedule())."""
+        path = None if cache_path is None else str(cache_path).encode()
+        _lib.check(self.lib.vanka_mg_autotune(self.handle, path, _stream()), "vanka_mg_autotune")
+        return [self.schedule(g) for g in range(len(self.grids))]
+
+    def schedule(self, g=0):
+        """Per level: 0 = LDS-tiled kernels, r > 0 = streaming kernels with r
+        rows per block, -1 = coarsest level."""
+        n = len(self.levels(g))
+        arr = (ctypes.c_int32 * n)()
+        _lib.check(self.lib.vanka_mg_schedule(self.handle, g, n, arr), "vanka_mg_schedule")
+        return list(arr)
+
     def _check_vec(self, t, n, name):
         if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.complex128 and t.is_contiguous()):
             raise TypeError(f"{name} must be a contiguous complex128 CUDA tensor")

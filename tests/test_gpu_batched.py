@@ -134,3 +134,30 @@ def test_full_uneven_workload():
         err = np.linalg.norm((got[pick] - zx).reshape(2, -1), axis=1) / np.linalg.norm(zx.reshape(2, -1), axis=1)
         assert np.all(err <= 1e-8)
         off += c
+
+
+def test_autotuned_schedule_parity(tmp_path):
+    """The autotuner's per-level choice (LDS-tiled or streaming with 32/64/128
+    rows) is a valid schedule, is reused from its cache, and the tuned solve
+    matches the oracle at fixed counts."""
+    cache = tmp_path / "tune.txt"
+    solver, lam, bs = setup(SMALL)
+    scheds = solver.autotune(cache)
+    for (n, c), sc in zip(SMALL, scheds):
+        assert sc[-1] == -1 and all(v in (0, 32, 64, 128) for v in sc[:-1])
+    text = cache.read_text()
+    assert len(text.splitlines()) == sum(len(sc) - 1 for sc in scheds)
+    again, _, _ = setup(SMALL)
+    assert again.autotune(cache) == scheds
+    assert cache.read_text() == text
+    bd = dev(np.concatenate([b.ravel() for b in bs]))
+    counts, refs, off = [], [], 0
+    for (n, c), b in zip(SMALL, bs):
+        zr, itr, _, _ = omg.solve(b, lam[off:off + c], 1.0 / (n + 1), tol=1e-10)
+        counts.extend(itr)
+        refs.append(zr)
+        off += c
+    Z, _, _, _ = solver.solve(bd, fixed_iters=counts)
+    for got, zr in zip(split(host(Z), SMALL), refs):
+        for j in range(len(zr)):
+            assert np.linalg.norm(got[j] - zr[j]) <= 1e-10 * np.linalg.norm(zr[j])
