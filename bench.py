@@ -53,6 +53,7 @@ def parse():
     p.add_argument("--cpu-sample", type=int, default=2, help="systems the oracle solves for the CPU baseline")
     p.add_argument("--no-autotune", action="store_true", help="keep the size heuristic kernel schedule")
     p.add_argument("--no-batched", action="store_true", help="skip the uneven-grid batched leg")
+    p.add_argument("--no-paper", action="store_true", help="skip the paper-protocol leg")
     p.add_argument("--copy-calibration", action="store_true",
                    help="run one plain 1 GiB device copy first (reference for hardware byte counters)")
     return p.parse_args()
@@ -99,6 +100,31 @@ def batched_leg(args, torch):
             "workload": "256x127^2 + 96x255^2 + 32x511^2, uniform shifts, V(2,2) to 1e-10, one batched solve",
             "iterations": {"min": int(iters.min()), "max": int(iters.max())}, "max_relres": float(relres.max()),
             "converged": bool(status == 0 and np.all(relres <= args.tol))}
+
+
+def paper_protocol_leg(args, torch):
+    """The paper's Sec. 3 protocol on Example 1 (eq. (9) shifts, n = 256,
+    h = tau = 1/256): W(1,0) cycles from h0 = 1/8 to a 1e-8 reduction, the
+    additive Vanka smoother (omega = 24/25) against damped Jacobi (4/5)."""
+    from paper_2203_11154_amd import Grid, VankaMG, inputs
+    n, nt = 255, 256
+    lam = inputs.example1_shifts(nt)
+    bd = torch.from_numpy(inputs.rhs(nt, n, n).ravel()).cuda()
+    out = {"workload": "Example 1: 256 BVM shifts on 255^2, W(1,0), tol 1e-8"}
+    for name, kw in (("vanka", dict(omega=0.96)), ("jacobi", dict(omega=0.8, smoother="jacobi", max_iter=200))):
+        s = VankaMG([Grid(n, num_systems=nt)], lam, nu1=1, nu2=0, gamma=2, **kw)
+        s.solve(bd, tol=1e-8)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            _, it, rr, st = s.solve(bd, tol=1e-8)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / args.steps
+        out[name] = {"cycles": int(np.max(it)), "rate": round(float(np.median(rr ** (1.0 / it))), 4),
+                     "ms_per_solve": round(1e3 * dt, 3), "systems_per_s": round(nt / dt, 1)}
+        del s
+    out["vanka_speedup_over_jacobi"] = round(out["jacobi"]["ms_per_solve"] / out["vanka"]["ms_per_solve"], 3)
+    return out
 
 
 def run_steps(solver, V, Vinv, F, U, steps, tol, torch):
@@ -214,6 +240,8 @@ def main():
 
     if not args.no_batched:
         out["batched_uneven"] = batched_leg(args, torch)
+    if not args.no_paper:
+        out["paper_protocol"] = paper_protocol_leg(args, torch)
 
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(b, lam, h, tol, args.cpu_sample)

@@ -121,6 +121,16 @@ int vanka_mg_setup(const vmg_grid* grids, int32_t n_grids, const double* shifts,
                    const vmg_opts* opts, void* hip_stream, vmg_handle** out);
 
 /*
+ * Per-system complex relaxation weights omega_j for the smoother (the
+ * complex relaxation parameter the paper leaves as future work after
+ * Example 3; S_j = I - omega_j M_{e,j} L_j).  omega: host, one complex value
+ * per system (interleaved doubles), or NULL to return to opts->omega.  The
+ * adjoint systems use conj(omega_j).  Synchronises the device.
+ * Returns VMG_OK, VMG_INVALID_ARG, VMG_HIP_ERROR.
+ */
+int vanka_mg_set_omega(vmg_handle* h, const double* omega);
+
+/*
  * Solve (A + lambda_j I) z_j = b_j for every system (eq. (2)), or with
  * conj != 0 the adjoint systems (A + conj(lambda_j) I) z_j = b_j.
  *   B, Z        device, complex128, all systems concatenated (see above).

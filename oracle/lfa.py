@@ -36,11 +36,13 @@ def symbol_S(t1, t2, eta, omega, smoother="vanka"):
 
 
 def high_frequency_grid(n=128):
-    """Uniform samples of T^H: a cell-centred n x n grid on [-pi/2, 3pi/2)^2
-    with the points of T^L removed."""
-    t = -np.pi / 2 + 2 * np.pi * (np.arange(n) + 0.5) / n
+    """Uniform samples of T^H: the node-centred n x n grid on [-pi/2, 3pi/2)^2
+    (n a multiple of 4, so theta = 0, pi/2 and pi are nodes) with the points of
+    T^L = [-pi/2, pi/2)^2 removed."""
+    n = 4 * ((n + 3) // 4)
+    t = -np.pi / 2 + 2 * np.pi * np.arange(n) / n
     t1, t2 = np.meshgrid(t, t, indexing="ij")
-    low = (np.abs(t1) < np.pi / 2) & (np.abs(t2) < np.pi / 2)
+    low = (t1 >= -np.pi / 2 - 1e-12) & (t1 < np.pi / 2 - 1e-12) & (t2 >= -np.pi / 2 - 1e-12) & (t2 < np.pi / 2 - 1e-12)
     return t1[~low], t2[~low]
 
 
@@ -105,6 +107,27 @@ def optimal_omega(eta, smoother="vanka", objective="two_grid", omegas=None):
         if best is None or f < best[1] - 1e-12:
             best = (float(w), f)
     return best
+
+
+def optimal_complex_omega(eta, smoother="vanka", n=64):
+    """Complex omega minimising the smoothing factor mu_loc of eq. (4) (the
+    complex relaxation parameter of the future work after Example 3): a scan
+    of the complex plane refined by Nelder-Mead.  Returns (omega, mu)."""
+    import scipy.optimize
+    t1, t2 = high_frequency_grid(n)
+
+    def mu(p):
+        return float(np.max(np.abs(symbol_S(t1, t2, eta, p[0] + 1j * p[1], smoother))))
+
+    best = None
+    for wr in np.linspace(0.3, 1.5, 25):
+        for wi in np.linspace(-0.8, 0.8, 33):
+            v = mu((wr, wi))
+            if best is None or v < best[1]:
+                best = ((wr, wi), v)
+    res = scipy.optimize.minimize(mu, best[0], method="Nelder-Mead", options={"xatol": 1e-6, "fatol": 1e-9})
+    w = res.x[0] + 1j * res.x[1]
+    return w, mu(res.x)
 
 
 def rfa_two_grid_spectrum(n, eta, omega, nu1, nu2, smoother="vanka"):

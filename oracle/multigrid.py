@@ -86,9 +86,11 @@ def solve(b, lam, h, tol=1e-10, max_iter=100, levels=0, omega=OMEGA_VANKA, nu1=2
     else:
         target = np.full(S, max_iter, dtype=np.int64)
         active = (bnorm > 0) & (relres > tol)
+    om = np.asarray(omega)
     while np.any(active):
         idx = np.nonzero(active)[0]
-        x[idx] = mg_cycle(0, x[idx], b[idx], lam[idx], shapes, omega, nu1, nu2, gamma, smoother)
+        om_idx = om[idx] if om.ndim == 1 else omega
+        x[idx] = mg_cycle(0, x[idx], b[idx], lam[idx], shapes, om_idx, nu1, nu2, gamma, smoother)
         iters[idx] += 1
         rel = residual_norms(x[idx], b[idx], lam[idx], h) / np.where(bnorm[idx] > 0, bnorm[idx], 1.0)
         for t, j in enumerate(idx):

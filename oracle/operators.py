@@ -88,13 +88,22 @@ def vanka_smoother_apply(r, lam, h):
     return (h * h / 4.0) * (4.0 * a * r + 2.0 * b * edges + c * corners)
 
 
+def _per_system(omega):
+    """A relaxation weight as a scalar or one (possibly complex) value per
+    system, shaped to broadcast against (S, ny, nx)."""
+    om = np.asarray(omega)
+    return om[:, None, None] if om.ndim == 1 else om
+
+
 def vanka_sweep(x, b, lam, h, omega):
     """One additive Vanka relaxation, x <- x + omega M_{e,j} (b - L_j x).
 
     Its error propagator is S_j = I - omega M_{e,j} L_j (Sec. 2, after
     eq. (3)).  Every patch correction uses the residual of the same old x
-    (the additive, parallel form of eq. (3))."""
-    return x + omega * vanka_smoother_apply(residual(x, b, lam, h), lam, h)
+    (the additive, parallel form of eq. (3)).  omega may be one value per
+    system and complex (the complex relaxation parameter the paper leaves for
+    future work after Example 3)."""
+    return x + _per_system(omega) * vanka_smoother_apply(residual(x, b, lam, h), lam, h)
 
 
 def jacobi_sweep(x, b, lam, h, omega):
@@ -103,7 +112,7 @@ def jacobi_sweep(x, b, lam, h, omega):
     (omega = 4/5 there)."""
     lam = np.asarray(lam, dtype=np.complex128)
     dinv = (h * h) / (4.0 + lam * h * h)
-    return x + omega * dinv[:, None, None] * residual(x, b, lam, h)
+    return x + _per_system(omega) * dinv[:, None, None] * residual(x, b, lam, h)
 
 
 def coarse_size(n):

@@ -221,7 +221,7 @@ int collect_timing(vmg_handle* H) {
 }
 
 // ---- coefficients (eq. (6)) ----
-void vanka_coef(cd lam, double h, double omega, int smoother, Coef<double>& c) {
+void vanka_coef(cd lam, double h, cd omega, int smoother, Coef<double>& c) {
     const cd eta = lam * h * h;
     const cd d4 = 4.0 / (h * h) + lam;
     cd ca, cb, cc;
@@ -980,6 +980,65 @@ int solve_impl(vmg_handle* H, const double* B, double* Z, double tol, int conj, 
 
 }  // namespace
 
+// Coefficient tables of grid G for all levels and both conj variants, and the
+// inverses of its shifted coarsest matrices.  omega: per-system complex
+// relaxation weights (interleaved, the grid's systems), or NULL for opts.omega.
+// The conj variant (the adjoint systems, shifts conj(lambda)) uses conj(omega).
+int upload_coefficients(vmg_handle* H, Group& G, const double* omega) {
+    const vmg_opts& o = H->opts;
+    std::vector<Coef<double>> c64((size_t)G.L * G.S);
+    std::vector<Coef<float>> c32((size_t)G.L * G.S);
+    const int nc = G.nc;
+    std::vector<double2> inv64((size_t)G.S * nc * nc);
+    std::vector<float2> inv32((size_t)G.S * nc * nc);
+    const int cnx = o.precision == 0 ? G.lv64.back().v.nx : G.lv32.back().v.nx;
+    const int cny = o.precision == 0 ? G.lv64.back().v.ny : G.lv32.back().v.ny;
+    const double ch = G.h * std::ldexp(1.0, G.L - 1);
+    const bool first_time = G.coef64[0] == nullptr;
+    for (int conj = 0; conj < 2; ++conj) {
+        for (int l = 0; l < G.L; ++l) {
+            const double hl = G.h * std::ldexp(1.0, l);
+            for (int s = 0; s < G.S; ++s) {
+                cd lam = H->shifts[G.sys0 + s];
+                cd om = omega ? cd(omega[2 * s], omega[2 * s + 1]) : cd(o.omega, 0.0);
+                if (conj) {
+                    lam = std::conj(lam);
+                    om = std::conj(om);
+                }
+                vanka_coef(lam, hl, om, o.smoother, c64[(size_t)l * G.S + s]);
+                c32[(size_t)l * G.S + s] = to_float(c64[(size_t)l * G.S + s]);
+            }
+        }
+        if (first_time) {
+            for (int s = 0; s < G.S; ++s) {
+                cd lam = H->shifts[G.sys0 + s];
+                if (conj) lam = std::conj(lam);
+                std::vector<cd> inv;
+                int rc = coarse_inverse(cnx, cny, ch, lam, inv);
+                if (rc) return rc;
+                for (int r = 0; r < nc; ++r)
+                    for (int k = 0; k < nc; ++k) {
+                        const cd v = inv[(size_t)r * nc + k];
+                        inv64[(size_t)s * nc * nc + (size_t)k * nc + r] = make_double2(v.real(), v.imag());
+                        inv32[(size_t)s * nc * nc + (size_t)k * nc + r] = make_float2((float)v.real(), (float)v.imag());
+                    }
+            }
+            int rc;
+            if ((rc = dev_malloc(H, (void**)&G.coef64[conj], sizeof(Coef<double>) * c64.size()))) return rc;
+            if ((rc = dev_malloc(H, (void**)&G.coef32[conj], sizeof(Coef<float>) * c32.size()))) return rc;
+            if ((rc = dev_malloc(H, (void**)&G.cinv64[conj], sizeof(double2) * inv64.size()))) return rc;
+            if ((rc = dev_malloc(H, (void**)&G.cinv32[conj], sizeof(float2) * inv32.size()))) return rc;
+            if (hipMemcpy(G.cinv64[conj], inv64.data(), sizeof(double2) * inv64.size(), hipMemcpyHostToDevice) ||
+                hipMemcpy(G.cinv32[conj], inv32.data(), sizeof(float2) * inv32.size(), hipMemcpyHostToDevice))
+                return VMG_HIP_ERROR;
+        }
+        if (hipMemcpy(G.coef64[conj], c64.data(), sizeof(Coef<double>) * c64.size(), hipMemcpyHostToDevice) ||
+            hipMemcpy(G.coef32[conj], c32.data(), sizeof(Coef<float>) * c32.size(), hipMemcpyHostToDevice))
+            return VMG_HIP_ERROR;
+    }
+    return VMG_OK;
+}
+
 // ============================================================================
 // C ABI
 // ============================================================================
@@ -1161,47 +1220,7 @@ int vanka_mg_setup(const vmg_grid* grids, int32_t n_grids, const double* shifts,
             const int nt = std::max(G.ntiles0, stream_tiles(G.lv64[0].v.nx, G.lv64[0].v.ny, o.nu2, true, 16));
             VMG_TRY(dev_malloc(H, (void**)&G.partial, sizeof(double) * (size_t)nt * G.S));
         }
-        // coefficients for all levels, both conj variants
-        std::vector<Coef<double>> c64((size_t)G.L * G.S);
-        std::vector<Coef<float>> c32((size_t)G.L * G.S);
-        const int nc = G.nc;
-        std::vector<double2> inv64((size_t)G.S * nc * nc);
-        std::vector<float2> inv32((size_t)G.S * nc * nc);
-        const int cnx = o.precision == 0 ? G.lv64.back().v.nx : G.lv32.back().v.nx;
-        const int cny = o.precision == 0 ? G.lv64.back().v.ny : G.lv32.back().v.ny;
-        const double ch = G.h * std::ldexp(1.0, G.L - 1);
-        for (int conj = 0; conj < 2; ++conj) {
-            for (int l = 0; l < G.L; ++l) {
-                const double hl = G.h * std::ldexp(1.0, l);
-                for (int s = 0; s < G.S; ++s) {
-                    cd lam = H->shifts[G.sys0 + s];
-                    if (conj) lam = std::conj(lam);
-                    vanka_coef(lam, hl, o.omega, o.smoother, c64[(size_t)l * G.S + s]);
-                    c32[(size_t)l * G.S + s] = to_float(c64[(size_t)l * G.S + s]);
-                }
-            }
-            for (int s = 0; s < G.S; ++s) {
-                cd lam = H->shifts[G.sys0 + s];
-                if (conj) lam = std::conj(lam);
-                std::vector<cd> inv;
-                VMG_TRY(coarse_inverse(cnx, cny, ch, lam, inv));
-                for (int r = 0; r < nc; ++r)
-                    for (int k = 0; k < nc; ++k) {
-                        const cd v = inv[(size_t)r * nc + k];
-                        inv64[(size_t)s * nc * nc + (size_t)k * nc + r] = make_double2(v.real(), v.imag());
-                        inv32[(size_t)s * nc * nc + (size_t)k * nc + r] = make_float2((float)v.real(), (float)v.imag());
-                    }
-            }
-            VMG_TRY(dev_malloc(H, (void**)&G.coef64[conj], sizeof(Coef<double>) * c64.size()));
-            VMG_TRY(dev_malloc(H, (void**)&G.coef32[conj], sizeof(Coef<float>) * c32.size()));
-            VMG_TRY(dev_malloc(H, (void**)&G.cinv64[conj], sizeof(double2) * inv64.size()));
-            VMG_TRY(dev_malloc(H, (void**)&G.cinv32[conj], sizeof(float2) * inv32.size()));
-            if (hipMemcpy(G.coef64[conj], c64.data(), sizeof(Coef<double>) * c64.size(), hipMemcpyHostToDevice) ||
-                hipMemcpy(G.coef32[conj], c32.data(), sizeof(Coef<float>) * c32.size(), hipMemcpyHostToDevice) ||
-                hipMemcpy(G.cinv64[conj], inv64.data(), sizeof(double2) * inv64.size(), hipMemcpyHostToDevice) ||
-                hipMemcpy(G.cinv32[conj], inv32.data(), sizeof(float2) * inv32.size(), hipMemcpyHostToDevice))
-                VMG_TRY(VMG_HIP_ERROR);
-        }
+        VMG_TRY(upload_coefficients(H, G, nullptr));
     }
 #undef VMG_TRY
     *out = H;
@@ -1236,6 +1255,16 @@ int vanka_mg_last_stats(vmg_handle* H, int32_t* iters, double* relres, void* hip
     if (iters) VMG_HIP(hipMemcpyAsync(iters, H->iters, sizeof(int) * H->S, hipMemcpyDeviceToHost, st));
     if (relres) VMG_HIP(hipMemcpyAsync(relres, H->relres, sizeof(double) * H->S, hipMemcpyDeviceToHost, st));
     VMG_HIP(hipStreamSynchronize(st));
+    return VMG_OK;
+}
+
+int vanka_mg_set_omega(vmg_handle* H, const double* omega) {
+    if (!H) return VMG_INVALID_ARG;
+    if (hipDeviceSynchronize() != hipSuccess) return VMG_HIP_ERROR;
+    for (auto& g : H->groups) {
+        int rc = upload_coefficients(H, g, omega ? omega + 2 * (size_t)g.sys0 : nullptr);
+        if (rc) return rc;
+    }
     return VMG_OK;
 }
 

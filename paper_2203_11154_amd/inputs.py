@@ -54,6 +54,33 @@ def uniform_shifts(S, seed=SEED_SHIFTS, re=(1.0, 1e4), im=(-1e4, 1e4)):
     return a + 1j * b
 
 
+def example1_shifts(n):
+    """Eigenvalues of the boundary-value-method matrix of Example 1,
+    B = (1/tau) tridiag(-1/2, 0, 1/2) with last row (..., -1, 1), tau = 1/n."""
+    B = np.zeros((n, n))
+    for i in range(n - 1):
+        if i > 0:
+            B[i, i - 1] = -0.5
+        B[i, i + 1] = 0.5
+    B[n - 1, n - 2], B[n - 1, n - 1] = -1.0, 1.0
+    return np.linalg.eigvals(B * n)
+
+
+def example2_shifts(n, beta=0.01):
+    """Eigenvalues of the (n+1) x (n+1) quasi-boundary-value matrix of
+    Example 2: first row (1, 0, ..., 0, 1/beta), then (-1, 1) steps; tau = 1/n."""
+    m = n + 1
+    B = np.eye(m) - np.eye(m, k=-1)
+    B[0, m - 1] = 1.0 / beta
+    return np.linalg.eigvals(B * n)
+
+
+def example3_shifts(count=128):
+    """Example 3 (Helmholtz): lambda_j = -j^2 (1 - 0.5 i), j = 1..count."""
+    j = np.arange(1, count + 1, dtype=np.float64)
+    return -(j ** 2) * (1.0 - 0.5j)
+
+
 def heat_parameters(K=16, seed=SEED_THETA):
     """theta_k ~ N(0, 1), k = 1..K."""
     return np.random.default_rng(seed).standard_normal(K)

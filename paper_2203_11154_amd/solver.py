@@ -97,6 +97,16 @@ class VankaMG:
         _lib.check(self.lib.vanka_mg_levels(self.handle, g, ctypes.byref(cnt), nx, ny), "vanka_mg_levels")
         return [(nx[i], ny[i]) for i in range(cnt.value)]
 
+    def set_omega(self, omega=None):
+        """Per-system complex relaxation weights (None: back to the scalar
+        omega given at construction)."""
+        if omega is None:
+            _lib.check(self.lib.vanka_mg_set_omega(self.handle, None), "vanka_mg_set_omega")
+            return
+        om = np.ascontiguousarray(np.broadcast_to(np.asarray(omega, dtype=np.complex128), (self.num_systems,)))
+        _lib.check(self.lib.vanka_mg_set_omega(self.handle, om.view(np.float64).ctypes.data_as(
+            ctypes.POINTER(ctypes.c_double))), "vanka_mg_set_omega")
+
     def autotune(self, cache_path=None):
         """Time the kernel schedules of every level and keep the fastest;
         returns the schedule per grid (see schedule())."""

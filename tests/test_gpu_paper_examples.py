@@ -1,0 +1,125 @@
+"""The paper's own experiments on the GPU path (Sec. 3): W(1,0) cycles from
+h0 = 1/8 to a 1e-8 residual reduction, the additive Vanka smoother
+(omega = 24/25) against damped Jacobi (omega = 4/5), on the shifts of
+Example 1 (eq. (9)), Example 2 (eq. (10)) and Example 3 (Helmholtz), plus the
+per-shift complex relaxation weight suggested as future work after Example 3.
+
+Checked: convergence, the observed rates against the LFA factors of Table 1,
+cycle counts and GPU time of Vanka against Jacobi, and parity with the oracle
+at fixed cycle counts."""
+import time
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import lfa, multigrid as omg, operators as ops
+from paper_2203_11154_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+W10 = dict(nu1=1, nu2=0, gamma=2)
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(np.asarray(a, dtype=np.complex128))).to("cuda")
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def timed_solve(solver, bd, tol):
+    solver.solve(bd, tol=tol)  # warm-up and graph capture
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    Z, iters, relres, status = solver.solve(bd, tol=tol)
+    torch.cuda.synchronize()
+    return Z, iters, relres, status, time.perf_counter() - t0
+
+
+def rates(relres, iters):
+    return relres ** (1.0 / np.maximum(iters, 1))
+
+
+def test_example1_vanka_vs_jacobi():
+    """Example 1, h = tau = 1/256 (255 x 255, 256 shifts): Vanka needs well
+    under half of Jacobi's W(1,0) cycles and time; observed rates near the
+    LFA factors 0.28 and 0.60 of Table 1."""
+    from paper_2203_11154_amd import Grid, VankaMG
+    n, nt = 255, 256
+    h = 1.0 / (n + 1)
+    lam = inputs.example1_shifts(nt)
+    b = inputs.rhs(nt, n, n)
+    bd = dev(b.ravel())
+    vanka = VankaMG([Grid(n, num_systems=nt)], lam, **W10)
+    jacobi = VankaMG([Grid(n, num_systems=nt)], lam, omega=0.8, smoother="jacobi", max_iter=200, **W10)
+    Zv, itv, rrv, stv, tv = timed_solve(vanka, bd, 1e-8)
+    Zj, itj, rrj, stj, tj = timed_solve(jacobi, bd, 1e-8)
+    assert stv == 0 and stj == 0
+    rv, rj = rates(rrv, itv), rates(rrj, itj)
+    print(f"Example 1 W(1,0) to 1e-8: Vanka {itv.min()}-{itv.max()} cycles, rate {np.median(rv):.3f}, {tv*1e3:.1f} ms;"
+          f" Jacobi {itj.min()}-{itj.max()} cycles, rate {np.median(rj):.3f}, {tj*1e3:.1f} ms")
+    assert 0.2 < np.median(rv) < 0.3 and 0.5 < np.median(rj) < 0.62
+    assert np.mean(itj) >= 2.0 * np.mean(itv)
+    assert tj >= 1.8 * tv
+    # parity at the GPU's counts for two shifts
+    pick = np.array([0, nt // 2])
+    for sol, Z, it, kw in ((vanka, Zv, itv, {}), (jacobi, Zj, itj, dict(smoother="jacobi", omega=0.8))):
+        z = host(Z).reshape(nt, n, n)
+        zr, _, _, _ = omg.solve(b[pick], lam[pick], h, fixed_iters=it[pick], **W10, **kw)
+        for k, j in enumerate(pick):
+            assert np.linalg.norm(z[j] - zr[k]) <= 1e-10 * np.linalg.norm(zr[k])
+
+
+def test_example2_uniform_rates():
+    """Example 2 (eq. (10), beta = 0.01, 257 shifts with real parts from
+    about -4.6 to 516): the same convergence rate for every shift."""
+    from paper_2203_11154_amd import Grid, VankaMG
+    n, nt = 255, 256
+    lam = inputs.example2_shifts(nt)
+    assert lam.real.min() < 0 < lam.real.max()
+    b = inputs.rhs(nt + 1, n, n, seed=7)
+    solver = VankaMG([Grid(n, num_systems=nt + 1)], lam, **W10)
+    Z, it, rr, status = solver.solve(dev(b.ravel()), tol=1e-8)
+    assert status == 0 and np.all(rr <= 1e-8)
+    r = rates(rr, it)
+    assert r.max() - r.min() < 0.05 and r.max() < 0.32
+    assert it.max() - it.min() <= 2
+
+
+def test_example3_deterioration_and_complex_omega():
+    """Example 3 (lambda_j = -j^2 (1 - 0.5 i), h = 1/128): every shift
+    converges, the cycle count grows with j; per-shift complex omegas from
+    the LFA optimum never cost more than one extra cycle, and a sweep with
+    complex omegas matches the oracle."""
+    from paper_2203_11154_amd import Grid, VankaMG, _lib
+    n = 127
+    h = 1.0 / (n + 1)
+    j = np.arange(8, 129, 8)
+    lam = inputs.example3_shifts(128)[j - 1]
+    b = inputs.rhs(len(j), n, n, seed=8)
+    bd = dev(b.ravel())
+    solver = VankaMG([Grid(n, num_systems=len(j))], lam, **W10)
+    Z, it, rr, status = solver.solve(bd, tol=1e-8)
+    assert status == 0 and np.all(rr <= 1e-8)
+    # a gradual, not strictly monotone, growth of the cycle count with j
+    assert it[-4:].mean() > it[:4].mean() + 3
+    assert np.corrcoef(j, it)[0, 1] > 0.8
+    oms = np.array([lfa.optimal_complex_omega(l * h * h)[0] for l in lam])
+    solver.set_omega(oms)
+    Zc, itc, rrc, stc = solver.solve(bd, tol=1e-8)
+    assert stc == 0 and np.all(rrc <= 1e-8) and np.all(itc <= it + 1)
+    # one sweep with the complex weights against the oracle
+    rng = np.random.default_rng(3)
+    x = rng.standard_normal((len(j), n, n)) + 1j * rng.standard_normal((len(j), n, n))
+    out = host(solver.apply_op(_lib.OP_SWEEP, 0, bd, dev(x.ravel()))).reshape(len(j), n, n)
+    ref = ops.vanka_sweep(x, b, lam, h, oms)
+    assert np.max(np.abs(out - ref)) <= 1e-13 * np.max(np.abs(ref))
+    # and the W(1,0) solve at fixed counts
+    zr, _, _, _ = omg.solve(b[:2], lam[:2], h, omega=oms[:2], fixed_iters=itc[:2], **W10)
+    z = host(Zc).reshape(len(j), n, n)
+    for k in range(2):
+        assert np.linalg.norm(z[k] - zr[k]) <= 1e-10 * np.linalg.norm(zr[k])

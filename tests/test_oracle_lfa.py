@@ -100,3 +100,31 @@ def test_helmholtz_deterioration():
     assert mus[0] < 0.2805
     assert all(b >= a - 1e-9 for a, b in zip(mus, mus[1:]))
     assert mus[-1] > 0.3
+
+
+def test_complex_omega_optimiser():
+    """eta = 0: the best complex omega is the real 24/25 with mu = 7/25
+    (Sec. 2.1); for the large Example 3 shifts a complex omega lowers the
+    smoothing factor below the real optimum (the paper's future-work
+    suggestion after Example 3)."""
+    w0, m0 = lfa.optimal_complex_omega(0.0)
+    assert abs(w0 - 24 / 25) < 2e-3 and m0 == pytest.approx(7 / 25, abs=2e-3)
+    lam = spectral.helmholtz_shifts(128)
+    h = 1.0 / 128
+    eta = lam[127] * h * h
+    w, m = lfa.optimal_complex_omega(eta)
+    assert abs(w.imag) > 1e-3
+    assert m < lfa.smoothing_factor(eta, 24 / 25, n=64) - 0.02
+
+
+def test_oracle_sweep_accepts_complex_per_system_omega():
+    from oracle import operators as ops
+    rng = np.random.default_rng(2)
+    x = rng.standard_normal((2, 7, 7)) + 1j * rng.standard_normal((2, 7, 7))
+    b = rng.standard_normal((2, 7, 7)) + 1j * rng.standard_normal((2, 7, 7))
+    lam = np.array([3 + 1j, -20 + 9j])
+    om = np.array([0.9 + 0.1j, 1.0 - 0.2j])
+    out = ops.vanka_sweep(x, b, lam, 0.125, om)
+    for j in range(2):
+        ref = ops.vanka_sweep(x[j:j + 1], b[j:j + 1], lam[j:j + 1], 0.125, om[j])
+        np.testing.assert_allclose(out[j], ref[0], rtol=1e-15)

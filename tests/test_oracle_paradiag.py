@@ -100,3 +100,21 @@ def test_heat_gradient_adjoint_vs_closed_form():
         Lp, _ = pd.heat_loss_closed_form(th + d, ths, n, nx, tau)
         Lm, _ = pd.heat_loss_closed_form(th - d, ths, n, nx, tau)
         assert (Lp - Lm) / (2 * eps) == pytest.approx(g[k], rel=1e-8)
+
+
+def test_example_shift_generators_match_oracle_matrices():
+    """The workload generators' shifts are the eigenvalues of the oracle's
+    matrices of eqs. (9) and (10) and the Example 3 formula."""
+    key = lambda z: (round(z.real, 6), round(z.imag, 6))
+    for n in (16, 64):
+        ref = np.linalg.eigvals(spectral.bvm_matrix(n))
+        np.testing.assert_allclose(sorted(inputs.example1_shifts(n), key=key), sorted(ref, key=key), rtol=1e-9)
+        ref2 = np.linalg.eigvals(spectral.qbvm_matrix(n, 0.01))
+        np.testing.assert_allclose(sorted(inputs.example2_shifts(n), key=key), sorted(ref2, key=key), rtol=1e-8)
+    np.testing.assert_array_equal(inputs.example3_shifts(128), spectral.helmholtz_shifts(128))
+    # Example 2 is an alpha-circulant with alpha = -1/beta: eigenvalues in closed form
+    n = 64
+    m = n + 1
+    k = np.arange(m)
+    closed = (1 - (100.0 ** (1 / m)) * np.exp(1j * np.pi * (2 * k + 1) / m)) * n
+    np.testing.assert_allclose(sorted(inputs.example2_shifts(n), key=key), sorted(closed, key=key), rtol=1e-8)
