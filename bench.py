@@ -183,7 +183,7 @@ def main():
     # dominant kernel: the finest-level fused correction + post-smoothing kernel
     # (HBM bound); it is the only launch of its instantiation, so HIP-event
     # and rocprofv3 averages cover the same launches
-    la, ms, by = solver.level_stats("up")[0]
+    _, la, ms, by = solver.level_stats("up")[0]
     gbs = by / (ms * 1e-3) / 1e9
     traffic = None
     if MEASURED_TRAFFIC["source_sha256_16"] == kernel_source_hash(MEASURED_TRAFFIC["source"]):
@@ -197,7 +197,7 @@ def main():
     for k in ("down", "up"):
         levels[k] = [{"level": l, "launches": a, "avg_ms": round(m / max(a, 1), 4),
                       "GB/s": round(b_ / (m * 1e-3) / 1e9, 1) if m > 0 else None}
-                     for l, (a, m, b_) in enumerate(solver.level_stats(k))]
+                     for l, a, m, b_ in solver.level_stats(k)]
     tl, tms, tby = stats["transform"]
     flops = 8.0 * S * S * n * n * tl
     kernels = {k: {"launches": v[0], "ms": round(v[1], 3),

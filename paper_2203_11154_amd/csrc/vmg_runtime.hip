@@ -332,8 +332,16 @@ struct CycleCtx {
 // Levels at least this wide run the fused streaming kernels.
 constexpr int STREAM_MIN_NX = 96;
 
+// The streaming kernels address each plane through a buffer range checked
+// in 32 bits (out-of-range offsets read zero); planes of 1 GiB and more stay
+// on the tiled kernels.
+bool stream_fits(const vmg_opts& o, const LevelView& v) {
+    const int64_t es = o.precision == 0 ? (int64_t)sizeof(double2) : (int64_t)sizeof(float2);
+    return v.plane * es < ((int64_t)1 << 30);
+}
+
 bool use_stream(const vmg_opts& o, const LevelView& v) {
-    return v.nx >= STREAM_MIN_NX && o.nu1 <= 2 && o.nu2 <= 2;
+    return v.nx >= STREAM_MIN_NX && o.nu1 <= 2 && o.nu2 <= 2 && stream_fits(o, v);
 }
 
 // Rows per block: tall blocks amortise the pipeline's start-up rows, short
@@ -350,7 +358,7 @@ const LevelView& cycle_view(const vmg_handle* H, const Group& g, int l) {
 // Kernel schedule of grid g at level l: the autotuned choice if there is
 // one, else the size heuristic above.
 bool sched_stream(const vmg_handle* H, const Group& g, int l) {
-    if (H->opts.nu1 > 2 || H->opts.nu2 > 2) return false;
+    if (H->opts.nu1 > 2 || H->opts.nu2 > 2 || !stream_fits(H->opts, cycle_view(H, g, l))) return false;
     if ((int)g.sched.size() > l && g.sched[l] >= 0) return g.sched[l] > 0;
     return use_stream(H->opts, cycle_view(H, g, l));
 }
@@ -1613,7 +1621,7 @@ extern "C" int vanka_mg_autotune(vmg_handle* H, const char* cache_path, void* hi
             }
             const LevelView& v = cycle_view(H, g, l);
             std::vector<int> cands{0};
-            if (H->opts.nu1 <= 2 && H->opts.nu2 <= 2 && v.nx >= 32)
+            if (H->opts.nu1 <= 2 && H->opts.nu2 <= 2 && v.nx >= 32 && stream_fits(H->opts, v))
                 for (int r : {32, 64, 128})
                     if (r <= 2 * v.ny) cands.push_back(r);
             int best = 0;

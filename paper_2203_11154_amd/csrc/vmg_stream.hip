@@ -51,13 +51,18 @@ template <typename C> __device__ __forceinline__ C fma2(C acc, C a, C b) {  // a
 #ifndef VMG_NEIGHBOR_DPP
 #define VMG_NEIGHBOR_DPP 1
 #endif
+template <int CTRL> __device__ __forceinline__ int dpp_move_i(int v) {
+    // bound_ctrl set: a lane whose source is off the wave receives 0, so no
+    // "old" operand has to be materialised
+    return __builtin_amdgcn_mov_dpp(v, CTRL, 0xF, 0xF, true);
+}
 template <int CTRL> __device__ __forceinline__ float dpp_move(float v) {
-    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+    return __int_as_float(dpp_move_i<CTRL>(__float_as_int(v)));
 }
 template <int CTRL> __device__ __forceinline__ double dpp_move(double v) {
     const long long b = __double_as_longlong(v);
-    const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffLL), CTRL, 0xF, 0xF, false);
-    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
+    const int lo = dpp_move_i<CTRL>((int)(b & 0xffffffffLL));
+    const int hi = dpp_move_i<CTRL>((int)(b >> 32));
     return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 template <typename C> __device__ __forceinline__ C from_left(C v) {
@@ -83,259 +88,462 @@ template <typename C> __device__ __forceinline__ C from_right(C v) {
     return r;
 }
 
-// three-row window, r[2] = newest row
-template <typename C> struct Win {
-    C r[3];
-    __device__ __forceinline__ void init() { r[0] = r[1] = r[2] = z2<C>(); }
-    __device__ __forceinline__ void push(C v) {
-        r[0] = r[1];
-        r[1] = r[2];
-        r[2] = v;
-    }
-};
+// Left + right neighbour sum.
+template <typename C> __device__ __forceinline__ C lr_sum(C v) { return add(from_left(v), from_right(v)); }
 
-// residual of the middle row of an iterate window: b - (d x - s (W + E + N + S))
+// Residual of a middle row: b - (d x - s (W + E + N + S)), from the rows
+// above (xo), at (xm) and below (xn).
 template <typename T, typename C>
-__device__ __forceinline__ C residual_mid(const Win<C>& xw, C bv, C d, T s) {
-    const C nb = add(add(from_left(xw.r[1]), from_right(xw.r[1])), add(xw.r[0], xw.r[2]));
-    return sub(bv, sub(mul(d, xw.r[1]), scl(nb, s)));
+__device__ __forceinline__ C residual_row(C xo, C xm, C xn, C bv, C d, T s) {
+    const C nb = add(lr_sum(xm), add(xo, xn));
+    return sub(bv, sub(mul(d, xm), scl(nb, s)));
 }
 
-// Vanka update of the middle row: x + ca r + cb (edge sum) + cc (corner sum),
-// with nw holding the left+right neighbour sums of the r rows
+// Vanka update of a middle row from the residual rows above (ro), at (rm)
+// and below (rn):  x + ca r + cb (edge sum) + cc (corner sum).  The lane
+// shifts commute with the (uniform) coefficients, so the four edge and four
+// corner terms take one neighbour sum:
+//   x + ca rm + cb (ro + rn) + LR(cb rm + cc (ro + rn)).
 template <typename T, typename C>
-__device__ __forceinline__ C vanka_mid(C xc, const Win<C>& rw, const Win<C>& nw, const Coef<T>& cf) {
-    const C edge = add(nw.r[1], add(rw.r[0], rw.r[2]));
-    const C corner = add(nw.r[0], nw.r[2]);
-    C v = fma2(xc, cf.ca, rw.r[1]);
-    v = fma2(v, cf.cb, edge);
-    return fma2(v, cf.cc, corner);
+__device__ __forceinline__ C vanka_row(C xc, C ro, C rm, C rn, const Coef<T>& cf) {
+    const C vs = add(ro, rn);
+    const C w = fma2(mul(cf.cb, rm), cf.cc, vs);
+    C v = fma2(xc, cf.ca, rm);
+    v = fma2(v, cf.cb, vs);
+    return add(v, lr_sum(w));
+}
+
+// Full weighting around a middle row, the same way:
+//   rm/4 + (ro + rn)/8 + LR(rm/8 + (ro + rn)/16).
+template <typename T, typename C> __device__ __forceinline__ C full_weight_row(C ro, C rm, C rn) {
+    const C vs = add(ro, rn);
+    const C w = add(scl(rm, (T)0.125), scl(vs, (T)0.0625));
+    return add(add(scl(rm, (T)0.25), scl(vs, (T)0.125)), lr_sum(w));
 }
 
 __device__ __forceinline__ bool in_rows(int k, int ny) { return k >= 1 && k <= ny; }
 
-// ---------------------------------------------------------------------------
+// Plane access through buffer resources.  The hardware range check returns
+// zero for a load, and drops a store, at a byte offset at or beyond the
+// plane's size; an invalid row or column therefore just adds OOB to the
+// offset (planes are kept below 1 GiB, so any sum holding OOB is out of
+// range).  Loads and stores then need no branches, which keeps the memory
+// counter waits exact and lets rows be fetched ahead.
+constexpr unsigned OOB = 0x40000000u;
+using rsrc_t = __amdgpu_buffer_rsrc_t;
+template <typename C> __device__ __forceinline__ rsrc_t plane_rsrc(const C* p, int64_t elems) {
+    return __builtin_amdgcn_make_buffer_rsrc((void*)p, (short)0, (int)(elems * (int64_t)sizeof(C)), 0x00020000);
+}
+// voff: per-lane byte offset (range checked); soff: uniform byte offset,
+// only ever non-zero for rows known to lie inside the plane
+__device__ __forceinline__ void bload(rsrc_t r, unsigned voff, unsigned soff, double2& v) {
+    v = __builtin_bit_cast(double2, __builtin_amdgcn_raw_buffer_load_b128(r, (int)voff, (int)soff, 0));
+}
+__device__ __forceinline__ void bload(rsrc_t r, unsigned voff, unsigned soff, float2& v) {
+    v = __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(r, (int)voff, (int)soff, 0));
+}
+__device__ __forceinline__ void bstore(rsrc_t r, unsigned voff, unsigned soff, double2 v) {
+    using V = __attribute__((ext_vector_type(4))) unsigned int;
+    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(V, v), r, (int)voff, (int)soff, 0);
+}
+__device__ __forceinline__ void bstore(rsrc_t r, unsigned voff, unsigned soff, float2 v) {
+    using V = __attribute__((ext_vector_type(2))) unsigned int;
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(V, v), r, (int)voff, (int)soff, 0);
+}
+// byte offset of row j when ok, else OOB (uniform)
+__device__ __forceinline__ unsigned row_off(bool ok, int j, int pitch, int es) {
+    return ok ? (unsigned)(j * pitch * es) : OOB;
+}
+
+// The hardware hands consecutive workgroups of a launch to the chip's eight
+// XCDs in turn, and each XCD has its own L2.  Renumber the blocks so that
+// every XCD receives one contiguous run of the logical order (x fastest):
+// strips that share halo columns then meet in the same L2.
+constexpr unsigned NXCD = 8;
+__device__ __forceinline__ uint3 xcd_block() {
+    const unsigned gx = gridDim.x, gxy = gridDim.x * gridDim.y;
+    const unsigned n = gxy * gridDim.z;
+    const unsigned L = blockIdx.x + gx * blockIdx.y + gxy * blockIdx.z;
+    const unsigned xcd = L % NXCD, k = L / NXCD, q = n / NXCD, r = n % NXCD;
+    const unsigned Lp = xcd * q + min(xcd, r) + k;
+    return make_uint3(Lp % gx, (Lp % gxy) / gx, Lp / gxy);
+}
+
+// Row pipelines.  Both kernels advance one grid row per step and are
+// unrolled by UNR steps, so that every ring of rows below has a length that
+// divides UNR and all ring slots are compile-time constants (no register
+// rotation): a value pushed at phase P of the unrolled block sits in slot
+// P mod L, the one pushed k steps earlier in (P - k) mod L.  Raw x and b rows
+// are fetched PF steps ahead of their use.  Every block of UNR rows starts at
+// an even row, so the parity of a row is that of its phase.
+//
+// Columns off the interior: b and x read zero there (out-of-range offsets),
+// and d, s are replaced by zero in those lanes, so the residual vanishes
+// there without a select; the smoothed iterate is cleared there by a lane
+// select.  Rows off the interior only occur in the unrolled blocks at the two
+// ends of a block's range ("edge" blocks); the interior blocks run a copy of
+// the step with every row test removed.
+#ifndef VMG_STREAM_PF
+#define VMG_STREAM_PF 2
+#endif
+#ifndef VMG_STREAM_MINWAVES
+#define VMG_STREAM_MINWAVES 0
+#endif
+#if VMG_STREAM_MINWAVES > 0
+#define VMG_STREAM_OCC __attribute__((amdgpu_waves_per_eu(VMG_STREAM_MINWAVES)))
+#else
+#define VMG_STREAM_OCC
+#endif
+constexpr int UNR = 6;
+constexpr int PF = VMG_STREAM_PF;
+static_assert(UNR % 6 == 0 && UNR % (PF + 1) == 0, "ring lengths must divide the unroll");
+template <int L> __host__ __device__ constexpr int slot(int p) { return ((p % L) + L * UNR) % L; }
+
+// An empty asm statement that takes v in registers: everything v depends on
+// is computed before this point.  Ends each step, so the compiler cannot sink
+// a step's arithmetic into a later one (which keeps many rows alive at once).
+__device__ __forceinline__ void pin(double& v) { asm volatile("" : "+v"(v)); }
+__device__ __forceinline__ void pin(float& v) { asm volatile("" : "+v"(v)); }
+__device__ __forceinline__ void pin(double2& v) { asm volatile("" : "+v"(v.x), "+v"(v.y)); }
+__device__ __forceinline__ void pin(float2& v) { asm volatile("" : "+v"(v.x), "+v"(v.y)); }
+
+template <typename C> __device__ __forceinline__ C lane_clear(bool keep, C v) {
+    C r;
+    r.x = keep ? v.x : 0;
+    r.y = keep ? v.y : 0;
+    return r;
+}
+
 template <typename T, int NS>
-__global__ __launch_bounds__(NT) void k_down(SegTable<T> tab, int ty) {
+struct DownPipe {
     using C = cplx<T>;
-    constexpr int HALO = 2 * NS + 2;
-    constexpr int OWN = 64 - 2 * HALO;
-    constexpr int NB = 2 * NS + 1;  // b rows in flight
-    const int lane = threadIdx.x & 63;
-    const LevelSeg<T> S = seg_of(tab, blockIdx.z);
-    const int sys = blockIdx.z - S.z0;
-    if ((int)blockIdx.x >= S.gx || (int)blockIdx.y >= S.gy) return;
-    if (!S.active[sys]) return;
-    const LevelView lf = S.lf, lc = S.lc;
-    const int x_zero = S.x_zero;
-    const T s = S.s;
-    const int c0 = 1 + (int)(blockIdx.x * (NT / 64) + (threadIdx.x >> 6)) * OWN;
-    if (c0 > lf.nx) return;  // whole wave idle; no block barriers in this kernel
-    const int i = c0 - HALO + lane;
-    const bool col_in = i >= 1 && i <= lf.nx;
-    const bool col_ld = i >= 0 && i <= lf.nx + 1;
-    const bool own = lane >= HALO && lane < HALO + OWN && col_in;
-    const int k0 = 1 + (int)blockIdx.y * ty;
-    const int k1 = min(lf.ny, k0 + ty - 1);
-    const int64_t base = (int64_t)sys * lf.plane;
-    const C* xs = S.x + base;
-    const C* bs = S.b + base;
-    C* xos = S.xo + base;
-    C* bcs = S.c + (int64_t)sys * lc.plane;
-    const Coef<T> cf = S.coef[sys];
+    static constexpr int HALO = 2 * NS + 2;
+    static constexpr int OWN = 64 - 2 * HALO;
+    C X[NS + 1][3], R[NS + 1][3];
+    C B[6];             // b rows j-1, j-2, ... (ring of 6 >= 2 NS + 1)
+    C xr[PF + 1], br[PF + 1];
+    rsrc_t xs, bs, xos, bcs;
+    LevelView lf, lc;
+    Coef<T> cf;
+    C dl;               // d on interior columns, else 0
+    T sl;               // s on interior columns, else 0
+    int k0, k1;
+    bool col_in;
+    unsigned ox, ob, oo, of;  // lane byte offsets: x, b, x written, coarse b (or OOB)
+    unsigned rx;              // bytes per fine row
+    unsigned rc;              // bytes per coarse row
 
-    Win<C> X[NS + 1], R[NS + 1], N[NS + 1];
-#pragma unroll
-    for (int q = 0; q <= NS; ++q) {
-        X[q].init();
-        R[q].init();
-        N[q].init();
+    template <bool EDGE> __device__ __forceinline__ C load_x(int j) const {
+        C v;
+        if constexpr (EDGE) bload(xs, ox + (j >= 0 && j <= lf.ny + 1 ? j * rx : OOB), 0, v);
+        else bload(xs, ox, j * rx, v);
+        return v;
     }
-    C B[NB];
-#pragma unroll
-    for (int q = 0; q < NB; ++q) B[q] = z2<C>();
-
-    const int jbeg = k0 - 2 * NS - 2, jend = k1 + 2 * NS + 2;
-    // rows are fetched one iteration ahead so their latency overlaps the
-    // current row's arithmetic
-    auto load_x = [&](int j) {
-        C v = z2<C>();
-        if (!x_zero && col_ld && j >= 0 && j <= lf.ny + 1) v = xs[(int64_t)j * lf.pitch + i];
+    template <bool EDGE> __device__ __forceinline__ C load_b(int j) const {
+        C v;
+        if constexpr (EDGE) bload(bs, ob + (in_rows(j, lf.ny) ? j * rx : OOB), 0, v);
+        else bload(bs, ob, j * rx, v);
         return v;
-    };
-    auto load_b = [&](int j) {
-        C v = z2<C>();
-        if (col_in && in_rows(j, lf.ny)) v = bs[(int64_t)j * lf.pitch + i];
-        return v;
-    };
-    C xnext = load_x(jbeg), bnext = load_b(jbeg - 1);
-    for (int j = jbeg; j <= jend; ++j) {
-        // newest iterate row j and newest right-hand side row j - 1
-        const C xn = xnext, bn = bnext;
-        xnext = load_x(j + 1);
-        bnext = load_b(j);
-        X[0].push(xn);
-#pragma unroll
-        for (int q = 0; q < NB - 1; ++q) B[q] = B[q + 1];
-        B[NB - 1] = bn;
+    }
+    // step at row j, phase P: push x_0 row j and b row j - 1; stage q turns
+    // x_q rows j-2q-2..j-2q into r_q row j-2q-1 and x_{q+1} row j-2q-2
+    template <int P, bool EDGE> __device__ __forceinline__ void step(int j) {
+        xr[slot<PF + 1>(P + PF)] = load_x<EDGE>(j + PF);
+        br[slot<PF + 1>(P + PF)] = load_b<EDGE>(j + PF - 1);
+        constexpr int n0 = slot<3>(P), n1 = slot<3>(P - 1), n2 = slot<3>(P - 2);
+        X[0][n0] = xr[slot<PF + 1>(P)];
+        B[slot<6>(P)] = br[slot<PF + 1>(P)];
 #pragma unroll
         for (int q = 0; q <= NS; ++q) {
-            // r_q at row j - 2q - 1 from x_q rows j - 2q - 2 .. j - 2q
-            const int rrow = j - 2 * q - 1;
-            C r = residual_mid<T>(X[q], B[NB - 1 - 2 * q], cf.d, s);
-            if (!(col_in && in_rows(rrow, lf.ny))) r = z2<C>();
-            R[q].push(r);
-            N[q].push(add(from_left(r), from_right(r)));
+            C r = residual_row<T>(X[q][n2], X[q][n1], X[q][n0], B[slot<6>(P - 2 * q)], dl, sl);
+            if constexpr (EDGE)
+                if (!in_rows(j - 2 * q - 1, lf.ny)) r = z2<C>();
+            R[q][n0] = r;
             if (q < NS) {
-                // x_{q+1} at row j - 2q - 2
-                const int xrow = j - 2 * q - 2;
-                C v = vanka_mid<T>(X[q].r[0], R[q], N[q], cf);
-                if (!(col_in && in_rows(xrow, lf.ny))) v = z2<C>();
-                X[q + 1].push(v);
+                C v = lane_clear(col_in, vanka_row<T>(X[q][n2], R[q][n2], R[q][n1], R[q][n0], cf));
+                if constexpr (EDGE)
+                    if (!in_rows(j - 2 * q - 2, lf.ny)) v = z2<C>();
+                X[q + 1][n0] = v;
             }
+            pin(R[q][n0]);
+            if (q < NS) pin(X[q + 1][n0]);
         }
-        if (NS > 0) {
+        if constexpr (NS > 0) {
             const int orow = j - 2 * NS;
-            if (own && orow >= k0 && orow <= k1) xos[(int64_t)orow * lf.pitch + i] = X[NS].r[2];
+            if constexpr (EDGE) bstore(xos, oo + (orow >= k0 && orow <= k1 ? orow * rx : OOB), 0, X[NS][n0]);
+            else bstore(xos, oo, orow * rx, X[NS][n0]);
         }
         // full weighting around fine row j - 2NS - 2 (even rows carry coarse nodes)
-        const int frow = j - 2 * NS - 2;
-        if (own && !(frow & 1) && !(i & 1) && frow >= k0 && frow <= k1 && frow >= 2) {
-            const Win<C>& rw = R[NS];
-            const Win<C>& nw = N[NS];
-            C v = scl(rw.r[1], (T)0.25);
-            v = add(v, scl(add(nw.r[1], add(rw.r[0], rw.r[2])), (T)0.125));
-            v = add(v, scl(add(nw.r[0], nw.r[2]), (T)0.0625));
-            const int K = frow >> 1, I = i >> 1;
-            if (K <= lc.ny && I <= lc.nx) bcs[(int64_t)K * lc.pitch + I] = v;
+        if constexpr ((P & 1) == 0) {
+            const int frow = j - 2 * NS - 2;
+            const C v = full_weight_row<T>(R[NS][n2], R[NS][n1], R[NS][n0]);
+            const int K = frow >> 1;
+            if constexpr (EDGE)
+                bstore(bcs, of + (frow >= k0 && frow <= k1 && frow >= 2 && K <= lc.ny ? K * rc : OOB), 0, v);
+            else bstore(bcs, of, K * rc, v);
         }
     }
+    // (the scheduling barriers keep each step's loads in their step, so that
+    // the fetch-ahead distance stays PF rows and the registers bounded)
+    template <bool EDGE> __device__ __forceinline__ void block(int j) {
+        step<0, EDGE>(j);
+        __builtin_amdgcn_sched_barrier(0);
+        step<1, EDGE>(j + 1);
+        __builtin_amdgcn_sched_barrier(0);
+        step<2, EDGE>(j + 2);
+        __builtin_amdgcn_sched_barrier(0);
+        step<3, EDGE>(j + 3);
+        __builtin_amdgcn_sched_barrier(0);
+        step<4, EDGE>(j + 4);
+        __builtin_amdgcn_sched_barrier(0);
+        step<5, EDGE>(j + 5);
+        __builtin_amdgcn_sched_barrier(0);
+    }
+};
+
+// ---------------------------------------------------------------------------
+template <typename T, int NS>
+__global__ __launch_bounds__(NT) VMG_STREAM_OCC void k_down(SegTable<T> tab, int ty) {
+    using C = cplx<T>;
+    using Pipe = DownPipe<T, NS>;
+    constexpr int HALO = Pipe::HALO, OWN = Pipe::OWN;
+    const uint3 blk = xcd_block();
+    const int lane = threadIdx.x & 63;
+    const LevelSeg<T> S = seg_of(tab, blk.z);
+    const int sys = blk.z - S.z0;
+    if ((int)blk.x >= S.gx || (int)blk.y >= S.gy) return;
+    if (!S.active[sys]) return;
+    Pipe p;
+    p.lf = S.lf;
+    p.lc = S.lc;
+    const int c0 = 1 + (int)(blk.x * (NT / 64) + (threadIdx.x >> 6)) * OWN;
+    if (c0 > p.lf.nx) return;  // whole wave idle; no block barriers in this kernel
+    const int i = c0 - HALO + lane;
+    p.col_in = i >= 1 && i <= p.lf.nx;
+    const bool col_ld = i >= 0 && i <= p.lf.nx + 1 && !S.x_zero;
+    const bool own = lane >= HALO && lane < HALO + OWN && p.col_in;
+    const unsigned es = sizeof(C);
+    p.ox = col_ld ? i * es : OOB;
+    p.ob = p.col_in ? i * es : OOB;
+    p.oo = own ? i * es : OOB;
+    p.of = (own && !(i & 1) && (i >> 1) <= p.lc.nx) ? (i >> 1) * es : OOB;
+    p.rx = p.lf.pitch * es;
+    p.rc = p.lc.pitch * es;
+    p.k0 = 1 + (int)blk.y * ty;
+    p.k1 = min(p.lf.ny, p.k0 + ty - 1);
+    const int64_t base = (int64_t)sys * p.lf.plane;
+    p.xs = plane_rsrc(S.x + base, p.lf.plane);
+    p.bs = plane_rsrc(S.b + base, p.lf.plane);
+    p.xos = plane_rsrc(S.xo + base, p.lf.plane);
+    p.bcs = plane_rsrc(S.c + (int64_t)sys * p.lc.plane, p.lc.plane);
+    p.cf = S.coef[sys];
+    p.dl = p.col_in ? p.cf.d : z2<C>();
+    p.sl = p.col_in ? S.s : (T)0;
+#pragma unroll
+    for (int q = 0; q <= NS; ++q)
+#pragma unroll
+        for (int w = 0; w < 3; ++w) p.X[q][w] = p.R[q][w] = z2<C>();
+#pragma unroll
+    for (int w = 0; w < 6; ++w) p.B[w] = z2<C>();
+    int jbeg = p.k0 - 2 * NS - 2;
+    jbeg -= jbeg & 1;
+    const int jend = p.k1 + 2 * NS + 2;
+    // unrolled blocks whose rows (and the rows they load and store) all lie
+    // inside the grid and the block's range
+    const int jlo = max(p.k0 + 2 * NS + 2, 2 * NS + 4), jhi = min(p.lf.ny - 4 - PF, p.k1 + 2 * NS - 5);
+#pragma unroll
+    for (int d = 0; d < PF; ++d) {
+        p.xr[d] = p.template load_x<true>(jbeg + d);
+        p.br[d] = p.template load_b<true>(jbeg + d - 1);
+    }
+    int j = jbeg;
+    for (; j <= jend && j < jlo; j += UNR) p.template block<true>(j);
+    for (; j <= jhi; j += UNR) p.template block<false>(j);
+    for (; j <= jend; j += UNR) p.template block<true>(j);
 }
+
+template <typename T, int NS, bool NORM>
+struct UpPipe {
+    using C = cplx<T>;
+    static constexpr int HALO = NORM ? 2 * NS + 1 : (NS > 0 ? 2 * NS : 1);
+    static constexpr int OWN = 64 - 2 * HALO;
+    C X[NS + 1][3], R[NS + 1][3];
+    C B[6];
+    C xr[PF + 1], br[PF + 1];
+    C er[3], ei[3];     // coarse rows: raw, and interpolated along x
+    rsrc_t xs, bs, es, xos;
+    LevelView lf, lc;
+    Coef<T> cf;
+    C dl;
+    T sl;
+    int k0, k1;
+    bool col_in, odd;
+    unsigned ox, oe, oo;  // lane byte offsets: x and b, coarse e, x written (or OOB)
+    unsigned rx, rc;
+    double acc;
+
+    template <bool EDGE> __device__ __forceinline__ C load_x(int j) const {
+        C v;
+        if constexpr (EDGE) bload(xs, ox + (in_rows(j, lf.ny) ? j * rx : OOB), 0, v);
+        else bload(xs, ox, j * rx, v);
+        return v;
+    }
+    template <bool EDGE> __device__ __forceinline__ C load_b(int j) const {
+        C v;
+        if constexpr (EDGE) bload(bs, ox + (in_rows(j, lf.ny) ? j * rx : OOB), 0, v);
+        else bload(bs, ox, j * rx, v);
+        return v;
+    }
+    template <bool EDGE> __device__ __forceinline__ C load_e(int K) const {
+        C v;
+        if constexpr (EDGE) bload(es, oe + (K >= 0 && K <= lc.ny + 1 ? K * rc : OOB), 0, v);
+        else bload(es, oe, K * rc, v);
+        return v;
+    }
+    // coarse column i/2 at an even fine column; the average of coarse columns
+    // (i-1)/2 and (i+1)/2 at an odd one (the right one via a lane shift)
+    __device__ __forceinline__ C interp_x(C v) const {
+        const C rv = from_right(v);
+        return odd ? scl(add(v, rv), (T)0.5) : v;
+    }
+    // Step at fine row j, phase P.  Coarse row K = jb/2 + c (jb the unrolled
+    // block's first row) lives in coarse slot c mod 3: its raw load is issued
+    // four fine rows ahead of row 2K - 1, where it is interpolated along x.
+    // Off the interior the interpolated correction is zero by itself (odd
+    // level sizes: the ring of the coarse grid lies on the fine ring).
+    template <int P, bool EDGE> __device__ __forceinline__ void step(int j) {
+        xr[slot<PF + 1>(P + PF)] = load_x<EDGE>(j + PF);
+        br[slot<PF + 1>(P + PF)] = load_b<EDGE>(j + PF - 1);
+        C e;
+        if constexpr ((P & 1) != 0) {
+            constexpr int lo = slot<3>((P - 1) / 2), hi = slot<3>((P + 1) / 2);
+            ei[hi] = interp_x(er[hi]);
+            e = scl(add(ei[lo], ei[hi]), (T)0.5);
+        } else {
+            er[slot<3>(P / 2 + 2)] = load_e<EDGE>((j >> 1) + 2);
+            e = ei[slot<3>(P / 2)];
+        }
+        constexpr int n0 = slot<3>(P), n1 = slot<3>(P - 1), n2 = slot<3>(P - 2);
+        X[0][n0] = add(xr[slot<PF + 1>(P)], e);
+        B[slot<6>(P)] = br[slot<PF + 1>(P)];
+#pragma unroll
+        for (int q = 0; q <= NS; ++q) {
+            if (q == NS && !NORM) break;
+            const int rrow = j - 2 * q - 1;
+            C r = residual_row<T>(X[q][n2], X[q][n1], X[q][n0], B[slot<6>(P - 2 * q)], dl, sl);
+            if constexpr (EDGE)
+                if (!in_rows(rrow, lf.ny)) r = z2<C>();
+            if (q == NS) {
+                // the owned-lane mask is applied once, at the end
+                if (!EDGE || (rrow >= k0 && rrow <= k1)) acc += (double)r.x * (double)r.x + (double)r.y * (double)r.y;
+                pin(acc);
+                break;
+            }
+            R[q][n0] = r;
+            C v = lane_clear(col_in, vanka_row<T>(X[q][n2], R[q][n2], R[q][n1], R[q][n0], cf));
+            if constexpr (EDGE)
+                if (!in_rows(j - 2 * q - 2, lf.ny)) v = z2<C>();
+            X[q + 1][n0] = v;
+            pin(R[q][n0]);
+            pin(X[q + 1][n0]);
+        }
+        pin(X[0][n0]);
+        const int orow = j - 2 * NS;
+        if constexpr (EDGE) bstore(xos, oo + (orow >= k0 && orow <= k1 ? orow * rx : OOB), 0, X[NS][n0]);
+        else bstore(xos, oo, orow * rx, X[NS][n0]);
+    }
+    template <bool EDGE> __device__ __forceinline__ void block(int j) {
+        step<0, EDGE>(j);
+        __builtin_amdgcn_sched_barrier(0);
+        step<1, EDGE>(j + 1);
+        __builtin_amdgcn_sched_barrier(0);
+        step<2, EDGE>(j + 2);
+        __builtin_amdgcn_sched_barrier(0);
+        step<3, EDGE>(j + 3);
+        __builtin_amdgcn_sched_barrier(0);
+        step<4, EDGE>(j + 4);
+        __builtin_amdgcn_sched_barrier(0);
+        step<5, EDGE>(j + 5);
+        __builtin_amdgcn_sched_barrier(0);
+    }
+};
 
 // ---------------------------------------------------------------------------
 template <typename T, int NS, bool NORM>
-__global__ __launch_bounds__(NT) void k_up(SegTable<T> tab, int ty) {
+__global__ __launch_bounds__(NT) VMG_STREAM_OCC void k_up(SegTable<T> tab, int ty) {
     using C = cplx<T>;
-    constexpr int HALO = NORM ? 2 * NS + 1 : (NS > 0 ? 2 * NS : 1);
-    constexpr int OWN = 64 - 2 * HALO;
-    constexpr int NB = 2 * NS + 1;
+    using Pipe = UpPipe<T, NS, NORM>;
+    constexpr int HALO = Pipe::HALO, OWN = Pipe::OWN;
     __shared__ double red[NT / 64];
+    const uint3 blk = xcd_block();
     const int lane = threadIdx.x & 63;
-    const LevelSeg<T> S = seg_of(tab, blockIdx.z);
-    const int sys = blockIdx.z - S.z0;
+    const LevelSeg<T> S = seg_of(tab, blk.z);
+    const int sys = blk.z - S.z0;
     // both exits are uniform over the block (before its only barrier)
-    if ((int)blockIdx.x >= S.gx || (int)blockIdx.y >= S.gy) return;
+    if ((int)blk.x >= S.gx || (int)blk.y >= S.gy) return;
     if (!S.active[sys]) return;
-    const LevelView lf = S.lf, lc = S.lc;
-    const T s = S.s;
+    Pipe p;
+    p.lf = S.lf;
+    p.lc = S.lc;
     double* partial = S.partial;
-    const int c0 = 1 + (int)(blockIdx.x * (NT / 64) + (threadIdx.x >> 6)) * OWN;
-    const bool wave_on = c0 <= lf.nx;
+    const int c0 = 1 + (int)(blk.x * (NT / 64) + (threadIdx.x >> 6)) * OWN;
+    const bool wave_on = c0 <= p.lf.nx;
     const int i = c0 - HALO + lane;
-    const bool col_in = wave_on && i >= 1 && i <= lf.nx;
-    const bool own = lane >= HALO && lane < HALO + OWN && col_in;
-    const int k0 = 1 + (int)blockIdx.y * ty;
-    const int k1 = min(lf.ny, k0 + ty - 1);
-    const int64_t base = (int64_t)sys * lf.plane;
-    const C* xs = S.x + base;
-    const C* bs = S.b + base;
-    const C* es = S.c + (int64_t)sys * lc.plane;
-    C* xos = S.xo + base;
-    const Coef<T> cf = S.coef[sys];
-
-    Win<C> X[NS + 1], R[NS + 1], N[NS + 1];
-#pragma unroll
-    for (int q = 0; q <= NS; ++q) {
-        X[q].init();
-        R[q].init();
-        N[q].init();
-    }
-    C B[NB];
-#pragma unroll
-    for (int q = 0; q < NB; ++q) B[q] = z2<C>();
-    double acc = 0.0;
-
-    const int jbeg = k0 - 2 * NS - 1, jend = k1 + 2 * NS + 1;
-    // Bilinear correction, streamed by coarse rows: lane i loads coarse column
-    // i/2 of each coarse row once; an odd column averages it with its right
-    // neighbour's value (coarse column (i+1)/2), fetched by a lane shift.
-    // Fine row j uses the x-interpolated coarse rows j/2 (even j) or
-    // (j-1)/2 and (j+1)/2 (odd j).  Raw loads of x, b and the next coarse row
-    // are issued one row ahead and combined only when the row is consumed.
-    const bool ecol = wave_on && i >= 0 && i <= lf.nx + 1;
-    auto load_e = [&](int K) {
-        C v = z2<C>();
-        if (ecol && K >= 0 && K <= lc.ny + 1) v = es[(int64_t)K * lc.pitch + (i >> 1)];
-        return v;
-    };
-    auto interp_x = [&](C v) {
-        const C rv = from_right(v);
-        return (i & 1) ? scl(add(v, rv), (T)0.5) : v;
-    };
-    auto load_x = [&](int j) {
-        C v = z2<C>();
-        if (col_in && in_rows(j, lf.ny)) v = xs[(int64_t)j * lf.pitch + i];
-        return v;
-    };
-    auto load_b = [&](int j) {
-        C v = z2<C>();
-        if (col_in && in_rows(j, lf.ny)) v = bs[(int64_t)j * lf.pitch + i];
-        return v;
-    };
+    p.col_in = wave_on && i >= 1 && i <= p.lf.nx;
+    p.odd = (i & 1) != 0;
+    const bool ecol = wave_on && i >= 0 && i <= p.lf.nx + 1;
+    const bool own = lane >= HALO && lane < HALO + OWN && p.col_in;
+    const unsigned es = sizeof(C);
+    p.ox = p.col_in ? i * es : OOB;
+    p.oe = ecol ? (i >> 1) * es : OOB;
+    p.oo = own ? i * es : OOB;
+    p.rx = p.lf.pitch * es;
+    p.rc = p.lc.pitch * es;
+    p.k0 = 1 + (int)blk.y * ty;
+    p.k1 = min(p.lf.ny, p.k0 + ty - 1);
+    const int64_t base = (int64_t)sys * p.lf.plane;
+    p.xs = plane_rsrc(S.x + base, p.lf.plane);
+    p.bs = plane_rsrc(S.b + base, p.lf.plane);
+    p.es = plane_rsrc(S.c + (int64_t)sys * p.lc.plane, p.lc.plane);
+    p.xos = plane_rsrc(S.xo + base, p.lf.plane);
+    p.cf = S.coef[sys];
+    p.dl = p.col_in ? p.cf.d : z2<C>();
+    p.sl = p.col_in ? S.s : (T)0;
+    p.acc = 0.0;
     if (wave_on) {
-        C e_lo = z2<C>(), e_hi = z2<C>(), e_raw = z2<C>();
-        if (jbeg & 1) {
-            e_hi = interp_x(load_e((jbeg - 1) >> 1));
-            e_raw = load_e((jbeg + 1) >> 1);
-        } else {
-            e_hi = interp_x(load_e(jbeg >> 1));
-        }
-        C xnext = load_x(jbeg), bnext = load_b(jbeg - 1);
-        for (int j = jbeg; j <= jend; ++j) {
-            const C xr = xnext, bn = bnext;
-            xnext = load_x(j + 1);
-            bnext = load_b(j);
-            if (j & 1) {
-                e_lo = e_hi;                 // coarse row (j - 1) / 2
-                e_hi = interp_x(e_raw);      // coarse row (j + 1) / 2
-            } else {
-                e_raw = load_e((j + 2) >> 1);  // needed by row j + 1
-            }
-            C xn = z2<C>();
-            if (col_in && in_rows(j, lf.ny)) xn = add(xr, (j & 1) ? scl(add(e_lo, e_hi), (T)0.5) : e_hi);
-            X[0].push(xn);
 #pragma unroll
-            for (int q = 0; q < NB - 1; ++q) B[q] = B[q + 1];
-            B[NB - 1] = bn;
+        for (int q = 0; q <= NS; ++q)
 #pragma unroll
-            for (int q = 0; q <= NS; ++q) {
-                if (q == NS && !NORM) break;
-                const int rrow = j - 2 * q - 1;
-                C r = residual_mid<T>(X[q], B[NB - 1 - 2 * q], cf.d, s);
-                if (!(col_in && in_rows(rrow, lf.ny))) r = z2<C>();
-                if (q == NS) {
-                    if (own && rrow >= k0 && rrow <= k1) acc += (double)r.x * (double)r.x + (double)r.y * (double)r.y;
-                    break;
-                }  // (the sum is written only for segments with a partial buffer)
-                R[q].push(r);
-                N[q].push(add(from_left(r), from_right(r)));
-                const int xrow = j - 2 * q - 2;
-                C v = vanka_mid<T>(X[q].r[0], R[q], N[q], cf);
-                if (!(col_in && in_rows(xrow, lf.ny))) v = z2<C>();
-                X[q + 1].push(v);
-            }
-            const int orow = j - 2 * NS;
-            if (own && orow >= k0 && orow <= k1) xos[(int64_t)orow * lf.pitch + i] = X[NS].r[2];
+            for (int w = 0; w < 3; ++w) p.X[q][w] = p.R[q][w] = z2<C>();
+#pragma unroll
+        for (int w = 0; w < 6; ++w) p.B[w] = z2<C>();
+        int jbeg = p.k0 - 2 * NS - 1;
+        jbeg -= jbeg & 1;
+        const int jend = p.k1 + 2 * NS + 1;
+        const int jlo = max(p.k0 + 2 * NS + 1, 2 * NS + 2);
+        const int jhi = min(min(p.lf.ny - 5 - PF, p.lf.ny - 7), p.k1 + 2 * NS - 5);
+        // coarse rows jbeg/2 (interpolated) and jbeg/2 + 1 (raw) before the first step
+        p.ei[0] = p.interp_x(p.template load_e<true>(jbeg >> 1));
+        p.er[1] = p.template load_e<true>((jbeg >> 1) + 1);
+#pragma unroll
+        for (int d = 0; d < PF; ++d) {
+            p.xr[d] = p.template load_x<true>(jbeg + d);
+            p.br[d] = p.template load_b<true>(jbeg + d - 1);
         }
+        int j = jbeg;
+        for (; j <= jend && j < jlo; j += UNR) p.template block<true>(j);
+        for (; j <= jhi; j += UNR) p.template block<false>(j);
+        for (; j <= jend; j += UNR) p.template block<true>(j);
     }
     if (NORM && partial) {
+        double acc = own ? p.acc : 0.0;
         for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
         if (lane == 0) red[threadIdx.x >> 6] = acc;
         __syncthreads();
         if (threadIdx.x == 0) {
             double t = 0.0;
             for (int w = 0; w < NT / 64; ++w) t += red[w];
-            partial[(int64_t)sys * (S.gx * S.gy) + blockIdx.y * S.gx + blockIdx.x] = t;
+            partial[(int64_t)sys * (S.gx * S.gy) + blk.y * S.gx + blk.x] = t;
         }
     }
 }

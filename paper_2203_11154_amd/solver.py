@@ -216,14 +216,15 @@ class VankaMG:
         _lib.check(self.lib.vanka_mg_set_timing(self.handle, int(enable), int(reset)), "vanka_mg_set_timing")
 
     def level_stats(self, kclass):
-        """[(launches, total_ms, total_algorithmic_bytes)] per level for one class."""
+        """[(level, launches, total_ms, total_algorithmic_bytes)] for every level
+        on which one class of kernel ran."""
         k = _lib.KERNEL_CLASSES.index(kclass)
         n = 32
         la = (ctypes.c_int64 * n)()
         ms = (ctypes.c_double * n)()
         by = (ctypes.c_double * n)()
         _lib.check(self.lib.vanka_mg_level_stats(self.handle, k, n, la, ms, by), "vanka_mg_level_stats")
-        return [(la[i], ms[i], by[i]) for i in range(n) if la[i] > 0]
+        return [(i, la[i], ms[i], by[i]) for i in range(n) if la[i] > 0]
 
     def kernel_stats(self):
         """{class: (launches, total_ms, total_algorithmic_bytes)}"""
