@@ -52,6 +52,13 @@ template <typename T> struct LevelSeg {
     int nc;               // coarsest level: unknowns per system
     int z0;               // first blockIdx.z of the segment
     int gx, gy;           // blocks of the segment in x and y
+    // streaming kernels (one wave per run of rows, see vmg_stream.hip)
+    int nsys;             // systems of the segment
+    int strips;           // column strips per system
+    int rows;             // rows per run (one run per wave)
+    int pieces;           // runs per strip
+    int waves;            // waves of the segment
+    int w0;               // first global wave of the segment
 };
 template <typename T> struct SegTable {
     int n;
@@ -135,14 +142,17 @@ void launch_transform(int n, int64_t m, const double2* M, int trans_conj, const 
 // Fused register-streaming level kernels (vmg_stream.hip), nu in {0, 1, 2},
 // batched over segments like the launchers above:
 //   down: nu sweeps, residual, full weighting -> xo (x_nu), c (coarse rhs)
-//   up:   x + P c, nu sweeps -> xo; per-block |b - L xo|^2 into a segment's
-//         partial (partial[sys * tiles + tile], tiles = stream_tiles(..., norm
-//         = true, ty)) when that pointer is not NULL.  `norm` selects the
-//         geometry with the extra halo lane the norm needs.
-// ty = rows per block.
-template <typename T> void launch_down(SegTable<T> tab, const int* nsys, int nu, int ty, hipStream_t st);
-template <typename T> void launch_up(SegTable<T> tab, const int* nsys, int nu, bool norm, int ty, hipStream_t st);
-int stream_tiles(int nx, int ny, int nu, bool norm, int ty);
+//   up:   x + P c, nu sweeps -> xo; with `norm`, the partial sums of
+//         |b - L xo|^2 go to a segment's partial buffer when that pointer is
+//         not NULL (partial[sys * tiles + t], tiles = stream_tiles(...)).
+//         `norm` selects the geometry with the extra halo lane the norm needs.
+// The work of a level is split evenly over the device's resident waves, with
+// at least rmin rows per wave.
+template <typename T> void launch_down(SegTable<T> tab, const int* nsys, int nu, int rmin, hipStream_t st);
+template <typename T> void launch_up(SegTable<T> tab, const int* nsys, int nu, bool norm, int rmin, hipStream_t st);
+template <typename T> int stream_tiles(int nx, int ny, int nsys, int nu, int rmin);
+int stream_tiles_max(int nx, int ny, int nu);  // over every rmin
+void stream_prepare();  // device occupancy of the streaming kernels (call outside stream capture)
 template <typename T> void launch_fill_zero(cplx<T>* x, LevelView lv, int nsys, hipStream_t st);
 
 // Shift sensitivities out[s] = -sum_p conj(z[s*m + p]) g[s*m + p]; partial

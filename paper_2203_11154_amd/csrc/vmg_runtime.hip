@@ -707,7 +707,7 @@ int level0_flips(const vmg_handle* H, const Group& g) {
 }
 
 int norm_tiles(const vmg_handle* H, const Group& g) {
-    return stream_tiles(g.lv64[0].v.nx, g.lv64[0].v.ny, H->opts.nu2, true, sched_rows(H, g, 0));
+    return stream_tiles<double>(g.lv64[0].v.nx, g.lv64[0].v.ny, g.S, H->opts.nu2, sched_rows(H, g, 0));
 }
 
 // residual norms of level 0 of every group (unless the last cycle's fused
@@ -1188,6 +1188,7 @@ int vanka_mg_setup(const vmg_grid* grids, int32_t n_grids, const double* shifts,
     }
     H->shifts.resize(total);
     for (int s = 0; s < total; ++s) H->shifts[s] = cd(shifts[2 * s], shifts[2 * s + 1]);
+    stream_prepare();
 
     int rc = VMG_OK;
 #define VMG_TRY(x)                 \
@@ -1224,8 +1225,7 @@ int vanka_mg_setup(const vmg_grid* grids, int32_t n_grids, const double* shifts,
         }
         G.ntiles0 = residual_tiles(G.lv64[0].v);
         {
-            // the smallest row block the tuning range allows sets the largest tile count
-            const int nt = std::max(G.ntiles0, stream_tiles(G.lv64[0].v.nx, G.lv64[0].v.ny, o.nu2, true, 16));
+            const int nt = std::max(G.ntiles0, stream_tiles_max(G.lv64[0].v.nx, G.lv64[0].v.ny, o.nu2));
             VMG_TRY(dev_malloc(H, (void**)&G.partial, sizeof(double) * (size_t)nt * G.S));
         }
         VMG_TRY(upload_coefficients(H, G, nullptr));

@@ -21,6 +21,10 @@
 // ring for the iterates, zero residual off the interior).
 #include "vmg_internal.h"
 
+#include <algorithm>
+#include <map>
+#include <mutex>
+
 namespace vmg {
 
 namespace {
@@ -142,13 +146,18 @@ __device__ __forceinline__ void bload(rsrc_t r, unsigned voff, unsigned soff, do
 __device__ __forceinline__ void bload(rsrc_t r, unsigned voff, unsigned soff, float2& v) {
     v = __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(r, (int)voff, (int)soff, 0));
 }
+// Stores carry the non-temporal hint (iterates written once per pass; the
+// cache keeps the rows that neighbouring waves read again).
+#ifndef VMG_STREAM_STORE_POLICY
+#define VMG_STREAM_STORE_POLICY 2
+#endif
 __device__ __forceinline__ void bstore(rsrc_t r, unsigned voff, unsigned soff, double2 v) {
     using V = __attribute__((ext_vector_type(4))) unsigned int;
-    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(V, v), r, (int)voff, (int)soff, 0);
+    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(V, v), r, (int)voff, (int)soff, VMG_STREAM_STORE_POLICY);
 }
 __device__ __forceinline__ void bstore(rsrc_t r, unsigned voff, unsigned soff, float2 v) {
     using V = __attribute__((ext_vector_type(2))) unsigned int;
-    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(V, v), r, (int)voff, (int)soff, 0);
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(V, v), r, (int)voff, (int)soff, VMG_STREAM_STORE_POLICY);
 }
 // byte offset of row j when ok, else OOB (uniform)
 __device__ __forceinline__ unsigned row_off(bool ok, int j, int pitch, int es) {
@@ -301,24 +310,17 @@ struct DownPipe {
     }
 };
 
-// ---------------------------------------------------------------------------
+// One wave's share of the work: rows k0..k1 of strip `strip` of system
+// `sys` of segment S (the pipeline adds its halo rows itself).
 template <typename T, int NS>
-__global__ __launch_bounds__(NT) VMG_STREAM_OCC void k_down(SegTable<T> tab, int ty) {
+__device__ __forceinline__ void down_piece(const LevelSeg<T>& S, int sys, int strip, int k0, int k1, int lane) {
     using C = cplx<T>;
     using Pipe = DownPipe<T, NS>;
     constexpr int HALO = Pipe::HALO, OWN = Pipe::OWN;
-    const uint3 blk = xcd_block();
-    const int lane = threadIdx.x & 63;
-    const LevelSeg<T> S = seg_of(tab, blk.z);
-    const int sys = blk.z - S.z0;
-    if ((int)blk.x >= S.gx || (int)blk.y >= S.gy) return;
-    if (!S.active[sys]) return;
     Pipe p;
     p.lf = S.lf;
     p.lc = S.lc;
-    const int c0 = 1 + (int)(blk.x * (NT / 64) + (threadIdx.x >> 6)) * OWN;
-    if (c0 > p.lf.nx) return;  // whole wave idle; no block barriers in this kernel
-    const int i = c0 - HALO + lane;
+    const int i = 1 + strip * OWN - HALO + lane;
     p.col_in = i >= 1 && i <= p.lf.nx;
     const bool col_ld = i >= 0 && i <= p.lf.nx + 1 && !S.x_zero;
     const bool own = lane >= HALO && lane < HALO + OWN && p.col_in;
@@ -329,8 +331,8 @@ __global__ __launch_bounds__(NT) VMG_STREAM_OCC void k_down(SegTable<T> tab, int
     p.of = (own && !(i & 1) && (i >> 1) <= p.lc.nx) ? (i >> 1) * es : OOB;
     p.rx = p.lf.pitch * es;
     p.rc = p.lc.pitch * es;
-    p.k0 = 1 + (int)blk.y * ty;
-    p.k1 = min(p.lf.ny, p.k0 + ty - 1);
+    p.k0 = k0;
+    p.k1 = k1;
     const int64_t base = (int64_t)sys * p.lf.plane;
     p.xs = plane_rsrc(S.x + base, p.lf.plane);
     p.bs = plane_rsrc(S.b + base, p.lf.plane);
@@ -345,12 +347,12 @@ __global__ __launch_bounds__(NT) VMG_STREAM_OCC void k_down(SegTable<T> tab, int
         for (int w = 0; w < 3; ++w) p.X[q][w] = p.R[q][w] = z2<C>();
 #pragma unroll
     for (int w = 0; w < 6; ++w) p.B[w] = z2<C>();
-    int jbeg = p.k0 - 2 * NS - 2;
+    int jbeg = k0 - 2 * NS - 2;
     jbeg -= jbeg & 1;
-    const int jend = p.k1 + 2 * NS + 2;
+    const int jend = k1 + 2 * NS + 2;
     // unrolled blocks whose rows (and the rows they load and store) all lie
-    // inside the grid and the block's range
-    const int jlo = max(p.k0 + 2 * NS + 2, 2 * NS + 4), jhi = min(p.lf.ny - 4 - PF, p.k1 + 2 * NS - 5);
+    // inside the grid and the piece
+    const int jlo = max(k0 + 2 * NS + 2, 2 * NS + 4), jhi = min(p.lf.ny - 4 - PF, k1 + 2 * NS - 5);
 #pragma unroll
     for (int d = 0; d < PF; ++d) {
         p.xr[d] = p.template load_x<true>(jbeg + d);
@@ -360,6 +362,50 @@ __global__ __launch_bounds__(NT) VMG_STREAM_OCC void k_down(SegTable<T> tab, int
     for (; j <= jend && j < jlo; j += UNR) p.template block<true>(j);
     for (; j <= jhi; j += UNR) p.template block<false>(j);
     for (; j <= jend; j += UNR) p.template block<true>(j);
+}
+
+// Segment of global wave gw (segments own consecutive wave ranges).
+template <typename T> __device__ __forceinline__ LevelSeg<T> seg_of_wave(const SegTable<T>& t, int gw) {
+    LevelSeg<T> r = t.s[0];
+#pragma unroll
+    for (int q = 1; q < MAXSEG; ++q)
+        if (q < t.n && gw >= t.s[q].w0) r = t.s[q];
+    return r;
+}
+
+// Work split: every strip of every system is cut into S.pieces runs of
+// S.rows rows (the last one shorter), one per wave; the host picks the cut so
+// that the waves fill the device evenly.  Waves are numbered with the run
+// fastest, then the strip, then the system, so neighbouring runs and strips
+// go to neighbouring waves (same XCD, same time).
+struct Piece {
+    int sys, strip, k0, k1, slot;
+};
+template <typename T> __device__ __forceinline__ Piece piece_of(const LevelSeg<T>& S, int lw) {
+    Piece pc;
+    const int t = lw / S.pieces;
+    const int run = lw - t * S.pieces;
+    pc.sys = t / S.strips;
+    pc.strip = t - pc.sys * S.strips;
+    pc.k0 = 1 + run * S.rows;
+    pc.k1 = min(S.lf.ny, pc.k0 + S.rows - 1);
+    pc.slot = lw;  // == (sys * strips + strip) * pieces + run
+    return pc;
+}
+
+// ---------------------------------------------------------------------------
+template <typename T, int NS>
+__global__ __launch_bounds__(NT) VMG_STREAM_OCC void k_down(SegTable<T> tab) {
+    // the wave index is uniform over the wave; say so, so that everything
+    // derived from it (segment, buffer resources, row bounds) lives in SGPRs
+    const int gw = (int)xcd_block().x * (NT / 64) + __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int lane = threadIdx.x & 63;
+    const LevelSeg<T> S = seg_of_wave(tab, gw);
+    const int lw = gw - S.w0;
+    if (lw >= S.waves) return;  // whole wave idle; no block barriers in this kernel
+    const Piece pc = piece_of(S, lw);
+    if (pc.k0 > pc.k1 || !S.active[pc.sys]) return;
+    down_piece<T, NS>(S, pc.sys, pc.strip, pc.k0, pc.k1, lane);
 }
 
 template <typename T, int NS, bool NORM>
@@ -468,30 +514,20 @@ struct UpPipe {
     }
 };
 
-// ---------------------------------------------------------------------------
+// Rows k0..k1 of one strip of one system; returns the lane's share of
+// sum |b - L x|^2 over the owned columns and rows (NORM).
 template <typename T, int NS, bool NORM>
-__global__ __launch_bounds__(NT) VMG_STREAM_OCC void k_up(SegTable<T> tab, int ty) {
+__device__ __forceinline__ double up_piece(const LevelSeg<T>& S, int sys, int strip, int k0, int k1, int lane) {
     using C = cplx<T>;
     using Pipe = UpPipe<T, NS, NORM>;
     constexpr int HALO = Pipe::HALO, OWN = Pipe::OWN;
-    __shared__ double red[NT / 64];
-    const uint3 blk = xcd_block();
-    const int lane = threadIdx.x & 63;
-    const LevelSeg<T> S = seg_of(tab, blk.z);
-    const int sys = blk.z - S.z0;
-    // both exits are uniform over the block (before its only barrier)
-    if ((int)blk.x >= S.gx || (int)blk.y >= S.gy) return;
-    if (!S.active[sys]) return;
     Pipe p;
     p.lf = S.lf;
     p.lc = S.lc;
-    double* partial = S.partial;
-    const int c0 = 1 + (int)(blk.x * (NT / 64) + (threadIdx.x >> 6)) * OWN;
-    const bool wave_on = c0 <= p.lf.nx;
-    const int i = c0 - HALO + lane;
-    p.col_in = wave_on && i >= 1 && i <= p.lf.nx;
+    const int i = 1 + strip * OWN - HALO + lane;
+    p.col_in = i >= 1 && i <= p.lf.nx;
     p.odd = (i & 1) != 0;
-    const bool ecol = wave_on && i >= 0 && i <= p.lf.nx + 1;
+    const bool ecol = i >= 0 && i <= p.lf.nx + 1;
     const bool own = lane >= HALO && lane < HALO + OWN && p.col_in;
     const unsigned es = sizeof(C);
     p.ox = p.col_in ? i * es : OOB;
@@ -499,8 +535,8 @@ __global__ __launch_bounds__(NT) VMG_STREAM_OCC void k_up(SegTable<T> tab, int t
     p.oo = own ? i * es : OOB;
     p.rx = p.lf.pitch * es;
     p.rc = p.lc.pitch * es;
-    p.k0 = 1 + (int)blk.y * ty;
-    p.k1 = min(p.lf.ny, p.k0 + ty - 1);
+    p.k0 = k0;
+    p.k1 = k1;
     const int64_t base = (int64_t)sys * p.lf.plane;
     p.xs = plane_rsrc(S.x + base, p.lf.plane);
     p.bs = plane_rsrc(S.b + base, p.lf.plane);
@@ -510,41 +546,51 @@ __global__ __launch_bounds__(NT) VMG_STREAM_OCC void k_up(SegTable<T> tab, int t
     p.dl = p.col_in ? p.cf.d : z2<C>();
     p.sl = p.col_in ? S.s : (T)0;
     p.acc = 0.0;
-    if (wave_on) {
 #pragma unroll
-        for (int q = 0; q <= NS; ++q)
+    for (int q = 0; q <= NS; ++q)
 #pragma unroll
-            for (int w = 0; w < 3; ++w) p.X[q][w] = p.R[q][w] = z2<C>();
+        for (int w = 0; w < 3; ++w) p.X[q][w] = p.R[q][w] = z2<C>();
 #pragma unroll
-        for (int w = 0; w < 6; ++w) p.B[w] = z2<C>();
-        int jbeg = p.k0 - 2 * NS - 1;
-        jbeg -= jbeg & 1;
-        const int jend = p.k1 + 2 * NS + 1;
-        const int jlo = max(p.k0 + 2 * NS + 1, 2 * NS + 2);
-        const int jhi = min(min(p.lf.ny - 5 - PF, p.lf.ny - 7), p.k1 + 2 * NS - 5);
-        // coarse rows jbeg/2 (interpolated) and jbeg/2 + 1 (raw) before the first step
-        p.ei[0] = p.interp_x(p.template load_e<true>(jbeg >> 1));
-        p.er[1] = p.template load_e<true>((jbeg >> 1) + 1);
+    for (int w = 0; w < 6; ++w) p.B[w] = z2<C>();
+    int jbeg = k0 - 2 * NS - 1;
+    jbeg -= jbeg & 1;
+    const int jend = k1 + 2 * NS + 1;
+    const int jlo = max(k0 + 2 * NS + 1, 2 * NS + 2);
+    const int jhi = min(min(p.lf.ny - 5 - PF, p.lf.ny - 7), k1 + 2 * NS - 5);
+    // coarse rows jbeg/2 (interpolated) and jbeg/2 + 1 (raw) before the first step
+    p.ei[0] = p.interp_x(p.template load_e<true>(jbeg >> 1));
+    p.er[1] = p.template load_e<true>((jbeg >> 1) + 1);
 #pragma unroll
-        for (int d = 0; d < PF; ++d) {
-            p.xr[d] = p.template load_x<true>(jbeg + d);
-            p.br[d] = p.template load_b<true>(jbeg + d - 1);
-        }
-        int j = jbeg;
-        for (; j <= jend && j < jlo; j += UNR) p.template block<true>(j);
-        for (; j <= jhi; j += UNR) p.template block<false>(j);
-        for (; j <= jend; j += UNR) p.template block<true>(j);
+    for (int d = 0; d < PF; ++d) {
+        p.xr[d] = p.template load_x<true>(jbeg + d);
+        p.br[d] = p.template load_b<true>(jbeg + d - 1);
     }
-    if (NORM && partial) {
-        double acc = own ? p.acc : 0.0;
+    int j = jbeg;
+    for (; j <= jend && j < jlo; j += UNR) p.template block<true>(j);
+    for (; j <= jhi; j += UNR) p.template block<false>(j);
+    for (; j <= jend; j += UNR) p.template block<true>(j);
+    return own ? p.acc : 0.0;
+}
+
+// ---------------------------------------------------------------------------
+// With NORM, every wave leaves its run's sum in the segment's partial buffer
+// (slot = the wave's index in the segment, S.pieces * S.strips per system).
+template <typename T, int NS, bool NORM>
+__global__ __launch_bounds__(NT) VMG_STREAM_OCC void k_up(SegTable<T> tab) {
+    // the wave index is uniform over the wave; say so, so that everything
+    // derived from it (segment, buffer resources, row bounds) lives in SGPRs
+    const int gw = (int)xcd_block().x * (NT / 64) + __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int lane = threadIdx.x & 63;
+    const LevelSeg<T> S = seg_of_wave(tab, gw);
+    const int lw = gw - S.w0;
+    if (lw >= S.waves) return;  // whole wave idle; no block barriers in this kernel
+    const Piece pc = piece_of(S, lw);
+    if (!S.active[pc.sys]) return;
+    double acc = 0.0;
+    if (pc.k0 <= pc.k1) acc = up_piece<T, NS, NORM>(S, pc.sys, pc.strip, pc.k0, pc.k1, lane);
+    if (NORM && S.partial) {
         for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
-        if (lane == 0) red[threadIdx.x >> 6] = acc;
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            double t = 0.0;
-            for (int w = 0; w < NT / 64; ++w) t += red[w];
-            partial[(int64_t)sys * (S.gx * S.gy) + blk.y * S.gx + blk.x] = t;
-        }
+        if (lane == 0) S.partial[pc.slot] = acc;
     }
 }
 
@@ -556,74 +602,135 @@ __global__ __launch_bounds__(NT) void k_fill_zero(cplx<T>* __restrict__ x, Level
         x[(int64_t)blockIdx.z * lv.plane + (int64_t)k * lv.pitch + i] = z2<cplx<T>>();
 }
 
-template <int NS> constexpr int down_own() { return 64 - 2 * (2 * NS + 2); }
-template <int NS, bool NORM> constexpr int up_own() { return 64 - 2 * (NORM ? 2 * NS + 1 : (NS > 0 ? 2 * NS : 1)); }
+template <int NS> constexpr int down_own() { return DownPipe<double, NS>::OWN; }
+template <int NS, bool NORM> constexpr int up_own() { return UpPipe<double, NS, NORM>::OWN; }
 
-inline dim3 stream_grid(int nx, int ny, int own, int ty, int nsys) {
-    const int tiles = (nx + own - 1) / own;
-    return dim3((tiles + NT / 64 - 1) / (NT / 64), (ny + ty - 1) / ty, nsys);
+// Waves of one kernel that are resident on the whole device at once.
+int resident_waves(const void* kernel) {
+    static std::mutex mu;
+    static std::map<std::pair<const void*, int>, int> cache;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) dev = 0;
+    std::lock_guard<std::mutex> lock(mu);
+    auto it = cache.find({kernel, dev});
+    if (it != cache.end()) return it->second;
+    int blocks = 0, cus = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, kernel, NT, 0) != hipSuccess || blocks < 1) blocks = 1;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1) cus = 1;
+    const int w = blocks * cus * (NT / 64);
+    cache[{kernel, dev}] = w;
+    return w;
 }
 
-template <typename T> dim3 stream_seg_grid(SegTable<T>& tab, const int* nsys, int own, int ty) {
-    int z = 0, gx = 1, gy = 1;
+// Cut of one segment's strips into runs of rows, one run per wave.  The
+// number of runs per strip p minimises (rounds of resident waves) x (rows per
+// run + the pipeline's start-up rows), with runs of at least
+// max(rmin, MIN_RUN) rows.
+constexpr int MIN_RUN = 16;
+struct RunGeom {
+    int strips, pieces, rows, waves;
+};
+RunGeom run_geom(int nx, int ny, int nsys, int own, int halo_rows, int rmin, int resident) {
+    RunGeom g;
+    g.strips = (nx + own - 1) / own;
+    const int64_t runs1 = (int64_t)nsys * g.strips;
+    const int pmax = std::max(1, ny / std::max(rmin, MIN_RUN));
+    int best = 1;
+    int64_t best_cost = -1;
+    for (int p = 1; p <= pmax; ++p) {
+        const int rows = (ny + p - 1) / p;
+        const int64_t rounds = (runs1 * p + resident - 1) / resident;
+        const int64_t cost = rounds * (rows + halo_rows);
+        if (best_cost < 0 || cost < best_cost) {
+            best_cost = cost;
+            best = p;
+        }
+    }
+    g.rows = (ny + best - 1) / best;
+    g.pieces = (ny + g.rows - 1) / g.rows;
+    g.waves = (int)(runs1 * g.pieces);
+    return g;
+}
+
+template <typename T>
+dim3 stream_seg_grid(SegTable<T>& tab, const int* nsys, int own, int halo_rows, int rmin, int resident) {
+    int w = 0;
     for (int q = 0; q < tab.n; ++q) {
         LevelSeg<T>& S = tab.s[q];
-        const dim3 g = stream_grid(S.lf.nx, S.lf.ny, own, ty, 1);
-        S.z0 = z;
-        S.gx = (int)g.x;
-        S.gy = (int)g.y;
-        gx = max(gx, S.gx);
-        gy = max(gy, S.gy);
-        z += nsys[q];
+        const RunGeom g = run_geom(S.lf.nx, S.lf.ny, nsys[q], own, halo_rows, rmin, resident);
+        S.z0 = 0;
+        S.nsys = nsys[q];
+        S.strips = g.strips;
+        S.rows = g.rows;
+        S.pieces = g.pieces;
+        S.waves = g.waves;
+        S.w0 = w;
+        w += g.waves;
     }
-    return dim3(gx, gy, z);
+    return dim3((w + NT / 64 - 1) / (NT / 64));
+}
+
+template <typename T, int NS> void down_go(SegTable<T> tab, const int* nsys, int rmin, hipStream_t st) {
+    const void* k = (const void*)&k_down<T, NS>;
+    const dim3 g = stream_seg_grid(tab, nsys, down_own<NS>(), 4 * NS + 9, rmin, resident_waves(k));
+    if (g.x == 0) return;
+    hipLaunchKernelGGL((k_down<T, NS>), g, dim3(NT), 0, st, tab);
+}
+template <typename T, int NS, bool NORM> void up_go(SegTable<T> tab, const int* nsys, int rmin, hipStream_t st) {
+    const void* k = (const void*)&k_up<T, NS, NORM>;
+    const dim3 g = stream_seg_grid(tab, nsys, up_own<NS, NORM>(), 4 * NS + 7, rmin, resident_waves(k));
+    if (g.x == 0) return;
+    hipLaunchKernelGGL((k_up<T, NS, NORM>), g, dim3(NT), 0, st, tab);
 }
 
 }  // namespace
 
-int stream_tiles(int nx, int ny, int nu, bool norm, int ty) {
-    int own = 0;
+template <typename T> int stream_tiles(int nx, int ny, int nsys, int nu, int rmin) {
+    const void* k;
+    int own;
     switch (nu) {
-        case 0: own = norm ? up_own<0, true>() : up_own<0, false>(); break;
-        case 1: own = norm ? up_own<1, true>() : up_own<1, false>(); break;
-        default: own = norm ? up_own<2, true>() : up_own<2, false>(); break;
+        case 0: k = (const void*)&k_up<T, 0, true>; own = up_own<0, true>(); break;
+        case 1: k = (const void*)&k_up<T, 1, true>; own = up_own<1, true>(); break;
+        default: k = (const void*)&k_up<T, 2, true>; own = up_own<2, true>(); break;
     }
-    const dim3 g = stream_grid(nx, ny, own, ty, 1);
-    return (int)(g.x * g.y);
+    const RunGeom g = run_geom(nx, ny, nsys, own, 4 * (nu < 2 ? nu : 2) + 7, rmin, resident_waves(k));
+    return g.strips * g.pieces;
 }
+template int stream_tiles<double>(int, int, int, int, int);
+// Occupancy queries of every streaming kernel up front (not inside a stream
+// capture).
+void stream_prepare() {
+#define VMG_PREP(T)                                                                                   \
+    resident_waves((const void*)&k_down<T, 0>), resident_waves((const void*)&k_down<T, 1>),           \
+        resident_waves((const void*)&k_down<T, 2>), resident_waves((const void*)&k_up<T, 0, true>),    \
+        resident_waves((const void*)&k_up<T, 1, true>), resident_waves((const void*)&k_up<T, 2, true>), \
+        resident_waves((const void*)&k_up<T, 0, false>), resident_waves((const void*)&k_up<T, 1, false>), \
+        resident_waves((const void*)&k_up<T, 2, false>)
+    VMG_PREP(double);
+    VMG_PREP(float);
+#undef VMG_PREP
+}
+
+int stream_tiles_max(int nx, int ny, int nu) {
+    const int own = nu == 0 ? up_own<0, true>() : (nu == 1 ? up_own<1, true>() : up_own<2, true>());
+    return ((nx + own - 1) / own) * std::max(1, ny / MIN_RUN);
+}
+template int stream_tiles<float>(int, int, int, int, int);
 
 template <typename T> void launch_down(SegTable<T> tab, const int* nsys, int nu, int ty, hipStream_t st) {
     switch (nu) {
-        case 0: {
-            const dim3 g = stream_seg_grid(tab, nsys, down_own<0>(), ty);
-            hipLaunchKernelGGL((k_down<T, 0>), g, dim3(NT), 0, st, tab, ty);
-            break;
-        }
-        case 1: {
-            const dim3 g = stream_seg_grid(tab, nsys, down_own<1>(), ty);
-            hipLaunchKernelGGL((k_down<T, 1>), g, dim3(NT), 0, st, tab, ty);
-            break;
-        }
-        default: {
-            const dim3 g = stream_seg_grid(tab, nsys, down_own<2>(), ty);
-            hipLaunchKernelGGL((k_down<T, 2>), g, dim3(NT), 0, st, tab, ty);
-            break;
-        }
+        case 0: down_go<T, 0>(tab, nsys, ty, st); break;
+        case 1: down_go<T, 1>(tab, nsys, ty, st); break;
+        default: down_go<T, 2>(tab, nsys, ty, st); break;
     }
 }
 
 template <typename T> void launch_up(SegTable<T> tab, const int* nsys, int nu, bool norm, int ty, hipStream_t st) {
-#define VMG_UP(NSV, NORMV)                                                          \
-    do {                                                                            \
-        const dim3 g = stream_seg_grid(tab, nsys, up_own<NSV, NORMV>(), ty);        \
-        hipLaunchKernelGGL((k_up<T, NSV, NORMV>), g, dim3(NT), 0, st, tab, ty);     \
-    } while (0)
     switch (nu) {
-        case 0: if (norm) VMG_UP(0, true); else VMG_UP(0, false); break;
-        case 1: if (norm) VMG_UP(1, true); else VMG_UP(1, false); break;
-        default: if (norm) VMG_UP(2, true); else VMG_UP(2, false); break;
+        case 0: if (norm) up_go<T, 0, true>(tab, nsys, ty, st); else up_go<T, 0, false>(tab, nsys, ty, st); break;
+        case 1: if (norm) up_go<T, 1, true>(tab, nsys, ty, st); else up_go<T, 1, false>(tab, nsys, ty, st); break;
+        default: if (norm) up_go<T, 2, true>(tab, nsys, ty, st); else up_go<T, 2, false>(tab, nsys, ty, st); break;
     }
-#undef VMG_UP
 }
 
 template <typename T> void launch_fill_zero(cplx<T>* x, LevelView lv, int nsys, hipStream_t st) {
