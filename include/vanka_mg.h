@@ -187,6 +187,7 @@ int vanka_mg_shift_gradient(vmg_handle* h, const double* Z, const double* G, dou
  *   transpose = 0:  R^m = F^m - ((U^m - U^{m-1})/tau + A U^m),  U^{-1} = 0
  *   transpose = 1:  R^m = F^m - ((U^m - U^{m+1})/tau + A U^m),  U^{n} = 0
  * for the handle's single grid (n = number of systems, m = nx*ny).
+ * With F == NULL the operator itself is applied: R = K U (K^T U).
  *   U, F, R  device, complex128 n x m; R may alias F.
  *   norm2    host, NULL or receives ||R||_2^2 (synchronises the stream).
  * Returns VMG_OK, VMG_INVALID_ARG, VMG_HIP_ERROR.
@@ -216,6 +217,28 @@ int paradiag_heat_residual(vmg_handle* h, double tau, const double* U, const dou
 int paradiag_heat_solve(vmg_handle* h, const double* V, const double* Vinv, double tau, const double* F,
                         double* U, double tol, double inner_tol, int32_t transpose, int32_t replay,
                         int32_t max_outer, int32_t* outer, double* relres, void* hip_stream);
+
+/*
+ * The same all-at-once heat system K u = f (K^T w = f with transpose) solved
+ * by a Krylov method instead of the stationary iteration: restarted flexible
+ * GMRES, right-preconditioned by the alpha-circulant ParaDIAG step P^{-1}
+ * (the circulant-type preconditioner of Sec. 1; every P^{-1} is applied by
+ * paradiag_apply with inner tolerance inner_tol).  From u = 0; a cycle of at
+ * most `restart` steps builds v_1 = r/||r||, z_j = P^{-1} v_j, the modified
+ * Gram-Schmidt Arnoldi vector of K z_j, and ends with u += sum_j y_j z_j,
+ * y minimising the Hessenberg least-squares residual (Givens rotations on the
+ * host).  Stops when ||f - K u|| <= tol ||f|| or after max_iter steps in all.
+ *   F, U     device, complex128 n x m; U may not alias F.
+ *   restart  1..200; the library keeps 2 restart + 1 vectors of n x m.
+ *   iters    host, NULL or receives the number of preconditioned steps.
+ *   relres   host, NULL or receives the final ||f - K u|| / ||f||.
+ * Synchronises the stream once per step.  Returns VMG_OK,
+ * VMG_NOT_CONVERGED (max_iter reached), VMG_INVALID_ARG, VMG_OOM,
+ * VMG_HIP_ERROR, VMG_NAN_DETECTED.
+ */
+int paradiag_heat_gmres(vmg_handle* h, const double* V, const double* Vinv, double tau, const double* F,
+                        double* U, double tol, double inner_tol, int32_t transpose, int32_t restart,
+                        int32_t max_iter, int32_t* iters, double* relres, void* hip_stream);
 
 /*
  * The time transform of eq. (1) on its own: out = (M kron I_m) in, i.e.

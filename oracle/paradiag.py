@@ -5,10 +5,11 @@ The all-at-once system of eq. (1) is (B kron I_h + I_t kron A) u = f with the
 n time slices of u stacked as the rows of an (n, ny, nx) array.  With
 B = V D V^{-1} it is solved in three steps:
   G = (V^{-1} kron I_h) F,   z_j = (A + lambda_j I)^{-1} g_j,   U = (V kron I_h) Z.
-The heat workload uses the alpha-circulant C_alpha as a preconditioner inside
-the stationary iteration u <- u + P_alpha^{-1}(f - K u) with K the
-backward-Euler all-at-once operator (the circulant-type preconditioner that
-Sec. 1 mentions).
+The heat workload uses the alpha-circulant C_alpha as a preconditioner (the
+circulant-type preconditioner that Sec. 1 mentions) for K, the
+backward-Euler all-at-once operator, inside either the stationary iteration
+u <- u + P_alpha^{-1}(f - K u) or a Krylov method (flexible GMRES with right
+preconditioning; the paper names the preconditioner, not the outer solver).
 """
 import numpy as np
 
@@ -91,6 +92,63 @@ def paradiag_heat_solve(f, tau, h, lam, V, Vinv, tol=1e-10, inner_tol=1e-12, max
         u = u + time_transform(Vl, Z)
     r = f - Kop(u, tau, h)
     return u, max_outer, np.linalg.norm(r) / fn
+
+
+def paradiag_heat_fgmres(f, tau, h, lam, V, Vinv, tol=1e-10, inner_tol=1e-12, restart=10, max_iter=100,
+                         transpose=False, solver="multigrid", **mg_opts):
+    """Restarted flexible GMRES on K u = f (K^T w = f with transpose=True),
+    right-preconditioned by the alpha-circulant ParaDIAG step P_alpha^{-1},
+    from u = 0.
+
+    Each restart cycle starts from r = f - K u, beta = ||r||, v_1 = r / beta.
+    Step j applies the preconditioner z_j = P^{-1} v_j and the operator
+    w = K z_j, orthogonalises w against v_1..v_j by modified Gram-Schmidt
+    (h_ij = <v_i, w>, w <- w - h_ij v_i), sets h_{j+1,j} = ||w|| and
+    v_{j+1} = w / h_{j+1,j}.  The coefficients y minimise
+    ||beta e_1 - H_j y|| (a dense least-squares solve); the cycle ends when
+    that minimum is at most tol ||f||, after `restart` steps, or at max_iter
+    steps in total, and then u <- u + sum_i y_i z_i.  The loop stops when the
+    true residual ||f - K u|| <= tol ||f||.
+    Returns (u, total_steps, relres, history of the least-squares residuals
+    relative to ||f||)."""
+    f = f.astype(np.complex128)
+    u = np.zeros_like(f)
+    fn = np.linalg.norm(f)
+    Kop = backward_euler_apply_transpose if transpose else backward_euler_apply
+    Vl, Vr = (Vinv.T, V.T) if transpose else (V, Vinv)
+
+    def precond(v):
+        G = time_transform(Vr, v)
+        return time_transform(Vl, shifted_block_solve(G, lam, h, inner_tol, solver, **mg_opts))
+
+    total, hist = 0, []
+    while True:
+        r = f - Kop(u, tau, h)
+        beta = np.linalg.norm(r)
+        if fn == 0.0 or beta <= tol * fn or total >= max_iter:
+            return u, total, (beta / fn if fn > 0 else 0.0), hist
+        Vb = [r / beta]
+        Zb = []
+        H = np.zeros((restart + 1, restart), dtype=np.complex128)
+        y = None
+        for j in range(restart):
+            Zb.append(precond(Vb[j]))
+            w = Kop(Zb[j], tau, h)
+            for i in range(j + 1):
+                H[i, j] = np.vdot(Vb[i], w)
+                w = w - H[i, j] * Vb[i]
+            H[j + 1, j] = np.linalg.norm(w)
+            Vb.append(w / H[j + 1, j] if H[j + 1, j] != 0 else w)
+            total += 1
+            e1 = np.zeros(j + 2, dtype=np.complex128)
+            e1[0] = beta
+            y = np.linalg.lstsq(H[:j + 2, :j + 1], e1, rcond=None)[0]
+            res = np.linalg.norm(e1 - H[:j + 2, :j + 1] @ y) / fn
+            hist.append(res)
+            if res <= tol or total >= max_iter or H[j + 1, j] == 0:
+                break
+        for i in range(len(y)):
+            u = u + y[i] * Zb[i]
 
 
 def heat_mode_coefficients(n, nx, tau):

@@ -28,7 +28,7 @@ KERNEL_CLASSES = ["sweep", "restrict", "prolong", "norm", "coarse", "pack", "tra
 NUM_KCLASS = len(KERNEL_CLASSES)
 
 EXPORTED = ["vanka_mg_default_opts", "vanka_mg_setup", "vanka_mg_solve", "paradiag_apply",
-            "vanka_mg_shift_gradient", "paradiag_heat_residual", "paradiag_heat_solve",
+            "vanka_mg_shift_gradient", "paradiag_heat_residual", "paradiag_heat_solve", "paradiag_heat_gmres",
             "paradiag_transform", "vanka_mg_apply_op", "vanka_mg_set_timing", "vanka_mg_kernel_stats",
             "vanka_mg_level_stats", "vanka_mg_autotune", "vanka_mg_schedule", "vanka_mg_set_omega",
             "vanka_mg_levels", "vanka_mg_last_stats", "vanka_mg_destroy", "vanka_mg_error_string"]
@@ -70,6 +70,7 @@ def load():
     lib.vanka_mg_shift_gradient.argtypes = [vp, vp, vp, vp, vp]
     lib.paradiag_heat_residual.argtypes = [vp, dbl, vp, vp, vp, i32, pdbl, vp]
     lib.paradiag_heat_solve.argtypes = [vp, vp, vp, dbl, vp, vp, dbl, dbl, i32, i32, i32, pi32, pdbl, vp]
+    lib.paradiag_heat_gmres.argtypes = [vp, vp, vp, dbl, vp, vp, dbl, dbl, i32, i32, i32, pi32, pdbl, vp]
     lib.paradiag_transform.argtypes = [i32, i64, vp, i32, vp, vp, vp]
     lib.vanka_mg_apply_op.argtypes = [vp, i32, i32, i32, vp, vp, vp, vp]
     lib.vanka_mg_set_timing.argtypes = [vp, i32, i32]

@@ -87,6 +87,21 @@ class HeatProblem:
         self.last = {"outer": outer.value, "relres": rel.value, "status": status}
         return u
 
+    def solve_gmres(self, f, transpose=False, restart=10, max_iter=100):
+        """u with K u = f (K^T u = f with transpose) by flexible GMRES,
+        right-preconditioned by the same ParaDIAG step."""
+        self.solver._check_vec(f, self.solver.total, "f")
+        u = torch.empty_like(f)
+        its = ctypes.c_int32(0)
+        rel = ctypes.c_double(0.0)
+        code = self.solver.lib.paradiag_heat_gmres(
+            self.solver.handle, _ptr(self.V), _ptr(self.Vinv), float(self.tau), _ptr(f), _ptr(u), float(self.tol),
+            float(self.inner_tol), int(bool(transpose)), int(restart), int(max_iter), ctypes.byref(its),
+            ctypes.byref(rel), _stream())
+        status = _lib.check(code, "paradiag_heat_gmres")
+        self.last = {"outer": its.value, "relres": rel.value, "status": status}
+        return u
+
     def residual(self, u, f, transpose=False):
         _, nrm = self.solver.heat_residual(self.tau, u, f, transpose=transpose)
         return nrm

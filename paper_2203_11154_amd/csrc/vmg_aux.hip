@@ -1,6 +1,7 @@
 // Kernels around the shifted solves: the shift sensitivity reduction used by
-// the adjoint, and the backward-Euler all-at-once heat residual that the
-// alpha-circulant ParaDIAG preconditioner is iterated on.  All reductions are
+// the adjoint, the backward-Euler all-at-once heat operator and residual that
+// the alpha-circulant ParaDIAG preconditioner is iterated on, and the vector
+// operations of the Krylov (flexible GMRES) outer solver.  All reductions are
 // two-stage with a fixed summation order.
 #include "vmg_internal.h"
 
@@ -61,7 +62,8 @@ __global__ __launch_bounds__(NT) void k_cdot_finalize(const double2* __restrict_
 }
 
 // R^m = F^m - ((U^m - U^{m-1})/tau + A U^m) (or U^{m+1} for the transpose);
-// block (tile of CHUNK nodes, slice m); partial |R|^2 per block.
+// with F == NULL, R^m = (K U)^m instead; block (tile of CHUNK nodes, slice m);
+// partial |R|^2 per block.
 __global__ __launch_bounds__(NT) void k_heat_residual(const double2* __restrict__ U, const double2* F,
                                                       double2* R, int n, int nx, int ny, double h, double tau,
                                                       int transpose, int ntiles, double* __restrict__ partial) {
@@ -85,10 +87,15 @@ __global__ __launch_bounds__(NT) void k_heat_residual(const double2* __restrict_
         if (k < ny - 1) { s.x += u[p + nx].x; s.y += u[p + nx].y; }
         double2 prev = make_double2(0.0, 0.0);
         if (has_nb) prev = U[(int64_t)nb * m + p];
-        const double2 f = F[(int64_t)sl * m + p];
         double2 r;
-        r.x = f.x - ((c.x - prev.x) * itau + (4.0 * c.x - s.x) * ih2);
-        r.y = f.y - ((c.y - prev.y) * itau + (4.0 * c.y - s.y) * ih2);
+        if (F) {
+            const double2 f = F[(int64_t)sl * m + p];
+            r.x = f.x - ((c.x - prev.x) * itau + (4.0 * c.x - s.x) * ih2);
+            r.y = f.y - ((c.y - prev.y) * itau + (4.0 * c.y - s.y) * ih2);
+        } else {
+            r.x = (c.x - prev.x) * itau + (4.0 * c.x - s.x) * ih2;
+            r.y = (c.y - prev.y) * itau + (4.0 * c.y - s.y) * ih2;
+        }
         R[(int64_t)sl * m + p] = r;
         acc += r.x * r.x + r.y * r.y;
     }
@@ -105,7 +112,54 @@ __global__ __launch_bounds__(NT) void k_sum_all(const double* __restrict__ parti
     if (threadIdx.x == 0) out[0] = acc;
 }
 
+// y += sign * a * x with a = *coef (device) or the value `a` when coef is NULL
+__global__ __launch_bounds__(NT) void k_zaxpy(double2* __restrict__ y, const double2* __restrict__ x, int64_t N,
+                                              const double2* coef, double sign, double2 a) {
+    if (coef) a = *coef;
+    a.x *= sign;
+    a.y *= sign;
+    for (int64_t p = (int64_t)blockIdx.x * NT + threadIdx.x; p < N; p += (int64_t)gridDim.x * NT) {
+        const double2 v = x[p];
+        double2 w = y[p];
+        w.x += a.x * v.x - a.y * v.y;
+        w.y += a.x * v.y + a.y * v.x;
+        y[p] = w;
+    }
+}
+
+// y *= 1 / sqrt(nrm2->x) (y unchanged when the norm is zero), or by `s` when
+// nrm2 is NULL
+__global__ __launch_bounds__(NT) void k_zscale(double2* __restrict__ y, int64_t N, const double2* nrm2, double s) {
+    if (nrm2) s = nrm2->x > 0.0 ? 1.0 / sqrt(nrm2->x) : 1.0;
+    for (int64_t p = (int64_t)blockIdx.x * NT + threadIdx.x; p < N; p += (int64_t)gridDim.x * NT) {
+        double2 w = y[p];
+        w.x *= s;
+        w.y *= s;
+        y[p] = w;
+    }
+}
+
+inline int stream_blocks(int64_t N) {
+    const int64_t b = (N + NT - 1) / NT;
+    return (int)(b < 8192 ? (b > 0 ? b : 1) : 8192);
+}
+
 }  // namespace
+
+void launch_zdot(const double2* a, const double2* b, int64_t N, double2* partial, double2* out, hipStream_t st) {
+    const int nt = aux_tiles(N);
+    hipLaunchKernelGGL(k_cdot_partial, dim3(nt, 1), dim3(NT), 0, st, a, b, N, nt, partial);
+    hipLaunchKernelGGL(k_cdot_finalize, dim3(1), dim3(NT), 0, st, partial, nt, 1.0, out);
+}
+
+void launch_zaxpy(double2* y, const double2* x, int64_t N, const double2* coef, double sign, double2 a,
+                  hipStream_t st) {
+    hipLaunchKernelGGL(k_zaxpy, dim3(stream_blocks(N)), dim3(NT), 0, st, y, x, N, coef, sign, a);
+}
+
+void launch_zscale(double2* y, int64_t N, const double2* nrm2, double s, hipStream_t st) {
+    hipLaunchKernelGGL(k_zscale, dim3(stream_blocks(N)), dim3(NT), 0, st, y, N, nrm2, s);
+}
 
 int aux_tiles(int64_t m) { return (int)((m + CHUNK - 1) / CHUNK); }
 

@@ -160,9 +160,19 @@ template <typename T> void launch_fill_zero(cplx<T>* x, LevelView lv, int nsys, 
 int aux_tiles(int64_t m);
 void launch_shift_gradient(const double2* z, const double2* g, int64_t m, int nsys, double2* partial,
                            double2* out, hipStream_t st);
-// Backward-Euler all-at-once heat residual (n slices of nx x ny); partial
-// holds n * aux_tiles(nx * ny) doubles; *out_norm2 (device) = ||R||^2.
+// Backward-Euler all-at-once heat residual R = F - K U (n slices of nx x ny),
+// or R = K U when F is NULL; partial holds n * aux_tiles(nx * ny) doubles;
+// *out_norm2 (device) = ||R||^2.
 void launch_heat_residual(const double2* U, const double2* F, double2* R, int n, int nx, int ny, double h,
                           double tau, int transpose, double* partial, double* out_norm2, hipStream_t st);
+
+// Krylov vector operations over N complex entries (all on `st`):
+//   zdot:  *out = sum conj(a) b (partial holds aux_tiles(N) entries)
+//   zaxpy: y += sign * c * x, c = *coef (device) or the value a if coef is NULL
+//   zscale: y *= 1/sqrt(nrm2->x) (device norm^2), or by s if nrm2 is NULL
+void launch_zdot(const double2* a, const double2* b, int64_t N, double2* partial, double2* out, hipStream_t st);
+void launch_zaxpy(double2* y, const double2* x, int64_t N, const double2* coef, double sign, double2 a,
+                  hipStream_t st);
+void launch_zscale(double2* y, int64_t N, const double2* nrm2, double s, hipStream_t st);
 
 }  // namespace vmg

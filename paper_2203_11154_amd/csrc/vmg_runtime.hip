@@ -120,6 +120,11 @@ struct vmg_handle {
     int64_t gbuf_elems = 0;
     double2* cdot_partial = nullptr;   // shift-gradient partial sums
     double2* rbuf = nullptr;           // heat residual of paradiag_heat_solve
+    double2* krylov = nullptr;         // flexible GMRES bases: restart+1 v's, then restart z's
+    int krylov_restart = 0;
+    double2* zdot_partial = nullptr;   // Krylov inner-product partial sums
+    double2* hcol = nullptr;           // one Hessenberg column (device)
+    double2* h_hcol = nullptr;         // and its pinned host copy
     std::vector<std::vector<int32_t>> heat_record[2];  // inner counts per outer step [transpose]
     double* heat_partial = nullptr;    // heat-residual partial sums (+1: the total)
     std::vector<void*> allocations;
@@ -1096,6 +1101,7 @@ int vanka_mg_destroy(vmg_handle* H) {
     for (void* p : H->allocations) (void)hipFree(p);
     if (H->h_int) (void)hipHostFree(H->h_int);
     if (H->h_dbl) (void)hipHostFree(H->h_dbl);
+    if (H->h_hcol) (void)hipHostFree(H->h_hcol);
     (void)hipSetDevice(prev);
     delete H;
     return VMG_OK;
@@ -1484,6 +1490,132 @@ extern "C" int paradiag_heat_solve(vmg_handle* H, const double* V, const double*
     return (!replay && rel > tol) ? VMG_NOT_CONVERGED : VMG_OK;
 }
 
+// Restarted flexible GMRES on the backward-Euler all-at-once system (K^T with
+// transpose), right-preconditioned by the alpha-circulant ParaDIAG step; the
+// same steps as the oracle's description: modified Gram-Schmidt Arnoldi on
+// the device, the small least-squares problem by Givens rotations on the host.
+extern "C" int paradiag_heat_gmres(vmg_handle* H, const double* V, const double* Vinv, double tau, const double* F,
+                                   double* U, double tol, double inner_tol, int32_t transpose, int32_t restart,
+                                   int32_t max_iter, int32_t* iters, double* relres, void* hip_stream) {
+    if (!H || !V || !Vinv || !F || !U || F == U || !(tau > 0.0) || !(tol > 0.0) || !(inner_tol > 0.0) ||
+        restart < 1 || restart > 200 || max_iter < 1)
+        return VMG_INVALID_ARG;
+    if (H->groups.size() != 1 || H->S > 512) return VMG_INVALID_ARG;
+    hipStream_t st = (hipStream_t)hip_stream;
+    Group& g = H->groups[0];
+    const int n = H->S;
+    const int64_t m = (int64_t)g.nx * g.ny;
+    const int64_t N = (int64_t)n * m;
+    const int tr = transpose ? 1 : 0;
+    if (H->krylov_restart < restart) {
+        if (H->krylov) {
+            (void)hipStreamSynchronize(st);
+            (void)hipFree(H->krylov);
+            H->allocations.erase(std::remove(H->allocations.begin(), H->allocations.end(), (void*)H->krylov),
+                                 H->allocations.end());
+            H->krylov = nullptr;
+            H->krylov_restart = 0;
+        }
+        int rc = dev_malloc(H, (void**)&H->krylov, sizeof(double2) * (size_t)(2 * restart + 1) * (size_t)N);
+        if (rc) return rc;
+        H->krylov_restart = restart;
+    }
+    if (!H->zdot_partial) {
+        int rc = dev_malloc(H, (void**)&H->zdot_partial, sizeof(double2) * (size_t)aux_tiles(N));
+        if (rc) return rc;
+        rc = dev_malloc(H, (void**)&H->hcol, sizeof(double2) * 202);
+        if (rc) return rc;
+        if (hipHostMalloc((void**)&H->h_hcol, sizeof(double2) * 202) != hipSuccess) return VMG_OOM;
+    }
+    const int R = H->krylov_restart;
+    auto vb = [&](int i) { return H->krylov + (size_t)i * N; };
+    auto zb = [&](int i) { return H->krylov + (size_t)(R + 1 + i) * N; };
+    double2* Ud = reinterpret_cast<double2*>(U);
+    const double2* Fd = reinterpret_cast<const double2*>(F);
+    const double2 zero = make_double2(0.0, 0.0);
+    VMG_HIP(hipMemsetAsync(U, 0, sizeof(double2) * (size_t)N, st));
+    // ||f||^2
+    launch_zdot(Fd, Fd, N, H->zdot_partial, H->hcol, st);
+    VMG_HIP(hipMemcpyAsync(H->h_hcol, H->hcol, sizeof(double2), hipMemcpyDeviceToHost, st));
+    VMG_HIP(hipStreamSynchronize(st));
+    const double fn = std::sqrt(H->h_hcol[0].x);
+    int total = 0;
+    double rel = 0.0;
+    int rc = VMG_OK;
+    using cd = std::complex<double>;
+    std::vector<cd> Hm((size_t)(R + 1) * R), gv(R + 1), cs(R), sn(R), y(R);
+    auto Hat = [&](int i, int j) -> cd& { return Hm[(size_t)i * R + j]; };
+    for (;;) {
+        // r = f - K u into v_0, beta = ||r||
+        double rr = 0.0;
+        rc = paradiag_heat_residual(H, tau, U, F, reinterpret_cast<double*>(vb(0)), tr, &rr, hip_stream);
+        if (rc) return rc;
+        if (!(rr == rr)) return VMG_NAN_DETECTED;
+        const double beta = std::sqrt(rr);
+        rel = fn > 0.0 ? beta / fn : 0.0;
+        if (fn == 0.0 || rel <= tol || total >= max_iter) break;
+        launch_zscale(vb(0), N, nullptr, 1.0 / beta, st);
+        std::fill(gv.begin(), gv.end(), cd(0.0));
+        gv[0] = beta;
+        int k = 0;  // Arnoldi steps of this cycle
+        for (int j = 0; j < R; ++j) {
+            // z_j = P^{-1} v_j, w = K z_j (in v_{j+1})
+            rc = paradiag_core(H, V, Vinv, reinterpret_cast<const double*>(vb(j)), reinterpret_cast<double*>(zb(j)),
+                               inner_tol, tr, nullptr, 0, st);
+            if (rc < 0) return rc;
+            rc = paradiag_heat_residual(H, tau, reinterpret_cast<const double*>(zb(j)), nullptr,
+                                        reinterpret_cast<double*>(vb(j + 1)), tr, nullptr, hip_stream);
+            if (rc) return rc;
+            for (int i = 0; i <= j; ++i) {
+                launch_zdot(vb(i), vb(j + 1), N, H->zdot_partial, H->hcol + i, st);
+                launch_zaxpy(vb(j + 1), vb(i), N, H->hcol + i, -1.0, zero, st);
+            }
+            launch_zdot(vb(j + 1), vb(j + 1), N, H->zdot_partial, H->hcol + j + 1, st);
+            launch_zscale(vb(j + 1), N, H->hcol + j + 1, 1.0, st);
+            if (check_hip()) return VMG_HIP_ERROR;
+            VMG_HIP(hipMemcpyAsync(H->h_hcol, H->hcol, sizeof(double2) * (size_t)(j + 2), hipMemcpyDeviceToHost, st));
+            VMG_HIP(hipStreamSynchronize(st));
+            for (int i = 0; i <= j; ++i) Hat(i, j) = cd(H->h_hcol[i].x, H->h_hcol[i].y);
+            const double hn = std::sqrt(std::max(H->h_hcol[j + 1].x, 0.0));
+            Hat(j + 1, j) = hn;
+            // previous rotations, then the one that zeroes h_{j+1,j}
+            for (int i = 0; i < j; ++i) {
+                const cd a = Hat(i, j), b = Hat(i + 1, j);
+                Hat(i, j) = std::conj(cs[i]) * a + std::conj(sn[i]) * b;
+                Hat(i + 1, j) = -sn[i] * a + cs[i] * b;
+            }
+            const cd a = Hat(j, j), b = Hat(j + 1, j);
+            const double den = std::sqrt(std::norm(a) + std::norm(b));
+            if (den == 0.0) {
+                cs[j] = 1.0;
+                sn[j] = 0.0;
+            } else {
+                cs[j] = a / den;
+                sn[j] = b / den;
+            }
+            Hat(j, j) = std::conj(cs[j]) * a + std::conj(sn[j]) * b;
+            Hat(j + 1, j) = 0.0;
+            gv[j + 1] = -sn[j] * gv[j];
+            gv[j] = std::conj(cs[j]) * gv[j];
+            ++total;
+            k = j + 1;
+            if (!(hn == hn)) return VMG_NAN_DETECTED;
+            if (std::abs(gv[j + 1]) <= tol * fn || total >= max_iter || hn == 0.0) break;
+        }
+        // back substitution H[0:k, 0:k] y = g[0:k], then u += sum y_i z_i
+        for (int i = k - 1; i >= 0; --i) {
+            cd t = gv[i];
+            for (int l = i + 1; l < k; ++l) t -= Hat(i, l) * y[l];
+            y[i] = Hat(i, i) != 0.0 ? t / Hat(i, i) : 0.0;
+        }
+        for (int i = 0; i < k; ++i) launch_zaxpy(Ud, zb(i), N, nullptr, 1.0, make_double2(y[i].real(), y[i].imag()), st);
+        if (check_hip()) return VMG_HIP_ERROR;
+    }
+    if (iters) *iters = total;
+    if (relres) *relres = rel;
+    return rel > tol ? VMG_NOT_CONVERGED : VMG_OK;
+}
+
 extern "C" int vanka_mg_shift_gradient(vmg_handle* H, const double* Z, const double* G, double* grad_lambda,
                                        void* hip_stream) {
     if (!H || !Z || !G || !grad_lambda) return VMG_INVALID_ARG;
@@ -1508,7 +1640,7 @@ extern "C" int vanka_mg_shift_gradient(vmg_handle* H, const double* Z, const dou
 
 extern "C" int paradiag_heat_residual(vmg_handle* H, double tau, const double* U, const double* F, double* R,
                                       int32_t transpose, double* norm2, void* hip_stream) {
-    if (!H || !U || !F || !R || U == R || !(tau > 0.0) || H->groups.size() != 1) return VMG_INVALID_ARG;
+    if (!H || !U || !R || U == R || !(tau > 0.0) || H->groups.size() != 1) return VMG_INVALID_ARG;
     hipStream_t st = (hipStream_t)hip_stream;
     Group& g = H->groups[0];
     const int n = H->S;

@@ -193,12 +193,13 @@ class VankaMG:
 
     def heat_residual(self, tau, U, F, out=None, transpose=False, norm=True):
         """R = F - K U for the backward-Euler all-at-once operator K (K^T with
-        transpose); returns (R, ||R||^2 or None)."""
+        transpose), or R = K U when F is None; returns (R, ||R||^2 or None)."""
         self._check_vec(U, self.total, "U")
-        self._check_vec(F, self.total, "F")
-        R = torch.empty_like(F) if out is None else out
+        if F is not None:
+            self._check_vec(F, self.total, "F")
+        R = torch.empty_like(U) if out is None else out
         nrm = ctypes.c_double(0.0)
-        code = self.lib.paradiag_heat_residual(self.handle, float(tau), _ptr(U), _ptr(F), _ptr(R),
+        code = self.lib.paradiag_heat_residual(self.handle, float(tau), _ptr(U), None if F is None else _ptr(F), _ptr(R),
                                                int(bool(transpose)), ctypes.byref(nrm) if norm else None, _stream())
         _lib.check(code, "paradiag_heat_residual")
         return R, (nrm.value if norm else None)

@@ -118,3 +118,88 @@ def test_example_shift_generators_match_oracle_matrices():
     k = np.arange(m)
     closed = (1 - (100.0 ** (1 / m)) * np.exp(1j * np.pi * (2 * k + 1) / m)) * n
     np.testing.assert_allclose(sorted(inputs.example2_shifts(n), key=key), sorted(closed, key=key), rtol=1e-8)
+
+
+@pytest.mark.parametrize("solver", ["dst", "multigrid"])
+def test_fgmres_heat_closed_form(solver):
+    """Flexible GMRES with the alpha-circulant preconditioner reaches the
+    closed-form mode recurrence, in no more preconditioned steps than the
+    stationary iteration."""
+    n, nx = 16, 31
+    h, tau = 1.0 / (nx + 1), 1.0 / n
+    theta = inputs.heat_parameters(8)
+    f = pd.heat_source(theta, n, nx, tau)
+    lam, V, Vinv = spectral.alpha_circulant_eig(n, 0.01, tau)
+    u, it, rel, hist = pd.paradiag_heat_fgmres(f, tau, h, lam, V, Vinv, tol=1e-10, solver=solver)
+    _, it_rich, _ = pd.paradiag_heat_solve(f, tau, h, lam, V, Vinv, tol=1e-10, solver=solver)
+    assert rel <= 1e-10 and it <= it_rich
+    c = pd.heat_mode_coefficients(n, nx, tau)
+    ref = np.zeros((n, nx, nx))
+    for k, th in enumerate(theta, start=1):
+        ref += th * c[k - 1][:, None, None] * exact.sine_mode(k, k, nx, nx)[None]
+    assert np.linalg.norm(u - ref) <= 1e-8 * np.linalg.norm(ref)
+    # the least-squares residuals never grow within a cycle
+    assert all(b <= a * (1 + 1e-12) for a, b in zip(hist, hist[1:]))
+
+
+def test_fgmres_terminates_by_spectrum():
+    """K - P_alpha = (B - C_alpha) kron I has rank m, and on each eigenvector
+    of A the preconditioned operator K P^{-1} is the identity plus a rank-one
+    term, so its eigenvalues are 1 and one more per distinct eigenvalue of A:
+    with the exact preconditioner GMRES ends within (number of distinct
+    eigenvalues of A) + 1 steps (minimal polynomial), for any right-hand side
+    and alpha.  A wrong Arnoldi coefficient or update breaks this."""
+    nx, n, alpha = 3, 12, 0.5
+    h, tau = 1.0 / (nx + 1), 1.0 / n
+    mu = np.round(np.sort(exact.laplacian_eigenvalues(nx, nx, h).ravel()), 9)
+    distinct = len(np.unique(mu))
+    lam, V, Vinv = spectral.alpha_circulant_eig(n, alpha, tau)
+    rng = np.random.default_rng(11)
+    f = rng.standard_normal((n, nx, nx)) + 1j * rng.standard_normal((n, nx, nx))
+    for tr in (False, True):
+        u, it, rel, hist = pd.paradiag_heat_fgmres(f, tau, h, lam, V, Vinv, tol=1e-12, restart=30,
+                                                   transpose=tr, solver="dst")
+        assert rel <= 1e-12 and it <= distinct + 1
+        Kop = pd.backward_euler_apply_transpose if tr else pd.backward_euler_apply
+        assert np.linalg.norm(f - Kop(u, tau, h)) <= 1e-11 * np.linalg.norm(f)
+
+
+def test_fgmres_first_step_minimises_over_richardson_step():
+    """The first stationary step u_1 = P^{-1} f lies in span{z_1}, over which
+    GMRES minimises the residual: its first least-squares residual is no
+    larger than the stationary iteration's first residual."""
+    n, nx = 8, 15
+    h, tau = 1.0 / (nx + 1), 1.0 / n
+    lam, V, Vinv = spectral.alpha_circulant_eig(n, 0.2, tau)
+    rng = np.random.default_rng(12)
+    f = rng.standard_normal((n, nx, nx))
+    _, _, _, hist = pd.paradiag_heat_fgmres(f, tau, h, lam, V, Vinv, tol=1e-14, max_iter=1, solver="dst")
+    _, _, rel1 = pd.paradiag_heat_solve(f, tau, h, lam, V, Vinv, tol=1e-14, max_outer=1, solver="dst")
+    assert hist[0] <= rel1 * (1 + 1e-12)
+
+
+def test_fgmres_matches_brute_force_krylov_minimum():
+    """With a fixed preconditioner, k GMRES steps minimise ||f - K u|| over
+    u in P^{-1} span{f, (K P^{-1}) f, ..., (K P^{-1})^{k-1} f}.  The minimum
+    is computed here by brute force (explicit power vectors and a dense
+    least-squares solve) for complex data, and every least-squares residual
+    the oracle reports must equal it."""
+    nx, n, alpha = 3, 6, 0.5
+    h, tau = 1.0 / (nx + 1), 1.0 / n
+    lam, V, Vinv = spectral.alpha_circulant_eig(n, alpha, tau)
+    rng = np.random.default_rng(13)
+    f = rng.standard_normal((n, nx, nx)) + 1j * rng.standard_normal((n, nx, nx))
+    # dense K and P from their definitions (Kronecker forms of eq. (1))
+    A = exact.dense_laplacian(nx, nx, h)
+    Bbe = (np.eye(n) - np.eye(n, k=-1)) / tau
+    K = np.kron(Bbe, np.eye(nx * nx)) + np.kron(np.eye(n), A)
+    P = np.kron(spectral.alpha_circulant(n, alpha, tau), np.eye(nx * nx)) + np.kron(np.eye(n), A)
+    KPi = K @ np.linalg.inv(P)
+    fv = f.ravel()
+    for k in range(1, 5):
+        W = np.stack([np.linalg.matrix_power(KPi, j) @ fv for j in range(k)], axis=1)
+        c = np.linalg.lstsq(KPi @ W, fv, rcond=None)[0]
+        best = np.linalg.norm(fv - KPi @ W @ c) / np.linalg.norm(fv)
+        _, _, _, hist = pd.paradiag_heat_fgmres(f, tau, h, lam, V, Vinv, tol=1e-15, restart=10, max_iter=k,
+                                                solver="dst")
+        assert hist[k - 1] == pytest.approx(best, rel=1e-7, abs=1e-14)
