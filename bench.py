@@ -54,6 +54,7 @@ def parse():
     p.add_argument("--no-autotune", action="store_true", help="keep the size heuristic kernel schedule")
     p.add_argument("--no-batched", action="store_true", help="skip the uneven-grid batched leg")
     p.add_argument("--no-paper", action="store_true", help="skip the paper-protocol leg")
+    p.add_argument("--no-heat", action="store_true", help="skip the heat (differentiation) leg")
     p.add_argument("--copy-calibration", action="store_true",
                    help="run one plain 1 GiB device copy first (reference for hardware byte counters)")
     return p.parse_args()
@@ -124,6 +125,53 @@ def paper_protocol_leg(args, torch):
                      "ms_per_solve": round(1e3 * dt, 3), "systems_per_s": round(nt / dt, 1)}
         del s
     out["vanka_speedup_over_jacobi"] = round(out["jacobi"]["ms_per_solve"] / out["vanka"]["ms_per_solve"], 3)
+    return out
+
+
+def heat_leg(args, torch):
+    """Differentiation workload: backward-Euler heat all-at-once system on
+    511^2 with n = 128 steps, alpha-circulant ParaDIAG preconditioner
+    (alpha = 0.01), source sum_k theta_k sin(k pi x) sin(k pi y) e^{-t} with 16
+    parameters.  Times the forward solve by the stationary iteration and by
+    flexible GMRES, and one loss gradient (forward + adjoint solve)."""
+    from paper_2203_11154_amd import inputs
+    from paper_2203_11154_amd.autograd import HeatProblem, HeatSolve
+    nx, n, K = 511, 128, 16
+    tau = 1.0 / n
+    lam = inputs.alpha_circulant_shifts(n, 0.01)
+    V, Vinv = inputs.alpha_circulant_vectors(n, 0.01)
+    prob = HeatProblem(nx, n, tau, lam, V, Vinv, tol=args.tol, inner_tol=1e-11)
+    xs = np.arange(1, nx + 1) / (nx + 1)
+    basis = torch.from_numpy(np.stack([np.outer(np.sin(k * np.pi * xs), np.sin(k * np.pi * xs))
+                                       for k in range(1, K + 1)])).cuda()
+    tdecay = torch.from_numpy(np.exp(-tau * np.arange(1, n + 1))).cuda()
+
+    def source(theta):
+        return (tdecay[:, None, None] * torch.tensordot(theta, basis, dims=1)[None]).to(torch.complex128).reshape(-1)
+
+    theta = torch.from_numpy(inputs.heat_parameters(K)).cuda()
+    theta_star = torch.from_numpy(inputs.heat_parameters(K, seed=inputs.SEED_THETA_STAR)).cuda()
+    f = source(theta)
+    out = {"workload": "heat 511^2 x 128 steps, alpha-circulant ParaDIAG preconditioner, 16 source parameters"}
+    for name, run in (("stationary", lambda: prob.solve(f)), ("fgmres", lambda: prob.solve_gmres(f))):
+        run()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            run()
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / args.steps
+        out[name] = {"ms_per_solve": round(1e3 * dt, 3), "preconditioned_steps": prob.last["outer"],
+                     "relres": prob.last["relres"]}
+    ustar = HeatSolve.apply(source(theta_star), prob).real.detach()
+    th = theta.clone().requires_grad_(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    loss = ((HeatSolve.apply(source(th), prob).real - ustar) ** 2).sum()
+    loss.backward()
+    torch.cuda.synchronize()
+    out["gradient"] = {"ms_forward_adjoint": round(1e3 * (time.perf_counter() - t0), 3),
+                       "adjoint_relres": prob.last["relres"], "grad_norm": float(th.grad.norm())}
     return out
 
 
@@ -242,6 +290,8 @@ def main():
         out["batched_uneven"] = batched_leg(args, torch)
     if not args.no_paper:
         out["paper_protocol"] = paper_protocol_leg(args, torch)
+    if not args.no_heat:
+        out["heat"] = heat_leg(args, torch)
 
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(b, lam, h, tol, args.cpu_sample)

@@ -12,6 +12,8 @@
 
 #include "vmg_internal.h"
 
+#include <algorithm>
+
 namespace vmg {
 
 namespace {
@@ -162,12 +164,134 @@ __global__ __launch_bounds__(TN) void k_transform(int n, int64_t m, const double
     }
 }
 
+// Register-resident variant for 2n = 16 NW (n = 8, 16, 32, 64): a block of
+// NW waves keeps the whole expanded matrix in registers (wave w holds real
+// rows 16w..16w+15 for every K, KS = 2n/4 MFMA steps, n VGPRs a lane) and
+// walks over tiles of CT*16 grid nodes, so Mx is read once per block and the
+// input is streamed through a double-buffered LDS tile.  Same lane layout and
+// row permutation as k_transform.
+constexpr int RT_CT = 2;               // 16-node column sub-tiles per tile
+constexpr int RT_NODES = 16 * RT_CT;   // nodes per tile
+
+// (two blocks a CU: 4 waves a SIMD for NW = 8)
+template <int NW>
+__global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(4))) void k_transform_reg(int64_t m, const double* __restrict__ Mx,
+                                                            const double2* __restrict__ in, RowLayout li,
+                                                            double2* __restrict__ out, RowLayout lo, int accumulate,
+                                                            int64_t ntiles) {
+    constexpr int n = 8 * NW, n2 = 2 * n, KS = n2 / 4, TT = 64 * NW;
+    // per thread of the tile load: complex rows x nodes = n x RT_NODES values
+    constexpr int LD = n * RT_NODES / TT;  // = 4
+    static_assert(LD * TT == n * RT_NODES, "tile load split");
+    __shared__ double sB[2][n2][RT_NODES + 1];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int arow = 16 * wave + tile_row_perm(lane & 15);
+    double av[KS];
+#pragma unroll
+    for (int s = 0; s < KS; ++s) av[s] = Mx[(int64_t)arow * n2 + 4 * s + (lane >> 4)];
+
+    // thread t loads complex row t / (RT_NODES / LD), nodes LD * (t % ...) ..
+    const int lrow = threadIdx.x / (RT_NODES / LD);
+    const int lcol = (threadIdx.x % (RT_NODES / LD)) * LD;
+    double2 rb[LD];
+    auto fetch = [&](int64_t tile) {
+        const int64_t c0 = tile * RT_NODES + lcol;
+#pragma unroll
+        for (int q = 0; q < LD; ++q) {
+            const int64_t p = c0 + q;
+            rb[q] = p < m ? in[(int64_t)lrow * li.row + node_off(li, p)] : make_double2(0.0, 0.0);
+        }
+    };
+    auto stage = [&](int buf) {
+#pragma unroll
+        for (int q = 0; q < LD; ++q) {
+            sB[buf][2 * lrow][lcol + q] = rb[q].x;
+            sB[buf][2 * lrow + 1][lcol + q] = rb[q].y;
+        }
+    };
+    int64_t tile = blockIdx.x;
+    if (tile >= ntiles) return;  // uniform over the block
+    fetch(tile);
+    stage(0);
+    __syncthreads();
+    int buf = 0;
+    for (; tile < ntiles; tile += gridDim.x) {
+        const int64_t next = tile + gridDim.x;
+        if (next < ntiles) fetch(next);
+        dbl4 acc[RT_CT];
+#pragma unroll
+        for (int c = 0; c < RT_CT; ++c) acc[c] = dbl4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int s = 0; s < KS; ++s)
+#pragma unroll
+            for (int c = 0; c < RT_CT; ++c)
+                acc[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[s], sB[buf][4 * s + (lane >> 4)][16 * c + (lane & 15)],
+                                                              acc[c], 0, 0, 0);
+        // complex rows of this lane: cr and cr + 4
+        const int cr = 8 * wave + (lane >> 4);
+#pragma unroll
+        for (int c = 0; c < RT_CT; ++c) {
+            const int64_t p = tile * RT_NODES + 16 * c + (lane & 15);
+            if (p < m) {
+                const int64_t o = node_off(lo, p);
+                double2 v0 = make_double2(acc[c][0], acc[c][1]);
+                double2 v1 = make_double2(acc[c][2], acc[c][3]);
+                double2* q0 = out + (int64_t)cr * lo.row + o;
+                double2* q1 = out + (int64_t)(cr + 4) * lo.row + o;
+                if (accumulate) {
+                    const double2 w0 = *q0, w1 = *q1;
+                    v0.x += w0.x; v0.y += w0.y;
+                    v1.x += w1.x; v1.y += w1.y;
+                }
+                *q0 = v0;
+                *q1 = v1;
+            }
+        }
+        if (next < ntiles) {
+            stage(buf ^ 1);
+            __syncthreads();
+            buf ^= 1;
+        }
+    }
+}
+
+template <int NW> int reg_blocks() {
+    static int blocks = 0;
+    if (!blocks) {
+        int per_cu = 0, cus = 0, dev = 0;
+        if (hipGetDevice(&dev) != hipSuccess) dev = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)&k_transform_reg<NW>, 64 * NW, 0) !=
+                hipSuccess || per_cu < 1)
+            per_cu = 1;
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1) cus = 1;
+        blocks = per_cu * cus;
+    }
+    return blocks;
+}
+
+template <int NW>
+void go_reg(int64_t m, const double* Mx, const double2* in, RowLayout li, double2* out, RowLayout lo, int accumulate,
+            hipStream_t st) {
+    const int64_t ntiles = (m + RT_NODES - 1) / RT_NODES;
+    const int64_t blocks = std::min<int64_t>(ntiles, reg_blocks<NW>());
+    if (blocks < 1) return;
+    hipLaunchKernelGGL((k_transform_reg<NW>), dim3((unsigned)blocks), dim3(64 * NW), 0, st, m, Mx, in, li, out, lo,
+                       accumulate, ntiles);
+}
+
 }  // namespace
 
 void launch_transform(int n, int64_t m, const double2* M, int trans_conj, const double2* in, RowLayout li,
                       double2* out, RowLayout lo, double2* mbuf, hipStream_t st, int accumulate) {
     double* Mx = reinterpret_cast<double*>(mbuf);
     hipLaunchKernelGGL(k_expand, dim3((n * n + 255) / 256), dim3(256), 0, st, M, n, trans_conj, Mx);
+    switch (n) {
+        case 8: go_reg<1>(m, Mx, in, li, out, lo, accumulate, st); return;
+        case 16: go_reg<2>(m, Mx, in, li, out, lo, accumulate, st); return;
+        case 32: go_reg<4>(m, Mx, in, li, out, lo, accumulate, st); return;
+        case 64: go_reg<8>(m, Mx, in, li, out, lo, accumulate, st); return;
+        default: break;
+    }
     const dim3 grid((unsigned)((m + COLS - 1) / COLS), (unsigned)((2 * n + ROWS - 1) / ROWS));
     hipLaunchKernelGGL(k_transform, grid, dim3(TN), 0, st, n, m, Mx, in, li, out, lo, accumulate);
 }
