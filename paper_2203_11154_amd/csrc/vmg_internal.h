@@ -127,6 +127,36 @@ void launch_norm_finalize(const double* partial, int ntiles, int nsys, int sys_o
 
 void launch_fill_int(int* p, int value, int n, hipStream_t st);
 
+// Small levels in one workgroup per system (vmg_tail.hip): the cycle
+// MG(lt, x, b) of levels lt..coarsest with gamma visits, nu1/nu2 sweeps.
+// One TailSeg per grid (device table built once); a launch names up to
+// MAXSEG of them with their x buffers and system offsets.
+constexpr int MAXT = 6;  // levels of a tail, coarsest included
+template <typename T> struct TailSeg {
+    const cplx<T>* b;          // right-hand side of the first tail level (padded planes)
+    LevelView gv;              // its global geometry
+    LevelView lv[MAXT];        // every tail level (nx, ny used)
+    T s[MAXT];                 // 1 / h^2 per level
+    const Coef<T>* coef[MAXT]; // per level, per system
+    const cplx<T>* cinvT;      // coarsest inverses, transposed
+    const int* active;         // per system
+    int nc;                    // coarsest unknowns per system
+    int nl;                    // tail levels
+};
+template <typename T> struct TailLaunch {
+    int n;
+    int seg[MAXSEG];           // index into the TailSeg table
+    int z0[MAXSEG];            // first workgroup (system) of the entry
+    int xz[MAXSEG];            // first tail level starts from x = 0
+    cplx<T>* x[MAXSEG];        // x of the first tail level (read unless xz, written)
+};
+template <typename T>
+void launch_tail(const TailSeg<T>* segs, const TailLaunch<T>& tl, int total_sys, int64_t lds_bytes, int nu1, int nu2,
+                 int gamma, hipStream_t st);
+template <typename T> int64_t tail_lds_bytes(const LevelView* lv, int nl);
+int tail_max_lds();        // dynamic LDS a workgroup may use (enables it for the tail kernels)
+constexpr int TAIL_MAX_COARSE_NODES = 1024;  // nodes of every level below the first
+
 // Complex GEMM out[i, p] = sum_k M[i, k] in[k, p] (M^H with trans_conj),
 // added to out when accumulate != 0, on FP64 matrix cores.  in/out rows may be padded planes: element p of row i
 // sits at i * row + (p / nx) * pitch + p % nx + off.

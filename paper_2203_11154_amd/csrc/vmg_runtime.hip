@@ -76,6 +76,8 @@ struct Group {
     int ntiles0 = 0;
     int nact = 0;   // systems active at the last host check (for byte accounting)
     std::vector<int> sched;  // per level: 0 = LDS-tiled kernels, r > 0 = streaming with r rows; empty = heuristic
+    int tail_lt = -1;        // first level run by the tail kernel (-1: none)
+    int64_t tail_lds = 0;    // its dynamic LDS bytes
 };
 
 struct GraphKey {
@@ -112,6 +114,8 @@ struct vmg_handle {
     int* target = nullptr;
     int* nanflag = nullptr;
     int stream_rows = 0;       // rows per block of the streaming kernels (0: by level size)
+    bool tail_on = true;       // small levels in one workgroup per system (VMG_TAIL=0 turns it off)
+    void* tail_dev[2] = {nullptr, nullptr};  // TailSeg<T> per grid, T of the cycle precision [conj]
     // pinned host staging
     int* h_int = nullptr;      // 3 * S ints
     double* h_dbl = nullptr;   // S doubles
@@ -419,6 +423,39 @@ template <typename T> struct SegBatch {
     }
 };
 
+// First level of grid g run by the tail kernel (g.L when none).
+int tail_start(const Group& g) { return g.tail_lt >= 0 ? g.tail_lt : g.L; }
+
+// Tail launches for grids gis (batches of MAXSEG): x of each grid's first
+// tail level in xs (read unless xzs), written in place.
+template <typename T>
+void enqueue_tails(vmg_handle* H, int conj, hipStream_t st, const std::vector<int>& gis,
+                   const std::vector<cplx<T>*>& xs, const std::vector<int>& xzs) {
+    const vmg_opts& o = H->opts;
+    const double E = sizeof(cplx<T>);
+    for (size_t k0 = 0; k0 < gis.size(); k0 += MAXSEG) {
+        TailLaunch<T> tl{};
+        int total = 0, lvl = 0;
+        int64_t lds = 0;
+        double bytes = 0.0;
+        for (size_t k = k0; k < gis.size() && k < k0 + MAXSEG; ++k) {
+            Group& g = H->groups[gis[k]];
+            tl.seg[tl.n] = gis[k];
+            tl.z0[tl.n] = total;
+            tl.xz[tl.n] = xzs[k];
+            tl.x[tl.n] = xs[k];
+            ++tl.n;
+            total += g.S;
+            lds = std::max(lds, g.tail_lds);
+            lvl = g.tail_lt;
+            bytes += (xzs[k] ? 2.0 : 3.0) * E * nodes(levels_of<T>(g)[g.tail_lt].v) * g.nact;
+        }
+        Timer t(H, st, VMG_K_COARSE, bytes, lvl);
+        launch_tail<T>(reinterpret_cast<const TailSeg<T>*>(H->tail_dev[conj]), tl, total, lds, o.nu1, o.nu2, o.gamma,
+                       st);
+    }
+}
+
 template <typename T> void enqueue_cycle(CycleCtx<T>& c, int l, bool x_zero) {
     vmg_handle* H = c.H;
     Group& g = *c.g;
@@ -428,6 +465,10 @@ template <typename T> void enqueue_cycle(CycleCtx<T>& c, int l, bool x_zero) {
     const vmg_opts& o = H->opts;
     const int one = g.S;
     if (l == 0) c.norm_fused = false;
+    if (l == g.tail_lt) {  // (a cycle entered below the tail's first level runs level by level)
+        enqueue_tails<T>(H, c.conj, c.st, {(int)(&g - &H->groups[0])}, {P<T>(lv.x[c.cur[l]])}, {x_zero ? 1 : 0});
+        return;
+    }
     if (l == g.L - 1) {
         Timer t(H, c.st, VMG_K_COARSE, E * ((double)g.nc * g.nc + 2.0 * g.nc) * g.nact, l);
         launch_coarse<T>(one_seg(make_seg<T>(H, g, c.conj, l, nullptr, P<T>(lv.b), P<T>(lv.x[c.cur[l]]), nullptr, 0,
@@ -527,7 +568,7 @@ void enqueue_batched_vcycle(vmg_handle* H, int conj, hipStream_t st, bool first,
     for (int d = dmax; d >= 1; --d) {
         std::vector<int> sg, lg;  // streamed / LDS-path grids of this phase
         for (int gi = 0; gi < ng; ++gi) {
-            if (H->groups[gi].L - 1 < d) continue;
+            if (H->groups[gi].L - 1 < d || level_of(gi, d) >= tail_start(H->groups[gi])) continue;
             const int l = level_of(gi, d);
             (sched_stream(H, H->groups[gi], l) ? sg : lg).push_back(gi);
         }
@@ -603,24 +644,49 @@ void enqueue_batched_vcycle(vmg_handle* H, int conj, hipStream_t st, bool first,
             }
         }
     }
-    // ---------------- coarsest level of every grid: one batched direct solve
-    for (int k0 = 0; k0 < ng; k0 += MAXSEG) {
-        SegBatch<T> bt;
-        for (int gi = k0; gi < ng && gi < k0 + MAXSEG; ++gi) {
+    // ---------------- small levels of every grid: one tail launch (or the
+    // batched direct solve of grids without a tail)
+    {
+        std::vector<int> tg, cg, xzs;
+        std::vector<cplx<T>*> xs;
+        for (int gi = 0; gi < ng; ++gi) {
             Group& g = H->groups[gi];
-            const int l = g.L - 1;
+            if (g.tail_lt < 0) {
+                cg.push_back(gi);
+                continue;
+            }
             auto& L = levels_of<T>(g);
-            bt.add(make_seg<T>(H, g, conj, l, nullptr, P<T>(L[l].b), P<T>(L[l].x[cur[gi][l]]), nullptr, 0, nullptr),
-                   g.S, E * ((double)g.nc * g.nc + 2.0 * g.nc) * g.nact);
+            const int lt = g.tail_lt;
+            tg.push_back(gi);
+            if (lt == 0) {
+                xs.push_back(P<T>(L[0].x[cur[gi][0]]));
+                xzs.push_back(first ? 1 : 0);
+            } else {
+                cur[gi][lt] = 0;
+                xs.push_back(P<T>(L[lt].x[0]));
+                xzs.push_back(1);
+            }
         }
-        Timer t(H, st, VMG_K_COARSE, bt.bytes, H->groups[k0].L - 1);
-        launch_coarse<T>(bt.tab, bt.nsys, st);
+        if (!tg.empty()) enqueue_tails<T>(H, conj, st, tg, xs, xzs);
+        for (size_t k0 = 0; k0 < cg.size(); k0 += MAXSEG) {
+            SegBatch<T> bt;
+            for (size_t k = k0; k < cg.size() && k < k0 + MAXSEG; ++k) {
+                Group& g = H->groups[cg[k]];
+                const int l = g.L - 1;
+                auto& L = levels_of<T>(g);
+                bt.add(make_seg<T>(H, g, conj, l, nullptr, P<T>(L[l].b), P<T>(L[l].x[cur[cg[k]][l]]), nullptr, 0,
+                                   nullptr),
+                       g.S, E * ((double)g.nc * g.nc + 2.0 * g.nc) * g.nact);
+            }
+            Timer t(H, st, VMG_K_COARSE, bt.bytes, H->groups[cg[k0]].L - 1);
+            launch_coarse<T>(bt.tab, bt.nsys, st);
+        }
     }
     // ---------------- ascent: phases d = 1 .. dmax
     for (int d = 1; d <= dmax; ++d) {
         std::vector<int> sg, lg;
         for (int gi = 0; gi < ng; ++gi) {
-            if (H->groups[gi].L - 1 < d) continue;
+            if (H->groups[gi].L - 1 < d || level_of(gi, d) >= tail_start(H->groups[gi])) continue;
             const int l = level_of(gi, d);
             (sched_stream(H, H->groups[gi], l) ? sg : lg).push_back(gi);
         }
@@ -707,6 +773,7 @@ int level0_flips(const vmg_handle* H, const Group& g) {
     const vmg_opts& o = H->opts;
     const LevelView& v = (o.precision == 0 ? g.lv64[0] : g.lv32[0]).v;
     (void)v;
+    if (g.tail_lt == 0) return 0;  // the whole cycle runs in place in one tail launch
     if (g.L > 1 && sched_stream(H, g, 0)) return (o.nu1 > 0 ? 1 : 0) + 1;
     return o.nu1 + o.nu2;
 }
@@ -1055,6 +1122,67 @@ int upload_coefficients(vmg_handle* H, Group& G, const double* omega) {
 // ============================================================================
 // C ABI
 // ============================================================================
+namespace {
+
+// Tail geometry of every grid (the finest level from which the rest of the
+// cycle fits one workgroup) and the device table of TailSeg records.
+template <typename T> int build_tails(vmg_handle* H) {
+    const int ng = (int)H->groups.size();
+    const int64_t maxlds = tail_max_lds();
+    std::vector<TailSeg<T>> tab[2];
+    tab[0].resize(ng);
+    tab[1].resize(ng);
+    bool any = false;
+    for (int gi = 0; gi < ng; ++gi) {
+        Group& g = H->groups[gi];
+        auto& L = levels_of<T>(g);
+        g.tail_lt = -1;
+        if (!H->tail_on || g.nc > TAIL_MAX_COARSE_NODES) continue;
+        for (int l = 0; l < g.L; ++l) {
+            const int nl = g.L - l;
+            if (nl > MAXT) continue;
+            LevelView lv[MAXT];
+            bool ok = true;
+            for (int q = 0; q < nl; ++q) {
+                lv[q] = L[l + q].v;
+                if (q >= 1 && lv[q].nx * lv[q].ny > TAIL_MAX_COARSE_NODES) ok = false;
+            }
+            const int64_t bytes = tail_lds_bytes<T>(lv, nl);
+            if (!ok || bytes > maxlds) continue;
+            g.tail_lt = l;
+            g.tail_lds = bytes;
+            break;
+        }
+        if (g.tail_lt < 0) continue;
+        any = true;
+        for (int conj = 0; conj < 2; ++conj) {
+            TailSeg<T>& t = tab[conj][gi];
+            const int lt = g.tail_lt;
+            t.b = P<T>(L[lt].b);
+            t.gv = L[lt].v;
+            t.nl = g.L - lt;
+            for (int q = 0; q < t.nl; ++q) {
+                t.lv[q] = L[lt + q].v;
+                t.s[q] = (T)(1.0 / (L[lt + q].h * L[lt + q].h));
+                t.coef[q] = coef_of<T>(g, conj, lt + q);
+            }
+            t.cinvT = cinv_of<T>(g, conj);
+            t.active = H->active + g.sys0;
+            t.nc = g.nc;
+        }
+    }
+    if (!any) return VMG_OK;
+    for (int conj = 0; conj < 2; ++conj) {
+        int rc = dev_malloc(H, &H->tail_dev[conj], sizeof(TailSeg<T>) * ng);
+        if (rc) return rc;
+        if (hipMemcpy(H->tail_dev[conj], tab[conj].data(), sizeof(TailSeg<T>) * ng, hipMemcpyHostToDevice) != hipSuccess)
+            return VMG_HIP_ERROR;
+    }
+    return VMG_OK;
+}
+
+}  // namespace
+
 extern "C" {
 
 int vanka_mg_default_opts(vmg_opts* o) {
@@ -1188,6 +1316,7 @@ int vanka_mg_setup(const vmg_grid* grids, int32_t n_grids, const double* shifts,
         }
     }
     H->S = total;
+    if (const char* e = std::getenv("VMG_TAIL")) H->tail_on = std::atoi(e) != 0;
     if (const char* e = std::getenv("VMG_STREAM_ROWS")) {
         const int r = std::atoi(e);
         if (r >= 16 && r <= 4096) H->stream_rows = r;
@@ -1236,6 +1365,7 @@ int vanka_mg_setup(const vmg_grid* grids, int32_t n_grids, const double* shifts,
         }
         VMG_TRY(upload_coefficients(H, G, nullptr));
     }
+    VMG_TRY(H->opts.precision == 0 ? build_tails<double>(H) : build_tails<float>(H));
 #undef VMG_TRY
     *out = H;
     return VMG_OK;

@@ -1,0 +1,304 @@
+// The small levels of a multigrid cycle in one workgroup per system.
+//
+// Below a few thousand nodes per system a level's kernels are bound by launch
+// and drain latency, not by bandwidth.  Here one 1024-thread workgroup runs,
+// for one system, the whole cycle MG(lt, x, b) of the levels lt..coarsest
+// (sweeps of eqs. (3)/(6), residual and full weighting, gamma recursive
+// visits of the next level, bilinear correction, and the direct coarsest
+// solve) with every iterate, right-hand side and residual of those levels in
+// LDS; only b of level lt is read from global memory (L2), and x of level lt
+// is read (unless it starts at zero) and written back once.
+//
+// LDS layout for a tail whose first level has P0 = (nx+2)(ny+2) padded nodes:
+//   region A  [0, P0)          x of level lt
+//   region B  [P0, P0 + Q)     the residual of level lt, or (while a deeper
+//                              level is active, when that residual is dead)
+//                              x and b of every deeper level followed by one
+//                              residual buffer shared by the deeper levels.
+// Restriction from level lt writes b of level lt+1 over its own residual, so
+// the full-weighting values are formed in registers first and stored after a
+// barrier.  Every array keeps a zero ring.
+#include "vmg_internal.h"
+
+#include <algorithm>
+
+namespace vmg {
+
+namespace {
+
+constexpr int TT = 1024;  // threads per workgroup (16 waves)
+
+template <typename C> __device__ __forceinline__ C tz() { C z; z.x = 0; z.y = 0; return z; }
+template <typename C> __device__ __forceinline__ C tadd(C a, C b) { C r; r.x = a.x + b.x; r.y = a.y + b.y; return r; }
+template <typename C> __device__ __forceinline__ C tsub(C a, C b) { C r; r.x = a.x - b.x; r.y = a.y - b.y; return r; }
+template <typename C, typename T> __device__ __forceinline__ C tscl(C a, T s) { C r; r.x = a.x * s; r.y = a.y * s; return r; }
+template <typename C> __device__ __forceinline__ C tmul(C a, C b) {
+    C r;
+    r.x = a.x * b.x - a.y * b.y;
+    r.y = a.x * b.y + a.y * b.x;
+    return r;
+}
+template <typename C> __device__ __forceinline__ C tfma(C a, C b, C c) {  // a + b c
+    C r;
+    r.x = a.x + b.x * c.x - b.y * c.y;
+    r.y = a.y + b.x * c.y + b.y * c.x;
+    return r;
+}
+
+__device__ __forceinline__ int padded(const LevelView& v) { return (v.nx + 2) * (v.ny + 2); }
+
+template <typename T> struct TailView {
+    const TailSeg<T>* S;
+    int sys;
+    cplx<T>* lds;
+    // element offsets of x, b (l >= 1) and the residual of level l
+    __device__ int xo(int l) const {
+        if (l == 0) return 0;
+        int off = padded(S->lv[0]);
+        for (int q = 1; q < l; ++q) off += 2 * padded(S->lv[q]);
+        return off;
+    }
+    __device__ int bo(int l) const { return xo(l) + padded(S->lv[l]); }
+    __device__ int ro(int l) const {
+        if (l == 0) return padded(S->lv[0]);
+        int off = padded(S->lv[0]);
+        for (int q = 1; q < S->nl; ++q) off += 2 * padded(S->lv[q]);
+        return off;
+    }
+};
+
+template <typename T> __device__ __forceinline__ cplx<T> load_b0(const TailView<T>& V, int k, int i) {
+    const LevelView g = V.S->gv;
+    return V.S->b[(int64_t)V.sys * g.plane + (int64_t)k * g.pitch + i];
+}
+
+// r = b - L x on every padded node of level l (zero on the ring)
+template <typename T> __device__ void residual(const TailView<T>& V, int l) {
+    using C = cplx<T>;
+    const LevelView v = V.S->lv[l];
+    const int pitch = v.nx + 2, P = padded(v);
+    const Coef<T> cf = V.S->coef[l][V.sys];
+    const T s = V.S->s[l];
+    const C* x = V.lds + V.xo(l);
+    const C* b = V.lds + V.bo(l);
+    C* r = V.lds + V.ro(l);
+    for (int t = threadIdx.x; t < P; t += TT) {
+        const int k = t / pitch, i = t - k * pitch;
+        C rv = tz<C>();
+        if (i >= 1 && i <= v.nx && k >= 1 && k <= v.ny) {
+            const C bv = l == 0 ? load_b0(V, k, i) : b[t];
+            const C nb = tadd(tadd(x[t - pitch], x[t + pitch]), tadd(x[t - 1], x[t + 1]));
+            rv = tsub(bv, tsub(tmul(cf.d, x[t]), tscl(nb, s)));
+        }
+        r[t] = rv;
+    }
+    __syncthreads();
+}
+
+// x += ca r + cb (edge sum of r) + cc (corner sum of r), in place
+template <typename T> __device__ void smooth(const TailView<T>& V, int l) {
+    using C = cplx<T>;
+    residual(V, l);
+    const LevelView v = V.S->lv[l];
+    const int pitch = v.nx + 2;
+    const Coef<T> cf = V.S->coef[l][V.sys];
+    C* x = V.lds + V.xo(l);
+    const C* r = V.lds + V.ro(l);
+    for (int t = threadIdx.x; t < v.nx * v.ny; t += TT) {
+        const int k = t / v.nx + 1, i = t - (k - 1) * v.nx + 1;
+        const int c = k * pitch + i;
+        const C edge = tadd(tadd(r[c - pitch], r[c + pitch]), tadd(r[c - 1], r[c + 1]));
+        const C corner = tadd(tadd(r[c - pitch - 1], r[c - pitch + 1]), tadd(r[c + pitch - 1], r[c + pitch + 1]));
+        C u = tfma(x[c], cf.ca, r[c]);
+        u = tfma(u, cf.cb, edge);
+        x[c] = tfma(u, cf.cc, corner);
+    }
+    __syncthreads();
+}
+
+// b_{l+1} = FW(b - L x) at level l; x_{l+1} = 0 (ring included)
+template <typename T> __device__ void restrict_down(const TailView<T>& V, int l) {
+    using C = cplx<T>;
+    residual(V, l);
+    const LevelView v = V.S->lv[l], vc = V.S->lv[l + 1];
+    const int pitch = v.nx + 2, pc = vc.nx + 2;
+    const C* r = V.lds + V.ro(l);
+    // one coarse node per thread (the host keeps the coarse levels of a tail
+    // at most TT nodes)
+    const int t = threadIdx.x;
+    C val = tz<C>();
+    const bool on = t < vc.nx * vc.ny;
+    int cc = 0;
+    if (on) {
+        const int K = t / vc.nx + 1, I = t - (K - 1) * vc.nx + 1;
+        const int c = 2 * K * pitch + 2 * I;
+        const C edge = tadd(tadd(r[c - pitch], r[c + pitch]), tadd(r[c - 1], r[c + 1]));
+        const C corner = tadd(tadd(r[c - pitch - 1], r[c - pitch + 1]), tadd(r[c + pitch - 1], r[c + pitch + 1]));
+        val = tscl(r[c], (T)0.25);
+        val = tadd(val, tscl(edge, (T)0.125));
+        val = tadd(val, tscl(corner, (T)0.0625));
+        cc = K * pc + I;
+    }
+    __syncthreads();  // every read of this level's residual is done
+    C* xc = V.lds + V.xo(l + 1);
+    C* bc = V.lds + V.bo(l + 1);
+    for (int q = threadIdx.x; q < padded(vc); q += TT) xc[q] = tz<C>();
+    if (on) bc[cc] = val;
+    __syncthreads();
+}
+
+// x_l += P x_{l+1} (bilinear; the coarse ring holds zeros)
+template <typename T> __device__ void prolong_up(const TailView<T>& V, int l) {
+    using C = cplx<T>;
+    const LevelView v = V.S->lv[l], vc = V.S->lv[l + 1];
+    const int pitch = v.nx + 2, pc = vc.nx + 2;
+    C* x = V.lds + V.xo(l);
+    const C* e = V.lds + V.xo(l + 1);
+    for (int t = threadIdx.x; t < v.nx * v.ny; t += TT) {
+        const int k = t / v.nx + 1, i = t - (k - 1) * v.nx + 1;
+        const int il = i >> 1, ir = (i + 1) >> 1, kl = k >> 1, kr = (k + 1) >> 1;
+        C w;
+        if (!(i & 1) && !(k & 1)) {
+            w = e[kl * pc + il];
+        } else {
+            const C row0 = (i & 1) ? tadd(e[kl * pc + il], e[kl * pc + ir]) : e[kl * pc + il];
+            const C row1 = (i & 1) ? tadd(e[kr * pc + il], e[kr * pc + ir]) : e[kr * pc + il];
+            w = (k & 1) ? tadd(row0, row1) : row0;
+            w = tscl(w, (T)((i & 1) ? 0.5 : 1.0) * (T)((k & 1) ? 0.5 : 1.0));
+        }
+        const int c = k * pitch + i;
+        x[c] = tadd(x[c], w);
+    }
+    __syncthreads();
+}
+
+// coarsest level: x = (A_c + lambda I)^{-1} b by the precomputed inverse
+template <typename T> __device__ void coarse_solve(const TailView<T>& V, int l) {
+    using C = cplx<T>;
+    const LevelView v = V.S->lv[l];
+    const int pitch = v.nx + 2, nc = V.S->nc;
+    C* x = V.lds + V.xo(l);
+    C* sb = V.lds + V.ro(l);  // right-hand side gathered densely (scratch)
+    for (int t = threadIdx.x; t < nc; t += TT) {
+        const int k = t / v.nx + 1, i = t - (k - 1) * v.nx + 1;
+        sb[t] = l == 0 ? load_b0(V, k, i) : V.lds[V.bo(l) + k * pitch + i];
+    }
+    __syncthreads();
+    const C* ci = V.S->cinvT + (int64_t)V.sys * nc * nc;
+    for (int t = threadIdx.x; t < nc; t += TT) {
+        C acc = tz<C>();
+        for (int k = 0; k < nc; ++k) acc = tfma(acc, ci[(int64_t)k * nc + t], sb[k]);
+        const int kk = t / v.nx + 1, i = t - (kk - 1) * v.nx + 1;
+        x[kk * pitch + i] = acc;
+    }
+    __syncthreads();
+}
+
+template <typename T>
+__global__ __launch_bounds__(TT) void k_tail(const TailSeg<T>* __restrict__ segs, TailLaunch<T> tl, int nu1, int nu2,
+                                             int gamma) {
+    using C = cplx<T>;
+    extern __shared__ double tail_lds[];
+    // entry of this workgroup (selected without indexing the argument arrays)
+    int seg = tl.seg[0], z0 = tl.z0[0], xz = tl.xz[0];
+    C* xg = tl.x[0];
+#pragma unroll
+    for (int j = 1; j < MAXSEG; ++j)
+        if (j < tl.n && (int)blockIdx.x >= tl.z0[j]) {
+            seg = tl.seg[j];
+            z0 = tl.z0[j];
+            xz = tl.xz[j];
+            xg = tl.x[j];
+        }
+    TailView<T> V;
+    V.S = segs + seg;
+    V.sys = (int)blockIdx.x - z0;
+    V.lds = reinterpret_cast<C*>(tail_lds);
+    if (!V.S->active[V.sys]) return;  // uniform over the workgroup
+    const int nl = V.S->nl;
+    const LevelView v0 = V.S->lv[0], g0 = V.S->gv;
+    C* x0 = V.lds;
+    C* gx = xg + (int64_t)V.sys * g0.plane;
+    for (int t = threadIdx.x; t < padded(v0); t += TT) {
+        const int k = t / (v0.nx + 2), i = t - k * (v0.nx + 2);
+        x0[t] = (xz || i < 1 || i > v0.nx || k < 1 || k > v0.ny) ? tz<C>() : gx[(int64_t)k * g0.pitch + i];
+    }
+    __syncthreads();
+    // MG(0) with gamma visits of every coarser level, without recursion:
+    // cnt holds, 4 bits per level, the visits of the next level made so far
+    unsigned cnt = 0;
+    int l = 0;
+    bool down = true;
+    for (;;) {
+        if (down) {
+            if (l == nl - 1) {
+                coarse_solve(V, l);
+                down = false;
+                continue;
+            }
+            for (int it = 0; it < nu1; ++it) smooth(V, l);
+            restrict_down(V, l);
+            cnt &= ~(15u << (4 * l));
+            ++l;
+            continue;
+        }
+        if (l == 0) break;
+        const int p = l - 1;
+        const unsigned c = ((cnt >> (4 * p)) & 15u) + 1u;
+        cnt = (cnt & ~(15u << (4 * p))) | (c << (4 * p));
+        if ((int)c < gamma) {
+            down = true;  // another visit of level l, from its current iterate
+            continue;
+        }
+        prolong_up(V, p);
+        for (int it = 0; it < nu2; ++it) smooth(V, p);
+        l = p;
+    }
+    for (int t = threadIdx.x; t < v0.nx * v0.ny; t += TT) {
+        const int k = t / v0.nx + 1, i = t - (k - 1) * v0.nx + 1;
+        gx[(int64_t)k * g0.pitch + i] = x0[k * (v0.nx + 2) + i];
+    }
+}
+
+}  // namespace
+
+template <typename T> int64_t tail_lds_bytes(const LevelView* lv, int nl) {
+    auto pad = [](const LevelView& v) { return (int64_t)(v.nx + 2) * (v.ny + 2); };
+    int64_t a = pad(lv[0]);
+    int64_t deep = 0;
+    for (int q = 1; q < nl; ++q) deep += 2 * pad(lv[q]);
+    if (nl > 1) deep += pad(lv[1]);  // residual buffer shared by the deeper levels
+    int64_t b = std::max(pad(lv[0]), deep);
+    // the coarsest solve gathers its right-hand side into the residual buffer
+    return (a + b) * (int64_t)sizeof(cplx<T>);
+}
+template int64_t tail_lds_bytes<double>(const LevelView*, int);
+template int64_t tail_lds_bytes<float>(const LevelView*, int);
+
+int tail_max_lds() {
+    static int max_lds = -1;
+    if (max_lds < 0) {
+        int dev = 0, v = 0;
+        if (hipGetDevice(&dev) != hipSuccess) dev = 0;
+        if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess) v = 65536;
+        max_lds = v;
+        // allow the dynamic allocation above the default limit
+        (void)hipFuncSetAttribute((const void*)&k_tail<double>, hipFuncAttributeMaxDynamicSharedMemorySize, v);
+        (void)hipFuncSetAttribute((const void*)&k_tail<float>, hipFuncAttributeMaxDynamicSharedMemorySize, v);
+        (void)hipGetLastError();
+    }
+    return max_lds;
+}
+
+template <typename T>
+void launch_tail(const TailSeg<T>* segs, const TailLaunch<T>& tl, int total_sys, int64_t lds_bytes, int nu1, int nu2,
+                 int gamma, hipStream_t st) {
+    if (total_sys <= 0) return;
+    hipLaunchKernelGGL((k_tail<T>), dim3(total_sys), dim3(TT), (size_t)lds_bytes, st, segs, tl, nu1, nu2, gamma);
+}
+template void launch_tail<double>(const TailSeg<double>*, const TailLaunch<double>&, int, int64_t, int, int, int,
+                                  hipStream_t);
+template void launch_tail<float>(const TailSeg<float>*, const TailLaunch<float>&, int, int64_t, int, int, int,
+                                 hipStream_t);
+
+}  // namespace vmg
