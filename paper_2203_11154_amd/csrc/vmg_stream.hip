@@ -413,6 +413,12 @@ struct UpPipe {
     using C = cplx<T>;
     static constexpr int HALO = NORM ? 2 * NS + 1 : (NS > 0 ? 2 * NS : 1);
     static constexpr int OWN = 64 - 2 * HALO;
+    // The correction at an odd column takes the right lane's coarse value, so
+    // lane 63 is wrong there and the error spreads one lane per stage.  With
+    // an even HALO lane 63 sits on an even column; with the odd HALO of the
+    // norm variant the strips start one column earlier (at the zero ring
+    // column) to the same effect.
+    static constexpr int COL0 = (HALO & 1) ? 0 : 1;
     C X[NS + 1][3], R[NS + 1][3];
     C B[6];
     C xr[PF + 1], br[PF + 1];
@@ -524,7 +530,7 @@ __device__ __forceinline__ double up_piece(const LevelSeg<T>& S, int sys, int st
     Pipe p;
     p.lf = S.lf;
     p.lc = S.lc;
-    const int i = 1 + strip * OWN - HALO + lane;
+    const int i = Pipe::COL0 + strip * OWN - HALO + lane;
     p.col_in = i >= 1 && i <= p.lf.nx;
     p.odd = (i & 1) != 0;
     const bool ecol = i >= 0 && i <= p.lf.nx + 1;
@@ -630,9 +636,9 @@ constexpr int MIN_RUN = 16;
 struct RunGeom {
     int strips, pieces, rows, waves;
 };
-RunGeom run_geom(int nx, int ny, int nsys, int own, int halo_rows, int rmin, int resident) {
+RunGeom run_geom(int nx, int ny, int nsys, int own, int col0, int halo_rows, int rmin, int resident) {
     RunGeom g;
-    g.strips = (nx + own - 1) / own;
+    g.strips = (nx + 1 - col0 + own - 1) / own;  // strips cover columns col0..nx
     const int64_t runs1 = (int64_t)nsys * g.strips;
     const int pmax = std::max(1, ny / std::max(rmin, MIN_RUN));
     int best = 1;
@@ -653,11 +659,11 @@ RunGeom run_geom(int nx, int ny, int nsys, int own, int halo_rows, int rmin, int
 }
 
 template <typename T>
-dim3 stream_seg_grid(SegTable<T>& tab, const int* nsys, int own, int halo_rows, int rmin, int resident) {
+dim3 stream_seg_grid(SegTable<T>& tab, const int* nsys, int own, int col0, int halo_rows, int rmin, int resident) {
     int w = 0;
     for (int q = 0; q < tab.n; ++q) {
         LevelSeg<T>& S = tab.s[q];
-        const RunGeom g = run_geom(S.lf.nx, S.lf.ny, nsys[q], own, halo_rows, rmin, resident);
+        const RunGeom g = run_geom(S.lf.nx, S.lf.ny, nsys[q], own, col0, halo_rows, rmin, resident);
         S.z0 = 0;
         S.nsys = nsys[q];
         S.strips = g.strips;
@@ -672,13 +678,14 @@ dim3 stream_seg_grid(SegTable<T>& tab, const int* nsys, int own, int halo_rows, 
 
 template <typename T, int NS> void down_go(SegTable<T> tab, const int* nsys, int rmin, hipStream_t st) {
     const void* k = (const void*)&k_down<T, NS>;
-    const dim3 g = stream_seg_grid(tab, nsys, down_own<NS>(), 4 * NS + 9, rmin, resident_waves(k));
+    const dim3 g = stream_seg_grid(tab, nsys, down_own<NS>(), 1, 4 * NS + 9, rmin, resident_waves(k));
     if (g.x == 0) return;
     hipLaunchKernelGGL((k_down<T, NS>), g, dim3(NT), 0, st, tab);
 }
 template <typename T, int NS, bool NORM> void up_go(SegTable<T> tab, const int* nsys, int rmin, hipStream_t st) {
     const void* k = (const void*)&k_up<T, NS, NORM>;
-    const dim3 g = stream_seg_grid(tab, nsys, up_own<NS, NORM>(), 4 * NS + 7, rmin, resident_waves(k));
+    const dim3 g = stream_seg_grid(tab, nsys, up_own<NS, NORM>(), UpPipe<T, NS, NORM>::COL0, 4 * NS + 7, rmin,
+                                   resident_waves(k));
     if (g.x == 0) return;
     hipLaunchKernelGGL((k_up<T, NS, NORM>), g, dim3(NT), 0, st, tab);
 }
@@ -693,7 +700,8 @@ template <typename T> int stream_tiles(int nx, int ny, int nsys, int nu, int rmi
         case 1: k = (const void*)&k_up<T, 1, true>; own = up_own<1, true>(); break;
         default: k = (const void*)&k_up<T, 2, true>; own = up_own<2, true>(); break;
     }
-    const RunGeom g = run_geom(nx, ny, nsys, own, 4 * (nu < 2 ? nu : 2) + 7, rmin, resident_waves(k));
+    const RunGeom g = run_geom(nx, ny, nsys, own, UpPipe<T, 2, true>::COL0, 4 * (nu < 2 ? nu : 2) + 7, rmin,
+                               resident_waves(k));
     return g.strips * g.pieces;
 }
 template int stream_tiles<double>(int, int, int, int, int);
@@ -713,7 +721,7 @@ void stream_prepare() {
 
 int stream_tiles_max(int nx, int ny, int nu) {
     const int own = nu == 0 ? up_own<0, true>() : (nu == 1 ? up_own<1, true>() : up_own<2, true>());
-    return ((nx + own - 1) / own) * std::max(1, ny / MIN_RUN);
+    return ((nx + own) / own) * std::max(1, ny / MIN_RUN);
 }
 template int stream_tiles<float>(int, int, int, int, int);
 

@@ -129,3 +129,25 @@ def test_streamed_full_size_sampled_sweep_and_solve():
     assert np.all(rr <= 1.01e-10)
     err = np.linalg.norm((z[pick] - zx).reshape(len(pick), -1), axis=1) / np.linalg.norm(zx.reshape(len(pick), -1), axis=1)
     assert np.all(err <= 1e-7)
+
+
+@pytest.mark.parametrize("nu1,nu2", [(2, 2), (1, 1), (0, 1)])
+def test_fused_norm_equals_host_residual(nu1, nu2):
+    """The stopping-test norm that the finest-level streaming kernel forms
+    equals the residual norm of the iterate it writes, recomputed on the host
+    in FP64, after 1 and 2 cycles (large residuals, so no cancellation noise):
+    every owned column of every strip carries exactly its own residual."""
+    solver, lam = make(nu1, nu2)
+    bs = [inputs.rhs(g["S"], g["ny"], g["nx"], seed=50 + k) for k, g in enumerate(GRIDS)]
+    bd = dev(np.concatenate([b.ravel() for b in bs]))
+    S = sum(g["S"] for g in GRIDS)
+    for cycles in (1, 2):
+        Z, it, rr, _ = solver.solve(bd, fixed_iters=np.full(S, cycles, dtype=np.int32))
+        z, off, sys = host(Z), 0, 0
+        for g, lg, b in zip(GRIDS, split_shifts(lam), bs):
+            n = g["nx"] * g["ny"] * g["S"]
+            zg = z[off:off + n].reshape(b.shape)
+            off += n
+            ref = omg.residual_norms(zg, b, lg, g["h"]) / np.linalg.norm(b.reshape(g["S"], -1), axis=1)
+            np.testing.assert_allclose(rr[sys:sys + g["S"]], ref, rtol=1e-9)
+            sys += g["S"]
