@@ -31,7 +31,9 @@ FP64_MFMA_PEAK_TFLOPS = 78.6
 # plain 1 GiB copy (profiles/).  Valid only for the kernel source it was
 # measured on: reported as null once that file changes.
 MEASURED_TRAFFIC = {"source": "vmg_stream.hip", "source_sha256_16": "944450ee382e42c9", "bytes_per_launch": 3843.2e6}
-DOMINANT = "k_up<double, 2, true>"   # fused correction + 2 sweeps + norm, finest level only
+# finest level across the boundary of two V-cycles: correction + 2 sweeps +
+# stopping-test norm, then the next cycle's 2 sweeps + residual + restriction
+DOMINANT = "k_edge<double, 2, 2>"
 
 
 def kernel_source_hash(name):
@@ -228,9 +230,9 @@ def main():
     ms_per_step = 1e3 * dt / args.steps
     value = S * args.steps / dt
 
-    # dominant kernel: the finest-level fused correction + post-smoothing kernel
-    # (HBM bound); it is the only launch of its instantiation, so HIP-event
-    # and rocprofv3 averages cover the same launches
+    # dominant kernel: the finest-level cycle-edge kernel (HBM bound); it is
+    # the only launch of its instantiation, so HIP-event and rocprofv3
+    # averages cover the same launches
     _, la, ms, by = solver.level_stats("up")[0]
     gbs = by / (ms * 1e-3) / 1e9
     traffic = None
@@ -240,7 +242,7 @@ def main():
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4),
                 "traffic": traffic, "launches": la, "avg_ms": round(ms / max(la, 1), 5),
                 "algorithmic_bytes_per_launch": round(by / max(la, 1)),
-                "bytes_per_node": "52 (read x, b, e/4; write x)"}
+                "bytes_per_node": "72 (read x, b, e/4; write x_k, x_(k+1) pre-smoothed, coarse rhs/4)"}
     levels = {}
     for k in ("down", "up"):
         levels[k] = [{"level": l, "launches": a, "avg_ms": round(m / max(a, 1), 4),

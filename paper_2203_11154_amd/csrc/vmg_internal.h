@@ -42,6 +42,8 @@ template <typename T> struct LevelSeg {
     cplx<T>* xo;          // iterate written
     cplx<T>* c;           // coarse right-hand side written (restriction) or
                           // coarse correction read (prolongation)
+    cplx<T>* xf;          // cycle-edge kernel: the finished iterate written
+    cplx<T>* cb;          // cycle-edge kernel: the next coarse right-hand side
     LevelView lf, lc;     // this level and the next coarser one
     T s;                  // 1 / h^2 of this level
     const Coef<T>* coef;  // per system of the segment
@@ -181,7 +183,13 @@ void launch_transform(int n, int64_t m, const double2* M, int trans_conj, const 
 template <typename T> void launch_down(SegTable<T> tab, const int* nsys, int nu, int rmin, hipStream_t st);
 template <typename T> void launch_up(SegTable<T> tab, const int* nsys, int nu, bool norm, int rmin, hipStream_t st);
 template <typename T> int stream_tiles(int nx, int ny, int nsys, int nu, int rmin);
-int stream_tiles_max(int nx, int ny, int nu);  // over every rmin
+int stream_tiles_max(int nx, int ny, int nu);  // over every rmin and kernel
+// Cycle-edge kernel (FP64 finest level, nu1, nu2 in {1, 2}): correction +
+// nu2 sweeps -> xf, norm partials (edge_tiles per system), nu1 sweeps -> xo,
+// full weighting -> cb; reads x, b and the coarse correction c.
+bool edge_supported(int nu1, int nu2);
+template <typename T> void launch_edge(SegTable<T> tab, const int* nsys, int nu1, int nu2, int rmin, hipStream_t st);
+template <typename T> int edge_tiles(int nx, int ny, int nsys, int nu1, int nu2, int rmin);
 void stream_prepare();  // device occupancy of the streaming kernels (call outside stream capture)
 template <typename T> void launch_fill_zero(cplx<T>* x, LevelView lv, int nsys, hipStream_t st);
 

@@ -13,6 +13,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <new>
+#include <type_traits>
 #include <vector>
 
 #include "../../include/vanka_mg.h"
@@ -60,6 +61,7 @@ struct Level {
     double h = 0;
     DevBuf x[2];
     DevBuf b;
+    DevBuf xf;  // finest level with the cycle-edge kernel: the finished iterate
 };
 
 struct Group {
@@ -115,6 +117,7 @@ struct vmg_handle {
     int* nanflag = nullptr;
     int stream_rows = 0;       // rows per block of the streaming kernels (0: by level size)
     bool tail_on = true;       // small levels in one workgroup per system (VMG_TAIL=0 turns it off)
+    bool edge_on = true;       // finest level across the cycle boundary in one pass (VMG_EDGE=0 turns it off)
     void* tail_dev[2] = {nullptr, nullptr};  // TailSeg<T> per grid, T of the cycle precision [conj]
     // pinned host staging
     int* h_int = nullptr;      // 3 * S ints
@@ -371,6 +374,17 @@ bool sched_stream(const vmg_handle* H, const Group& g, int l) {
     if ((int)g.sched.size() > l && g.sched[l] >= 0) return g.sched[l] > 0;
     return use_stream(H->opts, cycle_view(H, g, l));
 }
+// The cycle-edge kernel (finest level, FP64 V-cycles) may run for grid g /
+// runs with the current kernel schedule.
+bool edge_possible(const vmg_handle* H, const Group& g) {
+    const vmg_opts& o = H->opts;
+    return H->edge_on && o.precision == 0 && o.gamma == 1 && edge_supported(o.nu1, o.nu2) && g.L >= 2;
+}
+bool sched_stream(const vmg_handle* H, const Group& g, int l);
+bool use_edge(const vmg_handle* H, const Group& g) {
+    return edge_possible(H, g) && g.lv64[0].xf.ptr && g.tail_lt != 0 && sched_stream(H, g, 0);
+}
+
 int sched_rows(const vmg_handle* H, const Group& g, int l) {
     if ((int)g.sched.size() > l && g.sched[l] > 0) return g.sched[l];
     return stream_rows_for(H, cycle_view(H, g, l));
@@ -545,6 +559,13 @@ template <typename T> void enqueue_cycle(CycleCtx<T>& c, int l, bool x_zero) {
     }
 }
 
+template <typename T> void launch_edge_t(SegTable<T> tab, const int* nsys, int nu1, int nu2, int rmin, hipStream_t st);
+template <> void launch_edge_t<double>(SegTable<double> tab, const int* nsys, int nu1, int nu2, int rmin,
+                                       hipStream_t st) {
+    launch_edge<double>(tab, nsys, nu1, nu2, rmin, st);
+}
+template <> void launch_edge_t<float>(SegTable<float>, const int*, int, int, int, hipStream_t) {}
+
 // One V-cycle of every grid, batched: the grids are aligned at their
 // coarsest level, so phase d (d levels above the coarsest) is one launch per
 // kernel over all grids that reach that high, whatever their sizes.
@@ -570,6 +591,9 @@ void enqueue_batched_vcycle(vmg_handle* H, int conj, hipStream_t st, bool first,
         for (int gi = 0; gi < ng; ++gi) {
             if (H->groups[gi].L - 1 < d || level_of(gi, d) >= tail_start(H->groups[gi])) continue;
             const int l = level_of(gi, d);
+            // with the cycle-edge kernel the finest level's pre-smoothing and
+            // restriction were done by the previous cycle (all but the first)
+            if (l == 0 && !first && std::is_same<T, double>::value && use_edge(H, H->groups[gi])) continue;
             (sched_stream(H, H->groups[gi], l) ? sg : lg).push_back(gi);
         }
         // streamed grids: one fused launch per row-block height
@@ -684,11 +708,45 @@ void enqueue_batched_vcycle(vmg_handle* H, int conj, hipStream_t st, bool first,
     }
     // ---------------- ascent: phases d = 1 .. dmax
     for (int d = 1; d <= dmax; ++d) {
-        std::vector<int> sg, lg;
+        std::vector<int> sg, lg, eg;
         for (int gi = 0; gi < ng; ++gi) {
             if (H->groups[gi].L - 1 < d || level_of(gi, d) >= tail_start(H->groups[gi])) continue;
             const int l = level_of(gi, d);
+            if (l == 0 && std::is_same<T, double>::value && use_edge(H, H->groups[gi])) {
+                eg.push_back(gi);
+                continue;
+            }
             (sched_stream(H, H->groups[gi], l) ? sg : lg).push_back(gi);
+        }
+        // finest levels across the cycle boundary: correction + post-smoothing
+        // + norm, then the next cycle's pre-smoothing and restriction
+        while (!eg.empty()) {
+            const int ty = sched_rows(H, H->groups[eg[0]], 0);
+            SegBatch<T> bt;
+            std::vector<int> rest, done;
+            for (int gi : eg) {
+                Group& g = H->groups[gi];
+                auto& L = levels_of<T>(g);
+                if (sched_rows(H, g, 0) != ty || bt.full()) {
+                    rest.push_back(gi);
+                    continue;
+                }
+                LevelSeg<T> S = make_seg<T>(H, g, conj, 0, P<T>(L[0].x[cur[gi][0]]), P<T>(L[0].b),
+                                            P<T>(L[0].x[1 - cur[gi][0]]), P<T>(L[1].x[cur[gi][1]]), 0, partials[gi]);
+                S.xf = P<T>(L[0].xf);
+                S.cb = P<T>(L[1].b);
+                bt.add(S, g.S, bytes_of(g, 0, 2.0 + 0.25 + 2.0 + 0.25));
+                done.push_back(gi);
+            }
+            {
+                Timer t(H, st, VMG_K_UP, bt.bytes, 0);
+                launch_edge_t<T>(bt.tab, bt.nsys, o.nu1, o.nu2, ty, st);
+            }
+            for (int gi : done) {
+                cur[gi][0] ^= 1;
+                if (partials[gi]) fused[gi] = 1;
+            }
+            eg.swap(rest);
         }
         while (!sg.empty()) {
             const int ty = sched_rows(H, H->groups[sg[0]], level_of(sg[0], d));
@@ -778,7 +836,17 @@ int level0_flips(const vmg_handle* H, const Group& g) {
     return o.nu1 + o.nu2;
 }
 
+// Buffer of the finest iterate at the start of cycle `cycle` (0 or 1).  With
+// the cycle-edge kernel the pre-smoothed iterate alternates once per cycle,
+// after the first cycle's separate pre-smoothing pass.
+int level0_parity(const vmg_handle* H, const Group& g, int64_t cycle) {
+    if (use_edge(H, g)) return (int)((cycle + (cycle > 0 ? 1 : 0)) & 1);
+    return (int)((cycle * level0_flips(H, g)) & 1);
+}
+
 int norm_tiles(const vmg_handle* H, const Group& g) {
+    if (use_edge(H, g))
+        return edge_tiles<double>(g.lv64[0].v.nx, g.lv64[0].v.ny, g.S, H->opts.nu1, H->opts.nu2, sched_rows(H, g, 0));
     return stream_tiles<double>(g.lv64[0].v.nx, g.lv64[0].v.ny, g.S, H->opts.nu2, sched_rows(H, g, 0));
 }
 
@@ -899,7 +967,7 @@ int enqueue_cycle_all(vmg_handle* H, int conj, hipStream_t st, int64_t cycle, do
                 Group& g = H->groups[gi];
                 cur[gi].assign(g.L, 0);
                 // level-0 buffer parity is a function of the cycles run so far
-                cur[gi][0] = (int)((cycle * level0_flips(H, g)) & 1);
+                cur[gi][0] = level0_parity(H, g, cycle);
                 parts[gi] = g.partial;
             }
             enqueue_batched_vcycle<double>(H, conj, st, first, cur, parts, fused);
@@ -908,7 +976,7 @@ int enqueue_cycle_all(vmg_handle* H, int conj, hipStream_t st, int64_t cycle, do
             for (size_t gi = 0; gi < ng; ++gi) {
                 Group& g = H->groups[gi];
                 CycleCtx<double> ctx{H, &g, conj, st, std::vector<int>(g.L, 0)};
-                ctx.cur[0] = (int)((cycle * level0_flips(H, g)) & 1);
+                ctx.cur[0] = level0_parity(H, g, cycle);
                 ctx.norm_partial = g.partial;
                 enqueue_cycle<double>(ctx, 0, first);
                 cur0[gi] = ctx.cur[0];
@@ -949,7 +1017,7 @@ int run_cycle(vmg_handle* H, int conj, hipStream_t st, int64_t cycle, double tol
     if (!H->opts.graphs || H->timing) return enqueue_cycle_all(H, conj, st, cycle, tol, fixed);
     int par = 0;
     for (size_t gi = 0; gi < H->groups.size(); ++gi)
-        par |= (int)(((cycle * level0_flips(H, H->groups[gi])) & 1) << (gi & 31));
+        par |= level0_parity(H, H->groups[gi], cycle) << (gi & 31);
     if (H->opts.precision == 1) par = 0;
     GraphKey key{cycle == 0 ? 1 : 0, conj, fixed, par, tol};
     hipGraphExec_t exec = nullptr;
@@ -1037,9 +1105,14 @@ int solve_impl(vmg_handle* H, const double* B, double* Z, double tol, int conj, 
     for (auto& g : H->groups) {
         Level& l0 = g.lv64[0];
         Timer t(H, st, VMG_K_PACK, 32.0 * nodes(l0.v) * g.S);
-        const int flips = o.precision == 0 ? level0_flips(H, g) : 0;
-        launch_unpack<double>(P<double>(l0.x[0]), o.precision == 0 ? P<double>(l0.x[1]) : nullptr,
-                              reinterpret_cast<double2*>(Z) + off, l0.v, g.S, H->iters + g.sys0, flips, st);
+        if (use_edge(H, g)) {  // every cycle leaves its finished iterate in xf
+            launch_unpack<double>(P<double>(l0.xf), nullptr, reinterpret_cast<double2*>(Z) + off, l0.v, g.S,
+                                  H->iters + g.sys0, 0, st);
+        } else {
+            const int flips = o.precision == 0 ? level0_flips(H, g) : 0;
+            launch_unpack<double>(P<double>(l0.x[0]), o.precision == 0 ? P<double>(l0.x[1]) : nullptr,
+                                  reinterpret_cast<double2*>(Z) + off, l0.v, g.S, H->iters + g.sys0, flips, st);
+        }
         off += (int64_t)g.nx * g.ny * g.S;
     }
     if (check_hip()) return VMG_HIP_ERROR;
@@ -1317,6 +1390,7 @@ int vanka_mg_setup(const vmg_grid* grids, int32_t n_grids, const double* shifts,
     }
     H->S = total;
     if (const char* e = std::getenv("VMG_TAIL")) H->tail_on = std::atoi(e) != 0;
+    if (const char* e = std::getenv("VMG_EDGE")) H->edge_on = std::atoi(e) != 0;
     if (const char* e = std::getenv("VMG_STREAM_ROWS")) {
         const int r = std::atoi(e);
         if (r >= 16 && r <= 4096) H->stream_rows = r;
@@ -1351,6 +1425,7 @@ int vanka_mg_setup(const vmg_grid* grids, int32_t n_grids, const double* shifts,
             VMG_TRY(alloc_planes<double>(H, L.x[0], L.v, G.S));
             if (o.precision == 0) VMG_TRY(alloc_planes<double>(H, L.x[1], L.v, G.S));
             VMG_TRY(alloc_planes<double>(H, L.b, L.v, G.S));
+            if (l == 0 && edge_possible(H, G)) VMG_TRY(alloc_planes<double>(H, L.xf, L.v, G.S));
         }
         for (size_t l = 0; l < G.lv32.size(); ++l) {
             Level& L = G.lv32[l];

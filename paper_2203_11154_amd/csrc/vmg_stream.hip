@@ -159,6 +159,14 @@ __device__ __forceinline__ void bstore(rsrc_t r, unsigned voff, unsigned soff, f
     using V = __attribute__((ext_vector_type(2))) unsigned int;
     __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(V, v), r, (int)voff, (int)soff, VMG_STREAM_STORE_POLICY);
 }
+// row * bytes-per-row, computed where it is used: an opaque scalar multiply
+// keeps the compiler from hoisting every (row + constant) * rx of an unrolled
+// block into its own scalar register
+__device__ __forceinline__ unsigned srow(int row, unsigned rx) {
+    unsigned r;
+    asm volatile("s_mul_i32 %0, %1, %2" : "=s"(r) : "s"(row), "s"(rx));
+    return r;
+}
 // byte offset of row j when ok, else OOB (uniform)
 __device__ __forceinline__ unsigned row_off(bool ok, int j, int pitch, int es) {
     return ok ? (unsigned)(j * pitch * es) : OOB;
@@ -600,6 +608,233 @@ __global__ __launch_bounds__(NT) VMG_STREAM_OCC void k_up(SegTable<T> tab) {
     }
 }
 
+// ---------------------------------------------------------------------------
+// Finest level at the boundary of two V-cycles, in one pass: the bilinear
+// correction and NA post-smoothing sweeps that end cycle k (iterate written to
+// xf), the residual norm of that iterate (the stopping test), then NB
+// pre-smoothing sweeps of cycle k+1 from it (written to xo), their residual
+// and its full weighting (the next coarse right-hand side, written to cb).
+// Reads x, b and the coarse correction once instead of twice per cycle; if
+// the stopping test ends the solve, the pre-smoothed iterate is not used.
+// Unrolled by 12 steps: the right-hand side ring needs 2(NA+NB)+1 rows.
+constexpr int UNR_E = 12;
+#ifndef VMG_EDGE_PF
+#define VMG_EDGE_PF 1
+#endif
+#ifndef VMG_EDGE_BLDS
+#define VMG_EDGE_BLDS 1
+#endif
+constexpr int EPF = VMG_EDGE_PF;
+template <int L> __host__ __device__ constexpr int eslot(int p) { return ((p % L) + L * UNR_E) % L; }
+
+template <typename T, int NA, int NB>
+struct EdgePipe {
+    using C = cplx<T>;
+    static constexpr int NS = NA + NB;
+    static constexpr int HALO = 2 * NS + 2;  // NS+1 residuals, NS updates, the weighting's lane sum
+    static constexpr int OWN = 64 - 2 * HALO;
+    // an even HALO and strips from column 1 put lane 63 on an even column,
+    // where the correction needs no right-lane value
+    static constexpr int COL0 = 1;
+    static_assert(UNR_E % 12 == 0 && UNR_E % (EPF + 1) == 0 && 2 * NS + 1 <= 12, "ring lengths");
+    C X[NS + 1][3], R[NS + 1][3];
+#if VMG_EDGE_BLDS
+    C* B;               // this lane's column of the wave's 12-row ring in LDS (stride 64)
+#else
+    C B[12];
+#endif
+    C xr[EPF + 1], br[EPF + 1];
+    C er[3], ei[3];
+    rsrc_t xs, bs, es, xos, xfs, cbs;
+    LevelView lf, lc;
+    Coef<T> cf;
+    C dl;
+    T sl;
+    int k0, k1;
+    bool col_in, odd;
+    unsigned ox, oe, oo, of;
+    unsigned rx, rc;
+    double acc;
+
+    template <bool EDGE> __device__ __forceinline__ C load_x(int j) const {
+        C v;
+        if constexpr (EDGE) bload(xs, ox + (in_rows(j, lf.ny) ? j * rx : OOB), 0, v);
+        else bload(xs, ox, srow(j, rx), v);
+        return v;
+    }
+    template <bool EDGE> __device__ __forceinline__ C load_b(int j) const {
+        C v;
+        if constexpr (EDGE) bload(bs, ox + (in_rows(j, lf.ny) ? j * rx : OOB), 0, v);
+        else bload(bs, ox, srow(j, rx), v);
+        return v;
+    }
+    template <bool EDGE> __device__ __forceinline__ C load_e(int K) const {
+        C v;
+        if constexpr (EDGE) bload(es, oe + (K >= 0 && K <= lc.ny + 1 ? K * rc : OOB), 0, v);
+        else bload(es, oe, srow(K, rc), v);
+        return v;
+    }
+    __device__ __forceinline__ C interp_x(C v) const {
+        const C rv = from_right(v);
+        return odd ? scl(add(v, rv), (T)0.5) : v;
+    }
+    template <bool EDGE> __device__ __forceinline__ void store_row(rsrc_t r, int row, C v) const {
+        if constexpr (EDGE) bstore(r, oo + (row >= k0 && row <= k1 ? row * rx : OOB), 0, v);
+        else bstore(r, oo, srow(row, rx), v);
+    }
+    template <int P, bool EDGE> __device__ __forceinline__ void step(int j) {
+        xr[eslot<EPF + 1>(P + EPF)] = load_x<EDGE>(j + EPF);
+        br[eslot<EPF + 1>(P + EPF)] = load_b<EDGE>(j + EPF - 1);
+        C e;
+        if constexpr ((P & 1) != 0) {
+            constexpr int lo = eslot<3>((P - 1) / 2), hi = eslot<3>((P + 1) / 2);
+            ei[hi] = interp_x(er[hi]);
+            e = scl(add(ei[lo], ei[hi]), (T)0.5);
+        } else {
+            er[eslot<3>(P / 2 + 2)] = load_e<EDGE>((j >> 1) + 2);
+            e = ei[eslot<3>(P / 2)];
+        }
+        constexpr int n0 = eslot<3>(P), n1 = eslot<3>(P - 1), n2 = eslot<3>(P - 2);
+        X[0][n0] = add(xr[eslot<EPF + 1>(P)], e);
+#if VMG_EDGE_BLDS
+        B[eslot<12>(P) * 64] = br[eslot<EPF + 1>(P)];
+#else
+        B[eslot<12>(P)] = br[eslot<EPF + 1>(P)];
+#endif
+#pragma unroll
+        for (int q = 0; q <= NS; ++q) {
+            const int rrow = j - 2 * q - 1;
+#if VMG_EDGE_BLDS
+            const C bq = B[eslot<12>(P - 2 * q) * 64];
+#else
+            const C bq = B[eslot<12>(P - 2 * q)];
+#endif
+            C r = residual_row<T>(X[q][n2], X[q][n1], X[q][n0], bq, dl, sl);
+            if constexpr (EDGE)
+                if (!in_rows(rrow, lf.ny)) r = z2<C>();
+            if (q == NA) {
+                // stopping-test residual of cycle k's final iterate (owned-lane
+                // mask applied once, at the end)
+                if (!EDGE || (rrow >= k0 && rrow <= k1)) acc += (double)r.x * (double)r.x + (double)r.y * (double)r.y;
+                pin(acc);
+            }
+            R[q][n0] = r;
+            pin(R[q][n0]);
+            if (q < NS) {
+                C v = lane_clear(col_in, vanka_row<T>(X[q][n2], R[q][n2], R[q][n1], R[q][n0], cf));
+                if constexpr (EDGE)
+                    if (!in_rows(j - 2 * q - 2, lf.ny)) v = z2<C>();
+                X[q + 1][n0] = v;
+                pin(X[q + 1][n0]);
+            }
+        }
+        pin(X[0][n0]);
+        store_row<EDGE>(xfs, j - 2 * NA, X[NA][n0]);
+        store_row<EDGE>(xos, j - 2 * NS, X[NS][n0]);
+        if constexpr ((P & 1) == 0) {
+            const int frow = j - 2 * NS - 2;
+            const C v = full_weight_row<T>(R[NS][n2], R[NS][n1], R[NS][n0]);
+            const int K = frow >> 1;
+            if constexpr (EDGE)
+                bstore(cbs, of + (frow >= k0 && frow <= k1 && frow >= 2 && K <= lc.ny ? K * rc : OOB), 0, v);
+            else bstore(cbs, of, srow(K, rc), v);
+        }
+    }
+    template <bool EDGE> __device__ __forceinline__ void block(int j) {
+#define VMG_E(P)                      \
+    step<P, EDGE>(j + P);             \
+    __builtin_amdgcn_sched_barrier(0);
+        VMG_E(0) VMG_E(1) VMG_E(2) VMG_E(3) VMG_E(4) VMG_E(5)
+        VMG_E(6) VMG_E(7) VMG_E(8) VMG_E(9) VMG_E(10) VMG_E(11)
+#undef VMG_E
+    }
+};
+
+template <typename T, int NA, int NB>
+__device__ __forceinline__ double edge_piece(const LevelSeg<T>& S, int sys, int strip, int k0, int k1, int lane,
+                                             cplx<T>* bring) {
+    using C = cplx<T>;
+    using Pipe = EdgePipe<T, NA, NB>;
+    constexpr int HALO = Pipe::HALO, OWN = Pipe::OWN, NS = Pipe::NS, U = UNR_E;
+    Pipe p;
+#if VMG_EDGE_BLDS
+    p.B = bring + lane;
+#endif
+    p.lf = S.lf;
+    p.lc = S.lc;
+    const int i = Pipe::COL0 + strip * OWN - HALO + lane;
+    p.col_in = i >= 1 && i <= p.lf.nx;
+    p.odd = (i & 1) != 0;
+    const bool ecol = i >= 0 && i <= p.lf.nx + 1;
+    const bool own = lane >= HALO && lane < HALO + OWN && p.col_in;
+    const unsigned es = sizeof(C);
+    p.ox = p.col_in ? i * es : OOB;
+    p.oe = ecol ? (i >> 1) * es : OOB;
+    p.oo = own ? i * es : OOB;
+    p.of = (own && !(i & 1) && (i >> 1) <= p.lc.nx) ? (i >> 1) * es : OOB;
+    p.rx = p.lf.pitch * es;
+    p.rc = p.lc.pitch * es;
+    p.k0 = k0;
+    p.k1 = k1;
+    const int64_t base = (int64_t)sys * p.lf.plane;
+    p.xs = plane_rsrc(S.x + base, p.lf.plane);
+    p.bs = plane_rsrc(S.b + base, p.lf.plane);
+    p.es = plane_rsrc(S.c + (int64_t)sys * p.lc.plane, p.lc.plane);
+    p.xos = plane_rsrc(S.xo + base, p.lf.plane);
+    p.xfs = plane_rsrc(S.xf + base, p.lf.plane);
+    p.cbs = plane_rsrc(S.cb + (int64_t)sys * p.lc.plane, p.lc.plane);
+    p.cf = S.coef[sys];
+    p.dl = p.col_in ? p.cf.d : z2<C>();
+    p.sl = p.col_in ? S.s : (T)0;
+    p.acc = 0.0;
+#pragma unroll
+    for (int q = 0; q <= NS; ++q)
+#pragma unroll
+        for (int w = 0; w < 3; ++w) p.X[q][w] = p.R[q][w] = z2<C>();
+#pragma unroll
+    for (int w = 0; w < 12; ++w) p.B[w * (VMG_EDGE_BLDS ? 64 : 1)] = z2<C>();
+    int jbeg = k0 - 2 * NS - 2;
+    jbeg -= jbeg & 1;
+    const int jend = k1 + 2 * NS + 2;
+    const int jlo = max(k0 + 2 * NS + 2, 2 * NS + 4);
+    const int jhi = min(min(p.lf.ny - U + 1 - EPF, p.lf.ny - U - 1), k1 - U + 1 + 2 * NA);
+    p.ei[0] = p.interp_x(p.template load_e<true>(jbeg >> 1));
+    p.er[1] = p.template load_e<true>((jbeg >> 1) + 1);
+#pragma unroll
+    for (int d = 0; d < EPF; ++d) {
+        p.xr[d] = p.template load_x<true>(jbeg + d);
+        p.br[d] = p.template load_b<true>(jbeg + d - 1);
+    }
+    int j = jbeg;
+    for (; j <= jend && j < jlo; j += U) p.template block<true>(j);
+    for (; j <= jhi; j += U) p.template block<false>(j);
+    for (; j <= jend; j += U) p.template block<true>(j);
+    return own ? p.acc : 0.0;
+}
+
+template <typename T, int NA, int NB>
+__global__ __launch_bounds__(NT) VMG_STREAM_OCC void k_edge(SegTable<T> tab) {
+#if VMG_EDGE_BLDS
+    __shared__ cplx<T> bring[NT / 64][12 * 64];  // right-hand side rows, one ring per wave
+#endif
+    const int gw = (int)xcd_block().x * (NT / 64) + __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int lane = threadIdx.x & 63;
+    const LevelSeg<T> S = seg_of_wave(tab, gw);
+    const int lw = gw - S.w0;
+    if (lw >= S.waves) return;
+    const Piece pc = piece_of(S, lw);
+    if (!S.active[pc.sys]) return;
+#if VMG_EDGE_BLDS
+    double acc = edge_piece<T, NA, NB>(S, pc.sys, pc.strip, pc.k0, pc.k1, lane, bring[threadIdx.x >> 6]);
+#else
+    double acc = edge_piece<T, NA, NB>(S, pc.sys, pc.strip, pc.k0, pc.k1, lane, nullptr);
+#endif
+    if (S.partial) {
+        for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+        if (lane == 0) S.partial[pc.slot] = acc;
+    }
+}
+
 template <typename T>
 __global__ __launch_bounds__(NT) void k_fill_zero(cplx<T>* __restrict__ x, LevelView lv) {
     const int i = blockIdx.x * 64 + (threadIdx.x & 63) + 1;
@@ -690,7 +925,40 @@ template <typename T, int NS, bool NORM> void up_go(SegTable<T> tab, const int* 
     hipLaunchKernelGGL((k_up<T, NS, NORM>), g, dim3(NT), 0, st, tab);
 }
 
+template <typename T, int NA, int NB> void edge_go(SegTable<T> tab, const int* nsys, int rmin, hipStream_t st) {
+    using Pipe = EdgePipe<T, NA, NB>;
+    const void* k = (const void*)&k_edge<T, NA, NB>;
+    const dim3 g = stream_seg_grid(tab, nsys, Pipe::OWN, Pipe::COL0, 4 * Pipe::NS + 9, rmin, resident_waves(k));
+    if (g.x == 0) return;
+    hipLaunchKernelGGL((k_edge<T, NA, NB>), g, dim3(NT), 0, st, tab);
+}
+
+template <typename T, int NA, int NB> int edge_tiles_of(int nx, int ny, int nsys, int rmin) {
+    using Pipe = EdgePipe<T, NA, NB>;
+    const RunGeom g = run_geom(nx, ny, nsys, Pipe::OWN, Pipe::COL0, 4 * Pipe::NS + 9, rmin,
+                               resident_waves((const void*)&k_edge<T, NA, NB>));
+    return g.strips * g.pieces;
+}
+
 }  // namespace
+
+bool edge_supported(int nu1, int nu2) { return nu1 >= 1 && nu1 <= 2 && nu2 >= 1 && nu2 <= 2; }
+
+template <typename T> void launch_edge(SegTable<T> tab, const int* nsys, int nu1, int nu2, int rmin, hipStream_t st) {
+    if (nu2 == 1 && nu1 == 1) edge_go<T, 1, 1>(tab, nsys, rmin, st);
+    else if (nu2 == 1 && nu1 == 2) edge_go<T, 1, 2>(tab, nsys, rmin, st);
+    else if (nu2 == 2 && nu1 == 1) edge_go<T, 2, 1>(tab, nsys, rmin, st);
+    else edge_go<T, 2, 2>(tab, nsys, rmin, st);
+}
+template void launch_edge<double>(SegTable<double>, const int*, int, int, int, hipStream_t);
+
+template <typename T> int edge_tiles(int nx, int ny, int nsys, int nu1, int nu2, int rmin) {
+    if (nu2 == 1 && nu1 == 1) return edge_tiles_of<T, 1, 1>(nx, ny, nsys, rmin);
+    if (nu2 == 1 && nu1 == 2) return edge_tiles_of<T, 1, 2>(nx, ny, nsys, rmin);
+    if (nu2 == 2 && nu1 == 1) return edge_tiles_of<T, 2, 1>(nx, ny, nsys, rmin);
+    return edge_tiles_of<T, 2, 2>(nx, ny, nsys, rmin);
+}
+template int edge_tiles<double>(int, int, int, int, int, int);
 
 template <typename T> int stream_tiles(int nx, int ny, int nsys, int nu, int rmin) {
     const void* k;
@@ -717,10 +985,14 @@ void stream_prepare() {
     VMG_PREP(double);
     VMG_PREP(float);
 #undef VMG_PREP
+    resident_waves((const void*)&k_edge<double, 1, 1>), resident_waves((const void*)&k_edge<double, 1, 2>),
+        resident_waves((const void*)&k_edge<double, 2, 1>), resident_waves((const void*)&k_edge<double, 2, 2>);
 }
 
 int stream_tiles_max(int nx, int ny, int nu) {
-    const int own = nu == 0 ? up_own<0, true>() : (nu == 1 ? up_own<1, true>() : up_own<2, true>());
+    // the narrowest strips of any kernel that forms the norm: the cycle-edge kernel's
+    const int own = std::min(EdgePipe<double, 2, 2>::OWN,
+                             nu == 0 ? up_own<0, true>() : (nu == 1 ? up_own<1, true>() : up_own<2, true>()));
     return ((nx + own) / own) * std::max(1, ny / MIN_RUN);
 }
 template int stream_tiles<float>(int, int, int, int, int);
