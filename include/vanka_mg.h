@@ -300,7 +300,8 @@ int vanka_mg_last_stats(vmg_handle* h, int32_t* iters, double* relres, void* hip
  * Autotuner: for every grid and level above the coarsest, time each kernel
  * schedule on the handle's own buffers (the LDS-tiled sweep / restriction /
  * prolongation kernels, or the fused streaming kernels with 32, 64 or 128
- * rows per block) and keep the fastest.  cache_path (host string, NULL = no
+ * rows per block; on the finest level also the cycle-edge kernel, see
+ * vanka_mg_plan) and keep the fastest.  cache_path (host string, NULL = no
  * cache) is a text file of earlier choices keyed by device, precision, grid,
  * system count and smoothing counts; new choices are appended.  Results of
  * later solves are identical under every schedule up to rounding order.
@@ -311,6 +312,19 @@ int vanka_mg_autotune(vmg_handle* h, const char* cache_path, void* hip_stream);
 /* Schedule in use for grid g, levels 0..nlev-1: 0 = LDS-tiled kernels, r > 0
  * = streaming kernels with r rows per block, -1 = coarsest / beyond. */
 int vanka_mg_schedule(const vmg_handle* h, int32_t g, int32_t nlev, int32_t* sched);
+
+/* Fused kernels in use for grid g (host outputs): *edge = 1 when the finest
+ * level runs across the boundary of two V-cycles in one launch (FP64 cycles
+ * with 1 or 2 pre- and post-smoothing steps and a streamed finest level),
+ * else 0; *tail_level = the first level whose work (down to the coarsest
+ * solve and back) runs in one workgroup per system, -1 when none does.
+ * Either pointer may be NULL.  Untuned, the cycle-edge kernel runs on grids
+ * whose finest levels hold at least 16M nodes over all systems;
+ * vanka_mg_autotune times it against the separate launches per grid.
+ * Environment switches read at setup: VMG_EDGE=0 turns it off, VMG_EDGE=2
+ * uses it wherever it applies; VMG_TAIL=0 turns the tail kernel off.
+ * Returns VMG_OK or VMG_INVALID_ARG. */
+int vanka_mg_plan(const vmg_handle* h, int32_t g, int32_t* edge, int32_t* tail_level);
 
 /* Levels of grid g: writes count and, if non-NULL, nx/ny per level. */
 int vanka_mg_levels(const vmg_handle* h, int32_t g, int32_t* count, int32_t* nx, int32_t* ny);

@@ -30,7 +30,7 @@ NUM_KCLASS = len(KERNEL_CLASSES)
 EXPORTED = ["vanka_mg_default_opts", "vanka_mg_setup", "vanka_mg_solve", "paradiag_apply",
             "vanka_mg_shift_gradient", "paradiag_heat_residual", "paradiag_heat_solve", "paradiag_heat_gmres",
             "paradiag_transform", "vanka_mg_apply_op", "vanka_mg_set_timing", "vanka_mg_kernel_stats",
-            "vanka_mg_level_stats", "vanka_mg_autotune", "vanka_mg_schedule", "vanka_mg_set_omega",
+            "vanka_mg_level_stats", "vanka_mg_autotune", "vanka_mg_schedule", "vanka_mg_plan", "vanka_mg_set_omega",
             "vanka_mg_levels", "vanka_mg_last_stats", "vanka_mg_destroy", "vanka_mg_error_string"]
 
 
@@ -80,6 +80,7 @@ def load():
     lib.vanka_mg_autotune.argtypes = [vp, ctypes.c_char_p, vp]
     lib.vanka_mg_set_omega.argtypes = [vp, pdbl]
     lib.vanka_mg_schedule.argtypes = [vp, i32, i32, pi32]
+    lib.vanka_mg_plan.argtypes = [vp, i32, pi32, pi32]
     lib.vanka_mg_last_stats.argtypes = [vp, pi32, pdbl, vp]
     lib.vanka_mg_destroy.argtypes = [vp]
     lib.vanka_mg_error_string.argtypes = [ctypes.c_int]

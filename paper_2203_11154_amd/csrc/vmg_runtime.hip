@@ -79,6 +79,7 @@ struct Group {
     int nact = 0;   // systems active at the last host check (for byte accounting)
     std::vector<int> sched;  // per level: 0 = LDS-tiled kernels, r > 0 = streaming with r rows; empty = heuristic
     int tail_lt = -1;        // first level run by the tail kernel (-1: none)
+    int edge = -1;           // cycle-edge kernel: -1 untuned (used where possible), 0 off, 1 on
     int64_t tail_lds = 0;    // its dynamic LDS bytes
 };
 
@@ -117,7 +118,8 @@ struct vmg_handle {
     int* nanflag = nullptr;
     int stream_rows = 0;       // rows per block of the streaming kernels (0: by level size)
     bool tail_on = true;       // small levels in one workgroup per system (VMG_TAIL=0 turns it off)
-    bool edge_on = true;       // finest level across the cycle boundary in one pass (VMG_EDGE=0 turns it off)
+    int edge_mode = 1;         // finest level across the cycle boundary in one pass: VMG_EDGE=0 off,
+                               // 1 (default) on large finest levels or as autotuned, 2 wherever possible
     void* tail_dev[2] = {nullptr, nullptr};  // TailSeg<T> per grid, T of the cycle precision [conj]
     // pinned host staging
     int* h_int = nullptr;      // 3 * S ints
@@ -378,11 +380,17 @@ bool sched_stream(const vmg_handle* H, const Group& g, int l) {
 // runs with the current kernel schedule.
 bool edge_possible(const vmg_handle* H, const Group& g) {
     const vmg_opts& o = H->opts;
-    return H->edge_on && o.precision == 0 && o.gamma == 1 && edge_supported(o.nu1, o.nu2) && g.L >= 2;
+    return H->edge_mode != 0 && o.precision == 0 && o.gamma == 1 && edge_supported(o.nu1, o.nu2) && g.L >= 2;
 }
 bool sched_stream(const vmg_handle* H, const Group& g, int l);
+// Untuned, the kernel pays off once the finest levels of all systems hold
+// about 16M nodes or more: below that the runs per wave are short and the
+// halo rows it recomputes cost more than the pass it saves.
+constexpr double EDGE_MIN_NODES = 16.0 * 1024 * 1024;
 bool use_edge(const vmg_handle* H, const Group& g) {
-    return edge_possible(H, g) && g.lv64[0].xf.ptr && g.tail_lt != 0 && sched_stream(H, g, 0);
+    if (!(edge_possible(H, g) && g.lv64[0].xf.ptr && g.tail_lt != 0 && sched_stream(H, g, 0))) return false;
+    if (H->edge_mode == 2 || g.edge == 1) return true;
+    return g.edge < 0 && (double)g.nx * g.ny * g.S >= EDGE_MIN_NODES;
 }
 
 int sched_rows(const vmg_handle* H, const Group& g, int l) {
@@ -1390,7 +1398,7 @@ int vanka_mg_setup(const vmg_grid* grids, int32_t n_grids, const double* shifts,
     }
     H->S = total;
     if (const char* e = std::getenv("VMG_TAIL")) H->tail_on = std::atoi(e) != 0;
-    if (const char* e = std::getenv("VMG_EDGE")) H->edge_on = std::atoi(e) != 0;
+    if (const char* e = std::getenv("VMG_EDGE")) H->edge_mode = std::max(0, std::min(2, std::atoi(e)));
     if (const char* e = std::getenv("VMG_STREAM_ROWS")) {
         const int r = std::atoi(e);
         if (r >= 16 && r <= 4096) H->stream_rows = r;
@@ -1872,6 +1880,8 @@ extern "C" int paradiag_heat_residual(vmg_handle* H, double tau, const double* U
 // ---------------------------------------------------------------------------
 namespace {
 
+template <typename F> int time_reps(F&& run, hipStream_t st, double* ms_out);
+
 // Time one level's work (everything a cycle does on that level apart from the
 // recursion) under schedule `cand` (0: LDS-tiled, r > 0: streaming, r rows).
 template <typename T> int time_level(vmg_handle* H, Group& g, int l, int cand, hipStream_t st, double* ms_out) {
@@ -1897,9 +1907,26 @@ template <typename T> int time_level(vmg_handle* H, Group& g, int l, int cand, h
                 launch_sweep<T>(seg(P<T>(lv.x[i & 1]), P<T>(lv.b), P<T>(lv.x[1 - (i & 1)]), nullptr, 0), &one, st);
         }
     };
-    // the level-0 streaming candidate also forms the norm partial sums
-    double* saved = nullptr;
-    (void)saved;
+    return time_reps(run, st, ms_out);
+}
+
+// Time the finest level's per-cycle work with the cycle-edge kernel: one
+// launch for a cycle's correction and post-smoothing and the next cycle's
+// pre-smoothing and restriction (streaming, `rows` rows per wave).
+int time_edge(vmg_handle* H, Group& g, int rows, hipStream_t st, double* ms_out) {
+    auto& L = g.lv64;
+    const int one = g.S;
+    auto run = [&]() {
+        LevelSeg<double> S = make_seg<double>(H, g, 0, 0, P<double>(L[0].x[0]), P<double>(L[0].b),
+                                              P<double>(L[0].x[1]), P<double>(L[1].x[0]), 0, nullptr);
+        S.xf = P<double>(L[0].xf);
+        S.cb = P<double>(L[1].b);
+        launch_edge<double>(one_seg(S), &one, H->opts.nu1, H->opts.nu2, rows, st);
+    };
+    return time_reps(run, st, ms_out);
+}
+
+template <typename F> int time_reps(F&& run, hipStream_t st, double* ms_out) {
     hipEvent_t a = nullptr, b = nullptr;
     if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) return VMG_HIP_ERROR;
     for (int w = 0; w < 2; ++w) run();
@@ -1924,7 +1951,7 @@ std::string tune_key(const vmg_handle* H, const Group& g, int l) {
         if (ch == ' ') ch = '_';
     std::ostringstream k;
     k << arch << " " << (H->opts.precision == 0 ? "c128" : "c64") << " " << g.nx << " " << g.ny << " " << g.S << " "
-      << H->opts.nu1 << " " << H->opts.nu2 << " " << l;
+      << H->opts.nu1 << " " << H->opts.nu2 << " " << (l < 0 ? std::string("edge") : std::to_string(l));
     return k.str();
 }
 
@@ -1976,6 +2003,26 @@ extern "C" int vanka_mg_autotune(vmg_handle* H, const char* cache_path, void* hi
             g.sched[l] = best;
             fresh.push_back(key + " " + std::to_string(best));
         }
+        // the cycle-edge kernel against the finest level's separate streaming
+        // launches (small grids have too few rows per wave for its halo)
+        g.edge = -1;
+        if (H->edge_mode == 1 && edge_possible(H, g) && g.lv64[0].xf.ptr && g.tail_lt != 0 &&
+            sched_stream(H, g, 0)) {
+            const std::string key = tune_key(H, g, -1);
+            int found = -1;
+            for (auto& e : cache)
+                if (e.first == key) found = e.second;
+            if (found < 0) {
+                const int rows = sched_rows(H, g, 0);
+                double ms_edge = 0.0, ms_sep = 0.0;
+                int rc = time_edge(H, g, rows, st, &ms_edge);
+                if (!rc) rc = time_level<double>(H, g, 0, rows, st, &ms_sep);
+                if (rc) return rc;
+                found = ms_edge < ms_sep ? 1 : 0;
+                fresh.push_back(key + " " + std::to_string(found));
+            }
+            g.edge = found;
+        }
     }
     // launch sequences changed: drop captured cycles
     for (auto& gr : H->graphs) (void)hipGraphExecDestroy(gr.second);
@@ -1997,6 +2044,14 @@ extern "C" int vanka_mg_schedule(const vmg_handle* H, int32_t g, int32_t nlev, i
         }
         sched[l] = sched_stream(H, G, l) ? sched_rows(H, G, l) : 0;
     }
+    return VMG_OK;
+}
+
+extern "C" int vanka_mg_plan(const vmg_handle* H, int32_t g, int32_t* edge, int32_t* tail_level) {
+    if (!H || g < 0 || g >= (int)H->groups.size()) return VMG_INVALID_ARG;
+    const Group& G = H->groups[g];
+    if (edge) *edge = use_edge(H, G) ? 1 : 0;
+    if (tail_level) *tail_level = G.tail_lt;
     return VMG_OK;
 }
 

@@ -128,6 +128,14 @@ class VankaMG:
         if t.numel() != n:
             raise ValueError(f"{name} has {t.numel()} elements, expected {n}")
 
+    def plan(self, g=0):
+        """(edge, tail_level) of grid g: whether the finest level runs across
+        the boundary of two V-cycles in one launch, and the first level run
+        in one workgroup per system (-1: none)."""
+        e, t = ctypes.c_int32(0), ctypes.c_int32(0)
+        _lib.check(self.lib.vanka_mg_plan(self.handle, g, ctypes.byref(e), ctypes.byref(t)), "vanka_mg_plan")
+        return bool(e.value), int(t.value)
+
     def solve(self, B, tol=1e-10, conj=False, fixed_iters=None, out=None):
         """Solve every system; B holds all systems concatenated (any shape with
         the right number of elements).  Returns (Z, iters, relres, status)."""

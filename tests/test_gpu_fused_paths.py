@@ -1,0 +1,126 @@
+"""The fused kernels (the cycle-edge kernel on the finest level and the tail
+kernel on the small levels) against the level-by-level kernels they replace:
+the same iterates at fixed cycle counts, up to rounding order, for single
+grids and batches of uneven grids; and after autotuning, which may switch
+the cycle-edge kernel off per grid, the same results again."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import multigrid as omg
+from paper_2203_11154_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(np.asarray(a, dtype=np.complex128))).to("cuda")
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+CASES = [
+    ([(255, 255, 3)], 2, 2),
+    ([(255, 255, 2)], 1, 1),
+    ([(383, 191, 2), (127, 127, 3), (255, 255, 1)], 2, 1),
+    ([(511, 511, 1), (223, 111, 2)], 1, 2),
+]
+
+
+def build(grids, nu1, nu2, monkeypatch, fused, edge="2"):
+    """edge: "2" uses the cycle-edge kernel wherever it applies, "1" on large
+    grids or as autotuned (the default)."""
+    from paper_2203_11154_amd import Grid, VankaMG
+    monkeypatch.setenv("VMG_EDGE", edge if fused else "0")
+    monkeypatch.setenv("VMG_TAIL", "1" if fused else "0")
+    gs = [Grid(nx, ny, num_systems=S) for nx, ny, S in grids]
+    lam = inputs.alpha_circulant_shifts(sum(S for _, _, S in grids))
+    return VankaMG(gs, lam, nu1=nu1, nu2=nu2), lam
+
+
+@pytest.mark.parametrize("grids,nu1,nu2", CASES)
+def test_fused_equals_level_by_level(grids, nu1, nu2, monkeypatch):
+    fused, lam = build(grids, nu1, nu2, monkeypatch, True)
+    plain, _ = build(grids, nu1, nu2, monkeypatch, False)
+    for g in range(len(grids)):
+        e, t = fused.plan(g)
+        assert e and t > 0, (g, e, t)
+        assert plain.plan(g) == (False, -1)
+    S = sum(s for _, _, s in grids)
+    b = np.concatenate([inputs.rhs(s, ny, nx, seed=60 + k).ravel() for k, (nx, ny, s) in enumerate(grids)])
+    bd = dev(b)
+    for cycles in (1, 2, 5):
+        fi = np.full(S, cycles, dtype=np.int32)
+        Zf, itf, rrf, _ = fused.solve(bd, fixed_iters=fi)
+        Zp, itp, rrp, _ = plain.solve(bd, fixed_iters=fi)
+        np.testing.assert_array_equal(itf, fi)
+        zf, zp = host(Zf), host(Zp)
+        off = 0
+        for nx, ny, s in grids:
+            n = nx * ny
+            for j in range(s):
+                a, r = zf[off:off + n], zp[off:off + n]
+                assert np.linalg.norm(a - r) <= 1e-12 * np.linalg.norm(r), (nx, ny, j, cycles)
+                off += n
+        np.testing.assert_allclose(rrf, rrp, rtol=1e-9)
+    # free-running solves stop after the same counts
+    Zf, itf, rrf, stf = fused.solve(bd, tol=1e-10)
+    Zp, itp, rrp, stp = plain.solve(bd, tol=1e-10)
+    assert stf == 0 and stp == 0
+    np.testing.assert_array_equal(itf, itp)
+
+
+def test_fused_against_oracle_uneven_batch(monkeypatch):
+    """One grid of the uneven batch with both fused kernels, at the oracle's
+    cycle count, against the oracle's V(2,1) cycles."""
+    grids, nu1, nu2 = CASES[2]
+    fused, lam = build(grids, nu1, nu2, monkeypatch, True)
+    S = sum(s for _, _, s in grids)
+    b = np.concatenate([inputs.rhs(s, ny, nx, seed=70 + k).ravel() for k, (nx, ny, s) in enumerate(grids)])
+    Z, it, rr, _ = fused.solve(dev(b), fixed_iters=np.full(S, 3, dtype=np.int32))
+    nx, ny, s = grids[1]
+    off = grids[0][0] * grids[0][1] * grids[0][2]
+    z = host(Z)[off:off + nx * ny * s].reshape(s, ny, nx)
+    bb = b[off:off + nx * ny * s].reshape(s, ny, nx)
+    lg = lam[grids[0][2]:grids[0][2] + s]
+    zr, _, _, _ = omg.solve(bb, lg, 1.0 / (nx + 1), fixed_iters=np.full(s, 3), nu1=nu1, nu2=nu2)
+    for j in range(s):
+        assert np.linalg.norm(z[j] - zr[j]) <= 1e-11 * np.linalg.norm(zr[j])
+
+
+def test_autotune_keeps_results(monkeypatch, tmp_path):
+    """Autotuning (per-level schedules and the per-grid choice of the
+    cycle-edge kernel) changes only the rounding order; a second handle
+    reads the same choices back from the cache file."""
+    grids, nu1, nu2 = [(127, 127, 8), (1023, 1023, 2)], 2, 2
+    fused, lam = build(grids, nu1, nu2, monkeypatch, True, edge="1")
+    assert [fused.plan(g)[0] for g in range(len(grids))] == [False, False]  # untuned: too small
+    S = sum(s for _, _, s in grids)
+    b = np.concatenate([inputs.rhs(s, ny, nx, seed=80 + k).ravel() for k, (nx, ny, s) in enumerate(grids)])
+    bd = dev(b)
+    fi = np.full(S, 4, dtype=np.int32)
+    Z0, _, rr0, _ = fused.solve(bd, fixed_iters=fi)
+    z0 = host(Z0)
+    cache = tmp_path / "tune.txt"
+    fused.autotune(cache)
+    plans = [fused.plan(g) for g in range(len(grids))]
+    Z1, _, rr1, _ = fused.solve(bd, fixed_iters=fi)
+    z1 = host(Z1)
+    off = 0
+    for nx, ny, s in grids:
+        for j in range(s):
+            n = nx * ny
+            assert np.linalg.norm(z1[off:off + n] - z0[off:off + n]) <= 1e-12 * np.linalg.norm(z0[off:off + n])
+            off += n
+    np.testing.assert_allclose(rr1, rr0, rtol=1e-9)
+    # the edge choice is timed for grids whose finest level stayed streamed
+    streamed = sum(1 for g in range(len(grids)) if fused.schedule(g)[0] > 0)
+    assert sum(1 for line in cache.read_text().splitlines() if " edge " in line) == streamed
+    again, _ = build(grids, nu1, nu2, monkeypatch, True, edge="1")
+    again.autotune(cache)
+    assert [again.plan(g) for g in range(len(grids))] == plans
+    assert [again.schedule(g) for g in range(len(grids))] == [fused.schedule(g) for g in range(len(grids))]

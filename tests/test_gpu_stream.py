@@ -131,13 +131,18 @@ def test_streamed_full_size_sampled_sweep_and_solve():
     assert np.all(err <= 1e-7)
 
 
+@pytest.mark.parametrize("edge", ["0", "2"])
 @pytest.mark.parametrize("nu1,nu2", [(2, 2), (1, 1), (0, 1)])
-def test_fused_norm_equals_host_residual(nu1, nu2):
+def test_fused_norm_equals_host_residual(nu1, nu2, edge, monkeypatch):
     """The stopping-test norm that the finest-level streaming kernel forms
     equals the residual norm of the iterate it writes, recomputed on the host
     in FP64, after 1 and 2 cycles (large residuals, so no cancellation noise):
-    every owned column of every strip carries exactly its own residual."""
+    every owned column of every strip carries exactly its own residual.
+    edge = "2": the norm formed by the cycle-edge kernel (where it applies)."""
+    monkeypatch.setenv("VMG_EDGE", edge)
     solver, lam = make(nu1, nu2)
+    if edge == "2" and nu1 > 0:
+        assert all(solver.plan(g)[0] for g in range(len(GRIDS)))
     bs = [inputs.rhs(g["S"], g["ny"], g["nx"], seed=50 + k) for k, g in enumerate(GRIDS)]
     bd = dev(np.concatenate([b.ravel() for b in bs]))
     S = sum(g["S"] for g in GRIDS)
