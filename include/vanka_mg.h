@@ -278,7 +278,9 @@ enum {
     VMG_K_COARSE = 4, VMG_K_PACK = 5, VMG_K_TRANSFORM = 6, VMG_K_IR = 7,
     VMG_K_DOWN = 8,   /* fused pre-smoothing + residual + restriction */
     VMG_K_UP = 9,     /* fused correction + post-smoothing (+ norm)    */
-    VMG_NUM_KCLASS = 10
+    VMG_K_EDGE = 10,  /* finest level across two V-cycles: correction, post-smoothing, norm,
+                         pre-smoothing, residual, restriction in one pass */
+    VMG_NUM_KCLASS = 11
 };
 int vanka_mg_set_timing(vmg_handle* h, int32_t enable, int32_t reset);
 int vanka_mg_kernel_stats(vmg_handle* h, int64_t* launches /* [VMG_NUM_KCLASS] */,

@@ -24,7 +24,7 @@ OP_PROLONG_CORRECT = 3
 OP_COARSE_SOLVE = 4
 OP_CYCLE = 5
 
-KERNEL_CLASSES = ["sweep", "restrict", "prolong", "norm", "coarse", "pack", "transform", "ir", "down", "up"]
+KERNEL_CLASSES = ["sweep", "restrict", "prolong", "norm", "coarse", "pack", "transform", "ir", "down", "up", "edge"]
 NUM_KCLASS = len(KERNEL_CLASSES)
 
 EXPORTED = ["vanka_mg_default_opts", "vanka_mg_setup", "vanka_mg_solve", "paradiag_apply",

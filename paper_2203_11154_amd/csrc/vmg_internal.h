@@ -42,8 +42,13 @@ template <typename T> struct LevelSeg {
     cplx<T>* xo;          // iterate written
     cplx<T>* c;           // coarse right-hand side written (restriction) or
                           // coarse correction read (prolongation)
-    cplx<T>* xf;          // cycle-edge kernel: the finished iterate written
     cplx<T>* cb;          // cycle-edge kernel: the next coarse right-hand side
+    // finishing pass of the streaming correction + post-smoothing kernel (finest
+    // level after cycle-edge cycles), else NULL: cycles run per system, the
+    // iterate read after an odd count (x after an even one), dense destination
+    const int* iters;
+    const cplx<T>* xalt;
+    cplx<T>* zd;
     LevelView lf, lc;     // this level and the next coarser one
     T s;                  // 1 / h^2 of this level
     const Coef<T>* coef;  // per system of the segment
@@ -178,6 +183,9 @@ void launch_transform(int n, int64_t m, const double2* M, int trans_conj, const 
 //         |b - L xo|^2 go to a segment's partial buffer when that pointer is
 //         not NULL (partial[sys * tiles + t], tiles = stream_tiles(...)).
 //         `norm` selects the geometry with the extra halo lane the norm needs.
+//         Finishing pass (segment's iters set, norm off): runs for every
+//         system whatever its active flag, reads x or xalt by the parity of
+//         iters[sys] (zero result for 0) and writes the dense rows of zd.
 // The work of a level is split evenly over the device's resident waves, with
 // at least rmin rows per wave.
 template <typename T> void launch_down(SegTable<T> tab, const int* nsys, int nu, int rmin, hipStream_t st);
@@ -185,8 +193,10 @@ template <typename T> void launch_up(SegTable<T> tab, const int* nsys, int nu, b
 template <typename T> int stream_tiles(int nx, int ny, int nsys, int nu, int rmin);
 int stream_tiles_max(int nx, int ny, int nu);  // over every rmin and kernel
 // Cycle-edge kernel (FP64 finest level, nu1, nu2 in {1, 2}): correction +
-// nu2 sweeps -> xf, norm partials (edge_tiles per system), nu1 sweeps -> xo,
-// full weighting -> cb; reads x, b and the coarse correction c.
+// nu2 sweeps, norm partials of that iterate (edge_tiles per system), nu1
+// sweeps -> xo, full weighting -> cb; reads x, b and the coarse correction c
+// and leaves them untouched (the finishing pass of launch_up rebuilds the
+// last cycle's iterate from them).
 bool edge_supported(int nu1, int nu2);
 template <typename T> void launch_edge(SegTable<T> tab, const int* nsys, int nu1, int nu2, int rmin, hipStream_t st);
 template <typename T> int edge_tiles(int nx, int ny, int nsys, int nu1, int nu2, int rmin);

@@ -61,7 +61,6 @@ struct Level {
     double h = 0;
     DevBuf x[2];
     DevBuf b;
-    DevBuf xf;  // finest level with the cycle-edge kernel: the finished iterate
 };
 
 struct Group {
@@ -80,6 +79,7 @@ struct Group {
     std::vector<int> sched;  // per level: 0 = LDS-tiled kernels, r > 0 = streaming with r rows; empty = heuristic
     int tail_lt = -1;        // first level run by the tail kernel (-1: none)
     int edge = -1;           // cycle-edge kernel: -1 untuned (used where possible), 0 off, 1 on
+    int edge_c = 0;          // level-1 buffer holding the coarse correction the cycle-edge kernel reads
     int64_t tail_lds = 0;    // its dynamic LDS bytes
 };
 
@@ -388,7 +388,7 @@ bool sched_stream(const vmg_handle* H, const Group& g, int l);
 // halo rows it recomputes cost more than the pass it saves.
 constexpr double EDGE_MIN_NODES = 16.0 * 1024 * 1024;
 bool use_edge(const vmg_handle* H, const Group& g) {
-    if (!(edge_possible(H, g) && g.lv64[0].xf.ptr && g.tail_lt != 0 && sched_stream(H, g, 0))) return false;
+    if (!(edge_possible(H, g) && g.tail_lt != 0 && sched_stream(H, g, 0))) return false;
     if (H->edge_mode == 2 || g.edge == 1) return true;
     return g.edge < 0 && (double)g.nx * g.ny * g.S >= EDGE_MIN_NODES;
 }
@@ -741,13 +741,13 @@ void enqueue_batched_vcycle(vmg_handle* H, int conj, hipStream_t st, bool first,
                 }
                 LevelSeg<T> S = make_seg<T>(H, g, conj, 0, P<T>(L[0].x[cur[gi][0]]), P<T>(L[0].b),
                                             P<T>(L[0].x[1 - cur[gi][0]]), P<T>(L[1].x[cur[gi][1]]), 0, partials[gi]);
-                S.xf = P<T>(L[0].xf);
                 S.cb = P<T>(L[1].b);
-                bt.add(S, g.S, bytes_of(g, 0, 2.0 + 0.25 + 2.0 + 0.25));
+                g.edge_c = cur[gi][1];  // the same every cycle (coarse levels restart from buffer 0)
+                bt.add(S, g.S, bytes_of(g, 0, 2.0 + 0.25 + 1.0 + 0.25));
                 done.push_back(gi);
             }
             {
-                Timer t(H, st, VMG_K_UP, bt.bytes, 0);
+                Timer t(H, st, VMG_K_EDGE, bt.bytes, 0);
                 launch_edge_t<T>(bt.tab, bt.nsys, o.nu1, o.nu2, ty, st);
             }
             for (int gi : done) {
@@ -1112,11 +1112,20 @@ int solve_impl(vmg_handle* H, const double* B, double* Z, double tol, int conj, 
     off = 0;
     for (auto& g : H->groups) {
         Level& l0 = g.lv64[0];
-        Timer t(H, st, VMG_K_PACK, 32.0 * nodes(l0.v) * g.S);
-        if (use_edge(H, g)) {  // every cycle leaves its finished iterate in xf
-            launch_unpack<double>(P<double>(l0.xf), nullptr, reinterpret_cast<double2*>(Z) + off, l0.v, g.S,
-                                  H->iters + g.sys0, 0, st);
+        if (use_edge(H, g)) {
+            // the last cycle's correction and post-smoothing, rebuilt from the
+            // inputs its cycle-edge pass read (frozen since the system
+            // stopped), written straight into Z
+            Timer t(H, st, VMG_K_UP, 52.0 * nodes(l0.v) * g.S, 0);
+            LevelSeg<double> S = make_seg<double>(H, g, conj, 0, P<double>(l0.x[0]), P<double>(l0.b), nullptr,
+                                                  P<double>(g.lv64[1].x[g.edge_c]), 0, nullptr);
+            S.xalt = P<double>(l0.x[1]);
+            S.iters = H->iters + g.sys0;
+            S.zd = reinterpret_cast<double2*>(Z) + off;
+            const int one = g.S;
+            launch_up<double>(one_seg(S), &one, o.nu2, false, sched_rows(H, g, 0), st);
         } else {
+            Timer t(H, st, VMG_K_PACK, 32.0 * nodes(l0.v) * g.S);
             const int flips = o.precision == 0 ? level0_flips(H, g) : 0;
             launch_unpack<double>(P<double>(l0.x[0]), o.precision == 0 ? P<double>(l0.x[1]) : nullptr,
                                   reinterpret_cast<double2*>(Z) + off, l0.v, g.S, H->iters + g.sys0, flips, st);
@@ -1433,7 +1442,6 @@ int vanka_mg_setup(const vmg_grid* grids, int32_t n_grids, const double* shifts,
             VMG_TRY(alloc_planes<double>(H, L.x[0], L.v, G.S));
             if (o.precision == 0) VMG_TRY(alloc_planes<double>(H, L.x[1], L.v, G.S));
             VMG_TRY(alloc_planes<double>(H, L.b, L.v, G.S));
-            if (l == 0 && edge_possible(H, G)) VMG_TRY(alloc_planes<double>(H, L.xf, L.v, G.S));
         }
         for (size_t l = 0; l < G.lv32.size(); ++l) {
             Level& L = G.lv32[l];
@@ -1919,7 +1927,6 @@ int time_edge(vmg_handle* H, Group& g, int rows, hipStream_t st, double* ms_out)
     auto run = [&]() {
         LevelSeg<double> S = make_seg<double>(H, g, 0, 0, P<double>(L[0].x[0]), P<double>(L[0].b),
                                               P<double>(L[0].x[1]), P<double>(L[1].x[0]), 0, nullptr);
-        S.xf = P<double>(L[0].xf);
         S.cb = P<double>(L[1].b);
         launch_edge<double>(one_seg(S), &one, H->opts.nu1, H->opts.nu2, rows, st);
     };
@@ -2006,8 +2013,7 @@ extern "C" int vanka_mg_autotune(vmg_handle* H, const char* cache_path, void* hi
         // the cycle-edge kernel against the finest level's separate streaming
         // launches (small grids have too few rows per wave for its halo)
         g.edge = -1;
-        if (H->edge_mode == 1 && edge_possible(H, g) && g.lv64[0].xf.ptr && g.tail_lt != 0 &&
-            sched_stream(H, g, 0)) {
+        if (H->edge_mode == 1 && edge_possible(H, g) && g.tail_lt != 0 && sched_stream(H, g, 0)) {
             const std::string key = tune_key(H, g, -1);
             int found = -1;
             for (auto& e : cache)

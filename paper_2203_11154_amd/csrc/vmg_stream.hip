@@ -439,7 +439,7 @@ struct UpPipe {
     int k0, k1;
     bool col_in, odd;
     unsigned ox, oe, oo;  // lane byte offsets: x and b, coarse e, x written (or OOB)
-    unsigned rx, rc;
+    unsigned rx, rc, ro;  // row strides in bytes: x and b, coarse e, x written
     double acc;
 
     template <bool EDGE> __device__ __forceinline__ C load_x(int j) const {
@@ -509,8 +509,8 @@ struct UpPipe {
         }
         pin(X[0][n0]);
         const int orow = j - 2 * NS;
-        if constexpr (EDGE) bstore(xos, oo + (orow >= k0 && orow <= k1 ? orow * rx : OOB), 0, X[NS][n0]);
-        else bstore(xos, oo, orow * rx, X[NS][n0]);
+        if constexpr (EDGE) bstore(xos, oo + (orow >= k0 && orow <= k1 ? orow * ro : OOB), 0, X[NS][n0]);
+        else bstore(xos, oo, orow * ro, X[NS][n0]);
     }
     template <bool EDGE> __device__ __forceinline__ void block(int j) {
         step<0, EDGE>(j);
@@ -552,10 +552,29 @@ __device__ __forceinline__ double up_piece(const LevelSeg<T>& S, int sys, int st
     p.k0 = k0;
     p.k1 = k1;
     const int64_t base = (int64_t)sys * p.lf.plane;
-    p.xs = plane_rsrc(S.x + base, p.lf.plane);
-    p.bs = plane_rsrc(S.b + base, p.lf.plane);
-    p.es = plane_rsrc(S.c + (int64_t)sys * p.lc.plane, p.lc.plane);
-    p.xos = plane_rsrc(S.xo + base, p.lf.plane);
+    // finishing pass (S.iters set): the iterate read is the one the system's
+    // last cycle-edge pass read, x after an even number of cycles and xalt
+    // after an odd one; no cycle at all means a zero result (every read
+    // through an empty range returns zero)
+    const C* xsrc = S.x;
+    int64_t len = p.lf.plane, clen = p.lc.plane;
+    if (S.iters) {
+        const int it = S.iters[sys];
+        if (it & 1) xsrc = S.xalt;
+        if (it == 0) len = clen = 0;
+    }
+    p.xs = plane_rsrc(xsrc + base, len);
+    p.bs = plane_rsrc(S.b + base, len);
+    p.es = plane_rsrc(S.c + (int64_t)sys * p.lc.plane, clen);
+    if (S.zd) {
+        // dense rows of nx nodes: row r, column i (both from 1) at (r - 1) nx + i - 1
+        const int64_t m = (int64_t)p.lf.nx * p.lf.ny;
+        p.xos = plane_rsrc(S.zd + sys * m - (p.lf.nx + 1), m + p.lf.nx + 1);
+        p.ro = p.lf.nx * es;
+    } else {
+        p.xos = plane_rsrc(S.xo + base, p.lf.plane);
+        p.ro = p.rx;
+    }
     p.cf = S.coef[sys];
     p.dl = p.col_in ? p.cf.d : z2<C>();
     p.sl = p.col_in ? S.s : (T)0;
@@ -599,7 +618,7 @@ __global__ __launch_bounds__(NT) VMG_STREAM_OCC void k_up(SegTable<T> tab) {
     const int lw = gw - S.w0;
     if (lw >= S.waves) return;  // whole wave idle; no block barriers in this kernel
     const Piece pc = piece_of(S, lw);
-    if (!S.active[pc.sys]) return;
+    if (!S.iters && !S.active[pc.sys]) return;  // (the finishing pass runs for every system)
     double acc = 0.0;
     if (pc.k0 <= pc.k1) acc = up_piece<T, NS, NORM>(S, pc.sys, pc.strip, pc.k0, pc.k1, lane);
     if (NORM && S.partial) {
@@ -610,13 +629,15 @@ __global__ __launch_bounds__(NT) VMG_STREAM_OCC void k_up(SegTable<T> tab) {
 
 // ---------------------------------------------------------------------------
 // Finest level at the boundary of two V-cycles, in one pass: the bilinear
-// correction and NA post-smoothing sweeps that end cycle k (iterate written to
-// xf), the residual norm of that iterate (the stopping test), then NB
-// pre-smoothing sweeps of cycle k+1 from it (written to xo), their residual
-// and its full weighting (the next coarse right-hand side, written to cb).
-// Reads x, b and the coarse correction once instead of twice per cycle; if
-// the stopping test ends the solve, the pre-smoothed iterate is not used.
-// Unrolled by 12 steps: the right-hand side ring needs 2(NA+NB)+1 rows.
+// correction and NA post-smoothing sweeps that end cycle k, the residual norm
+// of that iterate (the stopping test), then NB pre-smoothing sweeps of cycle
+// k+1 from it (written to xo), their residual and its full weighting (the
+// next coarse right-hand side, written to cb).  Reads x, b and the coarse
+// correction once instead of twice per cycle.  Cycle k's finished iterate is
+// not stored: once a system stops, its inputs to this pass (x and the coarse
+// correction) are left untouched, and the finishing pass of k_up rebuilds the
+// iterate from them once.  Unrolled by 12 steps: the right-hand side ring
+// needs 2(NA+NB)+1 rows.
 constexpr int UNR_E = 12;
 #ifndef VMG_EDGE_PF
 #define VMG_EDGE_PF 1
@@ -645,7 +666,7 @@ struct EdgePipe {
 #endif
     C xr[EPF + 1], br[EPF + 1];
     C er[3], ei[3];
-    rsrc_t xs, bs, es, xos, xfs, cbs;
+    rsrc_t xs, bs, es, xos, cbs;
     LevelView lf, lc;
     Coef<T> cf;
     C dl;
@@ -729,7 +750,6 @@ struct EdgePipe {
             }
         }
         pin(X[0][n0]);
-        store_row<EDGE>(xfs, j - 2 * NA, X[NA][n0]);
         store_row<EDGE>(xos, j - 2 * NS, X[NS][n0]);
         if constexpr ((P & 1) == 0) {
             const int frow = j - 2 * NS - 2;
@@ -781,7 +801,6 @@ __device__ __forceinline__ double edge_piece(const LevelSeg<T>& S, int sys, int 
     p.bs = plane_rsrc(S.b + base, p.lf.plane);
     p.es = plane_rsrc(S.c + (int64_t)sys * p.lc.plane, p.lc.plane);
     p.xos = plane_rsrc(S.xo + base, p.lf.plane);
-    p.xfs = plane_rsrc(S.xf + base, p.lf.plane);
     p.cbs = plane_rsrc(S.cb + (int64_t)sys * p.lc.plane, p.lc.plane);
     p.cf = S.coef[sys];
     p.dl = p.col_in ? p.cf.d : z2<C>();

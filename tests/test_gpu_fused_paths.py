@@ -53,8 +53,11 @@ def test_fused_equals_level_by_level(grids, nu1, nu2, monkeypatch):
     S = sum(s for _, _, s in grids)
     b = np.concatenate([inputs.rhs(s, ny, nx, seed=60 + k).ravel() for k, (nx, ny, s) in enumerate(grids)])
     bd = dev(b)
-    for cycles in (1, 2, 5):
-        fi = np.full(S, cycles, dtype=np.int32)
+    # equal counts, then per-system counts of both parities and zero (the
+    # finishing pass picks each system's frozen buffers by its own count)
+    for fi in (np.full(S, 1, np.int32), np.full(S, 2, np.int32), np.full(S, 5, np.int32),
+               (np.arange(S) % 4).astype(np.int32), (np.arange(S) % 4 + 3).astype(np.int32)):
+        cycles = fi.tolist()
         Zf, itf, rrf, _ = fused.solve(bd, fixed_iters=fi)
         Zp, itp, rrp, _ = plain.solve(bd, fixed_iters=fi)
         np.testing.assert_array_equal(itf, fi)
