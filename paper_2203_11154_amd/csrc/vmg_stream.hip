@@ -96,11 +96,15 @@ template <typename C> __device__ __forceinline__ C from_right(C v) {
 template <typename C> __device__ __forceinline__ C lr_sum(C v) { return add(from_left(v), from_right(v)); }
 
 // Residual of a middle row: b - (d x - s (W + E + N + S)), from the rows
-// above (xo), at (xm) and below (xn).
+// above (xo), at (xm) and below (xn); three fused multiply-adds a component
+// after the neighbour sum.
 template <typename T, typename C>
 __device__ __forceinline__ C residual_row(C xo, C xm, C xn, C bv, C d, T s) {
     const C nb = add(lr_sum(xm), add(xo, xn));
-    return sub(bv, sub(mul(d, xm), scl(nb, s)));
+    C r;
+    r.x = __builtin_fma(d.y, xm.y, __builtin_fma(-d.x, xm.x, __builtin_fma(s, nb.x, bv.x)));
+    r.y = __builtin_fma(-d.y, xm.x, __builtin_fma(-d.x, xm.y, __builtin_fma(s, nb.y, bv.y)));
+    return r;
 }
 
 // Vanka update of a middle row from the residual rows above (ro), at (rm)
@@ -108,13 +112,19 @@ __device__ __forceinline__ C residual_row(C xo, C xm, C xn, C bv, C d, T s) {
 // shifts commute with the (uniform) coefficients, so the four edge and four
 // corner terms take one neighbour sum:
 //   x + ca rm + cb (ro + rn) + LR(cb rm + cc (ro + rn)).
+// Off the interior (mk = 0) every term but the neighbour sum is zero
+// already (zero iterate and residual there); mk multiplies that sum in the
+// final add, so the update is zero there without a select.
 template <typename T, typename C>
-__device__ __forceinline__ C vanka_row(C xc, C ro, C rm, C rn, const Coef<T>& cf) {
+__device__ __forceinline__ C vanka_row(C xc, C ro, C rm, C rn, const Coef<T>& cf, T mk) {
     const C vs = add(ro, rn);
     const C w = fma2(mul(cf.cb, rm), cf.cc, vs);
     C v = fma2(xc, cf.ca, rm);
     v = fma2(v, cf.cb, vs);
-    return add(v, lr_sum(w));
+    const C lr = lr_sum(w);
+    v.x = __builtin_fma(mk, lr.x, v.x);
+    v.y = __builtin_fma(mk, lr.y, v.y);
+    return v;
 }
 
 // Full weighting around a middle row, the same way:
@@ -224,13 +234,6 @@ __device__ __forceinline__ void pin(float& v) { asm volatile("" : "+v"(v)); }
 __device__ __forceinline__ void pin(double2& v) { asm volatile("" : "+v"(v.x), "+v"(v.y)); }
 __device__ __forceinline__ void pin(float2& v) { asm volatile("" : "+v"(v.x), "+v"(v.y)); }
 
-template <typename C> __device__ __forceinline__ C lane_clear(bool keep, C v) {
-    C r;
-    r.x = keep ? v.x : 0;
-    r.y = keep ? v.y : 0;
-    return r;
-}
-
 template <typename T, int NS>
 struct DownPipe {
     using C = cplx<T>;
@@ -246,6 +249,7 @@ struct DownPipe {
     T sl;               // s on interior columns, else 0
     int k0, k1;
     bool col_in;
+    T mk;  // 1 on interior columns, 0 off them
     unsigned ox, ob, oo, of;  // lane byte offsets: x, b, x written, coarse b (or OOB)
     unsigned rx;              // bytes per fine row
     unsigned rc;              // bytes per coarse row
@@ -277,7 +281,7 @@ struct DownPipe {
                 if (!in_rows(j - 2 * q - 1, lf.ny)) r = z2<C>();
             R[q][n0] = r;
             if (q < NS) {
-                C v = lane_clear(col_in, vanka_row<T>(X[q][n2], R[q][n2], R[q][n1], R[q][n0], cf));
+                C v = vanka_row<T>(X[q][n2], R[q][n2], R[q][n1], R[q][n0], cf, mk);
                 if constexpr (EDGE)
                     if (!in_rows(j - 2 * q - 2, lf.ny)) v = z2<C>();
                 X[q + 1][n0] = v;
@@ -330,6 +334,7 @@ __device__ __forceinline__ void down_piece(const LevelSeg<T>& S, int sys, int st
     p.lc = S.lc;
     const int i = 1 + strip * OWN - HALO + lane;
     p.col_in = i >= 1 && i <= p.lf.nx;
+    p.mk = p.col_in ? (T)1 : (T)0;
     const bool col_ld = i >= 0 && i <= p.lf.nx + 1 && !S.x_zero;
     const bool own = lane >= HALO && lane < HALO + OWN && p.col_in;
     const unsigned es = sizeof(C);
@@ -438,6 +443,7 @@ struct UpPipe {
     T sl;
     int k0, k1;
     bool col_in, odd;
+    T mk, hf;  // 1 / 0 on interior / other columns; 1/2 / 0 on odd / even columns
     unsigned ox, oe, oo;  // lane byte offsets: x and b, coarse e, x written (or OOB)
     unsigned rx, rc, ro;  // row strides in bytes: x and b, coarse e, x written
     double acc;
@@ -463,8 +469,12 @@ struct UpPipe {
     // coarse column i/2 at an even fine column; the average of coarse columns
     // (i-1)/2 and (i+1)/2 at an odd one (the right one via a lane shift)
     __device__ __forceinline__ C interp_x(C v) const {
+        // v + hf (right - v): the average at odd columns (hf = 1/2), v at even ones
         const C rv = from_right(v);
-        return odd ? scl(add(v, rv), (T)0.5) : v;
+        C r;
+        r.x = __builtin_fma(hf, rv.x - v.x, v.x);
+        r.y = __builtin_fma(hf, rv.y - v.y, v.y);
+        return r;
     }
     // Step at fine row j, phase P.  Coarse row K = jb/2 + c (jb the unrolled
     // block's first row) lives in coarse slot c mod 3: its raw load is issued
@@ -500,7 +510,7 @@ struct UpPipe {
                 break;
             }
             R[q][n0] = r;
-            C v = lane_clear(col_in, vanka_row<T>(X[q][n2], R[q][n2], R[q][n1], R[q][n0], cf));
+            C v = vanka_row<T>(X[q][n2], R[q][n2], R[q][n1], R[q][n0], cf, mk);
             if constexpr (EDGE)
                 if (!in_rows(j - 2 * q - 2, lf.ny)) v = z2<C>();
             X[q + 1][n0] = v;
@@ -540,7 +550,9 @@ __device__ __forceinline__ double up_piece(const LevelSeg<T>& S, int sys, int st
     p.lc = S.lc;
     const int i = Pipe::COL0 + strip * OWN - HALO + lane;
     p.col_in = i >= 1 && i <= p.lf.nx;
+    p.mk = p.col_in ? (T)1 : (T)0;
     p.odd = (i & 1) != 0;
+    p.hf = p.odd ? (T)0.5 : (T)0;
     const bool ecol = i >= 0 && i <= p.lf.nx + 1;
     const bool own = lane >= HALO && lane < HALO + OWN && p.col_in;
     const unsigned es = sizeof(C);
@@ -673,6 +685,7 @@ struct EdgePipe {
     T sl;
     int k0, k1;
     bool col_in, odd;
+    T mk, hf;  // 1 / 0 on interior / other columns; 1/2 / 0 on odd / even columns
     unsigned ox, oe, oo, of;
     unsigned rx, rc;
     double acc;
@@ -696,8 +709,12 @@ struct EdgePipe {
         return v;
     }
     __device__ __forceinline__ C interp_x(C v) const {
+        // v + hf (right - v): the average at odd columns (hf = 1/2), v at even ones
         const C rv = from_right(v);
-        return odd ? scl(add(v, rv), (T)0.5) : v;
+        C r;
+        r.x = __builtin_fma(hf, rv.x - v.x, v.x);
+        r.y = __builtin_fma(hf, rv.y - v.y, v.y);
+        return r;
     }
     template <bool EDGE> __device__ __forceinline__ void store_row(rsrc_t r, int row, C v) const {
         if constexpr (EDGE) bstore(r, oo + (row >= k0 && row <= k1 ? row * rx : OOB), 0, v);
@@ -742,7 +759,7 @@ struct EdgePipe {
             R[q][n0] = r;
             pin(R[q][n0]);
             if (q < NS) {
-                C v = lane_clear(col_in, vanka_row<T>(X[q][n2], R[q][n2], R[q][n1], R[q][n0], cf));
+                C v = vanka_row<T>(X[q][n2], R[q][n2], R[q][n1], R[q][n0], cf, mk);
                 if constexpr (EDGE)
                     if (!in_rows(j - 2 * q - 2, lf.ny)) v = z2<C>();
                 X[q + 1][n0] = v;
@@ -784,7 +801,9 @@ __device__ __forceinline__ double edge_piece(const LevelSeg<T>& S, int sys, int 
     p.lc = S.lc;
     const int i = Pipe::COL0 + strip * OWN - HALO + lane;
     p.col_in = i >= 1 && i <= p.lf.nx;
+    p.mk = p.col_in ? (T)1 : (T)0;
     p.odd = (i & 1) != 0;
+    p.hf = p.odd ? (T)0.5 : (T)0;
     const bool ecol = i >= 0 && i <= p.lf.nx + 1;
     const bool own = lane >= HALO && lane < HALO + OWN && p.col_in;
     const unsigned es = sizeof(C);
