@@ -47,11 +47,6 @@ __device__ __forceinline__ int64_t node_off(const RowLayout& L, int64_t p) {
     const int64_t r = p / L.nx;
     return L.off + r * L.pitch + (p - r * L.nx);
 }
-// the same for node indices below 2^32 (32-bit division)
-__device__ __forceinline__ int64_t node_off32(const RowLayout& L, unsigned p) {
-    const unsigned r = p / (unsigned)L.nx;
-    return L.off + (int64_t)r * L.pitch + (p - r * (unsigned)L.nx);
-}
 
 // One block: real rows [rb*ROWS, +ROWS) x nodes [cb*COLS, +COLS).
 // Wave w owns rows w*32..w*32+31 as 2 x 4 MFMA 16x16 tiles.
@@ -178,15 +173,12 @@ __global__ __launch_bounds__(TN) void k_transform(int n, int64_t m, const double
 #ifndef VMG_TR_CT
 #define VMG_TR_CT 2
 #endif
-#ifndef VMG_TR_WPE
-#define VMG_TR_WPE 4
-#endif
 constexpr int RT_CT = VMG_TR_CT;       // 16-node column sub-tiles per tile
 constexpr int RT_NODES = 16 * RT_CT;   // nodes per tile
 
 // (two blocks a CU: 4 waves a SIMD for NW = 8)
-template <int NW, bool I32>
-__global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(VMG_TR_WPE))) void k_transform_reg(int64_t m, const double* __restrict__ Mx,
+template <int NW>
+__global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(4))) void k_transform_reg(int64_t m, const double* __restrict__ Mx,
                                                             const double2* __restrict__ in, RowLayout li,
                                                             double2* __restrict__ out, RowLayout lo, int accumulate,
                                                             int64_t ntiles) {
@@ -210,8 +202,7 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(VMG_TR_
 #pragma unroll
         for (int q = 0; q < LD; ++q) {
             const int64_t p = c0 + q;
-            const int64_t o = I32 ? node_off32(li, (unsigned)p) : node_off(li, p);
-            rb[q] = p < m ? in[(int64_t)lrow * li.row + o] : make_double2(0.0, 0.0);
+            rb[q] = p < m ? in[(int64_t)lrow * li.row + node_off(li, p)] : make_double2(0.0, 0.0);
         }
     };
     auto stage = [&](int buf) {
@@ -245,7 +236,7 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(VMG_TR_
         for (int c = 0; c < RT_CT; ++c) {
             const int64_t p = tile * RT_NODES + 16 * c + (lane & 15);
             if (p < m) {
-                const int64_t o = I32 ? node_off32(lo, (unsigned)p) : node_off(lo, p);
+                const int64_t o = node_off(lo, p);
                 double2 v0 = make_double2(acc[c][0], acc[c][1]);
                 double2 v1 = make_double2(acc[c][2], acc[c][3]);
                 double2* q0 = out + (int64_t)cr * lo.row + o;
@@ -267,12 +258,12 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(VMG_TR_
     }
 }
 
-template <int NW, bool I32> int reg_blocks() {
+template <int NW> int reg_blocks() {
     static int blocks = 0;
     if (!blocks) {
         int per_cu = 0, cus = 0, dev = 0;
         if (hipGetDevice(&dev) != hipSuccess) dev = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)&k_transform_reg<NW, I32>, 64 * NW, 0) !=
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)&k_transform_reg<NW>, 64 * NW, 0) !=
                 hipSuccess || per_cu < 1)
             per_cu = 1;
         if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1) cus = 1;
@@ -285,21 +276,10 @@ template <int NW>
 void go_reg(int64_t m, const double* Mx, const double2* in, RowLayout li, double2* out, RowLayout lo, int accumulate,
             hipStream_t st) {
     const int64_t ntiles = (m + RT_NODES - 1) / RT_NODES;
-    // node indices (with the last tile's overhang) below 2^32: 32-bit offsets
-#ifndef VMG_TR_I32
-#define VMG_TR_I32 1
-#endif
-    if (VMG_TR_I32 && ntiles * RT_NODES < (int64_t(1) << 32)) {
-        const int64_t blocks = std::min<int64_t>(ntiles, reg_blocks<NW, true>());
-        if (blocks < 1) return;
-        hipLaunchKernelGGL((k_transform_reg<NW, true>), dim3((unsigned)blocks), dim3(64 * NW), 0, st, m, Mx, in, li,
-                           out, lo, accumulate, ntiles);
-        return;
-    }
-    const int64_t blocks = std::min<int64_t>(ntiles, reg_blocks<NW, false>());
+    const int64_t blocks = std::min<int64_t>(ntiles, reg_blocks<NW>());
     if (blocks < 1) return;
-    hipLaunchKernelGGL((k_transform_reg<NW, false>), dim3((unsigned)blocks), dim3(64 * NW), 0, st, m, Mx, in, li, out,
-                       lo, accumulate, ntiles);
+    hipLaunchKernelGGL((k_transform_reg<NW>), dim3((unsigned)blocks), dim3(64 * NW), 0, st, m, Mx, in, li, out, lo,
+                       accumulate, ntiles);
 }
 
 }  // namespace
