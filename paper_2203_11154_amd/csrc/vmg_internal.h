@@ -118,7 +118,9 @@ void launch_ir_update(double2* x, const float2* e, LevelView lx, LevelView le, c
 // with iters[s] == 0 is written as zero, and if sel != NULL system s reads
 // src1 instead of src0 when ((iters[s] * flips) & 1).
 template <typename T>
-void launch_pack(const cplx<T>* src, cplx<T>* dst, LevelView lv, int nsys, hipStream_t st);
+// pack: with partial set, also |dst|^2 per system in residual_tiles(lv) tiles
+// (partial[sys * tiles + t], the layout launch_residual writes)
+void launch_pack(const cplx<T>* src, cplx<T>* dst, LevelView lv, int nsys, hipStream_t st, double* partial = nullptr);
 template <typename T>
 void launch_unpack(const cplx<T>* src0, const cplx<T>* src1, cplx<T>* dst, LevelView lv, int nsys,
                    const int* iters, int flips, hipStream_t st);
@@ -173,8 +175,12 @@ struct RowLayout {
     int64_t row;   // elements per matrix row (one system / time slice)
     int64_t off;   // element offset of node 0
 };
-void launch_transform(int n, int64_t m, const double2* M, int trans_conj, const double2* in, RowLayout li,
-                      double2* out, RowLayout lo, double2* mbuf, hipStream_t st, int accumulate = 0);
+// With norm_partial set (and accumulate off), also sum |out|^2 per output
+// row into norm_partial[row * tiles + t] and return the tile count; 0 when
+// this product shape has no fused sums (nothing written there).
+int launch_transform(int n, int64_t m, const double2* M, int trans_conj, const double2* in, RowLayout li,
+                     double2* out, RowLayout lo, double2* mbuf, hipStream_t st, int accumulate = 0,
+                     double* norm_partial = nullptr, int max_tiles = 0);
 
 // Fused register-streaming level kernels (vmg_stream.hip), nu in {0, 1, 2},
 // batched over segments like the launchers above:

@@ -311,13 +311,28 @@ __global__ __launch_bounds__(NT) void k_ir_update(double2* __restrict__ x, const
 
 template <typename T>
 __global__ __launch_bounds__(NT) void k_pack(const cplx<T>* __restrict__ src, cplx<T>* __restrict__ dst,
-                                             LevelView lv) {
+                                             LevelView lv, double* __restrict__ partial) {
+    __shared__ double red[NT / 64];
     const int sys = blockIdx.z;
     const int i = blockIdx.x * 64 + (threadIdx.x & 63);
-    if (i >= lv.nx) return;
-    for (int k = blockIdx.y * 16 + (threadIdx.x >> 6); k < min(lv.ny, (int)(blockIdx.y + 1) * 16); k += NT / 64)
-        dst[(int64_t)sys * lv.plane + (int64_t)(k + 1) * lv.pitch + i + 1] =
-            src[((int64_t)sys * lv.ny + k) * lv.nx + i];
+    double acc = 0.0;
+    if (i < lv.nx) {
+        for (int k = blockIdx.y * 16 + (threadIdx.x >> 6); k < min(lv.ny, (int)(blockIdx.y + 1) * 16); k += NT / 64) {
+            const cplx<T> v = src[((int64_t)sys * lv.ny + k) * lv.nx + i];
+            dst[(int64_t)sys * lv.plane + (int64_t)(k + 1) * lv.pitch + i + 1] = v;
+            acc += (double)v.x * (double)v.x + (double)v.y * (double)v.y;
+        }
+    }
+    if (!partial) return;  // uniform over the grid
+    // |b|^2 of the tile, in the residual kernel's tile order and layout
+    for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0.0;
+        for (int w = 0; w < NT / 64; ++w) t += red[w];
+        partial[(int64_t)sys * (gridDim.x * gridDim.y) + blockIdx.y * gridDim.x + blockIdx.x] = t;
+    }
 }
 
 template <typename T>
@@ -439,8 +454,8 @@ void launch_ir_update(double2* x, const float2* e, LevelView lx, LevelView le, c
 }
 
 template <typename T>
-void launch_pack(const cplx<T>* src, cplx<T>* dst, LevelView lv, int nsys, hipStream_t st) {
-    hipLaunchKernelGGL((k_pack<T>), grid2(lv.nx, lv.ny, 64, 16, nsys), dim3(NT), 0, st, src, dst, lv);
+void launch_pack(const cplx<T>* src, cplx<T>* dst, LevelView lv, int nsys, hipStream_t st, double* partial) {
+    hipLaunchKernelGGL((k_pack<T>), grid2(lv.nx, lv.ny, 64, 16, nsys), dim3(NT), 0, st, src, dst, lv, partial);
 }
 
 template <typename T>
@@ -467,7 +482,7 @@ void launch_fill_int(int* p, int value, int n, hipStream_t st) {
     template void launch_restrict<T>(SegTable<T>, const int*, hipStream_t);                                      \
     template void launch_prolong<T>(SegTable<T>, const int*, hipStream_t);                                       \
     template void launch_coarse<T>(SegTable<T>, const int*, hipStream_t);                                        \
-    template void launch_pack<T>(const cplx<T>*, cplx<T>*, LevelView, int, hipStream_t);                      \
+    template void launch_pack<T>(const cplx<T>*, cplx<T>*, LevelView, int, hipStream_t, double*);             \
     template void launch_unpack<T>(const cplx<T>*, const cplx<T>*, cplx<T>*, LevelView, int, const int*, int,  \
                                    hipStream_t);
 VMG_INST(double)

@@ -75,6 +75,7 @@ struct Group {
     int nc = 0;
     double* partial = nullptr;
     int ntiles0 = 0;
+    int partial_cap = 0;  // partial sums per system the partial buffer holds
     int nact = 0;   // systems active at the last host check (for byte accounting)
     std::vector<int> sched;  // per level: 0 = LDS-tiled kernels, r > 0 = streaming with r rows; empty = heuristic
     int tail_lt = -1;        // first level run by the tail kernel (-1: none)
@@ -1052,8 +1053,11 @@ int run_cycle(vmg_handle* H, int conj, hipStream_t st, int64_t cycle, double tol
     return VMG_OK;
 }
 
+// bnorm_tiles > 0: the producer of the finest right-hand sides (one grid)
+// already left |b|^2 partial sums in that many tiles of the grid's partial
+// buffer.
 int solve_impl(vmg_handle* H, const double* B, double* Z, double tol, int conj, const int32_t* fixed,
-               int32_t* iters_out, double* relres_out, hipStream_t st) {
+               int32_t* iters_out, double* relres_out, hipStream_t st, int bnorm_tiles = 0) {
     const vmg_opts& o = H->opts;
     const int S = H->S;
     int maxc = 0;
@@ -1064,31 +1068,37 @@ int solve_impl(vmg_handle* H, const double* B, double* Z, double tol, int conj, 
     }
     VMG_HIP(hipMemcpyAsync(H->target, H->h_int, sizeof(int) * S, hipMemcpyHostToDevice, st));
     launch_fill_int(H->active, 1, S, st);
-    // pack B and measure ||b_j||
+    // pack B (FP64 cycles: with the partial sums of ||b_j||^2)
     int64_t off = 0;
     for (auto& g : H->groups) {
         Level& l0 = g.lv64[0];
         if (B) {
             Timer t(H, st, VMG_K_PACK, 32.0 * nodes(l0.v) * g.S);
-            launch_pack<double>(reinterpret_cast<const double2*>(B) + off, P<double>(l0.b), l0.v, g.S, st);
+            launch_pack<double>(reinterpret_cast<const double2*>(B) + off, P<double>(l0.b), l0.v, g.S, st,
+                                o.precision == 0 ? g.partial : nullptr);
         }
         off += (int64_t)g.nx * g.ny * g.S;
     }
-    // ||b_j||: the residual of x = 0
+    // ||b_j||: the residual of x = 0, unless its partial sums exist already
     for (auto& g : H->groups) {
         Level& l0 = g.lv64[0];
         const int* act = H->active + g.sys0;
+        int ntiles = g.ntiles0;
         if (o.precision == 0) {
-            Timer t(H, st, VMG_K_NORM, 16.0 * nodes(l0.v) * g.S);
-            launch_residual<double, double>(nullptr, P<double>(l0.b), nullptr, l0.v, l0.v, 1.0, coef_of<double>(g, 0, 0),
-                                            act, g.S, 1, g.partial, st);
+            if (bnorm_tiles > 0) {
+                ntiles = bnorm_tiles;
+            } else if (!B) {
+                Timer t(H, st, VMG_K_NORM, 16.0 * nodes(l0.v) * g.S);
+                launch_residual<double, double>(nullptr, P<double>(l0.b), nullptr, l0.v, l0.v, 1.0,
+                                                coef_of<double>(g, 0, 0), act, g.S, 1, g.partial, st);
+            }
         } else {
             Level& e0 = g.lv32[0];
             Timer t(H, st, VMG_K_IR, 24.0 * nodes(l0.v) * g.S);
             launch_residual<double, float>(nullptr, P<double>(l0.b), P<float>(e0.b), l0.v, e0.v, 1.0,
                                            coef_of<double>(g, 0, 0), act, g.S, 1, g.partial, st);
         }
-        launch_norm_finalize(g.partial, g.ntiles0, g.S, g.sys0, 0, tol, fixed != nullptr, H->bb, H->relres, H->iters,
+        launch_norm_finalize(g.partial, ntiles, g.S, g.sys0, 0, tol, fixed != nullptr, H->bb, H->relres, H->iters,
                              H->active, H->target, H->nanflag, st);
     }
     if (check_hip()) return VMG_HIP_ERROR;
@@ -1453,6 +1463,7 @@ int vanka_mg_setup(const vmg_grid* grids, int32_t n_grids, const double* shifts,
         {
             const int nt = std::max(G.ntiles0, stream_tiles_max(G.lv64[0].v.nx, G.lv64[0].v.ny, o.nu2));
             VMG_TRY(dev_malloc(H, (void**)&G.partial, sizeof(double) * (size_t)nt * G.S));
+            G.partial_cap = nt;
         }
         VMG_TRY(upload_coefficients(H, G, nullptr));
     }
@@ -1636,14 +1647,17 @@ int paradiag_core(vmg_handle* H, const double* V, const double* Vinv, const doub
     lb.pitch = l0.v.pitch;
     lb.row = l0.v.plane;
     lb.off = l0.v.pitch + 1;
+    // (FP64 cycles: with the partial sums of ||g_j||^2 for the stopping test)
+    int btiles = 0;
     {
         Timer t(H, st, VMG_K_TRANSFORM, 32.0 * (double)n * m);
-        launch_transform(n, m, reinterpret_cast<const double2*>(conj ? V : Vinv), conj ? 1 : 0,
-                         reinterpret_cast<const double2*>(F), dense_rows(m), P<double>(l0.b), lb, H->mbuf, st);
+        btiles = launch_transform(n, m, reinterpret_cast<const double2*>(conj ? V : Vinv), conj ? 1 : 0,
+                                  reinterpret_cast<const double2*>(F), dense_rows(m), P<double>(l0.b), lb, H->mbuf, st,
+                                  0, H->opts.precision == 0 ? g.partial : nullptr, g.partial_cap);
     }
     if (check_hip()) return VMG_HIP_ERROR;
     int rc = solve_impl(H, nullptr, reinterpret_cast<double*>(H->gbuf), tol, conj ? 1 : 0, fixed_iters, nullptr,
-                        nullptr, st);
+                        nullptr, st, btiles);
     if (rc < 0) return rc;
     {
         Timer t(H, st, VMG_K_TRANSFORM, (accumulate ? 48.0 : 32.0) * (double)n * m);

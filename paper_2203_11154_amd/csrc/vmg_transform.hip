@@ -177,11 +177,14 @@ constexpr int RT_CT = VMG_TR_CT;       // 16-node column sub-tiles per tile
 constexpr int RT_NODES = 16 * RT_CT;   // nodes per tile
 
 // (two blocks a CU: 4 waves a SIMD for NW = 8)
-template <int NW>
+// NORM: also the sums of |out|^2 per output row (see launch_transform), kept
+// per lane in LDS across tiles so that the MFMA loop's registers are untouched.
+template <int NW, bool NORM>
 __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(4))) void k_transform_reg(int64_t m, const double* __restrict__ Mx,
                                                             const double2* __restrict__ in, RowLayout li,
                                                             double2* __restrict__ out, RowLayout lo, int accumulate,
-                                                            int64_t ntiles) {
+                                                            int64_t ntiles, double* __restrict__ partial) {
+    __shared__ double sN[NORM ? 2 * 64 * NW : 1];
     constexpr int n = 8 * NW, n2 = 2 * n, KS = n2 / 4, TT = 64 * NW;
     // per thread of the tile load: complex rows x nodes = n x RT_NODES values
     constexpr int LD = n * RT_NODES / TT;  // = 4
@@ -213,7 +216,11 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(4))) vo
         }
     };
     int64_t tile = blockIdx.x;
-    if (tile >= ntiles) return;  // uniform over the block
+    if (tile >= ntiles) return;  // uniform over the block (never with NORM: one tile a block at least)
+    if constexpr (NORM) {
+        sN[2 * threadIdx.x] = 0.0;  // |out|^2 of the lane's two complex rows
+        sN[2 * threadIdx.x + 1] = 0.0;
+    }
     fetch(tile);
     stage(0);
     __syncthreads();
@@ -248,6 +255,10 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(4))) vo
                 }
                 *q0 = v0;
                 *q1 = v1;
+                if constexpr (NORM) {
+                    sN[2 * threadIdx.x] += v0.x * v0.x + v0.y * v0.y;
+                    sN[2 * threadIdx.x + 1] += v1.x * v1.x + v1.y * v1.y;
+                }
             }
         }
         if (next < ntiles) {
@@ -256,14 +267,27 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(4))) vo
             buf ^= 1;
         }
     }
+    if constexpr (NORM) {
+        // the 16 lanes of a lane group hold the same two rows
+        double s0 = sN[2 * threadIdx.x], s1 = sN[2 * threadIdx.x + 1];
+        for (int off = 8; off > 0; off >>= 1) {
+            s0 += __shfl_xor(s0, off, 64);
+            s1 += __shfl_xor(s1, off, 64);
+        }
+        if ((lane & 15) == 0) {
+            const int cr = 8 * wave + (lane >> 4);
+            partial[(int64_t)cr * gridDim.x + blockIdx.x] = s0;
+            partial[(int64_t)(cr + 4) * gridDim.x + blockIdx.x] = s1;
+        }
+    }
 }
 
-template <int NW> int reg_blocks() {
+template <int NW, bool NORM> int reg_blocks() {
     static int blocks = 0;
     if (!blocks) {
         int per_cu = 0, cus = 0, dev = 0;
         if (hipGetDevice(&dev) != hipSuccess) dev = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)&k_transform_reg<NW>, 64 * NW, 0) !=
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)&k_transform_reg<NW, NORM>, 64 * NW, 0) !=
                 hipSuccess || per_cu < 1)
             per_cu = 1;
         if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1) cus = 1;
@@ -273,30 +297,41 @@ template <int NW> int reg_blocks() {
 }
 
 template <int NW>
-void go_reg(int64_t m, const double* Mx, const double2* in, RowLayout li, double2* out, RowLayout lo, int accumulate,
-            hipStream_t st) {
+int go_reg(int64_t m, const double* Mx, const double2* in, RowLayout li, double2* out, RowLayout lo, int accumulate,
+           hipStream_t st, double* partial, int max_tiles) {
     const int64_t ntiles = (m + RT_NODES - 1) / RT_NODES;
-    const int64_t blocks = std::min<int64_t>(ntiles, reg_blocks<NW>());
-    if (blocks < 1) return;
-    hipLaunchKernelGGL((k_transform_reg<NW>), dim3((unsigned)blocks), dim3(64 * NW), 0, st, m, Mx, in, li, out, lo,
-                       accumulate, ntiles);
+    if (partial && !accumulate) {
+        const int64_t blocks = std::min<int64_t>(ntiles, reg_blocks<NW, true>());
+        if (blocks >= 1 && blocks <= max_tiles) {
+            hipLaunchKernelGGL((k_transform_reg<NW, true>), dim3((unsigned)blocks), dim3(64 * NW), 0, st, m, Mx, in, li,
+                               out, lo, 0, ntiles, partial);
+            return (int)blocks;
+        }
+    }
+    const int64_t blocks = std::min<int64_t>(ntiles, reg_blocks<NW, false>());
+    if (blocks < 1) return 0;
+    hipLaunchKernelGGL((k_transform_reg<NW, false>), dim3((unsigned)blocks), dim3(64 * NW), 0, st, m, Mx, in, li, out,
+                       lo, accumulate, ntiles, nullptr);
+    return 0;
 }
 
 }  // namespace
 
-void launch_transform(int n, int64_t m, const double2* M, int trans_conj, const double2* in, RowLayout li,
-                      double2* out, RowLayout lo, double2* mbuf, hipStream_t st, int accumulate) {
+int launch_transform(int n, int64_t m, const double2* M, int trans_conj, const double2* in, RowLayout li,
+                     double2* out, RowLayout lo, double2* mbuf, hipStream_t st, int accumulate, double* norm_partial,
+                     int max_tiles) {
     double* Mx = reinterpret_cast<double*>(mbuf);
     hipLaunchKernelGGL(k_expand, dim3((n * n + 255) / 256), dim3(256), 0, st, M, n, trans_conj, Mx);
     switch (n) {
-        case 8: go_reg<1>(m, Mx, in, li, out, lo, accumulate, st); return;
-        case 16: go_reg<2>(m, Mx, in, li, out, lo, accumulate, st); return;
-        case 32: go_reg<4>(m, Mx, in, li, out, lo, accumulate, st); return;
-        case 64: go_reg<8>(m, Mx, in, li, out, lo, accumulate, st); return;
+        case 8: return go_reg<1>(m, Mx, in, li, out, lo, accumulate, st, norm_partial, max_tiles);
+        case 16: return go_reg<2>(m, Mx, in, li, out, lo, accumulate, st, norm_partial, max_tiles);
+        case 32: return go_reg<4>(m, Mx, in, li, out, lo, accumulate, st, norm_partial, max_tiles);
+        case 64: return go_reg<8>(m, Mx, in, li, out, lo, accumulate, st, norm_partial, max_tiles);
         default: break;
     }
     const dim3 grid((unsigned)((m + COLS - 1) / COLS), (unsigned)((2 * n + ROWS - 1) / ROWS));
     hipLaunchKernelGGL(k_transform, grid, dim3(TN), 0, st, n, m, Mx, in, li, out, lo, accumulate);
+    return 0;
 }
 
 }  // namespace vmg
