@@ -31,6 +31,9 @@
  *   - hip_stream is a hipStream_t (NULL = the default stream).  Work is
  *     enqueued on that stream; a call returns once its work is enqueued unless
  *     it has host outputs, which imply a synchronisation of that stream.
+ *     Solves that stop at a tolerance also read the per-system state between
+ *     batches of cycles (stream synchronisations), so that no cycle is
+ *     launched after every system has stopped.
  *   - The caller owns every buffer it passes in; the library owns everything
  *     inside a handle.  A handle is used from one host thread and one stream at
  *     a time.
@@ -141,7 +144,9 @@ int vanka_mg_set_omega(vmg_handle* h, const double* omega);
  *   iters       host, NULL or one int per system: cycles (refinement steps)
  *               run.  relres: host, NULL or one double per system: final
  *               relative residual.  If both are NULL and every system has a
- *               fixed count, the call is fully asynchronous.
+ *               fixed count, the call is fully asynchronous (it then returns
+ *               VMG_OK without looking at the results: vanka_mg_last_stats
+ *               gives the counts and residuals afterwards).
  * A system with b_j = 0 returns z_j = 0 after zero cycles.
  * Returns VMG_OK, VMG_NOT_CONVERGED (some system reached max_iter above tol;
  * outputs valid), VMG_NAN_DETECTED, VMG_INVALID_ARG, VMG_HIP_ERROR.

@@ -125,6 +125,13 @@ struct vmg_handle {
     // pinned host staging
     int* h_int = nullptr;      // 3 * S ints
     double* h_dbl = nullptr;   // S doubles
+    // asynchronous fixed-count solves: per-call pinned copies of the counts,
+    // reused only once the copy that read them has run
+    static constexpr int TARGET_RING = 4;
+    int* h_target = nullptr;   // TARGET_RING * S ints
+    hipEvent_t target_ev[TARGET_RING] = {};
+    bool target_rec[TARGET_RING] = {};
+    int target_slot = 0;
     double2* mbuf = nullptr;   // n x n transform scratch (paradiag_apply)
     double2* gbuf = nullptr;   // n x m intermediate of paradiag_apply
     int64_t gbuf_elems = 0;
@@ -1055,18 +1062,34 @@ int run_cycle(vmg_handle* H, int conj, hipStream_t st, int64_t cycle, double tol
 
 // bnorm_tiles > 0: the producer of the finest right-hand sides (one grid)
 // already left |b|^2 partial sums in that many tiles of the grid's partial
-// buffer.
+// buffer.  With fixed counts and no host outputs nothing waits for the
+// device: all cycles up to the largest count are enqueued (the kernels of a
+// system that has reached its count return at once).
 int solve_impl(vmg_handle* H, const double* B, double* Z, double tol, int conj, const int32_t* fixed,
                int32_t* iters_out, double* relres_out, hipStream_t st, int bnorm_tiles = 0) {
     const vmg_opts& o = H->opts;
     const int S = H->S;
+    const bool async = fixed && !iters_out && !relres_out;
+    int* stage = H->h_int;
+    int slot = -1;
+    if (async) {
+        slot = H->target_slot;
+        H->target_slot = (slot + 1) % vmg_handle::TARGET_RING;
+        // the copy that last read this slot has run
+        if (H->target_rec[slot]) VMG_HIP(hipEventSynchronize(H->target_ev[slot]));
+        stage = H->h_target + (size_t)slot * S;
+    }
     int maxc = 0;
     for (int s = 0; s < S; ++s) {
-        H->h_int[s] = fixed ? fixed[s] : o.max_iter;
-        if (H->h_int[s] < 0) return VMG_INVALID_ARG;
-        maxc = std::max(maxc, H->h_int[s]);
+        stage[s] = fixed ? fixed[s] : o.max_iter;
+        if (stage[s] < 0) return VMG_INVALID_ARG;
+        maxc = std::max(maxc, stage[s]);
     }
-    VMG_HIP(hipMemcpyAsync(H->target, H->h_int, sizeof(int) * S, hipMemcpyHostToDevice, st));
+    VMG_HIP(hipMemcpyAsync(H->target, stage, sizeof(int) * S, hipMemcpyHostToDevice, st));
+    if (async) {
+        VMG_HIP(hipEventRecord(H->target_ev[slot], st));
+        H->target_rec[slot] = true;
+    }
     launch_fill_int(H->active, 1, S, st);
     // pack B (FP64 cycles: with the partial sums of ||b_j||^2)
     int64_t off = 0;
@@ -1107,9 +1130,17 @@ int solve_impl(vmg_handle* H, const double* B, double* Z, double tol, int conj, 
     // stop inside a batch: the device decides every stop exactly, the host
     // only avoids launching cycles for systems that have already stopped.
     int done = 0;
-    if (read_state(H, st)) return VMG_HIP_ERROR;
-    int batch = first_batch(o, tol, fixed, H, maxc);
-    while (done < maxc && any_active(H)) {
+    if (async) {
+        for (auto& g : H->groups) g.nact = g.S;
+        for (; done < maxc; ++done) {
+            const int rc = run_cycle(H, conj, st, done, tol, 1);
+            if (rc) return rc;
+        }
+    } else if (read_state(H, st)) {
+        return VMG_HIP_ERROR;
+    }
+    int batch = async ? 0 : first_batch(o, tol, fixed, H, maxc);
+    while (!async && done < maxc && any_active(H)) {
         const int nb = std::max(1, std::min(batch, maxc - done));
         for (int c = 0; c < nb; ++c) {
             const int rc = run_cycle(H, conj, st, done + c, tol, fixed != nullptr);
@@ -1143,6 +1174,7 @@ int solve_impl(vmg_handle* H, const double* B, double* Z, double tol, int conj, 
         off += (int64_t)g.nx * g.ny * g.S;
     }
     if (check_hip()) return VMG_HIP_ERROR;
+    if (async) return VMG_OK;  // counts, residuals and NaN flags: vanka_mg_last_stats
     VMG_HIP(hipMemcpyAsync(H->h_int, H->iters, sizeof(int) * S, hipMemcpyDeviceToHost, st));
     VMG_HIP(hipMemcpyAsync(H->h_int + S, H->nanflag, sizeof(int) * S, hipMemcpyDeviceToHost, st));
     VMG_HIP(hipMemcpyAsync(H->h_int + 2 * S, H->active, sizeof(int) * S, hipMemcpyDeviceToHost, st));
@@ -1330,6 +1362,9 @@ int vanka_mg_destroy(vmg_handle* H) {
     if (H->h_int) (void)hipHostFree(H->h_int);
     if (H->h_dbl) (void)hipHostFree(H->h_dbl);
     if (H->h_hcol) (void)hipHostFree(H->h_hcol);
+    if (H->h_target) (void)hipHostFree(H->h_target);
+    for (auto e : H->target_ev)
+        if (e) (void)hipEventDestroy(e);
     (void)hipSetDevice(prev);
     delete H;
     return VMG_OK;
@@ -1444,6 +1479,10 @@ int vanka_mg_setup(const vmg_grid* grids, int32_t n_grids, const double* shifts,
     VMG_TRY(dev_malloc(H, (void**)&H->nanflag, sizeof(int) * total));
     if (hipHostMalloc((void**)&H->h_int, sizeof(int) * 3 * total) != hipSuccess) VMG_TRY(VMG_OOM);
     if (hipHostMalloc((void**)&H->h_dbl, sizeof(double) * total) != hipSuccess) VMG_TRY(VMG_OOM);
+    if (hipHostMalloc((void**)&H->h_target, sizeof(int) * vmg_handle::TARGET_RING * total) != hipSuccess)
+        VMG_TRY(VMG_OOM);
+    for (auto& e : H->target_ev)
+        if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) VMG_TRY(VMG_HIP_ERROR);
 
     for (auto& G : H->groups) {
         // buffers

@@ -136,14 +136,16 @@ class VankaMG:
         _lib.check(self.lib.vanka_mg_plan(self.handle, g, ctypes.byref(e), ctypes.byref(t)), "vanka_mg_plan")
         return bool(e.value), int(t.value)
 
-    def solve(self, B, tol=1e-10, conj=False, fixed_iters=None, out=None):
+    def solve(self, B, tol=1e-10, conj=False, fixed_iters=None, out=None, stats=True):
         """Solve every system; B holds all systems concatenated (any shape with
-        the right number of elements).  Returns (Z, iters, relres, status)."""
+        the right number of elements).  Returns (Z, iters, relres, status).
+        stats=False with fixed_iters: no host outputs, the call only enqueues
+        work (iters and relres are None; see last_stats)."""
         self._check_vec(B, self.total, "B")
         Z = torch.empty_like(B) if out is None else out
         self._check_vec(Z, self.total, "out")
-        iters = np.zeros(self.num_systems, dtype=np.int32)
-        relres = np.zeros(self.num_systems, dtype=np.float64)
+        iters = np.zeros(self.num_systems, dtype=np.int32) if stats else None
+        relres = np.zeros(self.num_systems, dtype=np.float64) if stats else None
         fx = None
         if fixed_iters is not None:
             fa = np.ascontiguousarray(np.asarray(fixed_iters, dtype=np.int32).ravel())
@@ -151,8 +153,9 @@ class VankaMG:
                 raise ValueError("fixed_iters needs one count per system")
             fx = fa.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
         code = self.lib.vanka_mg_solve(self.handle, _ptr(B), _ptr(Z), float(tol), int(bool(conj)), fx,
-                                       iters.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
-                                       relres.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), _stream())
+                                       iters.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)) if stats else None,
+                                       relres.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) if stats else None,
+                                       _stream())
         if fixed_iters is not None:
             self._keep = fa
         status = _lib.check(code, "vanka_mg_solve")
