@@ -246,6 +246,30 @@ int paradiag_heat_gmres(vmg_handle* h, const double* V, const double* Vinv, doub
                         int32_t max_iter, int32_t* iters, double* relres, void* hip_stream);
 
 /*
+ * The ParaDIAG step above for the alpha-circulant preconditioner of
+ * backward Euler (the circulant-type ParaDIAG preconditioners of Sec. 1):
+ * V = diag(alpha^{-i/n}) W with W_ik = exp(-2 pi i ik/n) (indices from 0) and
+ * V^{-1} = W^H diag(alpha^{i/n}) / n, so each transform is a length-n DFT
+ * along the time index of every node between two diagonal scalings (one
+ * read and one write of every value instead of a GEMM).  The shifts given
+ * at setup must be the matching eigenvalues, lambda_j =
+ * (1 - alpha^{1/n} exp(2 pi i j/n)) / tau.  n = number of systems, a power of
+ * two in [2, 256]; 0 < alpha <= 1.  Other arguments and returns as
+ * paradiag_apply.
+ */
+int paradiag_apply_circulant(vmg_handle* h, double alpha, const double* F, double* U, double tol,
+                             int32_t conj, const int32_t* fixed_iters, void* hip_stream);
+
+/*
+ * The alpha-circulant transforms on their own (n, alpha as above):
+ * inverse = 0: out = (V^{-1} kron I) in (conj: V^H); inverse = 1:
+ * out = (V kron I) in (conj: V^{-H}).  in, out: device, complex128 n x m
+ * row-major, may not alias.  Returns VMG_OK, VMG_INVALID_ARG, VMG_HIP_ERROR.
+ */
+int paradiag_transform_circulant(int32_t n, int64_t m, double alpha, int32_t inverse, int32_t conj,
+                                 const double* in, double* out, void* hip_stream);
+
+/*
  * The time transform of eq. (1) on its own: out = (M kron I_m) in, i.e.
  * out[i, p] = sum_k M[i, k] in[k, p] for i, k < n and p < m, as a complex
  * GEMM on the FP64 matrix cores.  With trans_conj != 0, M^H replaces M.

@@ -178,6 +178,13 @@ struct RowLayout {
 // With norm_partial set (and accumulate off), also sum |out|^2 per output
 // row into norm_partial[row * tiles + t] and return the tile count; 0 when
 // this product shape has no fused sums (nothing written there).
+// The same products for the alpha-circulant eigenvector matrix V (time
+// steps n a power of two, 2..256) as scaled DFTs: inverse = 0 applies V^{-1}
+// (conj: V^H), inverse = 1 applies V (conj: V^{-H}).  norm_partial as above.
+bool circulant_supported(int n);
+int launch_circulant(int n, int64_t m, double alpha, int inverse, int conj, const double2* in, RowLayout li,
+                     double2* out, RowLayout lo, hipStream_t st, int accumulate = 0, double* norm_partial = nullptr,
+                     int max_tiles = 0);
 int launch_transform(int n, int64_t m, const double2* M, int trans_conj, const double2* in, RowLayout li,
                      double2* out, RowLayout lo, double2* mbuf, hipStream_t st, int accumulate = 0,
                      double* norm_partial = nullptr, int max_tiles = 0);

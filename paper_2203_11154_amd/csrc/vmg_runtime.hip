@@ -1647,6 +1647,16 @@ RowLayout dense_rows(int64_t m) {
 
 }  // namespace
 
+extern "C" int paradiag_transform_circulant(int32_t n, int64_t m, double alpha, int32_t inverse, int32_t conj,
+                                            const double* in, double* out, void* hip_stream) {
+    if (!circulant_supported(n) || m < 1 || m >= (int64_t)1 << 30 || !(alpha > 0.0) || !(alpha <= 1.0) || !in ||
+        !out || in == out)
+        return VMG_INVALID_ARG;
+    launch_circulant(n, m, alpha, inverse ? 1 : 0, conj ? 1 : 0, reinterpret_cast<const double2*>(in),
+                     dense_rows(m), reinterpret_cast<double2*>(out), dense_rows(m), (hipStream_t)hip_stream);
+    return check_hip();
+}
+
 extern "C" int paradiag_transform(int32_t n, int64_t m, const double* M, int32_t trans_conj, const double* in,
                                   double* out, void* hip_stream) {
     if (n < 1 || n > 512 || m < 1 || m >= (int64_t)1 << 30 || !M || !in || !out || in == out)
@@ -1664,12 +1674,15 @@ namespace {
 
 // One application of (V kron I) blockdiag(L_j^{-1}) (Vinv kron I) (or its
 // adjoint) to F; the result is written to U, or added to U with accumulate.
+// alpha > 0: V is the alpha-circulant eigenvector matrix (V, Vinv unused) and
+// both transforms are scaled DFTs.
 int paradiag_core(vmg_handle* H, const double* V, const double* Vinv, const double* F, double* U, double tol,
-                  int conj, const int32_t* fixed_iters, int accumulate, hipStream_t st) {
+                  int conj, const int32_t* fixed_iters, int accumulate, hipStream_t st, double alpha = 0.0) {
     Group& g = H->groups[0];
     const int n = H->S;
     const int64_t m = (int64_t)g.nx * g.ny;
-    if (!H->mbuf) {
+    const bool circ = alpha > 0.0;
+    if (!circ && !H->mbuf) {
         int rc = dev_malloc(H, (void**)&H->mbuf, sizeof(double) * 4 * (size_t)n * n);
         if (rc) return rc;
     }
@@ -1690,9 +1703,14 @@ int paradiag_core(vmg_handle* H, const double* V, const double* Vinv, const doub
     int btiles = 0;
     {
         Timer t(H, st, VMG_K_TRANSFORM, 32.0 * (double)n * m);
-        btiles = launch_transform(n, m, reinterpret_cast<const double2*>(conj ? V : Vinv), conj ? 1 : 0,
-                                  reinterpret_cast<const double2*>(F), dense_rows(m), P<double>(l0.b), lb, H->mbuf, st,
-                                  0, H->opts.precision == 0 ? g.partial : nullptr, g.partial_cap);
+        double* np = H->opts.precision == 0 ? g.partial : nullptr;
+        if (circ)
+            btiles = launch_circulant(n, m, alpha, 0, conj, reinterpret_cast<const double2*>(F), dense_rows(m),
+                                      P<double>(l0.b), lb, st, 0, np, g.partial_cap);
+        else
+            btiles = launch_transform(n, m, reinterpret_cast<const double2*>(conj ? V : Vinv), conj ? 1 : 0,
+                                      reinterpret_cast<const double2*>(F), dense_rows(m), P<double>(l0.b), lb, H->mbuf,
+                                      st, 0, np, g.partial_cap);
     }
     if (check_hip()) return VMG_HIP_ERROR;
     int rc = solve_impl(H, nullptr, reinterpret_cast<double*>(H->gbuf), tol, conj ? 1 : 0, fixed_iters, nullptr,
@@ -1700,8 +1718,12 @@ int paradiag_core(vmg_handle* H, const double* V, const double* Vinv, const doub
     if (rc < 0) return rc;
     {
         Timer t(H, st, VMG_K_TRANSFORM, (accumulate ? 48.0 : 32.0) * (double)n * m);
-        launch_transform(n, m, reinterpret_cast<const double2*>(conj ? Vinv : V), conj ? 1 : 0, H->gbuf,
-                         dense_rows(m), reinterpret_cast<double2*>(U), dense_rows(m), H->mbuf, st, accumulate);
+        if (circ)
+            launch_circulant(n, m, alpha, 1, conj, H->gbuf, dense_rows(m), reinterpret_cast<double2*>(U),
+                             dense_rows(m), st, accumulate);
+        else
+            launch_transform(n, m, reinterpret_cast<const double2*>(conj ? Vinv : V), conj ? 1 : 0, H->gbuf,
+                             dense_rows(m), reinterpret_cast<double2*>(U), dense_rows(m), H->mbuf, st, accumulate);
     }
     if (check_hip()) return VMG_HIP_ERROR;
     return rc;
@@ -1714,6 +1736,14 @@ extern "C" int paradiag_apply(vmg_handle* H, const double* V, const double* Vinv
     if (!H || !V || !Vinv || !F || !U || !(tol > 0.0)) return VMG_INVALID_ARG;
     if (H->groups.size() != 1 || H->S > 512) return VMG_INVALID_ARG;
     return paradiag_core(H, V, Vinv, F, U, tol, conj ? 1 : 0, fixed_iters, 0, (hipStream_t)hip_stream);
+}
+
+extern "C" int paradiag_apply_circulant(vmg_handle* H, double alpha, const double* F, double* U, double tol,
+                                        int32_t conj, const int32_t* fixed_iters, void* hip_stream) {
+    if (!H || !F || !U || !(tol > 0.0) || !(alpha > 0.0) || !(alpha <= 1.0)) return VMG_INVALID_ARG;
+    if (H->groups.size() != 1 || !circulant_supported(H->S)) return VMG_INVALID_ARG;
+    return paradiag_core(H, nullptr, nullptr, F, U, tol, conj ? 1 : 0, fixed_iters, 0, (hipStream_t)hip_stream,
+                         alpha);
 }
 
 extern "C" int paradiag_heat_solve(vmg_handle* H, const double* V, const double* Vinv, double tau, const double* F,

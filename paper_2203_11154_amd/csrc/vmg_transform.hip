@@ -315,7 +315,160 @@ int go_reg(int64_t m, const double* Mx, const double2* in, RowLayout li, double2
     return 0;
 }
 
+// ---------------------------------------------------------------------------
+// The same products for the alpha-circulant eigenvector matrix of the
+// backward-Euler time-stepping matrix, V = diag(alpha^{-i/n}) W with
+// W_ik = exp(-2 pi i ik/n) and V^{-1} = W^H diag(alpha^{i/n}) / n (indices
+// from 0): each is a length-n DFT along the time index of every node between
+// two diagonal scalings,
+//   out_k = post_k sum_i exp(sigma 2 pi i ik/n) pre_i in_i.
+// A block walks over tiles of FT_TILE / n nodes x n slices held in LDS (rows
+// stored in bit-reversed order, so the radix-2 decimation-in-time stages run
+// in place and end in natural order); twiddles and scalings are computed once
+// per block.  Memory bound: one read and one write of every value.
+constexpr int FT = 256;          // threads per block
+constexpr int FT_TILE = 2048;    // complex values per tile
+constexpr int FT_MAXN = 256;
+
+__device__ __forceinline__ int bit_reverse(int i, int logn) { return (int)(__brev((unsigned)i) >> (32 - logn)); }
+
+template <bool NORM>
+__global__ __launch_bounds__(FT) void k_circ_dft(int logn, int64_t m, int sign, double alpha, int variant,
+                                                 const double2* __restrict__ in, RowLayout li,
+                                                 double2* __restrict__ out, RowLayout lo, int accumulate,
+                                                 int64_t ntiles, double* __restrict__ partial) {
+    __shared__ double2 s[FT_TILE];
+    __shared__ double2 tw[FT_MAXN / 2];
+    __shared__ double pre[FT_MAXN], post[FT_MAXN];
+    const int n = 1 << logn;
+    const int logtn = 11 - logn;  // log2(FT_TILE / n)
+    const int tn = 1 << logtn;
+    for (int j = threadIdx.x; j < n / 2; j += FT) {
+        double sv, cv;
+        sincospi(2.0 * j / n, &sv, &cv);
+        tw[j] = make_double2(cv, sign * sv);
+    }
+    for (int i = threadIdx.x; i < n; i += FT) {
+        const double a = pow(alpha, (double)i / n);  // alpha^{i/n}
+        // 0: V^{-1} (pre alpha^{i/n}, post 1/n); 1: V (post alpha^{-k/n});
+        // 2: V^H (pre alpha^{-i/n}); 3: V^{-H} (post alpha^{k/n} / n)
+        pre[i] = variant == 0 ? a : (variant == 2 ? 1.0 / a : 1.0);
+        post[i] = variant == 0 ? 1.0 / n : (variant == 1 ? 1.0 / a : (variant == 3 ? a / n : 1.0));
+    }
+    double acc = 0.0;  // NORM: sum of |out|^2 of row threadIdx.x (< n)
+    // the next tile is loaded into registers while the current one is
+    // transformed in LDS
+    constexpr int LD = FT_TILE / FT;
+    double2 rb[LD];
+    auto fetch = [&](int64_t t) {
+#pragma unroll
+        for (int q = 0; q < LD; ++q) {
+            const int e = threadIdx.x + q * FT;
+            const int i = e >> logtn, c = e & (tn - 1);
+            const int64_t p = t * tn + c;
+            rb[q] = p < m ? in[(int64_t)i * li.row + node_off(li, p)] : make_double2(0.0, 0.0);
+        }
+    };
+    if (blockIdx.x < ntiles) fetch(blockIdx.x);
+    __syncthreads();
+    for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        const int64_t p0 = tile * tn;
+#pragma unroll
+        for (int q = 0; q < LD; ++q) {
+            const int e = threadIdx.x + q * FT;
+            const int i = e >> logtn, c = e & (tn - 1);
+            s[(bit_reverse(i, logn) << logtn) + c] = make_double2(rb[q].x * pre[i], rb[q].y * pre[i]);
+        }
+        __syncthreads();
+        if (tile + gridDim.x < ntiles) fetch(tile + gridDim.x);
+        for (int lh = 0; lh < logn; ++lh) {
+            const int half = 1 << lh;
+            for (int e = threadIdx.x; e < FT_TILE / 2; e += FT) {
+                const int c = e & (tn - 1);
+                const int b = e >> logtn;  // butterfly of the column
+                const int j = b & (half - 1);
+                const int k0 = ((b >> lh) << (lh + 1)) + j;
+                const double2 w = tw[j << (logn - 1 - lh)];
+                const double2 x0 = s[(k0 << logtn) + c];
+                const double2 x1 = s[((k0 + half) << logtn) + c];
+                const double2 t = make_double2(w.x * x1.x - w.y * x1.y, w.x * x1.y + w.y * x1.x);
+                s[(k0 << logtn) + c] = make_double2(x0.x + t.x, x0.y + t.y);
+                s[((k0 + half) << logtn) + c] = make_double2(x0.x - t.x, x0.y - t.y);
+            }
+            __syncthreads();
+        }
+        for (int e = threadIdx.x; e < FT_TILE; e += FT) {
+            const int k = e >> logtn, c = e & (tn - 1);
+            const int64_t p = p0 + c;
+            if (p < m) {
+                double2 v = s[e];
+                v.x *= post[k];
+                v.y *= post[k];
+                double2* q = out + (int64_t)k * lo.row + node_off(lo, p);
+                if (accumulate) {
+                    const double2 w = *q;
+                    v.x += w.x;
+                    v.y += w.y;
+                }
+                *q = v;
+                if (NORM) s[e] = v;
+            }
+        }
+        if constexpr (NORM) {
+            __syncthreads();
+            if (threadIdx.x < n) {
+                const int k = threadIdx.x;
+                for (int c = 0; c < tn && p0 + c < m; ++c) {
+                    const double2 v = s[(k << logtn) + c];
+                    acc += v.x * v.x + v.y * v.y;
+                }
+            }
+        }
+        __syncthreads();  // the tile is read completely before the next one is stored
+    }
+    if (NORM && threadIdx.x < n) partial[(int64_t)threadIdx.x * gridDim.x + blockIdx.x] = acc;
+}
+
+template <bool NORM> int circ_blocks() {
+    static int blocks = 0;
+    if (!blocks) {
+        int per_cu = 0, cus = 0, dev = 0;
+        if (hipGetDevice(&dev) != hipSuccess) dev = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)&k_circ_dft<NORM>, FT, 0) !=
+                hipSuccess || per_cu < 1)
+            per_cu = 1;
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1) cus = 1;
+        blocks = per_cu * cus;
+    }
+    return blocks;
+}
+
 }  // namespace
+
+bool circulant_supported(int n) { return n >= 2 && n <= FT_MAXN && (n & (n - 1)) == 0; }
+
+int launch_circulant(int n, int64_t m, double alpha, int inverse, int conj, const double2* in, RowLayout li,
+                     double2* out, RowLayout lo, hipStream_t st, int accumulate, double* norm_partial, int max_tiles) {
+    int logn = 0;
+    while ((1 << logn) < n) ++logn;
+    const int64_t tn = FT_TILE / n;
+    const int64_t ntiles = (m + tn - 1) / tn;
+    const int variant = conj ? (inverse ? 3 : 2) : (inverse ? 1 : 0);
+    const int sign = inverse ? -1 : 1;
+    if (norm_partial && !accumulate) {
+        const int64_t blocks = std::min<int64_t>(ntiles, circ_blocks<true>());
+        if (blocks >= 1 && blocks <= max_tiles) {
+            hipLaunchKernelGGL(k_circ_dft<true>, dim3((unsigned)blocks), dim3(FT), 0, st, logn, m, sign, alpha, variant,
+                               in, li, out, lo, 0, ntiles, norm_partial);
+            return (int)blocks;
+        }
+    }
+    const int64_t blocks = std::min<int64_t>(ntiles, circ_blocks<false>());
+    if (blocks >= 1)
+        hipLaunchKernelGGL(k_circ_dft<false>, dim3((unsigned)blocks), dim3(FT), 0, st, logn, m, sign, alpha, variant,
+                           in, li, out, lo, accumulate, ntiles, nullptr);
+    return 0;
+}
 
 int launch_transform(int n, int64_t m, const double2* M, int trans_conj, const double2* in, RowLayout li,
                      double2* out, RowLayout lo, double2* mbuf, hipStream_t st, int accumulate, double* norm_partial,

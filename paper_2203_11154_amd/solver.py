@@ -193,6 +193,19 @@ class VankaMG:
         status = _lib.check(code, "paradiag_apply")
         return U, status
 
+    def paradiag_apply_circulant(self, alpha, F, tol=1e-10, conj=False, out=None, fixed_iters=None):
+        """The same step for the alpha-circulant eigenvector matrix V, whose
+        transforms are scaled DFTs along the time index (the handle's shifts
+        must be the matching eigenvalues, see inputs.alpha_circulant_shifts)."""
+        self._check_vec(F, self.total, "F")
+        U = torch.empty_like(F) if out is None else out
+        keep, fx = self._fixed(fixed_iters)
+        code = self.lib.paradiag_apply_circulant(self.handle, float(alpha), _ptr(F), _ptr(U), float(tol),
+                                                 int(bool(conj)), fx, _stream())
+        del keep
+        status = _lib.check(code, "paradiag_apply_circulant")
+        return U, status
+
     def shift_gradient(self, Z, G):
         """grad_lambda[j] = -sum conj(Z_j) G_j (one complex value per system)."""
         self._check_vec(Z, self.total, "Z")
@@ -246,6 +259,21 @@ class VankaMG:
         by = (ctypes.c_double * n)()
         _lib.check(self.lib.vanka_mg_kernel_stats(self.handle, la, ms, by), "vanka_mg_kernel_stats")
         return {k: (la[i], ms[i], by[i]) for i, k in enumerate(_lib.KERNEL_CLASSES)}
+
+
+def transform_circulant(n, alpha, F, inverse=False, conj=False, out=None):
+    """out = (V^{-1} kron I) F (inverse: V kron I; conj: V^H, V^{-H}) for the
+    alpha-circulant eigenvector matrix V of n time steps, by scaled DFTs."""
+    _require_gpu()
+    lib = _lib.load()
+    m = F.numel() // n
+    if not (F.is_cuda and F.dtype == torch.complex128 and F.is_contiguous()) or F.numel() != n * m:
+        raise TypeError("transform_circulant needs a contiguous complex128 CUDA tensor of n x m values")
+    out = torch.empty_like(F) if out is None else out
+    code = lib.paradiag_transform_circulant(int(n), int(m), float(alpha), int(bool(inverse)), int(bool(conj)),
+                                            _ptr(F), _ptr(out), _stream())
+    _lib.check(code, "paradiag_transform_circulant")
+    return out
 
 
 def transform(M, F, trans_conj=False, out=None):
