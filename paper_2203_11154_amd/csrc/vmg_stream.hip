@@ -394,15 +394,18 @@ template <typename T> __device__ __forceinline__ LevelSeg<T> seg_of_wave(const S
 struct Piece {
     int sys, strip, k0, k1, slot;
 };
+// Waves are numbered strips fastest: the waves of a block, and neighbouring
+// blocks, cover adjacent strips of the same rows, so the halo columns two
+// strips share are read close together in time (mostly from L2).
 template <typename T> __device__ __forceinline__ Piece piece_of(const LevelSeg<T>& S, int lw) {
     Piece pc;
-    const int t = lw / S.pieces;
-    const int run = lw - t * S.pieces;
-    pc.sys = t / S.strips;
-    pc.strip = t - pc.sys * S.strips;
+    const int t = lw / S.strips;
+    pc.strip = lw - t * S.strips;
+    pc.sys = t / S.pieces;
+    const int run = t - pc.sys * S.pieces;
+    pc.slot = lw;  // == (sys * pieces + run) * strips + strip
     pc.k0 = 1 + run * S.rows;
     pc.k1 = min(S.lf.ny, pc.k0 + S.rows - 1);
-    pc.slot = lw;  // == (sys * strips + strip) * pieces + run
     return pc;
 }
 

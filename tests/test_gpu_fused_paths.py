@@ -70,11 +70,15 @@ def test_fused_equals_level_by_level(grids, nu1, nu2, monkeypatch):
                 assert np.linalg.norm(a - r) <= 1e-12 * np.linalg.norm(r), (nx, ny, j, cycles)
                 off += n
         np.testing.assert_allclose(rrf, rrp, rtol=1e-9)
-    # free-running solves stop after the same counts
-    Zf, itf, rrf, stf = fused.solve(bd, tol=1e-10)
-    Zp, itp, rrp, stp = plain.solve(bd, tol=1e-10)
-    assert stf == 0 and stp == 0
-    np.testing.assert_array_equal(itf, itp)
+    # free-running solves stop after the same counts, also for the adjoint
+    # (conjugate-shift) systems
+    for conj in (False, True):
+        Zf, itf, rrf, stf = fused.solve(bd, tol=1e-10, conj=conj)
+        Zp, itp, rrp, stp = plain.solve(bd, tol=1e-10, conj=conj)
+        assert stf == 0 and stp == 0
+        np.testing.assert_array_equal(itf, itp)
+        zf, zp = host(Zf), host(Zp)
+        assert np.linalg.norm(zf - zp) <= 1e-12 * np.linalg.norm(zp), conj
 
 
 def test_fused_against_oracle_uneven_batch(monkeypatch):
