@@ -165,6 +165,9 @@ void launch_tail(const TailSeg<T>* segs, const TailLaunch<T>& tl, int total_sys,
 template <typename T> int64_t tail_lds_bytes(const LevelView* lv, int nl);
 int tail_max_lds();        // dynamic LDS a workgroup may use (enables it for the tail kernels)
 constexpr int TAIL_MAX_COARSE_NODES = 1024;  // nodes of every level below the first
+// most padded nodes of a tail's first level (the kernel keeps its right-hand
+// side in registers: 5 values a thread in complex128, 10 in complex64)
+template <typename T> constexpr int tail_first_nodes_max() { return sizeof(T) == 8 ? 5 * 1024 : 10 * 1024; }
 
 // Complex GEMM out[i, p] = sum_k M[i, k] in[k, p] (M^H with trans_conj),
 // added to out when accumulate != 0, on FP64 matrix cores.  in/out rows may be padded planes: element p of row i

@@ -1279,6 +1279,7 @@ template <typename T> int build_tails(vmg_handle* H) {
                 lv[q] = L[l + q].v;
                 if (q >= 1 && lv[q].nx * lv[q].ny > TAIL_MAX_COARSE_NODES) ok = false;
             }
+            if ((int64_t)(lv[0].nx + 2) * (lv[0].ny + 2) > tail_first_nodes_max<T>()) ok = false;
             const int64_t bytes = tail_lds_bytes<T>(lv, nl);
             if (!ok || bytes > maxlds) continue;
             g.tail_lt = l;

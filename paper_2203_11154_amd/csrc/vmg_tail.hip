@@ -72,9 +72,47 @@ template <typename T> __device__ __forceinline__ cplx<T> load_b0(const TailView<
     return V.S->b[(int64_t)V.sys * g.plane + (int64_t)k * g.pitch + i];
 }
 
+// The first tail level's padded nodes a thread visits, t = threadIdx.x + j TT
+// (j < JMAX), with their right-hand side kept in registers and a bit per
+// node that is set on the interior: the level's passes then read no global
+// memory and divide by nothing.  JMAX bounds the nodes per thread of any
+// first level whose x and residual fit in LDS (the host checks it).
+template <typename T> struct Level0 {
+    static constexpr int JMAX = tail_first_nodes_max<T>() / TT;
+    cplx<T> b[JMAX];
+    unsigned in;
+};
+
 // r = b - L x on every padded node of level l (zero on the ring)
-template <typename T> __device__ void residual(const TailView<T>& V, int l) {
+template <typename T> __device__ void residual_first(const TailView<T>& V, const Level0<T>& f) {
     using C = cplx<T>;
+    const LevelView v = V.S->lv[0];
+    const int pitch = v.nx + 2, P = padded(v);
+    const Coef<T> cf = V.S->coef[0][V.sys];
+    const T s = V.S->s[0];
+    const C* x = V.lds;
+    C* r = V.lds + V.ro(0);
+#pragma unroll
+    for (int j = 0; j < Level0<T>::JMAX; ++j) {
+        const int t = threadIdx.x + j * TT;
+        if (t < P) {
+            C rv = tz<C>();
+            if ((f.in >> j) & 1u) {
+                const C nb = tadd(tadd(x[t - pitch], x[t + pitch]), tadd(x[t - 1], x[t + 1]));
+                rv = tsub(f.b[j], tsub(tmul(cf.d, x[t]), tscl(nb, s)));
+            }
+            r[t] = rv;
+        }
+    }
+    __syncthreads();
+}
+
+template <typename T> __device__ void residual(const TailView<T>& V, int l, const Level0<T>& f) {
+    using C = cplx<T>;
+    if (l == 0) {
+        residual_first(V, f);
+        return;
+    }
     const LevelView v = V.S->lv[l];
     const int pitch = v.nx + 2, P = padded(v);
     const Coef<T> cf = V.S->coef[l][V.sys];
@@ -86,7 +124,7 @@ template <typename T> __device__ void residual(const TailView<T>& V, int l) {
         const int k = t / pitch, i = t - k * pitch;
         C rv = tz<C>();
         if (i >= 1 && i <= v.nx && k >= 1 && k <= v.ny) {
-            const C bv = l == 0 ? load_b0(V, k, i) : b[t];
+            const C bv = b[t];
             const C nb = tadd(tadd(x[t - pitch], x[t + pitch]), tadd(x[t - 1], x[t + 1]));
             rv = tsub(bv, tsub(tmul(cf.d, x[t]), tscl(nb, s)));
         }
@@ -95,31 +133,42 @@ template <typename T> __device__ void residual(const TailView<T>& V, int l) {
     __syncthreads();
 }
 
+template <typename T, typename C>
+__device__ __forceinline__ void vanka_node(C* x, const C* r, int c, int pitch, const Coef<T>& cf) {
+    const C edge = tadd(tadd(r[c - pitch], r[c + pitch]), tadd(r[c - 1], r[c + 1]));
+    const C corner = tadd(tadd(r[c - pitch - 1], r[c - pitch + 1]), tadd(r[c + pitch - 1], r[c + pitch + 1]));
+    C u = tfma(x[c], cf.ca, r[c]);
+    u = tfma(u, cf.cb, edge);
+    x[c] = tfma(u, cf.cc, corner);
+}
+
 // x += ca r + cb (edge sum of r) + cc (corner sum of r), in place
-template <typename T> __device__ void smooth(const TailView<T>& V, int l) {
+template <typename T> __device__ void smooth(const TailView<T>& V, int l, const Level0<T>& f) {
     using C = cplx<T>;
-    residual(V, l);
+    residual(V, l, f);
     const LevelView v = V.S->lv[l];
     const int pitch = v.nx + 2;
     const Coef<T> cf = V.S->coef[l][V.sys];
     C* x = V.lds + V.xo(l);
     const C* r = V.lds + V.ro(l);
+    if (l == 0) {
+#pragma unroll
+        for (int j = 0; j < Level0<T>::JMAX; ++j)
+            if ((f.in >> j) & 1u) vanka_node<T>(x, r, (int)threadIdx.x + j * TT, pitch, cf);
+        __syncthreads();
+        return;
+    }
     for (int t = threadIdx.x; t < v.nx * v.ny; t += TT) {
         const int k = t / v.nx + 1, i = t - (k - 1) * v.nx + 1;
-        const int c = k * pitch + i;
-        const C edge = tadd(tadd(r[c - pitch], r[c + pitch]), tadd(r[c - 1], r[c + 1]));
-        const C corner = tadd(tadd(r[c - pitch - 1], r[c - pitch + 1]), tadd(r[c + pitch - 1], r[c + pitch + 1]));
-        C u = tfma(x[c], cf.ca, r[c]);
-        u = tfma(u, cf.cb, edge);
-        x[c] = tfma(u, cf.cc, corner);
+        vanka_node<T>(x, r, k * pitch + i, pitch, cf);
     }
     __syncthreads();
 }
 
 // b_{l+1} = FW(b - L x) at level l; x_{l+1} = 0 (ring included)
-template <typename T> __device__ void restrict_down(const TailView<T>& V, int l) {
+template <typename T> __device__ void restrict_down(const TailView<T>& V, int l, const Level0<T>& f) {
     using C = cplx<T>;
-    residual(V, l);
+    residual(V, l, f);
     const LevelView v = V.S->lv[l], vc = V.S->lv[l + 1];
     const int pitch = v.nx + 2, pc = vc.nx + 2;
     const C* r = V.lds + V.ro(l);
@@ -219,9 +268,16 @@ __global__ __launch_bounds__(TT) void k_tail(const TailSeg<T>* __restrict__ segs
     const LevelView v0 = V.S->lv[0], g0 = V.S->gv;
     C* x0 = V.lds;
     C* gx = xg + (int64_t)V.sys * g0.plane;
-    for (int t = threadIdx.x; t < padded(v0); t += TT) {
+    Level0<T> f;
+    f.in = 0u;
+#pragma unroll
+    for (int j = 0; j < Level0<T>::JMAX; ++j) {
+        const int t = threadIdx.x + j * TT;
         const int k = t / (v0.nx + 2), i = t - k * (v0.nx + 2);
-        x0[t] = (xz || i < 1 || i > v0.nx || k < 1 || k > v0.ny) ? tz<C>() : gx[(int64_t)k * g0.pitch + i];
+        const bool inner = t < padded(v0) && i >= 1 && i <= v0.nx && k >= 1 && k <= v0.ny;
+        f.b[j] = inner ? load_b0(V, k, i) : tz<C>();
+        f.in |= (inner ? 1u : 0u) << j;
+        if (t < padded(v0)) x0[t] = (xz || !inner) ? tz<C>() : gx[(int64_t)k * g0.pitch + i];
     }
     __syncthreads();
     // MG(0) with gamma visits of every coarser level, without recursion:
@@ -236,8 +292,8 @@ __global__ __launch_bounds__(TT) void k_tail(const TailSeg<T>* __restrict__ segs
                 down = false;
                 continue;
             }
-            for (int it = 0; it < nu1; ++it) smooth(V, l);
-            restrict_down(V, l);
+            for (int it = 0; it < nu1; ++it) smooth(V, l, f);
+            restrict_down(V, l, f);
             cnt &= ~(15u << (4 * l));
             ++l;
             continue;
@@ -251,7 +307,7 @@ __global__ __launch_bounds__(TT) void k_tail(const TailSeg<T>* __restrict__ segs
             continue;
         }
         prolong_up(V, p);
-        for (int it = 0; it < nu2; ++it) smooth(V, p);
+        for (int it = 0; it < nu2; ++it) smooth(V, p, f);
         l = p;
     }
     for (int t = threadIdx.x; t < v0.nx * v0.ny; t += TT) {
