@@ -253,17 +253,22 @@ struct DownPipe {
     unsigned ox, ob, oo, of;  // lane byte offsets: x, b, x written, coarse b (or OOB)
     unsigned rx;              // bytes per fine row
     unsigned rc;              // bytes per coarse row
+    // physical fine / coarse row of pipeline row j / coarse row K: the
+    // identity, or the reflection j -> ny + 1 - j for runs that stream upward
+    int fa, fs, ca, cs;
+    __device__ __forceinline__ int fph(int j) const { return fa + fs * j; }
+    __device__ __forceinline__ int cph(int K) const { return ca + cs * K; }
 
     template <bool EDGE> __device__ __forceinline__ C load_x(int j) const {
         C v;
-        if constexpr (EDGE) bload(xs, ox + (j >= 0 && j <= lf.ny + 1 ? j * rx : OOB), 0, v);
-        else bload(xs, ox, j * rx, v);
+        if constexpr (EDGE) bload(xs, ox + (j >= 0 && j <= lf.ny + 1 ? fph(j) * rx : OOB), 0, v);
+        else bload(xs, ox, fph(j) * rx, v);
         return v;
     }
     template <bool EDGE> __device__ __forceinline__ C load_b(int j) const {
         C v;
-        if constexpr (EDGE) bload(bs, ob + (in_rows(j, lf.ny) ? j * rx : OOB), 0, v);
-        else bload(bs, ob, j * rx, v);
+        if constexpr (EDGE) bload(bs, ob + (in_rows(j, lf.ny) ? fph(j) * rx : OOB), 0, v);
+        else bload(bs, ob, fph(j) * rx, v);
         return v;
     }
     // step at row j, phase P: push x_0 row j and b row j - 1; stage q turns
@@ -291,8 +296,8 @@ struct DownPipe {
         }
         if constexpr (NS > 0) {
             const int orow = j - 2 * NS;
-            if constexpr (EDGE) bstore(xos, oo + (orow >= k0 && orow <= k1 ? orow * rx : OOB), 0, X[NS][n0]);
-            else bstore(xos, oo, orow * rx, X[NS][n0]);
+            if constexpr (EDGE) bstore(xos, oo + (orow >= k0 && orow <= k1 ? fph(orow) * rx : OOB), 0, X[NS][n0]);
+            else bstore(xos, oo, fph(orow) * rx, X[NS][n0]);
         }
         // full weighting around fine row j - 2NS - 2 (even rows carry coarse nodes)
         if constexpr ((P & 1) == 0) {
@@ -300,8 +305,8 @@ struct DownPipe {
             const C v = full_weight_row<T>(R[NS][n2], R[NS][n1], R[NS][n0]);
             const int K = frow >> 1;
             if constexpr (EDGE)
-                bstore(bcs, of + (frow >= k0 && frow <= k1 && frow >= 2 && K <= lc.ny ? K * rc : OOB), 0, v);
-            else bstore(bcs, of, K * rc, v);
+                bstore(bcs, of + (frow >= k0 && frow <= k1 && frow >= 2 && K <= lc.ny ? cph(K) * rc : OOB), 0, v);
+            else bstore(bcs, of, cph(K) * rc, v);
         }
     }
     // (the scheduling barriers keep each step's loads in their step, so that
@@ -322,10 +327,33 @@ struct DownPipe {
     }
 };
 
+// Rows of a run.  Neighbouring runs of a strip walk in opposite directions:
+// an odd run takes its rows from the bottom up, through the reflection
+// j -> ny + 1 - j of the fine grid and K -> nyc + 1 - K of the coarse one
+// (every level has an odd row count, so the reflection keeps the parity of a
+// row and the pairing of fine row 2K with coarse row K).  Two runs that share
+// halo rows then reach them at the end of both walks, about the same time, and
+// the second reads come from L2.  k0, k1 become pipeline rows.
+template <typename Pipe> __device__ __forceinline__ void set_rows(Pipe& p, bool rev, int& k0, int& k1) {
+    const bool r = rev && (p.lf.ny & 1) != 0;
+    p.fa = r ? p.lf.ny + 1 : 0;
+    p.fs = r ? -1 : 1;
+    p.ca = r ? p.lc.ny + 1 : 0;
+    p.cs = p.fs;
+    if (r) {
+        const int t = p.lf.ny + 1 - k1;
+        k1 = p.lf.ny + 1 - k0;
+        k0 = t;
+    }
+    p.k0 = k0;
+    p.k1 = k1;
+}
+
 // One wave's share of the work: rows k0..k1 of strip `strip` of system
 // `sys` of segment S (the pipeline adds its halo rows itself).
 template <typename T, int NS>
-__device__ __forceinline__ void down_piece(const LevelSeg<T>& S, int sys, int strip, int k0, int k1, int lane) {
+__device__ __forceinline__ void down_piece(const LevelSeg<T>& S, int sys, int strip, int k0, int k1, bool rev,
+                                           int lane) {
     using C = cplx<T>;
     using Pipe = DownPipe<T, NS>;
     constexpr int HALO = Pipe::HALO, OWN = Pipe::OWN;
@@ -344,8 +372,7 @@ __device__ __forceinline__ void down_piece(const LevelSeg<T>& S, int sys, int st
     p.of = (own && !(i & 1) && (i >> 1) <= p.lc.nx) ? (i >> 1) * es : OOB;
     p.rx = p.lf.pitch * es;
     p.rc = p.lc.pitch * es;
-    p.k0 = k0;
-    p.k1 = k1;
+    set_rows(p, rev, k0, k1);
     const int64_t base = (int64_t)sys * p.lf.plane;
     p.xs = plane_rsrc(S.x + base, p.lf.plane);
     p.bs = plane_rsrc(S.b + base, p.lf.plane);
@@ -393,6 +420,7 @@ template <typename T> __device__ __forceinline__ LevelSeg<T> seg_of_wave(const S
 // go to neighbouring waves (same XCD, same time).
 struct Piece {
     int sys, strip, k0, k1, slot;
+    bool rev;  // odd runs stream their rows upward (see set_rows)
 };
 // Waves are numbered strips fastest: the waves of a block, and neighbouring
 // blocks, cover adjacent strips of the same rows, so the halo columns two
@@ -406,6 +434,7 @@ template <typename T> __device__ __forceinline__ Piece piece_of(const LevelSeg<T
     pc.slot = lw;  // == (sys * pieces + run) * strips + strip
     pc.k0 = 1 + run * S.rows;
     pc.k1 = min(S.lf.ny, pc.k0 + S.rows - 1);
+    pc.rev = (run & 1) != 0;
     return pc;
 }
 
@@ -421,7 +450,7 @@ __global__ __launch_bounds__(NT) VMG_STREAM_OCC void k_down(SegTable<T> tab) {
     if (lw >= S.waves) return;  // whole wave idle; no block barriers in this kernel
     const Piece pc = piece_of(S, lw);
     if (pc.k0 > pc.k1 || !S.active[pc.sys]) return;
-    down_piece<T, NS>(S, pc.sys, pc.strip, pc.k0, pc.k1, lane);
+    down_piece<T, NS>(S, pc.sys, pc.strip, pc.k0, pc.k1, pc.rev, lane);
 }
 
 template <typename T, int NS, bool NORM>
@@ -449,24 +478,29 @@ struct UpPipe {
     T mk, hf;  // 1 / 0 on interior / other columns; 1/2 / 0 on odd / even columns
     unsigned ox, oe, oo;  // lane byte offsets: x and b, coarse e, x written (or OOB)
     unsigned rx, rc, ro;  // row strides in bytes: x and b, coarse e, x written
+    // physical fine / coarse row of pipeline row j / coarse row K: the
+    // identity, or the reflection j -> ny + 1 - j for runs that stream upward
+    int fa, fs, ca, cs;
+    __device__ __forceinline__ int fph(int j) const { return fa + fs * j; }
+    __device__ __forceinline__ int cph(int K) const { return ca + cs * K; }
     double acc;
 
     template <bool EDGE> __device__ __forceinline__ C load_x(int j) const {
         C v;
-        if constexpr (EDGE) bload(xs, ox + (in_rows(j, lf.ny) ? j * rx : OOB), 0, v);
-        else bload(xs, ox, j * rx, v);
+        if constexpr (EDGE) bload(xs, ox + (in_rows(j, lf.ny) ? fph(j) * rx : OOB), 0, v);
+        else bload(xs, ox, fph(j) * rx, v);
         return v;
     }
     template <bool EDGE> __device__ __forceinline__ C load_b(int j) const {
         C v;
-        if constexpr (EDGE) bload(bs, ox + (in_rows(j, lf.ny) ? j * rx : OOB), 0, v);
-        else bload(bs, ox, j * rx, v);
+        if constexpr (EDGE) bload(bs, ox + (in_rows(j, lf.ny) ? fph(j) * rx : OOB), 0, v);
+        else bload(bs, ox, fph(j) * rx, v);
         return v;
     }
     template <bool EDGE> __device__ __forceinline__ C load_e(int K) const {
         C v;
-        if constexpr (EDGE) bload(es, oe + (K >= 0 && K <= lc.ny + 1 ? K * rc : OOB), 0, v);
-        else bload(es, oe, K * rc, v);
+        if constexpr (EDGE) bload(es, oe + (K >= 0 && K <= lc.ny + 1 ? cph(K) * rc : OOB), 0, v);
+        else bload(es, oe, cph(K) * rc, v);
         return v;
     }
     // coarse column i/2 at an even fine column; the average of coarse columns
@@ -522,8 +556,8 @@ struct UpPipe {
         }
         pin(X[0][n0]);
         const int orow = j - 2 * NS;
-        if constexpr (EDGE) bstore(xos, oo + (orow >= k0 && orow <= k1 ? orow * ro : OOB), 0, X[NS][n0]);
-        else bstore(xos, oo, orow * ro, X[NS][n0]);
+        if constexpr (EDGE) bstore(xos, oo + (orow >= k0 && orow <= k1 ? fph(orow) * ro : OOB), 0, X[NS][n0]);
+        else bstore(xos, oo, fph(orow) * ro, X[NS][n0]);
     }
     template <bool EDGE> __device__ __forceinline__ void block(int j) {
         step<0, EDGE>(j);
@@ -544,7 +578,8 @@ struct UpPipe {
 // Rows k0..k1 of one strip of one system; returns the lane's share of
 // sum |b - L x|^2 over the owned columns and rows (NORM).
 template <typename T, int NS, bool NORM>
-__device__ __forceinline__ double up_piece(const LevelSeg<T>& S, int sys, int strip, int k0, int k1, int lane) {
+__device__ __forceinline__ double up_piece(const LevelSeg<T>& S, int sys, int strip, int k0, int k1, bool rev,
+                                           int lane) {
     using C = cplx<T>;
     using Pipe = UpPipe<T, NS, NORM>;
     constexpr int HALO = Pipe::HALO, OWN = Pipe::OWN;
@@ -564,8 +599,7 @@ __device__ __forceinline__ double up_piece(const LevelSeg<T>& S, int sys, int st
     p.oo = own ? i * es : OOB;
     p.rx = p.lf.pitch * es;
     p.rc = p.lc.pitch * es;
-    p.k0 = k0;
-    p.k1 = k1;
+    set_rows(p, rev, k0, k1);
     const int64_t base = (int64_t)sys * p.lf.plane;
     // finishing pass (S.iters set): the iterate read is the one the system's
     // last cycle-edge pass read, x after an even number of cycles and xalt
@@ -635,7 +669,7 @@ __global__ __launch_bounds__(NT) VMG_STREAM_OCC void k_up(SegTable<T> tab) {
     const Piece pc = piece_of(S, lw);
     if (!S.iters && !S.active[pc.sys]) return;  // (the finishing pass runs for every system)
     double acc = 0.0;
-    if (pc.k0 <= pc.k1) acc = up_piece<T, NS, NORM>(S, pc.sys, pc.strip, pc.k0, pc.k1, lane);
+    if (pc.k0 <= pc.k1) acc = up_piece<T, NS, NORM>(S, pc.sys, pc.strip, pc.k0, pc.k1, pc.rev, lane);
     if (NORM && S.partial) {
         for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
         if (lane == 0) S.partial[pc.slot] = acc;
@@ -691,24 +725,29 @@ struct EdgePipe {
     T mk, hf;  // 1 / 0 on interior / other columns; 1/2 / 0 on odd / even columns
     unsigned ox, oe, oo, of;
     unsigned rx, rc;
+    // physical fine / coarse row of pipeline row j / coarse row K: the
+    // identity, or the reflection j -> ny + 1 - j for runs that stream upward
+    int fa, fs, ca, cs;
+    __device__ __forceinline__ int fph(int j) const { return fa + fs * j; }
+    __device__ __forceinline__ int cph(int K) const { return ca + cs * K; }
     double acc;
 
     template <bool EDGE> __device__ __forceinline__ C load_x(int j) const {
         C v;
-        if constexpr (EDGE) bload(xs, ox + (in_rows(j, lf.ny) ? j * rx : OOB), 0, v);
-        else bload(xs, ox, srow(j, rx), v);
+        if constexpr (EDGE) bload(xs, ox + (in_rows(j, lf.ny) ? fph(j) * rx : OOB), 0, v);
+        else bload(xs, ox, srow(fph(j), rx), v);
         return v;
     }
     template <bool EDGE> __device__ __forceinline__ C load_b(int j) const {
         C v;
-        if constexpr (EDGE) bload(bs, ox + (in_rows(j, lf.ny) ? j * rx : OOB), 0, v);
-        else bload(bs, ox, srow(j, rx), v);
+        if constexpr (EDGE) bload(bs, ox + (in_rows(j, lf.ny) ? fph(j) * rx : OOB), 0, v);
+        else bload(bs, ox, srow(fph(j), rx), v);
         return v;
     }
     template <bool EDGE> __device__ __forceinline__ C load_e(int K) const {
         C v;
-        if constexpr (EDGE) bload(es, oe + (K >= 0 && K <= lc.ny + 1 ? K * rc : OOB), 0, v);
-        else bload(es, oe, srow(K, rc), v);
+        if constexpr (EDGE) bload(es, oe + (K >= 0 && K <= lc.ny + 1 ? cph(K) * rc : OOB), 0, v);
+        else bload(es, oe, srow(cph(K), rc), v);
         return v;
     }
     __device__ __forceinline__ C interp_x(C v) const {
@@ -720,8 +759,8 @@ struct EdgePipe {
         return r;
     }
     template <bool EDGE> __device__ __forceinline__ void store_row(rsrc_t r, int row, C v) const {
-        if constexpr (EDGE) bstore(r, oo + (row >= k0 && row <= k1 ? row * rx : OOB), 0, v);
-        else bstore(r, oo, srow(row, rx), v);
+        if constexpr (EDGE) bstore(r, oo + (row >= k0 && row <= k1 ? fph(row) * rx : OOB), 0, v);
+        else bstore(r, oo, srow(fph(row), rx), v);
     }
     template <int P, bool EDGE> __device__ __forceinline__ void step(int j) {
         xr[eslot<EPF + 1>(P + EPF)] = load_x<EDGE>(j + EPF);
@@ -776,8 +815,8 @@ struct EdgePipe {
             const C v = full_weight_row<T>(R[NS][n2], R[NS][n1], R[NS][n0]);
             const int K = frow >> 1;
             if constexpr (EDGE)
-                bstore(cbs, of + (frow >= k0 && frow <= k1 && frow >= 2 && K <= lc.ny ? K * rc : OOB), 0, v);
-            else bstore(cbs, of, srow(K, rc), v);
+                bstore(cbs, of + (frow >= k0 && frow <= k1 && frow >= 2 && K <= lc.ny ? cph(K) * rc : OOB), 0, v);
+            else bstore(cbs, of, srow(cph(K), rc), v);
         }
     }
     template <bool EDGE> __device__ __forceinline__ void block(int j) {
@@ -791,8 +830,8 @@ struct EdgePipe {
 };
 
 template <typename T, int NA, int NB>
-__device__ __forceinline__ double edge_piece(const LevelSeg<T>& S, int sys, int strip, int k0, int k1, int lane,
-                                             cplx<T>* bring) {
+__device__ __forceinline__ double edge_piece(const LevelSeg<T>& S, int sys, int strip, int k0, int k1, bool rev,
+                                             int lane, cplx<T>* bring) {
     using C = cplx<T>;
     using Pipe = EdgePipe<T, NA, NB>;
     constexpr int HALO = Pipe::HALO, OWN = Pipe::OWN, NS = Pipe::NS, U = UNR_E;
@@ -816,8 +855,7 @@ __device__ __forceinline__ double edge_piece(const LevelSeg<T>& S, int sys, int 
     p.of = (own && !(i & 1) && (i >> 1) <= p.lc.nx) ? (i >> 1) * es : OOB;
     p.rx = p.lf.pitch * es;
     p.rc = p.lc.pitch * es;
-    p.k0 = k0;
-    p.k1 = k1;
+    set_rows(p, rev, k0, k1);
     const int64_t base = (int64_t)sys * p.lf.plane;
     p.xs = plane_rsrc(S.x + base, p.lf.plane);
     p.bs = plane_rsrc(S.b + base, p.lf.plane);
@@ -865,10 +903,12 @@ __global__ __launch_bounds__(NT) VMG_STREAM_OCC void k_edge(SegTable<T> tab) {
     if (lw >= S.waves) return;
     const Piece pc = piece_of(S, lw);
     if (!S.active[pc.sys]) return;
+    // (every run walks downward here: the kernel is at its register limit and
+    // measured slower with the reflected address arithmetic)
 #if VMG_EDGE_BLDS
-    double acc = edge_piece<T, NA, NB>(S, pc.sys, pc.strip, pc.k0, pc.k1, lane, bring[threadIdx.x >> 6]);
+    double acc = edge_piece<T, NA, NB>(S, pc.sys, pc.strip, pc.k0, pc.k1, false, lane, bring[threadIdx.x >> 6]);
 #else
-    double acc = edge_piece<T, NA, NB>(S, pc.sys, pc.strip, pc.k0, pc.k1, lane, nullptr);
+    double acc = edge_piece<T, NA, NB>(S, pc.sys, pc.strip, pc.k0, pc.k1, false, lane, nullptr);
 #endif
     if (S.partial) {
         for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
