@@ -388,7 +388,7 @@ bool sched_stream(const vmg_handle* H, const Group& g, int l) {
 // runs with the current kernel schedule.
 bool edge_possible(const vmg_handle* H, const Group& g) {
     const vmg_opts& o = H->opts;
-    return H->edge_mode != 0 && o.precision == 0 && o.gamma == 1 && edge_supported(o.nu1, o.nu2) && g.L >= 2;
+    return H->edge_mode != 0 && o.gamma == 1 && edge_supported(o.nu1, o.nu2) && g.L >= 2;
 }
 bool sched_stream(const vmg_handle* H, const Group& g, int l);
 // Untuned, the kernel pays off once the finest levels of all systems hold
@@ -580,18 +580,26 @@ template <> void launch_edge_t<double>(SegTable<double> tab, const int* nsys, in
                                        hipStream_t st) {
     launch_edge<double>(tab, nsys, nu1, nu2, rmin, st);
 }
-template <> void launch_edge_t<float>(SegTable<float>, const int*, int, int, int, hipStream_t) {}
+template <> void launch_edge_t<float>(SegTable<float> tab, const int* nsys, int nu1, int nu2, int rmin,
+                                      hipStream_t st) {
+    launch_edge<float>(tab, nsys, nu1, nu2, rmin, st);
+}
 
 // One V-cycle of every grid, batched: the grids are aligned at their
 // coarsest level, so phase d (d levels above the coarsest) is one launch per
 // kernel over all grids that reach that high, whatever their sizes.
 //   cur[g][l]   ping-pong state of grid g, level l (updated)
 //   first       level 0 starts from x = 0 (first cycle)
+//   last        the finest level ends the cycle with its own correction pass
+//               (the cycle-edge kernel otherwise runs it together with the
+//               next cycle's pre-smoothing; FP64 solves never set it: their
+//               last iterate is rebuilt by the finishing pass)
 //   partials[g] fused finest-level norm target of grid g (or NULL)
 //   fused[g]    set when grid g's norm partials were produced
 template <typename T>
-void enqueue_batched_vcycle(vmg_handle* H, int conj, hipStream_t st, bool first, std::vector<std::vector<int>>& cur,
-                            const std::vector<double*>& partials, std::vector<char>& fused) {
+void enqueue_batched_vcycle(vmg_handle* H, int conj, hipStream_t st, bool first, bool last,
+                            std::vector<std::vector<int>>& cur, const std::vector<double*>& partials,
+                            std::vector<char>& fused) {
     const vmg_opts& o = H->opts;
     const double E = sizeof(cplx<T>);
     const int ng = (int)H->groups.size();
@@ -609,7 +617,7 @@ void enqueue_batched_vcycle(vmg_handle* H, int conj, hipStream_t st, bool first,
             const int l = level_of(gi, d);
             // with the cycle-edge kernel the finest level's pre-smoothing and
             // restriction were done by the previous cycle (all but the first)
-            if (l == 0 && !first && std::is_same<T, double>::value && use_edge(H, H->groups[gi])) continue;
+            if (l == 0 && !first && use_edge(H, H->groups[gi])) continue;
             (sched_stream(H, H->groups[gi], l) ? sg : lg).push_back(gi);
         }
         // streamed grids: one fused launch per row-block height
@@ -728,7 +736,7 @@ void enqueue_batched_vcycle(vmg_handle* H, int conj, hipStream_t st, bool first,
         for (int gi = 0; gi < ng; ++gi) {
             if (H->groups[gi].L - 1 < d || level_of(gi, d) >= tail_start(H->groups[gi])) continue;
             const int l = level_of(gi, d);
-            if (l == 0 && std::is_same<T, double>::value && use_edge(H, H->groups[gi])) {
+            if (l == 0 && !last && use_edge(H, H->groups[gi])) {
                 eg.push_back(gi);
                 continue;
             }
@@ -856,12 +864,12 @@ int level0_flips(const vmg_handle* H, const Group& g) {
 // the cycle-edge kernel the pre-smoothed iterate alternates once per cycle,
 // after the first cycle's separate pre-smoothing pass.
 int level0_parity(const vmg_handle* H, const Group& g, int64_t cycle) {
-    if (use_edge(H, g)) return (int)((cycle + (cycle > 0 ? 1 : 0)) & 1);
+    if (H->opts.precision == 0 && use_edge(H, g)) return (int)((cycle + (cycle > 0 ? 1 : 0)) & 1);
     return (int)((cycle * level0_flips(H, g)) & 1);
 }
 
 int norm_tiles(const vmg_handle* H, const Group& g) {
-    if (use_edge(H, g))
+    if (H->opts.precision == 0 && use_edge(H, g))
         return edge_tiles<double>(g.lv64[0].v.nx, g.lv64[0].v.ny, g.S, H->opts.nu1, H->opts.nu2, sched_rows(H, g, 0));
     return stream_tiles<double>(g.lv64[0].v.nx, g.lv64[0].v.ny, g.S, H->opts.nu2, sched_rows(H, g, 0));
 }
@@ -986,7 +994,7 @@ int enqueue_cycle_all(vmg_handle* H, int conj, hipStream_t st, int64_t cycle, do
                 cur[gi][0] = level0_parity(H, g, cycle);
                 parts[gi] = g.partial;
             }
-            enqueue_batched_vcycle<double>(H, conj, st, first, cur, parts, fused);
+            enqueue_batched_vcycle<double>(H, conj, st, first, false, cur, parts, fused);
             for (size_t gi = 0; gi < ng; ++gi) cur0[gi] = cur[gi][0];
         } else {
             for (size_t gi = 0; gi < ng; ++gi) {
@@ -1005,7 +1013,8 @@ int enqueue_cycle_all(vmg_handle* H, int conj, hipStream_t st, int64_t cycle, do
         if (o.gamma == 1) {
             std::vector<double*> parts(ng, nullptr);
             std::vector<char> dummy(ng, 0);
-            for (int k = 0; k < o.ir_inner; ++k) enqueue_batched_vcycle<float>(H, conj, st, k == 0, cur, parts, dummy);
+            for (int k = 0; k < o.ir_inner; ++k)
+                enqueue_batched_vcycle<float>(H, conj, st, k == 0, k == o.ir_inner - 1, cur, parts, dummy);
         } else {
             for (size_t gi = 0; gi < ng; ++gi) {
                 Group& g = H->groups[gi];
@@ -1153,7 +1162,7 @@ int solve_impl(vmg_handle* H, const double* B, double* Z, double tol, int conj, 
     off = 0;
     for (auto& g : H->groups) {
         Level& l0 = g.lv64[0];
-        if (use_edge(H, g)) {
+        if (o.precision == 0 && use_edge(H, g)) {
             // the last cycle's correction and post-smoothing, rebuilt from the
             // inputs its cycle-edge pass read (frozen since the system
             // stopped), written straight into Z
@@ -2005,14 +2014,14 @@ template <typename T> int time_level(vmg_handle* H, Group& g, int l, int cand, h
 // Time the finest level's per-cycle work with the cycle-edge kernel: one
 // launch for a cycle's correction and post-smoothing and the next cycle's
 // pre-smoothing and restriction (streaming, `rows` rows per wave).
-int time_edge(vmg_handle* H, Group& g, int rows, hipStream_t st, double* ms_out) {
-    auto& L = g.lv64;
+template <typename T> int time_edge(vmg_handle* H, Group& g, int rows, hipStream_t st, double* ms_out) {
+    auto& L = levels_of<T>(g);
     const int one = g.S;
     auto run = [&]() {
-        LevelSeg<double> S = make_seg<double>(H, g, 0, 0, P<double>(L[0].x[0]), P<double>(L[0].b),
-                                              P<double>(L[0].x[1]), P<double>(L[1].x[0]), 0, nullptr);
-        S.cb = P<double>(L[1].b);
-        launch_edge<double>(one_seg(S), &one, H->opts.nu1, H->opts.nu2, rows, st);
+        LevelSeg<T> S = make_seg<T>(H, g, 0, 0, P<T>(L[0].x[0]), P<T>(L[0].b), P<T>(L[0].x[1]), P<T>(L[1].x[0]), 0,
+                                    nullptr);
+        S.cb = P<T>(L[1].b);
+        launch_edge<T>(one_seg(S), &one, H->opts.nu1, H->opts.nu2, rows, st);
     };
     return time_reps(run, st, ms_out);
 }
@@ -2105,8 +2114,10 @@ extern "C" int vanka_mg_autotune(vmg_handle* H, const char* cache_path, void* hi
             if (found < 0) {
                 const int rows = sched_rows(H, g, 0);
                 double ms_edge = 0.0, ms_sep = 0.0;
-                int rc = time_edge(H, g, rows, st, &ms_edge);
-                if (!rc) rc = time_level<double>(H, g, 0, rows, st, &ms_sep);
+                const bool f64 = H->opts.precision == 0;
+                int rc = f64 ? time_edge<double>(H, g, rows, st, &ms_edge) : time_edge<float>(H, g, rows, st, &ms_edge);
+                if (!rc)
+                    rc = f64 ? time_level<double>(H, g, 0, rows, st, &ms_sep) : time_level<float>(H, g, 0, rows, st, &ms_sep);
                 if (rc) return rc;
                 found = ms_edge < ms_sep ? 1 : 0;
                 fresh.push_back(key + " " + std::to_string(found));

@@ -41,6 +41,9 @@ template <typename C> __device__ __forceinline__ C mul(C a, C b) {
     r.y = a.x * b.y + a.y * b.x;
     return r;
 }
+// a * b + c rounded once, in the precision of the operands
+__device__ __forceinline__ double fmar(double a, double b, double c) { return __builtin_fma(a, b, c); }
+__device__ __forceinline__ float fmar(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 template <typename C> __device__ __forceinline__ C fma2(C acc, C a, C b) {  // acc + a * b
     C r;
     r.x = acc.x + a.x * b.x - a.y * b.y;
@@ -102,8 +105,8 @@ template <typename T, typename C>
 __device__ __forceinline__ C residual_row(C xo, C xm, C xn, C bv, C d, T s) {
     const C nb = add(lr_sum(xm), add(xo, xn));
     C r;
-    r.x = __builtin_fma(d.y, xm.y, __builtin_fma(-d.x, xm.x, __builtin_fma(s, nb.x, bv.x)));
-    r.y = __builtin_fma(-d.y, xm.x, __builtin_fma(-d.x, xm.y, __builtin_fma(s, nb.y, bv.y)));
+    r.x = fmar(d.y, xm.y, fmar(-d.x, xm.x, fmar(s, nb.x, bv.x)));
+    r.y = fmar(-d.y, xm.x, fmar(-d.x, xm.y, fmar(s, nb.y, bv.y)));
     return r;
 }
 
@@ -122,8 +125,8 @@ __device__ __forceinline__ C vanka_row(C xc, C ro, C rm, C rn, const Coef<T>& cf
     C v = fma2(xc, cf.ca, rm);
     v = fma2(v, cf.cb, vs);
     const C lr = lr_sum(w);
-    v.x = __builtin_fma(mk, lr.x, v.x);
-    v.y = __builtin_fma(mk, lr.y, v.y);
+    v.x = fmar(mk, lr.x, v.x);
+    v.y = fmar(mk, lr.y, v.y);
     return v;
 }
 
@@ -509,8 +512,8 @@ struct UpPipe {
         // v + hf (right - v): the average at odd columns (hf = 1/2), v at even ones
         const C rv = from_right(v);
         C r;
-        r.x = __builtin_fma(hf, rv.x - v.x, v.x);
-        r.y = __builtin_fma(hf, rv.y - v.y, v.y);
+        r.x = fmar(hf, rv.x - v.x, v.x);
+        r.y = fmar(hf, rv.y - v.y, v.y);
         return r;
     }
     // Step at fine row j, phase P.  Coarse row K = jb/2 + c (jb the unrolled
@@ -754,8 +757,8 @@ struct EdgePipe {
         // v + hf (right - v): the average at odd columns (hf = 1/2), v at even ones
         const C rv = from_right(v);
         C r;
-        r.x = __builtin_fma(hf, rv.x - v.x, v.x);
-        r.y = __builtin_fma(hf, rv.y - v.y, v.y);
+        r.x = fmar(hf, rv.x - v.x, v.x);
+        r.y = fmar(hf, rv.y - v.y, v.y);
         return r;
     }
     template <bool EDGE> __device__ __forceinline__ void store_row(rsrc_t r, int row, C v) const {
@@ -1032,6 +1035,7 @@ template <typename T> void launch_edge(SegTable<T> tab, const int* nsys, int nu1
     else edge_go<T, 2, 2>(tab, nsys, rmin, st);
 }
 template void launch_edge<double>(SegTable<double>, const int*, int, int, int, hipStream_t);
+template void launch_edge<float>(SegTable<float>, const int*, int, int, int, hipStream_t);
 
 template <typename T> int edge_tiles(int nx, int ny, int nsys, int nu1, int nu2, int rmin) {
     if (nu2 == 1 && nu1 == 1) return edge_tiles_of<T, 1, 1>(nx, ny, nsys, rmin);
@@ -1040,6 +1044,7 @@ template <typename T> int edge_tiles(int nx, int ny, int nsys, int nu1, int nu2,
     return edge_tiles_of<T, 2, 2>(nx, ny, nsys, rmin);
 }
 template int edge_tiles<double>(int, int, int, int, int, int);
+template int edge_tiles<float>(int, int, int, int, int, int);
 
 template <typename T> int stream_tiles(int nx, int ny, int nsys, int nu, int rmin) {
     const void* k;

@@ -131,3 +131,36 @@ def test_autotune_keeps_results(monkeypatch, tmp_path):
     again.autotune(cache)
     assert [again.plan(g) for g in range(len(grids))] == plans
     assert [again.schedule(g) for g in range(len(grids))] == [fused.schedule(g) for g in range(len(grids))]
+
+
+@pytest.mark.parametrize("ir_inner", [1, 2, 3])
+def test_refinement_cycles_with_edge_kernel(ir_inner, monkeypatch):
+    """Complex64 inner cycles of the FP64 refinement: with the cycle-edge
+    kernel between the inner cycles of a refinement step (the last one ends
+    with its own correction pass) the refinement gives the level-by-level
+    results at fixed step counts, and free-running solves reach 1e-10 after
+    the same number of steps."""
+    from paper_2203_11154_amd import Grid, VankaMG
+    grids = [(383, 191, 2), (255, 255, 1)]
+    S = sum(s for _, _, s in grids)
+    lam = inputs.alpha_circulant_shifts(S)
+    b = np.concatenate([inputs.rhs(s, ny, nx, seed=95 + k).ravel() for k, (nx, ny, s) in enumerate(grids)])
+    bd = dev(b)
+    out = {}
+    for edge in ("0", "2"):
+        monkeypatch.setenv("VMG_EDGE", edge)
+        monkeypatch.setenv("VMG_TAIL", "1")
+        solver = VankaMG([Grid(nx, ny, num_systems=s) for nx, ny, s in grids], lam, precision="c64_ir",
+                         ir_inner=ir_inner)
+        plan = [solver.plan(g)[0] for g in range(len(grids))]
+        assert plan == [edge == "2"] * len(grids), plan
+        Zf, itf, rrf, stf = solver.solve(bd, fixed_iters=np.full(S, 2, np.int32))
+        Z, it, rr, st = solver.solve(bd, tol=1e-10)
+        assert st == 0 and np.all(rr <= 1e-10)
+        out[edge] = (host(Zf), rrf, it, host(Z))
+    zf0, rr0, it0, z0 = out["0"]
+    zf2, rr2, it2, z2 = out["2"]
+    assert np.linalg.norm(zf2 - zf0) <= 1e-12 * np.linalg.norm(zf0)
+    np.testing.assert_allclose(rr2, rr0, rtol=1e-6)
+    np.testing.assert_array_equal(it2, it0)
+    assert np.linalg.norm(z2 - z0) <= 1e-9 * np.linalg.norm(z0)
