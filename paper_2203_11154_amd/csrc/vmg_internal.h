@@ -108,11 +108,13 @@ int launch_residual(const cplx<T>* x, const cplx<T>* b, cplx<TO>* rout, LevelVie
                     const Coef<T>* coef, const int* active, int nsys, int x_zero, double* partial,
                     hipStream_t st);
 int residual_tiles(LevelView lv);
+// End of a refinement step: xn = x + e (x = NULL: zero), rout = complex64 of
+// b - L xn, |b - L xn|^2 per tile as launch_residual; e and rout in layout le.
+int launch_ir_residual(const double2* x, const float2* e, const double2* b, double2* xn, float2* rout, LevelView lv,
+                       LevelView le, double s, const Coef<double>* coef, const int* active, int nsys, double* partial,
+                       hipStream_t st);
 
 
-// x64 = (x_zero ? 0 : x64) + e (per active system)
-void launch_ir_update(double2* x, const float2* e, LevelView lx, LevelView le, const int* active, int nsys,
-                      int x_zero, hipStream_t st);
 
 // unpadded <-> padded interior copies.  For unpack, if iters != NULL a system
 // with iters[s] == 0 is written as zero, and if sel != NULL system s reads

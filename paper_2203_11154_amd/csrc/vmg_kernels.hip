@@ -291,21 +291,50 @@ __global__ __launch_bounds__(NT) void k_coarse(SegTable<T> tab) {
     }
 }
 
-__global__ __launch_bounds__(NT) void k_ir_update(double2* __restrict__ x, const float2* __restrict__ e,
-                                                  LevelView lx, LevelView le, const int* __restrict__ active,
-                                                  int x_zero) {
+// One refinement step's end: x' = x + e (FP64 iterate plus the complex64
+// correction; x = 0 with x_zero), written to a second buffer, and the FP64
+// residual of x' (stored as complex64, the next step's right-hand side) with
+// its per-tile |r|^2 sums, in one pass.  x' at the neighbours is formed from
+// x and e on the fly (their rings are zero).
+__global__ __launch_bounds__(NT) void k_ir_residual(const double2* __restrict__ x, const float2* __restrict__ e,
+                                                    const double2* __restrict__ b, double2* __restrict__ xn,
+                                                    float2* __restrict__ rout, LevelView lv, LevelView le, double s,
+                                                    const Coef<double>* __restrict__ coef,
+                                                    const int* __restrict__ active, double* __restrict__ partial) {
+    constexpr int TX = 64, TY = 16;
+    __shared__ double red[NT / 64];
     const int sys = blockIdx.z;
     if (!active[sys]) return;
-    const int i = blockIdx.x * 64 + (threadIdx.x & 63) + 1;
-    if (i > lx.nx) return;
-    for (int k = blockIdx.y * 16 + (threadIdx.x >> 6) + 1; k <= min(lx.ny, (int)(blockIdx.y + 1) * 16);
-         k += NT / 64) {
-        const float2 ev = e[(int64_t)sys * le.plane + (int64_t)k * le.pitch + i];
-        const int64_t o = (int64_t)sys * lx.plane + (int64_t)k * lx.pitch + i;
-        double2 v = x_zero ? make_double2(0.0, 0.0) : x[o];
+    const int i = blockIdx.x * TX + (threadIdx.x & 63) + 1;
+    const int64_t base = (int64_t)sys * lv.plane, ebase = (int64_t)sys * le.plane;
+    const Coef<double> cf = coef[sys];
+    auto xv = [&](int k, int c) {
+        const float2 ev = e[ebase + (int64_t)k * le.pitch + c];
+        double2 v = x ? x[base + (int64_t)k * lv.pitch + c] : make_double2(0.0, 0.0);
         v.x += (double)ev.x;
         v.y += (double)ev.y;
-        x[o] = v;
+        return v;
+    };
+    double acc = 0.0;
+    if (i <= lv.nx) {
+        for (int k = blockIdx.y * TY + (threadIdx.x >> 6) + 1; k <= min(lv.ny, (int)(blockIdx.y + 1) * TY);
+             k += NT / 64) {
+            const double2 xc = xv(k, i);
+            const double2 nb = cadd(cadd(xv(k - 1, i), xv(k + 1, i)), cadd(xv(k, i - 1), xv(k, i + 1)));
+            const int64_t o = base + (int64_t)k * lv.pitch + i;
+            const double2 r = csub(b[o], csub(cmul(cf.d, xc), cscale(nb, s)));
+            xn[o] = xc;
+            acc += r.x * r.x + r.y * r.y;
+            rout[ebase + (int64_t)k * le.pitch + i] = make_float2((float)r.x, (float)r.y);
+        }
+    }
+    for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double tsum = 0.0;
+        for (int w = 0; w < NT / 64; ++w) tsum += red[w];
+        partial[(int64_t)sys * (gridDim.x * gridDim.y) + blockIdx.y * gridDim.x + blockIdx.x] = tsum;
     }
 }
 
@@ -448,9 +477,13 @@ int launch_residual(const cplx<T>* x, const cplx<T>* b, cplx<TO>* rout, LevelVie
     return residual_tiles(lv);
 }
 
-void launch_ir_update(double2* x, const float2* e, LevelView lx, LevelView le, const int* active, int nsys,
-                      int x_zero, hipStream_t st) {
-    hipLaunchKernelGGL(k_ir_update, grid2(lx.nx, lx.ny, 64, 16, nsys), dim3(NT), 0, st, x, e, lx, le, active, x_zero);
+
+int launch_ir_residual(const double2* x, const float2* e, const double2* b, double2* xn, float2* rout, LevelView lv,
+                       LevelView le, double s, const Coef<double>* coef, const int* active, int nsys, double* partial,
+                       hipStream_t st) {
+    hipLaunchKernelGGL(k_ir_residual, grid2(lv.nx, lv.ny, 64, 16, nsys), dim3(NT), 0, st, x, e, b, xn, rout, lv, le, s,
+                       coef, active, partial);
+    return residual_tiles(lv);
 }
 
 template <typename T>

@@ -884,20 +884,14 @@ int enqueue_norm_check(vmg_handle* H, hipStream_t st, int mode, double tol, int 
         const int* act = H->active + g.sys0;
         int ntiles = g.ntiles0;
         if (fused[gi]) {
-            ntiles = norm_tiles(H, g);
-        } else if (H->opts.precision == 0) {
+            // (refinement steps always end with the fused update + residual)
+            ntiles = H->opts.precision == 0 ? norm_tiles(H, g) : g.ntiles0;
+        } else {
             Level& l0 = g.lv64[0];
             Timer t(H, st, VMG_K_NORM, 2.0 * 16.0 * nodes(l0.v) * g.nact);
             launch_residual<double, double>(P<double>(l0.x[cur[gi]]), P<double>(l0.b), nullptr, l0.v, l0.v,
                                             1.0 / (l0.h * l0.h), coef_of<double>(g, conj, 0), act, g.S, x_zero,
                                             g.partial, st);
-        } else {
-            Level& l0 = g.lv64[0];
-            Level& e0 = g.lv32[0];
-            Timer t(H, st, VMG_K_IR, (2.0 * 16.0 + 8.0) * nodes(l0.v) * g.nact);
-            launch_residual<double, float>(P<double>(l0.x[0]), P<double>(l0.b), P<float>(e0.b), l0.v, e0.v,
-                                           1.0 / (l0.h * l0.h), coef_of<double>(g, conj, 0), act, g.S, x_zero,
-                                           g.partial, st);
         }
         launch_norm_finalize(g.partial, ntiles, g.S, g.sys0, mode, tol, fixed, H->bb, H->relres, H->iters,
                              H->active, H->target, H->nanflag, st);
@@ -1023,13 +1017,19 @@ int enqueue_cycle_all(vmg_handle* H, int conj, hipStream_t st, int64_t cycle, do
                 cur[gi] = ctx.cur;
             }
         }
+        // x' = x + e into the other FP64 buffer (refinement k reads buffer
+        // k mod 2), fused with the residual of x' that the stopping test and
+        // the next step's right-hand side need
+        const int p = (int)(cycle & 1);
         for (size_t gi = 0; gi < ng; ++gi) {
             Group& g = H->groups[gi];
             Level& l0 = g.lv64[0];
             Level& e0 = g.lv32[0];
-            Timer t(H, st, VMG_K_IR, (first ? 24.0 : 40.0) * nodes(l0.v) * g.nact);
-            launch_ir_update(P<double>(l0.x[0]), P<float>(e0.x[cur[gi][0]]), l0.v, e0.v, H->active + g.sys0, g.S, first,
-                             st);
+            Timer t(H, st, VMG_K_IR, ((first ? 0.0 : 16.0) + 8.0 + 16.0 + 16.0 + 8.0) * nodes(l0.v) * g.nact);
+            launch_ir_residual(first ? nullptr : P<double>(l0.x[p]), P<float>(e0.x[cur[gi][0]]), P<double>(l0.b),
+                               P<double>(l0.x[1 - p]), P<float>(e0.b), l0.v, e0.v, 1.0 / (l0.h * l0.h),
+                               coef_of<double>(g, conj, 0), H->active + g.sys0, g.S, g.partial, st);
+            fused[gi] = 1;
         }
     }
     return enqueue_norm_check(H, st, 1, tol, fixed, conj, cur0, fused);
@@ -1043,7 +1043,7 @@ int run_cycle(vmg_handle* H, int conj, hipStream_t st, int64_t cycle, double tol
     int par = 0;
     for (size_t gi = 0; gi < H->groups.size(); ++gi)
         par |= level0_parity(H, H->groups[gi], cycle) << (gi & 31);
-    if (H->opts.precision == 1) par = 0;
+    if (H->opts.precision == 1) par = (int)(cycle & 1);  // the FP64 iterate's buffer
     GraphKey key{cycle == 0 ? 1 : 0, conj, fixed, par, tol};
     hipGraphExec_t exec = nullptr;
     for (auto& e : H->graphs)
@@ -1176,9 +1176,10 @@ int solve_impl(vmg_handle* H, const double* B, double* Z, double tol, int conj, 
             launch_up<double>(one_seg(S), &one, o.nu2, false, sched_rows(H, g, 0), st);
         } else {
             Timer t(H, st, VMG_K_PACK, 32.0 * nodes(l0.v) * g.S);
-            const int flips = o.precision == 0 ? level0_flips(H, g) : 0;
-            launch_unpack<double>(P<double>(l0.x[0]), o.precision == 0 ? P<double>(l0.x[1]) : nullptr,
-                                  reinterpret_cast<double2*>(Z) + off, l0.v, g.S, H->iters + g.sys0, flips, st);
+            // (refinement: after k steps the FP64 iterate is in buffer k mod 2)
+            const int flips = o.precision == 0 ? level0_flips(H, g) : 1;
+            launch_unpack<double>(P<double>(l0.x[0]), P<double>(l0.x[1]), reinterpret_cast<double2*>(Z) + off, l0.v,
+                                  g.S, H->iters + g.sys0, flips, st);
         }
         off += (int64_t)g.nx * g.ny * g.S;
     }
@@ -1499,7 +1500,7 @@ int vanka_mg_setup(const vmg_grid* grids, int32_t n_grids, const double* shifts,
         for (size_t l = 0; l < G.lv64.size(); ++l) {
             Level& L = G.lv64[l];
             VMG_TRY(alloc_planes<double>(H, L.x[0], L.v, G.S));
-            if (o.precision == 0) VMG_TRY(alloc_planes<double>(H, L.x[1], L.v, G.S));
+            VMG_TRY(alloc_planes<double>(H, L.x[1], L.v, G.S));  // (refinement: the FP64 iterate alternates)
             VMG_TRY(alloc_planes<double>(H, L.b, L.v, G.S));
         }
         for (size_t l = 0; l < G.lv32.size(); ++l) {
