@@ -77,6 +77,39 @@ def cpu_baseline(b, lam, h, tol, count):
                       f"({int(iters.sum())} cycles, {dt:.1f} s; transforms excluded)"}
 
 
+def precision_leg(args, torch):
+    """The precision workload: 32 alpha-circulant shifts (alpha = 0.01,
+    tau = 1/32) on 2047^2, the ParaDIAG step to 1e-10 with complex64 V-cycles
+    inside FP64 refinement against FP64 V-cycles (both uninstrumented, cycles
+    replayed as graphs, autotuned; refinement with 2 inner cycles a step)."""
+    from paper_2203_11154_amd import Grid, VankaMG, inputs
+    n, S, tol = 2047, 32, args.tol
+    lam = inputs.alpha_circulant_shifts(S, 0.01)
+    V, Vinv = inputs.alpha_circulant_vectors(S, 0.01)
+    b = inputs.rhs(S, n, n, seed=4)
+    Fd = torch.from_numpy(np.ascontiguousarray(V @ b.reshape(S, -1)).ravel()).cuda()
+    del b
+    Vd, Vinvd = torch.from_numpy(V).cuda(), torch.from_numpy(Vinv).cuda()
+    Ud = torch.empty_like(Fd)
+    res = {"workload": "precision_2047: 32 alpha-circulant shifts on 2047x2047, ParaDIAG step to 1e-10"}
+    for name, kw in (("fp64", {}), ("fp32_ir", {"precision": "c64_ir", "ir_inner": 2})):
+        s = VankaMG([Grid(n, num_systems=S)], lam, **kw)
+        if not args.no_autotune:
+            s.autotune()
+        for _ in range(args.warmup):
+            s.paradiag_apply(Vd, Vinvd, Fd, tol=tol, out=Ud)
+        dt, st = run_steps(s, Vd, Vinvd, Fd, Ud, args.steps, tol, torch)
+        it, rr = s.last_stats()
+        res[name] = {"ms_per_step": round(1e3 * dt / args.steps, 3), "value": round(S * args.steps / dt, 2),
+                     "cycles_or_steps": {"min": int(it.min()), "max": int(it.max())}, "max_relres": float(rr.max()),
+                     "converged": st == 0 and bool(np.all(rr <= tol))}
+        del s
+    res["speedup_vs_fp64"] = round(res["fp64"]["ms_per_step"] / res["fp32_ir"]["ms_per_step"], 3)
+    del Fd, Ud
+    torch.cuda.empty_cache()
+    return res
+
+
 def batched_leg(args, torch):
     """384 systems on uneven grids (256 x 127^2, 96 x 255^2, 32 x 511^2) with
     shifts Re ~ U(1, 1e4), Im ~ U(-1e4, 1e4), solved to 1e-10 in one batched,
@@ -315,6 +348,9 @@ def main():
                           "refinement_steps": {"min": int(it_ir.min()), "max": int(it_ir.max())},
                           "max_relres": float(rr_ir.max()), "converged": ok, "dtype": "c64 cycles + c128 refinement"}
         del ir
+
+    if not args.no_ir:
+        out["fp32_ir_2047"] = precision_leg(args, torch)
 
     if not args.no_batched:
         out["batched_uneven"] = batched_leg(args, torch)
