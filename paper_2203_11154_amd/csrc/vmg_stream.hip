@@ -16,6 +16,13 @@
 //   k_up<NS>:   x_0 = x + P e (bilinear correction); NS sweeps as above;
 //               optionally per-block sums of |b - L x_NS|^2 (the stopping
 //               test on the finest level).  Writes x_NS; reads x, e, b once.
+//               As the finishing pass it rebuilds the last cycle's iterate
+//               of every system from the inputs of that cycle's k_edge pass
+//               and writes it to a dense output.
+//   k_edge<NA, NB>: the finest level across the boundary of two V-cycles:
+//               k_up<NA> with the stopping-test sums, then k_down<NB> from its
+//               result, in one pass (reads x, b, e once; writes the next
+//               cycle's pre-smoothed iterate and coarse right-hand side).
 //
 // Rows or columns outside the interior hold zero in every stage (Dirichlet
 // ring for the iterates, zero residual off the interior).
@@ -418,16 +425,14 @@ template <typename T> __device__ __forceinline__ LevelSeg<T> seg_of_wave(const S
 
 // Work split: every strip of every system is cut into S.pieces runs of
 // S.rows rows (the last one shorter), one per wave; the host picks the cut so
-// that the waves fill the device evenly.  Waves are numbered with the run
-// fastest, then the strip, then the system, so neighbouring runs and strips
-// go to neighbouring waves (same XCD, same time).
+// that the waves fill the device evenly.  Waves are numbered with the strip
+// fastest, then the run, then the system: the waves of a block, and
+// neighbouring blocks, cover adjacent strips of the same rows, so the halo
+// columns two strips share are read close together in time (mostly from L2).
 struct Piece {
     int sys, strip, k0, k1, slot;
     bool rev;  // odd runs stream their rows upward (see set_rows)
 };
-// Waves are numbered strips fastest: the waves of a block, and neighbouring
-// blocks, cover adjacent strips of the same rows, so the halo columns two
-// strips share are read close together in time (mostly from L2).
 template <typename T> __device__ __forceinline__ Piece piece_of(const LevelSeg<T>& S, int lw) {
     Piece pc;
     const int t = lw / S.strips;
