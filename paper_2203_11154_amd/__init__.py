@@ -9,9 +9,9 @@ does, and fails loudly if it has not been built.
 """
 import importlib
 
-__all__ = ["Grid", "VankaMG", "transform", "ShiftedSolve", "ParaDiag", "inputs"]
+__all__ = ["Grid", "VankaMG", "transform", "transform_circulant", "ShiftedSolve", "ParaDiag", "inputs"]
 
-_LAZY = {"Grid": "solver", "VankaMG": "solver", "transform": "solver",
+_LAZY = {"Grid": "solver", "VankaMG": "solver", "transform": "solver", "transform_circulant": "solver",
          "ShiftedSolve": "autograd", "ParaDiag": "autograd"}
 
 
