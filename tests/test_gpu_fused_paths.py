@@ -160,7 +160,16 @@ def test_refinement_cycles_with_edge_kernel(ir_inner, monkeypatch):
         out[edge] = (host(Zf), rrf, it, host(Z))
     zf0, rr0, it0, z0 = out["0"]
     zf2, rr2, it2, z2 = out["2"]
-    assert np.linalg.norm(zf2 - zf0) <= 1e-12 * np.linalg.norm(zf0)
-    np.testing.assert_allclose(rr2, rr0, rtol=1e-6)
+    # The two paths run the complex64 cycles in different kernels, and the
+    # compiler is free to fuse a product into a multiply-add in one and not in
+    # the other: they agree to complex64 rounding, not bit for bit.  A
+    # difference of a few u32 (6e-8) relative in the first refinement step's
+    # correction is damped by the second step's cycles (rate ~0.1 each), and
+    # the second step's own correction is ~1e-2 of the solution: 1e-7 bounds
+    # both with room.
+    assert np.linalg.norm(zf2 - zf0) <= 1e-7 * np.linalg.norm(zf0)
+    # (the residual weights that rounding-level difference by the stencil,
+    # ~8/h^2 against the smooth iterate: a relative 1e-5 of a 5e-6 residual)
+    np.testing.assert_allclose(rr2, rr0, rtol=1e-3)
     np.testing.assert_array_equal(it2, it0)
     assert np.linalg.norm(z2 - z0) <= 1e-9 * np.linalg.norm(z0)
