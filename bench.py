@@ -80,8 +80,9 @@ def cpu_baseline(b, lam, h, tol, count):
 def precision_leg(args, torch):
     """The precision workload: 32 alpha-circulant shifts (alpha = 0.01,
     tau = 1/32) on 2047^2, the ParaDIAG step to 1e-10 with complex64 V-cycles
-    inside FP64 refinement against FP64 V-cycles (both uninstrumented, cycles
-    replayed as graphs, autotuned; refinement with 2 inner cycles a step)."""
+    inside FP64 refinement, and FP64 V-cycles with a complex64 coarse-grid
+    correction, against FP64 V-cycles (all uninstrumented, cycles replayed as
+    graphs, autotuned; refinement with 2 inner cycles a step)."""
     from paper_2203_11154_amd import Grid, VankaMG, inputs
     n, S, tol = 2047, 32, args.tol
     lam = inputs.alpha_circulant_shifts(S, 0.01)
@@ -92,7 +93,8 @@ def precision_leg(args, torch):
     Vd, Vinvd = torch.from_numpy(V).cuda(), torch.from_numpy(Vinv).cuda()
     Ud = torch.empty_like(Fd)
     res = {"workload": "precision_2047: 32 alpha-circulant shifts on 2047x2047, ParaDIAG step to 1e-10"}
-    for name, kw in (("fp64", {}), ("fp32_ir", {"precision": "c64_ir", "ir_inner": 2})):
+    for name, kw in (("fp64", {}), ("fp32_ir", {"precision": "c64_ir", "ir_inner": 2}),
+                     ("fp32_coarse", {"precision": "c128_c64"})):
         s = VankaMG([Grid(n, num_systems=S)], lam, **kw)
         if not args.no_autotune:
             s.autotune()
@@ -105,6 +107,7 @@ def precision_leg(args, torch):
                      "converged": st == 0 and bool(np.all(rr <= tol))}
         del s
     res["speedup_vs_fp64"] = round(res["fp64"]["ms_per_step"] / res["fp32_ir"]["ms_per_step"], 3)
+    res["fp32_coarse_speedup_vs_fp64"] = round(res["fp64"]["ms_per_step"] / res["fp32_coarse"]["ms_per_step"], 3)
     del Fd, Ud
     torch.cuda.empty_cache()
     return res
@@ -348,6 +351,27 @@ def main():
                           "refinement_steps": {"min": int(it_ir.min()), "max": int(it_ir.max())},
                           "max_relres": float(rr_ir.max()), "converged": ok, "dtype": "c64 cycles + c128 refinement"}
         del ir
+        # FP64 V-cycles whose coarse-grid correction runs in complex64: the
+        # finest level, the stopping test and the result in FP64
+        mx = VankaMG([Grid(n, num_systems=S)], lam, precision="c128_c64")
+        if not args.no_autotune:
+            mx.autotune()
+        for _ in range(args.warmup):
+            mx.paradiag_apply(Vd, Vinvd, Fd, tol=tol, out=Ud)
+        mx.set_timing(True, reset=True)
+        dtm, st_m = run_steps(mx, Vd, Vinvd, Fd, Ud, args.steps, tol, torch)
+        mx.set_timing(False, reset=False)
+        it_m, rr_m = mx.last_stats()
+        dtmg, _ = run_steps(mx, Vd, Vinvd, Fd, Ud, args.steps, tol, torch)
+        out["fp32_coarse"] = {"value": round(S * args.steps / dtm, 2), "unit": "systems/s",
+                              "ms_per_step": round(1e3 * dtm / args.steps, 3),
+                              "speedup_vs_fp64": round(ms_per_step / (1e3 * dtm / args.steps), 3),
+                              "uninstrumented_ms_per_step": round(1e3 * dtmg / args.steps, 3),
+                              "uninstrumented_speedup_vs_fp64": round(dtg / dtmg, 3),
+                              "cycles": {"min": int(it_m.min()), "max": int(it_m.max())},
+                              "max_relres": float(rr_m.max()), "converged": st_m == 0 and bool(np.all(rr_m <= tol)),
+                              "dtype": "c128 finest level and stopping test, c64 coarse-grid correction"}
+        del mx
 
     if not args.no_ir:
         out["fp32_ir_2047"] = precision_leg(args, torch)

@@ -89,7 +89,13 @@ typedef struct {
     int32_t max_iter;     /* cycle (or refinement step) limit; default 100    */
     int32_t precision;    /* 0 = complex128 cycles (default);
                              1 = complex64 cycles inside FP64 iterative
-                                 refinement (residual and update in FP64)    */
+                                 refinement (residual and update in FP64);
+                             2 = FP64 V-cycles whose coarse-grid correction
+                                 runs in complex64 (finest level, stopping
+                                 test and result in FP64; gamma must be 1 and
+                                 every grid's finest level large enough for
+                                 the streaming kernels, else setup returns
+                                 VMG_INVALID_ARG)                            */
     int32_t smoother;     /* 0 = additive Vanka (default); 1 = damped Jacobi,
                              the comparison smoother of Sec. 3 (omega 4/5)   */
     int32_t ir_inner;     /* complex64 cycles per refinement step; default 3 */

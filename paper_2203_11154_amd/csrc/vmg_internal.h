@@ -205,9 +205,14 @@ int launch_transform(int n, int64_t m, const double2* M, int trans_conj, const d
 //         system whatever its active flag, reads x or xalt by the parity of
 //         iters[sys] (zero result for 0) and writes the dense rows of zd.
 // The work of a level is split evenly over the device's resident waves, with
-// at least rmin rows per wave.
-template <typename T> void launch_down(SegTable<T> tab, const int* nsys, int nu, int rmin, hipStream_t st);
-template <typename T> void launch_up(SegTable<T> tab, const int* nsys, int nu, bool norm, int rmin, hipStream_t st);
+// at least rmin rows per wave.  c32 (T = double only): the coarse level (c,
+// and cb of the edge kernel) holds complex64 values; the pointers in the
+// segment are then float2 data, and the coarse views those of the complex64
+// level.
+template <typename T>
+void launch_down(SegTable<T> tab, const int* nsys, int nu, int rmin, hipStream_t st, bool c32 = false);
+template <typename T>
+void launch_up(SegTable<T> tab, const int* nsys, int nu, bool norm, int rmin, hipStream_t st, bool c32 = false);
 template <typename T> int stream_tiles(int nx, int ny, int nsys, int nu, int rmin);
 int stream_tiles_max(int nx, int ny, int nu);  // over every rmin and kernel
 // Cycle-edge kernel (FP64 finest level, nu1, nu2 in {1, 2}): correction +
@@ -216,7 +221,8 @@ int stream_tiles_max(int nx, int ny, int nu);  // over every rmin and kernel
 // and leaves them untouched (the finishing pass of launch_up rebuilds the
 // last cycle's iterate from them).
 bool edge_supported(int nu1, int nu2);
-template <typename T> void launch_edge(SegTable<T> tab, const int* nsys, int nu1, int nu2, int rmin, hipStream_t st);
+template <typename T>
+void launch_edge(SegTable<T> tab, const int* nsys, int nu1, int nu2, int rmin, hipStream_t st, bool c32 = false);
 template <typename T> int edge_tiles(int nx, int ny, int nsys, int nu1, int nu2, int rmin);
 void stream_prepare();  // device occupancy of the streaming kernels (call outside stream capture)
 template <typename T> void launch_fill_zero(cplx<T>* x, LevelView lv, int nsys, hipStream_t st);

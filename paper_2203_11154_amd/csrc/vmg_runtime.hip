@@ -66,8 +66,8 @@ struct Level {
 struct Group {
     int nx = 0, ny = 0, S = 0, sys0 = 0, L = 0;
     double h = 0;
-    std::vector<Level> lv64;   // precision 0: all levels; precision 1: level 0 (x[0], b)
-    std::vector<Level> lv32;   // precision 1: all levels
+    std::vector<Level> lv64;   // precision 0: all levels; precisions 1 and 2: level 0
+    std::vector<Level> lv32;   // precision 1: all levels; precision 2: levels 1.. (level 0 holds only its view)
     Coef<double>* coef64[2] = {nullptr, nullptr};  // [conj][level * S + s]
     Coef<float>* coef32[2] = {nullptr, nullptr};
     double2* cinv64[2] = {nullptr, nullptr};       // [conj][s * nc * nc] transposed
@@ -351,19 +351,25 @@ struct CycleCtx {
     bool norm_fused = false;    // set when the last cycle produced those partials
 };
 
+// Precision of the cycles: 0 complex128 throughout; 1 complex64 cycles inside
+// FP64 refinement; 2 complex128 on the finest level and complex64 on the
+// coarser ones (the coarse-grid correction computed in complex64).
+bool level_f64(const vmg_opts& o, int l) { return o.precision == 0 || (o.precision == 2 && l == 0); }
+bool fine_f64(const vmg_opts& o) { return o.precision != 1; }  // the finest level's cycles run in FP64
+
 // Levels at least this wide run the fused streaming kernels.
 constexpr int STREAM_MIN_NX = 96;
 
 // The streaming kernels address each plane through a buffer range checked
 // in 32 bits (out-of-range offsets read zero); planes of 1 GiB and more stay
 // on the tiled kernels.
-bool stream_fits(const vmg_opts& o, const LevelView& v) {
-    const int64_t es = o.precision == 0 ? (int64_t)sizeof(double2) : (int64_t)sizeof(float2);
+bool stream_fits(const vmg_opts& o, const LevelView& v, int l) {
+    const int64_t es = level_f64(o, l) ? (int64_t)sizeof(double2) : (int64_t)sizeof(float2);
     return v.plane * es < ((int64_t)1 << 30);
 }
 
-bool use_stream(const vmg_opts& o, const LevelView& v) {
-    return v.nx >= STREAM_MIN_NX && o.nu1 <= 2 && o.nu2 <= 2 && stream_fits(o, v);
+bool use_stream(const vmg_opts& o, const LevelView& v, int l) {
+    return v.nx >= STREAM_MIN_NX && o.nu1 <= 2 && o.nu2 <= 2 && stream_fits(o, v, l);
 }
 
 // Rows per block: tall blocks amortise the pipeline's start-up rows, short
@@ -374,15 +380,15 @@ int stream_rows_for(const vmg_handle* H, const LevelView& v) {
 }
 
 const LevelView& cycle_view(const vmg_handle* H, const Group& g, int l) {
-    return H->opts.precision == 0 ? g.lv64[l].v : g.lv32[l].v;
+    return level_f64(H->opts, l) ? g.lv64[l].v : g.lv32[l].v;
 }
 
 // Kernel schedule of grid g at level l: the autotuned choice if there is
 // one, else the size heuristic above.
 bool sched_stream(const vmg_handle* H, const Group& g, int l) {
-    if (H->opts.nu1 > 2 || H->opts.nu2 > 2 || !stream_fits(H->opts, cycle_view(H, g, l))) return false;
+    if (H->opts.nu1 > 2 || H->opts.nu2 > 2 || !stream_fits(H->opts, cycle_view(H, g, l), l)) return false;
     if ((int)g.sched.size() > l && g.sched[l] >= 0) return g.sched[l] > 0;
-    return use_stream(H->opts, cycle_view(H, g, l));
+    return use_stream(H->opts, cycle_view(H, g, l), l);
 }
 // The cycle-edge kernel (finest level, FP64 V-cycles) may run for grid g /
 // runs with the current kernel schedule.
@@ -417,7 +423,7 @@ LevelSeg<T> make_seg(vmg_handle* H, Group& g, int conj, int l, const cplx<T>* x,
     S.xo = xo;
     S.c = c;
     S.lf = L[l].v;
-    S.lc = (l + 1 < g.L) ? L[l + 1].v : L[l].v;
+    S.lc = (l + 1 < (int)L.size()) ? L[l + 1].v : L[l].v;  // (precision 2, level 0: set by the caller)
     S.s = (T)(1.0 / (L[l].h * L[l].h));
     S.coef = coef_of<T>(g, conj, l);
     S.active = H->active + g.sys0;
@@ -596,10 +602,12 @@ template <> void launch_edge_t<float>(SegTable<float> tab, const int* nsys, int 
 //               last iterate is rebuilt by the finishing pass)
 //   partials[g] fused finest-level norm target of grid g (or NULL)
 //   fused[g]    set when grid g's norm partials were produced
+//   lmin        first level run (1: the coarse part of a precision-2 cycle,
+//               whose finest level the caller runs in FP64)
 template <typename T>
 void enqueue_batched_vcycle(vmg_handle* H, int conj, hipStream_t st, bool first, bool last,
                             std::vector<std::vector<int>>& cur, const std::vector<double*>& partials,
-                            std::vector<char>& fused) {
+                            std::vector<char>& fused, int lmin = 0) {
     const vmg_opts& o = H->opts;
     const double E = sizeof(cplx<T>);
     const int ng = (int)H->groups.size();
@@ -613,7 +621,8 @@ void enqueue_batched_vcycle(vmg_handle* H, int conj, hipStream_t st, bool first,
     for (int d = dmax; d >= 1; --d) {
         std::vector<int> sg, lg;  // streamed / LDS-path grids of this phase
         for (int gi = 0; gi < ng; ++gi) {
-            if (H->groups[gi].L - 1 < d || level_of(gi, d) >= tail_start(H->groups[gi])) continue;
+            if (H->groups[gi].L - 1 < d || level_of(gi, d) >= tail_start(H->groups[gi]) || level_of(gi, d) < lmin)
+                continue;
             const int l = level_of(gi, d);
             // with the cycle-edge kernel the finest level's pre-smoothing and
             // restriction were done by the previous cycle (all but the first)
@@ -734,7 +743,8 @@ void enqueue_batched_vcycle(vmg_handle* H, int conj, hipStream_t st, bool first,
     for (int d = 1; d <= dmax; ++d) {
         std::vector<int> sg, lg, eg;
         for (int gi = 0; gi < ng; ++gi) {
-            if (H->groups[gi].L - 1 < d || level_of(gi, d) >= tail_start(H->groups[gi])) continue;
+            if (H->groups[gi].L - 1 < d || level_of(gi, d) >= tail_start(H->groups[gi]) || level_of(gi, d) < lmin)
+                continue;
             const int l = level_of(gi, d);
             if (l == 0 && !last && use_edge(H, H->groups[gi])) {
                 eg.push_back(gi);
@@ -841,6 +851,110 @@ void enqueue_batched_vcycle(vmg_handle* H, int conj, hipStream_t st, bool first,
     }
 }
 
+// One V-cycle of every grid in precision 2: the finest level in FP64, the
+// coarse-grid correction in complex64.  The FP64 pre-smoothing and
+// restriction round the coarse right-hand side to complex64, the coarse
+// levels run the complex64 batched cycle from level 1, and the FP64
+// correction reads the complex64 coarse correction (widened exactly).  The
+// stopping test stays on the FP64 residual, so the solve reaches FP64
+// accuracy; complex64 rounding only perturbs each cycle's coarse correction.
+// Every grid's finest level is streamed (checked at setup).
+//   cur[g][0] the FP64 finest iterate's buffer, cur[g][l >= 1] complex64 levels
+void enqueue_mixed_vcycle(vmg_handle* H, int conj, hipStream_t st, bool first, std::vector<std::vector<int>>& cur,
+                          const std::vector<double*>& partials, std::vector<char>& fused) {
+    const vmg_opts& o = H->opts;
+    const int ng = (int)H->groups.size();
+    for (int gi = 0; gi < ng; ++gi) fused[gi] = 0;
+    // complex64 level-1 buffer, passed through a segment's FP64-typed pointer
+    auto c32 = [](DevBuf& b) { return reinterpret_cast<double2*>(P<float>(b)); };
+    auto per_node = [](Group& g, double by) { return by * nodes(g.lv64[0].v) * g.nact; };
+    // ---- finest level: pre-smoothing and restriction (with the cycle-edge
+    // kernel only in the first cycle)
+    std::vector<int> sg;
+    for (int gi = 0; gi < ng; ++gi)
+        if (first || !use_edge(H, H->groups[gi])) sg.push_back(gi);
+    while (!sg.empty()) {
+        const int ty = sched_rows(H, H->groups[sg[0]], 0);
+        SegBatch<double> bt;
+        std::vector<int> rest, done;
+        for (int gi : sg) {
+            Group& g = H->groups[gi];
+            if (sched_rows(H, g, 0) != ty || bt.full()) {
+                rest.push_back(gi);
+                continue;
+            }
+            Level& l0 = g.lv64[0];
+            LevelSeg<double> S = make_seg<double>(H, g, conj, 0, P<double>(l0.x[cur[gi][0]]), P<double>(l0.b),
+                                                  P<double>(l0.x[1 - cur[gi][0]]), c32(g.lv32[1].b), first ? 1 : 0,
+                                                  nullptr);
+            S.lc = g.lv32[1].v;
+            bt.add(S, g.S, per_node(g, 16.0 * ((first ? 0 : 1) + 1 + (o.nu1 > 0 ? 1 : 0)) + 2.0));
+            done.push_back(gi);
+        }
+        {
+            Timer t(H, st, VMG_K_DOWN, bt.bytes, 0);
+            launch_down<double>(bt.tab, bt.nsys, o.nu1, ty, st, true);
+        }
+        for (int gi : done) {
+            Group& g = H->groups[gi];
+            if (o.nu1 > 0) cur[gi][0] ^= 1;
+            else if (first) launch_fill_zero<double>(P<double>(g.lv64[0].x[cur[gi][0]]), g.lv64[0].v, g.S, st);
+        }
+        sg.swap(rest);
+    }
+    // ---- coarse levels: the complex64 cycle from level 1
+    {
+        std::vector<double*> none(ng, nullptr);
+        std::vector<char> unused(ng, 0);
+        enqueue_batched_vcycle<float>(H, conj, st, first, false, cur, none, unused, 1);
+    }
+    // ---- finest level: correction, post-smoothing and the norm partials;
+    // with the cycle-edge kernel also the next cycle's pre-smoothing and
+    // restriction
+    std::vector<int> eg, ug;
+    for (int gi = 0; gi < ng; ++gi) (use_edge(H, H->groups[gi]) ? eg : ug).push_back(gi);
+    for (int pass = 0; pass < 2; ++pass) {
+        std::vector<int>& q = pass == 0 ? eg : ug;
+        while (!q.empty()) {
+            const int ty = sched_rows(H, H->groups[q[0]], 0);
+            SegBatch<double> bt;
+            std::vector<int> rest, done;
+            bool any_norm = false;
+            for (int gi : q) {
+                Group& g = H->groups[gi];
+                if (sched_rows(H, g, 0) != ty || bt.full()) {
+                    rest.push_back(gi);
+                    continue;
+                }
+                Level& l0 = g.lv64[0];
+                LevelSeg<double> S = make_seg<double>(H, g, conj, 0, P<double>(l0.x[cur[gi][0]]), P<double>(l0.b),
+                                                      P<double>(l0.x[1 - cur[gi][0]]), c32(g.lv32[1].x[cur[gi][1]]),
+                                                      0, partials[gi]);
+                S.lc = g.lv32[1].v;
+                any_norm |= partials[gi] != nullptr;
+                if (pass == 0) {
+                    S.cb = c32(g.lv32[1].b);
+                    g.edge_c = cur[gi][1];  // the same every cycle (coarse levels restart from buffer 0)
+                }
+                bt.add(S, g.S, per_node(g, pass == 0 ? 52.0 : 50.0));
+                done.push_back(gi);
+            }
+            if (pass == 0) {
+                Timer t(H, st, VMG_K_EDGE, bt.bytes, 0);
+                launch_edge<double>(bt.tab, bt.nsys, o.nu1, o.nu2, ty, st, true);
+            } else {
+                Timer t(H, st, VMG_K_UP, bt.bytes, 0);
+                launch_up<double>(bt.tab, bt.nsys, o.nu2, any_norm, ty, st, true);
+            }
+            for (int gi : done) {
+                cur[gi][0] ^= 1;
+                if (partials[gi]) fused[gi] = 1;
+            }
+            q.swap(rest);
+        }
+    }
+}
+
 int check_hip() {
     hipError_t e = hipGetLastError();
     return e == hipSuccess ? VMG_OK : VMG_HIP_ERROR;
@@ -853,8 +967,6 @@ bool valid_grid_level(int n) { return n >= 3 && (n % 2) == 1; }
 // finest iterate in the same buffer if this is even).
 int level0_flips(const vmg_handle* H, const Group& g) {
     const vmg_opts& o = H->opts;
-    const LevelView& v = (o.precision == 0 ? g.lv64[0] : g.lv32[0]).v;
-    (void)v;
     if (g.tail_lt == 0) return 0;  // the whole cycle runs in place in one tail launch
     if (g.L > 1 && sched_stream(H, g, 0)) return (o.nu1 > 0 ? 1 : 0) + 1;
     return o.nu1 + o.nu2;
@@ -864,12 +976,12 @@ int level0_flips(const vmg_handle* H, const Group& g) {
 // the cycle-edge kernel the pre-smoothed iterate alternates once per cycle,
 // after the first cycle's separate pre-smoothing pass.
 int level0_parity(const vmg_handle* H, const Group& g, int64_t cycle) {
-    if (H->opts.precision == 0 && use_edge(H, g)) return (int)((cycle + (cycle > 0 ? 1 : 0)) & 1);
+    if (fine_f64(H->opts) && use_edge(H, g)) return (int)((cycle + (cycle > 0 ? 1 : 0)) & 1);
     return (int)((cycle * level0_flips(H, g)) & 1);
 }
 
 int norm_tiles(const vmg_handle* H, const Group& g) {
-    if (H->opts.precision == 0 && use_edge(H, g))
+    if (fine_f64(H->opts) && use_edge(H, g))
         return edge_tiles<double>(g.lv64[0].v.nx, g.lv64[0].v.ny, g.S, H->opts.nu1, H->opts.nu2, sched_rows(H, g, 0));
     return stream_tiles<double>(g.lv64[0].v.nx, g.lv64[0].v.ny, g.S, H->opts.nu2, sched_rows(H, g, 0));
 }
@@ -885,7 +997,7 @@ int enqueue_norm_check(vmg_handle* H, hipStream_t st, int mode, double tol, int 
         int ntiles = g.ntiles0;
         if (fused[gi]) {
             // (refinement steps always end with the fused update + residual)
-            ntiles = H->opts.precision == 0 ? norm_tiles(H, g) : g.ntiles0;
+            ntiles = fine_f64(H->opts) ? norm_tiles(H, g) : g.ntiles0;
         } else {
             Level& l0 = g.lv64[0];
             Timer t(H, st, VMG_K_NORM, 2.0 * 16.0 * nodes(l0.v) * g.nact);
@@ -977,7 +1089,19 @@ int enqueue_cycle_all(vmg_handle* H, int conj, hipStream_t st, int64_t cycle, do
     const size_t ng = H->groups.size();
     std::vector<int> cur0(ng, 0);
     std::vector<char> fused(ng, 0);
-    if (o.precision == 0) {
+    if (o.precision == 2) {
+        // (V-cycles only, checked at setup)
+        std::vector<std::vector<int>> cur(ng);
+        std::vector<double*> parts(ng);
+        for (size_t gi = 0; gi < ng; ++gi) {
+            Group& g = H->groups[gi];
+            cur[gi].assign(g.L, 0);
+            cur[gi][0] = level0_parity(H, g, cycle);
+            parts[gi] = g.partial;
+        }
+        enqueue_mixed_vcycle(H, conj, st, first, cur, parts, fused);
+        for (size_t gi = 0; gi < ng; ++gi) cur0[gi] = cur[gi][0];
+    } else if (o.precision == 0) {
         if (o.gamma == 1) {
             std::vector<std::vector<int>> cur(ng);
             std::vector<double*> parts(ng);
@@ -1107,7 +1231,7 @@ int solve_impl(vmg_handle* H, const double* B, double* Z, double tol, int conj, 
         if (B) {
             Timer t(H, st, VMG_K_PACK, 32.0 * nodes(l0.v) * g.S);
             launch_pack<double>(reinterpret_cast<const double2*>(B) + off, P<double>(l0.b), l0.v, g.S, st,
-                                o.precision == 0 ? g.partial : nullptr);
+                                fine_f64(o) ? g.partial : nullptr);
         }
         off += (int64_t)g.nx * g.ny * g.S;
     }
@@ -1116,7 +1240,7 @@ int solve_impl(vmg_handle* H, const double* B, double* Z, double tol, int conj, 
         Level& l0 = g.lv64[0];
         const int* act = H->active + g.sys0;
         int ntiles = g.ntiles0;
-        if (o.precision == 0) {
+        if (fine_f64(o)) {
             if (bnorm_tiles > 0) {
                 ntiles = bnorm_tiles;
             } else if (!B) {
@@ -1162,22 +1286,26 @@ int solve_impl(vmg_handle* H, const double* B, double* Z, double tol, int conj, 
     off = 0;
     for (auto& g : H->groups) {
         Level& l0 = g.lv64[0];
-        if (o.precision == 0 && use_edge(H, g)) {
+        if (fine_f64(o) && use_edge(H, g)) {
             // the last cycle's correction and post-smoothing, rebuilt from the
             // inputs its cycle-edge pass read (frozen since the system
             // stopped), written straight into Z
-            Timer t(H, st, VMG_K_UP, 52.0 * nodes(l0.v) * g.S, 0);
-            LevelSeg<double> S = make_seg<double>(H, g, conj, 0, P<double>(l0.x[0]), P<double>(l0.b), nullptr,
-                                                  P<double>(g.lv64[1].x[g.edge_c]), 0, nullptr);
+            const bool c32 = o.precision == 2;
+            Timer t(H, st, VMG_K_UP, (c32 ? 50.0 : 52.0) * nodes(l0.v) * g.S, 0);
+            double2* corr = c32 ? reinterpret_cast<double2*>(P<float>(g.lv32[1].x[g.edge_c]))
+                                : P<double>(g.lv64[1].x[g.edge_c]);
+            LevelSeg<double> S = make_seg<double>(H, g, conj, 0, P<double>(l0.x[0]), P<double>(l0.b), nullptr, corr,
+                                                  0, nullptr);
+            if (c32) S.lc = g.lv32[1].v;
             S.xalt = P<double>(l0.x[1]);
             S.iters = H->iters + g.sys0;
             S.zd = reinterpret_cast<double2*>(Z) + off;
             const int one = g.S;
-            launch_up<double>(one_seg(S), &one, o.nu2, false, sched_rows(H, g, 0), st);
+            launch_up<double>(one_seg(S), &one, o.nu2, false, sched_rows(H, g, 0), st, c32);
         } else {
             Timer t(H, st, VMG_K_PACK, 32.0 * nodes(l0.v) * g.S);
             // (refinement: after k steps the FP64 iterate is in buffer k mod 2)
-            const int flips = o.precision == 0 ? level0_flips(H, g) : 1;
+            const int flips = fine_f64(o) ? level0_flips(H, g) : 1;
             launch_unpack<double>(P<double>(l0.x[0]), P<double>(l0.x[1]), reinterpret_cast<double2*>(Z) + off, l0.v,
                                   g.S, H->iters + g.sys0, flips, st);
         }
@@ -1390,7 +1518,8 @@ int vanka_mg_setup(const vmg_grid* grids, int32_t n_grids, const double* shifts,
     vanka_mg_default_opts(&o);
     if (opts) o = *opts;
     if (!(o.omega > 0.0) || o.nu1 < 0 || o.nu2 < 0 || o.nu1 + o.nu2 < 1 || o.gamma < 1 || o.gamma > 2 ||
-        o.max_iter < 1 || o.precision < 0 || o.precision > 1 || o.smoother < 0 || o.smoother > 1 ||
+        o.max_iter < 1 || o.precision < 0 || o.precision > 2 || (o.precision == 2 && o.gamma != 1) ||
+        o.smoother < 0 || o.smoother > 1 ||
         o.ir_inner < 1 || o.check_every < 1 || o.graphs < 0 || o.graphs > 1)
         return VMG_INVALID_ARG;
     (void)hip_stream;
@@ -1453,7 +1582,7 @@ int vanka_mg_setup(const vmg_grid* grids, int32_t n_grids, const double* shifts,
             GG.lv64[l].v = make_view<double>(nxs[l], nys[l]);
             GG.lv64[l].h = gr.h * std::ldexp(1.0, l);
         }
-        if (o.precision == 1) {
+        if (o.precision >= 1) {
             GG.lv32.resize(GG.L);
             for (int l = 0; l < GG.L; ++l) {
                 GG.lv32[l].v = make_view<float>(nxs[l], nys[l]);
@@ -1503,7 +1632,8 @@ int vanka_mg_setup(const vmg_grid* grids, int32_t n_grids, const double* shifts,
             VMG_TRY(alloc_planes<double>(H, L.x[1], L.v, G.S));  // (refinement: the FP64 iterate alternates)
             VMG_TRY(alloc_planes<double>(H, L.b, L.v, G.S));
         }
-        for (size_t l = 0; l < G.lv32.size(); ++l) {
+        // (precision 2: the complex64 hierarchy starts at level 1)
+        for (size_t l = o.precision == 2 ? 1 : 0; l < G.lv32.size(); ++l) {
             Level& L = G.lv32[l];
             VMG_TRY(alloc_planes<float>(H, L.x[0], L.v, G.S));
             VMG_TRY(alloc_planes<float>(H, L.x[1], L.v, G.S));
@@ -1518,6 +1648,10 @@ int vanka_mg_setup(const vmg_grid* grids, int32_t n_grids, const double* shifts,
         VMG_TRY(upload_coefficients(H, G, nullptr));
     }
     VMG_TRY(H->opts.precision == 0 ? build_tails<double>(H) : build_tails<float>(H));
+    // precision 2 runs the finest level with the FP64 streaming kernels only
+    if (o.precision == 2)
+        for (auto& G : H->groups)
+            if (G.tail_lt == 0 || !sched_stream(H, G, 0)) VMG_TRY(VMG_INVALID_ARG);
 #undef VMG_TRY
     *out = H;
     return VMG_OK;
@@ -1714,7 +1848,7 @@ int paradiag_core(vmg_handle* H, const double* V, const double* Vinv, const doub
     int btiles = 0;
     {
         Timer t(H, st, VMG_K_TRANSFORM, 32.0 * (double)n * m);
-        double* np = H->opts.precision == 0 ? g.partial : nullptr;
+        double* np = fine_f64(H->opts) ? g.partial : nullptr;
         if (circ)
             btiles = launch_circulant(n, m, alpha, 0, conj, reinterpret_cast<const double2*>(F), dense_rows(m),
                                       P<double>(l0.b), lb, st, 0, np, g.partial_cap);
@@ -2051,7 +2185,8 @@ std::string tune_key(const vmg_handle* H, const Group& g, int l) {
     for (auto& ch : arch)
         if (ch == ' ') ch = '_';
     std::ostringstream k;
-    k << arch << " " << (H->opts.precision == 0 ? "c128" : "c64") << " " << g.nx << " " << g.ny << " " << g.S << " "
+    static const char* prec[3] = {"c128", "c64", "c128c64"};
+    k << arch << " " << prec[H->opts.precision] << " " << g.nx << " " << g.ny << " " << g.S << " "
       << H->opts.nu1 << " " << H->opts.nu2 << " " << (l < 0 ? std::string("edge") : std::to_string(l));
     return k.str();
 }
@@ -2075,7 +2210,9 @@ extern "C" int vanka_mg_autotune(vmg_handle* H, const char* cache_path, void* hi
     std::vector<std::string> fresh;
     for (auto& g : H->groups) {
         g.sched.assign(g.L, -1);
-        for (int l = 0; l + 1 < g.L; ++l) {
+        // (precision 2: the finest level keeps the streaming kernels and
+        // their row heuristic)
+        for (int l = H->opts.precision == 2 ? 1 : 0; l + 1 < g.L; ++l) {
             const std::string key = tune_key(H, g, l);
             int found = -2;
             for (auto& e : cache)
@@ -2086,7 +2223,7 @@ extern "C" int vanka_mg_autotune(vmg_handle* H, const char* cache_path, void* hi
             }
             const LevelView& v = cycle_view(H, g, l);
             std::vector<int> cands{0};
-            if (H->opts.nu1 <= 2 && H->opts.nu2 <= 2 && v.nx >= 32 && stream_fits(H->opts, v))
+            if (H->opts.nu1 <= 2 && H->opts.nu2 <= 2 && v.nx >= 32 && stream_fits(H->opts, v, l))
                 for (int r : {32, 64, 128})
                     if (r <= 2 * v.ny) cands.push_back(r);
             int best = 0;
@@ -2112,7 +2249,8 @@ extern "C" int vanka_mg_autotune(vmg_handle* H, const char* cache_path, void* hi
         // the cycle-edge kernel against the finest level's separate streaming
         // launches (small grids have too few rows per wave for its halo)
         g.edge = -1;
-        if (H->edge_mode == 1 && edge_possible(H, g) && g.tail_lt != 0 && sched_stream(H, g, 0)) {
+        if (H->edge_mode == 1 && H->opts.precision != 2 && edge_possible(H, g) && g.tail_lt != 0 &&
+            sched_stream(H, g, 0)) {
             const std::string key = tune_key(H, g, -1);
             int found = -1;
             for (auto& e : cache)

@@ -29,6 +29,7 @@
 #include "vmg_internal.h"
 
 #include <algorithm>
+#include <type_traits>
 #include <map>
 #include <mutex>
 
@@ -56,6 +57,18 @@ template <typename C> __device__ __forceinline__ C fma2(C acc, C a, C b) {  // a
     r.x = acc.x + a.x * b.x - a.y * b.y;
     r.y = acc.y + a.x * b.y + a.y * b.x;
     return r;
+}
+// complex value in another precision (round to nearest; the identity when
+// the types agree)
+template <typename D, typename S> __device__ __forceinline__ D cvt(S v) {
+    if constexpr (std::is_same<D, S>::value) {
+        return v;
+    } else {
+        D r;
+        r.x = v.x;
+        r.y = v.y;
+        return r;
+    }
 }
 // Value of the left (lane - 1) and right (lane + 1) neighbour; the wave's
 // edge lanes receive values of no meaning and are never owned.  With
@@ -244,9 +257,12 @@ __device__ __forceinline__ void pin(float& v) { asm volatile("" : "+v"(v)); }
 __device__ __forceinline__ void pin(double2& v) { asm volatile("" : "+v"(v.x), "+v"(v.y)); }
 __device__ __forceinline__ void pin(float2& v) { asm volatile("" : "+v"(v.x), "+v"(v.y)); }
 
-template <typename T, int NS>
+// TC: precision of the coarse level (the restricted residual is rounded to
+// it when the coarse levels run in complex64 under an FP64 finest level).
+template <typename T, int NS, typename TC = T>
 struct DownPipe {
     using C = cplx<T>;
+    using CC = cplx<TC>;
     static constexpr int HALO = 2 * NS + 2;
     static constexpr int OWN = 64 - 2 * HALO;
     C X[NS + 1][3], R[NS + 1][3];
@@ -312,7 +328,7 @@ struct DownPipe {
         // full weighting around fine row j - 2NS - 2 (even rows carry coarse nodes)
         if constexpr ((P & 1) == 0) {
             const int frow = j - 2 * NS - 2;
-            const C v = full_weight_row<T>(R[NS][n2], R[NS][n1], R[NS][n0]);
+            const CC v = cvt<CC>(full_weight_row<T>(R[NS][n2], R[NS][n1], R[NS][n0]));
             const int K = frow >> 1;
             if constexpr (EDGE)
                 bstore(bcs, of + (frow >= k0 && frow <= k1 && frow >= 2 && K <= lc.ny ? cph(K) * rc : OOB), 0, v);
@@ -361,11 +377,11 @@ template <typename Pipe> __device__ __forceinline__ void set_rows(Pipe& p, bool 
 
 // One wave's share of the work: rows k0..k1 of strip `strip` of system
 // `sys` of segment S (the pipeline adds its halo rows itself).
-template <typename T, int NS>
+template <typename T, int NS, typename TC>
 __device__ __forceinline__ void down_piece(const LevelSeg<T>& S, int sys, int strip, int k0, int k1, bool rev,
                                            int lane) {
     using C = cplx<T>;
-    using Pipe = DownPipe<T, NS>;
+    using Pipe = DownPipe<T, NS, TC>;
     constexpr int HALO = Pipe::HALO, OWN = Pipe::OWN;
     Pipe p;
     p.lf = S.lf;
@@ -379,15 +395,16 @@ __device__ __forceinline__ void down_piece(const LevelSeg<T>& S, int sys, int st
     p.ox = col_ld ? i * es : OOB;
     p.ob = p.col_in ? i * es : OOB;
     p.oo = own ? i * es : OOB;
-    p.of = (own && !(i & 1) && (i >> 1) <= p.lc.nx) ? (i >> 1) * es : OOB;
+    const unsigned ec = sizeof(cplx<TC>);
+    p.of = (own && !(i & 1) && (i >> 1) <= p.lc.nx) ? (i >> 1) * ec : OOB;
     p.rx = p.lf.pitch * es;
-    p.rc = p.lc.pitch * es;
+    p.rc = p.lc.pitch * ec;
     set_rows(p, rev, k0, k1);
     const int64_t base = (int64_t)sys * p.lf.plane;
     p.xs = plane_rsrc(S.x + base, p.lf.plane);
     p.bs = plane_rsrc(S.b + base, p.lf.plane);
     p.xos = plane_rsrc(S.xo + base, p.lf.plane);
-    p.bcs = plane_rsrc(S.c + (int64_t)sys * p.lc.plane, p.lc.plane);
+    p.bcs = plane_rsrc(reinterpret_cast<const cplx<TC>*>(S.c) + (int64_t)sys * p.lc.plane, p.lc.plane);
     p.cf = S.coef[sys];
     p.dl = p.col_in ? p.cf.d : z2<C>();
     p.sl = p.col_in ? S.s : (T)0;
@@ -447,7 +464,7 @@ template <typename T> __device__ __forceinline__ Piece piece_of(const LevelSeg<T
 }
 
 // ---------------------------------------------------------------------------
-template <typename T, int NS>
+template <typename T, int NS, typename TC>
 __global__ __launch_bounds__(NT) VMG_STREAM_OCC void k_down(SegTable<T> tab) {
     // the wave index is uniform over the wave; say so, so that everything
     // derived from it (segment, buffer resources, row bounds) lives in SGPRs
@@ -458,10 +475,10 @@ __global__ __launch_bounds__(NT) VMG_STREAM_OCC void k_down(SegTable<T> tab) {
     if (lw >= S.waves) return;  // whole wave idle; no block barriers in this kernel
     const Piece pc = piece_of(S, lw);
     if (pc.k0 > pc.k1 || !S.active[pc.sys]) return;
-    down_piece<T, NS>(S, pc.sys, pc.strip, pc.k0, pc.k1, pc.rev, lane);
+    down_piece<T, NS, TC>(S, pc.sys, pc.strip, pc.k0, pc.k1, pc.rev, lane);
 }
 
-template <typename T, int NS, bool NORM>
+template <typename T, int NS, bool NORM, typename TC = T>
 struct UpPipe {
     using C = cplx<T>;
     static constexpr int HALO = NORM ? 2 * NS + 1 : (NS > 0 ? 2 * NS : 1);
@@ -506,10 +523,10 @@ struct UpPipe {
         return v;
     }
     template <bool EDGE> __device__ __forceinline__ C load_e(int K) const {
-        C v;
+        cplx<TC> v;
         if constexpr (EDGE) bload(es, oe + (K >= 0 && K <= lc.ny + 1 ? cph(K) * rc : OOB), 0, v);
         else bload(es, oe, cph(K) * rc, v);
-        return v;
+        return cvt<C>(v);
     }
     // coarse column i/2 at an even fine column; the average of coarse columns
     // (i-1)/2 and (i+1)/2 at an odd one (the right one via a lane shift)
@@ -585,11 +602,11 @@ struct UpPipe {
 
 // Rows k0..k1 of one strip of one system; returns the lane's share of
 // sum |b - L x|^2 over the owned columns and rows (NORM).
-template <typename T, int NS, bool NORM>
+template <typename T, int NS, bool NORM, typename TC>
 __device__ __forceinline__ double up_piece(const LevelSeg<T>& S, int sys, int strip, int k0, int k1, bool rev,
                                            int lane) {
     using C = cplx<T>;
-    using Pipe = UpPipe<T, NS, NORM>;
+    using Pipe = UpPipe<T, NS, NORM, TC>;
     constexpr int HALO = Pipe::HALO, OWN = Pipe::OWN;
     Pipe p;
     p.lf = S.lf;
@@ -601,12 +618,12 @@ __device__ __forceinline__ double up_piece(const LevelSeg<T>& S, int sys, int st
     p.hf = p.odd ? (T)0.5 : (T)0;
     const bool ecol = i >= 0 && i <= p.lf.nx + 1;
     const bool own = lane >= HALO && lane < HALO + OWN && p.col_in;
-    const unsigned es = sizeof(C);
+    const unsigned es = sizeof(C), ec = sizeof(cplx<TC>);
     p.ox = p.col_in ? i * es : OOB;
-    p.oe = ecol ? (i >> 1) * es : OOB;
+    p.oe = ecol ? (i >> 1) * ec : OOB;
     p.oo = own ? i * es : OOB;
     p.rx = p.lf.pitch * es;
-    p.rc = p.lc.pitch * es;
+    p.rc = p.lc.pitch * ec;
     set_rows(p, rev, k0, k1);
     const int64_t base = (int64_t)sys * p.lf.plane;
     // finishing pass (S.iters set): the iterate read is the one the system's
@@ -622,7 +639,7 @@ __device__ __forceinline__ double up_piece(const LevelSeg<T>& S, int sys, int st
     }
     p.xs = plane_rsrc(xsrc + base, len);
     p.bs = plane_rsrc(S.b + base, len);
-    p.es = plane_rsrc(S.c + (int64_t)sys * p.lc.plane, clen);
+    p.es = plane_rsrc(reinterpret_cast<const cplx<TC>*>(S.c) + (int64_t)sys * p.lc.plane, clen);
     if (S.zd) {
         // dense rows of nx nodes: row r, column i (both from 1) at (r - 1) nx + i - 1
         const int64_t m = (int64_t)p.lf.nx * p.lf.ny;
@@ -665,7 +682,7 @@ __device__ __forceinline__ double up_piece(const LevelSeg<T>& S, int sys, int st
 // ---------------------------------------------------------------------------
 // With NORM, every wave leaves its run's sum in the segment's partial buffer
 // (slot = the wave's index in the segment, S.pieces * S.strips per system).
-template <typename T, int NS, bool NORM>
+template <typename T, int NS, bool NORM, typename TC>
 __global__ __launch_bounds__(NT) VMG_STREAM_OCC void k_up(SegTable<T> tab) {
     // the wave index is uniform over the wave; say so, so that everything
     // derived from it (segment, buffer resources, row bounds) lives in SGPRs
@@ -677,7 +694,7 @@ __global__ __launch_bounds__(NT) VMG_STREAM_OCC void k_up(SegTable<T> tab) {
     const Piece pc = piece_of(S, lw);
     if (!S.iters && !S.active[pc.sys]) return;  // (the finishing pass runs for every system)
     double acc = 0.0;
-    if (pc.k0 <= pc.k1) acc = up_piece<T, NS, NORM>(S, pc.sys, pc.strip, pc.k0, pc.k1, pc.rev, lane);
+    if (pc.k0 <= pc.k1) acc = up_piece<T, NS, NORM, TC>(S, pc.sys, pc.strip, pc.k0, pc.k1, pc.rev, lane);
     if (NORM && S.partial) {
         for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
         if (lane == 0) S.partial[pc.slot] = acc;
@@ -705,9 +722,10 @@ constexpr int UNR_E = 12;
 constexpr int EPF = VMG_EDGE_PF;
 template <int L> __host__ __device__ constexpr int eslot(int p) { return ((p % L) + L * UNR_E) % L; }
 
-template <typename T, int NA, int NB>
+template <typename T, int NA, int NB, typename TC = T>
 struct EdgePipe {
     using C = cplx<T>;
+    using CC = cplx<TC>;
     static constexpr int NS = NA + NB;
     static constexpr int HALO = 2 * NS + 2;  // NS+1 residuals, NS updates, the weighting's lane sum
     static constexpr int OWN = 64 - 2 * HALO;
@@ -753,10 +771,10 @@ struct EdgePipe {
         return v;
     }
     template <bool EDGE> __device__ __forceinline__ C load_e(int K) const {
-        C v;
+        CC v;
         if constexpr (EDGE) bload(es, oe + (K >= 0 && K <= lc.ny + 1 ? cph(K) * rc : OOB), 0, v);
         else bload(es, oe, srow(cph(K), rc), v);
-        return v;
+        return cvt<C>(v);
     }
     __device__ __forceinline__ C interp_x(C v) const {
         // v + hf (right - v): the average at odd columns (hf = 1/2), v at even ones
@@ -820,7 +838,7 @@ struct EdgePipe {
         store_row<EDGE>(xos, j - 2 * NS, X[NS][n0]);
         if constexpr ((P & 1) == 0) {
             const int frow = j - 2 * NS - 2;
-            const C v = full_weight_row<T>(R[NS][n2], R[NS][n1], R[NS][n0]);
+            const CC v = cvt<CC>(full_weight_row<T>(R[NS][n2], R[NS][n1], R[NS][n0]));
             const int K = frow >> 1;
             if constexpr (EDGE)
                 bstore(cbs, of + (frow >= k0 && frow <= k1 && frow >= 2 && K <= lc.ny ? cph(K) * rc : OOB), 0, v);
@@ -837,11 +855,11 @@ struct EdgePipe {
     }
 };
 
-template <typename T, int NA, int NB>
+template <typename T, int NA, int NB, typename TC>
 __device__ __forceinline__ double edge_piece(const LevelSeg<T>& S, int sys, int strip, int k0, int k1, bool rev,
                                              int lane, cplx<T>* bring) {
     using C = cplx<T>;
-    using Pipe = EdgePipe<T, NA, NB>;
+    using Pipe = EdgePipe<T, NA, NB, TC>;
     constexpr int HALO = Pipe::HALO, OWN = Pipe::OWN, NS = Pipe::NS, U = UNR_E;
     Pipe p;
 #if VMG_EDGE_BLDS
@@ -856,20 +874,20 @@ __device__ __forceinline__ double edge_piece(const LevelSeg<T>& S, int sys, int 
     p.hf = p.odd ? (T)0.5 : (T)0;
     const bool ecol = i >= 0 && i <= p.lf.nx + 1;
     const bool own = lane >= HALO && lane < HALO + OWN && p.col_in;
-    const unsigned es = sizeof(C);
+    const unsigned es = sizeof(C), ec = sizeof(cplx<TC>);
     p.ox = p.col_in ? i * es : OOB;
-    p.oe = ecol ? (i >> 1) * es : OOB;
+    p.oe = ecol ? (i >> 1) * ec : OOB;
     p.oo = own ? i * es : OOB;
-    p.of = (own && !(i & 1) && (i >> 1) <= p.lc.nx) ? (i >> 1) * es : OOB;
+    p.of = (own && !(i & 1) && (i >> 1) <= p.lc.nx) ? (i >> 1) * ec : OOB;
     p.rx = p.lf.pitch * es;
-    p.rc = p.lc.pitch * es;
+    p.rc = p.lc.pitch * ec;
     set_rows(p, rev, k0, k1);
     const int64_t base = (int64_t)sys * p.lf.plane;
     p.xs = plane_rsrc(S.x + base, p.lf.plane);
     p.bs = plane_rsrc(S.b + base, p.lf.plane);
-    p.es = plane_rsrc(S.c + (int64_t)sys * p.lc.plane, p.lc.plane);
+    p.es = plane_rsrc(reinterpret_cast<const cplx<TC>*>(S.c) + (int64_t)sys * p.lc.plane, p.lc.plane);
     p.xos = plane_rsrc(S.xo + base, p.lf.plane);
-    p.cbs = plane_rsrc(S.cb + (int64_t)sys * p.lc.plane, p.lc.plane);
+    p.cbs = plane_rsrc(reinterpret_cast<const cplx<TC>*>(S.cb) + (int64_t)sys * p.lc.plane, p.lc.plane);
     p.cf = S.coef[sys];
     p.dl = p.col_in ? p.cf.d : z2<C>();
     p.sl = p.col_in ? S.s : (T)0;
@@ -899,7 +917,7 @@ __device__ __forceinline__ double edge_piece(const LevelSeg<T>& S, int sys, int 
     return own ? p.acc : 0.0;
 }
 
-template <typename T, int NA, int NB>
+template <typename T, int NA, int NB, typename TC>
 __global__ __launch_bounds__(NT) VMG_STREAM_OCC void k_edge(SegTable<T> tab) {
 #if VMG_EDGE_BLDS
     __shared__ cplx<T> bring[NT / 64][12 * 64];  // right-hand side rows, one ring per wave
@@ -914,9 +932,9 @@ __global__ __launch_bounds__(NT) VMG_STREAM_OCC void k_edge(SegTable<T> tab) {
     // (every run walks downward here: the kernel is at its register limit and
     // measured slower with the reflected address arithmetic)
 #if VMG_EDGE_BLDS
-    double acc = edge_piece<T, NA, NB>(S, pc.sys, pc.strip, pc.k0, pc.k1, false, lane, bring[threadIdx.x >> 6]);
+    double acc = edge_piece<T, NA, NB, TC>(S, pc.sys, pc.strip, pc.k0, pc.k1, false, lane, bring[threadIdx.x >> 6]);
 #else
-    double acc = edge_piece<T, NA, NB>(S, pc.sys, pc.strip, pc.k0, pc.k1, false, lane, nullptr);
+    double acc = edge_piece<T, NA, NB, TC>(S, pc.sys, pc.strip, pc.k0, pc.k1, false, lane, nullptr);
 #endif
     if (S.partial) {
         for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
@@ -1000,32 +1018,38 @@ dim3 stream_seg_grid(SegTable<T>& tab, const int* nsys, int own, int col0, int h
     return dim3((w + NT / 64 - 1) / (NT / 64));
 }
 
-template <typename T, int NS> void down_go(SegTable<T> tab, const int* nsys, int rmin, hipStream_t st) {
-    const void* k = (const void*)&k_down<T, NS>;
+// (the run geometry always follows the occupancy of the kernel whose coarse
+// level has the precision of its own, so that a kernel reading or writing
+// complex64 coarse values splits its level, and its norm partial sums, the
+// same way)
+template <typename T, int NS, typename TC> void down_go(SegTable<T> tab, const int* nsys, int rmin, hipStream_t st) {
+    const void* k = (const void*)&k_down<T, NS, T>;
     const dim3 g = stream_seg_grid(tab, nsys, down_own<NS>(), 1, 4 * NS + 9, rmin, resident_waves(k));
     if (g.x == 0) return;
-    hipLaunchKernelGGL((k_down<T, NS>), g, dim3(NT), 0, st, tab);
+    hipLaunchKernelGGL((k_down<T, NS, TC>), g, dim3(NT), 0, st, tab);
 }
-template <typename T, int NS, bool NORM> void up_go(SegTable<T> tab, const int* nsys, int rmin, hipStream_t st) {
-    const void* k = (const void*)&k_up<T, NS, NORM>;
+template <typename T, int NS, bool NORM, typename TC>
+void up_go(SegTable<T> tab, const int* nsys, int rmin, hipStream_t st) {
+    const void* k = (const void*)&k_up<T, NS, NORM, T>;
     const dim3 g = stream_seg_grid(tab, nsys, up_own<NS, NORM>(), UpPipe<T, NS, NORM>::COL0, 4 * NS + 7, rmin,
                                    resident_waves(k));
     if (g.x == 0) return;
-    hipLaunchKernelGGL((k_up<T, NS, NORM>), g, dim3(NT), 0, st, tab);
+    hipLaunchKernelGGL((k_up<T, NS, NORM, TC>), g, dim3(NT), 0, st, tab);
 }
 
-template <typename T, int NA, int NB> void edge_go(SegTable<T> tab, const int* nsys, int rmin, hipStream_t st) {
+template <typename T, int NA, int NB, typename TC>
+void edge_go(SegTable<T> tab, const int* nsys, int rmin, hipStream_t st) {
     using Pipe = EdgePipe<T, NA, NB>;
-    const void* k = (const void*)&k_edge<T, NA, NB>;
+    const void* k = (const void*)&k_edge<T, NA, NB, T>;
     const dim3 g = stream_seg_grid(tab, nsys, Pipe::OWN, Pipe::COL0, 4 * Pipe::NS + 9, rmin, resident_waves(k));
     if (g.x == 0) return;
-    hipLaunchKernelGGL((k_edge<T, NA, NB>), g, dim3(NT), 0, st, tab);
+    hipLaunchKernelGGL((k_edge<T, NA, NB, TC>), g, dim3(NT), 0, st, tab);
 }
 
 template <typename T, int NA, int NB> int edge_tiles_of(int nx, int ny, int nsys, int rmin) {
     using Pipe = EdgePipe<T, NA, NB>;
     const RunGeom g = run_geom(nx, ny, nsys, Pipe::OWN, Pipe::COL0, 4 * Pipe::NS + 9, rmin,
-                               resident_waves((const void*)&k_edge<T, NA, NB>));
+                               resident_waves((const void*)&k_edge<T, NA, NB, T>));
     return g.strips * g.pieces;
 }
 
@@ -1033,14 +1057,25 @@ template <typename T, int NA, int NB> int edge_tiles_of(int nx, int ny, int nsys
 
 bool edge_supported(int nu1, int nu2) { return nu1 >= 1 && nu1 <= 2 && nu2 >= 1 && nu2 <= 2; }
 
-template <typename T> void launch_edge(SegTable<T> tab, const int* nsys, int nu1, int nu2, int rmin, hipStream_t st) {
-    if (nu2 == 1 && nu1 == 1) edge_go<T, 1, 1>(tab, nsys, rmin, st);
-    else if (nu2 == 1 && nu1 == 2) edge_go<T, 1, 2>(tab, nsys, rmin, st);
-    else if (nu2 == 2 && nu1 == 1) edge_go<T, 2, 1>(tab, nsys, rmin, st);
-    else edge_go<T, 2, 2>(tab, nsys, rmin, st);
+template <typename T, typename TC>
+void edge_launch(SegTable<T> tab, const int* nsys, int nu1, int nu2, int rmin, hipStream_t st) {
+    if (nu2 == 1 && nu1 == 1) edge_go<T, 1, 1, TC>(tab, nsys, rmin, st);
+    else if (nu2 == 1 && nu1 == 2) edge_go<T, 1, 2, TC>(tab, nsys, rmin, st);
+    else if (nu2 == 2 && nu1 == 1) edge_go<T, 2, 1, TC>(tab, nsys, rmin, st);
+    else edge_go<T, 2, 2, TC>(tab, nsys, rmin, st);
 }
-template void launch_edge<double>(SegTable<double>, const int*, int, int, int, hipStream_t);
-template void launch_edge<float>(SegTable<float>, const int*, int, int, int, hipStream_t);
+template <typename T>
+void launch_edge(SegTable<T> tab, const int* nsys, int nu1, int nu2, int rmin, hipStream_t st, bool c32) {
+    if constexpr (std::is_same<T, double>::value) {
+        if (c32) {
+            edge_launch<double, float>(tab, nsys, nu1, nu2, rmin, st);
+            return;
+        }
+    }
+    edge_launch<T, T>(tab, nsys, nu1, nu2, rmin, st);
+}
+template void launch_edge<double>(SegTable<double>, const int*, int, int, int, hipStream_t, bool);
+template void launch_edge<float>(SegTable<float>, const int*, int, int, int, hipStream_t, bool);
 
 template <typename T> int edge_tiles(int nx, int ny, int nsys, int nu1, int nu2, int rmin) {
     if (nu2 == 1 && nu1 == 1) return edge_tiles_of<T, 1, 1>(nx, ny, nsys, rmin);
@@ -1055,9 +1090,9 @@ template <typename T> int stream_tiles(int nx, int ny, int nsys, int nu, int rmi
     const void* k;
     int own;
     switch (nu) {
-        case 0: k = (const void*)&k_up<T, 0, true>; own = up_own<0, true>(); break;
-        case 1: k = (const void*)&k_up<T, 1, true>; own = up_own<1, true>(); break;
-        default: k = (const void*)&k_up<T, 2, true>; own = up_own<2, true>(); break;
+        case 0: k = (const void*)&k_up<T, 0, true, T>; own = up_own<0, true>(); break;
+        case 1: k = (const void*)&k_up<T, 1, true, T>; own = up_own<1, true>(); break;
+        default: k = (const void*)&k_up<T, 2, true, T>; own = up_own<2, true>(); break;
     }
     const RunGeom g = run_geom(nx, ny, nsys, own, UpPipe<T, 2, true>::COL0, 4 * (nu < 2 ? nu : 2) + 7, rmin,
                                resident_waves(k));
@@ -1068,16 +1103,16 @@ template int stream_tiles<double>(int, int, int, int, int);
 // capture).
 void stream_prepare() {
 #define VMG_PREP(T)                                                                                   \
-    resident_waves((const void*)&k_down<T, 0>), resident_waves((const void*)&k_down<T, 1>),           \
-        resident_waves((const void*)&k_down<T, 2>), resident_waves((const void*)&k_up<T, 0, true>),    \
-        resident_waves((const void*)&k_up<T, 1, true>), resident_waves((const void*)&k_up<T, 2, true>), \
-        resident_waves((const void*)&k_up<T, 0, false>), resident_waves((const void*)&k_up<T, 1, false>), \
-        resident_waves((const void*)&k_up<T, 2, false>)
+    resident_waves((const void*)&k_down<T, 0, T>), resident_waves((const void*)&k_down<T, 1, T>),             \
+        resident_waves((const void*)&k_down<T, 2, T>), resident_waves((const void*)&k_up<T, 0, true, T>),      \
+        resident_waves((const void*)&k_up<T, 1, true, T>), resident_waves((const void*)&k_up<T, 2, true, T>),  \
+        resident_waves((const void*)&k_up<T, 0, false, T>), resident_waves((const void*)&k_up<T, 1, false, T>), \
+        resident_waves((const void*)&k_up<T, 2, false, T>), resident_waves((const void*)&k_edge<T, 1, 1, T>),  \
+        resident_waves((const void*)&k_edge<T, 1, 2, T>), resident_waves((const void*)&k_edge<T, 2, 1, T>),    \
+        resident_waves((const void*)&k_edge<T, 2, 2, T>)
     VMG_PREP(double);
     VMG_PREP(float);
 #undef VMG_PREP
-    resident_waves((const void*)&k_edge<double, 1, 1>), resident_waves((const void*)&k_edge<double, 1, 2>),
-        resident_waves((const void*)&k_edge<double, 2, 1>), resident_waves((const void*)&k_edge<double, 2, 2>);
 }
 
 int stream_tiles_max(int nx, int ny, int nu) {
@@ -1088,20 +1123,49 @@ int stream_tiles_max(int nx, int ny, int nu) {
 }
 template int stream_tiles<float>(int, int, int, int, int);
 
-template <typename T> void launch_down(SegTable<T> tab, const int* nsys, int nu, int ty, hipStream_t st) {
+template <typename T, typename TC> void down_launch(SegTable<T> tab, const int* nsys, int nu, int ty, hipStream_t st) {
     switch (nu) {
-        case 0: down_go<T, 0>(tab, nsys, ty, st); break;
-        case 1: down_go<T, 1>(tab, nsys, ty, st); break;
-        default: down_go<T, 2>(tab, nsys, ty, st); break;
+        case 0: down_go<T, 0, TC>(tab, nsys, ty, st); break;
+        case 1: down_go<T, 1, TC>(tab, nsys, ty, st); break;
+        default: down_go<T, 2, TC>(tab, nsys, ty, st); break;
     }
 }
-
-template <typename T> void launch_up(SegTable<T> tab, const int* nsys, int nu, bool norm, int ty, hipStream_t st) {
-    switch (nu) {
-        case 0: if (norm) up_go<T, 0, true>(tab, nsys, ty, st); else up_go<T, 0, false>(tab, nsys, ty, st); break;
-        case 1: if (norm) up_go<T, 1, true>(tab, nsys, ty, st); else up_go<T, 1, false>(tab, nsys, ty, st); break;
-        default: if (norm) up_go<T, 2, true>(tab, nsys, ty, st); else up_go<T, 2, false>(tab, nsys, ty, st); break;
+template <typename T> void launch_down(SegTable<T> tab, const int* nsys, int nu, int ty, hipStream_t st, bool c32) {
+    if constexpr (std::is_same<T, double>::value) {
+        if (c32) {
+            down_launch<double, float>(tab, nsys, nu, ty, st);
+            return;
+        }
     }
+    down_launch<T, T>(tab, nsys, nu, ty, st);
+}
+
+template <typename T, typename TC>
+void up_launch(SegTable<T> tab, const int* nsys, int nu, bool norm, int ty, hipStream_t st) {
+    switch (nu) {
+        case 0:
+            if (norm) up_go<T, 0, true, TC>(tab, nsys, ty, st);
+            else up_go<T, 0, false, TC>(tab, nsys, ty, st);
+            break;
+        case 1:
+            if (norm) up_go<T, 1, true, TC>(tab, nsys, ty, st);
+            else up_go<T, 1, false, TC>(tab, nsys, ty, st);
+            break;
+        default:
+            if (norm) up_go<T, 2, true, TC>(tab, nsys, ty, st);
+            else up_go<T, 2, false, TC>(tab, nsys, ty, st);
+            break;
+    }
+}
+template <typename T>
+void launch_up(SegTable<T> tab, const int* nsys, int nu, bool norm, int ty, hipStream_t st, bool c32) {
+    if constexpr (std::is_same<T, double>::value) {
+        if (c32) {
+            up_launch<double, float>(tab, nsys, nu, norm, ty, st);
+            return;
+        }
+    }
+    up_launch<T, T>(tab, nsys, nu, norm, ty, st);
 }
 
 template <typename T> void launch_fill_zero(cplx<T>* x, LevelView lv, int nsys, hipStream_t st) {
@@ -1110,9 +1174,9 @@ template <typename T> void launch_fill_zero(cplx<T>* x, LevelView lv, int nsys, 
 template void launch_fill_zero<double>(double2*, LevelView, int, hipStream_t);
 template void launch_fill_zero<float>(float2*, LevelView, int, hipStream_t);
 
-template void launch_down<double>(SegTable<double>, const int*, int, int, hipStream_t);
-template void launch_down<float>(SegTable<float>, const int*, int, int, hipStream_t);
-template void launch_up<double>(SegTable<double>, const int*, int, bool, int, hipStream_t);
-template void launch_up<float>(SegTable<float>, const int*, int, bool, int, hipStream_t);
+template void launch_down<double>(SegTable<double>, const int*, int, int, hipStream_t, bool);
+template void launch_down<float>(SegTable<float>, const int*, int, int, hipStream_t, bool);
+template void launch_up<double>(SegTable<double>, const int*, int, bool, int, hipStream_t, bool);
+template void launch_up<float>(SegTable<float>, const int*, int, bool, int, hipStream_t, bool);
 
 }  // namespace vmg

@@ -42,8 +42,9 @@ class VankaMG:
     """Setup, solve and ParaDIAG application for batches of shifted systems
     (A + lambda_j I) z_j = b_j on one or more grids.
 
-    precision: "c128" (complex128 cycles) or "c64_ir" (complex64 cycles inside
-    FP64 iterative refinement).  smoother: "vanka" or "jacobi".
+    precision: "c128" (complex128 cycles), "c64_ir" (complex64 cycles inside
+    FP64 iterative refinement) or "c128_c64" (FP64 V-cycles with the
+    coarse-grid correction in complex64).  smoother: "vanka" or "jacobi".
     """
 
     def __init__(self, grids, shifts, omega=24.0 / 25.0, nu1=2, nu2=2, gamma=1, max_iter=100,
@@ -63,7 +64,7 @@ class VankaMG:
         self.lib.vanka_mg_default_opts(ctypes.byref(opts))
         opts.omega = omega
         opts.nu1, opts.nu2, opts.gamma, opts.max_iter = nu1, nu2, gamma, max_iter
-        opts.precision = {"c128": 0, "c64_ir": 1}[precision]
+        opts.precision = {"c128": 0, "c64_ir": 1, "c128_c64": 2}[precision]
         opts.smoother = {"vanka": 0, "jacobi": 1}[smoother]
         opts.ir_inner, opts.check_every = ir_inner, check_every
         opts.graphs = int(bool(graphs))
