@@ -2146,6 +2146,26 @@ template <typename T> int time_level(vmg_handle* H, Group& g, int l, int cand, h
     return time_reps(run, st, ms_out);
 }
 
+// The same for the FP64 finest level of a precision-2 handle (streaming
+// only; its coarse level is the complex64 level 1).
+int time_level0_mixed(vmg_handle* H, Group& g, int rows, hipStream_t st, double* ms_out) {
+    Level& lv = g.lv64[0];
+    Level& lc = g.lv32[1];
+    const vmg_opts& o = H->opts;
+    const int one = g.S;
+    auto seg = [&](double2* x, double2* xo, DevBuf& c) {
+        LevelSeg<double> S = make_seg<double>(H, g, 0, 0, x, P<double>(lv.b), xo,
+                                              reinterpret_cast<double2*>(P<float>(c)), 0, nullptr);
+        S.lc = lc.v;
+        return one_seg(S);
+    };
+    auto run = [&]() {
+        launch_down<double>(seg(P<double>(lv.x[0]), P<double>(lv.x[1]), lc.b), &one, o.nu1, rows, st, true);
+        launch_up<double>(seg(P<double>(lv.x[1]), P<double>(lv.x[0]), lc.x[0]), &one, o.nu2, true, rows, st, true);
+    };
+    return time_reps(run, st, ms_out);
+}
+
 // Time the finest level's per-cycle work with the cycle-edge kernel: one
 // launch for a cycle's correction and post-smoothing and the next cycle's
 // pre-smoothing and restriction (streaming, `rows` rows per wave).
@@ -2210,9 +2230,7 @@ extern "C" int vanka_mg_autotune(vmg_handle* H, const char* cache_path, void* hi
     std::vector<std::string> fresh;
     for (auto& g : H->groups) {
         g.sched.assign(g.L, -1);
-        // (precision 2: the finest level keeps the streaming kernels and
-        // their row heuristic)
-        for (int l = H->opts.precision == 2 ? 1 : 0; l + 1 < g.L; ++l) {
+        for (int l = 0; l + 1 < g.L; ++l) {
             const std::string key = tune_key(H, g, l);
             int found = -2;
             for (auto& e : cache)
@@ -2222,16 +2240,21 @@ extern "C" int vanka_mg_autotune(vmg_handle* H, const char* cache_path, void* hi
                 continue;
             }
             const LevelView& v = cycle_view(H, g, l);
-            std::vector<int> cands{0};
+            // (precision 2: the finest level has only the streaming kernels)
+            const bool mixed0 = H->opts.precision == 2 && l == 0;
+            std::vector<int> cands;
+            if (!mixed0) cands.push_back(0);
             if (H->opts.nu1 <= 2 && H->opts.nu2 <= 2 && v.nx >= 32 && stream_fits(H->opts, v, l))
                 for (int r : {32, 64, 128})
                     if (r <= 2 * v.ny) cands.push_back(r);
+            if (cands.empty()) continue;  // (precision 2 keeps its heuristic; setup checked it streams)
             int best = 0;
             double best_ms = 1e300;
             for (int c : cands) {
                 double ms = 0.0;
-                const int rc = H->opts.precision == 0 ? time_level<double>(H, g, l, c, st, &ms)
-                                                      : time_level<float>(H, g, l, c, st, &ms);
+                const int rc = mixed0                    ? time_level0_mixed(H, g, c, st, &ms)
+                               : H->opts.precision == 0 ? time_level<double>(H, g, l, c, st, &ms)
+                                                        : time_level<float>(H, g, l, c, st, &ms);
                 if (rc) return rc;
                 // the tiled schedule's six launches (against two) weigh more
                 // inside a replayed cycle than in this eager timing (a 127^2
