@@ -119,3 +119,57 @@ def test_mixed_setup_limits():
         with pytest.raises(_lib.VankaMGError) as e:
             VankaMG([Grid(n, num_systems=2)], lam, precision="c128_c64", **kw)
         assert e.value.code == _lib.VMG_INVALID_ARG
+
+
+@pytest.mark.parametrize("conj", [False, True])
+def test_mixed_paradiag_step_and_adjoint(conj):
+    """The ParaDIAG step (MFMA transforms around the shifted solves) and its
+    adjoint with the complex64 coarse-grid correction, against the FP64
+    handle: every system stops below 1e-10 (host FP64 check of the shifted
+    solves via the oracle's residual), so the two results agree to the
+    solves' conditioning."""
+    from paper_2203_11154_amd import Grid, VankaMG
+    n, S = 255, 8
+    h = 1.0 / (n + 1)
+    lam = inputs.alpha_circulant_shifts(S)
+    V, Vinv = inputs.alpha_circulant_vectors(S)
+    F = inputs.rhs(S, n, n, seed=61)
+    Vd, Vinvd, Fd = dev(V), dev(Vinv), dev(F.ravel())
+    out = {}
+    for prec in ("c128", "c128_c64"):
+        s = VankaMG([Grid(n, num_systems=S)], lam, precision=prec)
+        U, st = s.paradiag_apply(Vd, Vinvd, Fd, tol=1e-10, conj=conj)
+        it, rr = s.last_stats()
+        assert st == 0 and np.all(rr <= 1e-10)
+        out[prec] = (host(U).reshape(S, n, n), it)
+    # the shifted solves' right-hand sides and solutions, recovered on the
+    # host: G = V^{-1} F, Z = V^{-1} U (adjoint: G = V^H F, Z = V^H U)
+    M = V.conj().T if conj else Vinv
+    G = (M @ F.reshape(S, -1)).reshape(S, n, n)
+    Zm = (M @ out["c128_c64"][0].reshape(S, -1)).reshape(S, n, n)
+    lj = lam.conj() if conj else lam
+    r = omg.residual_norms(Zm, G, lj, h) / np.linalg.norm(G.reshape(S, -1), axis=1)
+    assert np.all(r <= 2e-10), r
+    assert relerr(out["c128_c64"][0], out["c128"][0]) <= 1e-7
+    assert np.all(out["c128_c64"][1] <= out["c128"][1] + 1)
+
+
+def test_mixed_uneven_batch():
+    """Grids of different depths in one handle (their complex64 coarse cycles
+    are batched per level phase): each reaches 1e-10 in FP64."""
+    from paper_2203_11154_amd import Grid, VankaMG
+    grids = [(511, 511, 2), (127, 127, 4), (255, 127, 3)]
+    S = sum(s for _, _, s in grids)
+    lam = inputs.alpha_circulant_shifts(S)
+    bs = rhs(grids, 70)
+    s = VankaMG([Grid(nx, ny, num_systems=k) for nx, ny, k in grids], lam, precision="c128_c64")
+    Z, it, rr, st = s.solve(dev(np.concatenate([b.ravel() for b in bs])), tol=1e-10)
+    assert st == 0 and np.all(rr <= 1e-10)
+    z = host(Z)
+    off = s0 = 0
+    for (nx, ny, k), b in zip(grids, bs):
+        zg = z[off:off + nx * ny * k].reshape(k, ny, nx)
+        r = omg.residual_norms(zg, b, lam[s0:s0 + k], 1.0 / (nx + 1)) / np.linalg.norm(b.reshape(k, -1), axis=1)
+        assert np.all(r <= 1.01e-10), (nx, ny, r)
+        off += nx * ny * k
+        s0 += k
