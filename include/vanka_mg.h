@@ -140,6 +140,36 @@ int vanka_mg_setup(const vmg_grid* grids, int32_t n_grids, const double* shifts,
 int vanka_mg_set_omega(vmg_handle* h, const double* omega);
 
 /*
+ * Local Fourier analysis (Sec. 2.1): for each eta = lambda h^2 the complex
+ * relaxation weight omega minimising the smoothing factor of eq. (4),
+ * mu = max over the high frequencies of |1 - omega M(theta) L(theta)| (the
+ * symbols of L_j and of the smoother, scaled by h^2), and that minimum.
+ * Host computation only (needs no device).
+ *   eta       host, count complex values (interleaved doubles).
+ *   smoother  0 = additive Vanka (eq. (6)), 1 = point Jacobi.
+ *   omega     host output, count complex values (interleaved doubles).
+ *   mu        host output, count doubles, or NULL.
+ * The high frequencies are sampled on a uniform grid of (cos t1, cos t2)
+ * with spacing 1/192; the minimum is exact for the samples up to about 1e-9.
+ * Returns VMG_OK or VMG_INVALID_ARG (NULL eta or omega, count < 0, bad
+ * smoother).
+ */
+int vanka_mg_lfa_omega(const double* eta, int32_t count, int32_t smoother, double* omega, double* mu);
+
+/*
+ * The complex relaxation parameter per shift (and level): sets, for every
+ * system j and level l, the omega vanka_mg_lfa_omega gives for
+ * eta = lambda_j h^2 with h the finest mesh width (per_level = 0: one weight
+ * per shift on every level) or the level's own h_l (per_level = 1), for the
+ * handle's smoother, and uploads the coefficients (the adjoint systems use
+ * the conjugates).  Replaces weights set by vanka_mg_set_omega;
+ * vanka_mg_set_omega(h, NULL) returns to opts->omega.  Synchronises the
+ * device.
+ * Returns VMG_OK, VMG_INVALID_ARG (per_level not 0 or 1), VMG_HIP_ERROR.
+ */
+int vanka_mg_optimize_omega(vmg_handle* h, int32_t per_level);
+
+/*
  * Solve (A + lambda_j I) z_j = b_j for every system (eq. (2)), or with
  * conj != 0 the adjoint systems (A + conj(lambda_j) I) z_j = b_j.
  *   B, Z        device, complex128, all systems concatenated (see above).

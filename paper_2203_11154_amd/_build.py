@@ -6,7 +6,8 @@ import subprocess
 import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-SOURCES = ["vmg_kernels.hip", "vmg_stream.hip", "vmg_transform.hip", "vmg_aux.hip", "vmg_tail.hip", "vmg_runtime.hip"]
+SOURCES = ["vmg_kernels.hip", "vmg_stream.hip", "vmg_transform.hip", "vmg_aux.hip", "vmg_tail.hip", "vmg_lfa.hip",
+           "vmg_runtime.hip"]
 LIB = os.path.join(HERE, "libvanka_mg.so")
 ARCH = "gfx950"
 

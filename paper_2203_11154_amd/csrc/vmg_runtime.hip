@@ -1332,9 +1332,10 @@ int solve_impl(vmg_handle* H, const double* B, double* Z, double tol, int conj, 
 
 // Coefficient tables of grid G for all levels and both conj variants, and the
 // inverses of its shifted coarsest matrices.  omega: per-system complex
-// relaxation weights (interleaved, the grid's systems), or NULL for opts.omega.
+// relaxation weights (interleaved, the grid's systems), or NULL for opts.omega;
+// omega_levels (takes precedence): one per level and system, [level][system].
 // The conj variant (the adjoint systems, shifts conj(lambda)) uses conj(omega).
-int upload_coefficients(vmg_handle* H, Group& G, const double* omega) {
+int upload_coefficients(vmg_handle* H, Group& G, const double* omega, const double* omega_levels = nullptr) {
     const vmg_opts& o = H->opts;
     std::vector<Coef<double>> c64((size_t)G.L * G.S);
     std::vector<Coef<float>> c32((size_t)G.L * G.S);
@@ -1350,7 +1351,10 @@ int upload_coefficients(vmg_handle* H, Group& G, const double* omega) {
             const double hl = G.h * std::ldexp(1.0, l);
             for (int s = 0; s < G.S; ++s) {
                 cd lam = H->shifts[G.sys0 + s];
-                cd om = omega ? cd(omega[2 * s], omega[2 * s + 1]) : cd(o.omega, 0.0);
+                const size_t ls = (size_t)l * G.S + s;
+                cd om = omega_levels ? cd(omega_levels[2 * ls], omega_levels[2 * ls + 1])
+                        : omega      ? cd(omega[2 * s], omega[2 * s + 1])
+                                     : cd(o.omega, 0.0);
                 if (conj) {
                     lam = std::conj(lam);
                     om = std::conj(om);
@@ -1693,6 +1697,28 @@ int vanka_mg_set_omega(vmg_handle* H, const double* omega) {
     if (hipDeviceSynchronize() != hipSuccess) return VMG_HIP_ERROR;
     for (auto& g : H->groups) {
         int rc = upload_coefficients(H, g, omega ? omega + 2 * (size_t)g.sys0 : nullptr);
+        if (rc) return rc;
+    }
+    return VMG_OK;
+}
+
+int vanka_mg_optimize_omega(vmg_handle* H, int32_t per_level) {
+    if (!H || per_level < 0 || per_level > 1) return VMG_INVALID_ARG;
+    if (hipDeviceSynchronize() != hipSuccess) return VMG_HIP_ERROR;
+    for (auto& g : H->groups) {
+        const size_t n = (size_t)g.L * g.S;
+        std::vector<double> eta(2 * n), om(2 * n);
+        for (int l = 0; l < g.L; ++l) {
+            // (per_level = 0: every level takes the finest level's weight)
+            const double hl = g.h * std::ldexp(1.0, per_level ? l : 0);
+            for (int s = 0; s < g.S; ++s) {
+                const cd e = H->shifts[g.sys0 + s] * (hl * hl);
+                eta[2 * ((size_t)l * g.S + s)] = e.real();
+                eta[2 * ((size_t)l * g.S + s) + 1] = e.imag();
+            }
+        }
+        int rc = vanka_mg_lfa_omega(eta.data(), (int32_t)n, H->opts.smoother, om.data(), nullptr);
+        if (!rc) rc = upload_coefficients(H, g, nullptr, om.data());
         if (rc) return rc;
     }
     return VMG_OK;

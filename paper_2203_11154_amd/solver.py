@@ -108,6 +108,11 @@ class VankaMG:
         _lib.check(self.lib.vanka_mg_set_omega(self.handle, om.view(np.float64).ctypes.data_as(
             ctypes.POINTER(ctypes.c_double))), "vanka_mg_set_omega")
 
+    def optimize_omega(self, per_level=False):
+        """Per shift (per_level: and level), the complex omega minimising the
+        LFA smoothing factor of the handle's smoother (vanka_mg_optimize_omega)."""
+        _lib.check(self.lib.vanka_mg_optimize_omega(self.handle, int(bool(per_level))), "vanka_mg_optimize_omega")
+
     def autotune(self, cache_path=None):
         """Time the kernel schedules of every level and keep the fastest;
         returns the schedule per grid (see schedule())."""
@@ -260,6 +265,22 @@ class VankaMG:
         by = (ctypes.c_double * n)()
         _lib.check(self.lib.vanka_mg_kernel_stats(self.handle, la, ms, by), "vanka_mg_kernel_stats")
         return {k: (la[i], ms[i], by[i]) for i, k in enumerate(_lib.KERNEL_CLASSES)}
+
+
+def lfa_omega(eta, smoother="vanka"):
+    """(omega, mu): for each eta = lambda h^2 the complex relaxation weight
+    minimising the LFA smoothing factor, and that factor (host computation,
+    vanka_mg_lfa_omega)."""
+    lib = _lib.load()
+    e = np.ascontiguousarray(np.atleast_1d(np.asarray(eta, dtype=np.complex128)))
+    om = np.empty_like(e)
+    mu = np.empty(e.shape, dtype=np.float64)
+    pd = ctypes.POINTER(ctypes.c_double)
+    _lib.check(lib.vanka_mg_lfa_omega(e.view(np.float64).ctypes.data_as(pd), e.size,
+                                      {"vanka": 0, "jacobi": 1}[smoother],
+                                      om.view(np.float64).ctypes.data_as(pd), mu.ctypes.data_as(pd)),
+               "vanka_mg_lfa_omega")
+    return om, mu
 
 
 def transform_circulant(n, alpha, F, inverse=False, conj=False, out=None):

@@ -123,3 +123,46 @@ def test_example3_deterioration_and_complex_omega():
     z = host(Zc).reshape(len(j), n, n)
     for k in range(2):
         assert np.linalg.norm(z[k] - zr[k]) <= 1e-10 * np.linalg.norm(zr[k])
+
+
+def test_example3_complex_omega_computed_by_the_library():
+    """The complex relaxation parameter computed by the library (LFA optimum of
+    the smoothing factor): one weight per shift from the finest level's eta
+    never costs more than one cycle over the real 24/25 (the oracle-computed
+    weights of the test above, now from the product); weights per shift and
+    level (each level's own eta = lambda_j h_l^2) converge too, and a sweep on
+    level 1 uses that level's weight (the oracle's sweep with it)."""
+    from paper_2203_11154_amd import Grid, VankaMG, _lib, lfa_omega
+    n = 127
+    h = 1.0 / (n + 1)
+    j = np.arange(8, 129, 8)
+    lam = inputs.example3_shifts(128)[j - 1]
+    b = inputs.rhs(len(j), n, n, seed=9)
+    bd = dev(b.ravel())
+    solver = VankaMG([Grid(n, num_systems=len(j))], lam, **W10)
+    _, it, rr, st = solver.solve(bd, tol=1e-8)
+    assert st == 0
+    solver.optimize_omega()
+    _, its, rrs, sts = solver.solve(bd, tol=1e-8)
+    assert sts == 0 and np.all(rrs <= 1e-8) and np.all(its <= it + 1), (it, its)
+    solver.optimize_omega(per_level=True)
+    _, itl, rrl, stl = solver.solve(bd, tol=1e-8)
+    assert stl == 0 and np.all(rrl <= 1e-8)
+    # level 1 (63^2, h1 = 2h) runs with the weight of eta = lambda (2h)^2
+    n1, h1 = 63, 2 * h
+    w1, _ = lfa_omega(lam * h1 * h1)
+    w0, _ = lfa_omega(lam * h * h)
+    assert np.max(np.abs(w1 - w0)) > 1e-3  # the levels' weights differ
+    rng = np.random.default_rng(4)
+    x = rng.standard_normal((len(j), n1, n1)) + 1j * rng.standard_normal((len(j), n1, n1))
+    b1 = rng.standard_normal((len(j), n1, n1)) + 1j * rng.standard_normal((len(j), n1, n1))
+    out = host(solver.apply_op(_lib.OP_SWEEP, 1, dev(b1.ravel()), dev(x.ravel()))).reshape(len(j), n1, n1)
+    ref = ops.vanka_sweep(x, b1, lam, h1, w1)
+    assert np.max(np.abs(out - ref)) <= 1e-13 * np.max(np.abs(ref))
+    # the adjoint systems use the conjugate weights: solves converge as well
+    _, itc, rrc, stc = solver.solve(bd, tol=1e-8, conj=True)
+    assert stc == 0 and np.all(rrc <= 1e-8)
+    solver.set_omega(None)
+    _, itr, _, _ = solver.solve(bd, tol=1e-8)
+    np.testing.assert_array_equal(itr, it)
+    print("cycles real 24/25:", it.tolist(), "per shift:", its.tolist(), "per shift and level:", itl.tolist())
