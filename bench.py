@@ -163,6 +163,27 @@ def paper_protocol_leg(args, torch):
                      "ms_per_solve": round(1e3 * dt, 3), "systems_per_s": round(nt / dt, 1)}
         del s
     out["vanka_speedup_over_jacobi"] = round(out["jacobi"]["ms_per_solve"] / out["vanka"]["ms_per_solve"], 3)
+    # Example 3 (Helmholtz shifts, h = 1/128, j = 8, 16, ..., 128): the real
+    # 24/25 against the library's LFA-optimal complex weights (per shift, and
+    # per shift and level)
+    n3 = 127
+    j = np.arange(8, 129, 8)
+    lam3 = inputs.example3_shifts(128)[j - 1]
+    b3 = torch.from_numpy(inputs.rhs(len(j), n3, n3, seed=9).ravel()).cuda()
+    s = VankaMG([Grid(n3, num_systems=len(j))], lam3, nu1=1, nu2=0, gamma=2)
+    ex3 = {"workload": "Example 3: 16 Helmholtz shifts (j = 8..128) on 127^2, W(1,0), tol 1e-8"}
+    for name, per_level in (("real_24_25", None), ("complex_per_shift", False), ("complex_per_level", True)):
+        if per_level is not None:
+            s.optimize_omega(per_level=per_level)
+        s.solve(b3, tol=1e-8)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, it, rr, st = s.solve(b3, tol=1e-8)
+        torch.cuda.synchronize()
+        ex3[name] = {"cycles": it.tolist(), "ms_per_solve": round(1e3 * (time.perf_counter() - t0), 3),
+                     "converged": st == 0 and bool(np.all(rr <= 1e-8))}
+    del s
+    out["example3_complex_omega"] = ex3
     return out
 
 
