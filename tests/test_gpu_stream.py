@@ -108,17 +108,19 @@ def test_streamed_solve_parity(nu1, nu2):
             assert np.linalg.norm(zg[j] - zr[j]) <= 1e-10 * np.linalg.norm(zr[j])
 
 
-def test_streamed_full_size_sampled_sweep_and_solve():
+@pytest.mark.parametrize("precision", ["c128", "c128_c64"])
+def test_streamed_full_size_sampled_sweep_and_solve(precision):
     """The 1023 x 1023 benchmark grid (64 alpha-circulant shifts, 8 levels, the
     launch configuration bench.py times, without the transforms): every system
     reaches 1e-10, and the solution matches the exact DST solution of the same
-    systems within the conditioning; 8 systems are compared in full."""
+    systems within the conditioning; 8 systems are compared in full.  Also
+    with the complex64 coarse-grid correction (the bench's leg of it)."""
     from paper_2203_11154_amd import Grid, VankaMG
     n, S = 1023, 64
     h = 1.0 / (n + 1)
     lam = inputs.alpha_circulant_shifts(S)
     b = inputs.rhs(S, n, n)
-    solver = VankaMG([Grid(n, num_systems=S)], lam)
+    solver = VankaMG([Grid(n, num_systems=S)], lam, precision=precision)
     Z, iters, relres, status = solver.solve(dev(b.ravel()), tol=1e-10)
     assert status == 0 and np.all(relres <= 1e-10) and np.all(iters == iters[0])
     z = host(Z).reshape(S, n, n)
