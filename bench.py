@@ -255,7 +255,7 @@ def run_steps(solver, V, Vinv, F, U, steps, tol, torch):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
+        print(json.dumps({"error": "the benchmark runs on one GPU only (the library has no multi-GPU path); --gpus must be 1",
                           "n_gpus": args.gpus}), flush=True)
         sys.exit(2)
     import torch
