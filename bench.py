@@ -316,7 +316,8 @@ def main():
     tl, tms, tby = stats["transform"]
     flops = 8.0 * S * S * n * n * tl
     kernels = {k: {"launches": v[0], "ms": round(v[1], 3),
-                   "GB/s": round(v[2] / (v[1] * 1e-3) / 1e9, 1) if v[1] > 0 else None}
+                   "GB/s": round(v[2] / (v[1] * 1e-3) / 1e9, 1) if v[1] > 0 else None,
+                   "hbm_frac": round(v[2] / (v[1] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4) if v[1] > 0 else None}
                for k, v in stats.items() if v[0] > 0}
     kernels["transform"]["TFLOP/s"] = round(flops / (tms * 1e-3) / 1e12, 2) if tms > 0 else None
     kernels["transform"]["mfma_frac"] = round(flops / (tms * 1e-3) / 1e12 / FP64_MFMA_PEAK_TFLOPS, 4) if tms else None
