@@ -117,7 +117,7 @@ def test_heat_gradient_closed_form(nx, n):
     L_cf, g_cf = opd.heat_loss_closed_form(theta_np, theta_star, n, nx, tau)
     # u meets ||f - K u|| <= 1e-10 ||f||; the error in u, and so in L and its
     # gradient, is that residual times the conditioning of K
-    assert float(loss) == pytest.approx(L_cf, rel=1e-6)
+    assert float(loss.detach()) == pytest.approx(L_cf, rel=1e-6)
     np.testing.assert_allclose(theta.grad.cpu().numpy(), g_cf, rtol=1e-6)
 
 
