@@ -2207,6 +2207,21 @@ template <typename T> int time_edge(vmg_handle* H, Group& g, int rows, hipStream
     return time_reps(run, st, ms_out);
 }
 
+// The cycle-edge kernel of a precision-2 handle (complex64 coarse level).
+int time_edge_mixed(vmg_handle* H, Group& g, int rows, hipStream_t st, double* ms_out) {
+    Level& l0 = g.lv64[0];
+    Level& l1 = g.lv32[1];
+    const int one = g.S;
+    auto run = [&]() {
+        LevelSeg<double> S = make_seg<double>(H, g, 0, 0, P<double>(l0.x[0]), P<double>(l0.b), P<double>(l0.x[1]),
+                                              reinterpret_cast<double2*>(P<float>(l1.x[0])), 0, nullptr);
+        S.cb = reinterpret_cast<double2*>(P<float>(l1.b));
+        S.lc = l1.v;
+        launch_edge<double>(one_seg(S), &one, H->opts.nu1, H->opts.nu2, rows, st, true);
+    };
+    return time_reps(run, st, ms_out);
+}
+
 template <typename F> int time_reps(F&& run, hipStream_t st, double* ms_out) {
     hipEvent_t a = nullptr, b = nullptr;
     if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) return VMG_HIP_ERROR;
@@ -2298,8 +2313,7 @@ extern "C" int vanka_mg_autotune(vmg_handle* H, const char* cache_path, void* hi
         // the cycle-edge kernel against the finest level's separate streaming
         // launches (small grids have too few rows per wave for its halo)
         g.edge = -1;
-        if (H->edge_mode == 1 && H->opts.precision != 2 && edge_possible(H, g) && g.tail_lt != 0 &&
-            sched_stream(H, g, 0)) {
+        if (H->edge_mode == 1 && edge_possible(H, g) && g.tail_lt != 0 && sched_stream(H, g, 0)) {
             const std::string key = tune_key(H, g, -1);
             int found = -1;
             for (auto& e : cache)
@@ -2307,10 +2321,14 @@ extern "C" int vanka_mg_autotune(vmg_handle* H, const char* cache_path, void* hi
             if (found < 0) {
                 const int rows = sched_rows(H, g, 0);
                 double ms_edge = 0.0, ms_sep = 0.0;
-                const bool f64 = H->opts.precision == 0;
-                int rc = f64 ? time_edge<double>(H, g, rows, st, &ms_edge) : time_edge<float>(H, g, rows, st, &ms_edge);
+                const int pr = H->opts.precision;
+                int rc = pr == 0   ? time_edge<double>(H, g, rows, st, &ms_edge)
+                         : pr == 2 ? time_edge_mixed(H, g, rows, st, &ms_edge)
+                                   : time_edge<float>(H, g, rows, st, &ms_edge);
                 if (!rc)
-                    rc = f64 ? time_level<double>(H, g, 0, rows, st, &ms_sep) : time_level<float>(H, g, 0, rows, st, &ms_sep);
+                    rc = pr == 0   ? time_level<double>(H, g, 0, rows, st, &ms_sep)
+                         : pr == 2 ? time_level0_mixed(H, g, rows, st, &ms_sep)
+                                   : time_level<float>(H, g, 0, rows, st, &ms_sep);
                 if (rc) return rc;
                 found = ms_edge < ms_sep ? 1 : 0;
                 fresh.push_back(key + " " + std::to_string(found));

@@ -173,3 +173,32 @@ def test_mixed_uneven_batch():
         assert np.all(r <= 1.01e-10), (nx, ny, r)
         off += nx * ny * k
         s0 += k
+
+
+def test_mixed_autotune(monkeypatch, tmp_path):
+    """Autotuning a precision-2 handle (the finest level's rows among the
+    streaming candidates, the complex64 levels' schedules, the edge choice)
+    changes rounding only: fixed-count results agree to the complex64
+    rounding of the coarse corrections, and the choices are cached under
+    their own precision key."""
+    from paper_2203_11154_amd import Grid, VankaMG
+    monkeypatch.setenv("VMG_EDGE", "1")
+    grids = [(255, 255, 3), (1023, 1023, 2)]
+    S = sum(s for _, _, s in grids)
+    lam = inputs.alpha_circulant_shifts(S)
+    solver = VankaMG([Grid(nx, ny, num_systems=s) for nx, ny, s in grids], lam, precision="c128_c64")
+    bd = dev(np.concatenate([b.ravel() for b in rhs(grids, 80)]))
+    fi = np.full(S, 3, np.int32)
+    Z0, _, rr0, _ = solver.solve(bd, fixed_iters=fi)
+    z0 = host(Z0)
+    cache = tmp_path / "tune.txt"
+    solver.autotune(cache)
+    assert all(solver.schedule(g)[0] > 0 for g in range(len(grids)))
+    Z1, _, rr1, _ = solver.solve(bd, fixed_iters=fi)
+    assert relerr(host(Z1), z0) <= 1e-5
+    np.testing.assert_allclose(rr1, rr0, rtol=1e-3)
+    lines = cache.read_text().splitlines()
+    assert lines and all(" c128c64 " in line for line in lines)
+    assert sum(1 for line in lines if " edge " in line) == len(grids)
+    _, it, rr, st = solver.solve(bd, tol=1e-10)
+    assert st == 0 and np.all(rr <= 1e-10)
