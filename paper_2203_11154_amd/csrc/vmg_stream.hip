@@ -24,6 +24,12 @@
 //               result, in one pass (reads x, b, e once; writes the next
 //               cycle's pre-smoothed iterate and coarse right-hand side).
 //
+// The last template argument of each kernel is the precision of the coarse
+// level it writes (the restricted residual) and reads (the correction e): the
+// level's own, or complex64 under an FP64 level when the coarse-grid
+// correction runs in complex64; values are rounded to it as they are stored
+// and widened (exactly) as they are read.
+//
 // Rows or columns outside the interior hold zero in every stage (Dirichlet
 // ring for the iterates, zero residual off the interior).
 #include "vmg_internal.h"
