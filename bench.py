@@ -52,7 +52,7 @@ def parse():
     p.add_argument("--tol", type=float, default=1e-10)
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-ir", action="store_true")
-    p.add_argument("--cpu-sample", type=int, default=2, help="systems the oracle solves for the CPU baseline")
+    p.add_argument("--cpu-sample", type=int, default=8, help="systems the oracle solves for the CPU baseline")
     p.add_argument("--no-autotune", action="store_true", help="keep the size heuristic kernel schedule")
     p.add_argument("--no-batched", action="store_true", help="skip the uneven-grid batched leg")
     p.add_argument("--no-paper", action="store_true", help="skip the paper-protocol leg")
