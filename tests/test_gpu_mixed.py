@@ -202,3 +202,27 @@ def test_mixed_autotune(monkeypatch, tmp_path):
     assert sum(1 for line in lines if " edge " in line) == len(grids)
     _, it, rr, st = solver.solve(bd, tol=1e-10)
     assert st == 0 and np.all(rr <= 1e-10)
+
+
+@pytest.mark.parametrize("nu1,nu2", [(1, 1), (0, 1), (2, 1), (1, 2)])
+def test_mixed_other_smoothing_counts(nu1, nu2, monkeypatch):
+    """Other pre-/post-smoothing counts (with nu1 = 0 the finest level's first
+    iterate is cleared by a fill instead of a sweep; the edge kernel runs for
+    nu1, nu2 >= 1): fixed counts follow the oracle's FP64 cycles to complex64
+    rounding, free-running solves reach 1e-10 in FP64."""
+    from paper_2203_11154_amd import Grid, VankaMG
+    monkeypatch.setenv("VMG_EDGE", "2")
+    grids = [(255, 255, 2)]
+    lam = inputs.alpha_circulant_shifts(2)
+    b = rhs(grids, 90)[0]
+    s = VankaMG([Grid(255, num_systems=2)], lam, precision="c128_c64", nu1=nu1, nu2=nu2)
+    assert s.plan(0)[0] == (nu1 >= 1 and nu2 >= 1)
+    Z, it, _, _ = s.solve(dev(b.ravel()), fixed_iters=np.full(2, 3, np.int32))
+    zr, _, _, _ = omg.solve(b, lam, 1.0 / 256, fixed_iters=np.full(2, 3), nu1=nu1, nu2=nu2)
+    z = host(Z).reshape(2, 255, 255)
+    for j in range(2):
+        assert relerr(z[j], zr[j]) <= 1e-5, (j, relerr(z[j], zr[j]))
+    Z, it, rr, st = s.solve(dev(b.ravel()), tol=1e-10)
+    assert st == 0 and np.all(rr <= 1e-10)
+    r = omg.residual_norms(host(Z).reshape(2, 255, 255), b, lam, 1.0 / 256) / np.linalg.norm(b.reshape(2, -1), axis=1)
+    assert np.all(r <= 1.01e-10)
