@@ -226,3 +226,22 @@ def test_mixed_other_smoothing_counts(nu1, nu2, monkeypatch):
     assert st == 0 and np.all(rr <= 1e-10)
     r = omg.residual_norms(host(Z).reshape(2, 255, 255), b, lam, 1.0 / 256) / np.linalg.norm(b.reshape(2, -1), axis=1)
     assert np.all(r <= 1.01e-10)
+
+
+def test_mixed_circulant_step():
+    """The alpha-circulant ParaDIAG step with DFT transforms (the norm sums of
+    the transformed right-hand sides fused into the forward transform) with
+    the complex64 coarse-grid correction: every system below 1e-10, the
+    result within 1e-7 of the FP64 handle's."""
+    from paper_2203_11154_amd import Grid, VankaMG
+    n, S, alpha = 255, 16, 0.01
+    lam = inputs.alpha_circulant_shifts(S, alpha)
+    Fd = dev(inputs.rhs(S, n, n, seed=62).ravel())
+    out = {}
+    for prec in ("c128", "c128_c64"):
+        s = VankaMG([Grid(n, num_systems=S)], lam, precision=prec)
+        U, st = s.paradiag_apply_circulant(alpha, Fd, tol=1e-10)
+        it, rr = s.last_stats()
+        assert st == 0 and np.all(rr <= 1e-10)
+        out[prec] = host(U)
+    assert relerr(out["c128_c64"], out["c128"]) <= 1e-7
