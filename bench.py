@@ -339,6 +339,24 @@ def main():
                 "traffic": traffic, "launches": la, "avg_ms": round(ms / max(la, 1), 5),
                 "algorithmic_bytes_per_launch": round(by / max(la, 1)),
                 "bytes_per_node": "56 (read x, b, e/4; write x_(k+1) pre-smoothed, coarse rhs/4)"}
+    # context: the same GPU's device-to-device copy rate (2 GiB read, 2 GiB
+    # written), and the kernel's measured traffic against it
+    src = torch.empty(1 << 28, dtype=torch.float64, device=dev).fill_(1.0)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(5):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    copy_gbs = 5 * 2 * src.numel() * 8 / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del src, dst
+    roofline["context"] = {"copy_GB/s": round(copy_gbs, 1)}
+    if traffic:
+        tr_gbs = traffic / (ms / max(la, 1) * 1e-3) / 1e9
+        roofline["context"].update({"traffic_GB/s": round(tr_gbs, 1),
+                                    "traffic_frac_of_copy": round(tr_gbs / copy_gbs, 3)})
     levels = {}
     for k in ("down", "up", "edge"):
         levels[k] = [{"level": l, "launches": a, "avg_ms": round(m / max(a, 1), 4),
