@@ -28,6 +28,7 @@
 #include <algorithm>
 #include <cmath>
 #include <complex>
+#include <thread>
 #include <vector>
 
 namespace {
@@ -155,13 +156,31 @@ void optimise(cd eta, int smoother, cd* omega, double* mu) {
 
 extern "C" int vanka_mg_lfa_omega(const double* eta, int32_t count, int32_t smoother, double* omega, double* mu) {
     if (!eta || !omega || count < 0 || smoother < 0 || smoother > 1) return VMG_INVALID_ARG;
-    for (int32_t k = 0; k < count; ++k) {
-        cd w;
-        double m;
-        optimise(cd(eta[2 * k], eta[2 * k + 1]), smoother, &w, &m);
-        omega[2 * k] = w.real();
-        omega[2 * k + 1] = w.imag();
-        if (mu) mu[k] = m;
+    // independent problems: split over host threads (each writes its own
+    // entries)
+    auto work = [&](int32_t k0, int32_t k1) {
+        for (int32_t k = k0; k < k1; ++k) {
+            cd w;
+            double m;
+            optimise(cd(eta[2 * k], eta[2 * k + 1]), smoother, &w, &m);
+            omega[2 * k] = w.real();
+            omega[2 * k + 1] = w.imag();
+            if (mu) mu[k] = m;
+        }
+    };
+    const int32_t nt =
+        std::max<int32_t>(1, std::min<int32_t>({count / 4, 16, (int32_t)std::thread::hardware_concurrency()}));
+    auto lo = [&](int32_t t) { return (int32_t)((int64_t)count * t / nt); };
+    // ranges 1.. on their own threads, range 0 here; a range whose thread
+    // cannot start runs here as well (nothing may throw across the C ABI)
+    std::vector<std::thread> pool;
+    int32_t started = 1;
+    try {
+        for (; started < nt; ++started) pool.emplace_back(work, lo(started), lo(started + 1));
+    } catch (...) {
     }
+    work(lo(0), lo(1));
+    for (int32_t t = started; t < nt; ++t) work(lo(t), lo(t + 1));
+    for (auto& th : pool) th.join();
     return VMG_OK;
 }
