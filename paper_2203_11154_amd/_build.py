@@ -1,6 +1,7 @@
 """Build step of the HIP library: compiles csrc/*.hip for gfx950 into
 libvanka_mg.so next to this file (run by ``__graft_entry__.build()`` or
 ``python -m paper_2203_11154_amd._build``)."""
+import concurrent.futures
 import os
 import subprocess
 import sys
@@ -26,16 +27,20 @@ def build(verbose=False):
     flags = ["-O3", "-std=c++17", f"--offload-arch={ARCH}", "-fPIC", "-Wall", "-Wno-unused-result",
              # keep the compiler from emitting packed FP32 ALU instructions
              "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
-    objs = []
-    for src in SOURCES:
-        obj = os.path.join(objdir, src.replace(".hip", ".o"))
+    objs = [os.path.join(objdir, src.replace(".hip", ".o")) for src in SOURCES]
+
+    def compile_one(src, obj):
         cmd = [hipcc()] + flags + ["-c", os.path.join(HERE, "csrc", src), "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
-        res = subprocess.run(cmd, capture_output=True, text=True)
-        if res.returncode != 0:
-            raise RuntimeError(f"hipcc failed for {src}:\n{res.stdout}\n{res.stderr}")
-        objs.append(obj)
+        return src, subprocess.run(cmd, capture_output=True, text=True)
+
+    # the sources compile independently: in parallel, a few at a time
+    workers = max(1, min(len(SOURCES), os.cpu_count() or 1, 8))
+    with concurrent.futures.ThreadPoolExecutor(max_workers=workers) as pool:
+        for src, res in pool.map(compile_one, SOURCES, objs):
+            if res.returncode != 0:
+                raise RuntimeError(f"hipcc failed for {src}:\n{res.stdout}\n{res.stderr}")
     tmp = LIB + ".tmp"
     cmd = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp] + objs
     res = subprocess.run(cmd, capture_output=True, text=True)
