@@ -348,6 +348,12 @@ enum {
     VMG_NUM_KCLASS = 11
 };
 int vanka_mg_set_timing(vmg_handle* h, int32_t enable, int32_t reset);
+/* Kernel classes timed while timing is on: bit k of mask for class k
+ * (VMG_K_*), 0 = every class (the default).  Events are recorded only around
+ * the launches of those classes, so a single timed class leaves the rest of
+ * the work unperturbed.  Returns VMG_OK or VMG_INVALID_ARG (bits beyond the
+ * classes). */
+int vanka_mg_set_timing_mask(vmg_handle* h, int32_t mask);
 int vanka_mg_kernel_stats(vmg_handle* h, int64_t* launches /* [VMG_NUM_KCLASS] */,
                           double* total_ms, double* total_bytes);
 /* The same sums for one kernel class split by multigrid level (0 = finest;

@@ -30,7 +30,7 @@ NUM_KCLASS = len(KERNEL_CLASSES)
 EXPORTED = ["vanka_mg_default_opts", "vanka_mg_setup", "vanka_mg_solve", "paradiag_apply",
             "vanka_mg_shift_gradient", "paradiag_heat_residual", "paradiag_heat_solve", "paradiag_heat_gmres",
             "paradiag_transform", "paradiag_transform_circulant", "paradiag_apply_circulant",
-            "vanka_mg_apply_op", "vanka_mg_set_timing", "vanka_mg_kernel_stats",
+            "vanka_mg_apply_op", "vanka_mg_set_timing", "vanka_mg_set_timing_mask", "vanka_mg_kernel_stats",
             "vanka_mg_level_stats", "vanka_mg_autotune", "vanka_mg_schedule", "vanka_mg_plan", "vanka_mg_set_omega",
             "vanka_mg_lfa_omega", "vanka_mg_optimize_omega", "vanka_mg_levels", "vanka_mg_last_stats", "vanka_mg_destroy", "vanka_mg_error_string"]
 
@@ -77,6 +77,7 @@ def load():
     lib.paradiag_apply_circulant.argtypes = [vp, dbl, vp, vp, dbl, i32, pi32, vp]
     lib.vanka_mg_apply_op.argtypes = [vp, i32, i32, i32, vp, vp, vp, vp]
     lib.vanka_mg_set_timing.argtypes = [vp, i32, i32]
+    lib.vanka_mg_set_timing_mask.argtypes = [vp, i32]
     lib.vanka_mg_kernel_stats.argtypes = [vp, pi64, pdbl, pdbl]
     lib.vanka_mg_level_stats.argtypes = [vp, i32, i32, pi64, pdbl, pdbl]
     lib.vanka_mg_levels.argtypes = [vp, i32, pi32, pi32, pi32]

@@ -150,6 +150,7 @@ struct vmg_handle {
     std::vector<std::pair<GraphKey, hipGraphExec_t>> graphs;
     // timing
     bool timing = false;
+    uint32_t timing_mask = ~0u;  // kernel classes timed while timing is on
     std::vector<TimedLaunch> pending;
     std::vector<hipEvent_t> event_pool;
     int64_t launches[VMG_NUM_KCLASS] = {};
@@ -207,13 +208,13 @@ struct Timer {
     hipEvent_t a = nullptr;
     Timer(vmg_handle* H_, hipStream_t st_, int k, double by, int lev = 0)
         : H(H_), st(st_), kclass(k), bytes(by), level(lev) {
-        if (H->timing) {
+        if (H->timing && ((H->timing_mask >> k) & 1u)) {
             a = get_event(H);
             if (a) (void)hipEventRecord(a, st);
         }
     }
     ~Timer() {
-        if (H->timing && a) {
+        if (a) {
             hipEvent_t b = get_event(H);
             if (b) {
                 (void)hipEventRecord(b, st);
@@ -1755,6 +1756,12 @@ int vanka_mg_set_timing(vmg_handle* H, int32_t enable, int32_t reset) {
             }
         }
     }
+    return VMG_OK;
+}
+
+int vanka_mg_set_timing_mask(vmg_handle* H, int32_t mask) {
+    if (!H || mask < 0 || mask >= (1 << VMG_NUM_KCLASS)) return VMG_INVALID_ARG;
+    H->timing_mask = mask == 0 ? ~0u : (uint32_t)mask;
     return VMG_OK;
 }
 

@@ -243,7 +243,11 @@ class VankaMG:
                    "vanka_mg_last_stats")
         return iters, relres
 
-    def set_timing(self, enable=True, reset=True):
+    def set_timing(self, enable=True, reset=True, classes=None):
+        """Per-kernel HIP-event timing on (eager launches) or off; classes: the
+        kernel classes (names of _lib.KERNEL_CLASSES) to time, None = all."""
+        mask = 0 if classes is None else sum(1 << _lib.KERNEL_CLASSES.index(c) for c in classes)
+        _lib.check(self.lib.vanka_mg_set_timing_mask(self.handle, mask), "vanka_mg_set_timing_mask")
         _lib.check(self.lib.vanka_mg_set_timing(self.handle, int(enable), int(reset)), "vanka_mg_set_timing")
 
     def level_stats(self, kclass):
