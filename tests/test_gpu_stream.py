@@ -158,3 +158,28 @@ def test_fused_norm_equals_host_residual(nu1, nu2, edge, monkeypatch):
             ref = omg.residual_norms(zg, b, lg, g["h"]) / np.linalg.norm(b.reshape(g["S"], -1), axis=1)
             np.testing.assert_allclose(rr[sys:sys + g["S"]], ref, rtol=1e-9)
             sys += g["S"]
+
+
+def test_timing_mask_times_only_the_chosen_classes(monkeypatch):
+    """With a class mask only those launches are timed (the others run
+    without events); the results do not depend on timing."""
+    from paper_2203_11154_amd import Grid, VankaMG
+    monkeypatch.setenv("VMG_EDGE", "2")
+    lam = inputs.alpha_circulant_shifts(2)
+    s = VankaMG([Grid(255, num_systems=2)], lam)
+    bd = dev(inputs.rhs(2, 255, 255, seed=33).ravel())
+    Z0, it0, _, _ = s.solve(bd, tol=1e-10)
+    z0 = host(Z0)
+    s.set_timing(True, reset=True, classes=["edge"])
+    Z1, it1, _, _ = s.solve(bd, tol=1e-10)
+    stats = s.kernel_stats()
+    s.set_timing(False, reset=False)
+    assert stats["edge"][0] >= int(it1.max()) and stats["edge"][1] > 0
+    assert all(v[0] == 0 for k, v in stats.items() if k != "edge")
+    s.set_timing(True, reset=True)
+    s.solve(bd, tol=1e-10)
+    stats = s.kernel_stats()
+    s.set_timing(False, reset=False)
+    assert stats["edge"][0] > 0 and stats["down"][0] > 0 and stats["up"][0] > 0
+    np.testing.assert_array_equal(it1, it0)
+    assert np.array_equal(host(Z1), z0)
