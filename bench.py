@@ -30,7 +30,7 @@ FP64_MFMA_PEAK_TFLOPS = 78.6
 # FETCH_SIZE and WRITE_SIZE on this workload, each scaled by its reading for a
 # plain 1 GiB copy (profiles/).  Valid only for the kernel source it was
 # measured on: reported as null once that file changes.
-MEASURED_TRAFFIC = {"source": "vmg_stream.hip", "source_sha256_16": "55aa523806855e73", "bytes_per_launch": 4062.9e6}
+MEASURED_TRAFFIC = {"source": "vmg_stream.hip", "source_sha256_16": "55aa523806855e73", "bytes_per_launch": 4065.1e6}
 # finest level across the boundary of two V-cycles: correction + 2 sweeps +
 # stopping-test norm, then the next cycle's 2 sweeps + residual + restriction
 DOMINANT = "k_edge<double, 2, 2, double>"
