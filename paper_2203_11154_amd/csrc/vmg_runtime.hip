@@ -84,8 +84,12 @@ struct Group {
     int64_t tail_lds = 0;    // its dynamic LDS bytes
 };
 
+// Launch sequence of one captured cycle.  parity holds the level-0 buffer
+// parity of every grid (one entry per grid, so any number of grids keys
+// exactly).
 struct GraphKey {
-    int first, conj, fixed, parity;
+    int first, conj, fixed;
+    std::vector<char> parity;
     double tol;
     bool operator==(const GraphKey& o) const {
         return first == o.first && conj == o.conj && fixed == o.fixed && parity == o.parity && tol == o.tol;
@@ -1165,11 +1169,14 @@ int enqueue_cycle_all(vmg_handle* H, int conj, hipStream_t st, int64_t cycle, do
 // sequence (first cycle or not, conj, level-0 buffer parity, tolerance).
 int run_cycle(vmg_handle* H, int conj, hipStream_t st, int64_t cycle, double tol, int fixed) {
     if (!H->opts.graphs || H->timing) return enqueue_cycle_all(H, conj, st, cycle, tol, fixed);
-    int par = 0;
-    for (size_t gi = 0; gi < H->groups.size(); ++gi)
-        par |= level0_parity(H, H->groups[gi], cycle) << (gi & 31);
-    if (H->opts.precision == 1) par = (int)(cycle & 1);  // the FP64 iterate's buffer
-    GraphKey key{cycle == 0 ? 1 : 0, conj, fixed, par, tol};
+    std::vector<char> par;
+    if (H->opts.precision == 1) {
+        par.push_back((char)(cycle & 1));  // the FP64 iterate's buffer
+    } else {
+        par.resize(H->groups.size());
+        for (size_t gi = 0; gi < H->groups.size(); ++gi) par[gi] = (char)level0_parity(H, H->groups[gi], cycle);
+    }
+    GraphKey key{cycle == 0 ? 1 : 0, conj, fixed, std::move(par), tol};
     hipGraphExec_t exec = nullptr;
     for (auto& e : H->graphs)
         if (e.first == key) exec = e.second;

@@ -117,3 +117,17 @@ def test_zero_rhs_and_fixed_iterations():
     assert iters[1] == 0 and np.all(z[1] == 0)
     z2, it2, _, _ = mg.solve(b, lam, h, fixed_iters=[3, 0])
     assert list(it2) == [3, 0]
+
+
+def test_observed_rate_hand_computed():
+    """The observed rate is the geometric mean of the per-cycle reductions of
+    the relative residual from r_0/||b|| = 1 (x0 = 0), i.e. the K-th root of
+    the last entry of a K-cycle history.  Values worked by hand: an arithmetic
+    mean of the ratios, a root of K - 1, or the first entry would each give
+    another number."""
+    # ratios 0.5, 0.2, 0.2: geometric mean 0.02^(1/3) = 0.271441761659..
+    assert mg.observed_rate([0.5, 0.1, 0.02]) == pytest.approx(0.2714417616594907, rel=1e-14)
+    # a constant contraction of 0.28 (Table 1's Vanka factor) over 5 cycles
+    assert mg.observed_rate([0.28, 0.0784, 0.021952, 0.00614656, 0.0017210368]) == pytest.approx(0.28, rel=1e-13)
+    assert mg.observed_rate([0.001]) == pytest.approx(0.001, rel=1e-15)
+    assert mg.observed_rate([]) == 0.0

@@ -203,3 +203,16 @@ def test_fgmres_matches_brute_force_krylov_minimum():
         _, _, _, hist = pd.paradiag_heat_fgmres(f, tau, h, lam, V, Vinv, tol=1e-15, restart=10, max_iter=k,
                                                 solver="dst")
         assert hist[k - 1] == pytest.approx(best, rel=1e-7, abs=1e-14)
+
+
+def test_helmholtz_shift_signs_by_hand():
+    """Example 3: lambda_j = -j^2 (1 - 0.5 i) = -j^2 + (j^2 / 2) i, so the real
+    parts are negative and the imaginary parts positive.  The first shifts
+    and the last one are written out by hand."""
+    lam = spectral.helmholtz_shifts(128)
+    assert lam[0] == complex(-1.0, 0.5)
+    assert lam[1] == complex(-4.0, 2.0)
+    assert lam[2] == complex(-9.0, 4.5)
+    assert lam[9] == complex(-100.0, 50.0)
+    assert lam[127] == complex(-16384.0, 8192.0)
+    assert np.all(lam.imag > 0) and np.all(lam.real < 0)
