@@ -5,6 +5,7 @@
 
 #include <algorithm>
 #include <fstream>
+#include <mutex>
 #include <sstream>
 #include <string>
 #include <cmath>
@@ -1793,20 +1794,33 @@ namespace {
 
 // Scratch for the expanded real transform matrix of the stand-alone
 // paradiag_transform entry point: one buffer per device, grown on demand and
-// kept until the process ends.
+// kept until the process ends.  Its reuse is ordered on the device: every
+// call makes its stream wait for the event recorded after the previous call's
+// kernels (on whatever stream they ran), so calls on different streams never
+// overwrite the matrix another call is still reading; a buffer is freed only
+// once that event has completed.
 struct TransformScratch {
     void* ptr = nullptr;
     size_t bytes = 0;
+    hipEvent_t done = nullptr;  // recorded after the last launch that read ptr
+    bool recorded = false;
 };
 TransformScratch g_tscratch[64];
+std::mutex g_tscratch_mu;
 
-int transform_scratch(size_t bytes, double2** out) {
+// Buffer of at least `bytes` on the current device, ready for use on `st`
+// (called with g_tscratch_mu held).
+int transform_scratch(size_t bytes, hipStream_t st, TransformScratch** out) {
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return VMG_HIP_ERROR;
     TransformScratch& sc = g_tscratch[dev];
+    if (!sc.done && hipEventCreateWithFlags(&sc.done, hipEventDisableTiming) != hipSuccess) {
+        sc.done = nullptr;
+        return VMG_HIP_ERROR;
+    }
     if (sc.bytes < bytes) {
         if (sc.ptr) {
-            if (hipDeviceSynchronize() != hipSuccess) return VMG_HIP_ERROR;
+            if (sc.recorded && hipEventSynchronize(sc.done) != hipSuccess) return VMG_HIP_ERROR;
             (void)hipFree(sc.ptr);
             sc.ptr = nullptr;
             sc.bytes = 0;
@@ -1816,8 +1830,10 @@ int transform_scratch(size_t bytes, double2** out) {
             return VMG_OOM;
         }
         sc.bytes = bytes;
+    } else if (sc.recorded && hipStreamWaitEvent(st, sc.done, 0) != hipSuccess) {
+        return VMG_HIP_ERROR;
     }
-    *out = static_cast<double2*>(sc.ptr);
+    *out = &sc;
     return VMG_OK;
 }
 
@@ -1846,12 +1862,16 @@ extern "C" int paradiag_transform(int32_t n, int64_t m, const double* M, int32_t
                                   double* out, void* hip_stream) {
     if (n < 1 || n > 512 || m < 1 || m >= (int64_t)1 << 30 || !M || !in || !out || in == out)
         return VMG_INVALID_ARG;
-    double2* mx = nullptr;
-    int rc = transform_scratch(sizeof(double) * 4 * (size_t)n * n, &mx);
+    const hipStream_t st = (hipStream_t)hip_stream;
+    std::lock_guard<std::mutex> lock(g_tscratch_mu);
+    TransformScratch* sc = nullptr;
+    int rc = transform_scratch(sizeof(double) * 4 * (size_t)n * n, st, &sc);
     if (rc) return rc;
     launch_transform(n, m, reinterpret_cast<const double2*>(M), trans_conj ? 1 : 0,
                      reinterpret_cast<const double2*>(in), dense_rows(m), reinterpret_cast<double2*>(out),
-                     dense_rows(m), mx, (hipStream_t)hip_stream);
+                     dense_rows(m), static_cast<double2*>(sc->ptr), st);
+    if (hipEventRecord(sc->done, st) != hipSuccess) return VMG_HIP_ERROR;
+    sc->recorded = true;
     return check_hip();
 }
 

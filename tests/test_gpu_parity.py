@@ -279,6 +279,30 @@ def test_transform_parity():
         assert maxrel(GH.reshape(n, m), M.conj().T @ F) <= 1e-13
 
 
+def test_transform_calls_on_two_streams():
+    """paradiag_transform keeps its expanded matrix in one library buffer per
+    device: calls on two streams, the second growing that buffer (larger n)
+    and a third reusing it while the others may still run, all give their own
+    products."""
+    from paper_2203_11154_amd import transform
+    rng = np.random.default_rng(17)
+    cases = [(64, 200003), (128, 50001), (64, 100001)]
+    data = []
+    for n, m in cases:
+        M = rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))
+        F = rng.standard_normal((n, m)) + 1j * rng.standard_normal((n, m))
+        data.append((M, F, dev(M), dev(F)))
+    torch.cuda.synchronize()
+    streams = [torch.cuda.Stream(), torch.cuda.Stream(), torch.cuda.Stream()]
+    outs = []
+    for (M, F, Md, Fd), st in zip(data, streams):
+        with torch.cuda.stream(st):
+            outs.append(transform(Md, Fd))
+    torch.cuda.synchronize()
+    for (M, F, _, _), G in zip(data, outs):
+        assert maxrel(G.cpu().numpy().reshape(F.shape), M @ F) <= 1e-13
+
+
 @pytest.mark.parametrize("conj", [False, True])
 def test_paradiag_apply_parity(conj):
     from paper_2203_11154_amd import Grid, VankaMG
