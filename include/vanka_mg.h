@@ -311,10 +311,33 @@ int paradiag_transform_circulant(int32_t n, int64_t m, double alpha, int32_t inv
  * GEMM on the FP64 matrix cores.  With trans_conj != 0, M^H replaces M.
  *   M        device, complex128 n x n row-major (1 <= n <= 512).
  *   in, out  device, complex128 n x m row-major; may not alias.
- * Returns VMG_OK, VMG_INVALID_ARG, VMG_HIP_ERROR.
+ * The expanded real form of M lives in a per-device buffer of the library
+ * (allocated on first use, grown when a larger n comes, kept until the
+ * process ends).  Its reuse is ordered on the device: each call's stream
+ * waits for the previous call's kernels, on whatever stream they ran, so
+ * calls on different streams are safe (and serialised there).
+ * Returns VMG_OK, VMG_INVALID_ARG, VMG_HIP_ERROR, VMG_OOM.
  */
 int paradiag_transform(int32_t n, int64_t m, const double* M, int32_t trans_conj,
                        const double* in, double* out, void* hip_stream);
+
+/*
+ * paradiag_transform for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same kernels and results, with the expanded matrix kept in
+ * a fixed device array of the library (4 n^2 doubles for n up to
+ * VMG_NOALLOC_MAX_N = 256, i.e. 2 MiB per GPU, held until the process ends;
+ * its address is looked up once per device on the first call there).  No
+ * allocation of any kind is made.  Every call on one GPU uses that GPU's one
+ * array: calls that overlap on the device (other streams, other host
+ * threads) race and must be ordered by the caller.
+ *   n        1 <= n <= VMG_NOALLOC_MAX_N; larger n returns VMG_INVALID_ARG.
+ *   other arguments as paradiag_transform.
+ * Returns VMG_OK, VMG_INVALID_ARG, VMG_HIP_ERROR.
+ */
+#define VMG_NOALLOC_MAX_N 256
+int paradiag_transform_noalloc(int32_t n, int64_t m, const double* M, int32_t trans_conj,
+                               const double* in, double* out, void* hip_stream);
 
 /*
  * Run one operation (VMG_OP_*) of the solver on caller data, for every system

@@ -9,9 +9,10 @@ does, and fails loudly if it has not been built.
 """
 import importlib
 
-__all__ = ["Grid", "VankaMG", "transform", "transform_circulant", "lfa_omega", "ShiftedSolve", "ParaDiag", "inputs"]
+__all__ = ["Grid", "VankaMG", "transform", "transform_noalloc", "transform_circulant", "lfa_omega", "ShiftedSolve", "ParaDiag", "inputs"]
 
-_LAZY = {"Grid": "solver", "VankaMG": "solver", "transform": "solver", "transform_circulant": "solver",
+_LAZY = {"Grid": "solver", "VankaMG": "solver", "transform": "solver", "transform_noalloc": "solver",
+         "transform_circulant": "solver",
          "lfa_omega": "solver",
          "ShiftedSolve": "autograd", "ParaDiag": "autograd"}
 

@@ -29,7 +29,7 @@ NUM_KCLASS = len(KERNEL_CLASSES)
 
 EXPORTED = ["vanka_mg_default_opts", "vanka_mg_setup", "vanka_mg_solve", "paradiag_apply",
             "vanka_mg_shift_gradient", "paradiag_heat_residual", "paradiag_heat_solve", "paradiag_heat_gmres",
-            "paradiag_transform", "paradiag_transform_circulant", "paradiag_apply_circulant",
+            "paradiag_transform", "paradiag_transform_noalloc", "paradiag_transform_circulant", "paradiag_apply_circulant",
             "vanka_mg_apply_op", "vanka_mg_set_timing", "vanka_mg_set_timing_mask", "vanka_mg_kernel_stats",
             "vanka_mg_level_stats", "vanka_mg_autotune", "vanka_mg_schedule", "vanka_mg_plan", "vanka_mg_set_omega",
             "vanka_mg_lfa_omega", "vanka_mg_optimize_omega", "vanka_mg_levels", "vanka_mg_last_stats", "vanka_mg_destroy", "vanka_mg_error_string"]
@@ -73,6 +73,7 @@ def load():
     lib.paradiag_heat_solve.argtypes = [vp, vp, vp, dbl, vp, vp, dbl, dbl, i32, i32, i32, pi32, pdbl, vp]
     lib.paradiag_heat_gmres.argtypes = [vp, vp, vp, dbl, vp, vp, dbl, dbl, i32, i32, i32, pi32, pdbl, vp]
     lib.paradiag_transform.argtypes = [i32, i64, vp, i32, vp, vp, vp]
+    lib.paradiag_transform_noalloc.argtypes = [i32, i64, vp, i32, vp, vp, vp]
     lib.paradiag_transform_circulant.argtypes = [i32, i64, dbl, i32, i32, vp, vp, vp]
     lib.paradiag_apply_circulant.argtypes = [vp, dbl, vp, vp, dbl, i32, pi32, vp]
     lib.vanka_mg_apply_op.argtypes = [vp, i32, i32, i32, vp, vp, vp, vp]

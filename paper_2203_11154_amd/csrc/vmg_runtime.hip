@@ -1837,6 +1837,32 @@ int transform_scratch(size_t bytes, hipStream_t st, TransformScratch** out) {
     return VMG_OK;
 }
 
+// Scratch of paradiag_transform_noalloc: the expanded real form of M
+// (2n x 2n doubles, n <= VMG_NOALLOC_MAX_N) in a file-scope device array, so
+// that entry point never allocates.  Each GPU holds its own copy, at its own
+// address, until the process ends.  In host code `scratch` names a host-side
+// stand-in, never the device memory: only the address hipGetSymbolAddress
+// returns for the current device is passed to kernels.
+static __device__ __align__(256) double scratch[4 * VMG_NOALLOC_MAX_N * VMG_NOALLOC_MAX_N];
+double* g_scratch_dev[64];  // device address of `scratch` per device (set once, on the first call there)
+std::mutex g_scratch_mu;
+
+int noalloc_scratch(double** out) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return VMG_HIP_ERROR;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+        void* p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) {
+            (void)hipGetLastError();
+            return VMG_HIP_ERROR;
+        }
+        g_scratch_dev[dev] = static_cast<double*>(p);
+    }
+    *out = g_scratch_dev[dev];
+    return VMG_OK;
+}
+
 RowLayout dense_rows(int64_t m) {
     RowLayout L;
     L.nx = (int)std::min<int64_t>(m, 1 << 30);
@@ -1872,6 +1898,19 @@ extern "C" int paradiag_transform(int32_t n, int64_t m, const double* M, int32_t
                      dense_rows(m), static_cast<double2*>(sc->ptr), st);
     if (hipEventRecord(sc->done, st) != hipSuccess) return VMG_HIP_ERROR;
     sc->recorded = true;
+    return check_hip();
+}
+
+extern "C" int paradiag_transform_noalloc(int32_t n, int64_t m, const double* M, int32_t trans_conj,
+                                          const double* in, double* out, void* hip_stream) {
+    if (n < 1 || n > VMG_NOALLOC_MAX_N || m < 1 || m >= (int64_t)1 << 30 || !M || !in || !out || in == out)
+        return VMG_INVALID_ARG;
+    double* mx = nullptr;
+    const int rc = noalloc_scratch(&mx);
+    if (rc) return rc;
+    launch_transform(n, m, reinterpret_cast<const double2*>(M), trans_conj ? 1 : 0,
+                     reinterpret_cast<const double2*>(in), dense_rows(m), reinterpret_cast<double2*>(out),
+                     dense_rows(m), reinterpret_cast<double2*>(mx), (hipStream_t)hip_stream);
     return check_hip();
 }
 

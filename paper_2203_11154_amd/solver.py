@@ -315,3 +315,20 @@ def transform(M, F, trans_conj=False, out=None):
     code = lib.paradiag_transform(n, m, _ptr(M), int(bool(trans_conj)), _ptr(F), _ptr(out), _stream())
     _lib.check(code, "paradiag_transform")
     return out
+
+def transform_noalloc(M, F, trans_conj=False, out=None):
+    """transform() through the entry point that allocates no device memory
+    (the expanded matrix lives in the library's fixed per-GPU array; n <= 256;
+    calls that overlap on one GPU race).  `out` must be given by callers that
+    cannot allocate."""
+    _require_gpu()
+    lib = _lib.load()
+    n = M.shape[0]
+    m = F.numel() // n
+    for t in (M, F):
+        if not (t.is_cuda and t.dtype == torch.complex128 and t.is_contiguous()):
+            raise TypeError("transform_noalloc needs contiguous complex128 CUDA tensors")
+    out = torch.empty_like(F) if out is None else out
+    code = lib.paradiag_transform_noalloc(n, m, _ptr(M), int(bool(trans_conj)), _ptr(F), _ptr(out), _stream())
+    _lib.check(code, "paradiag_transform_noalloc")
+    return out
