@@ -1,12 +1,20 @@
 """Benchmark of the ParaDIAG hot path on one MI355X.
 
 One step = one ParaDIAG application of eq. (1) to a batch of time slices:
-G = (V^{-1} kron I) F on the FP64 matrix cores, the 64 shifted systems
+G = (V^{-1} kron I) F on the FP64 matrix cores, the n shifted systems
 (A + lambda_j I) z_j = g_j solved to 1e-10 relative residual by V(2,2) Vanka
-multigrid, and U = (V kron I) Z.  The workload is the 1023 x 1023 unit-square
-grid with the 64 alpha-circulant shifts (alpha = 0.01, tau = 1/64); F is
-chosen as (V kron I) b with b_j ~ U(-1, 1) + i U(-1, 1), so the shifted
-systems see exactly those right-hand sides.
+multigrid, and U = (V kron I) Z.
+
+Headline workload (the precision workload): the 2047 x 2047 unit-square grid
+with the 32 alpha-circulant shifts (alpha = 0.01, tau = 1/32); F is chosen as
+(V kron I) b with b_j ~ U(-1, 1) + i U(-1, 1), so the shifted systems see
+exactly those right-hand sides.  `value` is the FP64 step's systems/s; the
+same step with complex64 V-cycles inside FP64 refinement and with FP64
+V-cycles whose coarse-grid correction runs in complex64 are reported beside
+it, with their speedups and each result's error against the FP64 oracle on
+a sample of systems.  Side legs: the same step on 1023 x 1023 with 64
+shifts, the 63 x 63 latency case (microseconds per solve), the uneven batch,
+the paper's protocol and the heat (differentiation) workload.
 
 Prints one JSON line.  Inputs are resident in HBM before the timed region.
 """
@@ -27,13 +35,23 @@ HBM_PEAK_GBS = 8000.0
 FP64_MFMA_PEAK_TFLOPS = 78.6
 
 # HBM bytes per launch of the dominant kernel measured with rocprofv3
-# FETCH_SIZE and WRITE_SIZE on this workload, each scaled by its reading for a
+# FETCH_SIZE and WRITE_SIZE on each workload, each scaled by its reading for a
 # plain 1 GiB copy (profiles/).  Valid only for the kernel source it was
 # measured on: reported as null once that file changes.
-MEASURED_TRAFFIC = {"source": "vmg_stream.hip", "source_sha256_16": "55aa523806855e73", "bytes_per_launch": 4065.1e6}
+MEASURED_TRAFFIC = {"source": "vmg_stream.hip", "source_sha256_16": "55aa523806855e73",
+                    "bytes_per_launch": {"plain_1023": 4065.1e6}}
 # finest level across the boundary of two V-cycles: correction + 2 sweeps +
 # stopping-test norm, then the next cycle's 2 sweeps + residual + restriction
 DOMINANT = "k_edge<double, 2, 2, double>"
+# systems of the headline workload the oracle solves (the cpu baseline and
+# the per-result errors): the smallest and the largest |lambda_j|
+ORACLE_SAMPLE = (0, 16)
+
+
+def progress(msg):
+    """One line on stderr per finished part of the run (stdout carries only
+    the JSON line)."""
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
 def kernel_source_hash(name):
@@ -47,70 +65,227 @@ def parse():
     p.add_argument("--gpus", type=int, default=1)
     p.add_argument("--steps", type=int, default=5)
     p.add_argument("--warmup", type=int, default=2)
-    p.add_argument("--n", type=int, default=1023, help="interior grid size")
-    p.add_argument("--systems", type=int, default=64, help="time slices = shifted systems")
     p.add_argument("--tol", type=float, default=1e-10)
     p.add_argument("--no-cpu-baseline", action="store_true")
-    p.add_argument("--no-ir", action="store_true")
-    p.add_argument("--cpu-sample", type=int, default=8, help="systems the oracle solves for the CPU baseline")
+    p.add_argument("--cpu-sample", type=int, default=len(ORACLE_SAMPLE),
+                   help="systems of the headline workload the oracle solves (cpu baseline, per-result errors)")
     p.add_argument("--no-autotune", action="store_true", help="keep the size heuristic kernel schedule")
-    p.add_argument("--no-batched", action="store_true", help="skip the uneven-grid batched leg")
-    p.add_argument("--no-paper", action="store_true", help="skip the paper-protocol leg")
-    p.add_argument("--no-heat", action="store_true", help="skip the heat (differentiation) leg")
+    p.add_argument("--legs", default="all",
+                   help="comma list of parts to run: headline (2047^2 x 32), plain (1023^2 x 64), small (63^2 x 8), "
+                        "batched, paper, heat; default all")
     p.add_argument("--copy-calibration", action="store_true",
                    help="run one plain 1 GiB device copy first (reference for hardware byte counters)")
     return p.parse_args()
 
 
-def cpu_baseline(b, lam, h, tol, count):
-    """The FP64 oracle on a bounded sample of the same workload: `count` of
-    the shifted systems solved to `tol` (transforms excluded), BLAS limited to
-    one thread so the core count is exact."""
+def host_info():
+    """The host the CPU baseline ran on: logical CPUs, those this process may
+    use, CPU model and RAM."""
+    info = {"nproc": os.cpu_count()}
+    try:
+        info["affinity_cpus"] = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        pass
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    info["cpu_model"] = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        with open("/proc/meminfo") as f:
+            for line in f:
+                if line.startswith("MemTotal"):
+                    info["ram_GiB"] = round(int(line.split()[1]) / 2 ** 20, 1)
+                    break
+    except OSError:
+        pass
+    return info
+
+
+def cpu_baseline(b, lam, h, tol, sample, gpu_solutions):
+    """The FP64 oracle on a bounded sample of the headline workload: the
+    systems `sample` solved to `tol` (transforms excluded), BLAS limited to
+    one thread so the core count is exact.  Also each GPU result's relative
+    error against the oracle's solution of the same system."""
     from threadpoolctl import threadpool_limits
     from oracle import multigrid as omg
+    idx = list(sample)
     with threadpool_limits(limits=1):
         t0 = time.perf_counter()
-        _, iters, relres, _ = omg.solve(b[:count], lam[:count], h, tol=tol)
+        z_or, iters, relres, _ = omg.solve(b[idx], lam[idx], h, tol=tol)
         dt = time.perf_counter() - t0
-    return {"value": count / dt, "unit": "systems/s", "cores": 1, "kind": "oracle",
-            "sample": f"{count} of the {len(lam)} shifted systems at {b.shape[-1]}^2, V(2,2) to {tol:g} "
-                      f"({int(iters.sum())} cycles, {dt:.1f} s; transforms excluded)"}
+    errors = {}
+    for name, zs in gpu_solutions.items():
+        errors[name] = {str(j): float(np.linalg.norm((zs[k] - z_or[k]).ravel()) / np.linalg.norm(z_or[k].ravel()))
+                        for k, j in enumerate(idx)}
+    return {"value": len(idx) / dt, "unit": "systems/s", "cores": 1, "kind": "oracle",
+            "sample": f"systems {idx} of the {len(lam)} shifted systems at {b.shape[-1]}^2, V(2,2) to {tol:g} "
+                      f"({int(iters.sum())} cycles, {dt:.1f} s; transforms excluded)",
+            "oracle_cycles": iters.tolist(), "oracle_relres": relres.tolist(), "host": host_info(),
+            "gpu_error_vs_oracle": errors}
 
 
-def precision_leg(args, torch):
-    """The precision workload: 32 alpha-circulant shifts (alpha = 0.01,
-    tau = 1/32) on 2047^2, the ParaDIAG step to 1e-10 with complex64 V-cycles
-    inside FP64 refinement, and FP64 V-cycles with a complex64 coarse-grid
-    correction, against FP64 V-cycles (all uninstrumented, cycles replayed as
-    graphs, autotuned; refinement with 2 inner cycles a step)."""
+def run_steps(solver, V, Vinv, F, U, steps, tol, torch):
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    status = 0
+    for _ in range(steps):
+        _, status = solver.paradiag_apply(V, Vinv, F, tol=tol, out=U)
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0, status
+
+
+def kernel_breakdown(solver, Vd, Vinvd, Fd, Ud, steps, tol, S, n, torch):
+    """Per kernel class and per level: a separate pass with every kernel class
+    timed by HIP events (its events perturb the step, so it is not timed as a
+    whole)."""
+    solver.set_timing(True, reset=True)
+    run_steps(solver, Vd, Vinvd, Fd, Ud, steps, tol, torch)
+    stats = solver.kernel_stats()
+    solver.set_timing(False, reset=False)
+    levels = {}
+    for k in ("down", "up", "edge"):
+        levels[k] = [{"level": l, "launches": a, "avg_ms": round(m / max(a, 1), 4),
+                      "GB/s": round(b_ / (m * 1e-3) / 1e9, 1) if m > 0 else None}
+                     for l, a, m, b_ in solver.level_stats(k)]
+    kernels = {k: {"launches": v[0], "ms": round(v[1], 3),
+                   "GB/s": round(v[2] / (v[1] * 1e-3) / 1e9, 1) if v[1] > 0 else None,
+                   "hbm_frac": round(v[2] / (v[1] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4) if v[1] > 0 else None}
+               for k, v in stats.items() if v[0] > 0}
+    tl, tms, _ = stats["transform"]
+    if tl and tms > 0:
+        flops = 8.0 * S * S * n * n * tl
+        kernels["transform"]["TFLOP/s"] = round(flops / (tms * 1e-3) / 1e12, 2)
+        kernels["transform"]["mfma_frac"] = round(flops / (tms * 1e-3) / 1e12 / FP64_MFMA_PEAK_TFLOPS, 4)
+    return kernels, levels
+
+
+def edge_kernel_rate(edge_levels):
+    """Level-0 cycle-edge launches of a timed pass: launches, average ms,
+    algorithmic bytes per launch and GB/s."""
+    for lvl, la, ms, by in edge_levels:
+        if lvl == 0 and la > 0 and ms > 0:
+            return {"launches": la, "avg_ms": round(ms / la, 5), "algorithmic_bytes_per_launch": round(by / la),
+                    "GB/s": round(by / (ms * 1e-3) / 1e9, 1),
+                    "hbm_frac": round(by / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+    return None
+
+
+PRECISIONS = (("fp64", {}, "c128"),
+              ("fp32_ir", {"precision": "c64_ir", "ir_inner": 2}, "c64 cycles + c128 refinement"),
+              ("fp32_coarse", {"precision": "c128_c64"},
+               "c128 finest level and stopping test, c64 coarse-grid correction"))
+
+
+def paradiag_leg(name, n, S, seed, args, torch, sample=(), breakdown=True, dft=True):
+    """One ParaDIAG step workload (n x n grid, S alpha-circulant shifts,
+    right-hand sides from `seed`) in the three precisions: FP64 V-cycles,
+    complex64 V-cycles inside FP64 refinement, FP64 V-cycles with a complex64
+    coarse-grid correction.  Timed steps record HIP events around the
+    finest-level cycle-edge kernel only.  Returns the leg's results and, for
+    the systems in `sample`, each precision's solution (host arrays)."""
     from paper_2203_11154_amd import Grid, VankaMG, inputs
-    n, S, tol = 2047, 32, args.tol
+    tol = args.tol
     lam = inputs.alpha_circulant_shifts(S, 0.01)
     V, Vinv = inputs.alpha_circulant_vectors(S, 0.01)
-    b = inputs.rhs(S, n, n, seed=4)
-    Fd = torch.from_numpy(np.ascontiguousarray(V @ b.reshape(S, -1)).ravel()).cuda()
-    del b
-    Vd, Vinvd = torch.from_numpy(V).cuda(), torch.from_numpy(Vinv).cuda()
+    b = inputs.rhs(S, n, n, seed=seed)
+    dev = torch.device("cuda:0")
+    Fd = torch.from_numpy(np.ascontiguousarray(V @ b.reshape(S, -1)).ravel()).to(dev)
+    Vd = torch.from_numpy(V).to(dev).contiguous()
+    Vinvd = torch.from_numpy(Vinv).to(dev).contiguous()
     Ud = torch.empty_like(Fd)
-    res = {"workload": "precision_2047: 32 alpha-circulant shifts on 2047x2047, ParaDIAG step to 1e-10"}
-    for name, kw in (("fp64", {}), ("fp32_ir", {"precision": "c64_ir", "ir_inner": 2}),
-                     ("fp32_coarse", {"precision": "c128_c64"})):
+    bd = torch.from_numpy(b.reshape(-1)).to(dev) if len(sample) else None
+    out = {"workload": f"{name}: {S} alpha-circulant shifts (alpha=0.01, tau=1/{S}) on the {n}x{n} unit-square "
+                       f"grid, ParaDIAG step (transform, V(2,2) Vanka multigrid to {tol:g}, inverse transform)",
+           "grid": n, "systems": S}
+    solutions = {}
+    m = n * n
+    for pname, kw, dtype in PRECISIONS:
         s = VankaMG([Grid(n, num_systems=S)], lam, **kw)
-        if not args.no_autotune:
-            s.autotune()
+        schedule = s.autotune() if not args.no_autotune else [s.schedule(0)]
         for _ in range(args.warmup):
             s.paradiag_apply(Vd, Vinvd, Fd, tol=tol, out=Ud)
+        s.set_timing(True, reset=True, classes=["edge"])
         dt, st = run_steps(s, Vd, Vinvd, Fd, Ud, args.steps, tol, torch)
+        edge = edge_kernel_rate(s.level_stats("edge"))
+        s.set_timing(False, reset=False)
         it, rr = s.last_stats()
-        res[name] = {"ms_per_step": round(1e3 * dt / args.steps, 3), "value": round(S * args.steps / dt, 2),
-                     "cycles_or_steps": {"min": int(it.min()), "max": int(it.max())}, "max_relres": float(rr.max()),
-                     "converged": st == 0 and bool(np.all(rr <= tol))}
+        r = {"value": round(S * args.steps / dt, 2), "unit": "systems/s",
+             "ms_per_step": round(1e3 * dt / args.steps, 3), "dtype": dtype,
+             ("cycles" if pname != "fp32_ir" else "refinement_steps"): {"min": int(it.min()), "max": int(it.max())},
+             "max_relres": float(rr.max()), "converged": st == 0 and bool(np.all(rr <= tol)),
+             "levels": len(s.levels()), "schedule": schedule[0], "edge_kernel": edge}
+        if pname == "fp64":
+            # the same steps without any event (cycles replayed as graphs)
+            dtg, _ = run_steps(s, Vd, Vinvd, Fd, Ud, args.steps, tol, torch)
+            r["uninstrumented"] = {"ms_per_step": round(1e3 * dtg / args.steps, 3),
+                                   "value": round(S * args.steps / dtg, 2)}
+            if dft:
+                # the alpha-circulant transforms as scaled DFTs instead of the
+                # MFMA GEMMs
+                for _ in range(args.warmup):
+                    s.paradiag_apply_circulant(0.01, Fd, tol=tol, out=Ud)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                for _ in range(args.steps):
+                    _, st_c = s.paradiag_apply_circulant(0.01, Fd, tol=tol, out=Ud)
+                torch.cuda.synchronize()
+                dtc = time.perf_counter() - t0
+                _, rr_c = s.last_stats()
+                r["circulant_dft_step"] = {"ms_per_step": round(1e3 * dtc / args.steps, 3),
+                                           "value": round(S * args.steps / dtc, 2),
+                                           "converged": st_c == 0 and bool(np.all(rr_c <= tol)),
+                                           "note": f"transforms as scaled length-{S} DFTs, uninstrumented"}
+        if breakdown:
+            r["kernels"], r["fused_by_level"] = kernel_breakdown(s, Vd, Vinvd, Fd, Ud, min(args.steps, 3), tol, S, n,
+                                                                 torch)
+        if len(sample):
+            # the shifted solves on their own (right-hand sides b), for the
+            # per-result error against the oracle
+            Z, _, rr_s, _ = s.solve(bd, tol=tol)
+            torch.cuda.synchronize()
+            solutions[pname] = np.stack([Z[j * m:(j + 1) * m].cpu().numpy().reshape(n, n) for j in sample])
+            del Z
+        out[pname] = r
+        progress(f"{name} {pname}: {r['ms_per_step']} ms/step, max relres {r['max_relres']:.3e}")
         del s
-    res["speedup_vs_fp64"] = round(res["fp64"]["ms_per_step"] / res["fp32_ir"]["ms_per_step"], 3)
-    res["fp32_coarse_speedup_vs_fp64"] = round(res["fp64"]["ms_per_step"] / res["fp32_coarse"]["ms_per_step"], 3)
-    del Fd, Ud
+        torch.cuda.empty_cache()
+    f64 = out["fp64"]["ms_per_step"]
+    for pname in ("fp32_ir", "fp32_coarse"):
+        out[pname]["speedup_vs_fp64"] = round(f64 / out[pname]["ms_per_step"], 3)
+    del Fd, Ud, bd
     torch.cuda.empty_cache()
-    return res
+    return out, solutions, (b, lam, 1.0 / (n + 1))
+
+
+def small_leg(args, torch):
+    """The latency case: 8 alpha-circulant shifts (tau = 1/8) on 63 x 63, V(2,2)
+    with 5 levels to 1e-10, one batched solve (graph replay): microseconds
+    per solve of all 8 systems."""
+    from paper_2203_11154_amd import Grid, VankaMG, inputs
+    n, S = 63, 8
+    lam = inputs.alpha_circulant_shifts(S)
+    bd = torch.from_numpy(inputs.rhs(S, n, n).ravel()).cuda()
+    s = VankaMG([Grid(n, num_systems=S, levels=5)], lam)
+    Z, _, _, _ = s.solve(bd, tol=args.tol)
+    for _ in range(max(args.warmup, 3)):
+        s.solve(bd, tol=args.tol, out=Z)
+    reps = max(20, args.steps)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        _, it, rr, st = s.solve(bd, tol=args.tol, out=Z)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / reps
+    return {"workload": "8 alpha-circulant shifts on 63x63, V(2,2), 5 levels, to 1e-10 (cache-resident, latency bound)",
+            "us_per_solve": round(1e6 * dt, 1), "us_per_system": round(1e6 * dt / S, 1),
+            "value": round(S / dt, 1), "unit": "systems/s", "cycles": {"min": int(it.min()), "max": int(it.max())},
+            "max_relres": float(rr.max()), "converged": st == 0 and bool(np.all(rr <= args.tol)),
+            "note": "host-timed solves (enqueue, device stopping test, host read of the counts) averaged over "
+                    f"{reps} calls"}
 
 
 def batched_leg(args, torch):
@@ -130,16 +305,39 @@ def batched_leg(args, torch):
     for _ in range(args.warmup):
         solver.solve(bd, tol=args.tol, out=Z)
     torch.cuda.synchronize()
+    w0 = time.monotonic_ns()
     t0 = time.perf_counter()
     for _ in range(args.steps):
         _, iters, relres, status = solver.solve(bd, tol=args.tol, out=Z)
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t0) / args.steps
+    w1 = time.monotonic_ns()
     out = {"value": round(S / dt, 1), "unit": "systems/s", "ms_per_step": round(1e3 * dt, 3),
            "workload": "256x127^2 + 96x255^2 + 32x511^2, uniform shifts, V(2,2) to 1e-10, one batched solve",
            "iterations": {"min": int(iters.min()), "max": int(iters.max())}, "max_relres": float(relres.max()),
-           "converged": bool(status == 0 and np.all(relres <= args.tol))}
+           "converged": bool(status == 0 and np.all(relres <= args.tol)),
+           "timed_window_monotonic_ns": [w0, w1]}
     del solver
+    # the 32 x 511^2 group on its own (its finest level, 267 MB a vector,
+    # is the batch's only one well above the 256 MB cache): GB/s of its
+    # finest-level kernels by algorithmic bytes, every kernel class timed
+    g511 = VankaMG([Grid(511, num_systems=32)], lam[-32:])
+    if not args.no_autotune:
+        g511.autotune()
+    b511 = bd[-32 * 511 * 511:].contiguous()
+    Z511, _, _, _ = g511.solve(b511, tol=args.tol)
+    g511.set_timing(True, reset=True)
+    for _ in range(max(1, min(args.steps, 3))):
+        g511.solve(b511, tol=args.tol, out=Z511)
+    g511.set_timing(False, reset=False)
+    fine = {}
+    for k in ("down", "up", "edge"):
+        for lvl, la, ms, by in g511.level_stats(k):
+            if lvl == 0 and la > 0 and ms > 0:
+                fine[k] = {"launches": la, "avg_ms": round(ms / la, 4), "GB/s": round(by / (ms * 1e-3) / 1e9, 1),
+                           "hbm_frac": round(by / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+    out["group_511_alone"] = {"finest_level_kernels": fine, "plan": list(g511.plan(0))}
+    del g511, Z511, b511
     # the same batch with the complex64 coarse-grid correction
     mx = VankaMG([Grid(n, num_systems=c) for n, c in groups], lam, precision="c128_c64")
     if not args.no_autotune:
@@ -256,6 +454,20 @@ def heat_leg(args, torch):
     dt = (time.perf_counter() - t0) / args.steps
     out["gradient"] = {"ms_forward_adjoint": round(1e3 * dt, 3), "adjoint_relres": prob.last["relres"],
                        "grad_norm": float(grad.norm())}
+    # central differences (step 1e-6) with the iteration counts of the last
+    # forward solve frozen (the solve is then one fixed linear map of f and
+    # the quadratic loss has no truncation error) against the adjoint gradient
+    g = grad.cpu().numpy()
+    th0 = theta.clone()
+    fd_err = {}
+    for k in (0, 5, 15):
+        e = torch.zeros(K, dtype=torch.float64, device="cuda")
+        e[k] = 1e-6
+        lp = float(((HeatSolve.apply(source(th0 + e), prob, True).real - ustar) ** 2).sum())
+        lm = float(((HeatSolve.apply(source(th0 - e), prob, True).real - ustar) ** 2).sum())
+        fd = (lp - lm) / 2e-6
+        fd_err[f"theta_{k}"] = {"adjoint": float(g[k]), "fd": fd, "rel_diff": abs(fd - g[k]) / abs(g[k])}
+    out["gradient"]["fd_check"] = fd_err
     del prob
     # the stationary solve with the shifted solves' coarse-grid corrections in
     # complex64 (same tolerances)
@@ -273,14 +485,42 @@ def heat_leg(args, torch):
     return out
 
 
-def run_steps(solver, V, Vinv, F, U, steps, tol, torch):
+def copy_rate(torch):
+    """The same GPU's device-to-device copy rate (2 GiB read, 2 GiB written)."""
+    src = torch.empty(1 << 28, dtype=torch.float64, device="cuda:0").fill_(1.0)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(5):
+        dst.copy_(src)
+    e1.record()
     torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    status = 0
-    for _ in range(steps):
-        _, status = solver.paradiag_apply(V, Vinv, F, tol=tol, out=U)
-    torch.cuda.synchronize()
-    return time.perf_counter() - t0, status
+    gbs = 5 * 2 * src.numel() * 8 / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del src, dst
+    torch.cuda.empty_cache()
+    return gbs
+
+
+def roofline_of(leg, traffic_key, copy_gbs):
+    """Roofline object of the dominant kernel (the FP64 cycle-edge kernel) from
+    the HIP events of the leg's timed steps."""
+    e = leg["fp64"]["edge_kernel"]
+    gbs = e["GB/s"]
+    traffic = None
+    if MEASURED_TRAFFIC["source_sha256_16"] == kernel_source_hash(MEASURED_TRAFFIC["source"]):
+        traffic = MEASURED_TRAFFIC["bytes_per_launch"].get(traffic_key)
+    n, S = leg["grid"], leg["systems"]
+    r = {"bound": "hbm", "kernel": DOMINANT, "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+         "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": traffic, "launches": e["launches"], "avg_ms": e["avg_ms"],
+         "algorithmic_bytes_per_launch": e["algorithmic_bytes_per_launch"],
+         "bytes_per_node": f"56 (read x, b, e/4; write x_(k+1) pre-smoothed, coarse rhs/4) x {n}^2 x {S}",
+         "context": {"copy_GB/s": round(copy_gbs, 1)}}
+    if traffic:
+        tr = traffic / (e["avg_ms"] * 1e-3) / 1e9
+        r["context"].update({"traffic_GB/s": round(tr, 1), "traffic_frac_of_copy": round(tr / copy_gbs, 3),
+                             "traffic_over_algorithmic": round(traffic / e["algorithmic_bytes_per_launch"], 4)})
+    return r
 
 
 def main():
@@ -290,182 +530,54 @@ def main():
                           "n_gpus": args.gpus}), flush=True)
         sys.exit(2)
     import torch
-    from paper_2203_11154_amd import Grid, VankaMG, inputs
-
-    n, S, tol = args.n, args.systems, args.tol
-    h = 1.0 / (n + 1)
-    lam = inputs.alpha_circulant_shifts(S, 0.01)
-    V, Vinv = inputs.alpha_circulant_vectors(S, 0.01)
-    b = inputs.rhs(S, n, n)
-    F_host = (V @ b.reshape(S, -1)).reshape(S, n, n)
-    dev = torch.device("cuda:0")
-    Vd = torch.from_numpy(V).to(dev).contiguous()
-    Vinvd = torch.from_numpy(Vinv).to(dev).contiguous()
-    Fd = torch.from_numpy(np.ascontiguousarray(F_host).ravel()).to(dev)
-    Ud = torch.empty_like(Fd)
-    del F_host
 
     if args.copy_calibration:
-        src = torch.ones(1 << 27, dtype=torch.float64, device=dev)
+        src = torch.ones(1 << 27, dtype=torch.float64, device="cuda:0")
         dst = torch.empty_like(src)
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
 
-    solver = VankaMG([Grid(n, num_systems=S)], lam)
-    schedule = solver.autotune() if not args.no_autotune else [solver.schedule(0)]
-    for _ in range(args.warmup):
-        solver.paradiag_apply(Vd, Vinvd, Fd, tol=tol, out=Ud)
-    # the timed steps record HIP events around the dominant kernel only (the
-    # roofline's durations), leaving the rest of the step unperturbed
-    solver.set_timing(True, reset=True, classes=["edge"])
-    dt, status = run_steps(solver, Vd, Vinvd, Fd, Ud, args.steps, tol, torch)
-    edge_levels = solver.level_stats("edge")
-    solver.set_timing(False, reset=False)
-    iters, relres = solver.last_stats()
-    if status != 0 or not np.all(relres <= tol):
-        raise SystemExit(f"FP64 ParaDIAG step did not converge: status {status}, max relres {relres.max():.3e}")
-    ms_per_step = 1e3 * dt / args.steps
-    value = S * args.steps / dt
-
-    # dominant kernel: the finest-level cycle-edge kernel (HBM bound); it is
-    # the only launch of its instantiation, so HIP-event and rocprofv3
-    # averages cover the same launches
-    _, la, ms, by = edge_levels[0]
-    gbs = by / (ms * 1e-3) / 1e9
-    traffic = None
-    if MEASURED_TRAFFIC["source_sha256_16"] == kernel_source_hash(MEASURED_TRAFFIC["source"]):
-        traffic = MEASURED_TRAFFIC["bytes_per_launch"]
-    roofline = {"bound": "hbm", "kernel": DOMINANT, "achieved": round(gbs, 1),
-                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4),
-                "traffic": traffic, "launches": la, "avg_ms": round(ms / max(la, 1), 5),
-                "algorithmic_bytes_per_launch": round(by / max(la, 1)),
-                "bytes_per_node": "56 (read x, b, e/4; write x_(k+1) pre-smoothed, coarse rhs/4)"}
-    # context: the same GPU's device-to-device copy rate (2 GiB read, 2 GiB
-    # written), and the kernel's measured traffic against it
-    src = torch.empty(1 << 28, dtype=torch.float64, device=dev).fill_(1.0)
-    dst = torch.empty_like(src)
-    dst.copy_(src)
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record()
-    for _ in range(5):
-        dst.copy_(src)
-    e1.record()
-    torch.cuda.synchronize()
-    copy_gbs = 5 * 2 * src.numel() * 8 / (e0.elapsed_time(e1) * 1e-3) / 1e9
-    del src, dst
-    roofline["context"] = {"copy_GB/s": round(copy_gbs, 1)}
-    if traffic:
-        tr_gbs = traffic / (ms / max(la, 1) * 1e-3) / 1e9
-        roofline["context"].update({"traffic_GB/s": round(tr_gbs, 1),
-                                    "traffic_frac_of_copy": round(tr_gbs / copy_gbs, 3)})
-    # per-kernel breakdown: a separate pass with every kernel class timed
-    # (untimed as a whole; its events perturb the step)
-    solver.set_timing(True, reset=True)
-    run_steps(solver, Vd, Vinvd, Fd, Ud, min(args.steps, 3), tol, torch)
-    stats = solver.kernel_stats()
-    solver.set_timing(False, reset=False)
-    levels = {}
-    for k in ("down", "up", "edge"):
-        levels[k] = [{"level": l, "launches": a, "avg_ms": round(m / max(a, 1), 4),
-                      "GB/s": round(b_ / (m * 1e-3) / 1e9, 1) if m > 0 else None}
-                     for l, a, m, b_ in solver.level_stats(k)]
-    tl, tms, tby = stats["transform"]
-    flops = 8.0 * S * S * n * n * tl
-    kernels = {k: {"launches": v[0], "ms": round(v[1], 3),
-                   "GB/s": round(v[2] / (v[1] * 1e-3) / 1e9, 1) if v[1] > 0 else None,
-                   "hbm_frac": round(v[2] / (v[1] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4) if v[1] > 0 else None}
-               for k, v in stats.items() if v[0] > 0}
-    kernels["transform"]["TFLOP/s"] = round(flops / (tms * 1e-3) / 1e12, 2) if tms > 0 else None
-    kernels["transform"]["mfma_frac"] = round(flops / (tms * 1e-3) / 1e12 / FP64_MFMA_PEAK_TFLOPS, 4) if tms else None
-
-    out = {"metric": METRIC, "value": round(value, 2), "unit": "systems/s", "n_gpus": 1, "steps": args.steps,
-           "warmup": args.warmup, "ms_per_step": round(ms_per_step, 3), "higher_is_better": True,
-           "scaling": "weak", "vs_baseline": None, "dtype": "c128", "data": "synthetic",
-           "config": {"workload": f"plain_{n}: {S} alpha-circulant shifts (alpha=0.01, tau=1/{S}) on the "
-                                  f"{n}x{n} unit-square grid, ParaDIAG step (transform, V(2,2) Vanka multigrid "
-                                  f"to {tol:g}, inverse transform)",
-                      "grid": n, "systems": S, "cycle": "V(2,2)", "levels": len(solver.levels()),
-                      "omega": 0.96, "precision": "FP64", "schedule": schedule[0]},
-           "iterations": {"min": int(iters.min()), "max": int(iters.max())},
-           "max_relres": float(relres.max()),
-           "roofline": roofline, "kernels": kernels, "fused_by_level": levels,
-           "kernels_note": "kernels and fused_by_level: a separate pass with every kernel class timed by HIP "
-                           "events; the timed steps time the dominant kernel only"}
-    # context: the same steps without per-kernel events (cycles replayed as
-    # captured graphs), and with the alpha-circulant transforms done as scaled
-    # DFTs (paradiag_apply_circulant) instead of the MFMA GEMMs
-    dtg, _ = run_steps(solver, Vd, Vinvd, Fd, Ud, args.steps, tol, torch)
-    for _ in range(args.warmup):
-        solver.paradiag_apply_circulant(0.01, Fd, tol=tol, out=Ud)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        _, st_c = solver.paradiag_apply_circulant(0.01, Fd, tol=tol, out=Ud)
-    torch.cuda.synchronize()
-    dtc = time.perf_counter() - t0
-    _, rr_c = solver.last_stats()
-    out["uninstrumented"] = {"ms_per_step": round(1e3 * dtg / args.steps, 3),
-                             "value": round(S * args.steps / dtg, 2),
-                             "note": "same steps, cycles replayed as graphs, no per-kernel events"}
-    out["circulant_dft_step"] = {"ms_per_step": round(1e3 * dtc / args.steps, 3),
-                                 "value": round(S * args.steps / dtc, 2),
-                                 "converged": st_c == 0 and bool(np.all(rr_c <= tol)),
-                                 "note": "transforms as scaled length-64 DFTs, uninstrumented"}
-    del solver
-    torch.cuda.empty_cache()
-
-    if not args.no_ir:
-        ir = VankaMG([Grid(n, num_systems=S)], lam, precision="c64_ir")
-        if not args.no_autotune:
-            ir.autotune()
-        for _ in range(args.warmup):
-            ir.paradiag_apply(Vd, Vinvd, Fd, tol=tol, out=Ud)
-        ir.set_timing(True, reset=True, classes=["edge"])
-        dti, st_ir = run_steps(ir, Vd, Vinvd, Fd, Ud, args.steps, tol, torch)
-        ir.set_timing(False, reset=False)
-        it_ir, rr_ir = ir.last_stats()
-        ok = st_ir == 0 and bool(np.all(rr_ir <= tol))
-        out["fp32_ir"] = {"value": round(S * args.steps / dti, 2), "unit": "systems/s",
-                          "ms_per_step": round(1e3 * dti / args.steps, 3),
-                          "speedup_vs_fp64": round(ms_per_step / (1e3 * dti / args.steps), 3),
-                          "refinement_steps": {"min": int(it_ir.min()), "max": int(it_ir.max())},
-                          "max_relres": float(rr_ir.max()), "converged": ok, "dtype": "c64 cycles + c128 refinement"}
-        del ir
-        # FP64 V-cycles whose coarse-grid correction runs in complex64: the
-        # finest level, the stopping test and the result in FP64
-        mx = VankaMG([Grid(n, num_systems=S)], lam, precision="c128_c64")
-        if not args.no_autotune:
-            mx.autotune()
-        for _ in range(args.warmup):
-            mx.paradiag_apply(Vd, Vinvd, Fd, tol=tol, out=Ud)
-        mx.set_timing(True, reset=True, classes=["edge"])
-        dtm, st_m = run_steps(mx, Vd, Vinvd, Fd, Ud, args.steps, tol, torch)
-        mx.set_timing(False, reset=False)
-        it_m, rr_m = mx.last_stats()
-        dtmg, _ = run_steps(mx, Vd, Vinvd, Fd, Ud, args.steps, tol, torch)
-        out["fp32_coarse"] = {"value": round(S * args.steps / dtm, 2), "unit": "systems/s",
-                              "ms_per_step": round(1e3 * dtm / args.steps, 3),
-                              "speedup_vs_fp64": round(ms_per_step / (1e3 * dtm / args.steps), 3),
-                              "uninstrumented_ms_per_step": round(1e3 * dtmg / args.steps, 3),
-                              "uninstrumented_speedup_vs_fp64": round(dtg / dtmg, 3),
-                              "cycles": {"min": int(it_m.min()), "max": int(it_m.max())},
-                              "max_relres": float(rr_m.max()), "converged": st_m == 0 and bool(np.all(rr_m <= tol)),
-                              "dtype": "c128 finest level and stopping test, c64 coarse-grid correction"}
-        del mx
-
-    if not args.no_ir:
-        out["fp32_ir_2047"] = precision_leg(args, torch)
-
-    if not args.no_batched:
+    legs = {"headline", "plain", "small", "batched", "paper", "heat"} if args.legs == "all" else \
+        set(x.strip() for x in args.legs.split(","))
+    out = {"metric": METRIC}
+    copy_gbs = copy_rate(torch)
+    sample = ORACLE_SAMPLE[:max(0, args.cpu_sample)] if not args.no_cpu_baseline else ()
+    if "headline" in legs:
+        head, solutions, (b, lam, h) = paradiag_leg("precision_2047", 2047, 32, 4, args, torch, sample=sample)
+        f64 = head["fp64"]
+        if not f64["converged"]:
+            raise SystemExit(f"FP64 ParaDIAG step did not converge: max relres {f64['max_relres']:.3e}")
+        out.update({"value": f64["value"], "unit": "systems/s", "n_gpus": 1, "steps": args.steps,
+                    "warmup": args.warmup, "ms_per_step": f64["ms_per_step"], "higher_is_better": True,
+                    "scaling": "weak", "vs_baseline": None, "dtype": "c128", "data": "synthetic",
+                    "config": {"workload": head["workload"], "grid": 2047, "systems": 32, "cycle": "V(2,2)",
+                               "levels": f64["levels"], "omega": 0.96, "precision": "FP64",
+                               "schedule": f64["schedule"]},
+                    "iterations": f64["cycles"], "max_relres": f64["max_relres"],
+                    "roofline": roofline_of(head, "precision_2047", copy_gbs),
+                    "fp32_ir": head["fp32_ir"], "fp32_coarse": head["fp32_coarse"],
+                    "fp64_detail": {k: v for k, v in f64.items() if k not in ("value", "ms_per_step")},
+                    "kernels_note": "kernels and fused_by_level: a separate pass with every kernel class timed by "
+                                    "HIP events; the timed steps time the dominant kernel only"})
+    if "plain" in legs:
+        plain, _, _ = paradiag_leg("plain_1023", 1023, 64, 0, args, torch)
+        plain["roofline"] = roofline_of(plain, "plain_1023", copy_gbs)
+        out["plain_1023"] = plain
+    if "small" in legs:
+        out["plain_63"] = small_leg(args, torch)
+        progress("plain_63 done")
+    if "batched" in legs:
         out["batched_uneven"] = batched_leg(args, torch)
-    if not args.no_paper:
+        progress("batched_uneven done")
+    if "paper" in legs:
         out["paper_protocol"] = paper_protocol_leg(args, torch)
-    if not args.no_heat:
+        progress("paper_protocol done")
+    if "heat" in legs:
         out["heat"] = heat_leg(args, torch)
-
-    if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(b, lam, h, tol, args.cpu_sample)
+        progress("heat done")
+    if "headline" in legs and len(sample):
+        out["cpu_baseline"] = cpu_baseline(b, lam, h, args.tol, sample, solutions)
     print(json.dumps(out), flush=True)
 
 

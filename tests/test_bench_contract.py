@@ -22,4 +22,5 @@ def test_traffic_entry_names_an_existing_kernel_source():
     import bench
     assert os.path.exists(os.path.join(ROOT, "paper_2203_11154_amd", "csrc", bench.MEASURED_TRAFFIC["source"]))
     assert len(bench.kernel_source_hash(bench.MEASURED_TRAFFIC["source"])) == 16
-    assert bench.MEASURED_TRAFFIC["bytes_per_launch"] > 0
+    per_workload = bench.MEASURED_TRAFFIC["bytes_per_launch"]
+    assert per_workload and all(v > 0 for v in per_workload.values())

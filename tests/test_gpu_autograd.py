@@ -121,12 +121,14 @@ def test_heat_gradient_closed_form(nx, n):
     np.testing.assert_allclose(theta.grad.cpu().numpy(), g_cf, rtol=1e-6)
 
 
-def test_heat_gradient_finite_differences():
+@pytest.mark.parametrize("nx,n", [(127, 32), (511, 128)])
+def test_heat_gradient_finite_differences(nx, n):
     """Central differences with step 1e-6 on frozen iteration counts (the
     solve is then one fixed linear map of f, so the quadratic loss has no
-    truncation error) against the adjoint gradient."""
+    truncation error) against the adjoint gradient, on a small grid and on
+    the differentiation workload's own 511^2 x 128."""
     from paper_2203_11154_amd.autograd import HeatSolve
-    nx, n, K = 127, 32, 16
+    K = 16
     prob, basis, tdecay, tau = heat_setup(nx, n, K)
     theta_np = inputs.heat_parameters(K)
     theta_star = inputs.heat_parameters(K, seed=inputs.SEED_THETA_STAR)
@@ -143,4 +145,6 @@ def test_heat_gradient_finite_differences():
         lp = float(((HeatSolve.apply(heat_source(theta.detach() + e, basis, tdecay), prob, True).real - ustar) ** 2).sum())
         lm = float(((HeatSolve.apply(heat_source(theta.detach() - e, basis, tdecay), prob, True).real - ustar) ** 2).sum())
         fd = (lp - lm) / (2 * step)
+        print(f"{nx}^2 x {n}: dL/dtheta_{k} adjoint {grad[k]:.10e}, central difference {fd:.10e}, "
+              f"rel. diff {abs(fd - grad[k]) / abs(grad[k]):.2e}")
         assert fd == pytest.approx(grad[k], rel=1e-5, abs=1e-9 * np.abs(grad).max())
