@@ -38,11 +38,13 @@ FP64_MFMA_PEAK_TFLOPS = 78.6
 # FETCH_SIZE and WRITE_SIZE on each workload, each scaled by its reading for a
 # plain 1 GiB copy (profiles/).  Valid only for the kernel source it was
 # measured on: reported as null once that file changes.
-MEASURED_TRAFFIC = {"source": "vmg_stream.hip", "source_sha256_16": "55aa523806855e73",
-                    "bytes_per_launch": {"plain_1023": 4065.1e6}}
+MEASURED_TRAFFIC = {"source": "vmg_stream.hip", "source_sha256_16": "7a175f185a18f108",
+                    "bytes_per_launch": {"precision_2047": 8129.0e6, "plain_1023": 4049.2e6}}
 # finest level across the boundary of two V-cycles: correction + 2 sweeps +
 # stopping-test norm, then the next cycle's 2 sweeps + residual + restriction
-DOMINANT = "k_edge<double, 2, 2, double>"
+# (template arguments: precision, sweeps after and before the boundary, the
+# coarse level's precision, damped Jacobi instead of Vanka)
+DOMINANT = "k_edge<double, 2, 2, double, false>"
 # systems of the headline workload the oracle solves (the cpu baseline and
 # the per-result errors): the smallest and the largest |lambda_j|
 ORACLE_SAMPLE = (0, 16)

@@ -26,9 +26,11 @@ struct LevelView {
 //   (L x)_p = d x_p - s (x_N + x_S + x_E + x_W),  d = 4/h^2 + lambda,  s = 1/h^2
 //   x'_p = x_p + ca r_p + cb (r_N + r_S + r_E + r_W) + cc (r_NE + r_NW + r_SE + r_SW)
 // For the Vanka stencil of eq. (6) with weight omega: ca = omega h^2 a,
-// cb = omega h^2 b / 2, cc = omega h^2 c / 4.  For damped Jacobi: ca = omega/d.
+// cb = omega h^2 b / 2, cc = omega h^2 c / 4, and the ratios alpha = ca / cb,
+// gamma = cc / cb (the streaming kernels' form of the update).  For damped
+// Jacobi: ca = omega/d (cb = cc = alpha = gamma = 0).
 template <typename T> struct Coef {
-    cplx<T> d, ca, cb, cc;
+    cplx<T> d, ca, cb, cc, alpha, gamma;
 };
 
 // One grid's share of a batched launch.  A launch covers up to MAXSEG grids
@@ -56,6 +58,7 @@ template <typename T> struct LevelSeg {
     const cplx<T>* cinvT; // coarsest level: transposed inverses
     double* partial;      // fused norm partial sums, or NULL
     int x_zero;           // the iterate read is zero (not loaded)
+    int jacobi;           // damped Jacobi smoother instead of Vanka
     int nc;               // coarsest level: unknowns per system
     int z0;               // first blockIdx.z of the segment
     int gx, gy;           // blocks of the segment in x and y

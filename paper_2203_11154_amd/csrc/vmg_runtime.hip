@@ -267,10 +267,15 @@ void vanka_coef(cd lam, double h, cd omega, int smoother, Coef<double>& c) {
         cb = omega * h * h * b / 2.0;
         cc = omega * h * h * cc_ / 4.0;
     }
+    // ca / cb = 2a/b = 2(14 + 8 eta + eta^2)/(4 + eta), cc / cb = c/(2b) = 1/(4 + eta)
+    const cd alpha = smoother == 1 ? cd(0.0) : 2.0 * (14.0 + 8.0 * eta + eta * eta) / (4.0 + eta);
+    const cd gamma = smoother == 1 ? cd(0.0) : 1.0 / (4.0 + eta);
     c.d = make_double2(d4.real(), d4.imag());
     c.ca = make_double2(ca.real(), ca.imag());
     c.cb = make_double2(cb.real(), cb.imag());
     c.cc = make_double2(cc.real(), cc.imag());
+    c.alpha = make_double2(alpha.real(), alpha.imag());
+    c.gamma = make_double2(gamma.real(), gamma.imag());
 }
 
 Coef<float> to_float(const Coef<double>& c) {
@@ -279,6 +284,8 @@ Coef<float> to_float(const Coef<double>& c) {
     f.ca = make_float2((float)c.ca.x, (float)c.ca.y);
     f.cb = make_float2((float)c.cb.x, (float)c.cb.y);
     f.cc = make_float2((float)c.cc.x, (float)c.cc.y);
+    f.alpha = make_float2((float)c.alpha.x, (float)c.alpha.y);
+    f.gamma = make_float2((float)c.gamma.x, (float)c.gamma.y);
     return f;
 }
 
@@ -437,6 +444,7 @@ LevelSeg<T> make_seg(vmg_handle* H, Group& g, int conj, int l, const cplx<T>* x,
     S.nc = g.nc;
     S.partial = partial;
     S.x_zero = x_zero;
+    S.jacobi = H->opts.smoother == 1;
     return S;
 }
 

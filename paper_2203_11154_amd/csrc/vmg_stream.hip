@@ -77,13 +77,9 @@ template <typename D, typename S> __device__ __forceinline__ D cvt(S v) {
     }
 }
 // Value of the left (lane - 1) and right (lane + 1) neighbour; the wave's
-// edge lanes receive values of no meaning and are never owned.  With
-// VMG_NEIGHBOR_DPP the move is a DPP wave shift (wave_shr:1 / wave_shl:1, a
-// VALU operand modifier; lane direction checked on gfx950), otherwise a
-// cross-lane permute through the LDS crossbar.
-#ifndef VMG_NEIGHBOR_DPP
-#define VMG_NEIGHBOR_DPP 1
-#endif
+// edge lanes receive values of no meaning and are never owned.  The move is a
+// DPP wave shift (wave_shr:1 / wave_shl:1, a VALU operand modifier; lane
+// direction checked on gfx950).
 template <int CTRL> __device__ __forceinline__ int dpp_move_i(int v) {
     // bound_ctrl set: a lane whose source is off the wave receives 0, so no
     // "old" operand has to be materialised
@@ -100,24 +96,14 @@ template <int CTRL> __device__ __forceinline__ double dpp_move(double v) {
 }
 template <typename C> __device__ __forceinline__ C from_left(C v) {
     C r;
-#if VMG_NEIGHBOR_DPP
     r.x = dpp_move<0x138>(v.x);
     r.y = dpp_move<0x138>(v.y);
-#else
-    r.x = __shfl_up(v.x, 1, 64);
-    r.y = __shfl_up(v.y, 1, 64);
-#endif
     return r;
 }
 template <typename C> __device__ __forceinline__ C from_right(C v) {
     C r;
-#if VMG_NEIGHBOR_DPP
     r.x = dpp_move<0x130>(v.x);
     r.y = dpp_move<0x130>(v.y);
-#else
-    r.x = __shfl_down(v.x, 1, 64);
-    r.y = __shfl_down(v.y, 1, 64);
-#endif
     return r;
 }
 
@@ -137,31 +123,42 @@ __device__ __forceinline__ C residual_row(C xo, C xm, C xn, C bv, C d, T s) {
 }
 
 // Vanka update of a middle row from the residual rows above (ro), at (rm)
-// and below (rn):  x + ca r + cb (edge sum) + cc (corner sum).  The lane
-// shifts commute with the (uniform) coefficients, so the four edge and four
-// corner terms take one neighbour sum:
-//   x + ca rm + cb (ro + rn) + LR(cb rm + cc (ro + rn)).
-// Off the interior (mk = 0) every term but the neighbour sum is zero
-// already (zero iterate and residual there); mk multiplies that sum in the
-// final add, so the update is zero there without a select.
-template <typename T, typename C>
+// and below (rn):  x + ca r + cb (edge sum) + cc (corner sum).  With
+// vs = ro + rn the edge sum is vs + LR(rm) and the corner sum LR(vs); the lane
+// shifts commute with the (uniform) coefficients, so with alpha = ca / cb and
+// gamma = cc / cb (per system and level) the update takes one neighbour sum
+// and three complex multiply-adds:
+//   x + cb (alpha rm + vs + LR(rm + gamma vs)).
+// Off the interior (mk = 0) every term but the neighbour sum is zero already
+// (zero iterate and residual there); mk multiplies that sum, so the update is
+// zero there without a select.  JAC: the damped Jacobi smoother, x + ca r.
+template <typename T, bool JAC, typename C>
 __device__ __forceinline__ C vanka_row(C xc, C ro, C rm, C rn, const Coef<T>& cf, T mk) {
-    const C vs = add(ro, rn);
-    const C w = fma2(mul(cf.cb, rm), cf.cc, vs);
-    C v = fma2(xc, cf.ca, rm);
-    v = fma2(v, cf.cb, vs);
-    const C lr = lr_sum(w);
-    v.x = fmar(mk, lr.x, v.x);
-    v.y = fmar(mk, lr.y, v.y);
-    return v;
+    if constexpr (JAC) {
+        return fma2(xc, cf.ca, rm);
+    } else {
+        const C vs = add(ro, rn);
+        const C t = fma2(rm, cf.gamma, vs);
+        C u = fma2(vs, cf.alpha, rm);
+        const C lr = lr_sum(t);
+        u.x = fmar(mk, lr.x, u.x);
+        u.y = fmar(mk, lr.y, u.y);
+        return fma2(xc, cf.cb, u);
+    }
 }
 
-// Full weighting around a middle row, the same way:
-//   rm/4 + (ro + rn)/8 + LR(rm/8 + (ro + rn)/16).
+// Full weighting around a middle row, the same way: with
+// w = rm/8 + (ro + rn)/16 it is rm/4 + (ro + rn)/8 + LR(w) = 2 w + LR(w).
 template <typename T, typename C> __device__ __forceinline__ C full_weight_row(C ro, C rm, C rn) {
     const C vs = add(ro, rn);
-    const C w = add(scl(rm, (T)0.125), scl(vs, (T)0.0625));
-    return add(add(scl(rm, (T)0.25), scl(vs, (T)0.125)), lr_sum(w));
+    C w;
+    w.x = fmar(vs.x, (T)0.0625, rm.x * (T)0.125);
+    w.y = fmar(vs.y, (T)0.0625, rm.y * (T)0.125);
+    const C lr = lr_sum(w);
+    C r;
+    r.x = fmar((T)2, w.x, lr.x);
+    r.y = fmar((T)2, w.y, lr.y);
+    return r;
 }
 
 __device__ __forceinline__ bool in_rows(int k, int ny) { return k >= 1 && k <= ny; }
@@ -187,16 +184,14 @@ __device__ __forceinline__ void bload(rsrc_t r, unsigned voff, unsigned soff, fl
 }
 // Stores carry the non-temporal hint (iterates written once per pass; the
 // cache keeps the rows that neighbouring waves read again).
-#ifndef VMG_STREAM_STORE_POLICY
-#define VMG_STREAM_STORE_POLICY 2
-#endif
+constexpr int STORE_POLICY = 2;  // non-temporal
 __device__ __forceinline__ void bstore(rsrc_t r, unsigned voff, unsigned soff, double2 v) {
     using V = __attribute__((ext_vector_type(4))) unsigned int;
-    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(V, v), r, (int)voff, (int)soff, VMG_STREAM_STORE_POLICY);
+    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(V, v), r, (int)voff, (int)soff, STORE_POLICY);
 }
 __device__ __forceinline__ void bstore(rsrc_t r, unsigned voff, unsigned soff, float2 v) {
     using V = __attribute__((ext_vector_type(2))) unsigned int;
-    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(V, v), r, (int)voff, (int)soff, VMG_STREAM_STORE_POLICY);
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(V, v), r, (int)voff, (int)soff, STORE_POLICY);
 }
 // row * bytes-per-row, computed where it is used: an opaque scalar multiply
 // keeps the compiler from hoisting every (row + constant) * rx of an unrolled
@@ -239,19 +234,8 @@ __device__ __forceinline__ uint3 xcd_block() {
 // select.  Rows off the interior only occur in the unrolled blocks at the two
 // ends of a block's range ("edge" blocks); the interior blocks run a copy of
 // the step with every row test removed.
-#ifndef VMG_STREAM_PF
-#define VMG_STREAM_PF 2
-#endif
-#ifndef VMG_STREAM_MINWAVES
-#define VMG_STREAM_MINWAVES 0
-#endif
-#if VMG_STREAM_MINWAVES > 0
-#define VMG_STREAM_OCC __attribute__((amdgpu_waves_per_eu(VMG_STREAM_MINWAVES)))
-#else
-#define VMG_STREAM_OCC
-#endif
 constexpr int UNR = 6;
-constexpr int PF = VMG_STREAM_PF;
+constexpr int PF = 2;  // rows of x and b fetched ahead
 static_assert(UNR % 6 == 0 && UNR % (PF + 1) == 0, "ring lengths must divide the unroll");
 template <int L> __host__ __device__ constexpr int slot(int p) { return ((p % L) + L * UNR) % L; }
 
@@ -265,7 +249,7 @@ __device__ __forceinline__ void pin(float2& v) { asm volatile("" : "+v"(v.x), "+
 
 // TC: precision of the coarse level (the restricted residual is rounded to
 // it when the coarse levels run in complex64 under an FP64 finest level).
-template <typename T, int NS, typename TC = T>
+template <typename T, int NS, typename TC = T, bool JAC = false>
 struct DownPipe {
     using C = cplx<T>;
     using CC = cplx<TC>;
@@ -318,7 +302,7 @@ struct DownPipe {
                 if (!in_rows(j - 2 * q - 1, lf.ny)) r = z2<C>();
             R[q][n0] = r;
             if (q < NS) {
-                C v = vanka_row<T>(X[q][n2], R[q][n2], R[q][n1], R[q][n0], cf, mk);
+                C v = vanka_row<T, JAC>(X[q][n2], R[q][n2], R[q][n1], R[q][n0], cf, mk);
                 if constexpr (EDGE)
                     if (!in_rows(j - 2 * q - 2, lf.ny)) v = z2<C>();
                 X[q + 1][n0] = v;
@@ -383,11 +367,11 @@ template <typename Pipe> __device__ __forceinline__ void set_rows(Pipe& p, bool 
 
 // One wave's share of the work: rows k0..k1 of strip `strip` of system
 // `sys` of segment S (the pipeline adds its halo rows itself).
-template <typename T, int NS, typename TC>
+template <typename T, int NS, typename TC, bool JAC>
 __device__ __forceinline__ void down_piece(const LevelSeg<T>& S, int sys, int strip, int k0, int k1, bool rev,
                                            int lane) {
     using C = cplx<T>;
-    using Pipe = DownPipe<T, NS, TC>;
+    using Pipe = DownPipe<T, NS, TC, JAC>;
     constexpr int HALO = Pipe::HALO, OWN = Pipe::OWN;
     Pipe p;
     p.lf = S.lf;
@@ -470,8 +454,8 @@ template <typename T> __device__ __forceinline__ Piece piece_of(const LevelSeg<T
 }
 
 // ---------------------------------------------------------------------------
-template <typename T, int NS, typename TC>
-__global__ __launch_bounds__(NT) VMG_STREAM_OCC void k_down(SegTable<T> tab) {
+template <typename T, int NS, typename TC, bool JAC = false>
+__global__ __launch_bounds__(NT) void k_down(SegTable<T> tab) {
     // the wave index is uniform over the wave; say so, so that everything
     // derived from it (segment, buffer resources, row bounds) lives in SGPRs
     const int gw = (int)xcd_block().x * (NT / 64) + __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
@@ -481,10 +465,10 @@ __global__ __launch_bounds__(NT) VMG_STREAM_OCC void k_down(SegTable<T> tab) {
     if (lw >= S.waves) return;  // whole wave idle; no block barriers in this kernel
     const Piece pc = piece_of(S, lw);
     if (pc.k0 > pc.k1 || !S.active[pc.sys]) return;
-    down_piece<T, NS, TC>(S, pc.sys, pc.strip, pc.k0, pc.k1, pc.rev, lane);
+    down_piece<T, NS, TC, JAC>(S, pc.sys, pc.strip, pc.k0, pc.k1, pc.rev, lane);
 }
 
-template <typename T, int NS, bool NORM, typename TC = T>
+template <typename T, int NS, bool NORM, typename TC = T, bool JAC = false>
 struct UpPipe {
     using C = cplx<T>;
     static constexpr int HALO = NORM ? 2 * NS + 1 : (NS > 0 ? 2 * NS : 1);
@@ -578,7 +562,7 @@ struct UpPipe {
                 break;
             }
             R[q][n0] = r;
-            C v = vanka_row<T>(X[q][n2], R[q][n2], R[q][n1], R[q][n0], cf, mk);
+            C v = vanka_row<T, JAC>(X[q][n2], R[q][n2], R[q][n1], R[q][n0], cf, mk);
             if constexpr (EDGE)
                 if (!in_rows(j - 2 * q - 2, lf.ny)) v = z2<C>();
             X[q + 1][n0] = v;
@@ -608,11 +592,11 @@ struct UpPipe {
 
 // Rows k0..k1 of one strip of one system; returns the lane's share of
 // sum |b - L x|^2 over the owned columns and rows (NORM).
-template <typename T, int NS, bool NORM, typename TC>
+template <typename T, int NS, bool NORM, typename TC, bool JAC>
 __device__ __forceinline__ double up_piece(const LevelSeg<T>& S, int sys, int strip, int k0, int k1, bool rev,
                                            int lane) {
     using C = cplx<T>;
-    using Pipe = UpPipe<T, NS, NORM, TC>;
+    using Pipe = UpPipe<T, NS, NORM, TC, JAC>;
     constexpr int HALO = Pipe::HALO, OWN = Pipe::OWN;
     Pipe p;
     p.lf = S.lf;
@@ -688,8 +672,8 @@ __device__ __forceinline__ double up_piece(const LevelSeg<T>& S, int sys, int st
 // ---------------------------------------------------------------------------
 // With NORM, every wave leaves its run's sum in the segment's partial buffer
 // (slot = the wave's index in the segment, S.pieces * S.strips per system).
-template <typename T, int NS, bool NORM, typename TC>
-__global__ __launch_bounds__(NT) VMG_STREAM_OCC void k_up(SegTable<T> tab) {
+template <typename T, int NS, bool NORM, typename TC, bool JAC = false>
+__global__ __launch_bounds__(NT) void k_up(SegTable<T> tab) {
     // the wave index is uniform over the wave; say so, so that everything
     // derived from it (segment, buffer resources, row bounds) lives in SGPRs
     const int gw = (int)xcd_block().x * (NT / 64) + __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
@@ -700,7 +684,7 @@ __global__ __launch_bounds__(NT) VMG_STREAM_OCC void k_up(SegTable<T> tab) {
     const Piece pc = piece_of(S, lw);
     if (!S.iters && !S.active[pc.sys]) return;  // (the finishing pass runs for every system)
     double acc = 0.0;
-    if (pc.k0 <= pc.k1) acc = up_piece<T, NS, NORM, TC>(S, pc.sys, pc.strip, pc.k0, pc.k1, pc.rev, lane);
+    if (pc.k0 <= pc.k1) acc = up_piece<T, NS, NORM, TC, JAC>(S, pc.sys, pc.strip, pc.k0, pc.k1, pc.rev, lane);
     if (NORM && S.partial) {
         for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
         if (lane == 0) S.partial[pc.slot] = acc;
@@ -719,16 +703,10 @@ __global__ __launch_bounds__(NT) VMG_STREAM_OCC void k_up(SegTable<T> tab) {
 // iterate from them once.  Unrolled by 12 steps: the right-hand side ring
 // needs 2(NA+NB)+1 rows.
 constexpr int UNR_E = 12;
-#ifndef VMG_EDGE_PF
-#define VMG_EDGE_PF 1
-#endif
-#ifndef VMG_EDGE_BLDS
-#define VMG_EDGE_BLDS 1
-#endif
-constexpr int EPF = VMG_EDGE_PF;
+constexpr int EPF = 1;  // rows of x and b fetched ahead
 template <int L> __host__ __device__ constexpr int eslot(int p) { return ((p % L) + L * UNR_E) % L; }
 
-template <typename T, int NA, int NB, typename TC = T>
+template <typename T, int NA, int NB, typename TC = T, bool JAC = false>
 struct EdgePipe {
     using C = cplx<T>;
     using CC = cplx<TC>;
@@ -740,11 +718,7 @@ struct EdgePipe {
     static constexpr int COL0 = 1;
     static_assert(UNR_E % 12 == 0 && UNR_E % (EPF + 1) == 0 && 2 * NS + 1 <= 12, "ring lengths");
     C X[NS + 1][3], R[NS + 1][3];
-#if VMG_EDGE_BLDS
     C* B;               // this lane's column of the wave's 12-row ring in LDS (stride 64)
-#else
-    C B[12];
-#endif
     C xr[EPF + 1], br[EPF + 1];
     C er[3], ei[3];
     rsrc_t xs, bs, es, xos, cbs;
@@ -808,19 +782,11 @@ struct EdgePipe {
         }
         constexpr int n0 = eslot<3>(P), n1 = eslot<3>(P - 1), n2 = eslot<3>(P - 2);
         X[0][n0] = add(xr[eslot<EPF + 1>(P)], e);
-#if VMG_EDGE_BLDS
         B[eslot<12>(P) * 64] = br[eslot<EPF + 1>(P)];
-#else
-        B[eslot<12>(P)] = br[eslot<EPF + 1>(P)];
-#endif
 #pragma unroll
         for (int q = 0; q <= NS; ++q) {
             const int rrow = j - 2 * q - 1;
-#if VMG_EDGE_BLDS
             const C bq = B[eslot<12>(P - 2 * q) * 64];
-#else
-            const C bq = B[eslot<12>(P - 2 * q)];
-#endif
             C r = residual_row<T>(X[q][n2], X[q][n1], X[q][n0], bq, dl, sl);
             if constexpr (EDGE)
                 if (!in_rows(rrow, lf.ny)) r = z2<C>();
@@ -833,7 +799,7 @@ struct EdgePipe {
             R[q][n0] = r;
             pin(R[q][n0]);
             if (q < NS) {
-                C v = vanka_row<T>(X[q][n2], R[q][n2], R[q][n1], R[q][n0], cf, mk);
+                C v = vanka_row<T, JAC>(X[q][n2], R[q][n2], R[q][n1], R[q][n0], cf, mk);
                 if constexpr (EDGE)
                     if (!in_rows(j - 2 * q - 2, lf.ny)) v = z2<C>();
                 X[q + 1][n0] = v;
@@ -861,16 +827,14 @@ struct EdgePipe {
     }
 };
 
-template <typename T, int NA, int NB, typename TC>
+template <typename T, int NA, int NB, typename TC, bool JAC>
 __device__ __forceinline__ double edge_piece(const LevelSeg<T>& S, int sys, int strip, int k0, int k1, bool rev,
                                              int lane, cplx<T>* bring) {
     using C = cplx<T>;
-    using Pipe = EdgePipe<T, NA, NB, TC>;
+    using Pipe = EdgePipe<T, NA, NB, TC, JAC>;
     constexpr int HALO = Pipe::HALO, OWN = Pipe::OWN, NS = Pipe::NS, U = UNR_E;
     Pipe p;
-#if VMG_EDGE_BLDS
     p.B = bring + lane;
-#endif
     p.lf = S.lf;
     p.lc = S.lc;
     const int i = Pipe::COL0 + strip * OWN - HALO + lane;
@@ -903,7 +867,7 @@ __device__ __forceinline__ double edge_piece(const LevelSeg<T>& S, int sys, int 
 #pragma unroll
         for (int w = 0; w < 3; ++w) p.X[q][w] = p.R[q][w] = z2<C>();
 #pragma unroll
-    for (int w = 0; w < 12; ++w) p.B[w * (VMG_EDGE_BLDS ? 64 : 1)] = z2<C>();
+    for (int w = 0; w < 12; ++w) p.B[w * 64] = z2<C>();
     int jbeg = k0 - 2 * NS - 2;
     jbeg -= jbeg & 1;
     const int jend = k1 + 2 * NS + 2;
@@ -923,11 +887,9 @@ __device__ __forceinline__ double edge_piece(const LevelSeg<T>& S, int sys, int 
     return own ? p.acc : 0.0;
 }
 
-template <typename T, int NA, int NB, typename TC>
-__global__ __launch_bounds__(NT) VMG_STREAM_OCC void k_edge(SegTable<T> tab) {
-#if VMG_EDGE_BLDS
+template <typename T, int NA, int NB, typename TC, bool JAC = false>
+__global__ __launch_bounds__(NT) void k_edge(SegTable<T> tab) {
     __shared__ cplx<T> bring[NT / 64][12 * 64];  // right-hand side rows, one ring per wave
-#endif
     const int gw = (int)xcd_block().x * (NT / 64) + __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const int lane = threadIdx.x & 63;
     const LevelSeg<T> S = seg_of_wave(tab, gw);
@@ -937,11 +899,7 @@ __global__ __launch_bounds__(NT) VMG_STREAM_OCC void k_edge(SegTable<T> tab) {
     if (!S.active[pc.sys]) return;
     // (every run walks downward here: the kernel is at its register limit and
     // measured slower with the reflected address arithmetic)
-#if VMG_EDGE_BLDS
-    double acc = edge_piece<T, NA, NB, TC>(S, pc.sys, pc.strip, pc.k0, pc.k1, false, lane, bring[threadIdx.x >> 6]);
-#else
-    double acc = edge_piece<T, NA, NB, TC>(S, pc.sys, pc.strip, pc.k0, pc.k1, false, lane, nullptr);
-#endif
+    double acc = edge_piece<T, NA, NB, TC, JAC>(S, pc.sys, pc.strip, pc.k0, pc.k1, false, lane, bring[threadIdx.x >> 6]);
     if (S.partial) {
         for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
         if (lane == 0) S.partial[pc.slot] = acc;
@@ -1032,7 +990,8 @@ template <typename T, int NS, typename TC> void down_go(SegTable<T> tab, const i
     const void* k = (const void*)&k_down<T, NS, T>;
     const dim3 g = stream_seg_grid(tab, nsys, down_own<NS>(), 1, 4 * NS + 9, rmin, resident_waves(k));
     if (g.x == 0) return;
-    hipLaunchKernelGGL((k_down<T, NS, TC>), g, dim3(NT), 0, st, tab);
+    if (tab.s[0].jacobi) hipLaunchKernelGGL((k_down<T, NS, TC, true>), g, dim3(NT), 0, st, tab);
+    else hipLaunchKernelGGL((k_down<T, NS, TC, false>), g, dim3(NT), 0, st, tab);
 }
 template <typename T, int NS, bool NORM, typename TC>
 void up_go(SegTable<T> tab, const int* nsys, int rmin, hipStream_t st) {
@@ -1040,7 +999,8 @@ void up_go(SegTable<T> tab, const int* nsys, int rmin, hipStream_t st) {
     const dim3 g = stream_seg_grid(tab, nsys, up_own<NS, NORM>(), UpPipe<T, NS, NORM>::COL0, 4 * NS + 7, rmin,
                                    resident_waves(k));
     if (g.x == 0) return;
-    hipLaunchKernelGGL((k_up<T, NS, NORM, TC>), g, dim3(NT), 0, st, tab);
+    if (tab.s[0].jacobi) hipLaunchKernelGGL((k_up<T, NS, NORM, TC, true>), g, dim3(NT), 0, st, tab);
+    else hipLaunchKernelGGL((k_up<T, NS, NORM, TC, false>), g, dim3(NT), 0, st, tab);
 }
 
 template <typename T, int NA, int NB, typename TC>
@@ -1049,7 +1009,8 @@ void edge_go(SegTable<T> tab, const int* nsys, int rmin, hipStream_t st) {
     const void* k = (const void*)&k_edge<T, NA, NB, T>;
     const dim3 g = stream_seg_grid(tab, nsys, Pipe::OWN, Pipe::COL0, 4 * Pipe::NS + 9, rmin, resident_waves(k));
     if (g.x == 0) return;
-    hipLaunchKernelGGL((k_edge<T, NA, NB, TC>), g, dim3(NT), 0, st, tab);
+    if (tab.s[0].jacobi) hipLaunchKernelGGL((k_edge<T, NA, NB, TC, true>), g, dim3(NT), 0, st, tab);
+    else hipLaunchKernelGGL((k_edge<T, NA, NB, TC, false>), g, dim3(NT), 0, st, tab);
 }
 
 template <typename T, int NA, int NB> int edge_tiles_of(int nx, int ny, int nsys, int rmin) {

@@ -170,10 +170,7 @@ __global__ __launch_bounds__(TN) void k_transform(int n, int64_t m, const double
 // walks over tiles of CT*16 grid nodes, so Mx is read once per block and the
 // input is streamed through a double-buffered LDS tile.  Same lane layout and
 // row permutation as k_transform.
-#ifndef VMG_TR_CT
-#define VMG_TR_CT 2
-#endif
-constexpr int RT_CT = VMG_TR_CT;       // 16-node column sub-tiles per tile
+constexpr int RT_CT = 2;               // 16-node column sub-tiles per tile
 constexpr int RT_NODES = 16 * RT_CT;   // nodes per tile
 
 // (two blocks a CU: 4 waves a SIMD for NW = 8)
