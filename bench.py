@@ -39,7 +39,7 @@ FP64_MFMA_PEAK_TFLOPS = 78.6
 # plain 1 GiB copy (profiles/).  Valid only for the kernel source it was
 # measured on: reported as null once that file changes.
 MEASURED_TRAFFIC = {"source": "vmg_stream.hip", "source_sha256_16": "7a175f185a18f108",
-                    "bytes_per_launch": {"precision_2047": 8129.0e6, "plain_1023": 4049.2e6}}
+                    "bytes_per_launch": {"precision_2047": 8129.9e6, "plain_1023": 4047.6e6}}
 # finest level across the boundary of two V-cycles: correction + 2 sweeps +
 # stopping-test norm, then the next cycle's 2 sweeps + residual + restriction
 # (template arguments: precision, sweeps after and before the boundary, the
