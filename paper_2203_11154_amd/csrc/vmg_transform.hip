@@ -43,10 +43,24 @@ __global__ void k_expand(const double2* __restrict__ M, int n, int trans_conj, d
 
 __device__ __forceinline__ int tile_row_perm(int r) { return 2 * ((r & 3) + 4 * (r >> 3)) + ((r >> 2) & 1); }
 
-__device__ __forceinline__ int64_t node_off(const RowLayout& L, int64_t p) {
-    const int64_t r = p / L.nx;
-    return L.off + r * L.pitch + (p - r * L.nx);
-}
+// Element offset of grid node p (< 2^30) in a row layout.  The row index
+// p / nx comes from a reciprocal computed once per thread: for p, nx < 2^30
+// the rounded product is within one of the quotient, and one compare fixes it
+// (a 64-bit integer division would cost tens of VALU instructions a node).
+struct NodeMap {
+    int nx, pitch;
+    int64_t off;
+    double inv;
+    __device__ __forceinline__ explicit NodeMap(const RowLayout& L)
+        : nx(L.nx), pitch(L.pitch), off(L.off), inv(1.0 / (double)L.nx) {}
+    __device__ __forceinline__ int64_t operator()(int64_t p64) const {
+        const int p = (int)p64;
+        int r = (int)((double)p * inv);
+        const int c = p - r * nx;
+        r += (c >= nx ? 1 : 0) - (c < 0 ? 1 : 0);
+        return off + (int64_t)r * pitch + (p - r * nx);
+    }
+};
 
 // One block: real rows [rb*ROWS, +ROWS) x nodes [cb*COLS, +COLS).
 // Wave w owns rows w*32..w*32+31 as 2 x 4 MFMA 16x16 tiles.
@@ -64,6 +78,7 @@ __global__ __launch_bounds__(TN) void k_transform(int n, int64_t m, const double
     __shared__ double sA[ROWS][KC + 1];
     __shared__ double sB[KC][COLS + 1];
     const int n2 = 2 * n;
+    const NodeMap mi(li), mo(lo);
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int row0 = blockIdx.y * ROWS;
     const int64_t col0 = (int64_t)blockIdx.x * COLS;
@@ -92,7 +107,7 @@ __global__ __launch_bounds__(TN) void k_transform(int n, int64_t m, const double
             const int kr = t / COLS, c = t - kr * COLS;
             const int gk = kc / 2 + kr;
             const int64_t p = col0 + c;
-            rb[q] = (gk < n && p < m) ? in[(int64_t)gk * li.row + node_off(li, p)] : make_double2(0.0, 0.0);
+            rb[q] = (gk < n && p < m) ? in[(int64_t)gk * li.row + mi(p)] : make_double2(0.0, 0.0);
         }
     };
     auto stage = [&]() {
@@ -147,7 +162,7 @@ __global__ __launch_bounds__(TN) void k_transform(int n, int64_t m, const double
         for (int b = 0; b < 4; ++b) {
             const int64_t p = col0 + b * 16 + (lane & 15);
             if (p >= m) continue;
-            const int64_t o = node_off(lo, p);
+            const int64_t o = mo(p);
             if (cr < n) {
                 double2 v = make_double2(acc[a][b][0], acc[a][b][1]);
                 double2* q = out + (int64_t)cr * lo.row + o;
@@ -193,23 +208,29 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(4))) vo
 #pragma unroll
     for (int s = 0; s < KS; ++s) av[s] = Mx[(int64_t)arow * n2 + 4 * s + (lane >> 4)];
 
-    // thread t loads complex row t / (RT_NODES / LD), nodes LD * (t % ...) ..
+    // thread t loads complex row t / (RT_NODES / LD), nodes lcol + q LS (q < LD):
+    // for n = 64 consecutive threads read consecutive nodes of a row (LS =
+    // RT_NODES / LD), for smaller n each thread reads LD consecutive nodes
+    // (LS = 1); each measured the faster for its n
+    constexpr bool SPREAD = NW >= 8;
+    constexpr int LS = SPREAD ? RT_NODES / LD : 1;
     const int lrow = threadIdx.x / (RT_NODES / LD);
-    const int lcol = (threadIdx.x % (RT_NODES / LD)) * LD;
+    const int lcol = SPREAD ? threadIdx.x % (RT_NODES / LD) : (threadIdx.x % (RT_NODES / LD)) * LD;
+    const NodeMap mi(li), mo(lo);
     double2 rb[LD];
     auto fetch = [&](int64_t tile) {
         const int64_t c0 = tile * RT_NODES + lcol;
 #pragma unroll
         for (int q = 0; q < LD; ++q) {
-            const int64_t p = c0 + q;
-            rb[q] = p < m ? in[(int64_t)lrow * li.row + node_off(li, p)] : make_double2(0.0, 0.0);
+            const int64_t p = c0 + q * LS;
+            rb[q] = p < m ? in[(int64_t)lrow * li.row + mi(p)] : make_double2(0.0, 0.0);
         }
     };
     auto stage = [&](int buf) {
 #pragma unroll
         for (int q = 0; q < LD; ++q) {
-            sB[buf][2 * lrow][lcol + q] = rb[q].x;
-            sB[buf][2 * lrow + 1][lcol + q] = rb[q].y;
+            sB[buf][2 * lrow][lcol + q * LS] = rb[q].x;
+            sB[buf][2 * lrow + 1][lcol + q * LS] = rb[q].y;
         }
     };
     int64_t tile = blockIdx.x;
@@ -240,7 +261,7 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(4))) vo
         for (int c = 0; c < RT_CT; ++c) {
             const int64_t p = tile * RT_NODES + 16 * c + (lane & 15);
             if (p < m) {
-                const int64_t o = node_off(lo, p);
+                const int64_t o = mo(p);
                 double2 v0 = make_double2(acc[c][0], acc[c][1]);
                 double2 v1 = make_double2(acc[c][2], acc[c][3]);
                 double2* q0 = out + (int64_t)cr * lo.row + o;
@@ -340,6 +361,7 @@ __global__ __launch_bounds__(FT) void k_circ_dft(int logn, int64_t m, int sign, 
     const int n = 1 << logn;
     const int logtn = 11 - logn;  // log2(FT_TILE / n)
     const int tn = 1 << logtn;
+    const NodeMap mi(li), mo(lo);
     for (int j = threadIdx.x; j < n / 2; j += FT) {
         double sv, cv;
         sincospi(2.0 * j / n, &sv, &cv);
@@ -363,7 +385,7 @@ __global__ __launch_bounds__(FT) void k_circ_dft(int logn, int64_t m, int sign, 
             const int e = threadIdx.x + q * FT;
             const int i = e >> logtn, c = e & (tn - 1);
             const int64_t p = t * tn + c;
-            rb[q] = p < m ? in[(int64_t)i * li.row + node_off(li, p)] : make_double2(0.0, 0.0);
+            rb[q] = p < m ? in[(int64_t)i * li.row + mi(p)] : make_double2(0.0, 0.0);
         }
     };
     if (blockIdx.x < ntiles) fetch(blockIdx.x);
@@ -401,7 +423,7 @@ __global__ __launch_bounds__(FT) void k_circ_dft(int logn, int64_t m, int sign, 
                 double2 v = s[e];
                 v.x *= post[k];
                 v.y *= post[k];
-                double2* q = out + (int64_t)k * lo.row + node_off(lo, p);
+                double2* q = out + (int64_t)k * lo.row + mo(p);
                 if (accumulate) {
                     const double2 w = *q;
                     v.x += w.x;
