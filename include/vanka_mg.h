@@ -140,6 +140,22 @@ int vanka_mg_setup(const vmg_grid* grids, int32_t n_grids, const double* shifts,
 int vanka_mg_set_omega(vmg_handle* h, const double* omega);
 
 /*
+ * New shifts lambda_j for the handle's systems (eq. (2)), in place: the
+ * Vanka coefficients of eq. (6) of every (system, level) and the inverses of
+ * the shifted coarsest matrices are recomputed and copied into the buffers
+ * the handle already holds, so nothing is allocated and the captured cycle
+ * graphs stay valid.  Relaxation weights return to opts->omega (call
+ * vanka_mg_set_omega or vanka_mg_optimize_omega again for others).
+ * Synchronises the device first (work already enqueued uses the old shifts).
+ *   shifts  host, one complex value per system (interleaved doubles), in the
+ *           order of vanka_mg_setup.
+ * Returns VMG_OK, VMG_INVALID_ARG (NULL, non-finite value), VMG_SINGULAR (a
+ * shifted coarsest matrix is singular; the previous shifts are kept),
+ * VMG_HIP_ERROR.
+ */
+int vanka_mg_set_shifts(vmg_handle* h, const double* shifts);
+
+/*
  * Local Fourier analysis (Sec. 2.1): for each eta = lambda h^2 the complex
  * relaxation weight omega minimising the smoothing factor of eq. (4),
  * mu = max over the high frequencies of |1 - omega M(theta) L(theta)| (the

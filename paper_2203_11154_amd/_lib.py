@@ -31,7 +31,7 @@ EXPORTED = ["vanka_mg_default_opts", "vanka_mg_setup", "vanka_mg_solve", "paradi
             "vanka_mg_shift_gradient", "paradiag_heat_residual", "paradiag_heat_solve", "paradiag_heat_gmres",
             "paradiag_transform", "paradiag_transform_noalloc", "paradiag_transform_circulant", "paradiag_apply_circulant",
             "vanka_mg_apply_op", "vanka_mg_set_timing", "vanka_mg_set_timing_mask", "vanka_mg_kernel_stats",
-            "vanka_mg_level_stats", "vanka_mg_autotune", "vanka_mg_schedule", "vanka_mg_plan", "vanka_mg_set_omega",
+            "vanka_mg_level_stats", "vanka_mg_autotune", "vanka_mg_schedule", "vanka_mg_plan", "vanka_mg_set_omega", "vanka_mg_set_shifts",
             "vanka_mg_lfa_omega", "vanka_mg_optimize_omega", "vanka_mg_levels", "vanka_mg_last_stats", "vanka_mg_destroy", "vanka_mg_error_string"]
 
 
@@ -84,6 +84,7 @@ def load():
     lib.vanka_mg_levels.argtypes = [vp, i32, pi32, pi32, pi32]
     lib.vanka_mg_autotune.argtypes = [vp, ctypes.c_char_p, vp]
     lib.vanka_mg_set_omega.argtypes = [vp, pdbl]
+    lib.vanka_mg_set_shifts.argtypes = [vp, pdbl]
     lib.vanka_mg_lfa_omega.argtypes = [pdbl, i32, i32, pdbl, pdbl]
     lib.vanka_mg_optimize_omega.argtypes = [vp, i32]
     lib.vanka_mg_schedule.argtypes = [vp, i32, i32, pi32]

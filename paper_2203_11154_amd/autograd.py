@@ -19,14 +19,16 @@ class ShiftedSolve(torch.autograd.Function):
     """z = ShiftedSolve.apply(b, lam, solver, tol): all systems of `solver`.
 
     b: complex128 CUDA tensor holding every system (solver layout).
-    lam: complex128 tensor of the solver's shifts (must equal the shifts the
-    solver was set up with; it carries the gradient with respect to them).
+    lam: complex128 tensor of the shifts, one per system; it carries the
+    gradient with respect to them.  When it differs from the solver's current
+    shifts the solver takes it in place (vanka_mg_set_shifts) before solving.
     """
 
     @staticmethod
     def forward(ctx, b, lam, solver, tol=1e-10):
-        if not np.allclose(lam.detach().cpu().numpy().ravel(), solver.shifts, rtol=0, atol=0):
-            raise ValueError("lam differs from the shifts the solver was set up with")
+        lam_h = lam.detach().cpu().numpy().astype(np.complex128).ravel()
+        if not np.array_equal(lam_h, solver.shifts):
+            solver.set_shifts(lam_h)
         z, _, _, status = solver.solve(b.detach().contiguous().reshape(-1), tol)
         ctx.solver, ctx.tol, ctx.shape = solver, tol, b.shape
         ctx.save_for_backward(z)

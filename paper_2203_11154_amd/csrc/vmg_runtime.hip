@@ -1352,7 +1352,10 @@ int solve_impl(vmg_handle* H, const double* B, double* Z, double tol, int conj, 
 // relaxation weights (interleaved, the grid's systems), or NULL for opts.omega;
 // omega_levels (takes precedence): one per level and system, [level][system].
 // The conj variant (the adjoint systems, shifts conj(lambda)) uses conj(omega).
-int upload_coefficients(vmg_handle* H, Group& G, const double* omega, const double* omega_levels = nullptr) {
+// (new_shifts: the coarsest inverses are recomputed too; they are computed
+// on the first call in any case)
+int upload_coefficients(vmg_handle* H, Group& G, const double* omega, const double* omega_levels = nullptr,
+                        bool new_shifts = false) {
     const vmg_opts& o = H->opts;
     std::vector<Coef<double>> c64((size_t)G.L * G.S);
     std::vector<Coef<float>> c32((size_t)G.L * G.S);
@@ -1380,7 +1383,7 @@ int upload_coefficients(vmg_handle* H, Group& G, const double* omega, const doub
                 c32[(size_t)l * G.S + s] = to_float(c64[(size_t)l * G.S + s]);
             }
         }
-        if (first_time) {
+        if (first_time || new_shifts) {
             for (int s = 0; s < G.S; ++s) {
                 cd lam = H->shifts[G.sys0 + s];
                 if (conj) lam = std::conj(lam);
@@ -1395,10 +1398,12 @@ int upload_coefficients(vmg_handle* H, Group& G, const double* omega, const doub
                     }
             }
             int rc;
-            if ((rc = dev_malloc(H, (void**)&G.coef64[conj], sizeof(Coef<double>) * c64.size()))) return rc;
-            if ((rc = dev_malloc(H, (void**)&G.coef32[conj], sizeof(Coef<float>) * c32.size()))) return rc;
-            if ((rc = dev_malloc(H, (void**)&G.cinv64[conj], sizeof(double2) * inv64.size()))) return rc;
-            if ((rc = dev_malloc(H, (void**)&G.cinv32[conj], sizeof(float2) * inv32.size()))) return rc;
+            if (first_time) {
+                if ((rc = dev_malloc(H, (void**)&G.coef64[conj], sizeof(Coef<double>) * c64.size()))) return rc;
+                if ((rc = dev_malloc(H, (void**)&G.coef32[conj], sizeof(Coef<float>) * c32.size()))) return rc;
+                if ((rc = dev_malloc(H, (void**)&G.cinv64[conj], sizeof(double2) * inv64.size()))) return rc;
+                if ((rc = dev_malloc(H, (void**)&G.cinv32[conj], sizeof(float2) * inv32.size()))) return rc;
+            }
             if (hipMemcpy(G.cinv64[conj], inv64.data(), sizeof(double2) * inv64.size(), hipMemcpyHostToDevice) ||
                 hipMemcpy(G.cinv32[conj], inv32.data(), sizeof(float2) * inv32.size(), hipMemcpyHostToDevice))
                 return VMG_HIP_ERROR;
@@ -1717,6 +1722,25 @@ int vanka_mg_set_omega(vmg_handle* H, const double* omega) {
         if (rc) return rc;
     }
     return VMG_OK;
+}
+
+int vanka_mg_set_shifts(vmg_handle* H, const double* shifts) {
+    if (!H || !shifts) return VMG_INVALID_ARG;
+    for (int s = 0; s < H->S; ++s)
+        if (!std::isfinite(shifts[2 * s]) || !std::isfinite(shifts[2 * s + 1])) return VMG_INVALID_ARG;
+    // work already enqueued reads the current coefficients
+    if (hipDeviceSynchronize() != hipSuccess) return VMG_HIP_ERROR;
+    const std::vector<cd> old = H->shifts;
+    for (int s = 0; s < H->S; ++s) H->shifts[s] = cd(shifts[2 * s], shifts[2 * s + 1]);
+    int rc = VMG_OK;
+    for (auto& g : H->groups)
+        if ((rc = upload_coefficients(H, g, nullptr, nullptr, true))) break;
+    if (rc) {
+        // keep the handle consistent: back to the previous shifts
+        H->shifts = old;
+        for (auto& g : H->groups) (void)upload_coefficients(H, g, nullptr, nullptr, true);
+    }
+    return rc;
 }
 
 int vanka_mg_optimize_omega(vmg_handle* H, int32_t per_level) {

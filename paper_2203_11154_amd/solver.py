@@ -108,6 +108,17 @@ class VankaMG:
         _lib.check(self.lib.vanka_mg_set_omega(self.handle, om.view(np.float64).ctypes.data_as(
             ctypes.POINTER(ctypes.c_double))), "vanka_mg_set_omega")
 
+    def set_shifts(self, lam):
+        """New shifts for the same grids, in place (coefficients and coarsest
+        inverses recomputed into the handle's buffers; weights back to the
+        constructor's omega)."""
+        sh = np.ascontiguousarray(np.asarray(lam, dtype=np.complex128).ravel())
+        if sh.size != self.num_systems:
+            raise ValueError(f"{sh.size} shifts for {self.num_systems} systems")
+        _lib.check(self.lib.vanka_mg_set_shifts(self.handle, sh.view(np.float64).ctypes.data_as(
+            ctypes.POINTER(ctypes.c_double))), "vanka_mg_set_shifts")
+        self.shifts = sh
+
     def optimize_omega(self, per_level=False):
         """Per shift (per_level: and level), the complex omega minimising the
         LFA smoothing factor of the handle's smoother (vanka_mg_optimize_omega)."""

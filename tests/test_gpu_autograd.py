@@ -58,6 +58,71 @@ def test_shifted_solve_gradients():
     assert abs(got - (dre + 1j * dim)) <= 1e-6 * abs(got)
 
 
+@pytest.mark.parametrize("precision", ["c128", "c128_c64"])
+def test_set_shifts_in_place_equals_fresh_setup(precision):
+    """New shifts taken in place (vanka_mg_set_shifts) give bitwise the
+    solves of a handle set up with them, free-running and replayed from the
+    graphs captured under the old shifts; a shift that makes a coarsest
+    matrix singular is refused and the previous shifts stay in force."""
+    from paper_2203_11154_amd import Grid, VankaMG, _lib
+    n, S = 127, 4
+    lam1 = inputs.alpha_circulant_shifts(S)
+    lam2 = inputs.uniform_shifts(S, seed=41)
+    bd = dev(inputs.rhs(S, n, n, seed=40).ravel())
+    s = VankaMG([Grid(n, num_systems=S)], lam1, precision=precision)
+    Z1, it1, _, _ = s.solve(bd, tol=1e-10)
+    Z1, it1, _, _ = s.solve(bd, tol=1e-10, out=Z1)  # (graphs of the old shifts captured)
+    s.set_shifts(lam2)
+    fresh = VankaMG([Grid(n, num_systems=S)], lam2, precision=precision)
+    for _ in range(2):
+        Za, ita, _, _ = s.solve(bd, tol=1e-10)
+        Zb, itb, _, _ = fresh.solve(bd, tol=1e-10)
+        np.testing.assert_array_equal(ita, itb)
+        assert torch.equal(Za, Zb)
+        Za, _, _, _ = s.solve(bd, fixed_iters=itb, stats=False)
+        Zb, _, _, _ = fresh.solve(bd, fixed_iters=itb, stats=False)
+        assert torch.equal(Za, Zb)
+    # back to the first shifts: the first solve again
+    s.set_shifts(lam1)
+    Z3, it3, _, _ = s.solve(bd, tol=1e-10)
+    np.testing.assert_array_equal(it3, it1)
+    assert torch.equal(Z3, Z1)
+    # coarsest grid 1 x 1 with h = 0.5: A_c + lambda = 16 + lambda
+    t = VankaMG([Grid(3, h=0.25, num_systems=1, levels=2)], np.array([1.0 + 1j]))
+    b3 = dev(inputs.rhs(1, 3, 3, seed=42).ravel())
+    Zt, _, _, _ = t.solve(b3, tol=1e-12)
+    with pytest.raises(_lib.VankaMGError) as e:
+        t.set_shifts(np.array([-16.0 + 0j]))
+    assert e.value.code == _lib.VMG_SINGULAR
+    Zt2, _, _, _ = t.solve(b3, tol=1e-12)
+    assert torch.equal(Zt, Zt2)
+
+
+def test_shift_gradient_steps_through_new_shifts():
+    """ShiftedSolve with shifts that change between calls: the solver takes
+    each new lambda in place, and value and gradient equal those of a solver
+    set up with that lambda."""
+    from paper_2203_11154_amd import Grid, VankaMG
+    from paper_2203_11154_amd.autograd import ShiftedSolve
+    n, S = 63, 3
+    lam = inputs.alpha_circulant_shifts(S)
+    b = dev(inputs.rhs(S, n, n, seed=43).ravel())
+    y = dev(inputs.rhs(S, n, n, seed=44).ravel())
+    solver = VankaMG([Grid(n, num_systems=S)], lam)
+    lt = dev(lam)
+    for step in range(3):
+        lt = lt.detach().requires_grad_(True)
+        loss = ((ShiftedSolve.apply(b, lt, solver, 1e-12) - y).abs() ** 2).sum()
+        loss.backward()
+        ref = VankaMG([Grid(n, num_systems=S)], host(lt))
+        lr = lt.detach().clone().requires_grad_(True)
+        loss_r = ((ShiftedSolve.apply(b, lr, ref, 1e-12) - y).abs() ** 2).sum()
+        loss_r.backward()
+        assert float(loss) == float(loss_r), step
+        assert torch.equal(lt.grad, lr.grad), step
+        lt = lt - 0.5 * lt.grad / lt.grad.abs().max()
+
+
 def test_paradiag_gradient_matches_adjoint():
     from paper_2203_11154_amd import Grid, VankaMG
     from paper_2203_11154_amd.autograd import ParaDiag
