@@ -118,7 +118,7 @@ def test_shift_gradient_steps_through_new_shifts():
         lr = lt.detach().clone().requires_grad_(True)
         loss_r = ((ShiftedSolve.apply(b, lr, ref, 1e-12) - y).abs() ** 2).sum()
         loss_r.backward()
-        assert float(loss) == float(loss_r), step
+        assert float(loss.detach()) == float(loss_r.detach()), step
         assert torch.equal(lt.grad, lr.grad), step
         lt = lt - 0.5 * lt.grad / lt.grad.abs().max()
 
