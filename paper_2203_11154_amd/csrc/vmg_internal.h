@@ -45,6 +45,17 @@ template <typename T> struct LevelSeg {
     cplx<T>* c;           // coarse right-hand side written (restriction) or
                           // coarse correction read (prolongation)
     cplx<T>* cb;          // cycle-edge kernel: the next coarse right-hand side
+    // refinement boundary (complex64 finest level of FP64 refinement): the
+    // FP64 iterate read and written, the FP64 right-hand side, coefficients
+    // and 1/h^2 of the finest level, and the next step's complex64
+    // right-hand side written
+    LevelView lh;         // (the finest level's FP64 planes)
+    const double2* xh;
+    double2* xho;
+    const double2* bh;
+    const Coef<double>* coefh;
+    double sh;
+    cplx<T>* bno;
     // finishing pass of the streaming correction + post-smoothing kernel (finest
     // level after cycle-edge cycles), else NULL: cycles run per system, the
     // iterate read after an odd count (x after an even one), dense destination
@@ -227,6 +238,14 @@ bool edge_supported(int nu1, int nu2);
 template <typename T>
 void launch_edge(SegTable<T> tab, const int* nsys, int nu1, int nu2, int rmin, hipStream_t st, bool c32 = false);
 template <typename T> int edge_tiles(int nx, int ny, int nsys, int nu1, int nu2, int rmin);
+// The boundary of two refinement steps on a streamed complex64 finest level,
+// in one pass: the last inner cycle's correction and nu2 sweeps (complex64),
+// x' = x + e and the FP64 residual of x' (its norm partials, ir_edge_tiles per
+// system; stored rounded to complex64 as the next step's right-hand side), then
+// the next step's first inner cycle from zero: nu1 sweeps, residual and full
+// weighting.  nu1, nu2 in {1, 2}.
+void launch_ir_edge(SegTable<float> tab, const int* nsys, int nu1, int nu2, int rmin, hipStream_t st);
+int ir_edge_tiles(int nx, int ny, int nsys, int nu1, int nu2, int rmin);
 void stream_prepare();  // device occupancy of the streaming kernels (call outside stream capture)
 template <typename T> void launch_fill_zero(cplx<T>* x, LevelView lv, int nsys, hipStream_t st);
 

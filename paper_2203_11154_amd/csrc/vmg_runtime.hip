@@ -82,6 +82,9 @@ struct Group {
     int tail_lt = -1;        // first level run by the tail kernel (-1: none)
     int edge = -1;           // cycle-edge kernel: -1 untuned (used where possible), 0 off, 1 on
     int edge_c = 0;          // level-1 buffer holding the coarse correction the cycle-edge kernel reads
+    DevBuf rhs_alt;          // refinement with the boundary kernel: the finest complex64 right-hand side
+                             // alternates between lv32[0].b (even steps) and this buffer (odd steps)
+    void* rhs_main = nullptr;  // lv32[0].b's own buffer
     int64_t tail_lds = 0;    // its dynamic LDS bytes
 };
 
@@ -124,6 +127,8 @@ struct vmg_handle {
     int* nanflag = nullptr;
     int stream_rows = 0;       // rows per block of the streaming kernels (0: by level size)
     bool tail_on = true;       // small levels in one workgroup per system (VMG_TAIL=0 turns it off)
+    int ir_edge_mode = 1;      // refinement step boundary in one pass where the finest level streams with the
+                               // cycle-edge kernel (VMG_IR_EDGE=0: the separate update + residual pass)
     int edge_mode = 1;         // finest level across the cycle boundary in one pass: VMG_EDGE=0 off,
                                // 1 (default) on large finest levels or as autotuned, 2 wherever possible
     void* tail_dev[2] = {nullptr, nullptr};  // TailSeg<T> per grid, T of the cycle precision [conj]
@@ -420,6 +425,18 @@ bool use_edge(const vmg_handle* H, const Group& g) {
     return g.edge < 0 && (double)g.nx * g.ny * g.S >= EDGE_MIN_NODES;
 }
 
+// Refinement (complex64 V-cycles in FP64 refinement): the boundary of two
+// steps runs in one pass (k_ir_edge) on grids whose complex64 finest level
+// uses the cycle-edge kernel.
+bool use_ir_edge(const vmg_handle* H, const Group& g) {
+    return H->opts.precision == 1 && H->ir_edge_mode && g.rhs_alt.ptr && use_edge(H, g);
+}
+// Finest-level buffer holding the pre-smoothed complex64 iterate at the start
+// of refinement step c >= 1 with the boundary kernel: step 0 flips it
+// ir_inner + 1 times (the first pre-smoothing, the ir_inner - 1 cycle-edge
+// passes, the boundary pass), every later step ir_inner times.
+int ir_level0_parity(const vmg_opts& o, int64_t c) { return (int)((1 + c * o.ir_inner) & 1); }
+
 int sched_rows(const vmg_handle* H, const Group& g, int l) {
     if ((int)g.sched.size() > l && g.sched[l] > 0) return g.sched[l];
     return stream_rows_for(H, cycle_view(H, g, l));
@@ -618,13 +635,25 @@ template <> void launch_edge_t<float>(SegTable<float> tab, const int* nsys, int 
 //   fused[g]    set when grid g's norm partials were produced
 //   lmin        first level run (1: the coarse part of a precision-2 cycle,
 //               whose finest level the caller runs in FP64)
+//   l0          per grid, overrides of the finest level's part (NULL: none):
+//               bit 0 = the finest level starts from zero (else it continues
+//               from the previous pass's pre-smoothed iterate, i.e. "first"
+//               for that level only), bit 1 = skip the finest level's
+//               correction pass (the refinement boundary kernel runs it)
 template <typename T>
 void enqueue_batched_vcycle(vmg_handle* H, int conj, hipStream_t st, bool first, bool last,
                             std::vector<std::vector<int>>& cur, const std::vector<double*>& partials,
-                            std::vector<char>& fused, int lmin = 0) {
+                            std::vector<char>& fused, int lmin = 0, const std::vector<char>* l0 = nullptr) {
     const vmg_opts& o = H->opts;
     const double E = sizeof(cplx<T>);
     const int ng = (int)H->groups.size();
+    // per grid: the finest level starts from zero / its correction pass is skipped
+    std::vector<char> first0(ng, first ? 1 : 0), noup0(ng, 0);
+    if (l0)
+        for (int gi = 0; gi < ng; ++gi) {
+            first0[gi] = (*l0)[gi] & 1;
+            noup0[gi] = ((*l0)[gi] >> 1) & 1;
+        }
     int dmax = 0;
     for (auto& g : H->groups) dmax = std::max(dmax, g.L - 1);
     for (int gi = 0; gi < ng; ++gi) fused[gi] = 0;
@@ -640,7 +669,7 @@ void enqueue_batched_vcycle(vmg_handle* H, int conj, hipStream_t st, bool first,
             const int l = level_of(gi, d);
             // with the cycle-edge kernel the finest level's pre-smoothing and
             // restriction were done by the previous cycle (all but the first)
-            if (l == 0 && !first && use_edge(H, H->groups[gi])) continue;
+            if (l == 0 && !first0[gi] && use_edge(H, H->groups[gi])) continue;
             (sched_stream(H, H->groups[gi], l) ? sg : lg).push_back(gi);
         }
         // streamed grids: one fused launch per row-block height
@@ -656,7 +685,7 @@ void enqueue_batched_vcycle(vmg_handle* H, int conj, hipStream_t st, bool first,
                     rest.push_back(gi);
                     continue;
                 }
-                const int xz = (l > 0 || first) ? 1 : 0;
+                const int xz = (l > 0 || first0[gi]) ? 1 : 0;
                 bt.add(make_seg<T>(H, g, conj, l, P<T>(L[l].x[cur[gi][l]]), P<T>(L[l].b), P<T>(L[l].x[1 - cur[gi][l]]),
                                    P<T>(L[l + 1].b), xz, nullptr),
                        g.S, bytes_of(g, l, (xz ? 0.0 : 1.0) + 1.0 + (o.nu1 > 0 ? 1.0 : 0.0) + 0.25));
@@ -671,14 +700,14 @@ void enqueue_batched_vcycle(vmg_handle* H, int conj, hipStream_t st, bool first,
                 const int l = level_of(gi, d);
                 auto& L = levels_of<T>(g);
                 if (o.nu1 > 0) cur[gi][l] ^= 1;
-                else if (l > 0 || first) launch_fill_zero<T>(P<T>(L[l].x[cur[gi][l]]), L[l].v, g.S, st);
+                else if (l > 0 || first0[gi]) launch_fill_zero<T>(P<T>(L[l].x[cur[gi][l]]), L[l].v, g.S, st);
             }
             sg.swap(rest);
         }
         // LDS-path grids: nu1 batched sweeps, then a batched restriction
         if (!lg.empty()) {
             std::vector<int> xz(ng, 0);
-            for (int gi : lg) xz[gi] = (level_of(gi, d) > 0 || first) ? 1 : 0;
+            for (int gi : lg) xz[gi] = (level_of(gi, d) > 0 || first0[gi]) ? 1 : 0;
             for (int it = 0; it < o.nu1; ++it) {
                 for (size_t k0 = 0; k0 < lg.size(); k0 += MAXSEG) {
                     SegBatch<T> bt;
@@ -731,7 +760,7 @@ void enqueue_batched_vcycle(vmg_handle* H, int conj, hipStream_t st, bool first,
             tg.push_back(gi);
             if (lt == 0) {
                 xs.push_back(P<T>(L[0].x[cur[gi][0]]));
-                xzs.push_back(first ? 1 : 0);
+                xzs.push_back(first0[gi] ? 1 : 0);
             } else {
                 cur[gi][lt] = 0;
                 xs.push_back(P<T>(L[lt].x[0]));
@@ -760,6 +789,7 @@ void enqueue_batched_vcycle(vmg_handle* H, int conj, hipStream_t st, bool first,
             if (H->groups[gi].L - 1 < d || level_of(gi, d) >= tail_start(H->groups[gi]) || level_of(gi, d) < lmin)
                 continue;
             const int l = level_of(gi, d);
+            if (l == 0 && noup0[gi]) continue;
             if (l == 0 && !last && use_edge(H, H->groups[gi])) {
                 eg.push_back(gi);
                 continue;
@@ -836,7 +866,7 @@ void enqueue_batched_vcycle(vmg_handle* H, int conj, hipStream_t st, bool first,
                     const int l = level_of(gi, d);
                     auto& L = levels_of<T>(g);
                     // with nu1 = 0 the iterate of a zero start is still zero here
-                    const int xz = (o.nu1 == 0 && (l > 0 || first)) ? 1 : 0;
+                    const int xz = (o.nu1 == 0 && (l > 0 || first0[gi])) ? 1 : 0;
                     bt.add(make_seg<T>(H, g, conj, l, P<T>(L[l].x[cur[gi][l]]), nullptr, P<T>(L[l].x[cur[gi][l]]),
                                        P<T>(L[l + 1].x[cur[gi][l + 1]]), xz, nullptr),
                            g.S, bytes_of(g, l, (xz ? 1.0 : 2.0) + 0.25));
@@ -1010,8 +1040,12 @@ int enqueue_norm_check(vmg_handle* H, hipStream_t st, int mode, double tol, int 
         const int* act = H->active + g.sys0;
         int ntiles = g.ntiles0;
         if (fused[gi]) {
-            // (refinement steps always end with the fused update + residual)
-            ntiles = fine_f64(H->opts) ? norm_tiles(H, g) : g.ntiles0;
+            // (refinement steps always end with the fused update + residual,
+            // or with the step boundary kernel)
+            ntiles = fine_f64(H->opts) ? norm_tiles(H, g)
+                     : use_ir_edge(H, g) ? ir_edge_tiles(g.lv32[0].v.nx, g.lv32[0].v.ny, g.S, H->opts.nu1,
+                                                         H->opts.nu2, sched_rows(H, g, 0))
+                                         : g.ntiles0;
         } else {
             Level& l0 = g.lv64[0];
             Timer t(H, st, VMG_K_NORM, 2.0 * 16.0 * nodes(l0.v) * g.nact);
@@ -1141,12 +1175,32 @@ int enqueue_cycle_all(vmg_handle* H, int conj, hipStream_t st, int64_t cycle, do
         }
     } else {
         std::vector<std::vector<int>> cur(ng);
-        for (size_t gi = 0; gi < ng; ++gi) cur[gi].assign(H->groups[gi].L, 0);
+        std::vector<char> irb(ng, 0);  // grids whose step boundary runs in one pass (k_ir_edge)
+        const int p = (int)(cycle & 1);
+        for (size_t gi = 0; gi < ng; ++gi) {
+            Group& g = H->groups[gi];
+            cur[gi].assign(g.L, 0);
+            irb[gi] = use_ir_edge(H, g) ? 1 : 0;
+            if (irb[gi]) {
+                // this step's right-hand side (the previous boundary pass wrote
+                // it), and the buffer holding the pre-smoothed iterate it left
+                g.lv32[0].b.ptr = p ? g.rhs_alt.ptr : g.rhs_main;
+                if (!first) cur[gi][0] = ir_level0_parity(o, cycle);
+            }
+        }
         if (o.gamma == 1) {
             std::vector<double*> parts(ng, nullptr);
             std::vector<char> dummy(ng, 0);
-            for (int k = 0; k < o.ir_inner; ++k)
-                enqueue_batched_vcycle<float>(H, conj, st, k == 0, k == o.ir_inner - 1, cur, parts, dummy);
+            for (int k = 0; k < o.ir_inner; ++k) {
+                // boundary grids: the first inner cycle's finest pre-smoothing
+                // was done by the previous boundary pass (all steps but the
+                // first), the last one's correction pass is done by the next
+                std::vector<char> l0(ng);
+                for (size_t gi = 0; gi < ng; ++gi)
+                    l0[gi] = irb[gi] ? (char)(((k == 0 && first) ? 1 : 0) | (k == o.ir_inner - 1 ? 2 : 0))
+                                     : (char)(k == 0 ? 1 : 0);
+                enqueue_batched_vcycle<float>(H, conj, st, k == 0, k == o.ir_inner - 1, cur, parts, dummy, 0, &l0);
+            }
         } else {
             for (size_t gi = 0; gi < ng; ++gi) {
                 Group& g = H->groups[gi];
@@ -1155,12 +1209,58 @@ int enqueue_cycle_all(vmg_handle* H, int conj, hipStream_t st, int64_t cycle, do
                 cur[gi] = ctx.cur;
             }
         }
-        // x' = x + e into the other FP64 buffer (refinement k reads buffer
-        // k mod 2), fused with the residual of x' that the stopping test and
-        // the next step's right-hand side need
-        const int p = (int)(cycle & 1);
+        // the step boundary in one pass: the last inner cycle's correction
+        // and post-smoothing, x' = x + e with its FP64 residual (the stopping
+        // test; rounded to complex64 it is the next step's right-hand side),
+        // and the next step's first pre-smoothing and restriction
+        std::vector<int> eg;
+        for (size_t gi = 0; gi < ng; ++gi)
+            if (irb[gi]) eg.push_back((int)gi);
+        while (!eg.empty()) {
+            const int ty = sched_rows(H, H->groups[eg[0]], 0);
+            SegBatch<float> bt;
+            std::vector<int> rest, done;
+            for (int gi : eg) {
+                Group& g = H->groups[gi];
+                if (sched_rows(H, g, 0) != ty || bt.full()) {
+                    rest.push_back(gi);
+                    continue;
+                }
+                auto& L = g.lv32;
+                Level& lh = g.lv64[0];
+                LevelSeg<float> S = make_seg<float>(H, g, conj, 0, P<float>(L[0].x[cur[gi][0]]), P<float>(L[0].b),
+                                                    P<float>(L[0].x[1 - cur[gi][0]]), P<float>(L[1].x[cur[gi][1]]), 0,
+                                                    g.partial);
+                S.cb = P<float>(L[1].b);
+                S.lh = lh.v;
+                S.xh = first ? nullptr : P<double>(lh.x[p]);
+                S.xho = P<double>(lh.x[1 - p]);
+                S.bh = P<double>(lh.b);
+                S.coefh = coef_of<double>(g, conj, 0);
+                S.sh = 1.0 / (lh.h * lh.h);
+                S.bno = static_cast<float2*>(p ? g.rhs_main : g.rhs_alt.ptr);
+                bt.add(S, g.S, (first ? 68.0 : 84.0) * nodes(lh.v) * g.nact);
+                done.push_back(gi);
+            }
+            {
+                Timer t(H, st, VMG_K_IR, bt.bytes, 0);
+                launch_ir_edge(bt.tab, bt.nsys, o.nu1, o.nu2, ty, st);
+            }
+            for (int gi : done) {
+                cur[gi][0] ^= 1;
+                fused[gi] = 1;
+            }
+            eg.swap(rest);
+        }
+        // other grids: x' = x + e into the other FP64 buffer (refinement k
+        // reads buffer k mod 2), fused with the residual of x' that the
+        // stopping test and the next step's right-hand side need
         for (size_t gi = 0; gi < ng; ++gi) {
             Group& g = H->groups[gi];
+            if (irb[gi]) {
+                g.lv32[0].b.ptr = g.rhs_main;
+                continue;
+            }
             Level& l0 = g.lv64[0];
             Level& e0 = g.lv32[0];
             Timer t(H, st, VMG_K_IR, ((first ? 0.0 : 16.0) + 8.0 + 16.0 + 16.0 + 8.0) * nodes(l0.v) * g.nact);
@@ -1619,6 +1719,7 @@ int vanka_mg_setup(const vmg_grid* grids, int32_t n_grids, const double* shifts,
     H->S = total;
     if (const char* e = std::getenv("VMG_TAIL")) H->tail_on = std::atoi(e) != 0;
     if (const char* e = std::getenv("VMG_EDGE")) H->edge_mode = std::max(0, std::min(2, std::atoi(e)));
+    if (const char* e = std::getenv("VMG_IR_EDGE")) H->ir_edge_mode = std::atoi(e) != 0;
     if (const char* e = std::getenv("VMG_STREAM_ROWS")) {
         const int r = std::atoi(e);
         if (r >= 16 && r <= 4096) H->stream_rows = r;
@@ -1664,6 +1765,12 @@ int vanka_mg_setup(const vmg_grid* grids, int32_t n_grids, const double* shifts,
             VMG_TRY(alloc_planes<float>(H, L.x[0], L.v, G.S));
             VMG_TRY(alloc_planes<float>(H, L.x[1], L.v, G.S));
             VMG_TRY(alloc_planes<float>(H, L.b, L.v, G.S));
+        }
+        // refinement: the second finest-level right-hand side of the step
+        // boundary kernel (which reads one step's and writes the next one's)
+        if (o.precision == 1 && o.gamma == 1 && edge_supported(o.nu1, o.nu2) && G.L >= 2) {
+            VMG_TRY(alloc_planes<float>(H, G.rhs_alt, G.lv32[0].v, G.S));
+            G.rhs_main = G.lv32[0].b.ptr;
         }
         G.ntiles0 = residual_tiles(G.lv64[0].v);
         {

@@ -906,6 +906,271 @@ __global__ __launch_bounds__(NT) void k_edge(SegTable<T> tab) {
     }
 }
 
+// ---------------------------------------------------------------------------
+// Boundary of two refinement steps (complex64 V-cycles inside FP64
+// refinement) on the finest level, in one pass.  Inputs: the last inner
+// cycle's pre-smoothed complex64 correction e, its coarse correction, the
+// inner right-hand side r (complex64), the FP64 iterate x and right-hand side
+// b.  Stages, each a row stencil as in the cycle-edge kernel:
+//   e <- e + P e_c, NA sweeps on L e = r           (complex64; ends step k)
+//   x' = x + e, r' = b - L x'                        (FP64; norm partials of r',
+//                                                    the step's stopping test)
+//   u = 0, NB sweeps on L u = r', FW(r' - L u)       (complex64; the first
+//                                                    inner cycle of step k+1)
+// Writes x' (FP64), r' rounded to complex64 (the next step's right-hand
+// side), u (the next cycle's pre-smoothed iterate) and the coarse right-hand
+// side.  The first sweep from zero is the update alone (its residual is r').
+template <int NA, int NB, bool JAC>
+struct IrEdgePipe {
+    using T = float;
+    using C = float2;
+    using D = double2;
+    static constexpr int NS = NA + NB;
+    static constexpr int HALO = 2 * NS + 2;
+    static constexpr int OWN = 64 - 2 * HALO;
+    static constexpr int COL0 = 1;
+    static_assert(2 * NS + 1 <= 12 && 2 * NB + 1 <= 6, "ring lengths");
+    C X[NS + 1][3], R[NS + 1][3];
+    C* B;              // this lane's column of the wave's 12-row ring of r (stride 64)
+    C RP[6];           // ring of r' rows for the sweeps of step k+1
+    C xr[EPF + 1], br[EPF + 1];
+    D xhr[EPF + 1], bhr[EPF + 1];  // FP64 x and b rows fetched ahead
+    D XP[3];           // x' rows
+    C er[3], ei[3];
+    rsrc_t xs, bs, es, xos, cbs, xhs, xhos, bhs, bnos;
+    LevelView lf, lc;
+    Coef<T> cf;
+    C dl;
+    T sl;
+    D dh;              // FP64 d on interior columns, else 0
+    double shl;        // FP64 1/h^2 on interior columns, else 0
+    int k0, k1;
+    bool col_in, odd;
+    T mk, hf;
+    unsigned ox, oe, oo, of, oxh, ooh;
+    unsigned rx, rc, rxh;
+    double acc;
+
+    template <bool EDGE> __device__ __forceinline__ C load_x(int j) const {
+        C v;
+        if constexpr (EDGE) bload(xs, ox + (in_rows(j, lf.ny) ? j * rx : OOB), 0, v);
+        else bload(xs, ox, srow(j, rx), v);
+        return v;
+    }
+    template <bool EDGE> __device__ __forceinline__ C load_b(int j) const {
+        C v;
+        if constexpr (EDGE) bload(bs, ox + (in_rows(j, lf.ny) ? j * rx : OOB), 0, v);
+        else bload(bs, ox, srow(j, rx), v);
+        return v;
+    }
+    template <bool EDGE> __device__ __forceinline__ D load_xh(int j) const {
+        D v;
+        if constexpr (EDGE) bload(xhs, oxh + (in_rows(j, lf.ny) ? j * rxh : OOB), 0, v);
+        else bload(xhs, oxh, srow(j, rxh), v);
+        return v;
+    }
+    template <bool EDGE> __device__ __forceinline__ D load_bh(int j) const {
+        D v;
+        if constexpr (EDGE) bload(bhs, oxh + (in_rows(j, lf.ny) ? j * rxh : OOB), 0, v);
+        else bload(bhs, oxh, srow(j, rxh), v);
+        return v;
+    }
+    template <bool EDGE> __device__ __forceinline__ C load_e(int K) const {
+        C v;
+        if constexpr (EDGE) bload(es, oe + (K >= 0 && K <= lc.ny + 1 ? K * rc : OOB), 0, v);
+        else bload(es, oe, srow(K, rc), v);
+        return v;
+    }
+    __device__ __forceinline__ C interp_x(C v) const {
+        const C rv = from_right(v);
+        C r;
+        r.x = fmar(hf, rv.x - v.x, v.x);
+        r.y = fmar(hf, rv.y - v.y, v.y);
+        return r;
+    }
+    // store of an owned row (rows k0..k1) of a plane with bytes-per-row rb
+    template <bool EDGE, typename V>
+    __device__ __forceinline__ void store_at(rsrc_t r, unsigned off, unsigned rb, int row, V v) const {
+        if constexpr (EDGE) bstore(r, off + (row >= k0 && row <= k1 ? row * rb : OOB), 0, v);
+        else bstore(r, off, srow(row, rb), v);
+    }
+    template <int P, bool EDGE> __device__ __forceinline__ void step(int j) {
+        xr[eslot<EPF + 1>(P + EPF)] = load_x<EDGE>(j + EPF);
+        br[eslot<EPF + 1>(P + EPF)] = load_b<EDGE>(j + EPF - 1);
+        // FP64 x at the row where e ends (j - 2NA), b one row above
+        xhr[eslot<EPF + 1>(P + EPF)] = load_xh<EDGE>(j + EPF - 2 * NA);
+        bhr[eslot<EPF + 1>(P + EPF)] = load_bh<EDGE>(j + EPF - 2 * NA - 1);
+        C e;
+        if constexpr ((P & 1) != 0) {
+            constexpr int lo = eslot<3>((P - 1) / 2), hi = eslot<3>((P + 1) / 2);
+            ei[hi] = interp_x(er[hi]);
+            e = scl(add(ei[lo], ei[hi]), (T)0.5);
+        } else {
+            er[eslot<3>(P / 2 + 2)] = load_e<EDGE>((j >> 1) + 2);
+            e = ei[eslot<3>(P / 2)];
+        }
+        constexpr int n0 = eslot<3>(P), n1 = eslot<3>(P - 1), n2 = eslot<3>(P - 2);
+        X[0][n0] = add(xr[eslot<EPF + 1>(P)], e);
+        B[eslot<12>(P) * 64] = br[eslot<EPF + 1>(P)];
+#pragma unroll
+        for (int q = 0; q <= NS; ++q) {
+            const int rrow = j - 2 * q - 1;
+            C r;
+            if (q == NA) {
+                // x' = x + e at row j - 2NA, then the FP64 residual of x' at row
+                // j - 2NA - 1 (the refinement step's stopping test)
+                const C ev = X[NA][n0];
+                D xp = xhr[eslot<EPF + 1>(P)];
+                xp.x += (double)ev.x;
+                xp.y += (double)ev.y;
+                XP[n0] = xp;
+                store_at<EDGE>(xhos, ooh, rxh, j - 2 * NA, xp);
+                D rh = residual_row<double>(XP[n2], XP[n1], XP[n0], bhr[eslot<EPF + 1>(P)], dh, shl);
+                if constexpr (EDGE)
+                    if (!in_rows(rrow, lf.ny)) rh = z2<D>();
+                if (!EDGE || (rrow >= k0 && rrow <= k1)) acc += rh.x * rh.x + rh.y * rh.y;
+                pin(acc);
+                pin(XP[n0]);
+                r = cvt<C>(rh);
+                RP[eslot<6>(P)] = r;
+                store_at<EDGE>(bnos, oo, rx, rrow, r);
+            } else {
+                const C bq = q < NA ? B[eslot<12>(P - 2 * q) * 64] : RP[eslot<6>(P - 2 * (q - NA))];
+                r = residual_row<T>(X[q][n2], X[q][n1], X[q][n0], bq, dl, sl);
+                if constexpr (EDGE)
+                    if (!in_rows(rrow, lf.ny)) r = z2<C>();
+            }
+            R[q][n0] = r;
+            pin(R[q][n0]);
+            if (q < NS) {
+                // (the first sweep of step k+1 starts from zero)
+                C v = vanka_row<T, JAC>(q == NA ? z2<C>() : X[q][n2], R[q][n2], R[q][n1], R[q][n0], cf, mk);
+                if constexpr (EDGE)
+                    if (!in_rows(j - 2 * q - 2, lf.ny)) v = z2<C>();
+                X[q + 1][n0] = v;
+                pin(X[q + 1][n0]);
+            }
+        }
+        pin(X[0][n0]);
+        store_at<EDGE>(xos, oo, rx, j - 2 * NS, X[NS][n0]);
+        if constexpr ((P & 1) == 0) {
+            const int frow = j - 2 * NS - 2;
+            const C v = full_weight_row<T>(R[NS][n2], R[NS][n1], R[NS][n0]);
+            const int K = frow >> 1;
+            if constexpr (EDGE)
+                bstore(cbs, of + (frow >= k0 && frow <= k1 && frow >= 2 && K <= lc.ny ? K * rc : OOB), 0, v);
+            else bstore(cbs, of, srow(K, rc), v);
+        }
+    }
+    template <bool EDGE> __device__ __forceinline__ void block(int j) {
+#define VMG_E(P)                      \
+    step<P, EDGE>(j + P);             \
+    __builtin_amdgcn_sched_barrier(0);
+        VMG_E(0) VMG_E(1) VMG_E(2) VMG_E(3) VMG_E(4) VMG_E(5)
+        VMG_E(6) VMG_E(7) VMG_E(8) VMG_E(9) VMG_E(10) VMG_E(11)
+#undef VMG_E
+    }
+};
+
+template <int NA, int NB, bool JAC>
+__device__ __forceinline__ double ir_edge_piece(const LevelSeg<float>& S, int sys, int strip, int k0, int k1, int lane,
+                                                float2* bring) {
+    using C = float2;
+    using D = double2;
+    using Pipe = IrEdgePipe<NA, NB, JAC>;
+    constexpr int HALO = Pipe::HALO, OWN = Pipe::OWN, NS = Pipe::NS, U = UNR_E;
+    Pipe p;
+    p.B = bring + lane;
+    p.lf = S.lf;
+    p.lc = S.lc;
+    const int i = Pipe::COL0 + strip * OWN - HALO + lane;
+    p.col_in = i >= 1 && i <= p.lf.nx;
+    p.mk = p.col_in ? 1.0f : 0.0f;
+    p.odd = (i & 1) != 0;
+    p.hf = p.odd ? 0.5f : 0.0f;
+    const bool ecol = i >= 0 && i <= p.lf.nx + 1;
+    const bool own = lane >= HALO && lane < HALO + OWN && p.col_in;
+    const unsigned es = sizeof(C), eh = sizeof(D);
+    p.ox = p.col_in ? i * es : OOB;
+    p.oe = ecol ? (i >> 1) * es : OOB;
+    p.oo = own ? i * es : OOB;
+    p.of = (own && !(i & 1) && (i >> 1) <= p.lc.nx) ? (i >> 1) * es : OOB;
+    p.rx = p.lf.pitch * es;
+    p.rc = p.lc.pitch * es;
+    // the FP64 planes of the finest level have their own pitch (S.lh); x' is
+    // written on owned columns only; with no FP64 iterate yet (x = 0) every
+    // read of it goes through an empty range and returns zero
+    p.oxh = p.col_in ? i * eh : OOB;
+    p.ooh = own ? i * eh : OOB;
+    p.rxh = S.lh.pitch * eh;
+    const int64_t bhase = (int64_t)sys * S.lh.plane;
+    p.xhs = S.xh ? plane_rsrc(S.xh + bhase, S.lh.plane) : plane_rsrc(S.xho + bhase, 0);
+    p.bhs = plane_rsrc(S.bh + bhase, S.lh.plane);
+    p.xhos = plane_rsrc(S.xho + bhase, S.lh.plane);
+    p.k0 = k0;
+    p.k1 = k1;
+    const int64_t base = (int64_t)sys * p.lf.plane;
+    p.xs = plane_rsrc(S.x + base, p.lf.plane);
+    p.bs = plane_rsrc(S.b + base, p.lf.plane);
+    p.es = plane_rsrc(S.c + (int64_t)sys * p.lc.plane, p.lc.plane);
+    p.xos = plane_rsrc(S.xo + base, p.lf.plane);
+    p.cbs = plane_rsrc(S.cb + (int64_t)sys * p.lc.plane, p.lc.plane);
+    p.bnos = plane_rsrc(S.bno + base, p.lf.plane);
+    p.cf = S.coef[sys];
+    p.dl = p.col_in ? p.cf.d : z2<C>();
+    p.sl = p.col_in ? S.s : 0.0f;
+    const Coef<double> ch = S.coefh[sys];
+    p.dh = p.col_in ? ch.d : z2<D>();
+    p.shl = p.col_in ? S.sh : 0.0;
+    p.acc = 0.0;
+#pragma unroll
+    for (int q = 0; q <= NS; ++q)
+#pragma unroll
+        for (int w = 0; w < 3; ++w) p.X[q][w] = p.R[q][w] = z2<C>();
+#pragma unroll
+    for (int w = 0; w < 3; ++w) p.XP[w] = z2<D>();
+#pragma unroll
+    for (int w = 0; w < 6; ++w) p.RP[w] = z2<C>();
+#pragma unroll
+    for (int w = 0; w < 12; ++w) p.B[w * 64] = z2<C>();
+    int jbeg = k0 - 2 * NS - 2;
+    jbeg -= jbeg & 1;
+    const int jend = k1 + 2 * NS + 2;
+    const int jlo = max(k0 + 2 * NS + 2, 2 * NS + 4);
+    const int jhi = min(min(p.lf.ny - U + 1 - EPF, p.lf.ny - U - 1), k1 - U + 1 + 2 * NA);
+    p.ei[0] = p.interp_x(p.template load_e<true>(jbeg >> 1));
+    p.er[1] = p.template load_e<true>((jbeg >> 1) + 1);
+#pragma unroll
+    for (int d = 0; d < EPF; ++d) {
+        p.xr[d] = p.template load_x<true>(jbeg + d);
+        p.br[d] = p.template load_b<true>(jbeg + d - 1);
+        p.xhr[d] = p.template load_xh<true>(jbeg + d - 2 * NA);
+        p.bhr[d] = p.template load_bh<true>(jbeg + d - 2 * NA - 1);
+    }
+    int j = jbeg;
+    for (; j <= jend && j < jlo; j += U) p.template block<true>(j);
+    for (; j <= jhi; j += U) p.template block<false>(j);
+    for (; j <= jend; j += U) p.template block<true>(j);
+    return own ? p.acc : 0.0;
+}
+
+template <int NA, int NB, bool JAC>
+__global__ __launch_bounds__(NT) void k_ir_edge(SegTable<float> tab) {
+    __shared__ float2 bring[NT / 64][12 * 64];  // inner right-hand side rows, one ring per wave
+    const int gw = (int)xcd_block().x * (NT / 64) + __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int lane = threadIdx.x & 63;
+    const LevelSeg<float> S = seg_of_wave(tab, gw);
+    const int lw = gw - S.w0;
+    if (lw >= S.waves) return;
+    const Piece pc = piece_of(S, lw);
+    if (!S.active[pc.sys]) return;
+    double acc = ir_edge_piece<NA, NB, JAC>(S, pc.sys, pc.strip, pc.k0, pc.k1, lane, bring[threadIdx.x >> 6]);
+    if (S.partial) {
+        for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+        if (lane == 0) S.partial[pc.slot] = acc;
+    }
+}
+
 template <typename T>
 __global__ __launch_bounds__(NT) void k_fill_zero(cplx<T>* __restrict__ x, LevelView lv) {
     const int i = blockIdx.x * 64 + (threadIdx.x & 63) + 1;
@@ -1053,6 +1318,38 @@ template <typename T> int edge_tiles(int nx, int ny, int nsys, int nu1, int nu2,
 template int edge_tiles<double>(int, int, int, int, int, int);
 template int edge_tiles<float>(int, int, int, int, int, int);
 
+namespace {
+// (the run geometry follows the Vanka kernel's occupancy for both smoothers,
+// as the norm partial sums are counted with it)
+template <int NA, int NB> void ir_edge_go(SegTable<float> tab, const int* nsys, int rmin, hipStream_t st) {
+    using Pipe = IrEdgePipe<NA, NB, false>;
+    const dim3 g = stream_seg_grid(tab, nsys, Pipe::OWN, Pipe::COL0, 4 * Pipe::NS + 9, rmin,
+                                   resident_waves((const void*)&k_ir_edge<NA, NB, false>));
+    if (g.x == 0) return;
+    if (tab.s[0].jacobi) hipLaunchKernelGGL((k_ir_edge<NA, NB, true>), g, dim3(NT), 0, st, tab);
+    else hipLaunchKernelGGL((k_ir_edge<NA, NB, false>), g, dim3(NT), 0, st, tab);
+}
+template <int NA, int NB> int ir_edge_tiles_of(int nx, int ny, int nsys, int rmin) {
+    using Pipe = IrEdgePipe<NA, NB, false>;
+    const RunGeom g = run_geom(nx, ny, nsys, Pipe::OWN, Pipe::COL0, 4 * Pipe::NS + 9, rmin,
+                               resident_waves((const void*)&k_ir_edge<NA, NB, false>));
+    return g.strips * g.pieces;
+}
+}  // namespace
+
+void launch_ir_edge(SegTable<float> tab, const int* nsys, int nu1, int nu2, int rmin, hipStream_t st) {
+    if (nu2 == 1 && nu1 == 1) ir_edge_go<1, 1>(tab, nsys, rmin, st);
+    else if (nu2 == 1 && nu1 == 2) ir_edge_go<1, 2>(tab, nsys, rmin, st);
+    else if (nu2 == 2 && nu1 == 1) ir_edge_go<2, 1>(tab, nsys, rmin, st);
+    else ir_edge_go<2, 2>(tab, nsys, rmin, st);
+}
+int ir_edge_tiles(int nx, int ny, int nsys, int nu1, int nu2, int rmin) {
+    if (nu2 == 1 && nu1 == 1) return ir_edge_tiles_of<1, 1>(nx, ny, nsys, rmin);
+    if (nu2 == 1 && nu1 == 2) return ir_edge_tiles_of<1, 2>(nx, ny, nsys, rmin);
+    if (nu2 == 2 && nu1 == 1) return ir_edge_tiles_of<2, 1>(nx, ny, nsys, rmin);
+    return ir_edge_tiles_of<2, 2>(nx, ny, nsys, rmin);
+}
+
 template <typename T> int stream_tiles(int nx, int ny, int nsys, int nu, int rmin) {
     const void* k;
     int own;
@@ -1080,6 +1377,8 @@ void stream_prepare() {
     VMG_PREP(double);
     VMG_PREP(float);
 #undef VMG_PREP
+    resident_waves((const void*)&k_ir_edge<1, 1, false>), resident_waves((const void*)&k_ir_edge<1, 2, false>),
+        resident_waves((const void*)&k_ir_edge<2, 1, false>), resident_waves((const void*)&k_ir_edge<2, 2, false>);
 }
 
 int stream_tiles_max(int nx, int ny, int nu) {
