@@ -207,6 +207,10 @@ int launch_circulant(int n, int64_t m, double alpha, int inverse, int conj, cons
 int launch_transform(int n, int64_t m, const double2* M, int trans_conj, const double2* in, RowLayout li,
                      double2* out, RowLayout lo, double2* mbuf, hipStream_t st, int accumulate = 0,
                      double* norm_partial = nullptr, int max_tiles = 0);
+// doubles of the scratch launch_transform expands M into (mbuf): 4 n^2, or
+// more for n whose expanded form is padded to whole MFMA fragments (at most
+// 4 n^2 for n a multiple of 8, and at most 4 * 256^2 for every n <= 256)
+size_t transform_scratch_doubles(int n);
 
 // Fused register-streaming level kernels (vmg_stream.hip), nu in {0, 1, 2},
 // batched over segments like the launchers above:

@@ -2030,7 +2030,7 @@ extern "C" int paradiag_transform(int32_t n, int64_t m, const double* M, int32_t
     const hipStream_t st = (hipStream_t)hip_stream;
     std::lock_guard<std::mutex> lock(g_tscratch_mu);
     TransformScratch* sc = nullptr;
-    int rc = transform_scratch(sizeof(double) * 4 * (size_t)n * n, st, &sc);
+    int rc = transform_scratch(sizeof(double) * transform_scratch_doubles(n), st, &sc);
     if (rc) return rc;
     launch_transform(n, m, reinterpret_cast<const double2*>(M), trans_conj ? 1 : 0,
                      reinterpret_cast<const double2*>(in), dense_rows(m), reinterpret_cast<double2*>(out),
@@ -2066,7 +2066,7 @@ int paradiag_core(vmg_handle* H, const double* V, const double* Vinv, const doub
     const int64_t m = (int64_t)g.nx * g.ny;
     const bool circ = alpha > 0.0;
     if (!circ && !H->mbuf) {
-        int rc = dev_malloc(H, (void**)&H->mbuf, sizeof(double) * 4 * (size_t)n * n);
+        int rc = dev_malloc(H, (void**)&H->mbuf, sizeof(double) * transform_scratch_doubles(n));
         if (rc) return rc;
     }
     if (!H->gbuf) {

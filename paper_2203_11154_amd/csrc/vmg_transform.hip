@@ -23,9 +23,7 @@ typedef double dbl4 __attribute__((ext_vector_type(4)));
 constexpr int TN = 512;        // threads per block, 8 waves
 constexpr int ROWS = 256;      // real output rows per block (32 per wave)
 constexpr int COLS = 64;       // grid nodes per block
-constexpr int KC = 16;         // real K per LDS chunk (8 complex time slices)
-constexpr int A_PER_T = ROWS * KC / TN;          // A-chunk doubles staged per thread
-constexpr int B_PER_T = (KC / 2) * COLS / TN;    // B-chunk complex values per thread
+constexpr int KC = 16;         // real K per chunk (8 complex time slices)
 
 // Mx from M (or M^H when trans_conj), n2 = 2n.
 __global__ void k_expand(const double2* __restrict__ M, int n, int trans_conj, double* __restrict__ Mx) {
@@ -42,6 +40,31 @@ __global__ void k_expand(const double2* __restrict__ M, int n, int trans_conj, d
 }
 
 __device__ __forceinline__ int tile_row_perm(int r) { return 2 * ((r & 3) + 4 * (r >> 3)) + ((r >> 2) & 1); }
+
+// Mx in the order k_transform's waves consume it: for row block rb (32 real
+// rows, one wave), K chunk c (KC real columns) and lane l, the eight values
+//   Mx[32 rb + 16 a + perm(l % 16)][KC c + 4 s + l / 16],  a < 2, s < 4,
+// at ((rb * nch + c) * 64 + l) * 8 + 4 a + s, zero outside the 2n x 2n matrix,
+// so that a lane reads its chunk as 64 contiguous bytes.
+__global__ void k_expand_frag(const double2* __restrict__ M, int n, int trans_conj, int nrb, int nch,
+                              double* __restrict__ Mf) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (int64_t)nrb * nch * 512) return;
+    const int v = (int)(t & 7), l = (int)((t >> 3) & 63);
+    const int64_t q = t >> 9;
+    const int c = (int)(q % nch), rb = (int)(q / nch);
+    const int r = 32 * rb + 16 * (v >> 2) + tile_row_perm(l & 15);
+    const int k = KC * c + 4 * (v & 3) + (l >> 4);
+    double x = 0.0;
+    if (r < 2 * n && k < 2 * n) {
+        const int i = r >> 1, kk = k >> 1;
+        double2 e = trans_conj ? M[(int64_t)kk * n + i] : M[(int64_t)i * n + kk];
+        if (trans_conj) e.y = -e.y;
+        // [[Re, -Im], [Im, Re]] block of complex entry (i, kk)
+        x = (r & 1) ? ((k & 1) ? e.x : e.y) : ((k & 1) ? -e.y : e.x);
+    }
+    Mf[t] = x;
+}
 
 // Element offset of grid node p (< 2^30) in a row layout.  The row index
 // p / nx comes from a reciprocal computed once per thread: for p, nx < 2^30
@@ -70,13 +93,13 @@ struct NodeMap {
 // Feeding MFMA row r from real row perm(r) = 2((r%4) + 4(r/8)) + (r/4)%2
 // makes those four values (re, im) of complex rows g and g+4 of the tile's
 // eight complex rows, so each lane stores two whole double2 results.
-// The next K chunk is fetched into registers while the current one is
-// multiplied out of LDS.
-__global__ __launch_bounds__(TN) void k_transform(int n, int64_t m, const double* __restrict__ Mx,
-                                                  const double2* __restrict__ in, RowLayout li,
-                                                  double2* __restrict__ out, RowLayout lo, int accumulate) {
-    __shared__ double sA[ROWS][KC + 1];
-    __shared__ double sB[KC][COLS + 1];
+// Each wave reads its own rows of Mx (fragment order, k_expand_frag) straight
+// into registers, a chunk ahead; the input chunk all waves share goes
+// through a double-buffered LDS tile (one barrier a chunk).  Two blocks a CU.
+__global__ __launch_bounds__(TN) __attribute__((amdgpu_waves_per_eu(4))) void k_transform(
+    int n, int64_t m, const double* __restrict__ Mf, int nch, const double2* __restrict__ in, RowLayout li,
+    double2* __restrict__ out, RowLayout lo, int accumulate) {
+    __shared__ double sB[2][KC][COLS + 1];
     const int n2 = 2 * n;
     const NodeMap mi(li), mo(lo);
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -84,73 +107,64 @@ __global__ __launch_bounds__(TN) void k_transform(int n, int64_t m, const double
     const int64_t col0 = (int64_t)blockIdx.x * COLS;
     const int wrow = row0 + wave * 32;
     const bool wave_active = wrow < n2;
-    const int arow = tile_row_perm(lane & 15);
+    const double2* af = reinterpret_cast<const double2*>(Mf + ((int64_t)(wrow >> 5) * nch * 64 + lane) * 8);
     dbl4 acc[2][4];
 #pragma unroll
     for (int a = 0; a < 2; ++a)
 #pragma unroll
         for (int b = 0; b < 4; ++b) acc[a][b] = dbl4{0.0, 0.0, 0.0, 0.0};
 
-    double ra[A_PER_T];
-    double2 rb[B_PER_T];
-    auto fetch = [&](int kc) {
-#pragma unroll
-        for (int q = 0; q < A_PER_T; ++q) {
-            const int t = threadIdx.x + q * TN;
-            const int r = t / KC, k = t - r * KC;
-            const int gr = row0 + r, gk = kc + k;
-            ra[q] = (gr < n2 && gk < n2) ? Mx[(int64_t)gr * n2 + gk] : 0.0;
-        }
-#pragma unroll
-        for (int q = 0; q < B_PER_T; ++q) {
-            const int t = threadIdx.x + q * TN;
-            const int kr = t / COLS, c = t - kr * COLS;
-            const int gk = kc / 2 + kr;
-            const int64_t p = col0 + c;
-            rb[q] = (gk < n && p < m) ? in[(int64_t)gk * li.row + mi(p)] : make_double2(0.0, 0.0);
-        }
+    // input chunk: complex row kr = t / COLS of the chunk, node t % COLS
+    const int kr = threadIdx.x / COLS, kcol = threadIdx.x % COLS;
+    const int64_t p = col0 + kcol;
+    const int64_t poff = p < m ? mi(p) : 0;
+    double2 rb;
+    auto fetch_b = [&](int c) {
+        const int gk = c * (KC / 2) + kr;
+        rb = (gk < n && p < m) ? in[(int64_t)gk * li.row + poff] : make_double2(0.0, 0.0);
     };
-    auto stage = [&]() {
-#pragma unroll
-        for (int q = 0; q < A_PER_T; ++q) {
-            const int t = threadIdx.x + q * TN;
-            const int r = t / KC, k = t - r * KC;
-            sA[r][k] = ra[q];
-        }
-#pragma unroll
-        for (int q = 0; q < B_PER_T; ++q) {
-            const int t = threadIdx.x + q * TN;
-            const int kr = t / COLS, c = t - kr * COLS;
-            sB[2 * kr][c] = rb[q].x;
-            sB[2 * kr + 1][c] = rb[q].y;
-        }
+    auto stage = [&](int buf) {
+        sB[buf][2 * kr][kcol] = rb.x;
+        sB[buf][2 * kr + 1][kcol] = rb.y;
     };
-
-    fetch(0);
-    stage();
+    double2 ac[4], an[4];  // this chunk's and the next chunk's A fragments
+    auto fetch_a = [&](int c, double2* dst) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) dst[q] = af[(int64_t)c * 256 + q];
+    };
+    if (wave_active) fetch_a(0, ac);
+    fetch_b(0);
+    stage(0);
     __syncthreads();
-    for (int kc = 0; kc < n2; kc += KC) {
-        const bool more = kc + KC < n2;
-        if (more) fetch(kc + KC);
+    int buf = 0;
+    for (int c = 0; c < nch; ++c) {
+        const bool more = c + 1 < nch;
+        if (more) {
+            fetch_b(c + 1);
+            if (wave_active) fetch_a(c + 1, an);
+        }
         if (wave_active) {
 #pragma unroll
-            for (int ks = 0; ks < KC; ks += 4) {
-                double av[2], bv[4];
+            for (int ks = 0; ks < 4; ++ks) {
+                double bv[4];
 #pragma unroll
-                for (int a = 0; a < 2; ++a) av[a] = sA[wave * 32 + a * 16 + arow][ks + (lane >> 4)];
+                for (int b = 0; b < 4; ++b) bv[b] = sB[buf][4 * ks + (lane >> 4)][b * 16 + (lane & 15)];
 #pragma unroll
-                for (int b = 0; b < 4; ++b) bv[b] = sB[ks + (lane >> 4)][b * 16 + (lane & 15)];
-#pragma unroll
-                for (int a = 0; a < 2; ++a)
+                for (int a = 0; a < 2; ++a) {
+                    // value 4a + ks of the lane's fragment
+                    const double av = (ks & 1) ? ac[2 * a + (ks >> 1)].y : ac[2 * a + (ks >> 1)].x;
 #pragma unroll
                     for (int b = 0; b < 4; ++b)
-                        acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], bv[b], acc[a][b], 0, 0, 0);
+                        acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv[b], acc[a][b], 0, 0, 0);
+                }
             }
         }
-        __syncthreads();
         if (more) {
-            stage();
+            stage(buf ^ 1);
             __syncthreads();
+            buf ^= 1;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) ac[q] = an[q];
         }
     }
     if (!wave_active) return;
@@ -160,9 +174,9 @@ __global__ __launch_bounds__(TN) void k_transform(int n, int64_t m, const double
         const int cr = (wrow + a * 16) / 2 + (lane >> 4);
 #pragma unroll
         for (int b = 0; b < 4; ++b) {
-            const int64_t p = col0 + b * 16 + (lane & 15);
-            if (p >= m) continue;
-            const int64_t o = mo(p);
+            const int64_t po = col0 + b * 16 + (lane & 15);
+            if (po >= m) continue;
+            const int64_t o = mo(po);
             if (cr < n) {
                 double2 v = make_double2(acc[a][b][0], acc[a][b][1]);
                 double2* q = out + (int64_t)cr * lo.row + o;
@@ -489,20 +503,33 @@ int launch_circulant(int n, int64_t m, double alpha, int inverse, int conj, cons
     return 0;
 }
 
+bool transform_reg(int n) { return n == 8 || n == 16 || n == 32 || n == 64; }
+
+size_t transform_scratch_doubles(int n) {
+    if (transform_reg(n)) return 4 * (size_t)n * n;
+    const size_t nrb = (2 * (size_t)n + 31) / 32, nch = (2 * (size_t)n + KC - 1) / KC;
+    return std::max(4 * (size_t)n * n, nrb * nch * 512);
+}
+
 int launch_transform(int n, int64_t m, const double2* M, int trans_conj, const double2* in, RowLayout li,
                      double2* out, RowLayout lo, double2* mbuf, hipStream_t st, int accumulate, double* norm_partial,
                      int max_tiles) {
     double* Mx = reinterpret_cast<double*>(mbuf);
-    hipLaunchKernelGGL(k_expand, dim3((n * n + 255) / 256), dim3(256), 0, st, M, n, trans_conj, Mx);
-    switch (n) {
-        case 8: return go_reg<1>(m, Mx, in, li, out, lo, accumulate, st, norm_partial, max_tiles);
-        case 16: return go_reg<2>(m, Mx, in, li, out, lo, accumulate, st, norm_partial, max_tiles);
-        case 32: return go_reg<4>(m, Mx, in, li, out, lo, accumulate, st, norm_partial, max_tiles);
-        case 64: return go_reg<8>(m, Mx, in, li, out, lo, accumulate, st, norm_partial, max_tiles);
-        default: break;
+    if (transform_reg(n)) {
+        hipLaunchKernelGGL(k_expand, dim3((n * n + 255) / 256), dim3(256), 0, st, M, n, trans_conj, Mx);
+        switch (n) {
+            case 8: return go_reg<1>(m, Mx, in, li, out, lo, accumulate, st, norm_partial, max_tiles);
+            case 16: return go_reg<2>(m, Mx, in, li, out, lo, accumulate, st, norm_partial, max_tiles);
+            case 32: return go_reg<4>(m, Mx, in, li, out, lo, accumulate, st, norm_partial, max_tiles);
+            default: return go_reg<8>(m, Mx, in, li, out, lo, accumulate, st, norm_partial, max_tiles);
+        }
     }
+    const int nrb = (2 * n + 31) / 32, nch = (2 * n + KC - 1) / KC;
+    const int64_t frag = (int64_t)nrb * nch * 512;
+    hipLaunchKernelGGL(k_expand_frag, dim3((unsigned)((frag + 255) / 256)), dim3(256), 0, st, M, n, trans_conj, nrb,
+                       nch, Mx);
     const dim3 grid((unsigned)((m + COLS - 1) / COLS), (unsigned)((2 * n + ROWS - 1) / ROWS));
-    hipLaunchKernelGGL(k_transform, grid, dim3(TN), 0, st, n, m, Mx, in, li, out, lo, accumulate);
+    hipLaunchKernelGGL(k_transform, grid, dim3(TN), 0, st, n, m, Mx, nch, in, li, out, lo, accumulate);
     return 0;
 }
 
