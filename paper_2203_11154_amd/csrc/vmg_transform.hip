@@ -198,7 +198,10 @@ __global__ __launch_bounds__(TN) __attribute__((amdgpu_waves_per_eu(4))) void k_
 // rows 16w..16w+15 for every K, KS = 2n/4 MFMA steps, n VGPRs a lane) and
 // walks over tiles of CT*16 grid nodes, so Mx is read once per block and the
 // input is streamed through a double-buffered LDS tile.  Same lane layout and
-// row permutation as k_transform.
+// row permutation as k_transform.  Tiles never cross a grid row of tx nodes
+// (the shorter row of the two layouts): in a padded plane, whose interior
+// rows start on 128-byte boundaries, a tile then reads or writes whole
+// cache lines only (the last tile of a row is partly empty).
 constexpr int RT_CT = 2;               // 16-node column sub-tiles per tile
 constexpr int RT_NODES = 16 * RT_CT;   // nodes per tile
 
@@ -209,7 +212,7 @@ template <int NW, bool NORM>
 __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(4))) void k_transform_reg(int64_t m, const double* __restrict__ Mx,
                                                             const double2* __restrict__ in, RowLayout li,
                                                             double2* __restrict__ out, RowLayout lo, int accumulate,
-                                                            int64_t ntiles, double* __restrict__ partial) {
+                                                            int tx, int64_t ntiles, double* __restrict__ partial) {
     __shared__ double sN[NORM ? 2 * 64 * NW : 1];
     constexpr int n = 8 * NW, n2 = 2 * n, KS = n2 / 4, TT = 64 * NW;
     // per thread of the tile load: complex rows x nodes = n x RT_NODES values
@@ -232,12 +235,21 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(4))) vo
     const int lcol = SPREAD ? threadIdx.x % (RT_NODES / LD) : (threadIdx.x % (RT_NODES / LD)) * LD;
     const NodeMap mi(li), mo(lo);
     double2 rb[LD];
+    // tile -> node of its first column, and that column within the grid row
+    const int tpr = (tx + RT_NODES - 1) / RT_NODES;
+    auto tile_at = [&](int64_t tile, int64_t& p0, int& col0) {
+        const int64_t r = tile / tpr;
+        col0 = (int)(tile - r * tpr) * RT_NODES;
+        p0 = r * tx + col0;
+    };
     auto fetch = [&](int64_t tile) {
-        const int64_t c0 = tile * RT_NODES + lcol;
+        int64_t p0;
+        int col0;
+        tile_at(tile, p0, col0);
 #pragma unroll
         for (int q = 0; q < LD; ++q) {
-            const int64_t p = c0 + q * LS;
-            rb[q] = p < m ? in[(int64_t)lrow * li.row + mi(p)] : make_double2(0.0, 0.0);
+            const int c = lcol + q * LS;
+            rb[q] = col0 + c < tx ? in[(int64_t)lrow * li.row + mi(p0 + c)] : make_double2(0.0, 0.0);
         }
     };
     auto stage = [&](int buf) {
@@ -271,11 +283,14 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(4))) vo
                                                               acc[c], 0, 0, 0);
         // complex rows of this lane: cr and cr + 4
         const int cr = 8 * wave + (lane >> 4);
+        int64_t p0;
+        int col0;
+        tile_at(tile, p0, col0);
 #pragma unroll
         for (int c = 0; c < RT_CT; ++c) {
-            const int64_t p = tile * RT_NODES + 16 * c + (lane & 15);
-            if (p < m) {
-                const int64_t o = mo(p);
+            const int j = 16 * c + (lane & 15);
+            if (col0 + j < tx) {
+                const int64_t o = mo(p0 + j);
                 double2 v0 = make_double2(acc[c][0], acc[c][1]);
                 double2 v1 = make_double2(acc[c][2], acc[c][3]);
                 double2* q0 = out + (int64_t)cr * lo.row + o;
@@ -331,19 +346,21 @@ template <int NW, bool NORM> int reg_blocks() {
 template <int NW>
 int go_reg(int64_t m, const double* Mx, const double2* in, RowLayout li, double2* out, RowLayout lo, int accumulate,
            hipStream_t st, double* partial, int max_tiles) {
-    const int64_t ntiles = (m + RT_NODES - 1) / RT_NODES;
+    // tiles within grid rows of the shorter layout row (m is a multiple of it)
+    const int tx = std::min(li.nx, lo.nx);
+    const int64_t ntiles = (m / tx) * ((tx + RT_NODES - 1) / RT_NODES);
     if (partial && !accumulate) {
         const int64_t blocks = std::min<int64_t>(ntiles, reg_blocks<NW, true>());
         if (blocks >= 1 && blocks <= max_tiles) {
             hipLaunchKernelGGL((k_transform_reg<NW, true>), dim3((unsigned)blocks), dim3(64 * NW), 0, st, m, Mx, in, li,
-                               out, lo, 0, ntiles, partial);
+                               out, lo, 0, tx, ntiles, partial);
             return (int)blocks;
         }
     }
     const int64_t blocks = std::min<int64_t>(ntiles, reg_blocks<NW, false>());
     if (blocks < 1) return 0;
     hipLaunchKernelGGL((k_transform_reg<NW, false>), dim3((unsigned)blocks), dim3(64 * NW), 0, st, m, Mx, in, li, out,
-                       lo, accumulate, ntiles, nullptr);
+                       lo, accumulate, tx, ntiles, nullptr);
     return 0;
 }
 
