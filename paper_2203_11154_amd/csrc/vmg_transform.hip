@@ -96,15 +96,19 @@ struct NodeMap {
 // Each wave reads its own rows of Mx (fragment order, k_expand_frag) straight
 // into registers, a chunk ahead; the input chunk all waves share goes
 // through a double-buffered LDS tile (one barrier a chunk).  Two blocks a CU.
+// Column blocks lie within grid rows of tx nodes, as in k_transform_reg.
 __global__ __launch_bounds__(TN) __attribute__((amdgpu_waves_per_eu(4))) void k_transform(
-    int n, int64_t m, const double* __restrict__ Mf, int nch, const double2* __restrict__ in, RowLayout li,
+    int n, int tx, const double* __restrict__ Mf, int nch, const double2* __restrict__ in, RowLayout li,
     double2* __restrict__ out, RowLayout lo, int accumulate) {
     __shared__ double sB[2][KC][COLS + 1];
     const int n2 = 2 * n;
     const NodeMap mi(li), mo(lo);
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int row0 = blockIdx.y * ROWS;
-    const int64_t col0 = (int64_t)blockIdx.x * COLS;
+    const int tpr = (tx + COLS - 1) / COLS;
+    const int grow = blockIdx.x / tpr;
+    const int gcol0 = (blockIdx.x - grow * tpr) * COLS;  // first column of the block in its grid row
+    const int64_t col0 = (int64_t)grow * tx + gcol0;     // its node
     const int wrow = row0 + wave * 32;
     const bool wave_active = wrow < n2;
     const double2* af = reinterpret_cast<const double2*>(Mf + ((int64_t)(wrow >> 5) * nch * 64 + lane) * 8);
@@ -116,12 +120,12 @@ __global__ __launch_bounds__(TN) __attribute__((amdgpu_waves_per_eu(4))) void k_
 
     // input chunk: complex row kr = t / COLS of the chunk, node t % COLS
     const int kr = threadIdx.x / COLS, kcol = threadIdx.x % COLS;
-    const int64_t p = col0 + kcol;
-    const int64_t poff = p < m ? mi(p) : 0;
+    const bool pin = gcol0 + kcol < tx;
+    const int64_t poff = pin ? mi(col0 + kcol) : 0;
     double2 rb;
     auto fetch_b = [&](int c) {
         const int gk = c * (KC / 2) + kr;
-        rb = (gk < n && p < m) ? in[(int64_t)gk * li.row + poff] : make_double2(0.0, 0.0);
+        rb = (gk < n && pin) ? in[(int64_t)gk * li.row + poff] : make_double2(0.0, 0.0);
     };
     auto stage = [&](int buf) {
         sB[buf][2 * kr][kcol] = rb.x;
@@ -174,9 +178,9 @@ __global__ __launch_bounds__(TN) __attribute__((amdgpu_waves_per_eu(4))) void k_
         const int cr = (wrow + a * 16) / 2 + (lane >> 4);
 #pragma unroll
         for (int b = 0; b < 4; ++b) {
-            const int64_t po = col0 + b * 16 + (lane & 15);
-            if (po >= m) continue;
-            const int64_t o = mo(po);
+            const int j = b * 16 + (lane & 15);
+            if (gcol0 + j >= tx) continue;
+            const int64_t o = mo(col0 + j);
             if (cr < n) {
                 double2 v = make_double2(acc[a][b][0], acc[a][b][1]);
                 double2* q = out + (int64_t)cr * lo.row + o;
@@ -545,8 +549,9 @@ int launch_transform(int n, int64_t m, const double2* M, int trans_conj, const d
     const int64_t frag = (int64_t)nrb * nch * 512;
     hipLaunchKernelGGL(k_expand_frag, dim3((unsigned)((frag + 255) / 256)), dim3(256), 0, st, M, n, trans_conj, nrb,
                        nch, Mx);
-    const dim3 grid((unsigned)((m + COLS - 1) / COLS), (unsigned)((2 * n + ROWS - 1) / ROWS));
-    hipLaunchKernelGGL(k_transform, grid, dim3(TN), 0, st, n, m, Mx, nch, in, li, out, lo, accumulate);
+    const int tx = std::min(li.nx, lo.nx);  // m is a multiple of it
+    const dim3 grid((unsigned)((m / tx) * ((tx + COLS - 1) / COLS)), (unsigned)((2 * n + ROWS - 1) / ROWS));
+    hipLaunchKernelGGL(k_transform, grid, dim3(TN), 0, st, n, tx, Mx, nch, in, li, out, lo, accumulate);
     return 0;
 }
 
