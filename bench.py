@@ -38,8 +38,8 @@ FP64_MFMA_PEAK_TFLOPS = 78.6
 # FETCH_SIZE and WRITE_SIZE on each workload, each scaled by its reading for a
 # plain 1 GiB copy (profiles/).  Valid only for the kernel source it was
 # measured on: reported as null once that file changes.
-MEASURED_TRAFFIC = {"source": "vmg_stream.hip", "source_sha256_16": "7a175f185a18f108",
-                    "bytes_per_launch": {"precision_2047": 8129.9e6, "plain_1023": 4047.6e6}}
+MEASURED_TRAFFIC = {"source": "vmg_stream.hip", "source_sha256_16": "f7c8f47653ac4bad",
+                    "bytes_per_launch": {"precision_2047": 8122.7e6, "plain_1023": 4048.8e6}}
 # finest level across the boundary of two V-cycles: correction + 2 sweeps +
 # stopping-test norm, then the next cycle's 2 sweeps + residual + restriction
 # (template arguments: precision, sweeps after and before the boundary, the
