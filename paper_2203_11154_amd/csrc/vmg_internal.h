@@ -193,6 +193,13 @@ struct RowLayout {
     int pitch;     // elements per stored grid row
     int64_t row;   // elements per matrix row (one system / time slice)
     int64_t off;   // element offset of node 0
+    // input rows only (the GEMM transforms): with sel set, row i sits alt
+    // elements further on when (sel[i] * flips) is odd, and reads as zero
+    // when sel[i] == 0 (a solve's iterates left in their two level-0
+    // buffers, selected by each system's cycle count)
+    const int* sel = nullptr;
+    int64_t alt = 0;
+    int flips = 0;
 };
 // With norm_partial set (and accumulate off), also sum |out|^2 per output
 // row into norm_partial[row * tiles + t] and return the tile count; 0 when

@@ -1315,8 +1315,14 @@ int run_cycle(vmg_handle* H, int conj, hipStream_t st, int64_t cycle, double tol
 // buffer.  With fixed counts and no host outputs nothing waits for the
 // device: all cycles up to the largest count are enqueued (the kernels of a
 // system that has reached its count return at once).
+// in_place (one grid only): where the result would be copied out of the
+// level-0 buffers, leave it there instead and describe it (base pointer and
+// row layout selecting each system's buffer by its cycle count) for a
+// consumer that reads those buffers directly; *in_place stays null where the
+// result was written to Z.
 int solve_impl(vmg_handle* H, const double* B, double* Z, double tol, int conj, const int32_t* fixed,
-               int32_t* iters_out, double* relres_out, hipStream_t st, int bnorm_tiles = 0) {
+               int32_t* iters_out, double* relres_out, hipStream_t st, int bnorm_tiles = 0,
+               const double2** in_place = nullptr, RowLayout* in_place_rows = nullptr) {
     const vmg_opts& o = H->opts;
     const int S = H->S;
     const bool async = fixed && !iters_out && !relres_out;
@@ -1420,11 +1426,26 @@ int solve_impl(vmg_handle* H, const double* B, double* Z, double tol, int conj, 
             const int one = g.S;
             launch_up<double>(one_seg(S), &one, o.nu2, false, sched_rows(H, g, 0), st, c32);
         } else {
-            Timer t(H, st, VMG_K_PACK, 32.0 * nodes(l0.v) * g.S);
             // (refinement: after k steps the FP64 iterate is in buffer k mod 2)
             const int flips = fine_f64(o) ? level0_flips(H, g) : 1;
-            launch_unpack<double>(P<double>(l0.x[0]), P<double>(l0.x[1]), reinterpret_cast<double2*>(Z) + off, l0.v,
-                                  g.S, H->iters + g.sys0, flips, st);
+            if (in_place && H->groups.size() == 1) {
+                RowLayout L;
+                L.nx = l0.v.nx;
+                L.pitch = l0.v.pitch;
+                L.row = l0.v.plane;
+                L.off = l0.v.pitch + 1;
+                L.sel = H->iters + g.sys0;
+                L.flips = flips;
+                // (both buffers sit at the same offset from a 128-byte boundary)
+                L.alt = (int64_t)(reinterpret_cast<intptr_t>(l0.x[1].ptr) - reinterpret_cast<intptr_t>(l0.x[0].ptr)) /
+                        (int64_t)sizeof(double2);
+                *in_place = P<double>(l0.x[0]);
+                *in_place_rows = L;
+            } else {
+                Timer t(H, st, VMG_K_PACK, 32.0 * nodes(l0.v) * g.S);
+                launch_unpack<double>(P<double>(l0.x[0]), P<double>(l0.x[1]), reinterpret_cast<double2*>(Z) + off,
+                                      l0.v, g.S, H->iters + g.sys0, flips, st);
+            }
         }
         off += (int64_t)g.nx * g.ny * g.S;
     }
@@ -2096,17 +2117,25 @@ int paradiag_core(vmg_handle* H, const double* V, const double* Vinv, const doub
                                       st, 0, np, g.partial_cap);
     }
     if (check_hip()) return VMG_HIP_ERROR;
+    // Z: the solve's results, copied to gbuf or (refinement, or levels without
+    // the finishing pass) left in the padded level-0 buffers and read there
+    const double2* zin = nullptr;
+    RowLayout zrows;
     int rc = solve_impl(H, nullptr, reinterpret_cast<double*>(H->gbuf), tol, conj ? 1 : 0, fixed_iters, nullptr,
-                        nullptr, st, btiles);
+                        nullptr, st, btiles, &zin, &zrows);
     if (rc < 0) return rc;
+    if (!zin) {
+        zin = H->gbuf;
+        zrows = dense_rows(m);
+    }
     {
         Timer t(H, st, VMG_K_TRANSFORM, (accumulate ? 48.0 : 32.0) * (double)n * m);
         if (circ)
-            launch_circulant(n, m, alpha, 1, conj, H->gbuf, dense_rows(m), reinterpret_cast<double2*>(U),
-                             dense_rows(m), st, accumulate);
+            launch_circulant(n, m, alpha, 1, conj, zin, zrows, reinterpret_cast<double2*>(U), dense_rows(m), st,
+                             accumulate);
         else
-            launch_transform(n, m, reinterpret_cast<const double2*>(conj ? Vinv : V), conj ? 1 : 0, H->gbuf,
-                             dense_rows(m), reinterpret_cast<double2*>(U), dense_rows(m), H->mbuf, st, accumulate);
+            launch_transform(n, m, reinterpret_cast<const double2*>(conj ? Vinv : V), conj ? 1 : 0, zin, zrows,
+                             reinterpret_cast<double2*>(U), dense_rows(m), H->mbuf, st, accumulate);
     }
     if (check_hip()) return VMG_HIP_ERROR;
     return rc;

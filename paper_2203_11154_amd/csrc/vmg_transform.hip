@@ -85,6 +85,15 @@ struct NodeMap {
     }
 };
 
+// Start of input row k (and whether it holds data): see RowLayout::sel.
+__device__ __forceinline__ bool in_row(const RowLayout& L, int k, int64_t& base) {
+    base = (int64_t)k * L.row;
+    if (!L.sel) return true;
+    const int it = L.sel[k];
+    if ((it * L.flips) & 1) base += L.alt;
+    return it != 0;
+}
+
 // One block: real rows [rb*ROWS, +ROWS) x nodes [cb*COLS, +COLS).
 // Wave w owns rows w*32..w*32+31 as 2 x 4 MFMA 16x16 tiles.
 // v_mfma_f64_16x16x4_f64 lane layout (measured on gfx950): A[i][k] at lane
@@ -125,7 +134,9 @@ __global__ __launch_bounds__(TN) __attribute__((amdgpu_waves_per_eu(4))) void k_
     double2 rb;
     auto fetch_b = [&](int c) {
         const int gk = c * (KC / 2) + kr;
-        rb = (gk < n && pin) ? in[(int64_t)gk * li.row + poff] : make_double2(0.0, 0.0);
+        int64_t base = 0;
+        const bool live = gk < n && pin && in_row(li, gk, base);
+        rb = live ? in[base + poff] : make_double2(0.0, 0.0);
     };
     auto stage = [&](int buf) {
         sB[buf][2 * kr][kcol] = rb.x;
@@ -246,6 +257,8 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(4))) vo
         col0 = (int)(tile - r * tpr) * RT_NODES;
         p0 = r * tx + col0;
     };
+    int64_t rbase;
+    const bool rlive = in_row(li, lrow, rbase);
     auto fetch = [&](int64_t tile) {
         int64_t p0;
         int col0;
@@ -253,7 +266,7 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(4))) vo
 #pragma unroll
         for (int q = 0; q < LD; ++q) {
             const int c = lcol + q * LS;
-            rb[q] = col0 + c < tx ? in[(int64_t)lrow * li.row + mi(p0 + c)] : make_double2(0.0, 0.0);
+            rb[q] = (rlive && col0 + c < tx) ? in[rbase + mi(p0 + c)] : make_double2(0.0, 0.0);
         }
     };
     auto stage = [&](int buf) {
@@ -420,7 +433,9 @@ __global__ __launch_bounds__(FT) void k_circ_dft(int logn, int64_t m, int sign, 
             const int e = threadIdx.x + q * FT;
             const int i = e >> logtn, c = e & (tn - 1);
             const int64_t p = t * tn + c;
-            rb[q] = p < m ? in[(int64_t)i * li.row + mi(p)] : make_double2(0.0, 0.0);
+            int64_t base;
+            const bool live = in_row(li, i, base);
+            rb[q] = (live && p < m) ? in[base + mi(p)] : make_double2(0.0, 0.0);
         }
     };
     if (blockIdx.x < ntiles) fetch(blockIdx.x);
