@@ -211,9 +211,16 @@ bool circulant_supported(int n);
 int launch_circulant(int n, int64_t m, double alpha, int inverse, int conj, const double2* in, RowLayout li,
                      double2* out, RowLayout lo, hipStream_t st, int accumulate = 0, double* norm_partial = nullptr,
                      int max_tiles = 0);
+// o32.p set (with norm_partial): the product rounded to complex64 is also
+// written to o32.p in layout o32.l, where the fused sums are formed (n = 8,
+// 16, 32, 64); a return of 0 means neither was written.
+struct Out32 {
+    float2* p = nullptr;
+    RowLayout l{};
+};
 int launch_transform(int n, int64_t m, const double2* M, int trans_conj, const double2* in, RowLayout li,
                      double2* out, RowLayout lo, double2* mbuf, hipStream_t st, int accumulate = 0,
-                     double* norm_partial = nullptr, int max_tiles = 0);
+                     double* norm_partial = nullptr, int max_tiles = 0, Out32 o32 = Out32{});
 // doubles of the scratch launch_transform expands M into (mbuf): 4 n^2, or
 // more for n whose expanded form is padded to whole MFMA fragments (at most
 // 4 n^2 for n a multiple of 8, and at most 4 * 256^2 for every n <= 256)

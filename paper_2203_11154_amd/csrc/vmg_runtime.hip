@@ -1312,7 +1312,8 @@ int run_cycle(vmg_handle* H, int conj, hipStream_t st, int64_t cycle, double tol
 
 // bnorm_tiles > 0: the producer of the finest right-hand sides (one grid)
 // already left |b|^2 partial sums in that many tiles of the grid's partial
-// buffer.  With fixed counts and no host outputs nothing waits for the
+// buffer (refinement: and the right-hand sides rounded to complex64 in the
+// complex64 finest level).  With fixed counts and no host outputs nothing waits for the
 // device: all cycles up to the largest count are enqueued (the kernels of a
 // system that has reached its count return at once).
 // in_place (one grid only): where the result would be copied out of the
@@ -1371,6 +1372,9 @@ int solve_impl(vmg_handle* H, const double* B, double* Z, double tol, int conj, 
                 launch_residual<double, double>(nullptr, P<double>(l0.b), nullptr, l0.v, l0.v, 1.0,
                                                 coef_of<double>(g, 0, 0), act, g.S, 1, g.partial, st);
             }
+        } else if (bnorm_tiles > 0) {
+            // refinement: the producer also left the complex64 right-hand sides
+            ntiles = bnorm_tiles;
         } else {
             Level& e0 = g.lv32[0];
             Timer t(H, st, VMG_K_IR, 24.0 * nodes(l0.v) * g.S);
@@ -2103,18 +2107,30 @@ int paradiag_core(vmg_handle* H, const double* V, const double* Vinv, const doub
     lb.pitch = l0.v.pitch;
     lb.row = l0.v.plane;
     lb.off = l0.v.pitch + 1;
-    // (FP64 cycles: with the partial sums of ||g_j||^2 for the stopping test)
+    // (FP64 cycles: with the partial sums of ||g_j||^2 for the stopping test;
+    // refinement, GEMM transform: also g rounded to complex64, the first
+    // step's right-hand side, so that no pass forms it from the FP64 g)
     int btiles = 0;
     {
         Timer t(H, st, VMG_K_TRANSFORM, 32.0 * (double)n * m);
-        double* np = fine_f64(H->opts) ? g.partial : nullptr;
+        const bool ir = H->opts.precision == 1 && !circ;
+        double* np = (fine_f64(H->opts) || ir) ? g.partial : nullptr;
+        Out32 o32;
+        if (ir) {
+            const Level& e0 = g.lv32[0];
+            o32.p = static_cast<float2*>(e0.b.ptr);
+            o32.l.nx = e0.v.nx;
+            o32.l.pitch = e0.v.pitch;
+            o32.l.row = e0.v.plane;
+            o32.l.off = e0.v.pitch + 1;
+        }
         if (circ)
             btiles = launch_circulant(n, m, alpha, 0, conj, reinterpret_cast<const double2*>(F), dense_rows(m),
                                       P<double>(l0.b), lb, st, 0, np, g.partial_cap);
         else
             btiles = launch_transform(n, m, reinterpret_cast<const double2*>(conj ? V : Vinv), conj ? 1 : 0,
                                       reinterpret_cast<const double2*>(F), dense_rows(m), P<double>(l0.b), lb, H->mbuf,
-                                      st, 0, np, g.partial_cap);
+                                      st, 0, np, g.partial_cap, o32);
     }
     if (check_hip()) return VMG_HIP_ERROR;
     // Z: the solve's results, copied to gbuf or (refinement, or levels without

@@ -222,12 +222,14 @@ constexpr int RT_NODES = 16 * RT_CT;   // nodes per tile
 
 // (two blocks a CU: 4 waves a SIMD for NW = 8)
 // NORM: also the sums of |out|^2 per output row (see launch_transform), kept
-// per lane in LDS across tiles so that the MFMA loop's registers are untouched.
-template <int NW, bool NORM>
+// per lane in LDS across tiles so that the MFMA loop's registers are untouched;
+// C32 (with NORM): also out rounded to complex64 into o32.p, layout o32.l.
+template <int NW, bool NORM, bool C32 = false>
 __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(4))) void k_transform_reg(int64_t m, const double* __restrict__ Mx,
                                                             const double2* __restrict__ in, RowLayout li,
                                                             double2* __restrict__ out, RowLayout lo, int accumulate,
-                                                            int tx, int64_t ntiles, double* __restrict__ partial) {
+                                                            int tx, int64_t ntiles, double* __restrict__ partial,
+                                                            Out32 o32) {
     __shared__ double sN[NORM ? 2 * 64 * NW : 1];
     constexpr int n = 8 * NW, n2 = 2 * n, KS = n2 / 4, TT = 64 * NW;
     // per thread of the tile load: complex rows x nodes = n x RT_NODES values
@@ -322,6 +324,11 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(4))) vo
                 if constexpr (NORM) {
                     sN[2 * threadIdx.x] += v0.x * v0.x + v0.y * v0.y;
                     sN[2 * threadIdx.x + 1] += v1.x * v1.x + v1.y * v1.y;
+                    if constexpr (C32) {
+                        const int64_t o2 = NodeMap(o32.l)(p0 + j);
+                        o32.p[(int64_t)cr * o32.l.row + o2] = make_float2((float)v0.x, (float)v0.y);
+                        o32.p[(int64_t)(cr + 4) * o32.l.row + o2] = make_float2((float)v1.x, (float)v1.y);
+                    }
                 }
             }
         }
@@ -362,22 +369,26 @@ template <int NW, bool NORM> int reg_blocks() {
 
 template <int NW>
 int go_reg(int64_t m, const double* Mx, const double2* in, RowLayout li, double2* out, RowLayout lo, int accumulate,
-           hipStream_t st, double* partial, int max_tiles) {
+           hipStream_t st, double* partial, int max_tiles, Out32 o32) {
     // tiles within grid rows of the shorter layout row (m is a multiple of it)
     const int tx = std::min(li.nx, lo.nx);
     const int64_t ntiles = (m / tx) * ((tx + RT_NODES - 1) / RT_NODES);
     if (partial && !accumulate) {
         const int64_t blocks = std::min<int64_t>(ntiles, reg_blocks<NW, true>());
         if (blocks >= 1 && blocks <= max_tiles) {
-            hipLaunchKernelGGL((k_transform_reg<NW, true>), dim3((unsigned)blocks), dim3(64 * NW), 0, st, m, Mx, in, li,
-                               out, lo, 0, tx, ntiles, partial);
+            if (o32.p)
+                hipLaunchKernelGGL((k_transform_reg<NW, true, true>), dim3((unsigned)blocks), dim3(64 * NW), 0, st, m, Mx,
+                                   in, li, out, lo, 0, tx, ntiles, partial, o32);
+            else
+                hipLaunchKernelGGL((k_transform_reg<NW, true>), dim3((unsigned)blocks), dim3(64 * NW), 0, st, m, Mx, in,
+                                   li, out, lo, 0, tx, ntiles, partial, o32);
             return (int)blocks;
         }
     }
     const int64_t blocks = std::min<int64_t>(ntiles, reg_blocks<NW, false>());
     if (blocks < 1) return 0;
     hipLaunchKernelGGL((k_transform_reg<NW, false>), dim3((unsigned)blocks), dim3(64 * NW), 0, st, m, Mx, in, li, out,
-                       lo, accumulate, tx, ntiles, nullptr);
+                       lo, accumulate, tx, ntiles, nullptr, Out32{});
     return 0;
 }
 
@@ -549,15 +560,15 @@ size_t transform_scratch_doubles(int n) {
 
 int launch_transform(int n, int64_t m, const double2* M, int trans_conj, const double2* in, RowLayout li,
                      double2* out, RowLayout lo, double2* mbuf, hipStream_t st, int accumulate, double* norm_partial,
-                     int max_tiles) {
+                     int max_tiles, Out32 o32) {
     double* Mx = reinterpret_cast<double*>(mbuf);
     if (transform_reg(n)) {
         hipLaunchKernelGGL(k_expand, dim3((n * n + 255) / 256), dim3(256), 0, st, M, n, trans_conj, Mx);
         switch (n) {
-            case 8: return go_reg<1>(m, Mx, in, li, out, lo, accumulate, st, norm_partial, max_tiles);
-            case 16: return go_reg<2>(m, Mx, in, li, out, lo, accumulate, st, norm_partial, max_tiles);
-            case 32: return go_reg<4>(m, Mx, in, li, out, lo, accumulate, st, norm_partial, max_tiles);
-            default: return go_reg<8>(m, Mx, in, li, out, lo, accumulate, st, norm_partial, max_tiles);
+            case 8: return go_reg<1>(m, Mx, in, li, out, lo, accumulate, st, norm_partial, max_tiles, o32);
+            case 16: return go_reg<2>(m, Mx, in, li, out, lo, accumulate, st, norm_partial, max_tiles, o32);
+            case 32: return go_reg<4>(m, Mx, in, li, out, lo, accumulate, st, norm_partial, max_tiles, o32);
+            default: return go_reg<8>(m, Mx, in, li, out, lo, accumulate, st, norm_partial, max_tiles, o32);
         }
     }
     const int nrb = (2 * n + 31) / 32, nch = (2 * n + KC - 1) / KC;
