@@ -86,10 +86,11 @@ def test_boundary_kernel_matches_separate_passes(nu1, nu2, inner, smoother, monk
         assert relerr(za, zb) <= 1e-8
 
 
-def test_boundary_kernel_exact_solution_and_graphs(monkeypatch):
+def test_boundary_kernel_exact_solution_and_graphs(monkeypatch, tmp_path):
     """Square grids: the refined solution within the conditioning of the exact
     (DST) solution; replayed graphs give bitwise the eager launches, also for
-    the adjoint (conjugate-shift) systems."""
+    the adjoint (conjugate-shift) systems (both handles take the schedule the
+    first one tuned, through the autotuner's cache file)."""
     grids = [(255, 255, 3)]
     b = inputs.rhs(3, 255, 255, seed=90)
     bd = dev(b.ravel())
@@ -99,7 +100,7 @@ def test_boundary_kernel_exact_solution_and_graphs(monkeypatch):
     out = {}
     for graphs in (True, False):
         s = VankaMG([Grid(255, num_systems=3)], lam, precision="c64_ir", ir_inner=2, graphs=graphs)
-        s.autotune()
+        s.autotune(cache_path=tmp_path / "tune.txt")
         for conj in (False, True):
             Z, it, rr, st = s.solve(bd, tol=1e-10, conj=conj)
             assert st == 0 and np.all(rr <= 1e-10)
