@@ -251,10 +251,13 @@ int stream_tiles_max(int nx, int ny, int nu);  // over every rmin and kernel
 // nu2 sweeps, norm partials of that iterate (edge_tiles per system), nu1
 // sweeps -> xo, full weighting -> cb; reads x, b and the coarse correction c
 // and leaves them untouched (the finishing pass of launch_up rebuilds the
-// last cycle's iterate from them).
+// last cycle's iterate from them).  paced (T = double, Vanka): blocks of a
+// CU's worth of waves on adjacent strips, held together by a barrier after
+// every block of rows (the same run geometry and results).
 bool edge_supported(int nu1, int nu2);
 template <typename T>
-void launch_edge(SegTable<T> tab, const int* nsys, int nu1, int nu2, int rmin, hipStream_t st, bool c32 = false);
+void launch_edge(SegTable<T> tab, const int* nsys, int nu1, int nu2, int rmin, hipStream_t st, bool c32 = false,
+                 bool paced = false);
 template <typename T> int edge_tiles(int nx, int ny, int nsys, int nu1, int nu2, int rmin);
 // The boundary of two refinement steps on a streamed complex64 finest level,
 // in one pass: the last inner cycle's correction and nu2 sweeps (complex64),

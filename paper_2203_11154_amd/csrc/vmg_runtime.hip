@@ -81,6 +81,7 @@ struct Group {
     std::vector<int> sched;  // per level: 0 = LDS-tiled kernels, r > 0 = streaming with r rows; empty = heuristic
     int tail_lt = -1;        // first level run by the tail kernel (-1: none)
     int edge = -1;           // cycle-edge kernel: -1 untuned (used where possible), 0 off, 1 on
+    int edge_pace = 0;       // FP64 cycle-edge kernel in paced blocks (autotuned)
     int edge_c = 0;          // level-1 buffer holding the coarse correction the cycle-edge kernel reads
     DevBuf rhs_alt;          // refinement with the boundary kernel: the finest complex64 right-hand side
                              // alternates between lv32[0].b (even steps) and this buffer (odd steps)
@@ -127,6 +128,8 @@ struct vmg_handle {
     int* nanflag = nullptr;
     int stream_rows = 0;       // rows per block of the streaming kernels (0: by level size)
     bool tail_on = true;       // small levels in one workgroup per system (VMG_TAIL=0 turns it off)
+    int pace_mode = -1;        // FP64 cycle-edge kernel in paced blocks: -1 as autotuned, VMG_EDGE_PACE=0 never,
+                               // 1 always
     int ir_edge_mode = 1;      // refinement step boundary in one pass where the finest level streams with the
                                // cycle-edge kernel (VMG_IR_EDGE=0: the separate update + residual pass)
     int edge_mode = 1;         // finest level across the cycle boundary in one pass: VMG_EDGE=0 off,
@@ -425,6 +428,11 @@ bool use_edge(const vmg_handle* H, const Group& g) {
     return g.edge < 0 && (double)g.nx * g.ny * g.S >= EDGE_MIN_NODES;
 }
 
+// The FP64 cycle-edge kernel of grid g runs in paced blocks.
+int edge_paced(const vmg_handle* H, const Group& g) {
+    return H->pace_mode >= 0 ? H->pace_mode : g.edge_pace;
+}
+
 // Refinement (complex64 V-cycles in FP64 refinement): the boundary of two
 // steps runs in one pass (k_ir_edge) on grids whose complex64 finest level
 // uses the cycle-edge kernel.
@@ -612,13 +620,14 @@ template <typename T> void enqueue_cycle(CycleCtx<T>& c, int l, bool x_zero) {
     }
 }
 
-template <typename T> void launch_edge_t(SegTable<T> tab, const int* nsys, int nu1, int nu2, int rmin, hipStream_t st);
+template <typename T>
+void launch_edge_t(SegTable<T> tab, const int* nsys, int nu1, int nu2, int rmin, hipStream_t st, bool paced);
 template <> void launch_edge_t<double>(SegTable<double> tab, const int* nsys, int nu1, int nu2, int rmin,
-                                       hipStream_t st) {
-    launch_edge<double>(tab, nsys, nu1, nu2, rmin, st);
+                                       hipStream_t st, bool paced) {
+    launch_edge<double>(tab, nsys, nu1, nu2, rmin, st, false, paced);
 }
 template <> void launch_edge_t<float>(SegTable<float> tab, const int* nsys, int nu1, int nu2, int rmin,
-                                      hipStream_t st) {
+                                      hipStream_t st, bool) {
     launch_edge<float>(tab, nsys, nu1, nu2, rmin, st);
 }
 
@@ -800,12 +809,13 @@ void enqueue_batched_vcycle(vmg_handle* H, int conj, hipStream_t st, bool first,
         // + norm, then the next cycle's pre-smoothing and restriction
         while (!eg.empty()) {
             const int ty = sched_rows(H, H->groups[eg[0]], 0);
+            const int pace = edge_paced(H, H->groups[eg[0]]);
             SegBatch<T> bt;
             std::vector<int> rest, done;
             for (int gi : eg) {
                 Group& g = H->groups[gi];
                 auto& L = levels_of<T>(g);
-                if (sched_rows(H, g, 0) != ty || bt.full()) {
+                if (sched_rows(H, g, 0) != ty || edge_paced(H, g) != pace || bt.full()) {
                     rest.push_back(gi);
                     continue;
                 }
@@ -818,7 +828,7 @@ void enqueue_batched_vcycle(vmg_handle* H, int conj, hipStream_t st, bool first,
             }
             {
                 Timer t(H, st, VMG_K_EDGE, bt.bytes, 0);
-                launch_edge_t<T>(bt.tab, bt.nsys, o.nu1, o.nu2, ty, st);
+                launch_edge_t<T>(bt.tab, bt.nsys, o.nu1, o.nu2, ty, st, pace != 0);
             }
             for (int gi : done) {
                 cur[gi][0] ^= 1;
@@ -961,12 +971,13 @@ void enqueue_mixed_vcycle(vmg_handle* H, int conj, hipStream_t st, bool first, s
         std::vector<int>& q = pass == 0 ? eg : ug;
         while (!q.empty()) {
             const int ty = sched_rows(H, H->groups[q[0]], 0);
+            const int pace = pass == 0 ? edge_paced(H, H->groups[q[0]]) : 0;
             SegBatch<double> bt;
             std::vector<int> rest, done;
             bool any_norm = false;
             for (int gi : q) {
                 Group& g = H->groups[gi];
-                if (sched_rows(H, g, 0) != ty || bt.full()) {
+                if (sched_rows(H, g, 0) != ty || (pass == 0 && edge_paced(H, g) != pace) || bt.full()) {
                     rest.push_back(gi);
                     continue;
                 }
@@ -985,7 +996,7 @@ void enqueue_mixed_vcycle(vmg_handle* H, int conj, hipStream_t st, bool first, s
             }
             if (pass == 0) {
                 Timer t(H, st, VMG_K_EDGE, bt.bytes, 0);
-                launch_edge<double>(bt.tab, bt.nsys, o.nu1, o.nu2, ty, st, true);
+                launch_edge<double>(bt.tab, bt.nsys, o.nu1, o.nu2, ty, st, true, pace != 0);
             } else {
                 Timer t(H, st, VMG_K_UP, bt.bytes, 0);
                 launch_up<double>(bt.tab, bt.nsys, o.nu2, any_norm, ty, st, true);
@@ -1745,6 +1756,7 @@ int vanka_mg_setup(const vmg_grid* grids, int32_t n_grids, const double* shifts,
     if (const char* e = std::getenv("VMG_TAIL")) H->tail_on = std::atoi(e) != 0;
     if (const char* e = std::getenv("VMG_EDGE")) H->edge_mode = std::max(0, std::min(2, std::atoi(e)));
     if (const char* e = std::getenv("VMG_IR_EDGE")) H->ir_edge_mode = std::atoi(e) != 0;
+    if (const char* e = std::getenv("VMG_EDGE_PACE")) H->pace_mode = std::atoi(e) != 0 ? 1 : 0;
     if (const char* e = std::getenv("VMG_STREAM_ROWS")) {
         const int r = std::atoi(e);
         if (r >= 16 && r <= 4096) H->stream_rows = r;
@@ -2452,20 +2464,21 @@ int time_level0_mixed(vmg_handle* H, Group& g, int rows, hipStream_t st, double*
 // Time the finest level's per-cycle work with the cycle-edge kernel: one
 // launch for a cycle's correction and post-smoothing and the next cycle's
 // pre-smoothing and restriction (streaming, `rows` rows per wave).
-template <typename T> int time_edge(vmg_handle* H, Group& g, int rows, hipStream_t st, double* ms_out) {
+template <typename T>
+int time_edge(vmg_handle* H, Group& g, int rows, hipStream_t st, double* ms_out, bool paced = false) {
     auto& L = levels_of<T>(g);
     const int one = g.S;
     auto run = [&]() {
         LevelSeg<T> S = make_seg<T>(H, g, 0, 0, P<T>(L[0].x[0]), P<T>(L[0].b), P<T>(L[0].x[1]), P<T>(L[1].x[0]), 0,
                                     nullptr);
         S.cb = P<T>(L[1].b);
-        launch_edge<T>(one_seg(S), &one, H->opts.nu1, H->opts.nu2, rows, st);
+        launch_edge<T>(one_seg(S), &one, H->opts.nu1, H->opts.nu2, rows, st, false, paced);
     };
     return time_reps(run, st, ms_out);
 }
 
 // The cycle-edge kernel of a precision-2 handle (complex64 coarse level).
-int time_edge_mixed(vmg_handle* H, Group& g, int rows, hipStream_t st, double* ms_out) {
+int time_edge_mixed(vmg_handle* H, Group& g, int rows, hipStream_t st, double* ms_out, bool paced = false) {
     Level& l0 = g.lv64[0];
     Level& l1 = g.lv32[1];
     const int one = g.S;
@@ -2474,7 +2487,7 @@ int time_edge_mixed(vmg_handle* H, Group& g, int rows, hipStream_t st, double* m
                                               reinterpret_cast<double2*>(P<float>(l1.x[0])), 0, nullptr);
         S.cb = reinterpret_cast<double2*>(P<float>(l1.b));
         S.lc = l1.v;
-        launch_edge<double>(one_seg(S), &one, H->opts.nu1, H->opts.nu2, rows, st, true);
+        launch_edge<double>(one_seg(S), &one, H->opts.nu1, H->opts.nu2, rows, st, true, paced);
     };
     return time_reps(run, st, ms_out);
 }
@@ -2505,7 +2518,8 @@ std::string tune_key(const vmg_handle* H, const Group& g, int l) {
     std::ostringstream k;
     static const char* prec[3] = {"c128", "c64", "c128c64"};
     k << arch << " " << prec[H->opts.precision] << " " << g.nx << " " << g.ny << " " << g.S << " "
-      << H->opts.nu1 << " " << H->opts.nu2 << " " << (l < 0 ? std::string("edge") : std::to_string(l));
+      << H->opts.nu1 << " " << H->opts.nu2 << " "
+      << (l == -1 ? std::string("edge") : l == -2 ? std::string("edgepace") : std::to_string(l));
     return k.str();
 }
 
@@ -2591,6 +2605,27 @@ extern "C" int vanka_mg_autotune(vmg_handle* H, const char* cache_path, void* hi
                 fresh.push_back(key + " " + std::to_string(found));
             }
             g.edge = found;
+        }
+        // the FP64 cycle-edge kernel in paced blocks against the plain ones
+        g.edge_pace = 0;
+        if (use_edge(H, g) && H->opts.precision != 1 && H->opts.smoother == 0) {
+            const std::string key = tune_key(H, g, -2);
+            int found = -1;
+            for (auto& e : cache)
+                if (e.first == key) found = e.second;
+            if (found < 0) {
+                const int rows = sched_rows(H, g, 0);
+                const bool mixed = H->opts.precision == 2;
+                double ms_plain = 0.0, ms_paced = 0.0;
+                int rc = mixed ? time_edge_mixed(H, g, rows, st, &ms_plain) : time_edge<double>(H, g, rows, st, &ms_plain);
+                if (!rc)
+                    rc = mixed ? time_edge_mixed(H, g, rows, st, &ms_paced, true)
+                               : time_edge<double>(H, g, rows, st, &ms_paced, true);
+                if (rc) return rc;
+                found = ms_paced < ms_plain ? 1 : 0;
+                fresh.push_back(key + " " + std::to_string(found));
+            }
+            g.edge_pace = found;
         }
     }
     // launch sequences changed: drop captured cycles

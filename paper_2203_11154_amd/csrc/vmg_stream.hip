@@ -827,7 +827,7 @@ struct EdgePipe {
     }
 };
 
-template <typename T, int NA, int NB, typename TC, bool JAC>
+template <typename T, int NA, int NB, typename TC, bool JAC, bool PACE>
 __device__ __forceinline__ double edge_piece(const LevelSeg<T>& S, int sys, int strip, int k0, int k1, bool rev,
                                              int lane, cplx<T>* bring) {
     using C = cplx<T>;
@@ -880,17 +880,34 @@ __device__ __forceinline__ double edge_piece(const LevelSeg<T>& S, int sys, int 
         p.xr[d] = p.template load_x<true>(jbeg + d);
         p.br[d] = p.template load_b<true>(jbeg + d - 1);
     }
+    // PACE: the block's waves (adjacent strips of the same rows) meet at a
+    // barrier after every block of rows, so that they read and write the
+    // same rows of the planes at about the same time.  Only pacing: no data
+    // passes between the waves, and a wave that ends early leaves the
+    // barrier to the others (its trip count may differ from theirs).
     int j = jbeg;
-    for (; j <= jend && j < jlo; j += U) p.template block<true>(j);
-    for (; j <= jhi; j += U) p.template block<false>(j);
-    for (; j <= jend; j += U) p.template block<true>(j);
+    for (; j <= jend && j < jlo; j += U) {
+        p.template block<true>(j);
+        if constexpr (PACE) __syncthreads();
+    }
+    for (; j <= jhi; j += U) {
+        p.template block<false>(j);
+        if constexpr (PACE) __syncthreads();
+    }
+    for (; j <= jend; j += U) {
+        p.template block<true>(j);
+        if constexpr (PACE) __syncthreads();
+    }
     return own ? p.acc : 0.0;
 }
 
-template <typename T, int NA, int NB, typename TC, bool JAC = false>
-__global__ __launch_bounds__(NT) void k_edge(SegTable<T> tab) {
-    __shared__ cplx<T> bring[NT / 64][12 * 64];  // right-hand side rows, one ring per wave
-    const int gw = (int)xcd_block().x * (NT / 64) + __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+// WB waves a block: NT / 64, or EDGE_WB (the waves of a CU at the FP64
+// kernel's occupancy) for the paced form.
+constexpr int EDGE_WB = 12;
+template <typename T, int NA, int NB, typename TC, bool JAC = false, int WB = NT / 64>
+__global__ __launch_bounds__(64 * WB) void k_edge(SegTable<T> tab) {
+    __shared__ cplx<T> bring[WB][12 * 64];  // right-hand side rows, one ring per wave
+    const int gw = (int)xcd_block().x * WB + __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const int lane = threadIdx.x & 63;
     const LevelSeg<T> S = seg_of_wave(tab, gw);
     const int lw = gw - S.w0;
@@ -899,7 +916,8 @@ __global__ __launch_bounds__(NT) void k_edge(SegTable<T> tab) {
     if (!S.active[pc.sys]) return;
     // (every run walks downward here: the kernel is at its register limit and
     // measured slower with the reflected address arithmetic)
-    double acc = edge_piece<T, NA, NB, TC, JAC>(S, pc.sys, pc.strip, pc.k0, pc.k1, false, lane, bring[threadIdx.x >> 6]);
+    double acc = edge_piece<T, NA, NB, TC, JAC, (WB > NT / 64)>(S, pc.sys, pc.strip, pc.k0, pc.k1, false, lane,
+                                                               bring[threadIdx.x >> 6]);
     if (S.partial) {
         for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
         if (lane == 0) S.partial[pc.slot] = acc;
@@ -1182,8 +1200,9 @@ __global__ __launch_bounds__(NT) void k_fill_zero(cplx<T>* __restrict__ x, Level
 template <int NS> constexpr int down_own() { return DownPipe<double, NS>::OWN; }
 template <int NS, bool NORM> constexpr int up_own() { return UpPipe<double, NS, NORM>::OWN; }
 
-// Waves of one kernel that are resident on the whole device at once.
-int resident_waves(const void* kernel) {
+// Waves of one kernel that are resident on the whole device at once, in
+// blocks of `threads`.
+int resident_waves(const void* kernel, int threads = NT) {
     static std::mutex mu;
     static std::map<std::pair<const void*, int>, int> cache;
     int dev = 0;
@@ -1192,9 +1211,10 @@ int resident_waves(const void* kernel) {
     auto it = cache.find({kernel, dev});
     if (it != cache.end()) return it->second;
     int blocks = 0, cus = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, kernel, NT, 0) != hipSuccess || blocks < 1) blocks = 1;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, kernel, threads, 0) != hipSuccess || blocks < 1)
+        blocks = 1;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1) cus = 1;
-    const int w = blocks * cus * (NT / 64);
+    const int w = blocks * cus * (threads / 64);
     cache[{kernel, dev}] = w;
     return w;
 }
@@ -1269,11 +1289,23 @@ void up_go(SegTable<T> tab, const int* nsys, int rmin, hipStream_t st) {
 }
 
 template <typename T, int NA, int NB, typename TC>
-void edge_go(SegTable<T> tab, const int* nsys, int rmin, hipStream_t st) {
+void edge_go(SegTable<T> tab, const int* nsys, int rmin, hipStream_t st, bool paced) {
     using Pipe = EdgePipe<T, NA, NB>;
     const void* k = (const void*)&k_edge<T, NA, NB, T>;
-    const dim3 g = stream_seg_grid(tab, nsys, Pipe::OWN, Pipe::COL0, 4 * Pipe::NS + 9, rmin, resident_waves(k));
+    const int resident = resident_waves(k);
+    dim3 g = stream_seg_grid(tab, nsys, Pipe::OWN, Pipe::COL0, 4 * Pipe::NS + 9, rmin, resident);
     if (g.x == 0) return;
+    if constexpr (std::is_same<T, double>::value) {
+        // paced blocks (Vanka only), where a CU holds as many of their waves as
+        // of the plain blocks' (the run geometry above assumes that count)
+        const void* kp = (const void*)&k_edge<T, NA, NB, TC, false, EDGE_WB>;
+        if (paced && !tab.s[0].jacobi && resident_waves(kp, 64 * EDGE_WB) == resident) {
+            const int w = tab.s[tab.n - 1].w0 + tab.s[tab.n - 1].waves;
+            g.x = (w + EDGE_WB - 1) / EDGE_WB;
+            hipLaunchKernelGGL((k_edge<T, NA, NB, TC, false, EDGE_WB>), g, dim3(64 * EDGE_WB), 0, st, tab);
+            return;
+        }
+    }
     if (tab.s[0].jacobi) hipLaunchKernelGGL((k_edge<T, NA, NB, TC, true>), g, dim3(NT), 0, st, tab);
     else hipLaunchKernelGGL((k_edge<T, NA, NB, TC, false>), g, dim3(NT), 0, st, tab);
 }
@@ -1290,24 +1322,24 @@ template <typename T, int NA, int NB> int edge_tiles_of(int nx, int ny, int nsys
 bool edge_supported(int nu1, int nu2) { return nu1 >= 1 && nu1 <= 2 && nu2 >= 1 && nu2 <= 2; }
 
 template <typename T, typename TC>
-void edge_launch(SegTable<T> tab, const int* nsys, int nu1, int nu2, int rmin, hipStream_t st) {
-    if (nu2 == 1 && nu1 == 1) edge_go<T, 1, 1, TC>(tab, nsys, rmin, st);
-    else if (nu2 == 1 && nu1 == 2) edge_go<T, 1, 2, TC>(tab, nsys, rmin, st);
-    else if (nu2 == 2 && nu1 == 1) edge_go<T, 2, 1, TC>(tab, nsys, rmin, st);
-    else edge_go<T, 2, 2, TC>(tab, nsys, rmin, st);
+void edge_launch(SegTable<T> tab, const int* nsys, int nu1, int nu2, int rmin, hipStream_t st, bool paced) {
+    if (nu2 == 1 && nu1 == 1) edge_go<T, 1, 1, TC>(tab, nsys, rmin, st, paced);
+    else if (nu2 == 1 && nu1 == 2) edge_go<T, 1, 2, TC>(tab, nsys, rmin, st, paced);
+    else if (nu2 == 2 && nu1 == 1) edge_go<T, 2, 1, TC>(tab, nsys, rmin, st, paced);
+    else edge_go<T, 2, 2, TC>(tab, nsys, rmin, st, paced);
 }
 template <typename T>
-void launch_edge(SegTable<T> tab, const int* nsys, int nu1, int nu2, int rmin, hipStream_t st, bool c32) {
+void launch_edge(SegTable<T> tab, const int* nsys, int nu1, int nu2, int rmin, hipStream_t st, bool c32, bool paced) {
     if constexpr (std::is_same<T, double>::value) {
         if (c32) {
-            edge_launch<double, float>(tab, nsys, nu1, nu2, rmin, st);
+            edge_launch<double, float>(tab, nsys, nu1, nu2, rmin, st, paced);
             return;
         }
     }
-    edge_launch<T, T>(tab, nsys, nu1, nu2, rmin, st);
+    edge_launch<T, T>(tab, nsys, nu1, nu2, rmin, st, paced);
 }
-template void launch_edge<double>(SegTable<double>, const int*, int, int, int, hipStream_t, bool);
-template void launch_edge<float>(SegTable<float>, const int*, int, int, int, hipStream_t, bool);
+template void launch_edge<double>(SegTable<double>, const int*, int, int, int, hipStream_t, bool, bool);
+template void launch_edge<float>(SegTable<float>, const int*, int, int, int, hipStream_t, bool, bool);
 
 template <typename T> int edge_tiles(int nx, int ny, int nsys, int nu1, int nu2, int rmin) {
     if (nu2 == 1 && nu1 == 1) return edge_tiles_of<T, 1, 1>(nx, ny, nsys, rmin);

@@ -148,13 +148,17 @@ def test_autotuned_schedule_parity(tmp_path):
     text = cache.read_text()
     # one line per grid and level, plus one "edge" line for each grid whose
     # finest level was tuned to stream (the cycle-edge kernel is timed only
-    # then, so that line follows the timing of the level choice)
+    # then, so that line follows the timing of the level choice), and one
+    # "edgepace" line for each grid that then uses the cycle-edge kernel
     lines = [ln.split() for ln in text.splitlines()]
-    level_lines = [ln for ln in lines if ln[-2] != "edge"]
+    level_lines = [ln for ln in lines if ln[-2] not in ("edge", "edgepace")]
     edge_lines = [ln for ln in lines if ln[-2] == "edge"]
+    pace_lines = [ln for ln in lines if ln[-2] == "edgepace"]
     assert len(level_lines) == sum(len(sc) - 1 for sc in scheds)
     streamed = {(n, n) for (n, c), sc in zip(SMALL, scheds) if sc[0] > 0}
     assert all((int(ln[2]), int(ln[3])) in streamed for ln in edge_lines)
+    assert all((int(ln[2]), int(ln[3])) in streamed for ln in pace_lines)
+    assert all(int(ln[-1]) in (0, 1) for ln in pace_lines)
     again, _, _ = setup(SMALL)
     assert again.autotune(cache) == scheds
     assert cache.read_text() == text
