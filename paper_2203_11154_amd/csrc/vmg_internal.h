@@ -265,7 +265,8 @@ template <typename T> int edge_tiles(int nx, int ny, int nsys, int nu1, int nu2,
 // system; stored rounded to complex64 as the next step's right-hand side), then
 // the next step's first inner cycle from zero: nu1 sweeps, residual and full
 // weighting.  nu1, nu2 in {1, 2}.
-void launch_ir_edge(SegTable<float> tab, const int* nsys, int nu1, int nu2, int rmin, hipStream_t st);
+void launch_ir_edge(SegTable<float> tab, const int* nsys, int nu1, int nu2, int rmin, hipStream_t st,
+                    bool paced = false);
 int ir_edge_tiles(int nx, int ny, int nsys, int nu1, int nu2, int rmin);
 void stream_prepare();  // device occupancy of the streaming kernels (call outside stream capture)
 template <typename T> void launch_fill_zero(cplx<T>* x, LevelView lv, int nsys, hipStream_t st);

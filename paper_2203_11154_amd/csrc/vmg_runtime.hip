@@ -1229,11 +1229,12 @@ int enqueue_cycle_all(vmg_handle* H, int conj, hipStream_t st, int64_t cycle, do
             if (irb[gi]) eg.push_back((int)gi);
         while (!eg.empty()) {
             const int ty = sched_rows(H, H->groups[eg[0]], 0);
+            const int pace = edge_paced(H, H->groups[eg[0]]);
             SegBatch<float> bt;
             std::vector<int> rest, done;
             for (int gi : eg) {
                 Group& g = H->groups[gi];
-                if (sched_rows(H, g, 0) != ty || bt.full()) {
+                if (sched_rows(H, g, 0) != ty || edge_paced(H, g) != pace || bt.full()) {
                     rest.push_back(gi);
                     continue;
                 }
@@ -1255,7 +1256,7 @@ int enqueue_cycle_all(vmg_handle* H, int conj, hipStream_t st, int64_t cycle, do
             }
             {
                 Timer t(H, st, VMG_K_IR, bt.bytes, 0);
-                launch_ir_edge(bt.tab, bt.nsys, o.nu1, o.nu2, ty, st);
+                launch_ir_edge(bt.tab, bt.nsys, o.nu1, o.nu2, ty, st, pace != 0);
             }
             for (int gi : done) {
                 cur[gi][0] ^= 1;
@@ -2492,6 +2493,28 @@ int time_edge_mixed(vmg_handle* H, Group& g, int rows, hipStream_t st, double* m
     return time_reps(run, st, ms_out);
 }
 
+// The refinement step boundary pass (k_ir_edge) of a precision-1 handle
+// (scratch contents: every buffer it writes is rewritten by a solve).
+int time_ir_edge(vmg_handle* H, Group& g, int rows, hipStream_t st, double* ms_out, bool paced) {
+    auto& L = g.lv32;
+    Level& lh = g.lv64[0];
+    const int one = g.S;
+    auto run = [&]() {
+        LevelSeg<float> S = make_seg<float>(H, g, 0, 0, P<float>(L[0].x[0]), P<float>(L[0].b), P<float>(L[0].x[1]),
+                                            P<float>(L[1].x[0]), 0, nullptr);
+        S.cb = P<float>(L[1].b);
+        S.lh = lh.v;
+        S.xh = P<double>(lh.x[0]);
+        S.xho = P<double>(lh.x[1]);
+        S.bh = P<double>(lh.b);
+        S.coefh = coef_of<double>(g, 0, 0);
+        S.sh = 1.0 / (lh.h * lh.h);
+        S.bno = static_cast<float2*>(g.rhs_alt.ptr);
+        launch_ir_edge(one_seg(S), &one, H->opts.nu1, H->opts.nu2, rows, st, paced);
+    };
+    return time_reps(run, st, ms_out);
+}
+
 template <typename F> int time_reps(F&& run, hipStream_t st, double* ms_out) {
     hipEvent_t a = nullptr, b = nullptr;
     if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) return VMG_HIP_ERROR;
@@ -2606,9 +2629,11 @@ extern "C" int vanka_mg_autotune(vmg_handle* H, const char* cache_path, void* hi
             }
             g.edge = found;
         }
-        // the FP64 cycle-edge kernel in paced blocks against the plain ones
+        // the FP64 cycle-edge kernel (refinement: the step boundary pass) in
+        // paced blocks against the plain ones
         g.edge_pace = 0;
-        if (use_edge(H, g) && H->opts.precision != 1 && H->opts.smoother == 0) {
+        const bool irb = use_ir_edge(H, g);
+        if (use_edge(H, g) && (H->opts.precision != 1 || irb) && H->opts.smoother == 0) {
             const std::string key = tune_key(H, g, -2);
             int found = -1;
             for (auto& e : cache)
@@ -2617,10 +2642,13 @@ extern "C" int vanka_mg_autotune(vmg_handle* H, const char* cache_path, void* hi
                 const int rows = sched_rows(H, g, 0);
                 const bool mixed = H->opts.precision == 2;
                 double ms_plain = 0.0, ms_paced = 0.0;
-                int rc = mixed ? time_edge_mixed(H, g, rows, st, &ms_plain) : time_edge<double>(H, g, rows, st, &ms_plain);
+                int rc = irb     ? time_ir_edge(H, g, rows, st, &ms_plain, false)
+                         : mixed ? time_edge_mixed(H, g, rows, st, &ms_plain)
+                                 : time_edge<double>(H, g, rows, st, &ms_plain);
                 if (!rc)
-                    rc = mixed ? time_edge_mixed(H, g, rows, st, &ms_paced, true)
-                               : time_edge<double>(H, g, rows, st, &ms_paced, true);
+                    rc = irb     ? time_ir_edge(H, g, rows, st, &ms_paced, true)
+                         : mixed ? time_edge_mixed(H, g, rows, st, &ms_paced, true)
+                                 : time_edge<double>(H, g, rows, st, &ms_paced, true);
                 if (rc) return rc;
                 found = ms_paced < ms_plain ? 1 : 0;
                 fresh.push_back(key + " " + std::to_string(found));

@@ -1090,7 +1090,7 @@ struct IrEdgePipe {
     }
 };
 
-template <int NA, int NB, bool JAC>
+template <int NA, int NB, bool JAC, bool PACE>
 __device__ __forceinline__ double ir_edge_piece(const LevelSeg<float>& S, int sys, int strip, int k0, int k1, int lane,
                                                 float2* bring) {
     using C = float2;
@@ -1165,24 +1165,35 @@ __device__ __forceinline__ double ir_edge_piece(const LevelSeg<float>& S, int sy
         p.xhr[d] = p.template load_xh<true>(jbeg + d - 2 * NA);
         p.bhr[d] = p.template load_bh<true>(jbeg + d - 2 * NA - 1);
     }
+    // (PACE: as in edge_piece)
     int j = jbeg;
-    for (; j <= jend && j < jlo; j += U) p.template block<true>(j);
-    for (; j <= jhi; j += U) p.template block<false>(j);
-    for (; j <= jend; j += U) p.template block<true>(j);
+    for (; j <= jend && j < jlo; j += U) {
+        p.template block<true>(j);
+        if constexpr (PACE) __syncthreads();
+    }
+    for (; j <= jhi; j += U) {
+        p.template block<false>(j);
+        if constexpr (PACE) __syncthreads();
+    }
+    for (; j <= jend; j += U) {
+        p.template block<true>(j);
+        if constexpr (PACE) __syncthreads();
+    }
     return own ? p.acc : 0.0;
 }
 
-template <int NA, int NB, bool JAC>
-__global__ __launch_bounds__(NT) void k_ir_edge(SegTable<float> tab) {
-    __shared__ float2 bring[NT / 64][12 * 64];  // inner right-hand side rows, one ring per wave
-    const int gw = (int)xcd_block().x * (NT / 64) + __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+template <int NA, int NB, bool JAC, int WB = NT / 64>
+__global__ __launch_bounds__(64 * WB) void k_ir_edge(SegTable<float> tab) {
+    __shared__ float2 bring[WB][12 * 64];  // inner right-hand side rows, one ring per wave
+    const int gw = (int)xcd_block().x * WB + __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const int lane = threadIdx.x & 63;
     const LevelSeg<float> S = seg_of_wave(tab, gw);
     const int lw = gw - S.w0;
     if (lw >= S.waves) return;
     const Piece pc = piece_of(S, lw);
     if (!S.active[pc.sys]) return;
-    double acc = ir_edge_piece<NA, NB, JAC>(S, pc.sys, pc.strip, pc.k0, pc.k1, lane, bring[threadIdx.x >> 6]);
+    double acc = ir_edge_piece<NA, NB, JAC, (WB > NT / 64)>(S, pc.sys, pc.strip, pc.k0, pc.k1, lane,
+                                                         bring[threadIdx.x >> 6]);
     if (S.partial) {
         for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
         if (lane == 0) S.partial[pc.slot] = acc;
@@ -1353,11 +1364,20 @@ template int edge_tiles<float>(int, int, int, int, int, int);
 namespace {
 // (the run geometry follows the Vanka kernel's occupancy for both smoothers,
 // as the norm partial sums are counted with it)
-template <int NA, int NB> void ir_edge_go(SegTable<float> tab, const int* nsys, int rmin, hipStream_t st) {
+template <int NA, int NB> void ir_edge_go(SegTable<float> tab, const int* nsys, int rmin, hipStream_t st, bool paced) {
     using Pipe = IrEdgePipe<NA, NB, false>;
-    const dim3 g = stream_seg_grid(tab, nsys, Pipe::OWN, Pipe::COL0, 4 * Pipe::NS + 9, rmin,
-                                   resident_waves((const void*)&k_ir_edge<NA, NB, false>));
+    const int resident = resident_waves((const void*)&k_ir_edge<NA, NB, false>);
+    dim3 g = stream_seg_grid(tab, nsys, Pipe::OWN, Pipe::COL0, 4 * Pipe::NS + 9, rmin, resident);
     if (g.x == 0) return;
+    // paced blocks as for the cycle-edge kernel (Vanka; where a CU holds as
+    // many of their waves as of the plain blocks')
+    const void* kp = (const void*)&k_ir_edge<NA, NB, false, EDGE_WB>;
+    if (paced && !tab.s[0].jacobi && resident_waves(kp, 64 * EDGE_WB) == resident) {
+        const int w = tab.s[tab.n - 1].w0 + tab.s[tab.n - 1].waves;
+        g.x = (w + EDGE_WB - 1) / EDGE_WB;
+        hipLaunchKernelGGL((k_ir_edge<NA, NB, false, EDGE_WB>), g, dim3(64 * EDGE_WB), 0, st, tab);
+        return;
+    }
     if (tab.s[0].jacobi) hipLaunchKernelGGL((k_ir_edge<NA, NB, true>), g, dim3(NT), 0, st, tab);
     else hipLaunchKernelGGL((k_ir_edge<NA, NB, false>), g, dim3(NT), 0, st, tab);
 }
@@ -1369,11 +1389,11 @@ template <int NA, int NB> int ir_edge_tiles_of(int nx, int ny, int nsys, int rmi
 }
 }  // namespace
 
-void launch_ir_edge(SegTable<float> tab, const int* nsys, int nu1, int nu2, int rmin, hipStream_t st) {
-    if (nu2 == 1 && nu1 == 1) ir_edge_go<1, 1>(tab, nsys, rmin, st);
-    else if (nu2 == 1 && nu1 == 2) ir_edge_go<1, 2>(tab, nsys, rmin, st);
-    else if (nu2 == 2 && nu1 == 1) ir_edge_go<2, 1>(tab, nsys, rmin, st);
-    else ir_edge_go<2, 2>(tab, nsys, rmin, st);
+void launch_ir_edge(SegTable<float> tab, const int* nsys, int nu1, int nu2, int rmin, hipStream_t st, bool paced) {
+    if (nu2 == 1 && nu1 == 1) ir_edge_go<1, 1>(tab, nsys, rmin, st, paced);
+    else if (nu2 == 1 && nu1 == 2) ir_edge_go<1, 2>(tab, nsys, rmin, st, paced);
+    else if (nu2 == 2 && nu1 == 1) ir_edge_go<2, 1>(tab, nsys, rmin, st, paced);
+    else ir_edge_go<2, 2>(tab, nsys, rmin, st, paced);
 }
 int ir_edge_tiles(int nx, int ny, int nsys, int nu1, int nu2, int rmin) {
     if (nu2 == 1 && nu1 == 1) return ir_edge_tiles_of<1, 1>(nx, ny, nsys, rmin);

@@ -32,10 +32,11 @@ def relerr(a, b):
 GRIDS = [(223, 111, 2), (255, 255, 2), (127, 255, 1)]
 
 
-def make(grids, monkeypatch, ir_edge, **kw):
+def make(grids, monkeypatch, ir_edge, pace="0", **kw):
     from paper_2203_11154_amd import Grid, VankaMG
     monkeypatch.setenv("VMG_EDGE", "2")
     monkeypatch.setenv("VMG_IR_EDGE", "1" if ir_edge else "0")
+    monkeypatch.setenv("VMG_EDGE_PACE", pace)
     lam = inputs.alpha_circulant_shifts(sum(s for _, _, s in grids))
     gs = [Grid(nx, ny, num_systems=s) for nx, ny, s in grids]
     return VankaMG(gs, lam, precision="c64_ir", **kw), lam
@@ -53,15 +54,19 @@ def host_relres(z, bs, lam, grids):
     return np.concatenate(out)
 
 
-@pytest.mark.parametrize("nu1,nu2,inner,smoother", [(2, 2, 2, "vanka"), (2, 2, 1, "vanka"), (2, 2, 3, "vanka"),
-                                                     (1, 2, 2, "vanka"), (2, 1, 2, "vanka"), (1, 1, 2, "vanka"),
-                                                     (2, 2, 2, "jacobi")])
-def test_boundary_kernel_matches_separate_passes(nu1, nu2, inner, smoother, monkeypatch):
+@pytest.mark.parametrize("nu1,nu2,inner,smoother,pace", [(2, 2, 2, "vanka", "0"), (2, 2, 1, "vanka", "0"),
+                                                          (2, 2, 3, "vanka", "0"), (1, 2, 2, "vanka", "0"),
+                                                          (2, 1, 2, "vanka", "0"), (1, 1, 2, "vanka", "0"),
+                                                          (2, 2, 2, "jacobi", "0"), (2, 2, 2, "vanka", "1"),
+                                                          (2, 1, 3, "vanka", "1")])
+def test_boundary_kernel_matches_separate_passes(nu1, nu2, inner, smoother, pace, monkeypatch):
+    """(pace = 1: the boundary pass in paced blocks, whose waves come from
+    the three grids with their different trip counts.)"""
     bs = [inputs.rhs(s, ny, nx, seed=80 + k) for k, (nx, ny, s) in enumerate(GRIDS)]
     bd = dev(np.concatenate([b.ravel() for b in bs]))
     res = {}
     for ir_edge in (True, False):
-        s, lam = make(GRIDS, monkeypatch, ir_edge, nu1=nu1, nu2=nu2, ir_inner=inner, smoother=smoother)
+        s, lam = make(GRIDS, monkeypatch, ir_edge, pace=pace, nu1=nu1, nu2=nu2, ir_inner=inner, smoother=smoother)
         for g in range(len(GRIDS)):
             assert s.plan(g)[0], g
         Z, it, rr, st = s.solve(bd, tol=1e-10)
