@@ -36,15 +36,20 @@ FP64_MFMA_PEAK_TFLOPS = 78.6
 
 # HBM bytes per launch of the dominant kernel measured with rocprofv3
 # FETCH_SIZE and WRITE_SIZE on each workload, each scaled by its reading for a
-# plain 1 GiB copy (profiles/).  Valid only for the kernel source it was
-# measured on: reported as null once that file changes.
-MEASURED_TRAFFIC = {"source": "vmg_stream.hip", "source_sha256_16": "f7c8f47653ac4bad",
-                    "bytes_per_launch": {"precision_2047": 8122.7e6, "plain_1023": 4048.8e6}}
+# plain 1 GiB copy (profiles/), for its plain-block (plan 1) and paced-block
+# (plan 2) form (both the autotuner's candidates in the same runs).  Valid
+# only for the kernel source it was measured on: reported as null once that
+# file changes.
+MEASURED_TRAFFIC = {"source": "vmg_stream.hip", "source_sha256_16": "ab09dead015ff5cf",
+                    "bytes_per_launch": {"precision_2047": {1: 8099.0e6, 2: 7710.9e6},
+                                         "plain_1023": {1: 4047.1e6, 2: 3886.6e6}}}
 # finest level across the boundary of two V-cycles: correction + 2 sweeps +
 # stopping-test norm, then the next cycle's 2 sweeps + residual + restriction
 # (template arguments: precision, sweeps after and before the boundary, the
-# coarse level's precision, damped Jacobi instead of Vanka)
-DOMINANT = "k_edge<double, 2, 2, double, false>"
+# coarse level's precision, damped Jacobi instead of Vanka, waves a block:
+# 12 in the paced blocks the autotuner may choose, else 4)
+def dominant_kernel(plan_edge):
+    return "k_edge<double, 2, 2, double, false, %d>" % (12 if plan_edge == 2 else 4)
 # systems of the headline workload the oracle solves (the cpu baseline and
 # the per-result errors): the smallest and the largest |lambda_j|
 ORACLE_SAMPLE = (0, 16)
@@ -219,7 +224,7 @@ def paradiag_leg(name, n, S, seed, args, torch, sample=(), breakdown=True, dft=T
              "ms_per_step": round(1e3 * dt / args.steps, 3), "dtype": dtype,
              ("cycles" if pname != "fp32_ir" else "refinement_steps"): {"min": int(it.min()), "max": int(it.max())},
              "max_relres": float(rr.max()), "converged": st == 0 and bool(np.all(rr <= tol)),
-             "levels": len(s.levels()), "schedule": schedule[0], "edge_kernel": edge}
+             "levels": len(s.levels()), "schedule": schedule[0], "edge_kernel": edge, "edge_plan": s.plan(0)[0]}
         if pname == "fp64":
             # the same steps without any event (cycles replayed as graphs)
             dtg, _ = run_steps(s, Vd, Vinvd, Fd, Ud, args.steps, tol, torch)
@@ -511,9 +516,10 @@ def roofline_of(leg, traffic_key, copy_gbs):
     gbs = e["GB/s"]
     traffic = None
     if MEASURED_TRAFFIC["source_sha256_16"] == kernel_source_hash(MEASURED_TRAFFIC["source"]):
-        traffic = MEASURED_TRAFFIC["bytes_per_launch"].get(traffic_key)
+        traffic = MEASURED_TRAFFIC["bytes_per_launch"].get(traffic_key, {}).get(leg["fp64"]["edge_plan"])
     n, S = leg["grid"], leg["systems"]
-    r = {"bound": "hbm", "kernel": DOMINANT, "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+    r = {"bound": "hbm", "kernel": dominant_kernel(leg["fp64"]["edge_plan"]), "achieved": gbs, "peak": HBM_PEAK_GBS,
+         "unit": "GB/s",
          "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": traffic, "launches": e["launches"], "avg_ms": e["avg_ms"],
          "algorithmic_bytes_per_launch": e["algorithmic_bytes_per_launch"],
          "bytes_per_node": f"56 (read x, b, e/4; write x_(k+1) pre-smoothed, coarse rhs/4) x {n}^2 x {S}",

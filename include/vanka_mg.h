@@ -426,16 +426,21 @@ int vanka_mg_autotune(vmg_handle* h, const char* cache_path, void* hip_stream);
 int vanka_mg_schedule(const vmg_handle* h, int32_t g, int32_t nlev, int32_t* sched);
 
 /* Fused kernels in use for grid g (host outputs): *edge = 1 when the finest
- * level runs across the boundary of two V-cycles in one launch (FP64 cycles
- * with 1 or 2 pre- and post-smoothing steps and a streamed finest level),
- * else 0; *tail_level = the first level whose work (down to the coarsest
- * solve and back) runs in one workgroup per system, -1 when none does.
- * Either pointer may be NULL.  Untuned, the cycle-edge kernel runs on grids
- * whose finest levels hold at least 16M nodes over all systems;
- * vanka_mg_autotune times it against the separate launches per grid.
- * Environment switches read at setup: VMG_EDGE=0 turns it off, VMG_EDGE=2
- * uses it wherever it applies; VMG_TAIL=0 turns the tail kernel off.
- * Returns VMG_OK or VMG_INVALID_ARG. */
+ * level runs across the boundary of two V-cycles in one launch (1 or 2 pre-
+ * and post-smoothing steps and a streamed finest level; refinement: also the
+ * boundary of two refinement steps), 2 when that kernel (refinement: the
+ * step boundary pass) runs in paced blocks
+ * (a CU's worth of waves on adjacent strips meeting at a barrier after every
+ * block of rows), else 0; *tail_level = the first level whose work (down to
+ * the coarsest solve and back) runs in one workgroup per system, -1 when none
+ * does.  Either pointer may be NULL.  Untuned, the cycle-edge kernel runs on
+ * grids whose finest levels hold at least 16M nodes over all systems, in
+ * plain blocks; vanka_mg_autotune times it against the separate launches per
+ * grid, and the paced blocks against the plain ones.  Environment switches
+ * read at setup: VMG_EDGE=0 turns it off, VMG_EDGE=2 uses it wherever it
+ * applies; VMG_EDGE_PACE=0/1 never/always paces it; VMG_IR_EDGE=0 keeps the
+ * refinement step boundary in separate passes; VMG_TAIL=0 turns the tail
+ * kernel off.  Returns VMG_OK or VMG_INVALID_ARG. */
 int vanka_mg_plan(const vmg_handle* h, int32_t g, int32_t* edge, int32_t* tail_level);
 
 /* Levels of grid g: writes count and, if non-NULL, nx/ny per level. */

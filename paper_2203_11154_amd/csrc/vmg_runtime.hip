@@ -2682,7 +2682,7 @@ extern "C" int vanka_mg_schedule(const vmg_handle* H, int32_t g, int32_t nlev, i
 extern "C" int vanka_mg_plan(const vmg_handle* H, int32_t g, int32_t* edge, int32_t* tail_level) {
     if (!H || g < 0 || g >= (int)H->groups.size()) return VMG_INVALID_ARG;
     const Group& G = H->groups[g];
-    if (edge) *edge = use_edge(H, G) ? 1 : 0;
+    if (edge) *edge = use_edge(H, G) ? (edge_paced(H, G) && H->opts.smoother == 0 ? 2 : 1) : 0;
     if (tail_level) *tail_level = G.tail_lt;
     return VMG_OK;
 }

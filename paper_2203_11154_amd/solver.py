@@ -147,11 +147,12 @@ class VankaMG:
 
     def plan(self, g=0):
         """(edge, tail_level) of grid g: whether the finest level runs across
-        the boundary of two V-cycles in one launch, and the first level run
-        in one workgroup per system (-1: none)."""
+        the boundary of two V-cycles in one launch (0 no, 1 yes, 2 yes in
+        paced blocks), and the first level run in one workgroup per system
+        (-1: none)."""
         e, t = ctypes.c_int32(0), ctypes.c_int32(0)
         _lib.check(self.lib.vanka_mg_plan(self.handle, g, ctypes.byref(e), ctypes.byref(t)), "vanka_mg_plan")
-        return bool(e.value), int(t.value)
+        return int(e.value), int(t.value)
 
     def solve(self, B, tol=1e-10, conj=False, fixed_iters=None, out=None, stats=True):
         """Solve every system; B holds all systems concatenated (any shape with

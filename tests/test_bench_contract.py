@@ -23,4 +23,4 @@ def test_traffic_entry_names_an_existing_kernel_source():
     assert os.path.exists(os.path.join(ROOT, "paper_2203_11154_amd", "csrc", bench.MEASURED_TRAFFIC["source"]))
     assert len(bench.kernel_source_hash(bench.MEASURED_TRAFFIC["source"])) == 16
     per_workload = bench.MEASURED_TRAFFIC["bytes_per_launch"]
-    assert per_workload and all(v > 0 for v in per_workload.values())
+    assert per_workload and all(set(v) <= {1, 2} and all(b > 0 for b in v.values()) for v in per_workload.values())
