@@ -174,6 +174,19 @@ template <typename T> struct TailLaunch {
     int z0[MAXSEG];            // first workgroup (system) of the entry
     int xz[MAXSEG];            // first tail level starts from x = 0
     cplx<T>* x[MAXSEG];        // x of the first tail level (read unless xz, written)
+    // whole solves (maxc > 0; the tail starts at the finest level): up to
+    // maxc cycles per system, each followed by the stopping test of the
+    // finest level's residual, on the per-system state at index sys0 + system
+    int maxc;
+    int fixed;                 // fixed counts: stop at target only
+    double tol;
+    int sys0[MAXSEG];
+    const double* bb;          // |b|^2
+    double* relres;
+    int* iters;
+    int* active;
+    const int* target;
+    int* nanflag;
 };
 template <typename T>
 void launch_tail(const TailSeg<T>* segs, const TailLaunch<T>& tl, int total_sys, int64_t lds_bytes, int nu1, int nu2,

@@ -128,6 +128,8 @@ struct vmg_handle {
     int* nanflag = nullptr;
     int stream_rows = 0;       // rows per block of the streaming kernels (0: by level size)
     bool tail_on = true;       // small levels in one workgroup per system (VMG_TAIL=0 turns it off)
+    bool tail_solve_on = true; // whole solves in one tail launch where the tail covers every level
+                               // (VMG_TAIL_SOLVE=0: one launch and one host-side stopping test a cycle)
     int pace_mode = -1;        // FP64 cycle-edge kernel in paced blocks: -1 as autotuned, VMG_EDGE_PACE=0 never,
                                // 1 always
     int ir_edge_mode = 1;      // refinement step boundary in one pass where the finest level streams with the
@@ -505,11 +507,22 @@ int tail_start(const Group& g) { return g.tail_lt >= 0 ? g.tail_lt : g.L; }
 // tail level in xs (read unless xzs), written in place.
 template <typename T>
 void enqueue_tails(vmg_handle* H, int conj, hipStream_t st, const std::vector<int>& gis,
-                   const std::vector<cplx<T>*>& xs, const std::vector<int>& xzs) {
+                   const std::vector<cplx<T>*>& xs, const std::vector<int>& xzs, int maxc = 0, double tol = 0.0,
+                   int fixed = 0) {
     const vmg_opts& o = H->opts;
     const double E = sizeof(cplx<T>);
     for (size_t k0 = 0; k0 < gis.size(); k0 += MAXSEG) {
         TailLaunch<T> tl{};
+        // whole solves (see TailLaunch)
+        tl.maxc = maxc;
+        tl.fixed = fixed;
+        tl.tol = tol;
+        tl.bb = H->bb;
+        tl.relres = H->relres;
+        tl.iters = H->iters;
+        tl.active = H->active;
+        tl.target = H->target;
+        tl.nanflag = H->nanflag;
         int total = 0, lvl = 0;
         int64_t lds = 0;
         double bytes = 0.0;
@@ -519,12 +532,14 @@ void enqueue_tails(vmg_handle* H, int conj, hipStream_t st, const std::vector<in
             tl.z0[tl.n] = total;
             tl.xz[tl.n] = xzs[k];
             tl.x[tl.n] = xs[k];
+            tl.sys0[tl.n] = g.sys0;
             ++tl.n;
             total += g.S;
             lds = std::max(lds, g.tail_lds);
             lvl = g.tail_lt;
             bytes += (xzs[k] ? 2.0 : 3.0) * E * nodes(levels_of<T>(g)[g.tail_lt].v) * g.nact;
         }
+        if (maxc > 0) bytes = 0.0;  // (whole solves: no per-launch byte count)
         Timer t(H, st, VMG_K_COARSE, bytes, lvl);
         launch_tail<T>(reinterpret_cast<const TailSeg<T>*>(H->tail_dev[conj]), tl, total, lds, o.nu1, o.nu2, o.gamma,
                        st);
@@ -1328,6 +1343,30 @@ int run_cycle(vmg_handle* H, int conj, hipStream_t st, int64_t cycle, double tol
 // complex64 finest level).  With fixed counts and no host outputs nothing waits for the
 // device: all cycles up to the largest count are enqueued (the kernels of a
 // system that has reached its count return at once).
+// Solves that run whole inside one tail launch: FP64 cycles on grids whose
+// every level, the finest included, runs in the tail kernel.
+bool tail_solves(const vmg_handle* H) {
+    if (H->opts.precision != 0 || !H->tail_solve_on) return false;
+    for (auto& g : H->groups)
+        if (g.tail_lt != 0) return false;
+    return true;
+}
+
+// Up to maxc cycles of every system from x = 0, each followed by its stopping
+// test, in one tail launch (per batch of grids).
+int enqueue_tail_solve(vmg_handle* H, int conj, hipStream_t st, int maxc, double tol, int fixed) {
+    std::vector<int> gis;
+    std::vector<double2*> xs;
+    std::vector<int> xzs;
+    for (size_t gi = 0; gi < H->groups.size(); ++gi) {
+        gis.push_back((int)gi);
+        xs.push_back(P<double>(H->groups[gi].lv64[0].x[0]));
+        xzs.push_back(1);
+    }
+    enqueue_tails<double>(H, conj, st, gis, xs, xzs, maxc, tol, fixed);
+    return check_hip();
+}
+
 // in_place (one grid only): where the result would be copied out of the
 // level-0 buffers, leave it there instead and describe it (base pointer and
 // row layout selecting each system's buffer by its cycle count) for a
@@ -1402,12 +1441,23 @@ int solve_impl(vmg_handle* H, const double* B, double* Z, double tol, int conj, 
     // stop inside a batch: the device decides every stop exactly, the host
     // only avoids launching cycles for systems that have already stopped.
     int done = 0;
+    const bool whole = tail_solves(H) && maxc > 0;
     if (async) {
         for (auto& g : H->groups) g.nact = g.S;
+        if (whole) {
+            const int rc = enqueue_tail_solve(H, conj, st, maxc, tol, 1);
+            if (rc) return rc;
+            done = maxc;
+        }
         for (; done < maxc; ++done) {
             const int rc = run_cycle(H, conj, st, done, tol, 1);
             if (rc) return rc;
         }
+    } else if (whole) {
+        // (every system stops inside the launch: no host reads in between)
+        const int rc = enqueue_tail_solve(H, conj, st, maxc, tol, fixed != nullptr);
+        if (rc) return rc;
+        done = maxc;
     } else if (read_state(H, st)) {
         return VMG_HIP_ERROR;
     }
@@ -1755,6 +1805,7 @@ int vanka_mg_setup(const vmg_grid* grids, int32_t n_grids, const double* shifts,
     }
     H->S = total;
     if (const char* e = std::getenv("VMG_TAIL")) H->tail_on = std::atoi(e) != 0;
+    if (const char* e = std::getenv("VMG_TAIL_SOLVE")) H->tail_solve_on = std::atoi(e) != 0;
     if (const char* e = std::getenv("VMG_EDGE")) H->edge_mode = std::max(0, std::min(2, std::atoi(e)));
     if (const char* e = std::getenv("VMG_IR_EDGE")) H->ir_edge_mode = std::atoi(e) != 0;
     if (const char* e = std::getenv("VMG_EDGE_PACE")) H->pace_mode = std::atoi(e) != 0 ? 1 : 0;

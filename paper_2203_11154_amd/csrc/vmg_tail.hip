@@ -247,9 +247,9 @@ template <typename T>
 __global__ __launch_bounds__(TT) void k_tail(const TailSeg<T>* __restrict__ segs, TailLaunch<T> tl, int nu1, int nu2,
                                              int gamma) {
     using C = cplx<T>;
-    extern __shared__ double tail_lds[];
+    extern __shared__ __align__(16) double tail_lds[];
     // entry of this workgroup (selected without indexing the argument arrays)
-    int seg = tl.seg[0], z0 = tl.z0[0], xz = tl.xz[0];
+    int seg = tl.seg[0], z0 = tl.z0[0], xz = tl.xz[0], sys0 = tl.sys0[0];
     C* xg = tl.x[0];
 #pragma unroll
     for (int j = 1; j < MAXSEG; ++j)
@@ -258,6 +258,7 @@ __global__ __launch_bounds__(TT) void k_tail(const TailSeg<T>* __restrict__ segs
             z0 = tl.z0[j];
             xz = tl.xz[j];
             xg = tl.x[j];
+            sys0 = tl.sys0[j];
         }
     TailView<T> V;
     V.S = segs + seg;
@@ -280,6 +281,13 @@ __global__ __launch_bounds__(TT) void k_tail(const TailSeg<T>* __restrict__ segs
         if (t < padded(v0)) x0[t] = (xz || !inner) ? tz<C>() : gx[(int64_t)k * g0.pitch + i];
     }
     __syncthreads();
+    // whole solves: cycles until the system stops (at most tl.maxc); else one.
+    // red: the per-wave norm sums and (last slot) the go-on flag; 144 bytes,
+    // so that the dynamic LDS after it stays 16-byte aligned for the
+    // double2 accesses
+    __shared__ __align__(16) double red[TT / 64 + 2];
+    const int ncyc = tl.maxc > 0 ? tl.maxc : 1;
+    for (int cyc = 0; cyc < ncyc; ++cyc) {
     // MG(0) with gamma visits of every coarser level, without recursion:
     // cnt holds, 4 bits per level, the visits of the next level made so far
     unsigned cnt = 0;
@@ -310,6 +318,44 @@ __global__ __launch_bounds__(TT) void k_tail(const TailSeg<T>* __restrict__ segs
         for (int it = 0; it < nu2; ++it) smooth(V, p, f);
         l = p;
     }
+    if (tl.maxc == 0) break;
+    // the stopping test of k_norm_finalize on |b - L x|^2 of the finest
+    // level (fixed-order sums: per thread, wave, then the waves in order)
+    residual_first(V, f);
+    {
+        const C* r = V.lds + V.ro(0);
+        double acc = 0.0;
+#pragma unroll
+        for (int j = 0; j < Level0<T>::JMAX; ++j)
+            if ((f.in >> j) & 1u) {
+                const C rv = r[threadIdx.x + j * TT];
+                acc += (double)rv.x * (double)rv.x + (double)rv.y * (double)rv.y;
+            }
+        for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+        if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double sum = 0.0;
+        for (int w = 0; w < TT / 64; ++w) sum += red[w];
+        const int gs = sys0 + V.sys;
+        const int it = tl.iters[gs] + 1;
+        tl.iters[gs] = it;
+        const double rel = sqrt(sum / tl.bb[gs]);
+        tl.relres[gs] = rel;
+        int on = 1;
+        if (!(rel == rel) || rel > 1.0e300) {
+            tl.nanflag[gs] = 1;
+            on = 0;
+        } else if (it >= tl.target[gs] || (!tl.fixed && rel <= tl.tol)) {
+            on = 0;
+        }
+        if (!on) tl.active[gs] = 0;
+        red[TT / 64] = on ? 1.0 : 0.0;
+    }
+    __syncthreads();
+    if (red[TT / 64] == 0.0) break;
+    }
     for (int t = threadIdx.x; t < v0.nx * v0.ny; t += TT) {
         const int k = t / v0.nx + 1, i = t - (k - 1) * v0.nx + 1;
         gx[(int64_t)k * g0.pitch + i] = x0[k * (v0.nx + 2) + i];
@@ -337,10 +383,11 @@ int tail_max_lds() {
         int dev = 0, v = 0;
         if (hipGetDevice(&dev) != hipSuccess) dev = 0;
         if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess) v = 65536;
-        max_lds = v;
+        // (less the kernel's own static LDS: the whole-solve reduction slots)
+        max_lds = v - 256;
         // allow the dynamic allocation above the default limit
-        (void)hipFuncSetAttribute((const void*)&k_tail<double>, hipFuncAttributeMaxDynamicSharedMemorySize, v);
-        (void)hipFuncSetAttribute((const void*)&k_tail<float>, hipFuncAttributeMaxDynamicSharedMemorySize, v);
+        (void)hipFuncSetAttribute((const void*)&k_tail<double>, hipFuncAttributeMaxDynamicSharedMemorySize, max_lds);
+        (void)hipFuncSetAttribute((const void*)&k_tail<float>, hipFuncAttributeMaxDynamicSharedMemorySize, max_lds);
         (void)hipGetLastError();
     }
     return max_lds;
