@@ -431,7 +431,8 @@ int vanka_mg_schedule(const vmg_handle* h, int32_t g, int32_t nlev, int32_t* sch
  * boundary of two refinement steps), 2 when that kernel (refinement: the
  * step boundary pass) runs in paced blocks
  * (a CU's worth of waves on adjacent strips meeting at a barrier after every
- * block of rows), else 0; *tail_level = the first level whose work (down to
+ * block of rows; so do the finest level's first pre-smoothing and its
+ * finishing pass), else 0; *tail_level = the first level whose work (down to
  * the coarsest solve and back) runs in one workgroup per system, -1 when none
  * does.  Either pointer may be NULL.  Untuned, the cycle-edge kernel runs on
  * grids whose finest levels hold at least 16M nodes over all systems, in

@@ -253,11 +253,15 @@ size_t transform_scratch_doubles(int n);
 // at least rmin rows per wave.  c32 (T = double only): the coarse level (c,
 // and cb of the edge kernel) holds complex64 values; the pointers in the
 // segment are then float2 data, and the coarse views those of the complex64
-// level.
+// level.  paced (T = double, two Vanka sweeps): as for the cycle-edge
+// kernel below, where a CU holds a block of 12 or 16 of the paced waves as
+// it holds the plain ones (else the plain launch).
 template <typename T>
-void launch_down(SegTable<T> tab, const int* nsys, int nu, int rmin, hipStream_t st, bool c32 = false);
+void launch_down(SegTable<T> tab, const int* nsys, int nu, int rmin, hipStream_t st, bool c32 = false,
+                 bool paced = false);
 template <typename T>
-void launch_up(SegTable<T> tab, const int* nsys, int nu, bool norm, int rmin, hipStream_t st, bool c32 = false);
+void launch_up(SegTable<T> tab, const int* nsys, int nu, bool norm, int rmin, hipStream_t st, bool c32 = false,
+               bool paced = false);
 template <typename T> int stream_tiles(int nx, int ny, int nsys, int nu, int rmin);
 int stream_tiles_max(int nx, int ny, int nu);  // over every rmin and kernel
 // Cycle-edge kernel (FP64 finest level, nu1, nu2 in {1, 2}): correction +

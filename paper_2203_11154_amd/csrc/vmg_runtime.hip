@@ -435,6 +435,13 @@ int edge_paced(const vmg_handle* H, const Group& g) {
     return H->pace_mode >= 0 ? H->pace_mode : g.edge_pace;
 }
 
+// So do the FP64 finest level's first pre-smoothing and restriction and the
+// finishing pass (the streaming launches of that level a solve keeps besides
+// the cycle-edge kernel).
+bool level0_paced(const vmg_handle* H, const Group& g) {
+    return fine_f64(H->opts) && H->opts.smoother == 0 && use_edge(H, g) && edge_paced(H, g) != 0;
+}
+
 // Refinement (complex64 V-cycles in FP64 refinement): the boundary of two
 // steps runs in one pass (k_ir_edge) on grids whose complex64 finest level
 // uses the cycle-edge kernel.
@@ -697,15 +704,19 @@ void enqueue_batched_vcycle(vmg_handle* H, int conj, hipStream_t st, bool first,
             (sched_stream(H, H->groups[gi], l) ? sg : lg).push_back(gi);
         }
         // streamed grids: one fused launch per row-block height
+        auto paced_at = [&](int gi) {
+            return std::is_same<T, double>::value && level_of(gi, d) == 0 && level0_paced(H, H->groups[gi]);
+        };
         while (!sg.empty()) {
             const int ty = sched_rows(H, H->groups[sg[0]], level_of(sg[0], d));
+            const bool pace = paced_at(sg[0]);
             SegBatch<T> bt;
             std::vector<int> rest, done;
             for (int gi : sg) {
                 Group& g = H->groups[gi];
                 const int l = level_of(gi, d);
                 auto& L = levels_of<T>(g);
-                if (sched_rows(H, g, l) != ty || bt.full()) {
+                if (sched_rows(H, g, l) != ty || paced_at(gi) != pace || bt.full()) {
                     rest.push_back(gi);
                     continue;
                 }
@@ -717,7 +728,7 @@ void enqueue_batched_vcycle(vmg_handle* H, int conj, hipStream_t st, bool first,
             }
             {
                 Timer t(H, st, VMG_K_DOWN, bt.bytes, level_of(done[0], d));
-                launch_down<T>(bt.tab, bt.nsys, o.nu1, ty, st);
+                launch_down<T>(bt.tab, bt.nsys, o.nu1, ty, st, false, pace);
             }
             for (int gi : done) {
                 Group& g = H->groups[gi];
@@ -944,11 +955,12 @@ void enqueue_mixed_vcycle(vmg_handle* H, int conj, hipStream_t st, bool first, s
         if (first || !use_edge(H, H->groups[gi])) sg.push_back(gi);
     while (!sg.empty()) {
         const int ty = sched_rows(H, H->groups[sg[0]], 0);
+        const bool pace = level0_paced(H, H->groups[sg[0]]);
         SegBatch<double> bt;
         std::vector<int> rest, done;
         for (int gi : sg) {
             Group& g = H->groups[gi];
-            if (sched_rows(H, g, 0) != ty || bt.full()) {
+            if (sched_rows(H, g, 0) != ty || level0_paced(H, g) != pace || bt.full()) {
                 rest.push_back(gi);
                 continue;
             }
@@ -962,7 +974,7 @@ void enqueue_mixed_vcycle(vmg_handle* H, int conj, hipStream_t st, bool first, s
         }
         {
             Timer t(H, st, VMG_K_DOWN, bt.bytes, 0);
-            launch_down<double>(bt.tab, bt.nsys, o.nu1, ty, st, true);
+            launch_down<double>(bt.tab, bt.nsys, o.nu1, ty, st, true, pace);
         }
         for (int gi : done) {
             Group& g = H->groups[gi];
@@ -1490,7 +1502,7 @@ int solve_impl(vmg_handle* H, const double* B, double* Z, double tol, int conj, 
             S.iters = H->iters + g.sys0;
             S.zd = reinterpret_cast<double2*>(Z) + off;
             const int one = g.S;
-            launch_up<double>(one_seg(S), &one, o.nu2, false, sched_rows(H, g, 0), st, c32);
+            launch_up<double>(one_seg(S), &one, o.nu2, false, sched_rows(H, g, 0), st, c32, level0_paced(H, g));
         } else {
             // (refinement: after k steps the FP64 iterate is in buffer k mod 2)
             const int flips = fine_f64(o) ? level0_flips(H, g) : 1;

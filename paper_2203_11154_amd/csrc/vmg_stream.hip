@@ -367,7 +367,7 @@ template <typename Pipe> __device__ __forceinline__ void set_rows(Pipe& p, bool 
 
 // One wave's share of the work: rows k0..k1 of strip `strip` of system
 // `sys` of segment S (the pipeline adds its halo rows itself).
-template <typename T, int NS, typename TC, bool JAC>
+template <typename T, int NS, typename TC, bool JAC, bool PACE = false>
 __device__ __forceinline__ void down_piece(const LevelSeg<T>& S, int sys, int strip, int k0, int k1, bool rev,
                                            int lane) {
     using C = cplx<T>;
@@ -416,9 +416,19 @@ __device__ __forceinline__ void down_piece(const LevelSeg<T>& S, int sys, int st
         p.br[d] = p.template load_b<true>(jbeg + d - 1);
     }
     int j = jbeg;
-    for (; j <= jend && j < jlo; j += UNR) p.template block<true>(j);
-    for (; j <= jhi; j += UNR) p.template block<false>(j);
-    for (; j <= jend; j += UNR) p.template block<true>(j);
+    // (PACE: as in edge_piece)
+    for (; j <= jend && j < jlo; j += UNR) {
+        p.template block<true>(j);
+        if constexpr (PACE) __syncthreads();
+    }
+    for (; j <= jhi; j += UNR) {
+        p.template block<false>(j);
+        if constexpr (PACE) __syncthreads();
+    }
+    for (; j <= jend; j += UNR) {
+        p.template block<true>(j);
+        if constexpr (PACE) __syncthreads();
+    }
 }
 
 // Segment of global wave gw (segments own consecutive wave ranges).
@@ -454,18 +464,19 @@ template <typename T> __device__ __forceinline__ Piece piece_of(const LevelSeg<T
 }
 
 // ---------------------------------------------------------------------------
-template <typename T, int NS, typename TC, bool JAC = false>
-__global__ __launch_bounds__(NT) void k_down(SegTable<T> tab) {
+// WB waves a block (more than NT / 64: paced blocks, see edge_piece)
+template <typename T, int NS, typename TC, bool JAC = false, int WB = NT / 64>
+__global__ __launch_bounds__(64 * WB) void k_down(SegTable<T> tab) {
     // the wave index is uniform over the wave; say so, so that everything
     // derived from it (segment, buffer resources, row bounds) lives in SGPRs
-    const int gw = (int)xcd_block().x * (NT / 64) + __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int gw = (int)xcd_block().x * WB + __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const int lane = threadIdx.x & 63;
     const LevelSeg<T> S = seg_of_wave(tab, gw);
     const int lw = gw - S.w0;
-    if (lw >= S.waves) return;  // whole wave idle; no block barriers in this kernel
+    if (lw >= S.waves) return;  // whole wave idle (paced blocks: see edge_piece)
     const Piece pc = piece_of(S, lw);
     if (pc.k0 > pc.k1 || !S.active[pc.sys]) return;
-    down_piece<T, NS, TC, JAC>(S, pc.sys, pc.strip, pc.k0, pc.k1, pc.rev, lane);
+    down_piece<T, NS, TC, JAC, (WB > NT / 64)>(S, pc.sys, pc.strip, pc.k0, pc.k1, pc.rev, lane);
 }
 
 template <typename T, int NS, bool NORM, typename TC = T, bool JAC = false>
@@ -592,7 +603,7 @@ struct UpPipe {
 
 // Rows k0..k1 of one strip of one system; returns the lane's share of
 // sum |b - L x|^2 over the owned columns and rows (NORM).
-template <typename T, int NS, bool NORM, typename TC, bool JAC>
+template <typename T, int NS, bool NORM, typename TC, bool JAC, bool PACE = false>
 __device__ __forceinline__ double up_piece(const LevelSeg<T>& S, int sys, int strip, int k0, int k1, bool rev,
                                            int lane) {
     using C = cplx<T>;
@@ -663,28 +674,39 @@ __device__ __forceinline__ double up_piece(const LevelSeg<T>& S, int sys, int st
         p.br[d] = p.template load_b<true>(jbeg + d - 1);
     }
     int j = jbeg;
-    for (; j <= jend && j < jlo; j += UNR) p.template block<true>(j);
-    for (; j <= jhi; j += UNR) p.template block<false>(j);
-    for (; j <= jend; j += UNR) p.template block<true>(j);
+    // (PACE: as in edge_piece)
+    for (; j <= jend && j < jlo; j += UNR) {
+        p.template block<true>(j);
+        if constexpr (PACE) __syncthreads();
+    }
+    for (; j <= jhi; j += UNR) {
+        p.template block<false>(j);
+        if constexpr (PACE) __syncthreads();
+    }
+    for (; j <= jend; j += UNR) {
+        p.template block<true>(j);
+        if constexpr (PACE) __syncthreads();
+    }
     return own ? p.acc : 0.0;
 }
 
 // ---------------------------------------------------------------------------
 // With NORM, every wave leaves its run's sum in the segment's partial buffer
 // (slot = the wave's index in the segment, S.pieces * S.strips per system).
-template <typename T, int NS, bool NORM, typename TC, bool JAC = false>
-__global__ __launch_bounds__(NT) void k_up(SegTable<T> tab) {
+template <typename T, int NS, bool NORM, typename TC, bool JAC = false, int WB = NT / 64>
+__global__ __launch_bounds__(64 * WB) void k_up(SegTable<T> tab) {
     // the wave index is uniform over the wave; say so, so that everything
     // derived from it (segment, buffer resources, row bounds) lives in SGPRs
-    const int gw = (int)xcd_block().x * (NT / 64) + __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int gw = (int)xcd_block().x * WB + __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const int lane = threadIdx.x & 63;
     const LevelSeg<T> S = seg_of_wave(tab, gw);
     const int lw = gw - S.w0;
-    if (lw >= S.waves) return;  // whole wave idle; no block barriers in this kernel
+    if (lw >= S.waves) return;  // whole wave idle (paced blocks: see edge_piece)
     const Piece pc = piece_of(S, lw);
     if (!S.iters && !S.active[pc.sys]) return;  // (the finishing pass runs for every system)
     double acc = 0.0;
-    if (pc.k0 <= pc.k1) acc = up_piece<T, NS, NORM, TC, JAC>(S, pc.sys, pc.strip, pc.k0, pc.k1, pc.rev, lane);
+    if (pc.k0 <= pc.k1)
+        acc = up_piece<T, NS, NORM, TC, JAC, (WB > NT / 64)>(S, pc.sys, pc.strip, pc.k0, pc.k1, pc.rev, lane);
     if (NORM && S.partial) {
         for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
         if (lane == 0) S.partial[pc.slot] = acc;
@@ -1282,19 +1304,51 @@ dim3 stream_seg_grid(SegTable<T>& tab, const int* nsys, int own, int col0, int h
 // level has the precision of its own, so that a kernel reading or writing
 // complex64 coarse values splits its level, and its norm partial sums, the
 // same way)
-template <typename T, int NS, typename TC> void down_go(SegTable<T> tab, const int* nsys, int rmin, hipStream_t st) {
+// Paced blocks (see edge_piece) for the FP64 Vanka kernels with two sweeps
+// that open and close a solve on the finest level: WB = the waves a CU holds
+// of the plain kernel (12 for k_down, 16 for k_up without the norm), launched
+// only where a CU holds one block of them, so that the run geometry the plain
+// grid was cut for stays the same.
+template <int WB, typename T> dim3 paced_grid(const SegTable<T>& tab, const void* kp, int resident) {
+    if (resident_waves(kp, 64 * WB) != resident) return dim3(0);
+    const int w = tab.s[tab.n - 1].w0 + tab.s[tab.n - 1].waves;
+    return dim3((w + WB - 1) / WB);
+}
+constexpr int DOWN_WB = 12, UP_WB = 16;
+
+template <typename T, int NS, typename TC>
+void down_go(SegTable<T> tab, const int* nsys, int rmin, hipStream_t st, bool paced) {
     const void* k = (const void*)&k_down<T, NS, T>;
-    const dim3 g = stream_seg_grid(tab, nsys, down_own<NS>(), 1, 4 * NS + 9, rmin, resident_waves(k));
+    const int resident = resident_waves(k);
+    const dim3 g = stream_seg_grid(tab, nsys, down_own<NS>(), 1, 4 * NS + 9, rmin, resident);
     if (g.x == 0) return;
+    if constexpr (std::is_same<T, double>::value && NS == 2) {
+        if (paced && !tab.s[0].jacobi) {
+            const dim3 gp = paced_grid<DOWN_WB>(tab, (const void*)&k_down<T, NS, TC, false, DOWN_WB>, resident);
+            if (gp.x) {
+                hipLaunchKernelGGL((k_down<T, NS, TC, false, DOWN_WB>), gp, dim3(64 * DOWN_WB), 0, st, tab);
+                return;
+            }
+        }
+    }
     if (tab.s[0].jacobi) hipLaunchKernelGGL((k_down<T, NS, TC, true>), g, dim3(NT), 0, st, tab);
     else hipLaunchKernelGGL((k_down<T, NS, TC, false>), g, dim3(NT), 0, st, tab);
 }
 template <typename T, int NS, bool NORM, typename TC>
-void up_go(SegTable<T> tab, const int* nsys, int rmin, hipStream_t st) {
+void up_go(SegTable<T> tab, const int* nsys, int rmin, hipStream_t st, bool paced) {
     const void* k = (const void*)&k_up<T, NS, NORM, T>;
-    const dim3 g = stream_seg_grid(tab, nsys, up_own<NS, NORM>(), UpPipe<T, NS, NORM>::COL0, 4 * NS + 7, rmin,
-                                   resident_waves(k));
+    const int resident = resident_waves(k);
+    const dim3 g = stream_seg_grid(tab, nsys, up_own<NS, NORM>(), UpPipe<T, NS, NORM>::COL0, 4 * NS + 7, rmin, resident);
     if (g.x == 0) return;
+    if constexpr (std::is_same<T, double>::value && NS == 2 && !NORM) {
+        if (paced && !tab.s[0].jacobi) {
+            const dim3 gp = paced_grid<UP_WB>(tab, (const void*)&k_up<T, NS, NORM, TC, false, UP_WB>, resident);
+            if (gp.x) {
+                hipLaunchKernelGGL((k_up<T, NS, NORM, TC, false, UP_WB>), gp, dim3(64 * UP_WB), 0, st, tab);
+                return;
+            }
+        }
+    }
     if (tab.s[0].jacobi) hipLaunchKernelGGL((k_up<T, NS, NORM, TC, true>), g, dim3(NT), 0, st, tab);
     else hipLaunchKernelGGL((k_up<T, NS, NORM, TC, false>), g, dim3(NT), 0, st, tab);
 }
@@ -1441,49 +1495,51 @@ int stream_tiles_max(int nx, int ny, int nu) {
 }
 template int stream_tiles<float>(int, int, int, int, int);
 
-template <typename T, typename TC> void down_launch(SegTable<T> tab, const int* nsys, int nu, int ty, hipStream_t st) {
+template <typename T, typename TC>
+void down_launch(SegTable<T> tab, const int* nsys, int nu, int ty, hipStream_t st, bool paced) {
     switch (nu) {
-        case 0: down_go<T, 0, TC>(tab, nsys, ty, st); break;
-        case 1: down_go<T, 1, TC>(tab, nsys, ty, st); break;
-        default: down_go<T, 2, TC>(tab, nsys, ty, st); break;
+        case 0: down_go<T, 0, TC>(tab, nsys, ty, st, paced); break;
+        case 1: down_go<T, 1, TC>(tab, nsys, ty, st, paced); break;
+        default: down_go<T, 2, TC>(tab, nsys, ty, st, paced); break;
     }
 }
-template <typename T> void launch_down(SegTable<T> tab, const int* nsys, int nu, int ty, hipStream_t st, bool c32) {
+template <typename T>
+void launch_down(SegTable<T> tab, const int* nsys, int nu, int ty, hipStream_t st, bool c32, bool paced) {
     if constexpr (std::is_same<T, double>::value) {
         if (c32) {
-            down_launch<double, float>(tab, nsys, nu, ty, st);
+            down_launch<double, float>(tab, nsys, nu, ty, st, paced);
             return;
         }
     }
-    down_launch<T, T>(tab, nsys, nu, ty, st);
+    down_launch<T, T>(tab, nsys, nu, ty, st, paced);
 }
 
 template <typename T, typename TC>
-void up_launch(SegTable<T> tab, const int* nsys, int nu, bool norm, int ty, hipStream_t st) {
+void up_launch(SegTable<T> tab, const int* nsys, int nu, bool norm, int ty, hipStream_t st, bool paced) {
     switch (nu) {
         case 0:
-            if (norm) up_go<T, 0, true, TC>(tab, nsys, ty, st);
-            else up_go<T, 0, false, TC>(tab, nsys, ty, st);
+            if (norm) up_go<T, 0, true, TC>(tab, nsys, ty, st, paced);
+            else up_go<T, 0, false, TC>(tab, nsys, ty, st, paced);
             break;
         case 1:
-            if (norm) up_go<T, 1, true, TC>(tab, nsys, ty, st);
-            else up_go<T, 1, false, TC>(tab, nsys, ty, st);
+            if (norm) up_go<T, 1, true, TC>(tab, nsys, ty, st, paced);
+            else up_go<T, 1, false, TC>(tab, nsys, ty, st, paced);
             break;
         default:
-            if (norm) up_go<T, 2, true, TC>(tab, nsys, ty, st);
-            else up_go<T, 2, false, TC>(tab, nsys, ty, st);
+            if (norm) up_go<T, 2, true, TC>(tab, nsys, ty, st, paced);
+            else up_go<T, 2, false, TC>(tab, nsys, ty, st, paced);
             break;
     }
 }
 template <typename T>
-void launch_up(SegTable<T> tab, const int* nsys, int nu, bool norm, int ty, hipStream_t st, bool c32) {
+void launch_up(SegTable<T> tab, const int* nsys, int nu, bool norm, int ty, hipStream_t st, bool c32, bool paced) {
     if constexpr (std::is_same<T, double>::value) {
         if (c32) {
-            up_launch<double, float>(tab, nsys, nu, norm, ty, st);
+            up_launch<double, float>(tab, nsys, nu, norm, ty, st, paced);
             return;
         }
     }
-    up_launch<T, T>(tab, nsys, nu, norm, ty, st);
+    up_launch<T, T>(tab, nsys, nu, norm, ty, st, paced);
 }
 
 template <typename T> void launch_fill_zero(cplx<T>* x, LevelView lv, int nsys, hipStream_t st) {
@@ -1492,9 +1548,9 @@ template <typename T> void launch_fill_zero(cplx<T>* x, LevelView lv, int nsys, 
 template void launch_fill_zero<double>(double2*, LevelView, int, hipStream_t);
 template void launch_fill_zero<float>(float2*, LevelView, int, hipStream_t);
 
-template void launch_down<double>(SegTable<double>, const int*, int, int, hipStream_t, bool);
-template void launch_down<float>(SegTable<float>, const int*, int, int, hipStream_t, bool);
-template void launch_up<double>(SegTable<double>, const int*, int, bool, int, hipStream_t, bool);
-template void launch_up<float>(SegTable<float>, const int*, int, bool, int, hipStream_t, bool);
+template void launch_down<double>(SegTable<double>, const int*, int, int, hipStream_t, bool, bool);
+template void launch_down<float>(SegTable<float>, const int*, int, int, hipStream_t, bool, bool);
+template void launch_up<double>(SegTable<double>, const int*, int, bool, int, hipStream_t, bool, bool);
+template void launch_up<float>(SegTable<float>, const int*, int, bool, int, hipStream_t, bool, bool);
 
 }  // namespace vmg

@@ -180,6 +180,38 @@ def test_forced_edge_kernel_vs_oracle(nu1, nu2, pace, precision, monkeypatch):
             off += m
 
 
+@pytest.mark.parametrize("precision", ["c128", "c128_c64"])
+def test_paced_blocks_bitwise_equal_plain(precision, monkeypatch):
+    """Paced blocks change when the waves run, not what they compute: with
+    VMG_EDGE_PACE=1 the cycle-edge kernel, the first pre-smoothing and
+    restriction and the finishing pass of V(2,2) on the finest level (both
+    grids of one launch, ragged strips and runs) give bitwise the iterates
+    of the plain blocks, at free-running and at fixed counts."""
+    from paper_2203_11154_amd import Grid, VankaMG
+    monkeypatch.setenv("VMG_EDGE", "2")
+    grids = [dict(nx=223, ny=111, h=1.0 / 224, S=3), dict(nx=127, ny=255, h=1.0 / 128, S=2)]
+    lam = np.concatenate([inputs.alpha_circulant_shifts(3), inputs.uniform_shifts(2)])
+    bs = [inputs.rhs(g["S"], g["ny"], g["nx"], seed=90 + k) for k, g in enumerate(grids)]
+    bd = dev(np.concatenate([x.ravel() for x in bs]))
+    out = {}
+    for pace in ("0", "1"):
+        monkeypatch.setenv("VMG_EDGE_PACE", pace)
+        gs = [Grid(g["nx"], g["ny"], h=g["h"], num_systems=g["S"], levels=5) for g in grids]
+        solver = VankaMG(gs, lam, nu1=2, nu2=2, precision=precision)
+        assert all(solver.plan(g)[0] == (2 if pace == "1" else 1) for g in range(len(grids)))
+        Z, iters, relres, status = solver.solve(bd, tol=1e-10)
+        assert status == 0 and np.all(relres <= 1e-10)
+        fixed = np.arange(len(lam), dtype=np.int32) % 3 + 1
+        Zf, itf, _, _ = solver.solve(bd, fixed_iters=fixed)
+        np.testing.assert_array_equal(itf, fixed)
+        out[pace] = (host(Z), iters, relres, host(Zf))
+        del solver
+    (z0, i0, r0, f0), (z1, i1, r1, f1) = out["0"], out["1"]
+    np.testing.assert_array_equal(i0, i1)
+    np.testing.assert_array_equal(r0, r1)
+    assert np.array_equal(z0, z1) and np.array_equal(f0, f1)
+
+
 def test_example2_vs_oracle():
     """Example 2 (eq. (10), beta = 0.01, h = tau = 1/256): the shift with the
     most negative real part and the one with the largest real part, W(1,0)
