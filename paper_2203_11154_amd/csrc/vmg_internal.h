@@ -87,6 +87,21 @@ template <typename T> struct SegTable {
 };
 
 #ifdef __HIPCC__
+// The hardware hands consecutive workgroups of a launch to the chip's eight
+// XCDs in turn, and each XCD has its own L2.  Renumber the blocks so that
+// every XCD receives one contiguous run of the logical order (x fastest):
+// strips that share halo columns, or tiles that share the cache lines at
+// their ends, then meet in the same L2.
+constexpr unsigned NXCD = 8;
+__device__ __forceinline__ uint3 xcd_block() {
+    const unsigned gx = gridDim.x, gxy = gridDim.x * gridDim.y;
+    const unsigned n = gxy * gridDim.z;
+    const unsigned L = blockIdx.x + gx * blockIdx.y + gxy * blockIdx.z;
+    const unsigned xcd = L % NXCD, k = L / NXCD, q = n / NXCD, r = n % NXCD;
+    const unsigned Lp = xcd * q + min(xcd, r) + k;
+    return make_uint3(Lp % gx, (Lp % gxy) / gx, Lp / gxy);
+}
+
 template <typename T> __device__ __forceinline__ LevelSeg<T> seg_of(const SegTable<T>& t, int z) {
     LevelSeg<T> r = t.s[0];
 #pragma unroll

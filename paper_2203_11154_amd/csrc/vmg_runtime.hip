@@ -126,7 +126,6 @@ struct vmg_handle {
     int* active = nullptr;
     int* target = nullptr;
     int* nanflag = nullptr;
-    int stream_rows = 0;       // rows per block of the streaming kernels (0: by level size)
     bool tail_on = true;       // small levels in one workgroup per system (VMG_TAIL=0 turns it off)
     bool tail_solve_on = true; // whole solves in one tail launch where the tail covers every level
                                // (VMG_TAIL_SOLVE=0: one launch and one host-side stopping test a cycle)
@@ -397,8 +396,7 @@ bool use_stream(const vmg_opts& o, const LevelView& v, int l) {
 
 // Rows per block: tall blocks amortise the pipeline's start-up rows, short
 // ones give small levels enough blocks to fill the GPU.
-int stream_rows_for(const vmg_handle* H, const LevelView& v) {
-    if (H->stream_rows > 0) return H->stream_rows;
+int stream_rows_for(const LevelView& v) {
     return v.ny > 600 ? 128 : (v.ny > 200 ? 64 : 32);
 }
 
@@ -456,7 +454,7 @@ int ir_level0_parity(const vmg_opts& o, int64_t c) { return (int)((1 + c * o.ir_
 
 int sched_rows(const vmg_handle* H, const Group& g, int l) {
     if ((int)g.sched.size() > l && g.sched[l] > 0) return g.sched[l];
-    return stream_rows_for(H, cycle_view(H, g, l));
+    return stream_rows_for(cycle_view(H, g, l));
 }
 
 // One grid's segment at level l (see LevelSeg).
@@ -1821,10 +1819,6 @@ int vanka_mg_setup(const vmg_grid* grids, int32_t n_grids, const double* shifts,
     if (const char* e = std::getenv("VMG_EDGE")) H->edge_mode = std::max(0, std::min(2, std::atoi(e)));
     if (const char* e = std::getenv("VMG_IR_EDGE")) H->ir_edge_mode = std::atoi(e) != 0;
     if (const char* e = std::getenv("VMG_EDGE_PACE")) H->pace_mode = std::atoi(e) != 0 ? 1 : 0;
-    if (const char* e = std::getenv("VMG_STREAM_ROWS")) {
-        const int r = std::atoi(e);
-        if (r >= 16 && r <= 4096) H->stream_rows = r;
-    }
     H->shifts.resize(total);
     for (int s = 0; s < total; ++s) H->shifts[s] = cd(shifts[2 * s], shifts[2 * s + 1]);
     stream_prepare();

@@ -206,20 +206,6 @@ __device__ __forceinline__ unsigned row_off(bool ok, int j, int pitch, int es) {
     return ok ? (unsigned)(j * pitch * es) : OOB;
 }
 
-// The hardware hands consecutive workgroups of a launch to the chip's eight
-// XCDs in turn, and each XCD has its own L2.  Renumber the blocks so that
-// every XCD receives one contiguous run of the logical order (x fastest):
-// strips that share halo columns then meet in the same L2.
-constexpr unsigned NXCD = 8;
-__device__ __forceinline__ uint3 xcd_block() {
-    const unsigned gx = gridDim.x, gxy = gridDim.x * gridDim.y;
-    const unsigned n = gxy * gridDim.z;
-    const unsigned L = blockIdx.x + gx * blockIdx.y + gxy * blockIdx.z;
-    const unsigned xcd = L % NXCD, k = L / NXCD, q = n / NXCD, r = n % NXCD;
-    const unsigned Lp = xcd * q + min(xcd, r) + k;
-    return make_uint3(Lp % gx, (Lp % gxy) / gx, Lp / gxy);
-}
-
 // Row pipelines.  Both kernels advance one grid row per step and are
 // unrolled by UNR steps, so that every ring of rows below has a length that
 // divides UNR and all ring slots are compile-time constants (no register

@@ -113,10 +113,11 @@ __global__ __launch_bounds__(TN) __attribute__((amdgpu_waves_per_eu(4))) void k_
     const int n2 = 2 * n;
     const NodeMap mi(li), mo(lo);
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int row0 = blockIdx.y * ROWS;
+    const uint3 xb = xcd_block();
+    const int row0 = xb.y * ROWS;
     const int tpr = (tx + COLS - 1) / COLS;
-    const int grow = blockIdx.x / tpr;
-    const int gcol0 = (blockIdx.x - grow * tpr) * COLS;  // first column of the block in its grid row
+    const int grow = xb.x / tpr;
+    const int gcol0 = (xb.x - grow * tpr) * COLS;  // first column of the block in its grid row
     const int64_t col0 = (int64_t)grow * tx + gcol0;     // its node
     const int wrow = row0 + wave * 32;
     const bool wave_active = wrow < n2;
@@ -278,7 +279,9 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(4))) vo
             sB[buf][2 * lrow + 1][lcol + q * LS] = rb[q].y;
         }
     };
-    int64_t tile = blockIdx.x;
+    // (neighbouring tiles, which share the cache lines at their ends in planes
+    // that do not start on a line, run on one XCD)
+    int64_t tile = xcd_block().x;
     if (tile >= ntiles) return;  // uniform over the block (never with NORM: one tile a block at least)
     if constexpr (NORM) {
         sN[2 * threadIdx.x] = 0.0;  // |out|^2 of the lane's two complex rows
@@ -449,9 +452,10 @@ __global__ __launch_bounds__(FT) void k_circ_dft(int logn, int64_t m, int sign, 
             rb[q] = (live && p < m) ? in[base + mi(p)] : make_double2(0.0, 0.0);
         }
     };
-    if (blockIdx.x < ntiles) fetch(blockIdx.x);
+    const int64_t t0 = xcd_block().x;  // (as in k_transform_reg)
+    if (t0 < ntiles) fetch(t0);
     __syncthreads();
-    for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    for (int64_t tile = t0; tile < ntiles; tile += gridDim.x) {
         const int64_t p0 = tile * tn;
 #pragma unroll
         for (int q = 0; q < LD; ++q) {
