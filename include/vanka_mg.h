@@ -411,8 +411,8 @@ int vanka_mg_last_stats(vmg_handle* h, int32_t* iters, double* relres, void* hip
 /*
  * Autotuner: for every grid and level above the coarsest, time each kernel
  * schedule on the handle's own buffers (the LDS-tiled sweep / restriction /
- * prolongation kernels, or the fused streaming kernels with 32, 64 or 128
- * rows per block; on the finest level also the cycle-edge kernel, see
+ * prolongation kernels, or the fused streaming kernels with 16, 32, 64 or
+ * 128 rows per block; on the finest level also the cycle-edge kernel, see
  * vanka_mg_plan) and keep the fastest.  cache_path (host string, NULL = no
  * cache) is a text file of earlier choices keyed by device, precision, grid,
  * system count and smoothing counts; new choices are appended.  Results of

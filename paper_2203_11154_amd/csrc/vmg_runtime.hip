@@ -397,7 +397,7 @@ bool use_stream(const vmg_opts& o, const LevelView& v, int l) {
 // Rows per block: tall blocks amortise the pipeline's start-up rows, short
 // ones give small levels enough blocks to fill the GPU.
 int stream_rows_for(const LevelView& v) {
-    return v.ny > 600 ? 128 : (v.ny > 200 ? 64 : 32);
+    return v.ny > 600 ? 128 : (v.ny > 200 ? 64 : 16);
 }
 
 const LevelView& cycle_view(const vmg_handle* H, const Group& g, int l) {
@@ -2637,7 +2637,7 @@ extern "C" int vanka_mg_autotune(vmg_handle* H, const char* cache_path, void* hi
             std::vector<int> cands;
             if (!mixed0) cands.push_back(0);
             if (H->opts.nu1 <= 2 && H->opts.nu2 <= 2 && v.nx >= 32 && stream_fits(H->opts, v, l))
-                for (int r : {32, 64, 128})
+                for (int r : {16, 32, 64, 128})
                     if (r <= 2 * v.ny) cands.push_back(r);
             if (cands.empty()) continue;  // (precision 2 keeps its heuristic; setup checked it streams)
             int best = 0;

@@ -137,14 +137,14 @@ def test_full_uneven_workload():
 
 
 def test_autotuned_schedule_parity(tmp_path):
-    """The autotuner's per-level choice (LDS-tiled or streaming with 32/64/128
+    """The autotuner's per-level choice (LDS-tiled or streaming with 16/32/64/128
     rows) is a valid schedule, is reused from its cache, and the tuned solve
     matches the oracle at fixed counts."""
     cache = tmp_path / "tune.txt"
     solver, lam, bs = setup(SMALL)
     scheds = solver.autotune(cache)
     for (n, c), sc in zip(SMALL, scheds):
-        assert sc[-1] == -1 and all(v in (0, 32, 64, 128) for v in sc[:-1])
+        assert sc[-1] == -1 and all(v in (0, 16, 32, 64, 128) for v in sc[:-1])
     text = cache.read_text()
     # one line per grid and level, plus one "edge" line for each grid whose
     # finest level was tuned to stream (the cycle-edge kernel is timed only
