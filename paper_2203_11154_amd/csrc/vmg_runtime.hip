@@ -2484,7 +2484,9 @@ template <typename T> int time_level(vmg_handle* H, Group& g, int l, int cand, h
     };
     auto run = [&]() {
         if (cand > 0) {
-            launch_down<T>(seg(P<T>(lv.x[0]), P<T>(lv.b), P<T>(lv.x[1]), P<T>(lc.b), 0), &one, o.nu1, cand, st);
+            // (the coarse levels start every visit from zero, as in the cycle)
+            launch_down<T>(seg(P<T>(lv.x[0]), P<T>(lv.b), P<T>(lv.x[1]), P<T>(lc.b), l > 0 ? 1 : 0), &one, o.nu1,
+                           cand, st);
             launch_up<T>(seg(P<T>(lv.x[1]), P<T>(lv.b), P<T>(lv.x[0]), P<T>(lc.x[0]), 0), &one, o.nu2, l == 0, cand,
                          st);
         } else {
@@ -2572,16 +2574,24 @@ int time_ir_edge(vmg_handle* H, Group& g, int rows, hipStream_t st, double* ms_o
     return time_reps(run, st, ms_out);
 }
 
+// (two untimed runs, whose time sets the repetitions: at least 5, about 4 ms
+// of timed work, at most 40)
 template <typename F> int time_reps(F&& run, hipStream_t st, double* ms_out) {
     hipEvent_t a = nullptr, b = nullptr;
     if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) return VMG_HIP_ERROR;
-    for (int w = 0; w < 2; ++w) run();
     (void)hipEventRecord(a, st);
-    const int reps = 5;
-    for (int r = 0; r < reps; ++r) run();
+    for (int w = 0; w < 2; ++w) run();
     (void)hipEventRecord(b, st);
     int rc = check_hip();
     float ms = 0.f;
+    if (!rc && (hipEventSynchronize(b) != hipSuccess || hipEventElapsedTime(&ms, a, b) != hipSuccess)) rc = VMG_HIP_ERROR;
+    const int reps = std::max(5, std::min(40, (int)(8.0 / std::max(1e-3, (double)ms))));
+    if (!rc) {
+        (void)hipEventRecord(a, st);
+        for (int r = 0; r < reps; ++r) run();
+        (void)hipEventRecord(b, st);
+        rc = check_hip();
+    }
     if (!rc && (hipEventSynchronize(b) != hipSuccess || hipEventElapsedTime(&ms, a, b) != hipSuccess)) rc = VMG_HIP_ERROR;
     (void)hipEventDestroy(a);
     (void)hipEventDestroy(b);
