@@ -37,12 +37,13 @@ FP64_MFMA_PEAK_TFLOPS = 78.6
 # HBM bytes per launch of the dominant kernel measured with rocprofv3
 # FETCH_SIZE and WRITE_SIZE on each workload, each scaled by its reading for a
 # plain 1 GiB copy (profiles/), for its plain-block (plan 1) and paced-block
-# (plan 2) form (both the autotuner's candidates in the same runs).  Valid
+# (plan 2) form (the autotuned run's form, and the other one with
+# VMG_EDGE_PACE set).  Valid
 # only for the kernel source it was measured on: reported as null once that
 # file changes.
-MEASURED_TRAFFIC = {"source": "vmg_stream.hip", "source_sha256_16": "ab09dead015ff5cf",
-                    "bytes_per_launch": {"precision_2047": {1: 8099.0e6, 2: 7710.9e6},
-                                         "plain_1023": {1: 4047.1e6, 2: 3886.6e6}}}
+MEASURED_TRAFFIC = {"source": "vmg_stream.hip", "source_sha256_16": "bbed6faedf3f4869",
+                    "bytes_per_launch": {"precision_2047": {1: 8125.3e6, 2: 7743.3e6},
+                                         "plain_1023": {1: 4048.1e6, 2: 3882.5e6}}}
 # finest level across the boundary of two V-cycles: correction + 2 sweeps +
 # stopping-test norm, then the next cycle's 2 sweeps + residual + restriction
 # (template arguments: precision, sweeps after and before the boundary, the
