@@ -233,12 +233,25 @@ template <typename T> __device__ void coarse_solve(const TailView<T>& V, int l) 
         sb[t] = l == 0 ? load_b0(V, k, i) : V.lds[V.bo(l) + k * pitch + i];
     }
     __syncthreads();
+    // CS consecutive lanes share an output row: lane q sums the products of
+    // k = q, q + CS, ... (all its loads in flight at once), and the lanes'
+    // sums meet in a fixed shuffle order
+    constexpr int CS = 16;
     const C* ci = V.S->cinvT + (int64_t)V.sys * nc * nc;
-    for (int t = threadIdx.x; t < nc; t += TT) {
+    const int q = threadIdx.x & (CS - 1);
+    for (int t0 = 0; t0 < nc; t0 += TT / CS) {
+        const int t = t0 + (int)threadIdx.x / CS;
         C acc = tz<C>();
-        for (int k = 0; k < nc; ++k) acc = tfma(acc, ci[(int64_t)k * nc + t], sb[k]);
-        const int kk = t / v.nx + 1, i = t - (kk - 1) * v.nx + 1;
-        x[kk * pitch + i] = acc;
+        if (t < nc)
+            for (int k = q; k < nc; k += CS) acc = tfma(acc, ci[(int64_t)k * nc + t], sb[k]);
+        for (int off = CS / 2; off > 0; off >>= 1) {
+            acc.x += __shfl_xor(acc.x, off, 64);
+            acc.y += __shfl_xor(acc.y, off, 64);
+        }
+        if (t < nc && q == 0) {
+            const int kk = t / v.nx + 1, i = t - (kk - 1) * v.nx + 1;
+            x[kk * pitch + i] = acc;
+        }
     }
     __syncthreads();
 }
