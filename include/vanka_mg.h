@@ -441,7 +441,10 @@ int vanka_mg_schedule(const vmg_handle* h, int32_t g, int32_t nlev, int32_t* sch
  * read at setup: VMG_EDGE=0 turns it off, VMG_EDGE=2 uses it wherever it
  * applies; VMG_EDGE_PACE=0/1 never/always paces it; VMG_IR_EDGE=0 keeps the
  * refinement step boundary in separate passes; VMG_TAIL=0 turns the tail
- * kernel off.  Returns VMG_OK or VMG_INVALID_ARG. */
+ * kernel off; VMG_RECOMP=0/2 never/always (on every streamed coarse level of
+ * a V(nu1, nu2) Vanka cycle with nu1, nu2 in {1, 2}; by default on FP64
+ * levels of at least 12M nodes over all systems) lets a coarse level's
+ * ascent recompute its pre-smoothed iterate instead of storing it.  Returns VMG_OK or VMG_INVALID_ARG. */
 int vanka_mg_plan(const vmg_handle* h, int32_t g, int32_t* edge, int32_t* tail_level);
 
 /* Levels of grid g: writes count and, if non-NULL, nx/ny per level. */

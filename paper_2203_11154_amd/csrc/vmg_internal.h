@@ -286,6 +286,13 @@ int stream_tiles_max(int nx, int ny, int nu);  // over every rmin and kernel
 // last cycle's iterate from them).  paced (T = double, Vanka): blocks of a
 // CU's worth of waves on adjacent strips, held together by a barrier after
 // every block of rows (the same run geometry and results).
+// Ascent of a coarse level visited from zero (V-cycles): nu1 sweeps from
+// zero rebuild the pre-smoothed iterate that the descent, given a null xo,
+// did not store, then the correction from c and nu2 sweeps -> xo; reads b
+// and c only.  Vanka, nu1 and nu2 in {1, 2} (edge_supported); the results
+// equal those of launch_up after a storing launch_down bit for bit.
+template <typename T>
+void launch_recomp(SegTable<T> tab, const int* nsys, int nu1, int nu2, int rmin, hipStream_t st);
 bool edge_supported(int nu1, int nu2);
 template <typename T>
 void launch_edge(SegTable<T> tab, const int* nsys, int nu1, int nu2, int rmin, hipStream_t st, bool c32 = false,

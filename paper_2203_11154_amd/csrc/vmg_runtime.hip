@@ -129,6 +129,8 @@ struct vmg_handle {
     bool tail_on = true;       // small levels in one workgroup per system (VMG_TAIL=0 turns it off)
     bool tail_solve_on = true; // whole solves in one tail launch where the tail covers every level
                                // (VMG_TAIL_SOLVE=0: one launch and one host-side stopping test a cycle)
+    int recomp_mode = 1;       // coarse ascents recompute the pre-smoothed iterate: 1 on large FP64 levels,
+                               // VMG_RECOMP=0 never, 2 on every level that can
     int pace_mode = -1;        // FP64 cycle-edge kernel in paced blocks: -1 as autotuned, VMG_EDGE_PACE=0 never,
                                // 1 always
     int ir_edge_mode = 1;      // refinement step boundary in one pass where the finest level streams with the
@@ -440,6 +442,24 @@ bool level0_paced(const vmg_handle* H, const Group& g) {
     return fine_f64(H->opts) && H->opts.smoother == 0 && use_edge(H, g) && edge_paced(H, g) != 0;
 }
 
+// A streamed coarse level of a V-cycle (visited once a cycle, from zero):
+// its descent stores no pre-smoothed iterate and its ascent recomputes it
+// (k_recomp), which saves the level the iterate's write and read but adds
+// the descent's sweeps to the ascent.  That pays where the level streams
+// from HBM at the VALU's pace: FP64 levels of at least RECOMP_MIN_NODES over
+// all systems (2047^2 x 32, level 1: 0.673 -> 0.562 ms a cycle; 1023^2 x 64,
+// level 1: 0.334 -> 0.30 ms).  Smaller FP64 levels (511^2 x 32: 0.175 ->
+// 0.184 ms) and complex64 ones, issue-bound already (1023^2 x 32: 0.360 ->
+// 0.383 ms), lose.
+constexpr double RECOMP_MIN_NODES = 12.0 * 1024 * 1024;
+bool recomp_level(const vmg_handle* H, const Group& g, int l) {
+    const vmg_opts& o = H->opts;
+    if (H->recomp_mode == 0 || l < 1 || o.gamma != 1 || o.smoother != 0 || !edge_supported(o.nu1, o.nu2))
+        return false;
+    return H->recomp_mode == 2 || (level_f64(o, l) && nodes(cycle_view(H, g, l)) * g.S >= RECOMP_MIN_NODES);
+}
+bool use_recomp(const vmg_handle* H, const Group& g, int l) { return recomp_level(H, g, l) && sched_stream(H, g, l); }
+
 // Refinement (complex64 V-cycles in FP64 refinement): the boundary of two
 // steps runs in one pass (k_ir_edge) on grids whose complex64 finest level
 // uses the cycle-edge kernel.
@@ -719,9 +739,10 @@ void enqueue_batched_vcycle(vmg_handle* H, int conj, hipStream_t st, bool first,
                     continue;
                 }
                 const int xz = (l > 0 || first0[gi]) ? 1 : 0;
-                bt.add(make_seg<T>(H, g, conj, l, P<T>(L[l].x[cur[gi][l]]), P<T>(L[l].b), P<T>(L[l].x[1 - cur[gi][l]]),
-                                   P<T>(L[l + 1].b), xz, nullptr),
-                       g.S, bytes_of(g, l, (xz ? 0.0 : 1.0) + 1.0 + (o.nu1 > 0 ? 1.0 : 0.0) + 0.25));
+                const bool rec = use_recomp(H, g, l);
+                bt.add(make_seg<T>(H, g, conj, l, P<T>(L[l].x[cur[gi][l]]), P<T>(L[l].b),
+                                   rec ? nullptr : P<T>(L[l].x[1 - cur[gi][l]]), P<T>(L[l + 1].b), xz, nullptr),
+                       g.S, bytes_of(g, l, (xz ? 0.0 : 1.0) + 1.0 + (o.nu1 > 0 && !rec ? 1.0 : 0.0) + 0.25));
                 done.push_back(gi);
             }
             {
@@ -862,6 +883,7 @@ void enqueue_batched_vcycle(vmg_handle* H, int conj, hipStream_t st, bool first,
         }
         while (!sg.empty()) {
             const int ty = sched_rows(H, H->groups[sg[0]], level_of(sg[0], d));
+            const bool rec = use_recomp(H, H->groups[sg[0]], level_of(sg[0], d));
             SegBatch<T> bt;
             std::vector<int> rest, done;
             bool any_norm = false;
@@ -869,7 +891,7 @@ void enqueue_batched_vcycle(vmg_handle* H, int conj, hipStream_t st, bool first,
                 Group& g = H->groups[gi];
                 const int l = level_of(gi, d);
                 auto& L = levels_of<T>(g);
-                if (sched_rows(H, g, l) != ty || bt.full()) {
+                if (sched_rows(H, g, l) != ty || use_recomp(H, g, l) != rec || bt.full()) {
                     rest.push_back(gi);
                     continue;
                 }
@@ -877,12 +899,13 @@ void enqueue_batched_vcycle(vmg_handle* H, int conj, hipStream_t st, bool first,
                 any_norm |= np != nullptr;
                 bt.add(make_seg<T>(H, g, conj, l, P<T>(L[l].x[cur[gi][l]]), P<T>(L[l].b), P<T>(L[l].x[1 - cur[gi][l]]),
                                    P<T>(L[l + 1].x[cur[gi][l + 1]]), 0, np),
-                       g.S, bytes_of(g, l, 2.0 + 0.25 + ((o.nu2 > 0 || np) ? 1.0 : 0.0)));
+                       g.S, bytes_of(g, l, (rec ? 1.0 : 2.0) + 0.25 + ((o.nu2 > 0 || np) ? 1.0 : 0.0)));
                 done.push_back(gi);
             }
             {
                 Timer t(H, st, VMG_K_UP, bt.bytes, level_of(done[0], d));
-                launch_up<T>(bt.tab, bt.nsys, o.nu2, any_norm, ty, st);
+                if (rec) launch_recomp<T>(bt.tab, bt.nsys, o.nu1, o.nu2, ty, st);
+                else launch_up<T>(bt.tab, bt.nsys, o.nu2, any_norm, ty, st);
             }
             for (int gi : done) {
                 const int l = level_of(gi, d);
@@ -1819,6 +1842,7 @@ int vanka_mg_setup(const vmg_grid* grids, int32_t n_grids, const double* shifts,
     if (const char* e = std::getenv("VMG_EDGE")) H->edge_mode = std::max(0, std::min(2, std::atoi(e)));
     if (const char* e = std::getenv("VMG_IR_EDGE")) H->ir_edge_mode = std::atoi(e) != 0;
     if (const char* e = std::getenv("VMG_EDGE_PACE")) H->pace_mode = std::atoi(e) != 0 ? 1 : 0;
+    if (const char* e = std::getenv("VMG_RECOMP")) H->recomp_mode = std::max(0, std::min(2, std::atoi(e)));
     H->shifts.resize(total);
     for (int s = 0; s < total; ++s) H->shifts[s] = cd(shifts[2 * s], shifts[2 * s + 1]);
     stream_prepare();
@@ -2482,13 +2506,20 @@ template <typename T> int time_level(vmg_handle* H, Group& g, int l, int cand, h
     auto seg = [&](const cplx<T>* x, const cplx<T>* b, cplx<T>* xo, cplx<T>* c, int xz) {
         return one_seg(make_seg<T>(H, g, 0, l, x, b, xo, c, xz, nullptr));
     };
+    // (as in the cycle: a coarse level's ascent recomputing its pre-smoothed
+    // iterate where use_recomp would hold for a streamed schedule)
+    const bool rec = recomp_level(H, g, l);
     auto run = [&]() {
         if (cand > 0) {
             // (the coarse levels start every visit from zero, as in the cycle)
-            launch_down<T>(seg(P<T>(lv.x[0]), P<T>(lv.b), P<T>(lv.x[1]), P<T>(lc.b), l > 0 ? 1 : 0), &one, o.nu1,
-                           cand, st);
-            launch_up<T>(seg(P<T>(lv.x[1]), P<T>(lv.b), P<T>(lv.x[0]), P<T>(lc.x[0]), 0), &one, o.nu2, l == 0, cand,
-                         st);
+            launch_down<T>(seg(P<T>(lv.x[0]), P<T>(lv.b), rec ? nullptr : P<T>(lv.x[1]), P<T>(lc.b), l > 0 ? 1 : 0),
+                           &one, o.nu1, cand, st);
+            if (rec)
+                launch_recomp<T>(seg(nullptr, P<T>(lv.b), P<T>(lv.x[0]), P<T>(lc.x[0]), 0), &one, o.nu1, o.nu2, cand,
+                                 st);
+            else
+                launch_up<T>(seg(P<T>(lv.x[1]), P<T>(lv.b), P<T>(lv.x[0]), P<T>(lc.x[0]), 0), &one, o.nu2, l == 0,
+                             cand, st);
         } else {
             for (int i = 0; i < o.nu1; ++i)
                 launch_sweep<T>(seg(P<T>(lv.x[i & 1]), P<T>(lv.b), P<T>(lv.x[1 - (i & 1)]), nullptr, 0), &one, st);

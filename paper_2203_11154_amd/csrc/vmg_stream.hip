@@ -379,7 +379,9 @@ __device__ __forceinline__ void down_piece(const LevelSeg<T>& S, int sys, int st
     const int64_t base = (int64_t)sys * p.lf.plane;
     p.xs = plane_rsrc(S.x + base, p.lf.plane);
     p.bs = plane_rsrc(S.b + base, p.lf.plane);
-    p.xos = plane_rsrc(S.xo + base, p.lf.plane);
+    // (no iterate output, S.xo null: its ascent recomputes it, see k_recomp;
+    // an empty range drops every store)
+    p.xos = S.xo ? plane_rsrc(S.xo + base, p.lf.plane) : plane_rsrc(S.b + base, 0);
     p.bcs = plane_rsrc(reinterpret_cast<const cplx<TC>*>(S.c) + (int64_t)sys * p.lc.plane, p.lc.plane);
     p.cf = S.coef[sys];
     p.dl = p.col_in ? p.cf.d : z2<C>();
@@ -933,6 +935,189 @@ __global__ __launch_bounds__(64 * WB) void k_edge(SegTable<T> tab) {
 }
 
 // ---------------------------------------------------------------------------
+// A coarse level's ascent that recomputes its pre-smoothed iterate.  Every
+// visit of a V-cycle's coarse level starts from zero, so the pre-smoothed
+// iterate x' = S^NPRE(0; b) is a function of that level's right-hand side
+// alone: the descent (k_down with no iterate output) need not store it, and
+// this pass rebuilds it on the way, from the same right-hand side rows it
+// reads for the post-smoothing anyway:
+//   x_0 = 0, NPRE sweeps  ->  x'   (the descent's stages)
+//   x' + P e, NPOST sweeps -> xo   (the plain ascent's stages)
+// Each stage is the same row stencil, in the same order, as in the two
+// passes it replaces, so the result is theirs bit for bit; the level moves
+// the iterate's write and read (2 of 5.5 complex values a node) less.  The
+// zero start is a runtime zero, as the descent's range-checked load of an
+// empty plane gives, so that no stage is simplified differently.  Unrolled by
+// 12 steps: the right-hand side ring needs 2 NS - 1 rows.
+template <typename T, int NPRE, int NPOST, bool JAC = false>
+struct RecompPipe {
+    using C = cplx<T>;
+    static constexpr int NS = NPRE + NPOST;
+    // a lane is wrong once a stage needs a neighbour the wave lacks: the
+    // first residual (of the zero start) is right on every lane, each later
+    // residual and every update widen the wrong edge by one lane (2 NS - 1)
+    static constexpr int HALO = 2 * NS;
+    static constexpr int OWN = 64 - 2 * HALO;
+    static constexpr int COL0 = 1;
+    static_assert(UNR_E % 12 == 0 && UNR_E % (EPF + 1) == 0 && 2 * NS - 1 <= 12 && NPRE >= 1 && NPOST >= 1,
+                  "ring lengths");
+    C X[NS + 1][3], R[NS][3];
+    C* B;  // this lane's column of the wave's 12-row ring in LDS (stride 64)
+    C br[EPF + 1];
+    C er[3], ei[3];
+    rsrc_t bs, es, xos;
+    LevelView lf, lc;
+    Coef<T> cf;
+    C dl;
+    T sl;
+    int k0, k1;
+    bool col_in, odd;
+    T mk, hf;
+    unsigned ox, oe, oo;
+    unsigned rx, rc;
+
+    template <bool EDGE> __device__ __forceinline__ C load_b(int j) const {
+        C v;
+        if constexpr (EDGE) bload(bs, ox + (in_rows(j, lf.ny) ? j * rx : OOB), 0, v);
+        else bload(bs, ox, srow(j, rx), v);
+        return v;
+    }
+    template <bool EDGE> __device__ __forceinline__ C load_e(int K) const {
+        C v;
+        if constexpr (EDGE) bload(es, oe + (K >= 0 && K <= lc.ny + 1 ? K * rc : OOB), 0, v);
+        else bload(es, oe, srow(K, rc), v);
+        return v;
+    }
+    __device__ __forceinline__ C interp_x(C v) const {
+        const C rv = from_right(v);
+        C r;
+        r.x = fmar(hf, rv.x - v.x, v.x);
+        r.y = fmar(hf, rv.y - v.y, v.y);
+        return r;
+    }
+    // Step at row j, phase P: push b row j - 1; stage q turns x_q rows
+    // j-2q-2..j-2q into r_q row j-2q-1 and x_{q+1} row j-2q-2.  The
+    // correction joins x_NPRE, whose newest row is j' = j - 2 NPRE: the coarse
+    // rows follow j' (phase Q = P - 2 NPRE, of P's parity) exactly as they
+    // follow the loaded row in the plain ascent.
+    template <int P, bool EDGE> __device__ __forceinline__ void step(int j) {
+        br[eslot<EPF + 1>(P + EPF)] = load_b<EDGE>(j + EPF - 1);
+        constexpr int Q = P - 2 * NPRE;
+        const int jq = j - 2 * NPRE;
+        C e;
+        if constexpr ((Q & 1) != 0) {
+            constexpr int lo = eslot<3>((Q - 1) / 2), hi = eslot<3>((Q + 1) / 2);
+            ei[hi] = interp_x(er[hi]);
+            e = scl(add(ei[lo], ei[hi]), (T)0.5);
+        } else {
+            er[eslot<3>(Q / 2 + 2)] = load_e<EDGE>((jq >> 1) + 2);
+            e = ei[eslot<3>(Q / 2)];
+        }
+        constexpr int n0 = eslot<3>(P), n1 = eslot<3>(P - 1), n2 = eslot<3>(P - 2);
+        B[eslot<12>(P) * 64] = br[eslot<EPF + 1>(P)];
+#pragma unroll
+        for (int q = 0; q < NS; ++q) {
+            const C bq = B[eslot<12>(P - 2 * q) * 64];
+            C r = residual_row<T>(X[q][n2], X[q][n1], X[q][n0], bq, dl, sl);
+            if constexpr (EDGE)
+                if (!in_rows(j - 2 * q - 1, lf.ny)) r = z2<C>();
+            R[q][n0] = r;
+            pin(R[q][n0]);
+            C v = vanka_row<T, JAC>(X[q][n2], R[q][n2], R[q][n1], R[q][n0], cf, mk);
+            if constexpr (EDGE)
+                if (!in_rows(j - 2 * q - 2, lf.ny)) v = z2<C>();
+            if (q + 1 == NPRE) v = add(v, e);
+            X[q + 1][n0] = v;
+            pin(X[q + 1][n0]);
+        }
+        const int orow = j - 2 * NS;
+        if constexpr (EDGE) bstore(xos, oo + (orow >= k0 && orow <= k1 ? orow * rx : OOB), 0, X[NS][n0]);
+        else bstore(xos, oo, srow(orow, rx), X[NS][n0]);
+    }
+    template <bool EDGE> __device__ __forceinline__ void block(int j) {
+#define VMG_R(P)                      \
+    step<P, EDGE>(j + P);             \
+    __builtin_amdgcn_sched_barrier(0);
+        VMG_R(0) VMG_R(1) VMG_R(2) VMG_R(3) VMG_R(4) VMG_R(5)
+        VMG_R(6) VMG_R(7) VMG_R(8) VMG_R(9) VMG_R(10) VMG_R(11)
+#undef VMG_R
+    }
+};
+
+template <typename T, int NPRE, int NPOST, bool JAC>
+__device__ __forceinline__ void recomp_piece(const LevelSeg<T>& S, int sys, int strip, int k0, int k1, int lane,
+                                             cplx<T>* bring) {
+    using C = cplx<T>;
+    using Pipe = RecompPipe<T, NPRE, NPOST, JAC>;
+    constexpr int HALO = Pipe::HALO, OWN = Pipe::OWN, NS = Pipe::NS, U = UNR_E;
+    Pipe p;
+    p.B = bring + lane;
+    p.lf = S.lf;
+    p.lc = S.lc;
+    const int i = Pipe::COL0 + strip * OWN - HALO + lane;
+    p.col_in = i >= 1 && i <= p.lf.nx;
+    p.mk = p.col_in ? (T)1 : (T)0;
+    p.odd = (i & 1) != 0;
+    p.hf = p.odd ? (T)0.5 : (T)0;
+    const bool ecol = i >= 0 && i <= p.lf.nx + 1;
+    const bool own = lane >= HALO && lane < HALO + OWN && p.col_in;
+    const unsigned es = sizeof(C);
+    p.ox = p.col_in ? i * es : OOB;
+    p.oe = ecol ? (i >> 1) * es : OOB;
+    p.oo = own ? i * es : OOB;
+    p.rx = p.lf.pitch * es;
+    p.rc = p.lc.pitch * es;
+    p.k0 = k0;
+    p.k1 = k1;
+    const int64_t base = (int64_t)sys * p.lf.plane;
+    p.bs = plane_rsrc(S.b + base, p.lf.plane);
+    p.es = plane_rsrc(S.c + (int64_t)sys * p.lc.plane, p.lc.plane);
+    p.xos = plane_rsrc(S.xo + base, p.lf.plane);
+    p.cf = S.coef[sys];
+    p.dl = p.col_in ? p.cf.d : z2<C>();
+    p.sl = p.col_in ? S.s : (T)0;
+    C zero = z2<C>();
+    pin(zero);
+#pragma unroll
+    for (int w = 0; w < 3; ++w) {
+        p.X[0][w] = zero;
+#pragma unroll
+        for (int q = 0; q < NS; ++q) p.X[q + 1][w] = p.R[q][w] = z2<C>();
+    }
+#pragma unroll
+    for (int w = 0; w < 12; ++w) p.B[w * 64] = z2<C>();
+    int jbeg = k0 - 2 * NS;
+    jbeg -= jbeg & 1;
+    const int jend = k1 + 2 * NS;
+    // blocks whose rows, loads and stores all lie inside the grid and the piece
+    const int jlo = max(k0 + 2 * NS, 2 * NS + 2);
+    const int jhi = min(min(p.lf.ny - U + 1 - EPF, p.lf.ny - U - 1), k1 - U + 1 + 2 * NS);
+    // coarse rows j'/2 (interpolated) and j'/2 + 1 (raw) of the first step's j'
+    const int jq = jbeg - 2 * NPRE;
+    p.ei[eslot<3>(-NPRE)] = p.interp_x(p.template load_e<true>(jq >> 1));
+    p.er[eslot<3>(1 - NPRE)] = p.template load_e<true>((jq >> 1) + 1);
+#pragma unroll
+    for (int d = 0; d < EPF; ++d) p.br[d] = p.template load_b<true>(jbeg + d - 1);
+    int j = jbeg;
+    for (; j <= jend && j < jlo; j += U) p.template block<true>(j);
+    for (; j <= jhi; j += U) p.template block<false>(j);
+    for (; j <= jend; j += U) p.template block<true>(j);
+}
+
+template <typename T, int NPRE, int NPOST, bool JAC = false>
+__global__ __launch_bounds__(NT) void k_recomp(SegTable<T> tab) {
+    __shared__ cplx<T> bring[NT / 64][12 * 64];  // right-hand side rows, one ring per wave
+    const int gw = (int)xcd_block().x * (NT / 64) + __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int lane = threadIdx.x & 63;
+    const LevelSeg<T> S = seg_of_wave(tab, gw);
+    const int lw = gw - S.w0;
+    if (lw >= S.waves) return;
+    const Piece pc = piece_of(S, lw);
+    if (pc.k0 > pc.k1 || !S.active[pc.sys]) return;
+    recomp_piece<T, NPRE, NPOST, JAC>(S, pc.sys, pc.strip, pc.k0, pc.k1, lane, bring[threadIdx.x >> 6]);
+}
+
+// ---------------------------------------------------------------------------
 // Boundary of two refinement steps (complex64 V-cycles inside FP64
 // refinement) on the finest level, in one pass.  Inputs: the last inner
 // cycle's pre-smoothed complex64 correction e, its coarse correction, the
@@ -1361,6 +1546,14 @@ void edge_go(SegTable<T> tab, const int* nsys, int rmin, hipStream_t st, bool pa
     else hipLaunchKernelGGL((k_edge<T, NA, NB, TC, false>), g, dim3(NT), 0, st, tab);
 }
 
+template <typename T, int NPRE, int NPOST> void recomp_go(SegTable<T> tab, const int* nsys, int rmin, hipStream_t st) {
+    using Pipe = RecompPipe<T, NPRE, NPOST>;
+    const void* k = (const void*)&k_recomp<T, NPRE, NPOST>;
+    const dim3 g = stream_seg_grid(tab, nsys, Pipe::OWN, Pipe::COL0, 4 * Pipe::NS + 1, rmin, resident_waves(k));
+    if (g.x == 0) return;
+    hipLaunchKernelGGL((k_recomp<T, NPRE, NPOST>), g, dim3(NT), 0, st, tab);
+}
+
 template <typename T, int NA, int NB> int edge_tiles_of(int nx, int ny, int nsys, int rmin) {
     using Pipe = EdgePipe<T, NA, NB>;
     const RunGeom g = run_geom(nx, ny, nsys, Pipe::OWN, Pipe::COL0, 4 * Pipe::NS + 9, rmin,
@@ -1391,6 +1584,15 @@ void launch_edge(SegTable<T> tab, const int* nsys, int nu1, int nu2, int rmin, h
 }
 template void launch_edge<double>(SegTable<double>, const int*, int, int, int, hipStream_t, bool, bool);
 template void launch_edge<float>(SegTable<float>, const int*, int, int, int, hipStream_t, bool, bool);
+
+template <typename T> void launch_recomp(SegTable<T> tab, const int* nsys, int nu1, int nu2, int rmin, hipStream_t st) {
+    if (nu1 == 1 && nu2 == 1) recomp_go<T, 1, 1>(tab, nsys, rmin, st);
+    else if (nu1 == 1 && nu2 == 2) recomp_go<T, 1, 2>(tab, nsys, rmin, st);
+    else if (nu1 == 2 && nu2 == 1) recomp_go<T, 2, 1>(tab, nsys, rmin, st);
+    else recomp_go<T, 2, 2>(tab, nsys, rmin, st);
+}
+template void launch_recomp<double>(SegTable<double>, const int*, int, int, int, hipStream_t);
+template void launch_recomp<float>(SegTable<float>, const int*, int, int, int, hipStream_t);
 
 template <typename T> int edge_tiles(int nx, int ny, int nsys, int nu1, int nu2, int rmin) {
     if (nu2 == 1 && nu1 == 1) return edge_tiles_of<T, 1, 1>(nx, ny, nsys, rmin);
