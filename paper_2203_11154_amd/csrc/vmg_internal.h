@@ -290,7 +290,7 @@ int stream_tiles_max(int nx, int ny, int nu);  // over every rmin and kernel
 // zero rebuild the pre-smoothed iterate that the descent, given a null xo,
 // did not store, then the correction from c and nu2 sweeps -> xo; reads b
 // and c only.  Vanka, nu1 and nu2 in {1, 2} (edge_supported); the results
-// equal those of launch_up after a storing launch_down bit for bit.
+// equal those of launch_up after a storing launch_down (up to zeros' signs).
 template <typename T>
 void launch_recomp(SegTable<T> tab, const int* nsys, int nu1, int nu2, int rmin, hipStream_t st);
 bool edge_supported(int nu1, int nu2);

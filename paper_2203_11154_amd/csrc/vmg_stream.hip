@@ -251,6 +251,7 @@ struct DownPipe {
     T sl;               // s on interior columns, else 0
     int k0, k1;
     bool col_in;
+    bool xz;            // the iterate read is zero: its residual is b itself
     T mk;  // 1 on interior columns, 0 off them
     unsigned ox, ob, oo, of;  // lane byte offsets: x, b, x written, coarse b (or OOB)
     unsigned rx;              // bytes per fine row
@@ -283,9 +284,16 @@ struct DownPipe {
         B[slot<6>(P)] = br[slot<PF + 1>(P)];
 #pragma unroll
         for (int q = 0; q <= NS; ++q) {
-            C r = residual_row<T>(X[q][n2], X[q][n1], X[q][n0], B[slot<6>(P - 2 * q)], dl, sl);
-            if constexpr (EDGE)
-                if (!in_rows(j - 2 * q - 1, lf.ny)) r = z2<C>();
+            C r;
+            // (a zero start: b - L 0 is b, up to the sign of a zero; the ring
+            // holds zero rows outside the grid)
+            if (q == 0 && xz) {
+                r = B[slot<6>(P)];
+            } else {
+                r = residual_row<T>(X[q][n2], X[q][n1], X[q][n0], B[slot<6>(P - 2 * q)], dl, sl);
+                if constexpr (EDGE)
+                    if (!in_rows(j - 2 * q - 1, lf.ny)) r = z2<C>();
+            }
             R[q][n0] = r;
             if (q < NS) {
                 C v = vanka_row<T, JAC>(X[q][n2], R[q][n2], R[q][n1], R[q][n0], cf, mk);
@@ -366,6 +374,7 @@ __device__ __forceinline__ void down_piece(const LevelSeg<T>& S, int sys, int st
     p.col_in = i >= 1 && i <= p.lf.nx;
     p.mk = p.col_in ? (T)1 : (T)0;
     const bool col_ld = i >= 0 && i <= p.lf.nx + 1 && !S.x_zero;
+    p.xz = S.x_zero != 0;
     const bool own = lane >= HALO && lane < HALO + OWN && p.col_in;
     const unsigned es = sizeof(C);
     p.ox = col_ld ? i * es : OOB;
@@ -944,11 +953,13 @@ __global__ __launch_bounds__(64 * WB) void k_edge(SegTable<T> tab) {
 //   x_0 = 0, NPRE sweeps  ->  x'   (the descent's stages)
 //   x' + P e, NPOST sweeps -> xo   (the plain ascent's stages)
 // Each stage is the same row stencil, in the same order, as in the two
-// passes it replaces, so the result is theirs bit for bit; the level moves
-// the iterate's write and read (2 of 5.5 complex values a node) less.  The
-// zero start is a runtime zero, as the descent's range-checked load of an
-// empty plane gives, so that no stage is simplified differently.  Unrolled by
-// 12 steps: the right-hand side ring needs 2 NS - 1 rows.
+// passes it replaces, except that the zero start's residual is b itself, so
+// the results equal theirs (up to the sign of a zero, which no later sum or
+// product turns into another value); the level moves the iterate's write and
+// read (2 of 5.5 complex values a node) less.  The zero start is a runtime
+// zero, as the descent's range-checked load of an empty plane gives, so that
+// no later stage is simplified differently.  Unrolled by 12 steps: the
+// right-hand side ring needs 2 NS - 1 rows.
 template <typename T, int NPRE, int NPOST, bool JAC = false>
 struct RecompPipe {
     using C = cplx<T>;
@@ -1018,9 +1029,12 @@ struct RecompPipe {
 #pragma unroll
         for (int q = 0; q < NS; ++q) {
             const C bq = B[eslot<12>(P - 2 * q) * 64];
-            C r = residual_row<T>(X[q][n2], X[q][n1], X[q][n0], bq, dl, sl);
+            // (the zero start's residual is b itself: the ring holds zero rows
+            // outside the grid, and the value equals the descent's b - L 0 up
+            // to the sign of a zero)
+            C r = q == 0 ? bq : residual_row<T>(X[q][n2], X[q][n1], X[q][n0], bq, dl, sl);
             if constexpr (EDGE)
-                if (!in_rows(j - 2 * q - 1, lf.ny)) r = z2<C>();
+                if (q > 0 && !in_rows(j - 2 * q - 1, lf.ny)) r = z2<C>();
             R[q][n0] = r;
             pin(R[q][n0]);
             C v = vanka_row<T, JAC>(X[q][n2], R[q][n2], R[q][n1], R[q][n0], cf, mk);

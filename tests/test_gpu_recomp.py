@@ -5,7 +5,8 @@ iterate is a function of that level's right-hand side: the descent stores no
 iterate and the ascent rebuilds it from b before the correction and the
 post-smoothing.  Every stage is the same row stencil as in the storing
 descent and plain ascent, so the iterates, counts and residuals equal those
-of VMG_RECOMP=0 bit for bit (VMG_RECOMP=2: on every level that can; by
+of VMG_RECOMP=0 (equal arrays: both take a zero start's residual to be b,
+so a zero may differ in sign only; VMG_RECOMP=2: on every level that can; by
 default only on large FP64 levels), in every precision and smoothing count
 the kernel takes, on grids whose strips and runs end ragged, and in batches of
 grids of different sizes; and the solves still meet the oracle.
@@ -58,7 +59,7 @@ def solve_both(monkeypatch, grids, nu1, nu2, precision, autotune=False, **kw):
 
 @pytest.mark.parametrize("nu1,nu2,precision", [(2, 2, "c128"), (2, 1, "c128"), (1, 2, "c128"), (1, 1, "c128"),
                                                (2, 2, "c64_ir"), (2, 2, "c128_c64"), (1, 2, "c128_c64")])
-def test_recompute_bitwise_equal_stored(nu1, nu2, precision, monkeypatch):
+def test_recompute_equal_stored(nu1, nu2, precision, monkeypatch):
     out, _, _ = solve_both(monkeypatch, GRIDS, nu1, nu2, precision)
     a, b = out["0"], out["2"]
     for k, (u, v) in enumerate(zip(a, b)):
@@ -67,7 +68,7 @@ def test_recompute_bitwise_equal_stored(nu1, nu2, precision, monkeypatch):
 
 def test_recompute_autotuned_vs_oracle(monkeypatch):
     """The autotuned schedule (each level timed with the recomputing ascent)
-    on one grid with three systems: bitwise the storing path's iterates, and
+    on one grid with three systems: the storing path's iterates, and
     every system at the oracle's V(2,2) count within 1e-10 of its iterate."""
     from paper_2203_11154_amd import Grid, VankaMG
     g = GRIDS[0]
