@@ -448,15 +448,18 @@ bool level0_paced(const vmg_handle* H, const Group& g) {
 // the descent's sweeps to the ascent.  That pays where the level streams
 // from HBM at the VALU's pace: FP64 levels of at least RECOMP_MIN_NODES over
 // all systems (2047^2 x 32, level 1: 0.673 -> 0.562 ms a cycle; 1023^2 x 64,
-// level 1: 0.334 -> 0.30 ms).  Smaller FP64 levels (511^2 x 32: 0.175 ->
-// 0.184 ms) and complex64 ones, issue-bound already (1023^2 x 32: 0.360 ->
-// 0.383 ms), lose.
+// level 1: 0.334 -> 0.30 ms) and complex64 ones, issue-bound already, only
+// from RECOMP_MIN_NODES_C64 on (1023^2 x 32 in FP32 refinement: 0.354 ->
+// 0.328 ms; 511^2 x 64: 0.200 -> 0.203 ms).  Smaller levels lose (FP64
+// 511^2 x 32: 0.167 -> 0.172 ms, complex64 511^2 x 32: 0.101 -> 0.123 ms).
 constexpr double RECOMP_MIN_NODES = 12.0 * 1024 * 1024;
+constexpr double RECOMP_MIN_NODES_C64 = 24.0 * 1024 * 1024;
 bool recomp_level(const vmg_handle* H, const Group& g, int l) {
     const vmg_opts& o = H->opts;
     if (H->recomp_mode == 0 || l < 1 || o.gamma != 1 || o.smoother != 0 || !edge_supported(o.nu1, o.nu2))
         return false;
-    return H->recomp_mode == 2 || (level_f64(o, l) && nodes(cycle_view(H, g, l)) * g.S >= RECOMP_MIN_NODES);
+    const double n = nodes(cycle_view(H, g, l)) * g.S;
+    return H->recomp_mode == 2 || n >= (level_f64(o, l) ? RECOMP_MIN_NODES : RECOMP_MIN_NODES_C64);
 }
 bool use_recomp(const vmg_handle* H, const Group& g, int l) { return recomp_level(H, g, l) && sched_stream(H, g, l); }
 
