@@ -443,7 +443,8 @@ int vanka_mg_schedule(const vmg_handle* h, int32_t g, int32_t nlev, int32_t* sch
  * refinement step boundary in separate passes; VMG_TAIL=0 turns the tail
  * kernel off; VMG_RECOMP=0/2 never/always (on every streamed coarse level of
  * a V(nu1, nu2) Vanka cycle with nu1, nu2 in {1, 2}; by default on FP64
- * levels of at least 12M nodes over all systems) lets a coarse level's
+ * levels of at least 12M nodes and complex64 levels of at least 24M nodes
+ * over all systems) lets a coarse level's
  * ascent recompute its pre-smoothed iterate instead of storing it.  Returns VMG_OK or VMG_INVALID_ARG. */
 int vanka_mg_plan(const vmg_handle* h, int32_t g, int32_t* edge, int32_t* tail_level);
 

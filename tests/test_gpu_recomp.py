@@ -7,7 +7,7 @@ post-smoothing.  Every stage is the same row stencil as in the storing
 descent and plain ascent, so the iterates, counts and residuals equal those
 of VMG_RECOMP=0 (equal arrays: both take a zero start's residual to be b,
 so a zero may differ in sign only; VMG_RECOMP=2: on every level that can; by
-default only on large FP64 levels), in every precision and smoothing count
+default only on large levels), in every precision and smoothing count
 the kernel takes, on grids whose strips and runs end ragged, and in batches of
 grids of different sizes; and the solves still meet the oracle.
 """
