@@ -87,6 +87,26 @@ template <typename T> struct SegTable {
 };
 
 #ifdef __HIPCC__
+// Complex arithmetic on double2 / float2 (x the real part, y the imaginary
+// part), written out so that every kernel rounds the same way.
+template <typename C> __device__ __forceinline__ C czero() { C z; z.x = 0; z.y = 0; return z; }
+template <typename C> __device__ __forceinline__ C cadd(C a, C b) { C r; r.x = a.x + b.x; r.y = a.y + b.y; return r; }
+template <typename C> __device__ __forceinline__ C csub(C a, C b) { C r; r.x = a.x - b.x; r.y = a.y - b.y; return r; }
+template <typename C, typename T> __device__ __forceinline__ C cscale(C a, T s) { C r; r.x = a.x * s; r.y = a.y * s; return r; }
+template <typename C> __device__ __forceinline__ C cmul(C a, C b) {
+    C r;
+    r.x = a.x * b.x - a.y * b.y;
+    r.y = a.x * b.y + a.y * b.x;
+    return r;
+}
+// a + b * c
+template <typename C> __device__ __forceinline__ C cfma(C a, C b, C c) {
+    C r;
+    r.x = a.x + b.x * c.x - b.y * c.y;
+    r.y = a.y + b.x * c.y + b.y * c.x;
+    return r;
+}
+
 // The hardware hands consecutive workgroups of a launch to the chip's eight
 // XCDs in turn, and each XCD has its own L2.  Renumber the blocks so that
 // every XCD receives one contiguous run of the logical order (x fastest):

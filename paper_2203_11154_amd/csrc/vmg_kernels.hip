@@ -14,24 +14,6 @@ namespace {
 
 constexpr int NT = 256;  // threads per block (4 wave64)
 
-template <typename C> __device__ __forceinline__ C czero() { C z; z.x = 0; z.y = 0; return z; }
-template <typename C> __device__ __forceinline__ C cadd(C a, C b) { C r; r.x = a.x + b.x; r.y = a.y + b.y; return r; }
-template <typename C> __device__ __forceinline__ C csub(C a, C b) { C r; r.x = a.x - b.x; r.y = a.y - b.y; return r; }
-template <typename C> __device__ __forceinline__ C cmul(C a, C b) {
-    C r;
-    r.x = a.x * b.x - a.y * b.y;
-    r.y = a.x * b.y + a.y * b.x;
-    return r;
-}
-template <typename C, typename T> __device__ __forceinline__ C cscale(C a, T s) { C r; r.x = a.x * s; r.y = a.y * s; return r; }
-// a + b * c
-template <typename C> __device__ __forceinline__ C cfma(C a, C b, C c) {
-    C r;
-    r.x = a.x + b.x * c.x - b.y * c.y;
-    r.y = a.y + b.x * c.y + b.y * c.x;
-    return r;
-}
-
 // ---------------------------------------------------------------------------
 // Additive Vanka sweep (eq. (3) with the explicit stencil of eq. (6)):
 //   r = b - L x on the tile plus a one-node halo (zero off the interior),

@@ -45,25 +45,9 @@ namespace {
 
 constexpr int NT = 256;
 
-template <typename C> __device__ __forceinline__ C z2() { C z; z.x = 0; z.y = 0; return z; }
-template <typename C> __device__ __forceinline__ C add(C a, C b) { C r; r.x = a.x + b.x; r.y = a.y + b.y; return r; }
-template <typename C> __device__ __forceinline__ C sub(C a, C b) { C r; r.x = a.x - b.x; r.y = a.y - b.y; return r; }
-template <typename C, typename T> __device__ __forceinline__ C scl(C a, T s) { C r; r.x = a.x * s; r.y = a.y * s; return r; }
-template <typename C> __device__ __forceinline__ C mul(C a, C b) {
-    C r;
-    r.x = a.x * b.x - a.y * b.y;
-    r.y = a.x * b.y + a.y * b.x;
-    return r;
-}
 // a * b + c rounded once, in the precision of the operands
 __device__ __forceinline__ double fmar(double a, double b, double c) { return __builtin_fma(a, b, c); }
 __device__ __forceinline__ float fmar(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
-template <typename C> __device__ __forceinline__ C fma2(C acc, C a, C b) {  // acc + a * b
-    C r;
-    r.x = acc.x + a.x * b.x - a.y * b.y;
-    r.y = acc.y + a.x * b.y + a.y * b.x;
-    return r;
-}
 // complex value in another precision (round to nearest; the identity when
 // the types agree)
 template <typename D, typename S> __device__ __forceinline__ D cvt(S v) {
@@ -108,14 +92,14 @@ template <typename C> __device__ __forceinline__ C from_right(C v) {
 }
 
 // Left + right neighbour sum.
-template <typename C> __device__ __forceinline__ C lr_sum(C v) { return add(from_left(v), from_right(v)); }
+template <typename C> __device__ __forceinline__ C lr_sum(C v) { return cadd(from_left(v), from_right(v)); }
 
 // Residual of a middle row: b - (d x - s (W + E + N + S)), from the rows
 // above (xo), at (xm) and below (xn); three fused multiply-adds a component
 // after the neighbour sum.
 template <typename T, typename C>
 __device__ __forceinline__ C residual_row(C xo, C xm, C xn, C bv, C d, T s) {
-    const C nb = add(lr_sum(xm), add(xo, xn));
+    const C nb = cadd(lr_sum(xm), cadd(xo, xn));
     C r;
     r.x = fmar(d.y, xm.y, fmar(-d.x, xm.x, fmar(s, nb.x, bv.x)));
     r.y = fmar(-d.y, xm.x, fmar(-d.x, xm.y, fmar(s, nb.y, bv.y)));
@@ -135,22 +119,22 @@ __device__ __forceinline__ C residual_row(C xo, C xm, C xn, C bv, C d, T s) {
 template <typename T, bool JAC, typename C>
 __device__ __forceinline__ C vanka_row(C xc, C ro, C rm, C rn, const Coef<T>& cf, T mk) {
     if constexpr (JAC) {
-        return fma2(xc, cf.ca, rm);
+        return cfma(xc, cf.ca, rm);
     } else {
-        const C vs = add(ro, rn);
-        const C t = fma2(rm, cf.gamma, vs);
-        C u = fma2(vs, cf.alpha, rm);
+        const C vs = cadd(ro, rn);
+        const C t = cfma(rm, cf.gamma, vs);
+        C u = cfma(vs, cf.alpha, rm);
         const C lr = lr_sum(t);
         u.x = fmar(mk, lr.x, u.x);
         u.y = fmar(mk, lr.y, u.y);
-        return fma2(xc, cf.cb, u);
+        return cfma(xc, cf.cb, u);
     }
 }
 
 // Full weighting around a middle row, the same way: with
 // w = rm/8 + (ro + rn)/16 it is rm/4 + (ro + rn)/8 + LR(w) = 2 w + LR(w).
 template <typename T, typename C> __device__ __forceinline__ C full_weight_row(C ro, C rm, C rn) {
-    const C vs = add(ro, rn);
+    const C vs = cadd(ro, rn);
     C w;
     w.x = fmar(vs.x, (T)0.0625, rm.x * (T)0.125);
     w.y = fmar(vs.y, (T)0.0625, rm.y * (T)0.125);
@@ -292,13 +276,13 @@ struct DownPipe {
             } else {
                 r = residual_row<T>(X[q][n2], X[q][n1], X[q][n0], B[slot<6>(P - 2 * q)], dl, sl);
                 if constexpr (EDGE)
-                    if (!in_rows(j - 2 * q - 1, lf.ny)) r = z2<C>();
+                    if (!in_rows(j - 2 * q - 1, lf.ny)) r = czero<C>();
             }
             R[q][n0] = r;
             if (q < NS) {
                 C v = vanka_row<T, JAC>(X[q][n2], R[q][n2], R[q][n1], R[q][n0], cf, mk);
                 if constexpr (EDGE)
-                    if (!in_rows(j - 2 * q - 2, lf.ny)) v = z2<C>();
+                    if (!in_rows(j - 2 * q - 2, lf.ny)) v = czero<C>();
                 X[q + 1][n0] = v;
             }
             pin(R[q][n0]);
@@ -393,14 +377,14 @@ __device__ __forceinline__ void down_piece(const LevelSeg<T>& S, int sys, int st
     p.xos = S.xo ? plane_rsrc(S.xo + base, p.lf.plane) : plane_rsrc(S.b + base, 0);
     p.bcs = plane_rsrc(reinterpret_cast<const cplx<TC>*>(S.c) + (int64_t)sys * p.lc.plane, p.lc.plane);
     p.cf = S.coef[sys];
-    p.dl = p.col_in ? p.cf.d : z2<C>();
+    p.dl = p.col_in ? p.cf.d : czero<C>();
     p.sl = p.col_in ? S.s : (T)0;
 #pragma unroll
     for (int q = 0; q <= NS; ++q)
 #pragma unroll
-        for (int w = 0; w < 3; ++w) p.X[q][w] = p.R[q][w] = z2<C>();
+        for (int w = 0; w < 3; ++w) p.X[q][w] = p.R[q][w] = czero<C>();
 #pragma unroll
-    for (int w = 0; w < 6; ++w) p.B[w] = z2<C>();
+    for (int w = 0; w < 6; ++w) p.B[w] = czero<C>();
     int jbeg = k0 - 2 * NS - 2;
     jbeg -= jbeg & 1;
     const int jend = k1 + 2 * NS + 2;
@@ -548,13 +532,13 @@ struct UpPipe {
         if constexpr ((P & 1) != 0) {
             constexpr int lo = slot<3>((P - 1) / 2), hi = slot<3>((P + 1) / 2);
             ei[hi] = interp_x(er[hi]);
-            e = scl(add(ei[lo], ei[hi]), (T)0.5);
+            e = cscale(cadd(ei[lo], ei[hi]), (T)0.5);
         } else {
             er[slot<3>(P / 2 + 2)] = load_e<EDGE>((j >> 1) + 2);
             e = ei[slot<3>(P / 2)];
         }
         constexpr int n0 = slot<3>(P), n1 = slot<3>(P - 1), n2 = slot<3>(P - 2);
-        X[0][n0] = add(xr[slot<PF + 1>(P)], e);
+        X[0][n0] = cadd(xr[slot<PF + 1>(P)], e);
         B[slot<6>(P)] = br[slot<PF + 1>(P)];
 #pragma unroll
         for (int q = 0; q <= NS; ++q) {
@@ -562,7 +546,7 @@ struct UpPipe {
             const int rrow = j - 2 * q - 1;
             C r = residual_row<T>(X[q][n2], X[q][n1], X[q][n0], B[slot<6>(P - 2 * q)], dl, sl);
             if constexpr (EDGE)
-                if (!in_rows(rrow, lf.ny)) r = z2<C>();
+                if (!in_rows(rrow, lf.ny)) r = czero<C>();
             if (q == NS) {
                 // the owned-lane mask is applied once, at the end
                 if (!EDGE || (rrow >= k0 && rrow <= k1)) acc += (double)r.x * (double)r.x + (double)r.y * (double)r.y;
@@ -572,7 +556,7 @@ struct UpPipe {
             R[q][n0] = r;
             C v = vanka_row<T, JAC>(X[q][n2], R[q][n2], R[q][n1], R[q][n0], cf, mk);
             if constexpr (EDGE)
-                if (!in_rows(j - 2 * q - 2, lf.ny)) v = z2<C>();
+                if (!in_rows(j - 2 * q - 2, lf.ny)) v = czero<C>();
             X[q + 1][n0] = v;
             pin(R[q][n0]);
             pin(X[q + 1][n0]);
@@ -648,15 +632,15 @@ __device__ __forceinline__ double up_piece(const LevelSeg<T>& S, int sys, int st
         p.ro = p.rx;
     }
     p.cf = S.coef[sys];
-    p.dl = p.col_in ? p.cf.d : z2<C>();
+    p.dl = p.col_in ? p.cf.d : czero<C>();
     p.sl = p.col_in ? S.s : (T)0;
     p.acc = 0.0;
 #pragma unroll
     for (int q = 0; q <= NS; ++q)
 #pragma unroll
-        for (int w = 0; w < 3; ++w) p.X[q][w] = p.R[q][w] = z2<C>();
+        for (int w = 0; w < 3; ++w) p.X[q][w] = p.R[q][w] = czero<C>();
 #pragma unroll
-    for (int w = 0; w < 6; ++w) p.B[w] = z2<C>();
+    for (int w = 0; w < 6; ++w) p.B[w] = czero<C>();
     int jbeg = k0 - 2 * NS - 1;
     jbeg -= jbeg & 1;
     const int jend = k1 + 2 * NS + 1;
@@ -794,13 +778,13 @@ struct EdgePipe {
         if constexpr ((P & 1) != 0) {
             constexpr int lo = eslot<3>((P - 1) / 2), hi = eslot<3>((P + 1) / 2);
             ei[hi] = interp_x(er[hi]);
-            e = scl(add(ei[lo], ei[hi]), (T)0.5);
+            e = cscale(cadd(ei[lo], ei[hi]), (T)0.5);
         } else {
             er[eslot<3>(P / 2 + 2)] = load_e<EDGE>((j >> 1) + 2);
             e = ei[eslot<3>(P / 2)];
         }
         constexpr int n0 = eslot<3>(P), n1 = eslot<3>(P - 1), n2 = eslot<3>(P - 2);
-        X[0][n0] = add(xr[eslot<EPF + 1>(P)], e);
+        X[0][n0] = cadd(xr[eslot<EPF + 1>(P)], e);
         B[eslot<12>(P) * 64] = br[eslot<EPF + 1>(P)];
 #pragma unroll
         for (int q = 0; q <= NS; ++q) {
@@ -808,7 +792,7 @@ struct EdgePipe {
             const C bq = B[eslot<12>(P - 2 * q) * 64];
             C r = residual_row<T>(X[q][n2], X[q][n1], X[q][n0], bq, dl, sl);
             if constexpr (EDGE)
-                if (!in_rows(rrow, lf.ny)) r = z2<C>();
+                if (!in_rows(rrow, lf.ny)) r = czero<C>();
             if (q == NA) {
                 // stopping-test residual of cycle k's final iterate (owned-lane
                 // mask applied once, at the end)
@@ -820,7 +804,7 @@ struct EdgePipe {
             if (q < NS) {
                 C v = vanka_row<T, JAC>(X[q][n2], R[q][n2], R[q][n1], R[q][n0], cf, mk);
                 if constexpr (EDGE)
-                    if (!in_rows(j - 2 * q - 2, lf.ny)) v = z2<C>();
+                    if (!in_rows(j - 2 * q - 2, lf.ny)) v = czero<C>();
                 X[q + 1][n0] = v;
                 pin(X[q + 1][n0]);
             }
@@ -878,15 +862,15 @@ __device__ __forceinline__ double edge_piece(const LevelSeg<T>& S, int sys, int 
     p.xos = plane_rsrc(S.xo + base, p.lf.plane);
     p.cbs = plane_rsrc(reinterpret_cast<const cplx<TC>*>(S.cb) + (int64_t)sys * p.lc.plane, p.lc.plane);
     p.cf = S.coef[sys];
-    p.dl = p.col_in ? p.cf.d : z2<C>();
+    p.dl = p.col_in ? p.cf.d : czero<C>();
     p.sl = p.col_in ? S.s : (T)0;
     p.acc = 0.0;
 #pragma unroll
     for (int q = 0; q <= NS; ++q)
 #pragma unroll
-        for (int w = 0; w < 3; ++w) p.X[q][w] = p.R[q][w] = z2<C>();
+        for (int w = 0; w < 3; ++w) p.X[q][w] = p.R[q][w] = czero<C>();
 #pragma unroll
-    for (int w = 0; w < 12; ++w) p.B[w * 64] = z2<C>();
+    for (int w = 0; w < 12; ++w) p.B[w * 64] = czero<C>();
     int jbeg = k0 - 2 * NS - 2;
     jbeg -= jbeg & 1;
     const int jend = k1 + 2 * NS + 2;
@@ -1019,7 +1003,7 @@ struct RecompPipe {
         if constexpr ((Q & 1) != 0) {
             constexpr int lo = eslot<3>((Q - 1) / 2), hi = eslot<3>((Q + 1) / 2);
             ei[hi] = interp_x(er[hi]);
-            e = scl(add(ei[lo], ei[hi]), (T)0.5);
+            e = cscale(cadd(ei[lo], ei[hi]), (T)0.5);
         } else {
             er[eslot<3>(Q / 2 + 2)] = load_e<EDGE>((jq >> 1) + 2);
             e = ei[eslot<3>(Q / 2)];
@@ -1034,13 +1018,13 @@ struct RecompPipe {
             // to the sign of a zero)
             C r = q == 0 ? bq : residual_row<T>(X[q][n2], X[q][n1], X[q][n0], bq, dl, sl);
             if constexpr (EDGE)
-                if (q > 0 && !in_rows(j - 2 * q - 1, lf.ny)) r = z2<C>();
+                if (q > 0 && !in_rows(j - 2 * q - 1, lf.ny)) r = czero<C>();
             R[q][n0] = r;
             pin(R[q][n0]);
             C v = vanka_row<T, JAC>(X[q][n2], R[q][n2], R[q][n1], R[q][n0], cf, mk);
             if constexpr (EDGE)
-                if (!in_rows(j - 2 * q - 2, lf.ny)) v = z2<C>();
-            if (q + 1 == NPRE) v = add(v, e);
+                if (!in_rows(j - 2 * q - 2, lf.ny)) v = czero<C>();
+            if (q + 1 == NPRE) v = cadd(v, e);
             X[q + 1][n0] = v;
             pin(X[q + 1][n0]);
         }
@@ -1088,18 +1072,18 @@ __device__ __forceinline__ void recomp_piece(const LevelSeg<T>& S, int sys, int 
     p.es = plane_rsrc(S.c + (int64_t)sys * p.lc.plane, p.lc.plane);
     p.xos = plane_rsrc(S.xo + base, p.lf.plane);
     p.cf = S.coef[sys];
-    p.dl = p.col_in ? p.cf.d : z2<C>();
+    p.dl = p.col_in ? p.cf.d : czero<C>();
     p.sl = p.col_in ? S.s : (T)0;
-    C zero = z2<C>();
+    C zero = czero<C>();
     pin(zero);
 #pragma unroll
     for (int w = 0; w < 3; ++w) {
         p.X[0][w] = zero;
 #pragma unroll
-        for (int q = 0; q < NS; ++q) p.X[q + 1][w] = p.R[q][w] = z2<C>();
+        for (int q = 0; q < NS; ++q) p.X[q + 1][w] = p.R[q][w] = czero<C>();
     }
 #pragma unroll
-    for (int w = 0; w < 12; ++w) p.B[w * 64] = z2<C>();
+    for (int w = 0; w < 12; ++w) p.B[w * 64] = czero<C>();
     int jbeg = k0 - 2 * NS;
     jbeg -= jbeg & 1;
     const int jend = k1 + 2 * NS;
@@ -1229,13 +1213,13 @@ struct IrEdgePipe {
         if constexpr ((P & 1) != 0) {
             constexpr int lo = eslot<3>((P - 1) / 2), hi = eslot<3>((P + 1) / 2);
             ei[hi] = interp_x(er[hi]);
-            e = scl(add(ei[lo], ei[hi]), (T)0.5);
+            e = cscale(cadd(ei[lo], ei[hi]), (T)0.5);
         } else {
             er[eslot<3>(P / 2 + 2)] = load_e<EDGE>((j >> 1) + 2);
             e = ei[eslot<3>(P / 2)];
         }
         constexpr int n0 = eslot<3>(P), n1 = eslot<3>(P - 1), n2 = eslot<3>(P - 2);
-        X[0][n0] = add(xr[eslot<EPF + 1>(P)], e);
+        X[0][n0] = cadd(xr[eslot<EPF + 1>(P)], e);
         B[eslot<12>(P) * 64] = br[eslot<EPF + 1>(P)];
 #pragma unroll
         for (int q = 0; q <= NS; ++q) {
@@ -1252,7 +1236,7 @@ struct IrEdgePipe {
                 store_at<EDGE>(xhos, ooh, rxh, j - 2 * NA, xp);
                 D rh = residual_row<double>(XP[n2], XP[n1], XP[n0], bhr[eslot<EPF + 1>(P)], dh, shl);
                 if constexpr (EDGE)
-                    if (!in_rows(rrow, lf.ny)) rh = z2<D>();
+                    if (!in_rows(rrow, lf.ny)) rh = czero<D>();
                 if (!EDGE || (rrow >= k0 && rrow <= k1)) acc += rh.x * rh.x + rh.y * rh.y;
                 pin(acc);
                 pin(XP[n0]);
@@ -1263,15 +1247,15 @@ struct IrEdgePipe {
                 const C bq = q < NA ? B[eslot<12>(P - 2 * q) * 64] : RP[eslot<6>(P - 2 * (q - NA))];
                 r = residual_row<T>(X[q][n2], X[q][n1], X[q][n0], bq, dl, sl);
                 if constexpr (EDGE)
-                    if (!in_rows(rrow, lf.ny)) r = z2<C>();
+                    if (!in_rows(rrow, lf.ny)) r = czero<C>();
             }
             R[q][n0] = r;
             pin(R[q][n0]);
             if (q < NS) {
                 // (the first sweep of step k+1 starts from zero)
-                C v = vanka_row<T, JAC>(q == NA ? z2<C>() : X[q][n2], R[q][n2], R[q][n1], R[q][n0], cf, mk);
+                C v = vanka_row<T, JAC>(q == NA ? czero<C>() : X[q][n2], R[q][n2], R[q][n1], R[q][n0], cf, mk);
                 if constexpr (EDGE)
-                    if (!in_rows(j - 2 * q - 2, lf.ny)) v = z2<C>();
+                    if (!in_rows(j - 2 * q - 2, lf.ny)) v = czero<C>();
                 X[q + 1][n0] = v;
                 pin(X[q + 1][n0]);
             }
@@ -1342,22 +1326,22 @@ __device__ __forceinline__ double ir_edge_piece(const LevelSeg<float>& S, int sy
     p.cbs = plane_rsrc(S.cb + (int64_t)sys * p.lc.plane, p.lc.plane);
     p.bnos = plane_rsrc(S.bno + base, p.lf.plane);
     p.cf = S.coef[sys];
-    p.dl = p.col_in ? p.cf.d : z2<C>();
+    p.dl = p.col_in ? p.cf.d : czero<C>();
     p.sl = p.col_in ? S.s : 0.0f;
     const Coef<double> ch = S.coefh[sys];
-    p.dh = p.col_in ? ch.d : z2<D>();
+    p.dh = p.col_in ? ch.d : czero<D>();
     p.shl = p.col_in ? S.sh : 0.0;
     p.acc = 0.0;
 #pragma unroll
     for (int q = 0; q <= NS; ++q)
 #pragma unroll
-        for (int w = 0; w < 3; ++w) p.X[q][w] = p.R[q][w] = z2<C>();
+        for (int w = 0; w < 3; ++w) p.X[q][w] = p.R[q][w] = czero<C>();
 #pragma unroll
-    for (int w = 0; w < 3; ++w) p.XP[w] = z2<D>();
+    for (int w = 0; w < 3; ++w) p.XP[w] = czero<D>();
 #pragma unroll
-    for (int w = 0; w < 6; ++w) p.RP[w] = z2<C>();
+    for (int w = 0; w < 6; ++w) p.RP[w] = czero<C>();
 #pragma unroll
-    for (int w = 0; w < 12; ++w) p.B[w * 64] = z2<C>();
+    for (int w = 0; w < 12; ++w) p.B[w * 64] = czero<C>();
     int jbeg = k0 - 2 * NS - 2;
     jbeg -= jbeg & 1;
     const int jend = k1 + 2 * NS + 2;
@@ -1412,7 +1396,7 @@ __global__ __launch_bounds__(NT) void k_fill_zero(cplx<T>* __restrict__ x, Level
     const int i = blockIdx.x * 64 + (threadIdx.x & 63) + 1;
     if (i > lv.nx) return;
     for (int k = blockIdx.y * 16 + (threadIdx.x >> 6) + 1; k <= min(lv.ny, (int)(blockIdx.y + 1) * 16); k += NT / 64)
-        x[(int64_t)blockIdx.z * lv.plane + (int64_t)k * lv.pitch + i] = z2<cplx<T>>();
+        x[(int64_t)blockIdx.z * lv.plane + (int64_t)k * lv.pitch + i] = czero<cplx<T>>();
 }
 
 template <int NS> constexpr int down_own() { return DownPipe<double, NS>::OWN; }

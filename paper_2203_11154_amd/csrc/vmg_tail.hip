@@ -28,23 +28,6 @@ namespace {
 
 constexpr int TT = 1024;  // threads per workgroup (16 waves)
 
-template <typename C> __device__ __forceinline__ C tz() { C z; z.x = 0; z.y = 0; return z; }
-template <typename C> __device__ __forceinline__ C tadd(C a, C b) { C r; r.x = a.x + b.x; r.y = a.y + b.y; return r; }
-template <typename C> __device__ __forceinline__ C tsub(C a, C b) { C r; r.x = a.x - b.x; r.y = a.y - b.y; return r; }
-template <typename C, typename T> __device__ __forceinline__ C tscl(C a, T s) { C r; r.x = a.x * s; r.y = a.y * s; return r; }
-template <typename C> __device__ __forceinline__ C tmul(C a, C b) {
-    C r;
-    r.x = a.x * b.x - a.y * b.y;
-    r.y = a.x * b.y + a.y * b.x;
-    return r;
-}
-template <typename C> __device__ __forceinline__ C tfma(C a, C b, C c) {  // a + b c
-    C r;
-    r.x = a.x + b.x * c.x - b.y * c.y;
-    r.y = a.y + b.x * c.y + b.y * c.x;
-    return r;
-}
-
 __device__ __forceinline__ int padded(const LevelView& v) { return (v.nx + 2) * (v.ny + 2); }
 
 template <typename T> struct TailView {
@@ -96,10 +79,10 @@ template <typename T> __device__ void residual_first(const TailView<T>& V, const
     for (int j = 0; j < Level0<T>::JMAX; ++j) {
         const int t = threadIdx.x + j * TT;
         if (t < P) {
-            C rv = tz<C>();
+            C rv = czero<C>();
             if ((f.in >> j) & 1u) {
-                const C nb = tadd(tadd(x[t - pitch], x[t + pitch]), tadd(x[t - 1], x[t + 1]));
-                rv = tsub(f.b[j], tsub(tmul(cf.d, x[t]), tscl(nb, s)));
+                const C nb = cadd(cadd(x[t - pitch], x[t + pitch]), cadd(x[t - 1], x[t + 1]));
+                rv = csub(f.b[j], csub(cmul(cf.d, x[t]), cscale(nb, s)));
             }
             r[t] = rv;
         }
@@ -122,11 +105,11 @@ template <typename T> __device__ void residual(const TailView<T>& V, int l, cons
     C* r = V.lds + V.ro(l);
     for (int t = threadIdx.x; t < P; t += TT) {
         const int k = t / pitch, i = t - k * pitch;
-        C rv = tz<C>();
+        C rv = czero<C>();
         if (i >= 1 && i <= v.nx && k >= 1 && k <= v.ny) {
             const C bv = b[t];
-            const C nb = tadd(tadd(x[t - pitch], x[t + pitch]), tadd(x[t - 1], x[t + 1]));
-            rv = tsub(bv, tsub(tmul(cf.d, x[t]), tscl(nb, s)));
+            const C nb = cadd(cadd(x[t - pitch], x[t + pitch]), cadd(x[t - 1], x[t + 1]));
+            rv = csub(bv, csub(cmul(cf.d, x[t]), cscale(nb, s)));
         }
         r[t] = rv;
     }
@@ -135,11 +118,11 @@ template <typename T> __device__ void residual(const TailView<T>& V, int l, cons
 
 template <typename T, typename C>
 __device__ __forceinline__ void vanka_node(C* x, const C* r, int c, int pitch, const Coef<T>& cf) {
-    const C edge = tadd(tadd(r[c - pitch], r[c + pitch]), tadd(r[c - 1], r[c + 1]));
-    const C corner = tadd(tadd(r[c - pitch - 1], r[c - pitch + 1]), tadd(r[c + pitch - 1], r[c + pitch + 1]));
-    C u = tfma(x[c], cf.ca, r[c]);
-    u = tfma(u, cf.cb, edge);
-    x[c] = tfma(u, cf.cc, corner);
+    const C edge = cadd(cadd(r[c - pitch], r[c + pitch]), cadd(r[c - 1], r[c + 1]));
+    const C corner = cadd(cadd(r[c - pitch - 1], r[c - pitch + 1]), cadd(r[c + pitch - 1], r[c + pitch + 1]));
+    C u = cfma(x[c], cf.ca, r[c]);
+    u = cfma(u, cf.cb, edge);
+    x[c] = cfma(u, cf.cc, corner);
 }
 
 // x += ca r + cb (edge sum of r) + cc (corner sum of r), in place
@@ -175,23 +158,23 @@ template <typename T> __device__ void restrict_down(const TailView<T>& V, int l,
     // one coarse node per thread (the host keeps the coarse levels of a tail
     // at most TT nodes)
     const int t = threadIdx.x;
-    C val = tz<C>();
+    C val = czero<C>();
     const bool on = t < vc.nx * vc.ny;
     int cc = 0;
     if (on) {
         const int K = t / vc.nx + 1, I = t - (K - 1) * vc.nx + 1;
         const int c = 2 * K * pitch + 2 * I;
-        const C edge = tadd(tadd(r[c - pitch], r[c + pitch]), tadd(r[c - 1], r[c + 1]));
-        const C corner = tadd(tadd(r[c - pitch - 1], r[c - pitch + 1]), tadd(r[c + pitch - 1], r[c + pitch + 1]));
-        val = tscl(r[c], (T)0.25);
-        val = tadd(val, tscl(edge, (T)0.125));
-        val = tadd(val, tscl(corner, (T)0.0625));
+        const C edge = cadd(cadd(r[c - pitch], r[c + pitch]), cadd(r[c - 1], r[c + 1]));
+        const C corner = cadd(cadd(r[c - pitch - 1], r[c - pitch + 1]), cadd(r[c + pitch - 1], r[c + pitch + 1]));
+        val = cscale(r[c], (T)0.25);
+        val = cadd(val, cscale(edge, (T)0.125));
+        val = cadd(val, cscale(corner, (T)0.0625));
         cc = K * pc + I;
     }
     __syncthreads();  // every read of this level's residual is done
     C* xc = V.lds + V.xo(l + 1);
     C* bc = V.lds + V.bo(l + 1);
-    for (int q = threadIdx.x; q < padded(vc); q += TT) xc[q] = tz<C>();
+    for (int q = threadIdx.x; q < padded(vc); q += TT) xc[q] = czero<C>();
     if (on) bc[cc] = val;
     __syncthreads();
 }
@@ -210,13 +193,13 @@ template <typename T> __device__ void prolong_up(const TailView<T>& V, int l) {
         if (!(i & 1) && !(k & 1)) {
             w = e[kl * pc + il];
         } else {
-            const C row0 = (i & 1) ? tadd(e[kl * pc + il], e[kl * pc + ir]) : e[kl * pc + il];
-            const C row1 = (i & 1) ? tadd(e[kr * pc + il], e[kr * pc + ir]) : e[kr * pc + il];
-            w = (k & 1) ? tadd(row0, row1) : row0;
-            w = tscl(w, (T)((i & 1) ? 0.5 : 1.0) * (T)((k & 1) ? 0.5 : 1.0));
+            const C row0 = (i & 1) ? cadd(e[kl * pc + il], e[kl * pc + ir]) : e[kl * pc + il];
+            const C row1 = (i & 1) ? cadd(e[kr * pc + il], e[kr * pc + ir]) : e[kr * pc + il];
+            w = (k & 1) ? cadd(row0, row1) : row0;
+            w = cscale(w, (T)((i & 1) ? 0.5 : 1.0) * (T)((k & 1) ? 0.5 : 1.0));
         }
         const int c = k * pitch + i;
-        x[c] = tadd(x[c], w);
+        x[c] = cadd(x[c], w);
     }
     __syncthreads();
 }
@@ -241,9 +224,9 @@ template <typename T> __device__ void coarse_solve(const TailView<T>& V, int l) 
     const int q = threadIdx.x & (CS - 1);
     for (int t0 = 0; t0 < nc; t0 += TT / CS) {
         const int t = t0 + (int)threadIdx.x / CS;
-        C acc = tz<C>();
+        C acc = czero<C>();
         if (t < nc)
-            for (int k = q; k < nc; k += CS) acc = tfma(acc, ci[(int64_t)k * nc + t], sb[k]);
+            for (int k = q; k < nc; k += CS) acc = cfma(acc, ci[(int64_t)k * nc + t], sb[k]);
         for (int off = CS / 2; off > 0; off >>= 1) {
             acc.x += __shfl_xor(acc.x, off, 64);
             acc.y += __shfl_xor(acc.y, off, 64);
@@ -289,9 +272,9 @@ __global__ __launch_bounds__(TT) void k_tail(const TailSeg<T>* __restrict__ segs
         const int t = threadIdx.x + j * TT;
         const int k = t / (v0.nx + 2), i = t - k * (v0.nx + 2);
         const bool inner = t < padded(v0) && i >= 1 && i <= v0.nx && k >= 1 && k <= v0.ny;
-        f.b[j] = inner ? load_b0(V, k, i) : tz<C>();
+        f.b[j] = inner ? load_b0(V, k, i) : czero<C>();
         f.in |= (inner ? 1u : 0u) << j;
-        if (t < padded(v0)) x0[t] = (xz || !inner) ? tz<C>() : gx[(int64_t)k * g0.pitch + i];
+        if (t < padded(v0)) x0[t] = (xz || !inner) ? czero<C>() : gx[(int64_t)k * g0.pitch + i];
     }
     __syncthreads();
     // whole solves: cycles until the system stops (at most tl.maxc); else one.
