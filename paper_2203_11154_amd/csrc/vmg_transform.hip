@@ -279,10 +279,17 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(4))) vo
             sB[buf][2 * lrow + 1][lcol + q * LS] = rb[q].y;
         }
     };
-    // (neighbouring tiles, which share the cache lines at their ends in planes
-    // that do not start on a line, run on one XCD)
-    int64_t tile = xcd_block().x;
-    if (tile >= ntiles) return;  // uniform over the block (never with NORM: one tile a block at least)
+    // Tile order: for n <= 32 block b walks the contiguous run [b T / G,
+    // (b + 1) T / G) of the T tiles (at least one, as G <= T), for n = 64 the
+    // tiles b, b + G, ...; each measured the faster for its n.  Neighbouring
+    // tiles, which share the cache lines at their ends in planes that do not
+    // start on a line, run in one block or on one XCD.
+    constexpr bool RUN = NW < 8;
+    const int64_t xb = xcd_block().x;
+    int64_t tile = RUN ? xb * ntiles / gridDim.x : xb;
+    const int64_t tend = RUN ? (xb + 1) * ntiles / gridDim.x : ntiles;
+    const int64_t tstep = RUN ? 1 : gridDim.x;
+    if (tile >= tend) return;  // uniform over the block (never with NORM: one tile a block at least)
     if constexpr (NORM) {
         sN[2 * threadIdx.x] = 0.0;  // |out|^2 of the lane's two complex rows
         sN[2 * threadIdx.x + 1] = 0.0;
@@ -291,9 +298,9 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(4))) vo
     stage(0);
     __syncthreads();
     int buf = 0;
-    for (; tile < ntiles; tile += gridDim.x) {
-        const int64_t next = tile + gridDim.x;
-        if (next < ntiles) fetch(next);
+    for (; tile < tend; tile += tstep) {
+        const int64_t next = tile + tstep;
+        if (next < tend) fetch(next);
         dbl4 acc[RT_CT];
 #pragma unroll
         for (int c = 0; c < RT_CT; ++c) acc[c] = dbl4{0.0, 0.0, 0.0, 0.0};
@@ -335,7 +342,7 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(4))) vo
                 }
             }
         }
-        if (next < ntiles) {
+        if (next < tend) {
             stage(buf ^ 1);
             __syncthreads();
             buf ^= 1;
