@@ -298,6 +298,12 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(4))) vo
     stage(0);
     __syncthreads();
     int buf = 0;
+    // (contiguous runs) a store into the cache line that the run's next tile
+    // completes waits for that tile's stores, so that both parts of the line
+    // reach L2 together rather than one part being written back alone
+    double2* dq0 = nullptr;
+    double2* dq1 = nullptr;
+    double2 dv0 = make_double2(0.0, 0.0), dv1 = make_double2(0.0, 0.0);
     for (; tile < tend; tile += tstep) {
         const int64_t next = tile + tstep;
         if (next < tend) fetch(next);
@@ -315,6 +321,24 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(4))) vo
         int64_t p0;
         int col0;
         tile_at(tile, p0, col0);
+        // lines of the next tile's first node in this lane's two rows (only
+        // the last 16 nodes of a tile can share one: a line holds 8 nodes)
+        bool has_next = false;
+        uintptr_t ln0 = 0, ln1 = 0;
+        if constexpr (RUN) {
+            if (dq0) *dq0 = dv0;
+            if (dq1) *dq1 = dv1;
+            dq0 = dq1 = nullptr;
+            if (next < tend) {
+                int64_t pn;
+                int cn;
+                tile_at(next, pn, cn);
+                const int64_t on = mo(pn);
+                has_next = true;
+                ln0 = (uintptr_t)(out + (int64_t)cr * lo.row + on) >> 7;
+                ln1 = (uintptr_t)(out + (int64_t)(cr + 4) * lo.row + on) >> 7;
+            }
+        }
 #pragma unroll
         for (int c = 0; c < RT_CT; ++c) {
             const int j = 16 * c + (lane & 15);
@@ -329,8 +353,20 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(4))) vo
                     v0.x += w0.x; v0.y += w0.y;
                     v1.x += w1.x; v1.y += w1.y;
                 }
-                *q0 = v0;
-                *q1 = v1;
+                const bool d0 = RUN && c == RT_CT - 1 && has_next && ((uintptr_t)q0 >> 7) == ln0;
+                const bool d1 = RUN && c == RT_CT - 1 && has_next && ((uintptr_t)q1 >> 7) == ln1;
+                if (d0) {
+                    dq0 = q0;
+                    dv0 = v0;
+                } else {
+                    *q0 = v0;
+                }
+                if (d1) {
+                    dq1 = q1;
+                    dv1 = v1;
+                } else {
+                    *q1 = v1;
+                }
                 if constexpr (NORM) {
                     sN[2 * threadIdx.x] += v0.x * v0.x + v0.y * v0.y;
                     sN[2 * threadIdx.x + 1] += v1.x * v1.x + v1.y * v1.y;
@@ -348,6 +384,8 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(4))) vo
             buf ^= 1;
         }
     }
+    if (dq0) *dq0 = dv0;  // (never taken: a store waits only for a next tile)
+    if (dq1) *dq1 = dv1;
     if constexpr (NORM) {
         // the 16 lanes of a lane group hold the same two rows
         double s0 = sN[2 * threadIdx.x], s1 = sN[2 * threadIdx.x + 1];
