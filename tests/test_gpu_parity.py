@@ -269,8 +269,12 @@ def test_transform_parity():
     from paper_2203_11154_amd import transform
     rng = np.random.default_rng(5)
     # n = 8, 16, 32, 64 take the register-resident kernel (ragged node tails
-    # included), the others the LDS-chunked one
-    for n, m in [(8, 1), (8, 100003), (13, 100), (16, 33), (32, 1000), (64, 31), (64, 4097), (128, 3000), (200, 777)]:
+    # included), the others the LDS-chunked one; for n <= 32 the long rows
+    # (m = 100003, 200001, 300007: rows that start off cache lines) give each
+    # block a run of several tiles, whose stores into a line that the next
+    # tile completes wait for that tile
+    for n, m in [(8, 1), (8, 100003), (13, 100), (16, 33), (16, 200001), (32, 1000), (32, 300007), (64, 31),
+                 (64, 4097), (128, 3000), (200, 777)]:
         M = rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))
         F = rng.standard_normal((n, m)) + 1j * rng.standard_normal((n, m))
         G = host(transform(dev(M), dev(F)))
