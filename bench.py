@@ -227,10 +227,14 @@ def paradiag_leg(name, n, S, seed, args, torch, sample=(), breakdown=True, dft=T
              "max_relres": float(rr.max()), "converged": st == 0 and bool(np.all(rr <= tol)),
              "levels": len(s.levels()), "schedule": schedule[0], "edge_kernel": edge, "edge_plan": s.plan(0)[0]}
         if pname == "fp64":
-            # the same steps without any event (cycles replayed as graphs)
+            # the same steps without any event (cycles replayed as graphs);
+            # the host window (CLOCK_MONOTONIC) locates them in a kernel trace
+            w0 = time.monotonic_ns()
             dtg, _ = run_steps(s, Vd, Vinvd, Fd, Ud, args.steps, tol, torch)
+            w1 = time.monotonic_ns()
             r["uninstrumented"] = {"ms_per_step": round(1e3 * dtg / args.steps, 3),
-                                   "value": round(S * args.steps / dtg, 2)}
+                                   "value": round(S * args.steps / dtg, 2),
+                                   "timed_window_monotonic_ns": [w0, w1]}
             if dft:
                 # the alpha-circulant transforms as scaled DFTs instead of the
                 # MFMA GEMMs
