@@ -30,25 +30,54 @@ constexpr int TT = 1024;  // threads per workgroup (16 waves)
 
 __device__ __forceinline__ int padded(const LevelView& v) { return (v.nx + 2) * (v.ny + 2); }
 
+// A tail level's constants for the workgroup's system, gathered into LDS
+// once per launch: read from the segment table in global memory (scalar
+// loads, the offsets by loops over the levels) they cost every step of a
+// cycle about 1,500 clocks before its first node.
+template <typename T> struct alignas(16) TailLevel {
+    Coef<T> cf;
+    T s;
+    int nx, ny;
+    int xo, bo, ro;  // element offsets of x, b (l >= 1) and the residual of the level
+};
+
 template <typename T> struct TailView {
     const TailSeg<T>* S;
     int sys;
     cplx<T>* lds;
-    // element offsets of x, b (l >= 1) and the residual of level l
-    __device__ int xo(int l) const {
-        if (l == 0) return 0;
-        int off = padded(S->lv[0]);
-        for (int q = 1; q < l; ++q) off += 2 * padded(S->lv[q]);
-        return off;
+    const TailLevel<T>* L;  // per level, in LDS
+    __device__ LevelView lv(int l) const {
+        LevelView v;
+        v.nx = L[l].nx;
+        v.ny = L[l].ny;
+        v.pitch = v.nx + 2;
+        v.plane = 0;
+        return v;
     }
-    __device__ int bo(int l) const { return xo(l) + padded(S->lv[l]); }
-    __device__ int ro(int l) const {
-        if (l == 0) return padded(S->lv[0]);
-        int off = padded(S->lv[0]);
-        for (int q = 1; q < S->nl; ++q) off += 2 * padded(S->lv[q]);
-        return off;
-    }
+    __device__ int xo(int l) const { return L[l].xo; }
+    __device__ int bo(int l) const { return L[l].bo; }
+    __device__ int ro(int l) const { return L[l].ro; }
 };
+
+// Level l's entry of the table (offsets as laid out in the header comment).
+template <typename T> __device__ void fill_level(TailLevel<T>& e, const TailSeg<T>* S, int sys, int l) {
+    e.cf = S->coef[l][sys];
+    e.s = S->s[l];
+    e.nx = S->lv[l].nx;
+    e.ny = S->lv[l].ny;
+    const int p0 = padded(S->lv[0]);
+    int xo = 0;
+    if (l > 0) {
+        xo = p0;
+        for (int q = 1; q < l; ++q) xo += 2 * padded(S->lv[q]);
+    }
+    int ro = p0;
+    if (l > 0)
+        for (int q = 1; q < S->nl; ++q) ro += 2 * padded(S->lv[q]);
+    e.xo = xo;
+    e.bo = xo + padded(S->lv[l]);
+    e.ro = ro;
+}
 
 template <typename T> __device__ __forceinline__ cplx<T> load_b0(const TailView<T>& V, int k, int i) {
     const LevelView g = V.S->gv;
@@ -69,10 +98,10 @@ template <typename T> struct Level0 {
 // r = b - L x on every padded node of level l (zero on the ring)
 template <typename T> __device__ void residual_first(const TailView<T>& V, const Level0<T>& f) {
     using C = cplx<T>;
-    const LevelView v = V.S->lv[0];
+    const LevelView v = V.lv(0);
     const int pitch = v.nx + 2, P = padded(v);
-    const Coef<T> cf = V.S->coef[0][V.sys];
-    const T s = V.S->s[0];
+    const Coef<T> cf = V.L[0].cf;
+    const T s = V.L[0].s;
     const C* x = V.lds;
     C* r = V.lds + V.ro(0);
 #pragma unroll
@@ -96,10 +125,10 @@ template <typename T> __device__ void residual(const TailView<T>& V, int l, cons
         residual_first(V, f);
         return;
     }
-    const LevelView v = V.S->lv[l];
+    const LevelView v = V.lv(l);
     const int pitch = v.nx + 2, P = padded(v);
-    const Coef<T> cf = V.S->coef[l][V.sys];
-    const T s = V.S->s[l];
+    const Coef<T> cf = V.L[l].cf;
+    const T s = V.L[l].s;
     const C* x = V.lds + V.xo(l);
     const C* b = V.lds + V.bo(l);
     C* r = V.lds + V.ro(l);
@@ -129,9 +158,9 @@ __device__ __forceinline__ void vanka_node(C* x, const C* r, int c, int pitch, c
 template <typename T> __device__ void smooth(const TailView<T>& V, int l, const Level0<T>& f) {
     using C = cplx<T>;
     residual(V, l, f);
-    const LevelView v = V.S->lv[l];
+    const LevelView v = V.lv(l);
     const int pitch = v.nx + 2;
-    const Coef<T> cf = V.S->coef[l][V.sys];
+    const Coef<T> cf = V.L[l].cf;
     C* x = V.lds + V.xo(l);
     const C* r = V.lds + V.ro(l);
     if (l == 0) {
@@ -152,7 +181,7 @@ template <typename T> __device__ void smooth(const TailView<T>& V, int l, const 
 template <typename T> __device__ void restrict_down(const TailView<T>& V, int l, const Level0<T>& f) {
     using C = cplx<T>;
     residual(V, l, f);
-    const LevelView v = V.S->lv[l], vc = V.S->lv[l + 1];
+    const LevelView v = V.lv(l), vc = V.lv(l + 1);
     const int pitch = v.nx + 2, pc = vc.nx + 2;
     const C* r = V.lds + V.ro(l);
     // one coarse node per thread (the host keeps the coarse levels of a tail
@@ -182,7 +211,7 @@ template <typename T> __device__ void restrict_down(const TailView<T>& V, int l,
 // x_l += P x_{l+1} (bilinear; the coarse ring holds zeros)
 template <typename T> __device__ void prolong_up(const TailView<T>& V, int l) {
     using C = cplx<T>;
-    const LevelView v = V.S->lv[l], vc = V.S->lv[l + 1];
+    const LevelView v = V.lv(l), vc = V.lv(l + 1);
     const int pitch = v.nx + 2, pc = vc.nx + 2;
     C* x = V.lds + V.xo(l);
     const C* e = V.lds + V.xo(l + 1);
@@ -207,7 +236,7 @@ template <typename T> __device__ void prolong_up(const TailView<T>& V, int l) {
 // coarsest level: x = (A_c + lambda I)^{-1} b by the precomputed inverse
 template <typename T> __device__ void coarse_solve(const TailView<T>& V, int l) {
     using C = cplx<T>;
-    const LevelView v = V.S->lv[l];
+    const LevelView v = V.lv(l);
     const int pitch = v.nx + 2, nc = V.S->nc;
     C* x = V.lds + V.xo(l);
     C* sb = V.lds + V.ro(l);  // right-hand side gathered densely (scratch)
@@ -262,6 +291,9 @@ __global__ __launch_bounds__(TT) void k_tail(const TailSeg<T>* __restrict__ segs
     V.lds = reinterpret_cast<C*>(tail_lds);
     if (!V.S->active[V.sys]) return;  // uniform over the workgroup
     const int nl = V.S->nl;
+    __shared__ TailLevel<T> tlev[MAXT];
+    if ((int)threadIdx.x < nl) fill_level(tlev[threadIdx.x], V.S, V.sys, (int)threadIdx.x);
+    V.L = tlev;  // (read after the barrier below)
     const LevelView v0 = V.S->lv[0], g0 = V.S->gv;
     C* x0 = V.lds;
     C* gx = xg + (int64_t)V.sys * g0.plane;
@@ -279,8 +311,9 @@ __global__ __launch_bounds__(TT) void k_tail(const TailSeg<T>* __restrict__ segs
     __syncthreads();
     // whole solves: cycles until the system stops (at most tl.maxc); else one.
     // red: the per-wave norm sums and (last slot) the go-on flag; 144 bytes,
-    // so that the dynamic LDS after it stays 16-byte aligned for the
-    // double2 accesses
+    // so that the static LDS (with the level table, whose entries are 16-byte
+    // aligned) stays a multiple of 16 bytes and the dynamic LDS after it
+    // 16-byte aligned for the double2 accesses
     __shared__ __align__(16) double red[TT / 64 + 2];
     const int ncyc = tl.maxc > 0 ? tl.maxc : 1;
     for (int cyc = 0; cyc < ncyc; ++cyc) {
@@ -379,8 +412,9 @@ int tail_max_lds() {
         int dev = 0, v = 0;
         if (hipGetDevice(&dev) != hipSuccess) dev = 0;
         if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess) v = 65536;
-        // (less the kernel's own static LDS: the whole-solve reduction slots)
-        max_lds = v - 256;
+        // (less the kernel's own static LDS: the per-level constants and the
+        // whole-solve reduction slots)
+        max_lds = v - 1024;
         // allow the dynamic allocation above the default limit
         (void)hipFuncSetAttribute((const void*)&k_tail<double>, hipFuncAttributeMaxDynamicSharedMemorySize, max_lds);
         (void)hipFuncSetAttribute((const void*)&k_tail<float>, hipFuncAttributeMaxDynamicSharedMemorySize, max_lds);
