@@ -38,8 +38,19 @@ template <typename T> struct alignas(16) TailLevel {
     Coef<T> cf;
     T s;
     int nx, ny;
-    int xo, bo, ro;  // element offsets of x, b (l >= 1) and the residual of the level
+    int xo, bo, ro;      // element offsets of x, b (l >= 1) and the residual of the level
+    float inx, ipitch;   // 1 / nx and 1 / (nx + 2), for qdiv
 };
+
+// t / p for 0 <= t < 2^16 and p >= 1, from the float reciprocal ip of p: the
+// float quotient is then within 1e-3 of t / p, and one correction makes it
+// exact (a fraction of the instructions of an integer division)
+__device__ __forceinline__ int qdiv(int t, int p, float ip) {
+    int q = (int)((float)t * ip);
+    const int r = t - q * p;
+    q += (r >= p ? 1 : 0) - (r < 0 ? 1 : 0);
+    return q;
+}
 
 template <typename T> struct TailView {
     const TailSeg<T>* S;
@@ -77,6 +88,8 @@ template <typename T> __device__ void fill_level(TailLevel<T>& e, const TailSeg<
     e.xo = xo;
     e.bo = xo + padded(S->lv[l]);
     e.ro = ro;
+    e.inx = 1.0f / (float)e.nx;
+    e.ipitch = 1.0f / (float)(e.nx + 2);
 }
 
 template <typename T> __device__ __forceinline__ cplx<T> load_b0(const TailView<T>& V, int k, int i) {
@@ -133,7 +146,7 @@ template <typename T> __device__ void residual(const TailView<T>& V, int l, cons
     const C* b = V.lds + V.bo(l);
     C* r = V.lds + V.ro(l);
     for (int t = threadIdx.x; t < P; t += TT) {
-        const int k = t / pitch, i = t - k * pitch;
+        const int k = qdiv(t, pitch, V.L[l].ipitch), i = t - k * pitch;
         C rv = czero<C>();
         if (i >= 1 && i <= v.nx && k >= 1 && k <= v.ny) {
             const C bv = b[t];
@@ -171,7 +184,7 @@ template <typename T> __device__ void smooth(const TailView<T>& V, int l, const 
         return;
     }
     for (int t = threadIdx.x; t < v.nx * v.ny; t += TT) {
-        const int k = t / v.nx + 1, i = t - (k - 1) * v.nx + 1;
+        const int k = qdiv(t, v.nx, V.L[l].inx) + 1, i = t - (k - 1) * v.nx + 1;
         vanka_node<T>(x, r, k * pitch + i, pitch, cf);
     }
     __syncthreads();
@@ -191,7 +204,7 @@ template <typename T> __device__ void restrict_down(const TailView<T>& V, int l,
     const bool on = t < vc.nx * vc.ny;
     int cc = 0;
     if (on) {
-        const int K = t / vc.nx + 1, I = t - (K - 1) * vc.nx + 1;
+        const int K = qdiv(t, vc.nx, V.L[l + 1].inx) + 1, I = t - (K - 1) * vc.nx + 1;
         const int c = 2 * K * pitch + 2 * I;
         const C edge = cadd(cadd(r[c - pitch], r[c + pitch]), cadd(r[c - 1], r[c + 1]));
         const C corner = cadd(cadd(r[c - pitch - 1], r[c - pitch + 1]), cadd(r[c + pitch - 1], r[c + pitch + 1]));
@@ -216,7 +229,7 @@ template <typename T> __device__ void prolong_up(const TailView<T>& V, int l) {
     C* x = V.lds + V.xo(l);
     const C* e = V.lds + V.xo(l + 1);
     for (int t = threadIdx.x; t < v.nx * v.ny; t += TT) {
-        const int k = t / v.nx + 1, i = t - (k - 1) * v.nx + 1;
+        const int k = qdiv(t, v.nx, V.L[l].inx) + 1, i = t - (k - 1) * v.nx + 1;
         const int il = i >> 1, ir = (i + 1) >> 1, kl = k >> 1, kr = (k + 1) >> 1;
         C w;
         if (!(i & 1) && !(k & 1)) {
@@ -241,7 +254,7 @@ template <typename T> __device__ void coarse_solve(const TailView<T>& V, int l) 
     C* x = V.lds + V.xo(l);
     C* sb = V.lds + V.ro(l);  // right-hand side gathered densely (scratch)
     for (int t = threadIdx.x; t < nc; t += TT) {
-        const int k = t / v.nx + 1, i = t - (k - 1) * v.nx + 1;
+        const int k = qdiv(t, v.nx, V.L[l].inx) + 1, i = t - (k - 1) * v.nx + 1;
         sb[t] = l == 0 ? load_b0(V, k, i) : V.lds[V.bo(l) + k * pitch + i];
     }
     __syncthreads();
@@ -261,7 +274,7 @@ template <typename T> __device__ void coarse_solve(const TailView<T>& V, int l) 
             acc.y += __shfl_xor(acc.y, off, 64);
         }
         if (t < nc && q == 0) {
-            const int kk = t / v.nx + 1, i = t - (kk - 1) * v.nx + 1;
+            const int kk = qdiv(t, v.nx, V.L[l].inx) + 1, i = t - (kk - 1) * v.nx + 1;
             x[kk * pitch + i] = acc;
         }
     }
@@ -414,7 +427,7 @@ int tail_max_lds() {
         if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess) v = 65536;
         // (less the kernel's own static LDS: the per-level constants and the
         // whole-solve reduction slots)
-        max_lds = v - 1024;
+        max_lds = v - 1280;
         // allow the dynamic allocation above the default limit
         (void)hipFuncSetAttribute((const void*)&k_tail<double>, hipFuncAttributeMaxDynamicSharedMemorySize, max_lds);
         (void)hipFuncSetAttribute((const void*)&k_tail<float>, hipFuncAttributeMaxDynamicSharedMemorySize, max_lds);
